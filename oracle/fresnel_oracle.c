@@ -1,0 +1,412 @@
+/*
+ * fresnel_oracle.c -- plain, slow FP64 reference for areal-quadrature Fresnel
+ * diffraction (Barnett, "Efficient high-order accurate Fresnel diffraction via
+ * areal quadrature and the nonuniform FFT", arXiv:2010.05978).
+ *
+ * THIS IS TEST INFRASTRUCTURE, NOT PART OF THE PRODUCT PATH.  Only the test
+ * suite, the smoke check and the CPU-baseline leg of the benchmark may load it.
+ * It shares no source with the GPU library.
+ *
+ * Everything here follows the paper's definitions literally:
+ *   - 1D Gauss-Legendre rules (used throughout sec. 3),
+ *   - vector line-integral rules on the boundary (eq. vliq; eq. ptr for the
+ *     periodic trapezoid variant, Gauss-Legendre panels otherwise),
+ *   - the "dilation" areal rule (eqs. aqnod / aqwei, sec. 3.1),
+ *   - the starshade disc + petal rule (sec. 3.2, with the weight's A(r) taken
+ *     at the radial node, i.e. the Jacobian of theta = A(r) t),
+ *   - the direct areal-quadrature sum (eq. faq), un-factorised, phase carried
+ *     in turns and reduced before cos/sin, pairwise summation over nodes,
+ *   - the Babinet complement u_oc = 1 - u_ap (eq. bab),
+ *   - the exact gradient of the quadrature sum with respect to node
+ *     coordinates and weights, and its chain rule through the perturbed
+ *     starshade construction.
+ * No blocking, fusion or factorisation beyond what those definitions state.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_PI 3.14159265358979323846264338327950288
+
+/* ------------------------------------------------------------------------ */
+/* Gauss-Legendre rule on [-1,1]: q nodes ascending, weights.               */
+/* Newton iteration on the Legendre polynomial P_q, evaluated with the      */
+/* three-term recurrence k P_k = (2k-1) x P_{k-1} - (k-1) P_{k-2}.          */
+/* ------------------------------------------------------------------------ */
+static void legendre_eval(int q, double x, double* p, double* dp)
+{
+    double p0 = 1.0, p1 = x;
+    if (q == 0) { *p = 1.0; *dp = 0.0; return; }
+    for (int k = 2; k <= q; k++) {
+        double pk = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = pk;
+    }
+    *p = p1;
+    /* derivative from P_q and P_{q-1}: (x^2-1) P_q' = q (x P_q - P_{q-1}) */
+    *dp = q * (x * p1 - p0) / (x * x - 1.0);
+}
+
+int orc_gauss_legendre(int q, double* x, double* w)
+{
+    if (q < 1) return 1;
+    for (int i = 0; i < q; i++) {
+        /* i-th largest root: classical Chebyshev-like initial guess */
+        double t = cos(ORC_PI * (i + 0.75) / (q + 0.5));
+        double p, dp;
+        for (int it = 0; it < 100; it++) {
+            legendre_eval(q, t, &p, &dp);
+            double dt = p / dp;
+            t -= dt;
+            if (fabs(dt) < 1e-16) break;
+        }
+        legendre_eval(q, t, &p, &dp);
+        /* store ascending */
+        x[q - 1 - i] = t;
+        w[q - 1 - i] = 2.0 / ((1.0 - t * t) * dp * dp);
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Boundary (vector line-integral) rules, eq. vliq:                         */
+/*   int_{dOmega} f . ds  ~=  sum_i f(X_i,Y_i) . (W_i,V_i),  CCW.           */
+/* ------------------------------------------------------------------------ */
+
+/* radial Fourier curve r(t) = r0 + sum_{k=1}^K a_k cos kt + b_k sin kt,     */
+/* x(t) = r(t) (cos t, sin t).  Returns position and derivative at t.      */
+static void radial_curve(double r0, const double* a, const double* b, int K,
+                         double t, double* X, double* Y, double* dX, double* dY)
+{
+    double r = r0, dr = 0.0;
+    for (int k = 1; k <= K; k++) {
+        double ak = a ? a[k - 1] : 0.0, bk = b ? b[k - 1] : 0.0;
+        r += ak * cos(k * t) + bk * sin(k * t);
+        dr += k * (-ak * sin(k * t) + bk * cos(k * t));
+    }
+    double c = cos(t), s = sin(t);
+    *X = r * c;
+    *Y = r * s;
+    *dX = dr * c - r * s;
+    *dY = dr * s + r * c;
+}
+
+/* Gauss-Legendre panels in the angle t: P equal panels of [0,2pi), q nodes
+ * each; n = P q boundary nodes.  Panel p node i sits at
+ * t = (2pi/P)(p + (1+x_i)/2) with line weight (pi/P) w_i, and
+ * (W,V) = weight * x'(t)  (eq. vliq1 with the GL rule replacing the PTR). */
+int orc_bdry_radial_gl(double r0, const double* a, const double* b, int K,
+                       int P, int q, double* X, double* Y, double* W, double* V)
+{
+    if (P < 1 || q < 1) return 1;
+    double* gx = (double*)malloc(sizeof(double) * q);
+    double* gw = (double*)malloc(sizeof(double) * q);
+    orc_gauss_legendre(q, gx, gw);
+    for (int p = 0; p < P; p++)
+        for (int i = 0; i < q; i++) {
+            double t = (2.0 * ORC_PI / P) * (p + 0.5 * (1.0 + gx[i]));
+            double om = (ORC_PI / P) * gw[i];
+            double x, y, dx, dy;
+            radial_curve(r0, a, b, K, t, &x, &y, &dx, &dy);
+            int64_t ii = (int64_t)p * q + i;
+            X[ii] = x; Y[ii] = y; W[ii] = om * dx; V[ii] = om * dy;
+        }
+    free(gx); free(gw);
+    return 0;
+}
+
+/* Periodic trapezoid rule, eq. ptr: t_i = 2 pi i / n, weight 2 pi / n,     */
+/* i = 1..n (stored at index i-1).                                          */
+int orc_bdry_radial_ptr(double r0, const double* a, const double* b, int K,
+                        int n, double* X, double* Y, double* W, double* V)
+{
+    if (n < 1) return 1;
+    for (int i = 1; i <= n; i++) {
+        double t = 2.0 * ORC_PI * i / n, om = 2.0 * ORC_PI / n;
+        double x, y, dx, dy;
+        radial_curve(r0, a, b, K, t, &x, &y, &dx, &dy);
+        X[i - 1] = x; Y[i - 1] = y; W[i - 1] = om * dx; V[i - 1] = om * dy;
+    }
+    return 0;
+}
+
+/* Polygon with nv vertices (CCW), q GL nodes per straight edge:            */
+/* node v_e + (1+x_i)/2 (v_{e+1}-v_e), vector weight (v_{e+1}-v_e) w_i / 2. */
+int orc_bdry_polygon(const double* vx, const double* vy, int nv, int q,
+                     double* X, double* Y, double* W, double* V)
+{
+    if (nv < 3 || q < 1) return 1;
+    double* gx = (double*)malloc(sizeof(double) * q);
+    double* gw = (double*)malloc(sizeof(double) * q);
+    orc_gauss_legendre(q, gx, gw);
+    for (int e = 0; e < nv; e++) {
+        int f = (e + 1) % nv;
+        double ex = vx[f] - vx[e], ey = vy[f] - vy[e];
+        for (int i = 0; i < q; i++) {
+            double s = 0.5 * (1.0 + gx[i]);
+            int64_t ii = (int64_t)e * q + i;
+            X[ii] = vx[e] + s * ex;
+            Y[ii] = vy[e] + s * ey;
+            W[ii] = 0.5 * gw[i] * ex;
+            V[ii] = 0.5 * gw[i] * ey;
+        }
+    }
+    free(gx); free(gw);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Dilation areal rule, eqs. aqnod / aqwei (sec. 3.1):                      */
+/*   alpha_l, wt_l = m-node GL on (0,1);                                    */
+/*   node j = l + i m  (0-based, radial index l inner):                     */
+/*   (x_j, y_j) = alpha_l (X_i, Y_i),  w_j = alpha_l wt_l (X_i V_i - Y_i W_i) */
+/* ------------------------------------------------------------------------ */
+int orc_dilation(const double* X, const double* Y, const double* W, const double* V,
+                 int64_t n, int m, double* x, double* y, double* w)
+{
+    if (m < 1 || n < 0) return 1;
+    double* gx = (double*)malloc(sizeof(double) * m);
+    double* gw = (double*)malloc(sizeof(double) * m);
+    orc_gauss_legendre(m, gx, gw);
+    for (int64_t i = 0; i < n; i++) {
+        double cross = X[i] * V[i] - Y[i] * W[i];
+        for (int l = 0; l < m; l++) {
+            double al = 0.5 * (1.0 + gx[l]);
+            double wl = 0.5 * gw[l];
+            int64_t j = (int64_t)l + i * m;
+            x[j] = al * X[i];
+            y[j] = al * Y[i];
+            w[j] = al * wl * cross;
+        }
+    }
+    free(gx); free(gw);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Starshade rule (sec. 3.2, eq. Omega).                                     */
+/* Apodisation A(r) = 1 for r < a, exp(-((r-a)/b)^p) for a <= r <= R (the   */
+/* offset hyper-Gaussian family).                                           */
+/* Disc of radius a: PTR boundary rule with nd nodes (eq. ptr), dilation    */
+/* with md radial nodes.  Petal k = 0..Np-1 centred at theta_k = 2 pi k/Np:  */
+/* r_l, wr_l = GL on (a,R) (m nodes); tau_i, om_i = GL on [-1,1] (np nodes); */
+/* half-width angle h(r) = pi A(r)/Np, node r_l (cos phi, sin phi) with     */
+/* phi = theta_k + h(r_l) tau_i, weight r_l wr_l h(r_l) om_i.  (This equals */
+/* the printed petal rule with angular nodes t_i = (pi/Np) tau_i, with the  */
+/* apodisation in the weight evaluated at the radial node r_l.)             */
+/*                                                                          */
+/* Optional lateral edge perturbation, K sine modes per edge:               */
+/*   d+(r) = sum_k c+_k sin(k pi (r-a)/(R-a)),  likewise d-(r);             */
+/* the upper edge moves outward by d+ (arc length), the lower edge by d-:   */
+/*   mid(r) = (d+ - d-)/(2r),  h(r) = pi A/Np + (d+ + d-)/(2r),              */
+/*   phi = theta_k + mid + h tau.                                           */
+/* coef layout: petal k: c+ at [2kK, 2kK+K), c- at [2kK+K, 2kK+2K).          */
+/* Node order: disc first (i outer, l inner), then petals k, i outer, l     */
+/* inner.  N = nd md + Np np m.                                             */
+/* ------------------------------------------------------------------------ */
+static double hg_profile(double r, double a, double b, double p)
+{
+    if (r < a) return 1.0;
+    return exp(-pow((r - a) / b, p));
+}
+
+int64_t orc_starshade_size(int Np, int m, int np, int nd, int md)
+{
+    return (int64_t)nd * md + (int64_t)Np * np * m;
+}
+
+int orc_starshade(int Np, double a, double R, double b, double p,
+                  int m, int np, int nd, int md, const double* coef, int K,
+                  double* x, double* y, double* w)
+{
+    if (Np < 1 || m < 1 || np < 1 || nd < 0 || md < 1 || !(R > a) || !(a >= 0)) return 1;
+    /* disc */
+    if (nd > 0) {
+        double* X = (double*)malloc(sizeof(double) * nd * 4);
+        orc_bdry_radial_ptr(a, NULL, NULL, 0, nd, X, X + nd, X + 2 * nd, X + 3 * nd);
+        orc_dilation(X, X + nd, X + 2 * nd, X + 3 * nd, nd, md, x, y, w);
+        free(X);
+    }
+    int64_t off = (int64_t)nd * md;
+    double* rx = (double*)malloc(sizeof(double) * m);
+    double* rw = (double*)malloc(sizeof(double) * m);
+    double* tx = (double*)malloc(sizeof(double) * np);
+    double* tw = (double*)malloc(sizeof(double) * np);
+    orc_gauss_legendre(m, rx, rw);
+    orc_gauss_legendre(np, tx, tw);
+    for (int k = 0; k < Np; k++) {
+        double thk = 2.0 * ORC_PI * k / Np;
+        for (int i = 0; i < np; i++)
+            for (int l = 0; l < m; l++) {
+                double r = a + 0.5 * (R - a) * (1.0 + rx[l]);
+                double wr = 0.5 * (R - a) * rw[l];
+                double dp = 0.0, dm = 0.0;
+                if (coef && K > 0)
+                    for (int s = 1; s <= K; s++) {
+                        double sk = sin(s * ORC_PI * (r - a) / (R - a));
+                        dp += coef[2 * k * K + (s - 1)] * sk;
+                        dm += coef[2 * k * K + K + (s - 1)] * sk;
+                    }
+                double mid = (dp - dm) / (2.0 * r);
+                double half = ORC_PI * hg_profile(r, a, b, p) / Np + (dp + dm) / (2.0 * r);
+                double phi = thk + mid + half * tx[i];
+                int64_t j = off + (int64_t)k * np * m + (int64_t)i * m + l;
+                x[j] = r * cos(phi);
+                y[j] = r * sin(phi);
+                w[j] = r * wr * half * tw[i];
+            }
+    }
+    free(rx); free(rw); free(tx); free(tw);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Direct sum, eq. faq, and Babinet, eq. bab:                               */
+/*  u_ap(k) = 1/(i lambda z) sum_j exp(i pi |xi_k - x_j|^2/(lambda z)) w_j   */
+/*  u_oc(k) = 1 - u_ap(k)                                                   */
+/* The phase is kept in turns, t = |xi-x|^2/(2 lambda z), reduced to         */
+/* f = t - rint(t) (exact in FP64) before cos/sin(2 pi f).  The sum over j  */
+/* is pairwise.  Output u is interleaved (re, im).                          */
+/* ------------------------------------------------------------------------ */
+typedef struct { double re, im; } cplx;
+
+static cplx pairwise_terms(const double* x, const double* y, const double* w,
+                           int64_t j0, int64_t j1, double xi, double eta, double inv2lz)
+{
+    cplx s = {0.0, 0.0};
+    if (j1 - j0 <= 16) {
+        for (int64_t j = j0; j < j1; j++) {
+            double dx = xi - x[j], dy = eta - y[j];
+            double t = (dx * dx + dy * dy) * inv2lz;
+            double f = t - rint(t);
+            double ang = 2.0 * ORC_PI * f;
+            s.re += cos(ang) * w[j];
+            s.im += sin(ang) * w[j];
+        }
+        return s;
+    }
+    int64_t jm = j0 + (j1 - j0) / 2;
+    cplx a = pairwise_terms(x, y, w, j0, jm, xi, eta, inv2lz);
+    cplx b = pairwise_terms(x, y, w, jm, j1, xi, eta, inv2lz);
+    s.re = a.re + b.re;
+    s.im = a.im + b.im;
+    return s;
+}
+
+int orc_fresnel_direct(const double* x, const double* y, const double* w, int64_t N,
+                       double lambda, double z, const double* xi, const double* eta,
+                       int64_t M, int occulter, double* u)
+{
+    double lz = lambda * z;
+    if (!(lz > 0.0)) return 2;
+    double inv2lz = 1.0 / (2.0 * lz);
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t k = 0; k < M; k++) {
+        cplx s = {0.0, 0.0};
+        if (N > 0) s = pairwise_terms(x, y, w, 0, N, xi[k], eta[k], inv2lz);
+        /* multiply by 1/(i lz) = -i/lz */
+        double re = s.im / lz, im = -s.re / lz;
+        if (occulter) { re = 1.0 - re; im = -im; }
+        u[2 * k] = re;
+        u[2 * k + 1] = im;
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Gradient of a real loss L through the direct sum.                        */
+/* g_k = dL/dRe(u_k) + i dL/dIm(u_k) (interleaved), so that                 */
+/* dL = sum_k Re(conj(g_k) du_k).  With E_kj = exp(i pi|xi_k-x_j|^2/lz),     */
+/* a_k = conj(g_k) (negated for an occulter, since u_oc = 1 - u_ap):        */
+/*   G_j  = sum_k a_k E_kj,   Hx_j = sum_k a_k E_kj xi_k,  Hy_j likewise,    */
+/*   dL/dw_j = Re[G_j / (i lz)],                                            */
+/*   dL/dx_j = Re[(w_j/(i lz)) (2 pi i/lz) (x_j G_j - Hx_j)],  y likewise.  */
+/* (du_k/dx_j = (w_j/(i lz)) E_kj (2 pi i / lz)(x_j - xi_k).)               */
+/* ------------------------------------------------------------------------ */
+int orc_fresnel_direct_vjp(const double* x, const double* y, const double* w, int64_t N,
+                           double lambda, double z, const double* xi, const double* eta,
+                           int64_t M, int occulter, const double* g,
+                           double* gx, double* gy, double* gw)
+{
+    double lz = lambda * z;
+    if (!(lz > 0.0)) return 2;
+    double inv2lz = 1.0 / (2.0 * lz);
+    double sgn = occulter ? -1.0 : 1.0;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t j = 0; j < N; j++) {
+        double Gr = 0, Gi = 0, Hxr = 0, Hxi = 0, Hyr = 0, Hyi = 0;
+        for (int64_t k = 0; k < M; k++) {
+            double dx = xi[k] - x[j], dy = eta[k] - y[j];
+            double t = (dx * dx + dy * dy) * inv2lz;
+            double f = t - rint(t);
+            double c = cos(2.0 * ORC_PI * f), s = sin(2.0 * ORC_PI * f);
+            double ar = sgn * g[2 * k], ai = -sgn * g[2 * k + 1]; /* a = sgn conj(g) */
+            double er = ar * c - ai * s, ei = ar * s + ai * c;     /* a E */
+            Gr += er; Gi += ei;
+            Hxr += er * xi[k]; Hxi += ei * xi[k];
+            Hyr += er * eta[k]; Hyi += ei * eta[k];
+        }
+        /* G/(i lz) = (Gi - i Gr)/lz */
+        gw[j] = Gi / lz;
+        /* (w/(i lz)) (2 pi i/lz) = 2 pi w / lz^2 (real) */
+        double fac = 2.0 * ORC_PI * w[j] / (lz * lz);
+        gx[j] = fac * (x[j] * Gr - Hxr);
+        gy[j] = fac * (y[j] * Gr - Hyr);
+    }
+    return 0;
+}
+
+/* Chain rule through the perturbed starshade construction (same parameters */
+/* as orc_starshade).  Disc nodes do not depend on the coefficients.  For a  */
+/* petal node, with s_k(r) = sin(k pi (r-a)/(R-a)):                          */
+/*   dphi/dc+_k = s_k (1 + tau)/(2r),  dphi/dc-_k = s_k (tau - 1)/(2r),      */
+/*   dw/dc+-_k  = wr om s_k / 2,  d(x,y)/dphi = (-y, x).                     */
+int orc_starshade_vjp(int Np, double a, double R, double b, double p,
+                      int m, int np, int nd, int md, const double* coef, int K,
+                      const double* gx, const double* gy, const double* gw, double* gcoef)
+{
+    if (Np < 1 || m < 1 || np < 1 || K < 1) return 1;
+    int64_t off = (int64_t)nd * md;
+    double* x = (double*)malloc(sizeof(double) * orc_starshade_size(Np, m, np, nd, md) * 3);
+    int64_t N = orc_starshade_size(Np, m, np, nd, md);
+    double* y = x + N;
+    double* w = y + N;
+    orc_starshade(Np, a, R, b, p, m, np, nd, md, coef, K, x, y, w);
+    double* rx = (double*)malloc(sizeof(double) * m);
+    double* rw = (double*)malloc(sizeof(double) * m);
+    double* tx = (double*)malloc(sizeof(double) * np);
+    double* tw = (double*)malloc(sizeof(double) * np);
+    orc_gauss_legendre(m, rx, rw);
+    orc_gauss_legendre(np, tx, tw);
+    for (int k = 0; k < Np; k++)
+        for (int s = 1; s <= K; s++) {
+            double accp = 0.0, accm = 0.0;
+            for (int i = 0; i < np; i++)
+                for (int l = 0; l < m; l++) {
+                    double r = a + 0.5 * (R - a) * (1.0 + rx[l]);
+                    double wr = 0.5 * (R - a) * rw[l];
+                    double sk = sin(s * ORC_PI * (r - a) / (R - a));
+                    int64_t j = off + (int64_t)k * np * m + (int64_t)i * m + l;
+                    double dphi_term = gx[j] * (-y[j]) + gy[j] * x[j];
+                    double dw = wr * tw[i] * sk / 2.0;
+                    accp += dphi_term * sk * (1.0 + tx[i]) / (2.0 * r) + gw[j] * dw;
+                    accm += dphi_term * sk * (tx[i] - 1.0) / (2.0 * r) + gw[j] * dw;
+                }
+            gcoef[2 * k * K + (s - 1)] = accp;
+            gcoef[2 * k * K + K + (s - 1)] = accm;
+        }
+    free(rx); free(rw); free(tx); free(tw); free(x);
+    return 0;
+}
+
+/* Number of OpenMP threads the direct sum will use (1 without OpenMP). */
+int orc_num_threads(void)
+{
+#ifdef _OPENMP
+    extern int omp_get_max_threads(void);
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

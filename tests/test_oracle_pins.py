@@ -1,0 +1,385 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by mathematics.
+
+Every test here runs on the CPU.  The oracle is checked against closed forms,
+invariants, library routines and brute force, never against itself, so that a
+dropped term, a wrong sign or index, or a transposed operand fails one of them.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.integrate
+import scipy.special
+
+import oracle
+import workloads
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ------------------------------------------------------------ 1D GL rules
+@pytest.mark.parametrize("q", [1, 2, 5, 20, 64, 320])
+def test_gauss_legendre_matches_numpy(q):
+    x, w = oracle.gauss_legendre(q)
+    xr, wr = np.polynomial.legendre.leggauss(q)
+    assert np.abs(x - xr).max() < 1e-14
+    assert np.abs(w - wr).max() < 1e-14 * max(1.0, wr.max())
+
+
+@pytest.mark.parametrize("q", [3, 7, 16])
+def test_gauss_legendre_exact_degree(q):
+    x, w = oracle.gauss_legendre(q)
+    for k in range(2 * q):
+        exact = 0.0 if k % 2 else 2.0 / (k + 1)
+        assert abs((w * x ** k).sum() - exact) < 1e-14
+    # degree 2q is not integrated exactly
+    assert abs((w * x ** (2 * q)).sum() - 2.0 / (2 * q + 1)) > 1e-10
+
+
+# ------------------------------------------------ boundary + areal rules
+def test_disk_area_and_moments():
+    x, y, w = oracle.quad_radial(1.0, panels=6, q=20, m=40)
+    assert len(x) == 4800
+    assert abs(w.sum() - math.pi) < 1e-14
+    assert abs((w * (x * x + y * y)).sum() - math.pi / 2) < 1e-13   # polar moment pi R^4/2
+    assert abs((w * x).sum()) < 1e-14 and abs((w * y).sum()) < 1e-14
+    # radius-2 disk: area scales as R^2, polar moment as R^4
+    x, y, w = oracle.quad_radial(2.0, panels=6, q=20, m=40)
+    assert abs(w.sum() - 4 * math.pi) < 1e-13
+    assert abs((w * (x * x + y * y)).sum() - 8 * math.pi) < 1e-12
+
+
+def test_starfish_area():
+    wl = workloads.workload(2)
+    s = wl.shape
+    x, y, w = oracle.quad_radial(s.r0, s.a, s.b, s.panels, s.q, s.m)
+    assert len(x) == 40_000
+    # area of r = 1 + eps cos 5t is pi (1 + eps^2/2)
+    assert abs(w.sum() - math.pi * (1 + 0.3 ** 2 / 2)) < 1e-13
+    # five-fold symmetry: first moments vanish
+    assert abs((w * x).sum()) < 1e-13 and abs((w * y).sum()) < 1e-13
+
+
+def test_radial_sine_mode_area():
+    # r = 1 + b1 sin t: area = pi (1 + b1^2/2); centroid x = 0, y = pi b1 / area
+    b1 = 0.2
+    x, y, w = oracle.quad_radial(1.0, [0.0], [b1], panels=8, q=16, m=30)
+    A = math.pi * (1 + b1 ** 2 / 2)
+    assert abs(w.sum() - A) < 1e-13
+    # first moment about y: int r^3/3 sin t dt = (1/3) int (1+b sin)^3 sin = (1/3)(3b pi + 3/4 b^3 pi)
+    My = (3 * b1 * math.pi + 0.75 * b1 ** 3 * math.pi) / 3
+    assert abs((w * y).sum() - My) < 1e-13
+    assert abs((w * x).sum()) < 1e-13
+
+
+def test_ptr_rule_disk():
+    X, Y, W, V = oracle.boundary_radial_ptr(1.5, n=64)
+    x, y, w = oracle.dilation(X, Y, W, V, 20)
+    assert abs(w.sum() - math.pi * 1.5 ** 2) < 1e-13
+
+
+def _shoelace(vx, vy):
+    return 0.5 * (vx * np.roll(vy, -1) - np.roll(vx, -1) * vy).sum()
+
+
+def test_polygon_area_and_centroid():
+    vx = np.array([0.0, 2.0, 2.5, 1.0, -0.5])
+    vy = np.array([-1.0, -0.8, 0.7, 1.5, 0.4])
+    x, y, w = oracle.quad_polygon(vx, vy, q=4, m=6)
+    A = _shoelace(vx, vy)
+    assert abs(w.sum() - A) < 1e-13
+    cross = vx * np.roll(vy, -1) - np.roll(vx, -1) * vy
+    cx = ((vx + np.roll(vx, -1)) * cross).sum() / (6 * A)
+    cy = ((vy + np.roll(vy, -1)) * cross).sum() / (6 * A)
+    assert abs((w * x).sum() / A - cx) < 1e-13
+    assert abs((w * y).sum() / A - cy) < 1e-13
+
+
+def test_polygon_not_starshaped_about_origin_still_integrates():
+    # L-shaped hexagon that does not contain the origin; dilation nodes spill
+    # outside and weights go negative, but polynomials integrate exactly.
+    vx = np.array([1.0, 3.0, 3.0, 2.0, 2.0, 1.0])
+    vy = np.array([1.0, 1.0, 2.0, 2.0, 3.0, 3.0])
+    x, y, w = oracle.quad_polygon(vx, vy, q=3, m=4)
+    assert (w < 0).any()
+    assert abs(w.sum() - _shoelace(vx, vy)) < 1e-13
+    # int x^2 y over the L: split into [1,3]x[1,2] and [1,2]x[2,3]
+    exact = (27 - 1) / 3 * (4 - 1) / 2 + (8 - 1) / 3 * (9 - 4) / 2
+    assert abs((w * x * x * y).sum() - exact) < 1e-12
+
+
+def _starshade_area(Np, a, R, b, p):
+    f = lambda r: r * math.exp(-((r - a) / b) ** p)
+    val, err = scipy.integrate.quad(f, a, R, epsabs=1e-13, epsrel=1e-13, limit=400)
+    return math.pi * a * a + 2 * math.pi * val
+
+
+def test_starshade_area_workload3():
+    s = workloads.workload(3).shape
+    x, y, w = oracle.quad_starshade(s.Np, s.a, s.R, s.b, s.p, s.m, s.np_, s.nd, s.md)
+    assert len(x) == 998_400 == s.n_nodes
+    A = _starshade_area(s.Np, s.a, s.R, s.b, s.p)
+    assert abs(w.sum() - A) < 1e-10 * A
+    assert abs((w * x).sum()) < 1e-9 and abs((w * y).sum()) < 1e-9
+    # every petal node lies inside its petal: |angle - theta_k| < pi A(r)/Np
+    off = s.nd * s.md
+    r = np.hypot(x[off:], y[off:])
+    assert r.min() > s.a and r.max() < s.R
+
+
+def test_starshade_hg_paper_node_count():
+    g = json.load(open(os.path.join(GOLDEN, "hg_starshade.json")))
+    N = oracle.starshade_size(g["Np"], g["m"], g["np"], g["nd"], g["md"])
+    assert N == g["N"]
+    x, y, w = oracle.quad_starshade(g["Np"], g["a"], g["R"], g["b"], g["p"],
+                                    g["m"], g["np"], g["nd"], g["md"])
+    assert len(w) == g["N"]
+    A = _starshade_area(g["Np"], g["a"], g["R"], g["b"], g["p"])
+    assert abs(w.sum() - A) < 1e-9 * A
+    assert abs(g["R"] ** 2 / (g["lambda"] * g["z"]) - g["fresnel_number"]) < 0.05
+
+
+def test_perturbed_starshade_area_closed_form():
+    wl = workloads.workload(5, reduced=True)
+    s = wl.shape
+    x, y, w = oracle.quad_starshade(s.Np, s.a, s.R, s.b, s.p, s.m, s.np_, s.nd, s.md,
+                                    s.coef, s.K)
+    A0 = _starshade_area(s.Np, s.a, s.R, s.b, s.p)
+    # each edge displaced by d(r) adds int_a^R d(r) dr;
+    # int_0^L sin(k pi u/L) du = 2L/(k pi) for odd k, 0 for even k
+    L = s.R - s.a
+    c = s.coef.reshape(s.Np, 2, s.K)
+    k = np.arange(1, s.K + 1)
+    ints = np.where(k % 2 == 1, 2 * L / (k * math.pi), 0.0)
+    dA = (c.sum(axis=1) * ints).sum()
+    # the reduced rule (m = 64) is not fully converged in r for the HG profile;
+    # the closed form area is matched to the rule's own unperturbed error
+    x0, y0, w0 = oracle.quad_starshade(s.Np, s.a, s.R, s.b, s.p, s.m, s.np_, s.nd, s.md)
+    assert abs(w0.sum() - A0) < 1e-8 * A0
+    assert abs((w.sum() - w0.sum()) - dA) < 1e-12
+
+
+# ----------------------------------------------------- the direct sum
+def _lommel_disk(rho, R, lz):
+    """Aperture disk field by Lommel functions (Born & Wolf sec. 8.8)."""
+    u = 2 * math.pi * R * R / lz
+    v = 2 * math.pi * R * rho / lz
+    pre = -np.exp(1j * math.pi * (rho * rho + R * R) / lz)
+    S = 60
+    if v > u:
+        U1 = sum((-1) ** s * (u / v) ** (1 + 2 * s) * scipy.special.jv(1 + 2 * s, v) for s in range(S))
+        U2 = sum((-1) ** s * (u / v) ** (2 + 2 * s) * scipy.special.jv(2 + 2 * s, v) for s in range(S))
+    else:
+        V0 = sum((-1) ** s * (v / u) ** (2 * s) * scipy.special.jv(2 * s, v) for s in range(S))
+        V1 = sum((-1) ** s * (v / u) ** (1 + 2 * s) * scipy.special.jv(1 + 2 * s, v) for s in range(S))
+        phi = u / 2 + v * v / (2 * u)
+        U1 = math.sin(phi) - V1
+        U2 = -math.cos(phi) + V0
+    return pre * (U2 + 1j * U1)
+
+
+def _hankel_disk(rho, R, lz, nq=4000):
+    """u_ap(rho) = (2 pi/(i lz)) e^{i pi rho^2/lz} int_0^R e^{i pi r^2/lz} J0(2 pi rho r/lz) r dr."""
+    xg, wg = np.polynomial.legendre.leggauss(200)
+    edges = np.linspace(0, R, nq // 200 + 1)
+    acc = 0j
+    for a0, b0 in zip(edges[:-1], edges[1:]):
+        r = a0 + (b0 - a0) * (xg + 1) / 2
+        ww = wg * (b0 - a0) / 2
+        acc += (ww * np.exp(1j * math.pi * r * r / lz) * scipy.special.jv(0, 2 * math.pi * rho * r / lz) * r).sum()
+    return 2 * math.pi / (1j * lz) * np.exp(1j * math.pi * rho * rho / lz) * acc
+
+
+@pytest.mark.parametrize("rho", [0.001, 0.3, 0.7, 0.99, 1.01, 1.3, 2.0])
+def test_lommel_matches_hankel(rho):
+    assert abs(_lommel_disk(rho, 1.0, 0.1) - _hankel_disk(rho, 1.0, 0.1)) < 1e-12
+
+
+def test_disk_on_axis_closed_form():
+    # workload-1 rule: u_ap(0) = 1 - exp(i pi R^2/(lambda z)); F = 10 -> 0
+    wl = workloads.workload(1)
+    s = wl.shape
+    x, y, w = oracle.quad_radial(s.r0, panels=s.panels, q=s.q, m=s.m)
+    u = oracle.fresnel_direct(x, y, w, wl.lam, wl.z, [0.0], [0.0])[0]
+    exact = 1 - np.exp(1j * math.pi / (wl.lam * wl.z))
+    assert abs(u - exact) < 1e-12
+    # a non-integer Fresnel number, converged rule
+    x, y, w = oracle.quad_radial(1.0, panels=16, q=20, m=80)
+    for lz in (0.07, 0.13, 0.3):
+        u = oracle.fresnel_direct(x, y, w, 1.0, lz, [0.0], [0.0])[0]
+        assert abs(u - (1 - np.exp(1j * math.pi / lz))) < 1e-13
+
+
+def test_disk_off_axis_lommel():
+    x, y, w = oracle.quad_radial(1.0, panels=16, q=20, m=80)
+    lz = 0.1
+    rhos = np.array([0.1, 0.5, 0.8, 1.0, 1.2, 1.4])
+    th = np.linspace(0.3, 5.0, len(rhos))
+    xi, eta = rhos * np.cos(th), rhos * np.sin(th)
+    u = oracle.fresnel_direct(x, y, w, 1.0, lz, xi, eta)
+    for k, rho in enumerate(rhos):
+        assert abs(u[k] - _lommel_disk(rho, 1.0, lz)) < 1e-10, rho
+    # workload-1 rule: accurate inside rho <= 0.5
+    wl = workloads.workload(1)
+    x, y, w = oracle.quad_radial(1.0, panels=6, q=20, m=40)
+    u = oracle.fresnel_direct(x, y, w, wl.lam, wl.z, [0.25, 0.0], [0.0, -0.5])
+    assert abs(u[0] - _lommel_disk(0.25, 1.0, 0.1)) < 1e-10
+    assert abs(u[1] - _lommel_disk(0.5, 1.0, 0.1)) < 1e-9
+
+
+def test_babinet_poisson_spot():
+    x, y, w = oracle.quad_radial(1.0, panels=16, q=20, m=80)
+    for lz in (0.1, 0.0731):
+        uoc = oracle.fresnel_direct(x, y, w, 1.0, lz, [0.0], [0.0], occulter=True)[0]
+        assert abs(uoc - np.exp(1j * math.pi / lz)) < 1e-13
+        assert abs(abs(uoc) - 1) < 1e-13
+    xi, eta = np.array([0.3, -1.2, 2.0]), np.array([0.1, 0.4, -0.7])
+    uap = oracle.fresnel_direct(x, y, w, 1.0, 0.1, xi, eta)
+    uoc = oracle.fresnel_direct(x, y, w, 1.0, 0.1, xi, eta, occulter=True)
+    assert np.abs(uoc - (1 - uap)).max() < 1e-15
+
+
+def test_annulus_linearity():
+    # annulus = disk(b) minus disk(a): on axis e^{i pi a^2/lz} - e^{i pi b^2/lz}
+    a, b, lz = 0.6, 1.1, 0.05
+    x1, y1, w1 = oracle.quad_radial(b, panels=16, q=20, m=120)
+    x2, y2, w2 = oracle.quad_radial(a, panels=16, q=20, m=120)
+    x = np.concatenate([x1, x2]); y = np.concatenate([y1, y2]); w = np.concatenate([w1, -w2])
+    u = oracle.fresnel_direct(x, y, w, 1.0, lz, [0.0], [0.0])[0]
+    assert abs(u - (np.exp(1j * math.pi * a * a / lz) - np.exp(1j * math.pi * b * b / lz))) < 1e-12
+
+
+def test_translation_invariance_and_reflection_symmetry():
+    s = workloads.workload(2).shape
+    x, y, w = oracle.quad_radial(s.r0, s.a, s.b, 8, 20, 40)
+    lz = 0.2
+    xi = np.array([0.2, -0.9, 1.4, 0.0]); eta = np.array([0.5, 0.3, -1.1, 0.0])
+    u = oracle.fresnel_direct(x, y, w, 1.0, lz, xi, eta)
+    # shift aperture and targets together
+    d = np.array([0.37, -1.21])
+    u2 = oracle.fresnel_direct(x + d[0], y + d[1], w, 1.0, lz, xi + d[0], eta + d[1])
+    assert np.abs(u - u2).max() < 1e-12
+    # the starfish is symmetric under y -> -y
+    u3 = oracle.fresnel_direct(x, y, w, 1.0, lz, xi, -eta)
+    assert np.abs(u - u3).max() < 1e-12
+    # rotation of the targets by 2 pi / 5 leaves the field unchanged once the
+    # rule is converged (the 20x20 x 100 rule of workload 2 is)
+    x, y, w = oracle.quad_radial(s.r0, s.a, s.b, s.panels, s.q, s.m)
+    u = oracle.fresnel_direct(x, y, w, 1.0, lz, xi, eta)
+    c, sn = math.cos(2 * math.pi / 5), math.sin(2 * math.pi / 5)
+    u4 = oracle.fresnel_direct(x, y, w, 1.0, lz, c * xi - sn * eta, sn * xi + c * eta)
+    assert np.abs(u - u4).max() < 1e-12
+
+
+def test_brute_force_mpmath():
+    mp = pytest.importorskip("mpmath")
+    mp.mp.dps = 40
+    g = np.random.Generator(np.random.PCG64(7))
+    N, M = 48, 12
+    x = g.uniform(-1, 1, N); y = g.uniform(-1, 1, N); w = g.uniform(-0.5, 1.0, N)
+    xi = g.uniform(-2, 2, M); eta = g.uniform(-2, 2, M)
+    lam, z = 0.3, 0.25
+    u = oracle.fresnel_direct(x, y, w, lam, z, xi, eta)
+    uo = oracle.fresnel_direct(x, y, w, lam, z, xi, eta, occulter=True)
+    lz = mp.mpf(lam) * mp.mpf(z)
+    for k in range(M):
+        s = mp.mpc(0)
+        for j in range(N):
+            r2 = (mp.mpf(xi[k]) - mp.mpf(x[j])) ** 2 + (mp.mpf(eta[k]) - mp.mpf(y[j])) ** 2
+            s += mp.expj(mp.pi * r2 / lz) * mp.mpf(w[j])
+        s = s / (mp.mpc(0, 1) * lz)
+        ref = complex(s)
+        assert abs(u[k] - ref) < 1e-13 * max(1, abs(ref))
+        assert abs(uo[k] - (1 - ref)) < 1e-13 * max(1, abs(ref))
+
+
+def test_empty_quadrature():
+    u = oracle.fresnel_direct([], [], [], 1.0, 1.0, [0.0, 1.0], [0.0, 2.0])
+    assert np.all(u == 0)
+    uo = oracle.fresnel_direct([], [], [], 1.0, 1.0, [0.0], [0.0], occulter=True)
+    assert uo[0] == 1
+
+
+def test_grid_targets_convention():
+    xi, eta = oracle.grid_targets(4, 6, 0.5, 0.25, xc=1.0, yc=-1.0)
+    assert xi.shape == (24,)
+    # k1 fastest, -n/2 <= k < n/2
+    assert np.allclose(xi[:4], 1.0 + 0.5 * np.array([-2, -1, 0, 1]))
+    assert np.allclose(eta[::4], -1.0 + 0.25 * np.array([-3, -2, -1, 0, 1, 2]))
+
+
+# ----------------------------------------------------------- gradients
+def _torch_direct(x, y, w, lz, xi, eta, occulter):
+    import torch
+    ph = math.pi * ((xi[:, None] - x[None, :]) ** 2 + (eta[:, None] - y[None, :]) ** 2) / lz
+    E = torch.polar(torch.ones_like(ph), ph)
+    u = (E * w[None, :].to(E.dtype)).sum(1) / (1j * lz)
+    return 1 - u if occulter else u
+
+
+@pytest.mark.parametrize("occulter", [False, True])
+def test_vjp_matches_torch_autograd(occulter):
+    torch = pytest.importorskip("torch")
+    g = np.random.Generator(np.random.PCG64(11))
+    N, M = 40, 30
+    x = g.uniform(-1, 1, N); y = g.uniform(-1, 1, N); w = g.uniform(0.1, 1.0, N)
+    xi = g.uniform(-1.5, 1.5, M); eta = g.uniform(-1.5, 1.5, M)
+    lz = 0.2
+    tx, ty, tw = (torch.tensor(t, requires_grad=True) for t in (x, y, w))
+    u = _torch_direct(tx, ty, tw, lz, torch.tensor(xi), torch.tensor(eta), occulter)
+    u.retain_grad()
+    wt = torch.tensor(g.uniform(0.5, 2.0, M))
+    L = (wt * u.abs() ** 2).sum()
+    L.backward()
+    gu = u.grad.detach().numpy()
+    gx, gy, gw = oracle.fresnel_direct_vjp(x, y, w, 1.0, lz, xi, eta, gu, occulter)
+    for a, b in ((gx, tx.grad), (gy, ty.grad), (gw, tw.grad)):
+        b = b.numpy()
+        assert np.abs(a - b).max() < 1e-11 * np.abs(b).max()
+
+
+def test_vjp_finite_difference():
+    g = np.random.Generator(np.random.PCG64(12))
+    N, M = 20, 25
+    x = g.uniform(-1, 1, N); y = g.uniform(-1, 1, N); w = g.uniform(0.1, 1.0, N)
+    xi = g.uniform(-1.5, 1.5, M); eta = g.uniform(-1.5, 1.5, M)
+    lam, z = 0.5, 0.4
+
+    def loss(x, y, w):
+        u = oracle.fresnel_direct(x, y, w, lam, z, xi, eta, occulter=True)
+        return (np.abs(u) ** 2).sum()
+
+    u = oracle.fresnel_direct(x, y, w, lam, z, xi, eta, occulter=True)
+    gx, gy, gw = oracle.fresnel_direct_vjp(x, y, w, lam, z, xi, eta, 2 * u, occulter=True)
+    h = 1e-6
+    for j in (0, 7, 19):
+        for arr, gref in ((x, gx), (y, gy), (w, gw)):
+            p = arr.copy(); p[j] += h
+            mm = arr.copy(); mm[j] -= h
+            args_p = [p if a is arr else a for a in (x, y, w)]
+            args_m = [mm if a is arr else a for a in (x, y, w)]
+            fd = (loss(*args_p) - loss(*args_m)) / (2 * h)
+            assert abs(fd - gref[j]) < 1e-6 * max(1.0, abs(gref[j]))
+
+
+def test_starshade_vjp_chain_rule():
+    # <g_coef, dc> must equal sum_j gx dx + gy dy + gw dw for nodes moved by dc
+    wl = workloads.workload(5, reduced=True)
+    s = wl.shape
+    Np, K = 6, 3
+    m, np_, nd, md = 12, 8, 30, 12
+    g = np.random.Generator(np.random.PCG64(13))
+    coef = g.normal(0, 1e-2, 2 * Np * K)
+    x, y, w = oracle.quad_starshade(Np, s.a, s.R, s.b, s.p, m, np_, nd, md, coef, K)
+    gx, gy, gw = g.normal(size=(3, len(x)))
+    gc = oracle.starshade_vjp(Np, s.a, s.R, s.b, s.p, m, np_, nd, md, coef, K, gx, gy, gw)
+    h = 1e-6
+    for idx in (0, 4, 2 * K + 1, 2 * Np * K - 1):
+        cp = coef.copy(); cp[idx] += h
+        cm = coef.copy(); cm[idx] -= h
+        xp, yp, wp = oracle.quad_starshade(Np, s.a, s.R, s.b, s.p, m, np_, nd, md, cp, K)
+        xm, ym, wm = oracle.quad_starshade(Np, s.a, s.R, s.b, s.p, m, np_, nd, md, cm, K)
+        fd = ((gx * (xp - xm)).sum() + (gy * (yp - ym)).sum() + (gw * (wp - wm)).sum()) / (2 * h)
+        assert abs(fd - gc[idx]) < 1e-7 * max(1.0, abs(gc[idx])), idx
