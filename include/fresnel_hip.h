@@ -1,0 +1,235 @@
+/*
+ * fresnel_hip.h -- C ABI of libfresnel_hip.so: fast scalar Fresnel diffraction
+ * from binary planar apertures and occulters on AMD Instinct MI355X (gfx950).
+ *
+ * Method (Barnett, arXiv:2010.05978):
+ *   The field of an aperture Omega at target (xi, eta) is the Fresnel integral
+ *     u_ap = 1/(i lambda z) iint_Omega exp(i pi |(xi,eta)-(x,y)|^2/(lambda z)) dx dy
+ *   (eq. fres; the plane propagation phase exp(2 pi i z/lambda) is dropped, as in
+ *   sec. 2).  For an occulter, Babinet gives u_oc = 1 - u_ap (eq. bab).
+ *   An areal quadrature (x_j, y_j, w_j) of Omega (eq. aq) turns the integral
+ *   into the sum of eq. faq, which factorises (eq. split) into a source chirp
+ *   c_j = exp(i pi |x_j|^2/(lambda z)) w_j, a 2D nonuniform FFT (type 3 for
+ *   scattered targets, eq. nufft3 / sec. 2.1; type 1 for a uniform target grid,
+ *   sec. 2.2), and a target chirp exp(i pi |xi_k|^2/(lambda z))/(i lambda z).
+ *
+ * Conventions used by every call:
+ *   - Every call returns an fh_status; FH_OK is 0.  No C++ exception crosses
+ *     the ABI.  On failure a message is available from fh_last_error() (thread
+ *     local, valid until the next failing call on the same thread).
+ *   - Lengths are metres (any consistent unit works; only lambda*z enters).
+ *   - Complex arrays are interleaved (re, im).  In FH_FP64 contexts complex
+ *     values are double (complex128); in FH_MIXED contexts the fields and
+ *     field cotangents are float (complex64).  Node coordinates and weights
+ *     are always double.
+ *   - fh_memspace says where a caller pointer lives: FH_MEM_HOST (pageable
+ *     or pinned host memory; the call copies and synchronises) or
+ *     FH_MEM_DEVICE (device memory on the context's device; work is
+ *     enqueued on the context's stream and the call returns without
+ *     synchronising, except where noted).
+ *   - Caller buffers are owned by the caller.  fh_ctx and fh_quad objects are
+ *     owned by the library and released with fh_destroy / fh_quad_destroy.
+ *   - One context per host thread and stream; calls on one context are
+ *     serialised on its stream.
+ *   - Empty inputs: a quadrature with N = 0 nodes gives u_ap = 0 (u_oc = 1);
+ *     M = 0 targets is a no-op.  Nodes outside Omega and negative weights are
+ *     legal (sec. 3.1 allows them for non-star-shaped domains).
+ */
+#ifndef FRESNEL_HIP_H
+#define FRESNEL_HIP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum fh_status {
+    FH_OK = 0,
+    FH_ERR_INVALID_ARG = 1,    /* null pointer, negative size, bad option   */
+    FH_ERR_ODD_GRID = 2,       /* target grid sizes must be even (sec. 2.2)  */
+    FH_ERR_NONPOSITIVE_LZ = 3, /* lambda * z must be > 0                     */
+    FH_ERR_NONFINITE = 4,      /* NaN or Inf scalar argument                 */
+    FH_ERR_ALLOC = 5,          /* device memory exhausted (or capped)        */
+    FH_ERR_HIP = 6,            /* HIP runtime error                          */
+    FH_ERR_FFT = 7,            /* rocFFT plan or execution error             */
+    FH_ERR_UNSUPPORTED = 8     /* valid request outside the implemented range */
+} fh_status;
+
+typedef enum fh_precision {
+    FH_FP64 = 0,  /* spreading, FFT and outputs in double                    */
+    FH_MIXED = 1  /* spreading and FFT in float with float accumulation;     */
+                  /* chirp phases and node rescaling in double               */
+} fh_precision;
+
+typedef enum fh_memspace { FH_MEM_HOST = 0, FH_MEM_DEVICE = 1 } fh_memspace;
+
+typedef struct fh_ctx fh_ctx;
+typedef struct fh_quad fh_quad;
+
+/* NUFFT and spreading options.  Zero in any field means "choose
+ * automatically".  The exponential-of-semicircle kernel
+ * phi(z) = exp(beta (sqrt(1 - z^2) - 1)) on |z| <= 1 spans kernel_width
+ * fine-grid cells; sigma is the fine-grid upsampling factor (2 or 1.25, the
+ * two factors the paper reports for its FFTs, sec. 3.1). */
+typedef struct fh_options {
+    double sigma;           /* 2.0 or 1.25                                   */
+    int32_t kernel_width;   /* 2..16 cells                                   */
+    double beta;            /* kernel shape parameter                        */
+    int32_t tile;           /* spread tile edge in cells: 8, 16, 32 or 64    */
+    int32_t max_subproblem; /* max nonuniform points per spread work item    */
+    int32_t spread_method;  /* 1: thread per point, 2: wavefront per point   */
+} fh_options;
+
+/* ---------------------------------------------------------------- context */
+
+/* Create a context on HIP device `device` with precision `prec` and target
+ * accuracy `tol` (the relative L2 error of the field against the exact
+ * quadrature sum; e.g. 1e-9 for FH_FP64, 1e-5 for FH_MIXED).  `opt` may be
+ * NULL.  The context owns a stream-ordered workspace, cached FFT plans and
+ * kernel tables; it starts on the device's null stream. */
+fh_status fh_create(fh_ctx** out, int device, fh_precision prec, double tol,
+                    const fh_options* opt);
+fh_status fh_destroy(fh_ctx* ctx);
+/* Bind the context to a HIP stream (hipStream_t passed as void*).  The
+ * previous stream is synchronised first. */
+fh_status fh_set_stream(fh_ctx* ctx, void* hip_stream);
+/* Block until all work enqueued by the context has finished. */
+fh_status fh_synchronize(fh_ctx* ctx);
+/* Replace the NUFFT/spread options (NULL restores automatic choices). */
+fh_status fh_set_options(fh_ctx* ctx, const fh_options* opt);
+/* Report the kernel parameters a type-1 call with an n-point grid would
+ * use: kernel width, beta, sigma and fine-grid size. */
+fh_status fh_query_params(const fh_ctx* ctx, int32_t n, int32_t* width, double* beta,
+                          double* sigma, int32_t* nf);
+const char* fh_status_string(fh_status s);
+const char* fh_last_error(void);
+
+/* ------------------------------------------------------------- quadrature
+ * Each generator runs on the device and returns a library-owned areal rule
+ * (x_j, y_j, w_j), j = 0..N-1, in double. */
+
+/* Dilation rule (sec. 3.1, eqs. aqnod/aqwei) from a caller-supplied vector
+ * line-integral rule (eq. vliq) on the boundary: nodes (X_i, Y_i) and vector
+ * weights (W_i, V_i), i = 0..n-1, counter-clockwise.  m radial
+ * Gauss-Legendre nodes on (0,1); node j = l + i m, N = n m. */
+fh_status fh_quad_from_boundary(fh_ctx* ctx, const double* X, const double* Y,
+                                const double* W, const double* V, int64_t n, int32_t m,
+                                fh_memspace mem, fh_quad** out);
+
+/* Star-shaped curve x(t) = r(t)(cos t, sin t), r(t) = r0 + sum_{k=1}^{K}
+ * a[k-1] cos kt + b[k-1] sin kt (host arrays; a or b may be NULL for zeros;
+ * K <= 64).  Boundary rule: `panels` equal panels in t with q Gauss-Legendre
+ * nodes each (eq. vliq1 with Gauss-Legendre in place of the trapezoid rule);
+ * panels = 0 selects the periodic trapezoid rule of eq. ptr with q nodes.
+ * Then the dilation rule with m radial nodes.  N = panels q m (or q m). */
+fh_status fh_quad_radial(fh_ctx* ctx, double r0, const double* a, const double* b,
+                         int32_t K, int32_t panels, int32_t q, int32_t m, fh_quad** out);
+
+/* Polygon with nv >= 3 CCW vertices (host arrays), q Gauss-Legendre nodes
+ * per edge, m radial nodes.  N = nv q m. */
+fh_status fh_quad_polygon(fh_ctx* ctx, const double* vx, const double* vy, int32_t nv,
+                          int32_t q, int32_t m, fh_quad** out);
+
+/* Starshade disc + petal rule (sec. 3.2, eq. Omega): Np petals, disc radius
+ * a, tip radius R, apodisation A(r) = exp(-((r-a)/b)^p) on (a, R).  Disc:
+ * periodic trapezoid rule with nd boundary nodes and md radial nodes.
+ * Petal k (centre angle 2 pi k/Np): m Gauss-Legendre radii on (a, R) times
+ * np Gauss-Legendre angles across the petal width 2 pi A(r)/Np, weight
+ * r w_r (pi A(r)/Np) w_t.  N = nd md + Np np m; disc nodes first, then
+ * petals, angular index outer and radial index inner.
+ * Optional edge perturbation: coef (2 Np K doubles, in memory `coef_mem`, or
+ * NULL) moves petal k's upper edge outward by the arc length
+ * d+(r) = sum_s coef[2kK+s-1] sin(s pi (r-a)/(R-a)) and its lower edge by
+ * d-(r) = sum_s coef[2kK+K+s-1] sin(s pi (r-a)/(R-a)), s = 1..K <= 64. */
+fh_status fh_quad_starshade(fh_ctx* ctx, int32_t Np, double a, double R, double b, double p,
+                            int32_t m, int32_t np, int32_t nd, int32_t md,
+                            const double* coef, int32_t K, fh_memspace coef_mem,
+                            fh_quad** out);
+
+/* Raw areal rule (eq. aq): N nodes and weights, copied into a new object. */
+fh_status fh_quad_from_nodes(fh_ctx* ctx, const double* x, const double* y, const double* w,
+                             int64_t N, fh_memspace mem, fh_quad** out);
+
+fh_status fh_quad_size(const fh_quad* q, int64_t* N);
+/* Copy the rule out (x, y, w each N doubles; any may be NULL). */
+fh_status fh_quad_export(const fh_quad* q, double* x, double* y, double* w, fh_memspace mem);
+/* Device pointers of the rule's arrays (owned by the object). */
+fh_status fh_quad_device_ptrs(const fh_quad* q, const double** x, const double** y,
+                              const double** w);
+fh_status fh_quad_destroy(fh_quad* q);
+
+/* ------------------------------------------------------------------ fields */
+
+/* Field on the uniform grid (sec. 2.2, type-1 NUFFT): targets
+ * (xc + h1 k1, yc + h2 k2), -n1/2 <= k1 < n1/2, -n2/2 <= k2 < n2/2, n1 and
+ * n2 even.  A translated grid (xc, yc != 0) is handled by pre-phasing the
+ * strengths.  Output u[(k2 + n2/2) n1 + (k1 + n1/2)] (k1 fastest), complex
+ * in the context's precision.  occulter != 0 returns u_oc = 1 - u_ap. */
+fh_status fh_field_grid(fh_ctx* ctx, const fh_quad* q, double lambda, double z,
+                        int32_t n1, int32_t n2, double h1, double h2, double xc, double yc,
+                        int32_t occulter, void* u, fh_memspace mem);
+
+/* Field at M scattered targets (xi_k, eta_k) (sec. 2.1, type-3 NUFFT).  xi,
+ * eta and u are all in `mem`.  This call reads the target bounding box back
+ * to the host to size the fine grid, so it synchronises the stream once. */
+fh_status fh_field_points(fh_ctx* ctx, const fh_quad* q, double lambda, double z, int64_t M,
+                          const double* xi, const double* eta, int32_t occulter, void* u,
+                          fh_memspace mem);
+
+/* B grid fields in one batched pass: instance b uses rule q[b], lambda[b],
+ * z[b] and occulter[b] (host arrays of length B), all on the same grid
+ * parameters.  u (device, B n1 n2 complex) is written instance-major.  All
+ * instances share one fine-grid size; the spread runs as one persistent
+ * launch over every instance's work items, the FFT is one batched rocFFT
+ * call, and the sequence is captured once into a hipGraph keyed by the batch
+ * signature and replayed on later calls with the same signature. */
+fh_status fh_field_grid_batch(fh_ctx* ctx, int32_t B, const fh_quad* const* q,
+                              const double* lambda, const double* z, int32_t n1, int32_t n2,
+                              double h1, double h2, double xc, double yc,
+                              const int32_t* occulter, void* u);
+
+/* ----------------------------------------------------------------- adjoint */
+
+/* Vector-Jacobian product of fh_field_grid with respect to the rule's nodes
+ * and weights.  g_u (device, same layout and precision as the field) holds
+ * dL/dRe(u) + i dL/dIm(u) for a real loss L.  Outputs (device doubles, N
+ * each): dL/dx_j, dL/dy_j, dL/dw_j.  Derivation: du_k/dw_j =
+ * E_kj/(i lambda z), du_k/dx_j = (w_j/(i lambda z)) E_kj (2 pi i/(lambda z))
+ * (x_j - xi_k) with E_kj the Fresnel kernel of eq. faq; the sums over k are
+ * evaluated as three type-2 NUFFTs sharing one set of kernel weights. */
+fh_status fh_field_grid_vjp(fh_ctx* ctx, const fh_quad* q, double lambda, double z,
+                            int32_t n1, int32_t n2, double h1, double h2, double xc, double yc,
+                            int32_t occulter, const void* g_u, double* g_x, double* g_y,
+                            double* g_w);
+
+/* Chain (dL/dx, dL/dy, dL/dw) of a perturbed starshade rule (same
+ * parameters as fh_quad_starshade; all arrays on the device) to dL/dcoef
+ * (2 Np K doubles). */
+fh_status fh_starshade_vjp(fh_ctx* ctx, int32_t Np, double a, double R, double b, double p,
+                           int32_t m, int32_t np, int32_t nd, int32_t md, const double* coef,
+                           int32_t K, const double* g_x, const double* g_y, const double* g_w,
+                           double* g_coef);
+
+/* --------------------------------------------------------------- autotuner */
+
+/* Time fh_field_grid for this rule and grid over a set of tile sizes,
+ * subproblem sizes, spread methods and upsampling factors that all meet the
+ * context's tolerance; keep the fastest in the context and return it in
+ * *best.  If cache_path is not NULL the result is read from / appended to
+ * that JSON-lines file, keyed by precision, tolerance, grid size and node
+ * count class. */
+fh_status fh_autotune_grid(fh_ctx* ctx, const fh_quad* q, double lambda, double z, int32_t n1,
+                           int32_t n2, double h1, double h2, const char* cache_path,
+                           fh_options* best);
+
+/* Device time in milliseconds of the stages of the most recent field call
+ * on this context, when timing is enabled (FH_TIMING=1 in the environment
+ * at fh_create): [0] prep+bin, [1] spread, [2] FFT, [3] epilogue or
+ * interpolation, [4] total.  Synchronises the stream. */
+fh_status fh_last_timing(fh_ctx* ctx, double* ms5);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FRESNEL_HIP_H */

@@ -1,0 +1,156 @@
+"""MI355X-native fast Fresnel diffraction (Barnett, arXiv:2010.05978).
+
+The compute path lives in ``libfresnel_hip.so`` (HIP kernels for gfx950 plus
+rocFFT) behind the C ABI of ``include/fresnel_hip.h``.  This package is the
+Python binding: ``_binding`` mirrors the C entry points one to one, and
+``Context``/``Quad`` below only allocate torch tensors for outputs and pass
+pointers and the current torch stream through.  There is no fallback: if the
+library is missing, using the package raises.
+"""
+from __future__ import annotations
+
+from ._binding import (  # noqa: F401
+    EXPORTED, FH_ERR_ALLOC, FH_ERR_FFT, FH_ERR_HIP, FH_ERR_INVALID_ARG, FH_ERR_NONFINITE,
+    FH_ERR_NONPOSITIVE_LZ, FH_ERR_ODD_GRID, FH_ERR_UNSUPPORTED, FH_FP64, FH_MEM_DEVICE, FH_MEM_HOST,
+    FH_MIXED, FH_OK, LIB_PATH, FresnelError, fh_options, lib,
+)
+from . import _binding as abi  # noqa: F401
+
+__all__ = ["Context", "Quad", "FresnelError", "fh_options", "abi", "lib", "LIB_PATH"]
+
+
+class Quad:
+    """A device-resident areal quadrature rule owned by the library."""
+
+    def __init__(self, ctx: "Context", handle):
+        self.ctx = ctx
+        self.handle = handle
+
+    @property
+    def N(self) -> int:
+        return abi.fh_quad_size(self.handle)
+
+    def export(self):
+        """(x, y, w) as float64 device tensors (copies)."""
+        import torch
+        n = self.N
+        out = [torch.empty(n, dtype=torch.float64, device=self.ctx.device) for _ in range(3)]
+        abi.fh_quad_export(self.handle, *out)
+        return tuple(out)
+
+    def close(self):
+        # a rule's device memory belongs to its context; once the context is
+        # gone there is nothing left to release
+        if self.handle is not None and self.ctx.handle is not None:
+            abi.fh_quad_destroy(self.handle)
+        self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Context:
+    """A library context bound to the current torch stream of one GPU."""
+
+    def __init__(self, precision: str = "fp64", tol: float | None = None, device: int = 0,
+                 options: fh_options | None = None):
+        import torch
+        if precision not in ("fp64", "mixed"):
+            raise ValueError("precision must be 'fp64' or 'mixed'")
+        if not torch.cuda.is_available():
+            raise RuntimeError("no HIP device visible to torch")
+        self.precision = precision
+        self.tol = tol if tol is not None else (1e-9 if precision == "fp64" else 1e-5)
+        self.device = torch.device("cuda", device)
+        self.cdtype = torch.complex128 if precision == "fp64" else torch.complex64
+        self.handle = abi.fh_create(device, FH_FP64 if precision == "fp64" else FH_MIXED, self.tol, options)
+        abi.fh_set_stream(self.handle, torch.cuda.current_stream(self.device))
+
+    # ------------------------------------------------------- quadrature
+    def quad_radial(self, r0, a=None, b=None, panels=1, q=20, m=10) -> Quad:
+        return Quad(self, abi.fh_quad_radial(self.handle, r0, a, b, panels, q, m))
+
+    def quad_polygon(self, vx, vy, q, m) -> Quad:
+        return Quad(self, abi.fh_quad_polygon(self.handle, vx, vy, q, m))
+
+    def quad_starshade(self, Np, a, R, b, p, m, np_, nd, md, coef=None, K=0) -> Quad:
+        return Quad(self, abi.fh_quad_starshade(self.handle, Np, a, R, b, p, m, np_, nd, md, coef, K))
+
+    def quad_from_boundary(self, X, Y, W, V, m) -> Quad:
+        return Quad(self, abi.fh_quad_from_boundary(self.handle, X, Y, W, V, m))
+
+    def quad_from_nodes(self, x, y, w) -> Quad:
+        return Quad(self, abi.fh_quad_from_nodes(self.handle, x, y, w))
+
+    def quad_for(self, shape) -> Quad:
+        """Rule for a shape description with the attributes of workloads.py's
+        RadialCurve / Polygon / Starshade."""
+        kind = type(shape).__name__
+        if kind == "RadialCurve":
+            a = shape.a if len(shape.a) else None
+            b = shape.b if len(shape.b) else None
+            return self.quad_radial(shape.r0, a, b, shape.panels, shape.q, shape.m)
+        if kind == "Polygon":
+            return self.quad_polygon(shape.vx, shape.vy, shape.q, shape.m)
+        if kind == "Starshade":
+            return self.quad_starshade(shape.Np, shape.a, shape.R, shape.b, shape.p, shape.m, shape.np_,
+                                       shape.nd, shape.md, shape.coef, shape.K)
+        raise TypeError(f"unknown shape {kind}")
+
+    # ------------------------------------------------------------ fields
+    def field_grid(self, quad: Quad, lam, z, n1, n2, h1, h2, xc=0.0, yc=0.0, occulter=False, out=None):
+        import torch
+        if out is None:
+            out = torch.empty((n2, n1), dtype=self.cdtype, device=self.device)
+        abi.fh_field_grid(self.handle, quad.handle, lam, z, n1, n2, h1, h2, xc, yc, occulter, out)
+        return out
+
+    def field_points(self, quad: Quad, lam, z, xi, eta, occulter=False, out=None):
+        import torch
+        if out is None:
+            dev = xi.device if hasattr(xi, "device") else self.device
+            out = torch.empty(len(xi), dtype=self.cdtype, device=dev)
+        abi.fh_field_points(self.handle, quad.handle, lam, z, xi, eta, occulter, out)
+        return out
+
+    def field_grid_batch(self, quads, lams, zs, n1, n2, h1, h2, xc=0.0, yc=0.0, occulter=False, out=None):
+        import torch
+        if out is None:
+            out = torch.empty((len(quads), n2, n1), dtype=self.cdtype, device=self.device)
+        abi.fh_field_grid_batch(self.handle, [q.handle for q in quads], lams, zs, n1, n2, h1, h2, xc, yc,
+                                occulter, out)
+        return out
+
+    def field_grid_vjp(self, quad: Quad, lam, z, n1, n2, h1, h2, g_u, xc=0.0, yc=0.0, occulter=False):
+        import torch
+        n = quad.N
+        gx, gy, gw = (torch.empty(n, dtype=torch.float64, device=self.device) for _ in range(3))
+        abi.fh_field_grid_vjp(self.handle, quad.handle, lam, z, n1, n2, h1, h2, xc, yc, occulter,
+                              g_u.contiguous(), gx, gy, gw)
+        return gx, gy, gw
+
+    def query_params(self, n):
+        return abi.fh_query_params(self.handle, n)
+
+    def set_options(self, options: fh_options | None):
+        abi.fh_set_options(self.handle, options)
+
+    def synchronize(self):
+        abi.fh_synchronize(self.handle)
+
+    def last_timing(self):
+        return abi.fh_last_timing(self.handle)
+
+    def close(self):
+        if self.handle is not None:
+            abi.fh_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

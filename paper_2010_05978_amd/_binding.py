@@ -1,0 +1,304 @@
+"""ctypes binding of libfresnel_hip.so (argument marshalling only).
+
+Every function here has the name of the C entry point it calls and does no
+arithmetic of the method: all steps run in the library's HIP kernels.  Arrays
+may be torch tensors (device or host) or numpy arrays (host); the memory space
+argument of the C call follows from where the array lives.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libfresnel_hip.so")
+
+FH_OK = 0
+FH_ERR_INVALID_ARG = 1
+FH_ERR_ODD_GRID = 2
+FH_ERR_NONPOSITIVE_LZ = 3
+FH_ERR_NONFINITE = 4
+FH_ERR_ALLOC = 5
+FH_ERR_HIP = 6
+FH_ERR_FFT = 7
+FH_ERR_UNSUPPORTED = 8
+
+FH_FP64 = 0
+FH_MIXED = 1
+FH_MEM_HOST = 0
+FH_MEM_DEVICE = 1
+
+EXPORTED = [
+    "fh_create", "fh_destroy", "fh_set_stream", "fh_synchronize", "fh_set_options", "fh_query_params",
+    "fh_status_string", "fh_last_error", "fh_quad_from_boundary", "fh_quad_radial", "fh_quad_polygon",
+    "fh_quad_starshade", "fh_quad_from_nodes", "fh_quad_size", "fh_quad_export", "fh_quad_device_ptrs",
+    "fh_quad_destroy", "fh_field_grid", "fh_field_points", "fh_field_grid_batch", "fh_field_grid_vjp",
+    "fh_starshade_vjp", "fh_autotune_grid", "fh_last_timing",
+]
+
+
+class FresnelError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        self.status = status
+        super().__init__(f"{_status_name(status)}: {message}")
+
+
+class fh_options(ctypes.Structure):
+    _fields_ = [("sigma", ctypes.c_double), ("kernel_width", ctypes.c_int32), ("beta", ctypes.c_double),
+                ("tile", ctypes.c_int32), ("max_subproblem", ctypes.c_int32), ("spread_method", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """Load the shared library; raise if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_2010_05978_amd.build` (hipcc, gfx950)")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64, d = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+        pvp = ctypes.POINTER(ctypes.c_void_p)
+        sig = {
+            "fh_create": [pvp, ctypes.c_int, ctypes.c_int, d, ctypes.POINTER(fh_options)],
+            "fh_destroy": [vp],
+            "fh_set_stream": [vp, vp],
+            "fh_synchronize": [vp],
+            "fh_set_options": [vp, ctypes.POINTER(fh_options)],
+            "fh_query_params": [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(d), ctypes.POINTER(d),
+                                ctypes.POINTER(i32)],
+            "fh_quad_from_boundary": [vp, vp, vp, vp, vp, i64, i32, ctypes.c_int, pvp],
+            "fh_quad_radial": [vp, d, vp, vp, i32, i32, i32, i32, pvp],
+            "fh_quad_polygon": [vp, vp, vp, i32, i32, i32, pvp],
+            "fh_quad_starshade": [vp, i32, d, d, d, d, i32, i32, i32, i32, vp, i32, ctypes.c_int, pvp],
+            "fh_quad_from_nodes": [vp, vp, vp, vp, i64, ctypes.c_int, pvp],
+            "fh_quad_size": [vp, ctypes.POINTER(i64)],
+            "fh_quad_export": [vp, vp, vp, vp, ctypes.c_int],
+            "fh_quad_device_ptrs": [vp, pvp, pvp, pvp],
+            "fh_quad_destroy": [vp],
+            "fh_field_grid": [vp, vp, d, d, i32, i32, d, d, d, d, i32, vp, ctypes.c_int],
+            "fh_field_points": [vp, vp, d, d, i64, vp, vp, i32, vp, ctypes.c_int],
+            "fh_field_grid_batch": [vp, i32, vp, vp, vp, i32, i32, d, d, d, d, vp, vp],
+            "fh_field_grid_vjp": [vp, vp, d, d, i32, i32, d, d, d, d, i32, vp, vp, vp, vp],
+            "fh_starshade_vjp": [vp, i32, d, d, d, d, i32, i32, i32, i32, vp, i32, vp, vp, vp, vp],
+            "fh_autotune_grid": [vp, vp, d, d, i32, i32, d, d, ctypes.c_char_p, ctypes.POINTER(fh_options)],
+            "fh_last_timing": [vp, ctypes.POINTER(d)],
+        }
+        for name, args in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = ctypes.c_int
+        L.fh_status_string.argtypes = [ctypes.c_int]
+        L.fh_status_string.restype = ctypes.c_char_p
+        L.fh_last_error.argtypes = []
+        L.fh_last_error.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def _status_name(s: int) -> str:
+    try:
+        return lib().fh_status_string(s).decode()
+    except Exception:  # pragma: no cover
+        return f"status {s}"
+
+
+def _check(status: int):
+    if status != FH_OK:
+        raise FresnelError(status, lib().fh_last_error().decode())
+
+
+# ------------------------------------------------------------ marshalling
+def _is_torch(a):
+    return type(a).__module__.startswith("torch")
+
+
+def _ptr_mem(a):
+    """(pointer, memspace) of a torch tensor or numpy array (or None)."""
+    if a is None:
+        return None, FH_MEM_HOST
+    if _is_torch(a):
+        if not a.is_contiguous():
+            raise ValueError("tensor must be contiguous")
+        return ctypes.c_void_p(a.data_ptr()), (FH_MEM_DEVICE if a.is_cuda else FH_MEM_HOST)
+    if isinstance(a, np.ndarray):
+        if not a.flags.c_contiguous:
+            raise ValueError("array must be C-contiguous")
+        return ctypes.c_void_p(a.ctypes.data), FH_MEM_HOST
+    raise TypeError(f"unsupported array type {type(a)}")
+
+
+def _same_mem(*arrays):
+    mems = {_ptr_mem(a)[1] for a in arrays if a is not None}
+    if len(mems) > 1:
+        raise ValueError("arrays must all be on the host or all on the device")
+    return mems.pop() if mems else FH_MEM_HOST
+
+
+# ----------------------------------------------------------------- calls
+def fh_create(device: int = 0, precision: int = FH_FP64, tol: float = 1e-9, options: fh_options | None = None):
+    h = ctypes.c_void_p()
+    _check(lib().fh_create(ctypes.byref(h), device, precision, tol,
+                           ctypes.byref(options) if options is not None else None))
+    return h
+
+
+def fh_destroy(ctx):
+    _check(lib().fh_destroy(ctx))
+
+
+def fh_set_stream(ctx, stream):
+    """stream: a torch.cuda.Stream, an int handle, or None for the null stream."""
+    if stream is not None and hasattr(stream, "cuda_stream"):
+        stream = stream.cuda_stream
+    _check(lib().fh_set_stream(ctx, ctypes.c_void_p(stream or 0)))
+
+
+def fh_synchronize(ctx):
+    _check(lib().fh_synchronize(ctx))
+
+
+def fh_set_options(ctx, options: fh_options | None):
+    _check(lib().fh_set_options(ctx, ctypes.byref(options) if options is not None else None))
+
+
+def fh_query_params(ctx, n: int):
+    w, beta, sigma, nf = ctypes.c_int32(), ctypes.c_double(), ctypes.c_double(), ctypes.c_int32()
+    _check(lib().fh_query_params(ctx, n, ctypes.byref(w), ctypes.byref(beta), ctypes.byref(sigma),
+                                 ctypes.byref(nf)))
+    return {"width": w.value, "beta": beta.value, "sigma": sigma.value, "nf": nf.value}
+
+
+def fh_status_string(s: int) -> str:
+    return lib().fh_status_string(s).decode()
+
+
+def fh_last_error() -> str:
+    return lib().fh_last_error().decode()
+
+
+def _new_quad():
+    return ctypes.c_void_p()
+
+
+def fh_quad_from_boundary(ctx, X, Y, W, V, m: int):
+    mem = _same_mem(X, Y, W, V)
+    q = _new_quad()
+    _check(lib().fh_quad_from_boundary(ctx, _ptr_mem(X)[0], _ptr_mem(Y)[0], _ptr_mem(W)[0], _ptr_mem(V)[0],
+                                       len(X), m, mem, ctypes.byref(q)))
+    return q
+
+
+def fh_quad_radial(ctx, r0: float, a=None, b=None, panels: int = 1, q: int = 20, m: int = 10):
+    K = 0 if a is None else len(a)
+    a = None if a is None else np.ascontiguousarray(a, dtype=np.float64)
+    b = None if b is None else np.ascontiguousarray(b, dtype=np.float64)
+    if b is not None and len(b) != K:
+        raise ValueError("a and b must have the same length")
+    h = _new_quad()
+    _check(lib().fh_quad_radial(ctx, r0, _ptr_mem(a)[0], _ptr_mem(b)[0], K, panels, q, m, ctypes.byref(h)))
+    return h
+
+
+def fh_quad_polygon(ctx, vx, vy, q: int, m: int):
+    vx = np.ascontiguousarray(vx, dtype=np.float64)
+    vy = np.ascontiguousarray(vy, dtype=np.float64)
+    h = _new_quad()
+    _check(lib().fh_quad_polygon(ctx, _ptr_mem(vx)[0], _ptr_mem(vy)[0], len(vx), q, m, ctypes.byref(h)))
+    return h
+
+
+def fh_quad_starshade(ctx, Np, a, R, b, p, m, np_, nd, md, coef=None, K=0):
+    if coef is not None and not _is_torch(coef):
+        coef = np.ascontiguousarray(coef, dtype=np.float64)
+    ptr, mem = _ptr_mem(coef)
+    h = _new_quad()
+    _check(lib().fh_quad_starshade(ctx, Np, a, R, b, p, m, np_, nd, md, ptr, K if coef is not None else 0,
+                                   mem, ctypes.byref(h)))
+    return h
+
+
+def fh_quad_from_nodes(ctx, x, y, w):
+    mem = _same_mem(x, y, w)
+    h = _new_quad()
+    _check(lib().fh_quad_from_nodes(ctx, _ptr_mem(x)[0], _ptr_mem(y)[0], _ptr_mem(w)[0], len(x), mem,
+                                    ctypes.byref(h)))
+    return h
+
+
+def fh_quad_size(q) -> int:
+    n = ctypes.c_int64()
+    _check(lib().fh_quad_size(q, ctypes.byref(n)))
+    return n.value
+
+
+def fh_quad_export(q, x=None, y=None, w=None):
+    mem = _same_mem(x, y, w)
+    _check(lib().fh_quad_export(q, _ptr_mem(x)[0], _ptr_mem(y)[0], _ptr_mem(w)[0], mem))
+
+
+def fh_quad_device_ptrs(q):
+    x, y, w = ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_void_p()
+    _check(lib().fh_quad_device_ptrs(q, ctypes.byref(x), ctypes.byref(y), ctypes.byref(w)))
+    return x.value, y.value, w.value
+
+
+def fh_quad_destroy(q):
+    _check(lib().fh_quad_destroy(q))
+
+
+def fh_field_grid(ctx, q, lam, z, n1, n2, h1, h2, xc, yc, occulter, u):
+    ptr, mem = _ptr_mem(u)
+    _check(lib().fh_field_grid(ctx, q, lam, z, n1, n2, h1, h2, xc, yc, int(bool(occulter)), ptr, mem))
+
+
+def fh_field_points(ctx, q, lam, z, xi, eta, occulter, u):
+    mem = _same_mem(xi, eta, u)
+    _check(lib().fh_field_points(ctx, q, lam, z, len(xi), _ptr_mem(xi)[0], _ptr_mem(eta)[0],
+                                 int(bool(occulter)), _ptr_mem(u)[0], mem))
+
+
+def fh_field_grid_batch(ctx, quads, lams, zs, n1, n2, h1, h2, xc, yc, occulter, u):
+    B = len(quads)
+    qarr = (ctypes.c_void_p * B)(*[q.value if isinstance(q, ctypes.c_void_p) else q for q in quads])
+    la = np.ascontiguousarray(lams, dtype=np.float64)
+    za = np.ascontiguousarray(zs, dtype=np.float64)
+    oc = np.ascontiguousarray(np.broadcast_to(np.asarray(occulter, dtype=np.int32), (B,)))
+    ptr, mem = _ptr_mem(u)
+    if mem != FH_MEM_DEVICE:
+        raise ValueError("fh_field_grid_batch writes device memory only")
+    _check(lib().fh_field_grid_batch(ctx, B, ctypes.cast(qarr, ctypes.c_void_p), _ptr_mem(la)[0],
+                                     _ptr_mem(za)[0], n1, n2, h1, h2, xc, yc, _ptr_mem(oc)[0], ptr))
+
+
+def fh_field_grid_vjp(ctx, q, lam, z, n1, n2, h1, h2, xc, yc, occulter, g_u, g_x, g_y, g_w):
+    for a in (g_u, g_x, g_y, g_w):
+        if _ptr_mem(a)[1] != FH_MEM_DEVICE:
+            raise ValueError("fh_field_grid_vjp takes device arrays")
+    _check(lib().fh_field_grid_vjp(ctx, q, lam, z, n1, n2, h1, h2, xc, yc, int(bool(occulter)),
+                                   _ptr_mem(g_u)[0], _ptr_mem(g_x)[0], _ptr_mem(g_y)[0], _ptr_mem(g_w)[0]))
+
+
+def fh_starshade_vjp(ctx, Np, a, R, b, p, m, np_, nd, md, coef, K, g_x, g_y, g_w, g_coef):
+    for t in (coef, g_x, g_y, g_w, g_coef):
+        if _ptr_mem(t)[1] != FH_MEM_DEVICE:
+            raise ValueError("fh_starshade_vjp takes device arrays")
+    _check(lib().fh_starshade_vjp(ctx, Np, a, R, b, p, m, np_, nd, md, _ptr_mem(coef)[0], K,
+                                  _ptr_mem(g_x)[0], _ptr_mem(g_y)[0], _ptr_mem(g_w)[0], _ptr_mem(g_coef)[0]))
+
+
+def fh_autotune_grid(ctx, q, lam, z, n1, n2, h1, h2, cache_path=None):
+    best = fh_options()
+    cp = cache_path.encode() if cache_path else None
+    _check(lib().fh_autotune_grid(ctx, q, lam, z, n1, n2, h1, h2, cp, ctypes.byref(best)))
+    return best
+
+
+def fh_last_timing(ctx):
+    arr = (ctypes.c_double * 5)()
+    _check(lib().fh_last_timing(ctx, arr))
+    return list(arr)

@@ -1,0 +1,197 @@
+// fh_common.hpp -- internal declarations of libfresnel_hip (not installed).
+//
+// Shared between the host-side control code and the HIP kernels: the context
+// and quadrature objects, workspace arena, error reporting, kernel-parameter
+// structs and the small helpers that several translation units need.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <rocfft/rocfft.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <map>
+#include <memory>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "fresnel_hip.h"
+
+namespace fh {
+
+// ------------------------------------------------------------------ errors
+void set_error(const char* fmt, ...) __attribute__((format(printf, 1, 2)));
+
+#define FH_HIP(call)                                                                  \
+    do {                                                                              \
+        hipError_t e_ = (call);                                                       \
+        if (e_ != hipSuccess) {                                                       \
+            ::fh::set_error("%s failed: %s (%s:%d)", #call, hipGetErrorString(e_),    \
+                            __FILE__, __LINE__);                                      \
+            return (e_ == hipErrorOutOfMemory) ? FH_ERR_ALLOC : FH_ERR_HIP;           \
+        }                                                                             \
+    } while (0)
+
+#define FH_TRY(call)                        \
+    do {                                    \
+        fh_status s_ = (call);              \
+        if (s_ != FH_OK) return s_;         \
+    } while (0)
+
+#define FH_ARG(cond, code, ...)             \
+    do {                                    \
+        if (!(cond)) {                      \
+            ::fh::set_error(__VA_ARGS__);   \
+            return code;                    \
+        }                                   \
+    } while (0)
+
+constexpr double kPi = 3.14159265358979323846264338327950288;
+constexpr int kMaxWidth = 16;
+constexpr int kMaxFourier = 64;
+
+// ------------------------------------------------------------ ES kernel
+// phi(z) = exp(beta (sqrt(1 - z^2) - 1)), |z| <= 1, spanning `w` cells.
+struct EsKernel {
+    int w = 0;
+    double beta = 0;
+    double sigma = 2.0;
+};
+
+// 1/Phi(theta) for |theta| <= theta_max as a Chebyshev series in
+// s = 2 (theta/theta_max)^2 - 1 (Phi is even and entire).
+constexpr int kMaxCheb = 96;
+struct InvPhiCheb {
+    double theta_max = 0;
+    int deg = 0;
+    double c[kMaxCheb + 1];
+};
+
+// ----------------------------------------------- per-instance prep params
+// Source-side parameters of one (quadrature, lambda, z) instance.
+//   phase in turns: t = (x^2 + y^2) pa + x px + y py + pc
+//   fine-grid coordinate: g1 = (x - cx) s1, g2 = (y - cy) s2
+struct InstParams {
+    const double* x;
+    const double* y;
+    const double* w;
+    int64_t N;
+    int64_t node_off;  // first slot of this instance in the concatenated node range
+    int32_t tile_off;  // first tile id of this instance
+    int32_t pad_;
+    double pa, px, py, pc;
+    double cx, cy, s1, s2;
+};
+
+struct GridGeom {
+    int nf1, nf2;  // fine grid (x fastest)
+    int T;         // tile edge
+    int ntx, nty;  // tiles per dimension
+    int W;         // kernel width
+    int L;         // padded tile edge T + W - 1
+    int P;         // max points per subproblem
+};
+
+struct Sub {
+    int tile;
+    int start;
+    int end;
+};
+
+// ---------------------------------------------------------- rocFFT plans
+struct FftPlan {
+    rocfft_plan plan = nullptr;
+    rocfft_execution_info info = nullptr;
+    void* work = nullptr;
+    size_t work_bytes = 0;
+};
+
+// ------------------------------------------------------------- workspace
+// One stream-ordered bump arena per context.  A call first sums what it
+// needs, grows the arena if necessary (synchronising), then carves buffers.
+struct Arena {
+    char* base = nullptr;
+    size_t cap = 0;
+    size_t used = 0;
+    void reset() { used = 0; }
+    template <class T>
+    T* take(size_t count) {
+        size_t bytes = (count * sizeof(T) + 255) & ~size_t(255);
+        T* p = reinterpret_cast<T*>(base + used);
+        used += bytes;
+        return p;
+    }
+};
+inline size_t aligned_bytes(size_t b) { return (b + 255) & ~size_t(255); }
+
+struct GraphEntry {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+}  // namespace fh
+
+// ---------------------------------------------------------------- objects
+struct fh_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    fh_precision prec = FH_FP64;
+    double tol = 1e-9;
+    fh_options opt{};
+    int cu_count = 256;
+    bool timing = false;
+    hipEvent_t ev[6]{};
+    double last_ms[5]{};
+
+    fh::Arena arena;
+    size_t alloc_cap = 0;  // optional cap on device bytes (testing)
+    size_t alloc_total = 0;
+
+    std::map<int, double*> gl_cache;  // device GL tables: x[q], w[q]
+    std::map<std::tuple<int, int, int, long long>, double*> iphi_cache;
+    std::map<std::tuple<int, int, int, int>, fh::FftPlan> fft_cache;
+    std::map<size_t, std::vector<void*>> pool;  // freed quadrature buffers by size
+    std::map<std::string, fh::GraphEntry> graph_cache;
+    std::map<void*, size_t> owned;  // every hipMalloc'd block and its size
+    double* bbox_dev = nullptr;      // bounding-box reduction scratch
+    double* bbox_host = nullptr;     // pinned readback of the box
+};
+
+struct fh_quad {
+    fh_ctx* ctx = nullptr;
+    int64_t N = 0;
+    double* buf = nullptr;  // 3 N doubles: x, y, w
+    size_t buf_bytes = 0;
+    double* x = nullptr;
+    double* y = nullptr;
+    double* w = nullptr;
+    bool bbox_valid = false;
+    double bbox[4] = {0, 0, 0, 0};  // xmin, xmax, ymin, ymax
+};
+
+namespace fh {
+// context services (fh_context.cpp)
+fh_status dev_alloc(fh_ctx* c, size_t bytes, void** p);
+fh_status dev_free(fh_ctx* c, void* p);
+fh_status arena_reserve(fh_ctx* c, size_t bytes);
+fh_status gl_table(fh_ctx* c, int q, const double** dev);  // x[q] then w[q]
+void gl_host(int q, std::vector<double>& x, std::vector<double>& w);
+EsKernel choose_kernel(const fh_ctx* c, int n_hint);
+int pick_tile(const fh_ctx* c, int nf);
+int next_fft_size(int n, int multiple);
+double phi_hat(const EsKernel& k, double theta);
+fh_status iphi_table(fh_ctx* c, const EsKernel& k, int n, int nf, const double** dev);
+void inv_phi_cheb(const EsKernel& k, double theta_max, InvPhiCheb* out);
+fh_status fft_plan(fh_ctx* c, int nf1, int nf2, int batch, FftPlan** out);
+fh_status fft_exec(fh_ctx* c, FftPlan* p, void* data);
+fh_status quad_alloc(fh_ctx* c, int64_t N, fh_quad** out);
+fh_status quad_bbox(fh_ctx* c, const fh_quad* q, double* bb);
+fh_status device_bbox(fh_ctx* c, const double* x, const double* y, int64_t n, double* bb);
+void timing_mark(fh_ctx* c, int i);
+void timing_finish(fh_ctx* c);
+
+// kernel launchers shared across translation units (fh_field.hip)
+fh_status launch_zero(fh_ctx* c, void* p, size_t bytes);
+}  // namespace fh

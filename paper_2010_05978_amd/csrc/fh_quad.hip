@@ -1,0 +1,442 @@
+// fh_quad.hip -- areal quadrature generation on the device.
+//
+// Boundary vector line-integral rules (eq. vliq): Gauss-Legendre panels in
+// angle for star-shaped curves (eq. vliq1 with Gauss-Legendre in place of the
+// trapezoid rule), the periodic trapezoid rule (eq. ptr), and Gauss-Legendre
+// nodes along polygon edges.  The dilation areal rule (eqs. aqnod/aqwei,
+// sec. 3.1) and the starshade disc + petal rule (sec. 3.2) turn them into
+// areal nodes and weights.  One thread per boundary node, then one thread per
+// areal node; every coordinate is double.
+#include <algorithm>
+#include <cstring>
+
+#include "fh_common.hpp"
+
+namespace fh {
+namespace {
+
+struct RadialParams {
+    double r0;
+    int K;
+    int panels;  // 0: periodic trapezoid rule with q nodes
+    int q;
+    double a[kMaxFourier];
+    double b[kMaxFourier];
+};
+
+// Boundary node i of the star-shaped curve r(t)(cos t, sin t).
+__global__ void k_bdry_radial(RadialParams rp, const double* __restrict__ gl, int64_t n,
+                              double* __restrict__ X, double* __restrict__ Y,
+                              double* __restrict__ Wv, double* __restrict__ Vv)
+{
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double t, om;
+    if (rp.panels > 0) {
+        const int p = (int)(i / rp.q), k = (int)(i % rp.q);
+        const double xg = gl[k], wg = gl[rp.q + k];
+        t = (2.0 * kPi / rp.panels) * (p + 0.5 * (1.0 + xg));
+        om = (kPi / rp.panels) * wg;
+    } else {
+        // trapezoid nodes t_i = 2 pi i / n, i = 1..n
+        t = 2.0 * kPi * (double)(i + 1) / (double)n;
+        om = 2.0 * kPi / (double)n;
+    }
+    double r = rp.r0, dr = 0.0;
+    for (int k = 1; k <= rp.K; ++k) {
+        double s, c;
+        sincos(k * t, &s, &c);
+        r += rp.a[k - 1] * c + rp.b[k - 1] * s;
+        dr += k * (rp.b[k - 1] * c - rp.a[k - 1] * s);
+    }
+    double st, ct;
+    sincos(t, &st, &ct);
+    X[i] = r * ct;
+    Y[i] = r * st;
+    Wv[i] = om * (dr * ct - r * st);
+    Vv[i] = om * (dr * st + r * ct);
+}
+
+// Gauss-Legendre nodes along each straight edge of a CCW polygon.
+__global__ void k_bdry_polygon(const double* __restrict__ vx, const double* __restrict__ vy, int nv,
+                               int q, const double* __restrict__ gl, double* __restrict__ X,
+                               double* __restrict__ Y, double* __restrict__ Wv,
+                               double* __restrict__ Vv)
+{
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= (int64_t)nv * q) return;
+    const int e = (int)(i / q), k = (int)(i % q);
+    const int f = (e + 1 == nv) ? 0 : e + 1;
+    const double ex = vx[f] - vx[e], ey = vy[f] - vy[e];
+    const double s = 0.5 * (1.0 + gl[k]);
+    const double hw = 0.5 * gl[q + k];
+    X[i] = vx[e] + s * ex;
+    Y[i] = vy[e] + s * ey;
+    Wv[i] = hw * ex;
+    Vv[i] = hw * ey;
+}
+
+// Dilation rule: node j = l + i m takes alpha_l (X_i, Y_i) with weight
+// alpha_l wt_l (X_i V_i - Y_i W_i); alpha, wt = m-node GL on (0,1).
+__global__ void k_dilation(const double* __restrict__ X, const double* __restrict__ Y,
+                           const double* __restrict__ Wv, const double* __restrict__ Vv, int64_t n,
+                           int m, const double* __restrict__ gl, double* __restrict__ x,
+                           double* __restrict__ y, double* __restrict__ w)
+{
+    int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (j >= n * m) return;
+    const int64_t i = j / m;
+    const int l = (int)(j - i * m);
+    const double al = 0.5 * (1.0 + gl[l]);
+    const double wl = 0.5 * gl[m + l];
+    const double Xi = X[i], Yi = Y[i];
+    x[j] = al * Xi;
+    y[j] = al * Yi;
+    w[j] = al * wl * (Xi * Vv[i] - Yi * Wv[i]);
+}
+
+struct PetalParams {
+    int Np, m, np, K;
+    double a, R, b, p;
+    int64_t off;  // first petal node
+};
+
+// Petal node j = off + k np m + i m + l.
+__global__ void k_petals(PetalParams pp, const double* __restrict__ glm, const double* __restrict__ gln,
+                         const double* __restrict__ coef, double* __restrict__ x,
+                         double* __restrict__ y, double* __restrict__ w)
+{
+    const int64_t per = (int64_t)pp.np * pp.m;
+    int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= per * pp.Np) return;
+    const int k = (int)(t / per);
+    const int64_t rem = t - k * per;
+    const int i = (int)(rem / pp.m);
+    const int l = (int)(rem - (int64_t)i * pp.m);
+    const double L = pp.R - pp.a;
+    const double r = pp.a + 0.5 * L * (1.0 + glm[l]);
+    const double wr = 0.5 * L * glm[pp.m + l];
+    const double tau = gln[i], wt = gln[pp.np + i];
+    const double A = exp(-pow((r - pp.a) / pp.b, pp.p));
+    double dp = 0.0, dm = 0.0;
+    if (coef) {
+        const double* cp = coef + 2 * (int64_t)k * pp.K;
+        for (int s = 1; s <= pp.K; ++s) {
+            const double sk = sin(s * kPi * (r - pp.a) / L);
+            dp += cp[s - 1] * sk;
+            dm += cp[pp.K + s - 1] * sk;
+        }
+    }
+    const double mid = (dp - dm) / (2.0 * r);
+    const double half = kPi * A / pp.Np + (dp + dm) / (2.0 * r);
+    const double phi = 2.0 * kPi * k / pp.Np + mid + half * tau;
+    double sp, cp;
+    sincos(phi, &sp, &cp);
+    const int64_t j = pp.off + t;
+    x[j] = r * cp;
+    y[j] = r * sp;
+    w[j] = r * wr * half * wt;
+}
+
+inline unsigned nblocks(int64_t n, int bs) { return (unsigned)std::max<int64_t>(1, (n + bs - 1) / bs); }
+
+fh_status radial_into(fh_ctx* c, const RadialParams& rp, int64_t n, int m, double* x, double* y,
+                      double* w)
+{
+    const double* glq = nullptr;
+    const double* glm = nullptr;
+    if (rp.panels > 0) FH_TRY(gl_table(c, rp.q, &glq));
+    FH_TRY(gl_table(c, m, &glm));
+    FH_TRY(arena_reserve(c, 4 * aligned_bytes(sizeof(double) * n)));
+    double* X = c->arena.take<double>(n);
+    double* Y = c->arena.take<double>(n);
+    double* Wv = c->arena.take<double>(n);
+    double* Vv = c->arena.take<double>(n);
+    hipLaunchKernelGGL(k_bdry_radial, dim3(nblocks(n, 256)), dim3(256), 0, c->stream, rp, glq, n, X,
+                       Y, Wv, Vv);
+    hipLaunchKernelGGL(k_dilation, dim3(nblocks(n * m, 256)), dim3(256), 0, c->stream, X, Y, Wv, Vv,
+                       n, m, glm, x, y, w);
+    FH_HIP(hipGetLastError());
+    return FH_OK;
+}
+
+}  // namespace
+}  // namespace fh
+
+using namespace fh;
+
+extern "C" {
+
+fh_status fh_quad_radial(fh_ctx* c, double r0, const double* a, const double* b, int32_t K,
+                         int32_t panels, int32_t q, int32_t m, fh_quad** out)
+{
+    try {
+        FH_ARG(c && out, FH_ERR_INVALID_ARG, "NULL argument");
+        *out = nullptr;
+        FH_ARG(K >= 0 && K <= kMaxFourier, FH_ERR_INVALID_ARG, "K must be in [0, %d]", kMaxFourier);
+        FH_ARG(panels >= 0 && q >= 1 && m >= 1, FH_ERR_INVALID_ARG, "need panels >= 0, q >= 1, m >= 1");
+        FH_ARG(std::isfinite(r0), FH_ERR_NONFINITE, "r0 not finite");
+        RadialParams rp{};
+        rp.r0 = r0;
+        rp.K = K;
+        rp.panels = panels;
+        rp.q = q;
+        for (int k = 0; k < K; ++k) {
+            rp.a[k] = a ? a[k] : 0.0;
+            rp.b[k] = b ? b[k] : 0.0;
+            FH_ARG(std::isfinite(rp.a[k]) && std::isfinite(rp.b[k]), FH_ERR_NONFINITE,
+                   "Fourier coefficient %d not finite", k + 1);
+        }
+        const int64_t n = panels > 0 ? (int64_t)panels * q : q;
+        FH_HIP(hipSetDevice(c->device));
+        fh_quad* qd = nullptr;
+        FH_TRY(quad_alloc(c, n * m, &qd));
+        fh_status s = radial_into(c, rp, n, m, qd->x, qd->y, qd->w);
+        if (s != FH_OK) {
+            fh_quad_destroy(qd);
+            return s;
+        }
+        *out = qd;
+        return FH_OK;
+    } catch (...) {
+        set_error("host allocation failed");
+        return FH_ERR_ALLOC;
+    }
+}
+
+fh_status fh_quad_polygon(fh_ctx* c, const double* vx, const double* vy, int32_t nv, int32_t q,
+                          int32_t m, fh_quad** out)
+{
+    try {
+        FH_ARG(c && out && vx && vy, FH_ERR_INVALID_ARG, "NULL argument");
+        *out = nullptr;
+        FH_ARG(nv >= 3 && q >= 1 && m >= 1, FH_ERR_INVALID_ARG, "need nv >= 3, q >= 1, m >= 1");
+        for (int i = 0; i < nv; ++i)
+            FH_ARG(std::isfinite(vx[i]) && std::isfinite(vy[i]), FH_ERR_NONFINITE, "vertex %d not finite", i);
+        FH_HIP(hipSetDevice(c->device));
+        const double* glq = nullptr;
+        const double* glm = nullptr;
+        FH_TRY(gl_table(c, q, &glq));
+        FH_TRY(gl_table(c, m, &glm));
+        const int64_t n = (int64_t)nv * q;
+        fh_quad* qd = nullptr;
+        FH_TRY(quad_alloc(c, n * m, &qd));
+        fh_status s = arena_reserve(c, 4 * aligned_bytes(sizeof(double) * n) +
+                                           2 * aligned_bytes(sizeof(double) * nv));
+        if (s != FH_OK) {
+            fh_quad_destroy(qd);
+            return s;
+        }
+        double* X = c->arena.take<double>(n);
+        double* Y = c->arena.take<double>(n);
+        double* Wv = c->arena.take<double>(n);
+        double* Vv = c->arena.take<double>(n);
+        double* dvx = c->arena.take<double>(nv);
+        double* dvy = c->arena.take<double>(nv);
+        FH_HIP(hipMemcpyAsync(dvx, vx, sizeof(double) * nv, hipMemcpyHostToDevice, c->stream));
+        FH_HIP(hipMemcpyAsync(dvy, vy, sizeof(double) * nv, hipMemcpyHostToDevice, c->stream));
+        hipLaunchKernelGGL(k_bdry_polygon, dim3(nblocks(n, 256)), dim3(256), 0, c->stream, dvx, dvy,
+                           nv, q, glq, X, Y, Wv, Vv);
+        hipLaunchKernelGGL(k_dilation, dim3(nblocks(n * m, 256)), dim3(256), 0, c->stream, X, Y, Wv,
+                           Vv, n, m, glm, qd->x, qd->y, qd->w);
+        FH_HIP(hipGetLastError());
+        // the host vertex arrays may be released by the caller on return
+        FH_HIP(hipStreamSynchronize(c->stream));
+        *out = qd;
+        return FH_OK;
+    } catch (...) {
+        set_error("host allocation failed");
+        return FH_ERR_ALLOC;
+    }
+}
+
+fh_status fh_quad_from_boundary(fh_ctx* c, const double* X, const double* Y, const double* W,
+                                const double* V, int64_t n, int32_t m, fh_memspace mem,
+                                fh_quad** out)
+{
+    try {
+        FH_ARG(c && out, FH_ERR_INVALID_ARG, "NULL argument");
+        *out = nullptr;
+        FH_ARG(n >= 0 && m >= 1, FH_ERR_INVALID_ARG, "need n >= 0, m >= 1");
+        FH_ARG(n == 0 || (X && Y && W && V), FH_ERR_INVALID_ARG, "NULL boundary array");
+        FH_ARG(mem == FH_MEM_HOST || mem == FH_MEM_DEVICE, FH_ERR_INVALID_ARG, "bad memspace");
+        FH_HIP(hipSetDevice(c->device));
+        const double* glm = nullptr;
+        FH_TRY(gl_table(c, m, &glm));
+        fh_quad* qd = nullptr;
+        FH_TRY(quad_alloc(c, n * m, &qd));
+        if (n == 0) {
+            *out = qd;
+            return FH_OK;
+        }
+        const double *dX = X, *dY = Y, *dW = W, *dV = V;
+        if (mem == FH_MEM_HOST) {
+            fh_status s = arena_reserve(c, 4 * aligned_bytes(sizeof(double) * n));
+            if (s != FH_OK) {
+                fh_quad_destroy(qd);
+                return s;
+            }
+            double* b[4];
+            const double* h[4] = {X, Y, W, V};
+            for (int k = 0; k < 4; ++k) {
+                b[k] = c->arena.take<double>(n);
+                FH_HIP(hipMemcpyAsync(b[k], h[k], sizeof(double) * n, hipMemcpyHostToDevice, c->stream));
+            }
+            dX = b[0]; dY = b[1]; dW = b[2]; dV = b[3];
+        }
+        hipLaunchKernelGGL(k_dilation, dim3(nblocks(n * m, 256)), dim3(256), 0, c->stream, dX, dY, dW,
+                           dV, n, m, glm, qd->x, qd->y, qd->w);
+        FH_HIP(hipGetLastError());
+        if (mem == FH_MEM_HOST) FH_HIP(hipStreamSynchronize(c->stream));
+        *out = qd;
+        return FH_OK;
+    } catch (...) {
+        set_error("host allocation failed");
+        return FH_ERR_ALLOC;
+    }
+}
+
+fh_status fh_quad_starshade(fh_ctx* c, int32_t Np, double a, double R, double b, double p, int32_t m,
+                            int32_t np, int32_t nd, int32_t md, const double* coef, int32_t K,
+                            fh_memspace coef_mem, fh_quad** out)
+{
+    try {
+        FH_ARG(c && out, FH_ERR_INVALID_ARG, "NULL argument");
+        *out = nullptr;
+        FH_ARG(Np >= 1 && m >= 1 && np >= 1 && nd >= 0 && md >= 1, FH_ERR_INVALID_ARG,
+               "need Np, m, np, md >= 1 and nd >= 0");
+        FH_ARG(std::isfinite(a) && std::isfinite(R) && std::isfinite(b) && std::isfinite(p),
+               FH_ERR_NONFINITE, "starshade scalar not finite");
+        FH_ARG(a >= 0 && R > a && b > 0 && p > 0, FH_ERR_INVALID_ARG, "need 0 <= a < R, b > 0, p > 0");
+        FH_ARG(!coef || (K >= 1 && K <= kMaxFourier), FH_ERR_INVALID_ARG, "K must be in [1, %d]",
+               kMaxFourier);
+        FH_ARG(coef_mem == FH_MEM_HOST || coef_mem == FH_MEM_DEVICE, FH_ERR_INVALID_ARG, "bad memspace");
+        FH_HIP(hipSetDevice(c->device));
+        const double* glm = nullptr;
+        const double* gln = nullptr;
+        const double* glmd = nullptr;
+        FH_TRY(gl_table(c, m, &glm));
+        FH_TRY(gl_table(c, np, &gln));
+        FH_TRY(gl_table(c, md, &glmd));
+        const int64_t Nd = (int64_t)nd * md;
+        const int64_t N = Nd + (int64_t)Np * np * m;
+        fh_quad* qd = nullptr;
+        FH_TRY(quad_alloc(c, N, &qd));
+        const size_t ncoef = coef ? (size_t)2 * Np * K : 0;
+        fh_status s = arena_reserve(c, 4 * aligned_bytes(sizeof(double) * std::max(nd, 1)) +
+                                           aligned_bytes(sizeof(double) * std::max<size_t>(ncoef, 1)));
+        if (s != FH_OK) {
+            fh_quad_destroy(qd);
+            return s;
+        }
+        double* X = c->arena.take<double>(nd);
+        double* Y = c->arena.take<double>(nd);
+        double* Wv = c->arena.take<double>(nd);
+        double* Vv = c->arena.take<double>(nd);
+        const double* dcoef = coef;
+        if (coef && coef_mem == FH_MEM_HOST) {
+            double* dc = c->arena.take<double>(ncoef);
+            FH_HIP(hipMemcpyAsync(dc, coef, sizeof(double) * ncoef, hipMemcpyHostToDevice, c->stream));
+            dcoef = dc;
+        }
+        if (nd > 0) {
+            // disc of radius a: trapezoid boundary rule (eq. ptr) + dilation
+            RadialParams rp{};
+            rp.r0 = a;
+            rp.K = 0;
+            rp.panels = 0;
+            rp.q = nd;
+            hipLaunchKernelGGL(k_bdry_radial, dim3(nblocks(nd, 256)), dim3(256), 0, c->stream, rp,
+                               (const double*)nullptr, (int64_t)nd, X, Y, Wv, Vv);
+            hipLaunchKernelGGL(k_dilation, dim3(nblocks(Nd, 256)), dim3(256), 0, c->stream, X, Y, Wv, Vv,
+                               (int64_t)nd, md, glmd, qd->x, qd->y, qd->w);
+        }
+        PetalParams pp{Np, m, np, coef ? K : 0, a, R, b, p, Nd};
+        hipLaunchKernelGGL(k_petals, dim3(nblocks((int64_t)Np * np * m, 256)), dim3(256), 0, c->stream,
+                           pp, glm, gln, dcoef, qd->x, qd->y, qd->w);
+        FH_HIP(hipGetLastError());
+        if (coef && coef_mem == FH_MEM_HOST) FH_HIP(hipStreamSynchronize(c->stream));
+        *out = qd;
+        return FH_OK;
+    } catch (...) {
+        set_error("host allocation failed");
+        return FH_ERR_ALLOC;
+    }
+}
+
+fh_status fh_quad_from_nodes(fh_ctx* c, const double* x, const double* y, const double* w, int64_t N,
+                             fh_memspace mem, fh_quad** out)
+{
+    try {
+        FH_ARG(c && out, FH_ERR_INVALID_ARG, "NULL argument");
+        *out = nullptr;
+        FH_ARG(N >= 0, FH_ERR_INVALID_ARG, "N must be >= 0");
+        FH_ARG(N == 0 || (x && y && w), FH_ERR_INVALID_ARG, "NULL node array");
+        FH_ARG(mem == FH_MEM_HOST || mem == FH_MEM_DEVICE, FH_ERR_INVALID_ARG, "bad memspace");
+        FH_HIP(hipSetDevice(c->device));
+        fh_quad* qd = nullptr;
+        FH_TRY(quad_alloc(c, N, &qd));
+        if (N > 0) {
+            hipMemcpyKind kind = mem == FH_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+            FH_HIP(hipMemcpyAsync(qd->x, x, sizeof(double) * N, kind, c->stream));
+            FH_HIP(hipMemcpyAsync(qd->y, y, sizeof(double) * N, kind, c->stream));
+            FH_HIP(hipMemcpyAsync(qd->w, w, sizeof(double) * N, kind, c->stream));
+            if (mem == FH_MEM_HOST) FH_HIP(hipStreamSynchronize(c->stream));
+        }
+        *out = qd;
+        return FH_OK;
+    } catch (...) {
+        set_error("host allocation failed");
+        return FH_ERR_ALLOC;
+    }
+}
+
+fh_status fh_quad_size(const fh_quad* q, int64_t* N)
+{
+    FH_ARG(q && N, FH_ERR_INVALID_ARG, "NULL argument");
+    *N = q->N;
+    return FH_OK;
+}
+
+fh_status fh_quad_export(const fh_quad* q, double* x, double* y, double* w, fh_memspace mem)
+{
+    FH_ARG(q, FH_ERR_INVALID_ARG, "NULL quadrature");
+    FH_ARG(mem == FH_MEM_HOST || mem == FH_MEM_DEVICE, FH_ERR_INVALID_ARG, "bad memspace");
+    fh_ctx* c = q->ctx;
+    FH_HIP(hipSetDevice(c->device));
+    hipMemcpyKind kind = mem == FH_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
+    const size_t bytes = sizeof(double) * q->N;
+    if (q->N > 0) {
+        if (x) FH_HIP(hipMemcpyAsync(x, q->x, bytes, kind, c->stream));
+        if (y) FH_HIP(hipMemcpyAsync(y, q->y, bytes, kind, c->stream));
+        if (w) FH_HIP(hipMemcpyAsync(w, q->w, bytes, kind, c->stream));
+    }
+    if (mem == FH_MEM_HOST) FH_HIP(hipStreamSynchronize(c->stream));
+    return FH_OK;
+}
+
+fh_status fh_quad_device_ptrs(const fh_quad* q, const double** x, const double** y, const double** w)
+{
+    FH_ARG(q, FH_ERR_INVALID_ARG, "NULL quadrature");
+    if (x) *x = q->x;
+    if (y) *y = q->y;
+    if (w) *w = q->w;
+    return FH_OK;
+}
+
+fh_status fh_quad_destroy(fh_quad* q)
+{
+    if (!q) return FH_OK;
+    try {
+        // keep the buffer for the next rule of the same size: work already
+        // enqueued on the context stream that reads it stays ordered before
+        // any later writer on the same stream.
+        q->ctx->pool[q->buf_bytes].push_back(q->buf);
+    } catch (...) {
+        (void)dev_free(q->ctx, q->buf);
+    }
+    delete q;
+    return FH_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,296 @@
+"""GPU path vs the CPU FP64 oracle, through the C ABI.
+
+Bars (relative L2 over the compared targets, on u_ap):
+  FP64 context, tol 1e-9   ->  <= 1e-9
+  mixed context, tol 1e-5  ->  <= 1e-5
+Full-size workloads compare a seeded sample of targets that the oracle sums
+one by one.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-9, "mixed": 1e-5}
+
+
+def relL2(a, b):
+    a = np.asarray(a).ravel()
+    b = np.asarray(b).ravel()
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def fh():
+    import paper_2010_05978_amd as fh
+    print("libfresnel_hip:", fh.LIB_PATH, flush=True)
+    return fh
+
+
+@pytest.fixture(scope="module", params=["fp64", "mixed"])
+def ctx(request, fh):
+    c = fh.Context(request.param)
+    yield c
+    c.close()
+
+
+def oracle_quad(shape):
+    k = type(shape).__name__
+    if k == "RadialCurve":
+        return oracle.quad_radial(shape.r0, shape.a if len(shape.a) else None,
+                                  shape.b if len(shape.b) else None, shape.panels, shape.q, shape.m)
+    if k == "Polygon":
+        return oracle.quad_polygon(shape.vx, shape.vy, shape.q, shape.m)
+    return oracle.quad_starshade(shape.Np, shape.a, shape.R, shape.b, shape.p, shape.m, shape.np_,
+                                 shape.nd, shape.md, shape.coef, shape.K)
+
+
+def cpu(t):
+    return t.detach().cpu().numpy()
+
+
+# ------------------------------------------------------------- quadrature
+@pytest.mark.parametrize("wid", [1, 2, 3])
+def test_quadrature_matches_oracle(fh, wid):
+    c = fh.Context("fp64")
+    shape = workloads.workload(wid).shape
+    print(f"quadrature workload {wid}", flush=True)
+    q = c.quad_for(shape)
+    x, y, w = (cpu(t) for t in q.export())
+    xo, yo, wo = oracle_quad(shape)
+    assert len(x) == len(xo) == shape.n_nodes
+    sc = np.abs(xo).max()
+    assert np.abs(x - xo).max() <= 1e-14 * sc
+    assert np.abs(y - yo).max() <= 1e-14 * sc
+    assert np.abs(w - wo).max() <= 1e-14 * np.abs(wo).max()
+    c.close()
+
+
+def test_quadrature_polygon_perturbed_starshade_and_boundary(fh):
+    c = fh.Context("fp64")
+    shapes = workloads.batch_shapes(count=4, nmin=2000, nmax=5000)
+    for s in shapes:
+        q = c.quad_for(s)
+        x, y, w = (cpu(t) for t in q.export())
+        xo, yo, wo = oracle_quad(s)
+        assert np.abs(x - xo).max() <= 1e-14 * np.abs(xo).max()
+        assert np.abs(w - wo).max() <= 1e-14 * np.abs(wo).max()
+    s = workloads.workload(5, reduced=True).shape
+    for coef_on_device in (False, True):
+        coef = torch.tensor(s.coef, device="cuda") if coef_on_device else s.coef
+        q = c.quad_starshade(s.Np, s.a, s.R, s.b, s.p, s.m, s.np_, s.nd, s.md, coef, s.K)
+        x, y, w = (cpu(t) for t in q.export())
+        xo, yo, wo = oracle_quad(s)
+        assert np.abs(x - xo).max() <= 1e-14 * 12
+        assert np.abs(w - wo).max() <= 1e-14 * np.abs(wo).max()
+    # user-supplied boundary rule -> dilation
+    X, Y, W, V = oracle.boundary_radial_ptr(1.3, n=50)
+    q = c.quad_from_boundary(X, Y, W, V, 7)
+    x, y, w = (cpu(t) for t in q.export())
+    xo, yo, wo = oracle.dilation(X, Y, W, V, 7)
+    assert np.abs(w - wo).max() <= 1e-14 * np.abs(wo).max()
+    c.close()
+
+
+# --------------------------------------------------------------- type 1
+def test_grid_workload1_full(ctx):
+    wl = workloads.workload(1)
+    g = wl.grid
+    print(f"type-1 workload 1 {ctx.precision}", flush=True)
+    q = ctx.quad_for(wl.shape)
+    u = cpu(ctx.field_grid(q, wl.lam, wl.z, g.n1, g.n2, g.h1, g.h2))
+    x, y, w = oracle_quad(wl.shape)
+    xi, eta = oracle.grid_targets(g.n1, g.n2, g.h1, g.h2)
+    ref = oracle.fresnel_direct(x, y, w, wl.lam, wl.z, xi, eta)
+    err = relL2(u, ref)
+    print(f"  rel L2 = {err:.3e}", flush=True)
+    assert err <= TOL[ctx.precision]
+    # occulter output is the Babinet complement of the same sum
+    uo = cpu(ctx.field_grid(q, wl.lam, wl.z, g.n1, g.n2, g.h1, g.h2, occulter=True))
+    assert relL2(1 - uo, ref) <= TOL[ctx.precision]
+
+
+@pytest.mark.parametrize("n1,n2,h1,h2,xc,yc", [
+    (34, 18, 0.07, 0.11, 0.0, 0.0),        # rectangular, ragged tile tail
+    (64, 64, 0.05, 0.05, 0.31, -0.47),     # translated grid (pre-phasing)
+    (2, 2, 0.5, 0.5, 0.0, 0.0),            # smallest grid
+    (256, 130, 0.012, 0.02, -0.2, 0.1),
+])
+def test_grid_shapes_and_translation(ctx, n1, n2, h1, h2, xc, yc):
+    a = np.zeros(5)
+    a[4] = 0.3
+    shape = workloads.RadialCurve(1.0, a, np.zeros(5), panels=10, q=16, m=40)
+    lam, z = 5e-7, 0.2 / 5e-7
+    q = ctx.quad_for(shape)
+    u = cpu(ctx.field_grid(q, lam, z, n1, n2, h1, h2, xc, yc))
+    x, y, w = oracle_quad(shape)
+    xi, eta = oracle.grid_targets(n1, n2, h1, h2, xc, yc)
+    ref = oracle.fresnel_direct(x, y, w, lam, z, xi, eta)
+    assert u.shape == (n2, n1)
+    assert relL2(u, ref) <= TOL[ctx.precision]
+
+
+def test_grid_folding_undersampled(ctx):
+    # target grid coarser than the field: rescaled nodes leave [-pi, pi) and
+    # must be folded (sec. 2.2)
+    shape = workloads.RadialCurve(1.0, np.zeros(0), np.zeros(0), panels=6, q=20, m=40)
+    lam, z, n, h = 1.0, 0.1, 16, 0.4
+    q = ctx.quad_for(shape)
+    u = cpu(ctx.field_grid(q, lam, z, n, n, h, h))
+    x, y, w = oracle_quad(shape)
+    xi, eta = oracle.grid_targets(n, n, h, h)
+    ref = oracle.fresnel_direct(x, y, w, lam, z, xi, eta)
+    assert 2 * math.pi * h * 1.0 / (lam * z) > math.pi
+    assert relL2(u, ref) <= TOL[ctx.precision]
+
+
+def test_single_node_plane_wave(ctx):
+    # one node: u_k = exp(i pi |xi_k - x0|^2/lz) w0/(i lz) at every target
+    x0, y0, w0 = np.array([0.123]), np.array([-0.456]), np.array([0.7])
+    q = ctx.quad_from_nodes(x0, y0, w0)
+    lam, z = 1.0, 0.3
+    u = cpu(ctx.field_grid(q, lam, z, 40, 24, 0.05, 0.07))
+    xi, eta = oracle.grid_targets(40, 24, 0.05, 0.07)
+    ref = np.exp(1j * math.pi * ((xi - x0) ** 2 + (eta - y0) ** 2) / (lam * z)) * w0 / (1j * lam * z)
+    assert relL2(u, ref) <= TOL[ctx.precision]
+
+
+def test_empty_rule(ctx):
+    q = ctx.quad_from_nodes(np.zeros(0), np.zeros(0), np.zeros(0))
+    u = cpu(ctx.field_grid(q, 1.0, 1.0, 8, 6, 0.1, 0.1))
+    assert np.all(u == 0)
+    u = cpu(ctx.field_grid(q, 1.0, 1.0, 8, 6, 0.1, 0.1, occulter=True))
+    assert np.all(u == 1)
+    xi = torch.zeros(5, dtype=torch.float64, device="cuda")
+    u = cpu(ctx.field_points(q, 1.0, 1.0, xi, xi, occulter=True))
+    assert np.all(u == 1)
+
+
+def test_grid_workload2_full_size_sampled(ctx):
+    wl = workloads.workload(2)
+    g = wl.grid
+    print(f"type-1 workload 2 {ctx.precision}", flush=True)
+    q = ctx.quad_for(wl.shape)
+    u = cpu(ctx.field_grid(q, wl.lam, wl.z, g.n1, g.n2, g.h1, g.h2)).ravel()
+    rng = np.random.Generator(np.random.PCG64(99))
+    idx = rng.choice(g.M, 3000, replace=False)
+    x, y, w = oracle_quad(wl.shape)
+    xi, eta = oracle.grid_targets(g.n1, g.n2, g.h1, g.h2)
+    ref = oracle.fresnel_direct(x, y, w, wl.lam, wl.z, xi[idx], eta[idx])
+    err = relL2(u[idx], ref)
+    print(f"  rel L2 (3000 samples) = {err:.3e}", flush=True)
+    assert err <= TOL[ctx.precision]
+
+
+# --------------------------------------------------------------- type 3
+def test_points_workload2_sampled(ctx):
+    wl = workloads.workload(2)
+    xi, eta = wl.points
+    print(f"type-3 workload 2 {ctx.precision}", flush=True)
+    q = ctx.quad_for(wl.shape)
+    dxi = torch.tensor(xi, device="cuda")
+    deta = torch.tensor(eta, device="cuda")
+    u = cpu(ctx.field_points(q, wl.lam, wl.z, dxi, deta))
+    rng = np.random.Generator(np.random.PCG64(98))
+    idx = rng.choice(len(xi), 3000, replace=False)
+    x, y, w = oracle_quad(wl.shape)
+    ref = oracle.fresnel_direct(x, y, w, wl.lam, wl.z, xi[idx], eta[idx])
+    err = relL2(u[idx], ref)
+    print(f"  rel L2 (3000 samples) = {err:.3e}", flush=True)
+    assert err <= TOL[ctx.precision]
+    # host arrays in, host array out: same answer
+    uh = np.empty(len(xi), dtype=np.complex128 if ctx.precision == "fp64" else np.complex64)
+    from paper_2010_05978_amd import abi
+    abi.fh_field_points(ctx.handle, q.handle, wl.lam, wl.z, xi, eta, False, uh)
+    assert relL2(uh[idx], ref) <= TOL[ctx.precision]
+
+
+def test_points_small_full(ctx):
+    shape = workloads.workload(1).shape
+    wl = workloads.workload(1)
+    g = np.random.Generator(np.random.PCG64(5))
+    M = 777
+    xi = g.uniform(-1.7, 0.9, M)
+    eta = g.uniform(-0.4, 1.3, M)
+    q = ctx.quad_for(shape)
+    u = cpu(ctx.field_points(q, wl.lam, wl.z, torch.tensor(xi, device="cuda"), torch.tensor(eta, device="cuda")))
+    x, y, w = oracle_quad(shape)
+    ref = oracle.fresnel_direct(x, y, w, wl.lam, wl.z, xi, eta)
+    assert relL2(u, ref) <= TOL[ctx.precision]
+    # single target (zero target extent)
+    u1 = cpu(ctx.field_points(q, wl.lam, wl.z, torch.tensor(xi[:1], device="cuda"),
+                              torch.tensor(eta[:1], device="cuda")))
+    assert abs(u1[0] - ref[0]) <= TOL[ctx.precision] * max(1.0, abs(ref[0])) * 10
+
+
+def test_points_equal_grid_at_grid_targets(ctx):
+    wl = workloads.workload(1)
+    g = wl.grid
+    q = ctx.quad_for(wl.shape)
+    ug = cpu(ctx.field_grid(q, wl.lam, wl.z, g.n1, g.n2, g.h1, g.h2)).ravel()
+    xi, eta = oracle.grid_targets(g.n1, g.n2, g.h1, g.h2)
+    up = cpu(ctx.field_points(q, wl.lam, wl.z, torch.tensor(xi, device="cuda"), torch.tensor(eta, device="cuda")))
+    assert relL2(up, ug) <= 2 * TOL[ctx.precision]
+
+
+def test_starshade_workload3_points_sampled(ctx):
+    wl = workloads.workload(3)
+    xi, eta = wl.points
+    print(f"type-3 workload 3 {ctx.precision}", flush=True)
+    q = ctx.quad_for(wl.shape)
+    rng = np.random.Generator(np.random.PCG64(97))
+    idx = rng.choice(len(xi), 400, replace=False)
+    x, y, w = oracle_quad(wl.shape)
+    for lam in wl.lams:
+        u = cpu(ctx.field_points(q, lam, wl.z, torch.tensor(xi, device="cuda"), torch.tensor(eta, device="cuda"),
+                                 occulter=True))
+        ref = oracle.fresnel_direct(x, y, w, lam, wl.z, xi[idx], eta[idx])
+        err = relL2(1 - u[idx], ref)
+        print(f"  lambda={lam:.2e} rel L2 (u_ap, 400 samples) = {err:.3e}", flush=True)
+        assert err <= TOL[ctx.precision]
+
+
+def test_starshade_workload3_grid_sampled(ctx):
+    wl = workloads.workload(3)
+    g = wl.grid
+    print(f"type-1 workload 3 {ctx.precision}", flush=True)
+    q = ctx.quad_for(wl.shape)
+    u = cpu(ctx.field_grid(q, wl.lam, wl.z, g.n1, g.n2, g.h1, g.h2, occulter=True)).ravel()
+    rng = np.random.Generator(np.random.PCG64(96))
+    idx = rng.choice(g.M, 400, replace=False)
+    x, y, w = oracle_quad(wl.shape)
+    xi, eta = oracle.grid_targets(g.n1, g.n2, g.h1, g.h2)
+    ref = oracle.fresnel_direct(x, y, w, wl.lam, wl.z, xi[idx], eta[idx])
+    err = relL2(1 - u[idx], ref)
+    print(f"  rel L2 (u_ap, 400 samples) = {err:.3e}", flush=True)
+    assert err <= TOL[ctx.precision]
+
+
+# -------------------------------------------------------- error statuses
+def test_error_statuses(fh):
+    c = fh.Context("fp64")
+    q = c.quad_radial(1.0, panels=2, q=4, m=3)
+    u = torch.empty((4, 5), dtype=torch.complex128, device="cuda")
+    from paper_2010_05978_amd import abi
+    with pytest.raises(fh.FresnelError) as e:
+        abi.fh_field_grid(c.handle, q.handle, 1.0, 1.0, 5, 4, 0.1, 0.1, 0, 0, False, u)
+    assert e.value.status == fh.FH_ERR_ODD_GRID
+    with pytest.raises(fh.FresnelError) as e:
+        abi.fh_field_grid(c.handle, q.handle, 1.0, -1.0, 4, 4, 0.1, 0.1, 0, 0, False, u)
+    assert e.value.status == fh.FH_ERR_NONPOSITIVE_LZ
+    with pytest.raises(fh.FresnelError) as e:
+        abi.fh_field_grid(c.handle, q.handle, float("nan"), 1.0, 4, 4, 0.1, 0.1, 0, 0, False, u)
+    assert e.value.status == fh.FH_ERR_NONFINITE
+    with pytest.raises(fh.FresnelError) as e:
+        abi.fh_quad_radial(c.handle, 1.0, np.zeros(65), None, 1, 4, 3)
+    assert e.value.status == fh.FH_ERR_INVALID_ARG
+    # the context stays usable after errors
+    v = c.field_grid(q, 1.0, 1.0, 4, 4, 0.1, 0.1)
+    assert torch.isfinite(torch.view_as_real(v)).all()
+    c.close()
