@@ -1,0 +1,152 @@
+#!/usr/bin/env python3
+"""Throughput of the fast Fresnel-diffraction path on one MI355X.
+
+A step is one pass of the whole hot path over the starfish workload (Fresnel
+number 20; workload 2 of workloads.py): device quadrature generation (20 GL
+panels x 20 nodes on the boundary, dilation with 100 radial nodes: 40,000
+nodes), the type-1 field on the 1000 x 1000 target grid, and the type-3 field
+at 1e5 scattered targets in the disk |x| < 1.5.  Shape parameters and target
+coordinates are resident on the device before the timed region starts.
+
+value = targets per second of the FP64 path (tolerance 1e-9, relative L2
+against the exact quadrature sum); the mixed-precision path (tolerance 1e-5)
+is timed in the same run and reported beside it.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle sample")
+    ap.add_argument("--only", choices=["fp64", "mixed"], default=None, help="time one precision only")
+    return ap.parse_args()
+
+
+class Step:
+    """One pass of the hot path for one precision."""
+
+    def __init__(self, fh, precision, wl, dev):
+        import torch
+        self.ctx = fh.Context(precision)
+        self.wl = wl
+        self.shape = wl.shape
+        g = wl.grid
+        self.g = g
+        self.xi = torch.tensor(wl.points[0], device=dev)
+        self.eta = torch.tensor(wl.points[1], device=dev)
+        self.ugrid = torch.empty((g.n2, g.n1), dtype=self.ctx.cdtype, device=dev)
+        self.upts = torch.empty(len(wl.points[0]), dtype=self.ctx.cdtype, device=dev)
+        self.M = g.M + len(wl.points[0])
+
+    def __call__(self):
+        wl, g = self.wl, self.g
+        q = self.ctx.quad_for(self.shape)
+        self.ctx.field_grid(q, wl.lam, wl.z, g.n1, g.n2, g.h1, g.h2, out=self.ugrid)
+        self.ctx.field_points(q, wl.lam, wl.z, self.xi, self.eta, out=self.upts)
+        q.close()
+
+
+def time_steps(step, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    step.ctx.set_timing(True)
+    step.ctx.timing_totals(0, reset=True)
+    step.ctx.timing_totals(1, reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    grid_ms, ngrid = step.ctx.timing_totals(0)
+    pts_ms, npts = step.ctx.timing_totals(1)
+    step.ctx.set_timing(False)
+    return dt, [v / max(ngrid, 1) for v in grid_ms], [v / max(npts, 1) for v in pts_ms]
+
+
+def cpu_baseline(wl, seconds):
+    """The oracle (direct FP64 sum) on a seeded sample of the step's targets."""
+    import numpy as np
+    import oracle
+    s = wl.shape
+    x, y, w = oracle.quad_radial(s.r0, s.a, s.b, s.panels, s.q, s.m)
+    xi_g, eta_g = oracle.grid_targets(wl.grid.n1, wl.grid.n2, wl.grid.h1, wl.grid.h2)
+    xi = np.concatenate([xi_g, wl.points[0]])
+    eta = np.concatenate([eta_g, wl.points[1]])
+    rng = np.random.Generator(np.random.PCG64(4242))
+    probe = rng.choice(len(xi), 512, replace=False)
+    t0 = time.perf_counter()
+    oracle.fresnel_direct(x, y, w, wl.lam, wl.z, xi[probe], eta[probe])
+    per = (time.perf_counter() - t0) / 512
+    n = int(min(len(xi), max(1024, seconds / max(per, 1e-9))))
+    idx = rng.choice(len(xi), n, replace=False)
+    t0 = time.perf_counter()
+    oracle.fresnel_direct(x, y, w, wl.lam, wl.z, xi[idx], eta[idx])
+    dt = time.perf_counter() - t0
+    return {"value": n / dt, "unit": "targets/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"{n} of the step's {len(xi)} targets (grid and scattered, seeded), "
+                      f"direct FP64 sum over all {len(x)} nodes, {dt:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported by this build "
+              "(the path shards by instance or by node; see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_2010_05978_amd as fh
+    import workloads
+
+    dev = torch.device("cuda", 0)
+    wl = workloads.workload(2)
+    precs = [args.only] if args.only else ["fp64", "mixed"]
+    res = {}
+    for p in precs:
+        st = Step(fh, p, wl, dev)
+        dt, gstage, pstage = time_steps(st, args.steps, args.warmup)
+        res[p] = {"ms_per_step": 1e3 * dt / args.steps, "value": st.M * args.steps / dt,
+                  "grid_stage_ms": gstage, "points_stage_ms": pstage,
+                  "params": st.ctx.query_params(wl.grid.n1)}
+        st.ctx.close()
+    main_p = precs[0]
+    r = res[main_p]
+    out = {
+        "metric": "target pts/s at 1e-9 (FP64) vs 1e-5 (mixed); backward/forward time ratio",
+        "value": r["value"], "unit": "targets/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": r["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if main_p == "fp64" else "c64-f64phase", "data": "synthetic",
+        "config": {"workload": "starfish r=1+0.3cos5t, Fresnel number 20, 40000 nodes; 1000x1000 grid "
+                               "(type 1) + 1e5 random targets (type 3)",
+                   "tolerance": 1e-9 if main_p == "fp64" else 1e-5, "targets_per_step": 1_100_000},
+        "stages_ms": {p: {"grid": res[p]["grid_stage_ms"], "points": res[p]["points_stage_ms"]} for p in precs},
+    }
+    if "mixed" in res and main_p != "mixed":
+        out["mixed"] = {"value": res["mixed"]["value"], "ms_per_step": res["mixed"]["ms_per_step"],
+                        "dtype": "c64-f64phase", "tolerance": 1e-5}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

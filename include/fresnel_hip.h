@@ -74,7 +74,7 @@ typedef struct fh_quad fh_quad;
  * two factors the paper reports for its FFTs, sec. 3.1). */
 typedef struct fh_options {
     double sigma;           /* 2.0 or 1.25                                   */
-    int32_t kernel_width;   /* 2..16 cells                                   */
+    int32_t kernel_width;   /* 2..20 cells                                   */
     double beta;            /* kernel shape parameter                        */
     int32_t tile;           /* spread tile edge in cells: 8, 16, 32 or 64    */
     int32_t max_subproblem; /* max nonuniform points per spread work item    */
@@ -223,11 +223,21 @@ fh_status fh_autotune_grid(fh_ctx* ctx, const fh_quad* q, double lambda, double 
                            int32_t n2, double h1, double h2, const char* cache_path,
                            fh_options* best);
 
-/* Device time in milliseconds of the stages of the most recent field call
- * on this context, when timing is enabled (FH_TIMING=1 in the environment
- * at fh_create): [0] prep+bin, [1] spread, [2] FFT, [3] epilogue or
- * interpolation, [4] total.  Synchronises the stream. */
+/* Stage timing.  While enabled (fh_set_timing, or FH_TIMING=1 in the
+ * environment at fh_create) every fh_field_grid / fh_field_points /
+ * fh_field_grid_vjp call records HIP events on the context stream around
+ * its stages, without synchronising.  Stages: [0] strengths + binning,
+ * [1] spread (or, for the adjoint, its gather), [2] FFT, [3] finish
+ * (deconvolution epilogue, type-3 interpolation, or adjoint node
+ * gradients), [4] whole call.  While timing is on, batched calls run
+ * eagerly instead of as a hipGraph so that their stages can be timed.
+ * fh_last_timing returns the most recent call's stage times in
+ * milliseconds; fh_timing_totals returns, for one kind of call (0 grid,
+ * 1 points, 2 adjoint, 3 batch), the sums over all timed calls since its
+ * last reset and their count.  Both synchronise. */
+fh_status fh_set_timing(fh_ctx* ctx, int32_t enable);
 fh_status fh_last_timing(fh_ctx* ctx, double* ms5);
+fh_status fh_timing_totals(fh_ctx* ctx, int32_t kind, double* ms5, int64_t* ncalls, int32_t reset);
 
 #ifdef __cplusplus
 }

@@ -144,6 +144,12 @@ class Context:
     def last_timing(self):
         return abi.fh_last_timing(self.handle)
 
+    def set_timing(self, enable: bool):
+        abi.fh_set_timing(self.handle, enable)
+
+    def timing_totals(self, kind: int, reset: bool = False):
+        return abi.fh_timing_totals(self.handle, kind, reset)
+
     def close(self):
         if self.handle is not None:
             abi.fh_destroy(self.handle)

@@ -35,7 +35,7 @@ EXPORTED = [
     "fh_status_string", "fh_last_error", "fh_quad_from_boundary", "fh_quad_radial", "fh_quad_polygon",
     "fh_quad_starshade", "fh_quad_from_nodes", "fh_quad_size", "fh_quad_export", "fh_quad_device_ptrs",
     "fh_quad_destroy", "fh_field_grid", "fh_field_points", "fh_field_grid_batch", "fh_field_grid_vjp",
-    "fh_starshade_vjp", "fh_autotune_grid", "fh_last_timing",
+    "fh_starshade_vjp", "fh_autotune_grid", "fh_set_timing", "fh_last_timing", "fh_timing_totals",
 ]
 
 
@@ -86,7 +86,9 @@ def lib():
             "fh_field_grid_vjp": [vp, vp, d, d, i32, i32, d, d, d, d, i32, vp, vp, vp, vp],
             "fh_starshade_vjp": [vp, i32, d, d, d, d, i32, i32, i32, i32, vp, i32, vp, vp, vp, vp],
             "fh_autotune_grid": [vp, vp, d, d, i32, i32, d, d, ctypes.c_char_p, ctypes.POINTER(fh_options)],
+            "fh_set_timing": [vp, i32],
             "fh_last_timing": [vp, ctypes.POINTER(d)],
+            "fh_timing_totals": [vp, i32, ctypes.POINTER(d), ctypes.POINTER(i64), i32],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -298,7 +300,22 @@ def fh_autotune_grid(ctx, q, lam, z, n1, n2, h1, h2, cache_path=None):
     return best
 
 
+def fh_set_timing(ctx, enable: bool):
+    _check(lib().fh_set_timing(ctx, int(bool(enable))))
+
+
 def fh_last_timing(ctx):
     arr = (ctypes.c_double * 5)()
     _check(lib().fh_last_timing(ctx, arr))
     return list(arr)
+
+
+TIMING_GRID, TIMING_POINTS, TIMING_VJP, TIMING_BATCH = 0, 1, 2, 3
+
+
+def fh_timing_totals(ctx, kind: int, reset: bool = False):
+    """(per-stage millisecond sums, number of timed calls) for one call kind."""
+    arr = (ctypes.c_double * 5)()
+    n = ctypes.c_int64()
+    _check(lib().fh_timing_totals(ctx, kind, arr, ctypes.byref(n), int(bool(reset))))
+    return list(arr), n.value

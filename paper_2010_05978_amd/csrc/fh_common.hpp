@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 #include <rocfft/rocfft.h>
 
+#include <array>
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
@@ -49,7 +50,7 @@ void set_error(const char* fmt, ...) __attribute__((format(printf, 1, 2)));
     } while (0)
 
 constexpr double kPi = 3.14159265358979323846264338327950288;
-constexpr int kMaxWidth = 16;
+constexpr int kMaxWidth = 20;
 constexpr int kMaxFourier = 64;
 
 // ------------------------------------------------------------ ES kernel
@@ -92,6 +93,7 @@ struct GridGeom {
     int W;         // kernel width
     int L;         // padded tile edge T + W - 1
     int P;         // max points per subproblem
+    int method;    // 1: thread per point, 2: wavefront per point
 };
 
 struct Sub {
@@ -141,9 +143,19 @@ struct fh_ctx {
     double tol = 1e-9;
     fh_options opt{};
     int cu_count = 256;
+    // Stage timing: every timed call records 6 events on the context stream
+    // (start, after bin, after spread, after FFT, after finish, end); the
+    // sets are read back only when the caller asks, so timing adds no sync.
+    // Calls are tallied per kind: 0 grid, 1 points, 2 adjoint, 3 batch.
     bool timing = false;
-    hipEvent_t ev[6]{};
+    int timing_kind = 0;
+    std::vector<std::pair<int, std::array<hipEvent_t, 6>>> ev_sets;  // recorded, not yet read
+    std::vector<std::array<hipEvent_t, 6>> ev_free;                   // reusable
+    std::array<hipEvent_t, 6> ev_cur{};
+    bool ev_open = false;
     double last_ms[5]{};
+    double sum_ms[4][5]{};
+    int64_t timed_calls[4]{};
 
     fh::Arena arena;
     size_t alloc_cap = 0;  // optional cap on device bytes (testing)

@@ -355,21 +355,48 @@ fh_status fft_exec(fh_ctx* c, FftPlan* p, void* data)
 // ----------------------------------------------------------------- timing
 void timing_mark(fh_ctx* c, int i)
 {
-    if (c->timing) (void)hipEventRecord(c->ev[i], c->stream);
+    if (!c->timing) return;
+    if (i == 0) {
+        if (c->ev_free.empty()) {
+            std::array<hipEvent_t, 6> s{};
+            for (auto& e : s)
+                if (hipEventCreate(&e) != hipSuccess) return;
+            c->ev_free.push_back(s);
+        }
+        c->ev_cur = c->ev_free.back();
+        c->ev_free.pop_back();
+        c->ev_open = true;
+    }
+    if (!c->ev_open) return;
+    (void)hipEventRecord(c->ev_cur[i], c->stream);
+    if (i == 5) {
+        c->ev_sets.emplace_back(c->timing_kind, c->ev_cur);
+        c->ev_open = false;
+    }
 }
 
+// Read back every recorded set: accumulate stage sums and keep the last.
 void timing_finish(fh_ctx* c)
 {
-    if (!c->timing) return;
-    (void)hipEventSynchronize(c->ev[5]);
-    float ms;
-    for (int i = 0; i < 4; ++i) {
+    for (auto& ks : c->ev_sets) {
+        const int kind = ks.first;
+        auto& s = ks.second;
+        (void)hipEventSynchronize(s[5]);
+        float ms;
+        for (int i = 0; i < 4; ++i) {
+            ms = 0;
+            (void)hipEventElapsedTime(&ms, s[i], s[i + 1]);
+            c->last_ms[i] = ms;
+            c->sum_ms[kind][i] += ms;
+        }
         ms = 0;
-        (void)hipEventElapsedTime(&ms, c->ev[i], c->ev[i + 1]);
-        c->last_ms[i] = ms;
+        (void)hipEventElapsedTime(&ms, s[0], s[5]);
+        c->last_ms[4] = ms;
+        c->sum_ms[kind][4] += ms;
+        c->timed_calls[kind]++;
+        c->ev_free.push_back(s);
     }
-    (void)hipEventElapsedTime(&ms, c->ev[0], c->ev[5]);
-    c->last_ms[4] = ms;
+    c->ev_sets.clear();
 }
 
 // ----------------------------------------------------------- quad objects
@@ -473,8 +500,6 @@ fh_status fh_create(fh_ctx** out, int device, fh_precision prec, double tol, con
         c->cu_count = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
         if (const char* cap = std::getenv("FH_ALLOC_CAP_BYTES")) c->alloc_cap = std::strtoull(cap, nullptr, 10);
         if (const char* t = std::getenv("FH_TIMING")) c->timing = std::atoi(t) != 0;
-        if (c->timing)
-            for (auto& e : c->ev) FH_HIP(hipEventCreate(&e));
         *out = c.release();
         return FH_OK;
     } catch (...) {
@@ -498,8 +523,11 @@ fh_status fh_destroy(fh_ctx* c)
     }
     for (auto& kv : c->owned) (void)hipFree(kv.first);
     if (c->bbox_host) (void)hipHostFree(c->bbox_host);
-    if (c->timing)
-        for (auto& e : c->ev) (void)hipEventDestroy(e);
+    timing_finish(c);
+    for (auto& s : c->ev_free)
+        for (auto& e : s) (void)hipEventDestroy(e);
+    if (c->ev_open)
+        for (auto& e : c->ev_cur) (void)hipEventDestroy(e);
     delete c;
     return FH_OK;
 }
@@ -548,9 +576,31 @@ fh_status fh_query_params(const fh_ctx* c, int32_t n, int32_t* width, double* be
 fh_status fh_last_timing(fh_ctx* c, double* ms5)
 {
     FH_ARG(c && ms5, FH_ERR_INVALID_ARG, "NULL argument");
-    FH_ARG(c->timing, FH_ERR_UNSUPPORTED, "timing is off (set FH_TIMING=1 before fh_create)");
+    FH_ARG(c->timing, FH_ERR_UNSUPPORTED, "timing is off (fh_set_timing)");
     timing_finish(c);
     for (int i = 0; i < 5; ++i) ms5[i] = c->last_ms[i];
+    return FH_OK;
+}
+
+fh_status fh_set_timing(fh_ctx* c, int32_t enable)
+{
+    FH_ARG(c, FH_ERR_INVALID_ARG, "ctx is NULL");
+    timing_finish(c);
+    c->timing = enable != 0;
+    return FH_OK;
+}
+
+fh_status fh_timing_totals(fh_ctx* c, int32_t kind, double* ms5, int64_t* ncalls, int32_t reset)
+{
+    FH_ARG(c && ms5 && ncalls, FH_ERR_INVALID_ARG, "NULL argument");
+    FH_ARG(kind >= 0 && kind < 4, FH_ERR_INVALID_ARG, "kind must be 0..3");
+    timing_finish(c);
+    for (int i = 0; i < 5; ++i) ms5[i] = c->sum_ms[kind][i];
+    *ncalls = c->timed_calls[kind];
+    if (reset) {
+        for (double& v : c->sum_ms[kind]) v = 0;
+        c->timed_calls[kind] = 0;
+    }
     return FH_OK;
 }
 

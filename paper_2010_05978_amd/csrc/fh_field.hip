@@ -104,21 +104,48 @@ __global__ void k_fill_field(R* __restrict__ u, int64_t M, R re)
 }
 
 // ------------------------------------------------------------------- bin
-__global__ void k_bin_count(InstParams p0, const InstParams* __restrict__ table, int ninst,
-                            int64_t Ntot, GridGeom gg, int* __restrict__ cnt, int* __restrict__ rank)
+// Rank of each lane's key among all increments of cnt[key]: one atomic per
+// distinct key in the wavefront (quadrature nodes arrive in spoke order, so a
+// wavefront touches only a few tiles, and the crowded tiles near the origin
+// would otherwise serialise thousands of same-address atomics).
+__device__ __forceinline__ int wave_rank(int* __restrict__ cnt, int key, bool valid)
+{
+    const int lane = (int)__lane_id();
+    uint64_t remaining = __ballot(valid);
+    int rank = 0;
+    while (remaining) {
+        const int leader = __ffsll((unsigned long long)remaining) - 1;
+        const int lkey = __shfl(key, leader);
+        const uint64_t same = __ballot(valid && key == lkey) & remaining;
+        int base = 0;
+        if (lane == leader) base = atomicAdd(&cnt[lkey], __popcll(same));
+        base = __shfl(base, leader);
+        if ((same >> lane) & 1ull) rank = base + __popcll(same & ((1ull << lane) - 1ull));
+        remaining &= ~same;
+    }
+    return rank;
+}
+
+__global__ void __launch_bounds__(256) k_bin_count(InstParams p0, const InstParams* __restrict__ table, int ninst,
+                                                   int64_t Ntot, GridGeom gg, int* __restrict__ cnt,
+                                                   int* __restrict__ rank)
 {
     const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (j >= Ntot) return;
-    const InstParams ip = table ? table[find_inst(table, ninst, j)] : p0;
-    const int64_t jj = j - ip.node_off;
-    const double x = ip.x[jj], y = ip.y[jj];
-    int l1, l2;
-    double d1, d2;
-    bool ok1, ok2;
-    cell_of((x - ip.cx) * ip.s1, gg.nf1, gg.W, l1, d1, ok1);
-    cell_of((y - ip.cy) * ip.s2, gg.nf2, gg.W, l2, d2, ok2);
-    const int tile = ip.tile_off + (l2 / gg.T) * gg.ntx + (l1 / gg.T);
-    rank[j] = atomicAdd(&cnt[tile], 1);
+    const bool valid = j < Ntot;
+    int tile = 0;
+    if (valid) {
+        const InstParams ip = table ? table[find_inst(table, ninst, j)] : p0;
+        const int64_t jj = j - ip.node_off;
+        const double x = ip.x[jj], y = ip.y[jj];
+        int l1, l2;
+        double d1, d2;
+        bool ok1, ok2;
+        cell_of((x - ip.cx) * ip.s1, gg.nf1, gg.W, l1, d1, ok1);
+        cell_of((y - ip.cy) * ip.s2, gg.nf2, gg.W, l2, d2, ok2);
+        tile = ip.tile_off + (l2 / gg.T) * gg.ntx + (l1 / gg.T);
+    }
+    const int r = wave_rank(cnt, tile, valid);
+    if (valid) rank[j] = r;
 }
 
 // One block: exclusive scan of tile counts -> tile offsets, and the list of
@@ -204,6 +231,28 @@ __global__ void k_bin_place(InstParams p0, const InstParams* __restrict__ table,
 }
 
 // ----------------------------------------------------------------- spread
+// Add a padded L x L LDS tile (split re/im planes) into the periodic fine
+// grid at origin (ox, oy); empty cells are skipped.
+template <class R>
+__device__ __forceinline__ void flush_tile(const R* sre, const R* sim, int L, R* __restrict__ g, int ox, int oy,
+                                           int nf1, int nf2)
+{
+    const int LL = L * L;
+    for (int e = threadIdx.x; e < LL; e += blockDim.x) {
+        const R vr = sre[e], vi = sim[e];
+        if (vr != R(0) || vi != R(0)) {
+            const int jy = e / L, ix = e - jy * L;
+            int gx = ox + ix;
+            if (gx >= nf1) gx -= nf1;
+            int gy = oy + jy;
+            if (gy >= nf2) gy -= nf2;
+            R* dst = g + 2 * ((size_t)gy * nf1 + gx);
+            atomicAdd(dst, vr);
+            atomicAdd(dst + 1, vi);
+        }
+    }
+}
+
 // One work item (tile, point range) per loop trip of a block; each thread
 // spreads whole points into the block's LDS tile (split re/im planes) with
 // LDS atomics; the tile is then added once into the fine grid.
@@ -252,20 +301,112 @@ __global__ void __launch_bounds__(256) k_spread(const Sub* __restrict__ subs, co
             }
         }
         __syncthreads();
-        R* g = grid + (size_t)inst * gg.nf1 * gg.nf2 * 2;
+        flush_tile(sre, sim, L, grid + (size_t)inst * gg.nf1 * gg.nf2 * 2, ox, oy, gg.nf1, gg.nf2);
+        __syncthreads();
+    }
+}
+
+// Uniform (scalar) copy of lane q's value.
+__device__ __forceinline__ int lane_val(int v, int q) { return __builtin_amdgcn_readlane(v, q); }
+__device__ __forceinline__ float lane_val(float v, int q)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), q));
+}
+__device__ __forceinline__ double lane_val(double v, int q)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), q);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), q);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Wavefront-per-point spread.  A wavefront loads 64 points and stages their
+// 2W kernel values in LDS; it then walks the points one at a time with its
+// lanes laid over the W x W stencil (ceil(W^2/64) passes), so the LDS atomics
+// of one instruction never share an address however tightly the points
+// cluster (the dilation rule crowds nodes near the origin).
+template <class R, int W>
+__global__ void __launch_bounds__(256) k_spread_wave(const Sub* __restrict__ subs, const int* __restrict__ nsub_ptr,
+                                                     const uint32_t* __restrict__ cell,
+                                                     const typename V2<R>::T* __restrict__ dd,
+                                                     const typename V2<R>::T* __restrict__ cc,
+                                                     R* __restrict__ grid, GridGeom gg, int tiles_per_inst, R beta)
+{
+    constexpr int KS = 2 * W + 1;               // staging stride per point
+    constexpr int NPASS = (W * W + 63) / 64;    // stencil passes per point
+    extern __shared__ unsigned char smem_raw[];
+    R* sre = reinterpret_cast<R*>(smem_raw);
+    const int L = gg.L, LL = L * L;
+    R* sim = sre + LL;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    R* kb = sim + LL + wv * 64 * KS;
+    int pa[NPASS], pb[NPASS];
+    bool pv[NPASS];
+#pragma unroll
+    for (int p = 0; p < NPASS; ++p) {
+        const int e = lane + 64 * p;
+        pv[p] = e < W * W;
+        pa[p] = pv[p] ? e % W : 0;
+        pb[p] = pv[p] ? e / W : 0;
+    }
+    const int nsub = *nsub_ptr;
+    for (int s = blockIdx.x; s < nsub; s += gridDim.x) {
+        const Sub sb = subs[s];
+        const int inst = sb.tile / tiles_per_inst;
+        const int tl = sb.tile - inst * tiles_per_inst;
+        const int ty = tl / gg.ntx, tx = tl - ty * gg.ntx;
+        const int ox = tx * gg.T, oy = ty * gg.T;
         for (int e = threadIdx.x; e < LL; e += blockDim.x) {
-            const R vr = sre[e], vi = sim[e];
-            if (vr != R(0) || vi != R(0)) {
-                const int jy = e / L, ix = e - jy * L;
-                int gx = ox + ix;
-                if (gx >= gg.nf1) gx -= gg.nf1;
-                int gy = oy + jy;
-                if (gy >= gg.nf2) gy -= gg.nf2;
-                R* dst = g + 2 * ((size_t)gy * gg.nf1 + gx);
-                atomicAdd(dst, vr);
-                atomicAdd(dst + 1, vi);
-            }
+            sre[e] = R(0);
+            sim[e] = R(0);
         }
+        __syncthreads();
+        for (int base = sb.start + wv * 64; base < sb.end; base += nw * 64) {
+            const int p = base + lane;
+            int l1 = 0, l2 = 0;
+            R cr = R(0), ci = R(0);
+            if (p < sb.end) {
+                const uint32_t cp = cell[p];
+                l1 = (int)(cp & 0xffffu) - ox;
+                l2 = (int)(cp >> 16) - oy;
+                const typename V2<R>::T dv = dd[p];
+                const typename V2<R>::T cv = cc[p];
+                cr = cv.x;
+                ci = cv.y;
+                R k[W];
+                es_weights<R, W>(dv.x, beta, k);
+#pragma unroll
+                for (int a = 0; a < W; ++a) kb[lane * KS + a] = k[a];
+                es_weights<R, W>(dv.y, beta, k);
+#pragma unroll
+                for (int b = 0; b < W; ++b) kb[lane * KS + W + b] = k[b];
+            }
+            // LDS traffic of one wavefront is processed in order; the fences
+            // keep the compiler from moving the staging reads above the writes.
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            const int np = min(64, sb.end - base);
+            for (int q = 0; q < np; ++q) {
+                const int ql1 = lane_val(l1, q), ql2 = lane_val(l2, q);
+                const R qr = lane_val(cr, q), qi = lane_val(ci, q);
+                const R* kq = kb + q * KS;
+#pragma unroll
+                for (int pp = 0; pp < NPASS; ++pp) {
+                    if (pv[pp]) {
+                        const R kv = kq[pa[pp]] * kq[W + pb[pp]];
+                        const int idx = (ql2 + pb[pp]) * L + ql1 + pa[pp];
+                        atomicAdd(sre + idx, qr * kv);
+                        atomicAdd(sim + idx, qi * kv);
+                    }
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+        __syncthreads();
+        flush_tile(sre, sim, L, grid + (size_t)inst * gg.nf1 * gg.nf2 * 2, ox, oy, gg.nf1, gg.nf2);
         __syncthreads();
     }
 }
@@ -445,41 +586,69 @@ __global__ void __launch_bounds__(256) k_bbox_partial(const double* __restrict__
     }
 }
 
-__global__ void k_bbox_final(const double* __restrict__ part, int nparts, double* __restrict__ out)
+__global__ void __launch_bounds__(256) k_bbox_final(const double* __restrict__ part, int nparts,
+                                                    double* __restrict__ out)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    __shared__ double s[5][256];
     double v[5] = {INFINITY, -INFINITY, INFINITY, -INFINITY, 0.0};
-    for (int p = 0; p < nparts; ++p) {
+    for (int p = threadIdx.x; p < nparts; p += blockDim.x) {
         v[0] = fmin(v[0], part[5 * p]);
         v[1] = fmax(v[1], part[5 * p + 1]);
         v[2] = fmin(v[2], part[5 * p + 2]);
         v[3] = fmax(v[3], part[5 * p + 3]);
         v[4] = fmax(v[4], part[5 * p + 4]);
     }
-    for (int q = 0; q < 5; ++q) out[q] = v[q];
+    for (int q = 0; q < 5; ++q) s[q][threadIdx.x] = v[q];
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) {
+            const int t = threadIdx.x;
+            s[0][t] = fmin(s[0][t], s[0][t + o]);
+            s[1][t] = fmax(s[1][t], s[1][t + o]);
+            s[2][t] = fmin(s[2][t], s[2][t + o]);
+            s[3][t] = fmax(s[3][t], s[3][t + o]);
+            s[4][t] = fmax(s[4][t], s[4][t + o]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int q = 0; q < 5; ++q) out[q] = s[q][0];
 }
 
 // ------------------------------------------------------- launch helpers
+constexpr size_t kLdsBudget = 64 * 1024;
+
 template <class R, int W>
-void launch_spread_w(fh_ctx* c, unsigned grid, size_t lds, const Sub* subs, const int* nsub,
-                     const uint32_t* cell, const void* dd, const void* cc, R* fine, const GridGeom& gg,
-                     int tpi, double beta)
+void launch_spread_w(fh_ctx* c, unsigned grid, const Sub* subs, const int* nsub, const uint32_t* cell,
+                     const void* dd, const void* cc, R* fine, const GridGeom& gg, int tpi, double beta)
 {
-    hipLaunchKernelGGL((k_spread<R, W>), dim3(grid), dim3(256), lds, c->stream, subs, nsub, cell,
-                       (const typename V2<R>::T*)dd, (const typename V2<R>::T*)cc, fine, gg, tpi, (R)beta);
+    const size_t tile = 2 * sizeof(R) * (size_t)gg.L * gg.L;
+    if (gg.method == 1) {
+        hipLaunchKernelGGL((k_spread<R, W>), dim3(grid), dim3(256), tile, c->stream, subs, nsub, cell,
+                           (const typename V2<R>::T*)dd, (const typename V2<R>::T*)cc, fine, gg, tpi, (R)beta);
+        return;
+    }
+    const size_t per_wave = sizeof(R) * 64 * (2 * W + 1);
+    int nw = 4;
+    while (nw > 1 && tile + nw * per_wave > kLdsBudget) --nw;
+    hipLaunchKernelGGL((k_spread_wave<R, W>), dim3(grid), dim3(64 * nw), tile + nw * per_wave, c->stream, subs,
+                       nsub, cell, (const typename V2<R>::T*)dd, (const typename V2<R>::T*)cc, fine, gg, tpi,
+                       (R)beta);
 }
 
 template <class R>
 fh_status launch_spread(fh_ctx* c, unsigned grid, const Sub* subs, const int* nsub, const uint32_t* cell,
                         const void* dd, const void* cc, R* fine, const GridGeom& gg, int tpi, double beta)
 {
-    const size_t lds = 2 * sizeof(R) * (size_t)gg.L * gg.L;
+    FH_ARG(2 * sizeof(R) * (size_t)gg.L * gg.L + sizeof(R) * 64 * (2 * gg.W + 1) <= kLdsBudget,
+           FH_ERR_UNSUPPORTED, "spread tile %d with width %d exceeds the LDS budget", gg.T, gg.W);
     switch (gg.W) {
 #define FH_SPREAD_CASE(w) \
-    case w: launch_spread_w<R, w>(c, grid, lds, subs, nsub, cell, dd, cc, fine, gg, tpi, beta); break;
+    case w: launch_spread_w<R, w>(c, grid, subs, nsub, cell, dd, cc, fine, gg, tpi, beta); break;
         FH_SPREAD_CASE(2) FH_SPREAD_CASE(3) FH_SPREAD_CASE(4) FH_SPREAD_CASE(5) FH_SPREAD_CASE(6)
         FH_SPREAD_CASE(7) FH_SPREAD_CASE(8) FH_SPREAD_CASE(9) FH_SPREAD_CASE(10) FH_SPREAD_CASE(11)
         FH_SPREAD_CASE(12) FH_SPREAD_CASE(13) FH_SPREAD_CASE(14) FH_SPREAD_CASE(15) FH_SPREAD_CASE(16)
+        FH_SPREAD_CASE(17) FH_SPREAD_CASE(18) FH_SPREAD_CASE(19) FH_SPREAD_CASE(20)
 #undef FH_SPREAD_CASE
     default: set_error("kernel width %d unsupported", gg.W); return FH_ERR_UNSUPPORTED;
     }
@@ -501,6 +670,7 @@ fh_status launch_interp(fh_ctx* c, int W, const R* G, const double* xi, const do
         FH_INTERP_CASE(2) FH_INTERP_CASE(3) FH_INTERP_CASE(4) FH_INTERP_CASE(5) FH_INTERP_CASE(6)
         FH_INTERP_CASE(7) FH_INTERP_CASE(8) FH_INTERP_CASE(9) FH_INTERP_CASE(10) FH_INTERP_CASE(11)
         FH_INTERP_CASE(12) FH_INTERP_CASE(13) FH_INTERP_CASE(14) FH_INTERP_CASE(15) FH_INTERP_CASE(16)
+        FH_INTERP_CASE(17) FH_INTERP_CASE(18) FH_INTERP_CASE(19) FH_INTERP_CASE(20)
 #undef FH_INTERP_CASE
     default: set_error("kernel width %d unsupported", W); return FH_ERR_UNSUPPORTED;
     }
@@ -575,6 +745,15 @@ fh_status run_spread(fh_ctx* c, const InstParams& p0, const InstParams* table, i
     return FH_OK;
 }
 
+// Spread method and work-item size: the wavefront-per-point spread is the
+// default (robust to the dense clusters of dilation rules); small work items
+// spread one crowded tile over many CUs.
+void spread_defaults(const fh_ctx* c, GridGeom& g)
+{
+    g.method = c->opt.spread_method > 0 ? c->opt.spread_method : 2;
+    g.P = c->opt.max_subproblem > 0 ? c->opt.max_subproblem : (g.method == 2 ? 256 : 1024);
+}
+
 fh_status check_lz(double lambda, double z)
 {
     FH_ARG(std::isfinite(lambda) && std::isfinite(z), FH_ERR_NONFINITE, "lambda or z not finite");
@@ -606,7 +785,7 @@ T1Plan plan_t1(fh_ctx* c, int n1, int n2)
     g.nf2 = next_fft_size(std::max(need2, T + W), T);
     g.ntx = g.nf1 / T;
     g.nty = g.nf2 / T;
-    g.P = c->opt.max_subproblem > 0 ? c->opt.max_subproblem : 1024;
+    spread_defaults(c, g);
     p.ntiles = g.ntx * g.nty;
     return p;
 }
@@ -661,6 +840,7 @@ fh_status field_grid_impl(fh_ctx* c, const fh_quad* q, double lambda, double z, 
     SpreadBufs sb = spread_carve(c, N, pl.ntiles, gg.P, rs);
     R* dout = mem == FH_MEM_HOST ? c->arena.take<R>(2 * M) : static_cast<R*>(u);
 
+    c->timing_kind = 0;
     timing_mark(c, 0);
     if (N == 0) {
         hipLaunchKernelGGL((k_fill_field<R>), dim3(nblocks(M, 256)), dim3(256), 0, c->stream, dout, M,
@@ -779,7 +959,7 @@ fh_status field_points_impl(fh_ctx* c, const fh_quad* q, double lambda, double z
     gg.nf2 = d2.nf;
     gg.ntx = d1.nf / T0;
     gg.nty = d2.nf / T0;
-    gg.P = c->opt.max_subproblem > 0 ? c->opt.max_subproblem : 1024;
+    spread_defaults(c, gg);
     const int ntiles = gg.ntx * gg.nty;
 
     const double* ip1 = nullptr;
@@ -824,6 +1004,7 @@ fh_status field_points_impl(fh_ctx* c, const fh_quad* q, double lambda, double z
     ip.s1 = d1.s;
     ip.s2 = d2.s;
 
+    c->timing_kind = 1;
     timing_mark(c, 0);
     FH_TRY(run_spread<R>(c, ip, nullptr, 1, N, gg, ntiles, sbuf, fine, fine_bytes, k.beta));
     hipLaunchKernelGGL((k_t3_precorrect<R>), dim3(nblocks(d1.m, 256), d2.m), dim3(256), 0, c->stream, fine,
@@ -936,6 +1117,7 @@ fh_status field_grid_batch_impl(fh_ctx* c, int B, const fh_quad* const* qs, cons
         return FH_OK;
     };
     if (!use_graph) {
+        c->timing_kind = 3;
         timing_mark(c, 0);
         return run();
     }
@@ -998,7 +1180,7 @@ fh_status device_bbox(fh_ctx* c, const double* x, const double* y, int64_t n, do
     double* hv = c->bbox_host;
     const unsigned g = (unsigned)std::min<int64_t>(parts, (n + 255) / 256);
     hipLaunchKernelGGL(k_bbox_partial, dim3(g), dim3(256), 0, c->stream, x, y, n, dv);
-    hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(64), 0, c->stream, dv, (int)g, dv + 5 * parts);
+    hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(256), 0, c->stream, dv, (int)g, dv + 5 * parts);
     FH_HIP(hipGetLastError());
     FH_HIP(hipMemcpyAsync(hv, dv + 5 * parts, sizeof(double) * 5, hipMemcpyDeviceToHost, c->stream));
     FH_HIP(hipStreamSynchronize(c->stream));

@@ -136,6 +136,34 @@ def test_grid_shapes_and_translation(ctx, n1, n2, h1, h2, xc, yc):
     assert relL2(u, ref) <= TOL[ctx.precision]
 
 
+@pytest.mark.parametrize("method,tile,P,sigma", [
+    (1, 16, 64, 0.0), (2, 16, 64, 0.0), (1, 32, 1024, 0.0), (2, 32, 4096, 0.0), (2, 8, 256, 0.0),
+    (2, 32, 256, 1.25), (1, 16, 512, 1.25),
+])
+def test_spread_variants(fh, ctx, method, tile, P, sigma):
+    # every spread method / tile / work-item size / upsampling the autotuner
+    # may pick meets the same bar
+    wl = workloads.workload(2)
+    shape = workloads.RadialCurve(1.0, wl.shape.a, wl.shape.b, panels=12, q=16, m=60)
+    opt = fh.fh_options(sigma=sigma, kernel_width=0, beta=0.0, tile=tile, max_subproblem=P, spread_method=method)
+    ctx.set_options(opt)
+    try:
+        q = ctx.quad_for(shape)
+        n = 160
+        u = cpu(ctx.field_grid(q, wl.lam, wl.z, n, n, 0.02, 0.02))
+        xi_t = torch.tensor(wl.points[0][:3000], device="cuda")
+        eta_t = torch.tensor(wl.points[1][:3000], device="cuda")
+        up = cpu(ctx.field_points(q, wl.lam, wl.z, xi_t, eta_t))
+    finally:
+        ctx.set_options(None)
+    x, y, w = oracle_quad(shape)
+    xi, eta = oracle.grid_targets(n, n, 0.02, 0.02)
+    ref = oracle.fresnel_direct(x, y, w, wl.lam, wl.z, xi, eta)
+    assert relL2(u, ref) <= TOL[ctx.precision]
+    refp = oracle.fresnel_direct(x, y, w, wl.lam, wl.z, wl.points[0][:3000], wl.points[1][:3000])
+    assert relL2(up, refp) <= TOL[ctx.precision]
+
+
 def test_grid_folding_undersampled(ctx):
     # target grid coarser than the field: rescaled nodes leave [-pi, pi) and
     # must be folded (sec. 2.2)
