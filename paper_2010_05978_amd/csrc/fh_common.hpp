@@ -73,7 +73,8 @@ struct InvPhiCheb {
 // ----------------------------------------------- per-instance prep params
 // Source-side parameters of one (quadrature, lambda, z) instance.
 //   phase in turns: t = (x^2 + y^2) pa + x px + y py + pc
-//   fine-grid coordinate: g1 = (x - cx) s1, g2 = (y - cy) s2
+//   fine-grid coordinate: g1 = (x - cx) s1, g2 = (y - cy) s2 - sh2, where the
+//   integer sh2 is the first fine-grid row of the instance's window
 struct InstParams {
     const double* x;
     const double* y;
@@ -81,19 +82,21 @@ struct InstParams {
     int64_t N;
     int64_t node_off;  // first slot of this instance in the concatenated node range
     int32_t tile_off;  // first tile id of this instance
-    int32_t pad_;
+    int32_t sh2;
     double pa, px, py, pc;
     double cx, cy, s1, s2;
 };
 
 struct GridGeom {
-    int nf1, nf2;  // fine grid (x fastest)
+    int nf1, nf2;  // fine grid period (x fastest)
     int T;         // tile edge
-    int ntx, nty;  // tiles per dimension
+    int ntx, nty;  // tiles per dimension (nty covers the held rows)
     int W;         // kernel width
     int L;         // padded tile edge T + W - 1
-    int P;         // max points per subproblem
+    int P;         // min points per spread work item
     int method;    // 1: thread per point, 2: wavefront per point
+    int rows;      // fine-grid rows held per instance (nf2 unless windowed)
+    int wrap_y;    // 1 when the held rows are the whole period
 };
 
 struct Sub {
@@ -166,6 +169,7 @@ struct fh_ctx {
     std::map<std::tuple<int, int, int, int>, fh::FftPlan> fft_cache;
     std::map<size_t, std::vector<void*>> pool;  // freed quadrature buffers by size
     std::map<std::string, fh::GraphEntry> graph_cache;
+    std::map<std::tuple<int, long long, long long>, fh::InvPhiCheb> cheb_cache;
     std::map<void*, size_t> owned;  // every hipMalloc'd block and its size
     double* bbox_dev = nullptr;      // bounding-box reduction scratch
     double* bbox_host = nullptr;     // pinned readback of the box
@@ -196,11 +200,16 @@ int next_fft_size(int n, int multiple);
 double phi_hat(const EsKernel& k, double theta);
 fh_status iphi_table(fh_ctx* c, const EsKernel& k, int n, int nf, const double** dev);
 void inv_phi_cheb(const EsKernel& k, double theta_max, InvPhiCheb* out);
+const InvPhiCheb& inv_phi_cheb_cached(fh_ctx* c, const EsKernel& k, double theta_max);
+// 2D transforms of nf1 x nf2 grids (nf1 fastest), or batched 1D transforms
+// of length nf1 when nf2 == 0; forward, in place, contiguous batches.
 fh_status fft_plan(fh_ctx* c, int nf1, int nf2, int batch, FftPlan** out);
 fh_status fft_exec(fh_ctx* c, FftPlan* p, void* data);
 fh_status quad_alloc(fh_ctx* c, int64_t N, fh_quad** out);
 fh_status quad_bbox(fh_ctx* c, const fh_quad* q, double* bb);
 fh_status device_bbox(fh_ctx* c, const double* x, const double* y, int64_t n, double* bb);
+fh_status device_bbox2(fh_ctx* c, const double* x1, const double* y1, int64_t n1, double* bb1, const double* x2,
+                       const double* y2, int64_t n2, double* bb2);
 void timing_mark(fh_ctx* c, int i);
 void timing_finish(fh_ctx* c);
 

@@ -298,6 +298,21 @@ void inv_phi_cheb(const EsKernel& k, double theta_max, InvPhiCheb* out)
     }
 }
 
+const InvPhiCheb& inv_phi_cheb_cached(fh_ctx* c, const EsKernel& k, double theta_max)
+{
+    long long kb, tb;
+    std::memcpy(&kb, &k.beta, sizeof(kb));
+    std::memcpy(&tb, &theta_max, sizeof(tb));
+    auto key = std::make_tuple(k.w, kb, tb);
+    auto it = c->cheb_cache.find(key);
+    if (it == c->cheb_cache.end()) {
+        InvPhiCheb ch;
+        inv_phi_cheb(k, theta_max, &ch);
+        it = c->cheb_cache.emplace(key, ch).first;
+    }
+    return it->second;
+}
+
 // ---------------------------------------------------------------- rocFFT
 static std::once_flag g_rocfft_once;
 
@@ -314,7 +329,7 @@ fh_status fft_plan(fh_ctx* c, int nf1, int nf2, int batch, FftPlan** out)
     size_t lengths[2] = {(size_t)nf1, (size_t)nf2};
     rocfft_precision pr = c->prec == FH_FP64 ? rocfft_precision_double : rocfft_precision_single;
     rocfft_status st = rocfft_plan_create(&p.plan, rocfft_placement_inplace,
-                                          rocfft_transform_type_complex_forward, pr, 2, lengths,
+                                          rocfft_transform_type_complex_forward, pr, nf2 > 0 ? 2 : 1, lengths,
                                           (size_t)batch, nullptr);
     if (st != rocfft_status_success) {
         set_error("rocfft_plan_create(%d x %d, batch %d) failed with %d", nf1, nf2, batch, (int)st);

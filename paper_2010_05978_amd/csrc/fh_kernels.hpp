@@ -1,0 +1,950 @@
+// fh_kernels.hpp -- device kernels and host launch helpers shared by the
+// forward field path (fh_field.hip) and its adjoint (fh_adjoint.hip).
+//
+// Binning: counting sort of nodes into T x T fine-grid tiles.  Spread: the
+// exponential-of-semicircle (ES) kernel into a (T+W-1)^2 LDS tile per work
+// item, written to one slot per work item.  Reduce: every fine-grid cell sums
+// the slots that cover it.  Type-1 finish: transpose/pad between the two FFT
+// passes and the deconvolving epilogue.  Type-3 finish: precorrection and
+// interpolation.  Plus bounding boxes and fills.
+#pragma once
+#include <algorithm>
+#include <cstring>
+
+#include "fh_common.hpp"
+
+namespace fh {
+namespace {
+
+inline unsigned nblocks(int64_t n, int bs) { return (unsigned)std::max<int64_t>(1, (n + bs - 1) / bs); }
+
+template <class R> struct V2;
+template <> struct V2<float> { using T = float2; };
+template <> struct V2<double> { using T = double2; };
+
+constexpr int kMaxSubPerTile = 64;  // work items per tile before items grow
+constexpr size_t kLdsBudget = 64 * 1024;
+
+// --------------------------------------------------------- device helpers
+__device__ __forceinline__ int find_inst(const InstParams* t, int n, int64_t j)
+{
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (t[mid].node_off <= j) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Fine-grid coordinate g -> first stencil cell (wrapped to [0, nf)) and the
+// offset d = cell - g in [-W/2, -W/2 + 1).  Non-finite g is mapped to cell 0
+// and flagged, so no index is ever out of range.
+__device__ __forceinline__ void cell_of(double g, int nf, int W, int& cell, double& d, bool& ok)
+{
+    const double fnf = (double)nf;
+    double gm = g - fnf * floor(g / fnf);
+    ok = (gm >= 0.0) && (gm <= fnf);
+    if (!ok) gm = 0.0;
+    const double l0 = ceil(gm - 0.5 * W);
+    d = l0 - gm;
+    int i = (int)l0;
+    if (i < 0) i += nf;
+    if (i >= nf) i -= nf;
+    cell = i;
+}
+
+// Node -> (x cell, y cell, offsets); y is relative to the instance's window.
+__device__ __forceinline__ bool node_cell(const InstParams& ip, const GridGeom& gg, double x, double y, int& l1,
+                                          int& l2, double& d1, double& d2)
+{
+    bool ok1, ok2;
+    cell_of((x - ip.cx) * ip.s1, gg.nf1, gg.W, l1, d1, ok1);
+    cell_of((y - ip.cy) * ip.s2 - (double)ip.sh2, gg.nf2, gg.W, l2, d2, ok2);
+    bool ok = ok1 && ok2;
+    if (!gg.wrap_y && l2 > gg.rows - gg.W) ok = false;  // outside the window
+    if (!ok) {
+        l1 = 0;
+        l2 = 0;
+    }
+    return ok;
+}
+
+template <class R, int W>
+__device__ __forceinline__ void es_weights(R d, R beta, R* k)
+{
+    const R s = R(2) / R(W);
+#pragma unroll
+    for (int a = 0; a < W; ++a) {
+        const R z = (d + R(a)) * s;
+        const R q = R(1) - z * z;
+        if constexpr (sizeof(R) == 4)
+            k[a] = __expf(beta * (__fsqrt_rn(fmaxf(q, 0.0f)) - 1.0f));
+        else
+            k[a] = exp(beta * (sqrt(fmax(q, 0.0)) - 1.0));
+    }
+}
+
+__device__ __forceinline__ double cheb_inv_phi(const InvPhiCheb& ch, double theta)
+{
+    const double u = theta / ch.theta_max;
+    const double s = 2.0 * u * u - 1.0;
+    double b1 = 0.0, b2 = 0.0;
+    for (int j = ch.deg; j >= 1; --j) {
+        const double b0 = 2.0 * s * b1 - b2 + ch.c[j];
+        b2 = b1;
+        b1 = b0;
+    }
+    return s * b1 - b2 + ch.c[0];
+}
+
+// Uniform (scalar) copy of lane q's value.
+__device__ __forceinline__ int lane_val(int v, int q) { return __builtin_amdgcn_readlane(v, q); }
+__device__ __forceinline__ float lane_val(float v, int q)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), q));
+}
+__device__ __forceinline__ double lane_val(double v, int q)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), q);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), q);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// ----------------------------------------------------------------- fills
+__global__ void k_zero16(uint4* __restrict__ p, size_t n)
+{
+    size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) p[i] = make_uint4(0, 0, 0, 0);
+}
+
+template <class R>
+__global__ void k_fill_field(R* __restrict__ u, int64_t M, R re)
+{
+    int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (k >= M) return;
+    u[2 * k] = re;
+    u[2 * k + 1] = R(0);
+}
+
+// ------------------------------------------------------------------- bin
+// Rank of each lane's key among all increments of cnt[key].  Lanes sharing a
+// key elect a leader; the leaders of all distinct keys in the wavefront issue
+// their atomics together (one round trip), and each lane adds its position
+// among the lanes with its key.  Quadrature nodes arrive in spoke order, so a
+// wavefront touches few tiles, while the crowded tiles near the origin would
+// otherwise serialise thousands of same-address atomics.
+__device__ __forceinline__ int wave_rank(int* __restrict__ cnt, int key, bool valid)
+{
+    const int lane = (int)__lane_id();
+    uint64_t remaining = __ballot(valid);
+    uint64_t mine = 0;
+    int leader = lane;
+    while (remaining) {
+        const int l = __ffsll((unsigned long long)remaining) - 1;
+        const int lkey = __shfl(key, l);
+        const uint64_t same = __ballot(valid && key == lkey) & remaining;
+        if ((same >> lane) & 1ull) {
+            mine = same;
+            leader = l;
+        }
+        remaining &= ~same;
+    }
+    int base = 0;
+    if (valid && leader == lane) base = atomicAdd(&cnt[key], __popcll(mine));
+    base = __shfl(base, leader);
+    return base + __popcll(mine & ((1ull << lane) - 1ull));
+}
+
+__global__ void __launch_bounds__(256) k_bin_count(InstParams p0, const InstParams* __restrict__ table, int ninst,
+                                                   int64_t Ntot, GridGeom gg, int* __restrict__ cnt,
+                                                   int* __restrict__ rank)
+{
+    const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const bool valid = j < Ntot;
+    int tile = 0;
+    if (valid) {
+        const InstParams ip = table ? table[find_inst(table, ninst, j)] : p0;
+        const int64_t jj = j - ip.node_off;
+        int l1, l2;
+        double d1, d2;
+        node_cell(ip, gg, ip.x[jj], ip.y[jj], l1, l2, d1, d2);
+        tile = ip.tile_off + (l2 / gg.T) * gg.ntx + (l1 / gg.T);
+    }
+    const int r = wave_rank(cnt, tile, valid);
+    if (valid) rank[j] = r;
+}
+
+// One block: exclusive scan of tile counts -> tile offsets, and the list of
+// spread work items (tile, [start, end)).  A tile's items hold at least P
+// points and at most kMaxSubPerTile items are made per tile, so a crowded
+// tile is spread by many CUs while the reduce stays short.
+__global__ void __launch_bounds__(1024) k_scan_tiles(const int* __restrict__ cnt, int ntiles, int P,
+                                                     int* __restrict__ off, int* __restrict__ tsub,
+                                                     Sub* __restrict__ subs, int* __restrict__ nsub_out)
+{
+    __shared__ int sa[1024];
+    __shared__ int sb[1024];
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int chunk = (ntiles + nt - 1) / nt;
+    const int t0 = min(ntiles, tid * chunk), t1 = min(ntiles, t0 + chunk);
+    int a = 0, b = 0;
+    for (int t = t0; t < t1; ++t) {
+        const int c = cnt[t];
+        const int Pt = max(P, (c + kMaxSubPerTile - 1) / kMaxSubPerTile);
+        a += c;
+        b += (c + Pt - 1) / Pt;
+    }
+    sa[tid] = a;
+    sb[tid] = b;
+    __syncthreads();
+    for (int o = 1; o < nt; o <<= 1) {
+        const int va = tid >= o ? sa[tid - o] : 0;
+        const int vb = tid >= o ? sb[tid - o] : 0;
+        __syncthreads();
+        sa[tid] += va;
+        sb[tid] += vb;
+        __syncthreads();
+    }
+    int ea = sa[tid] - a, eb = sb[tid] - b;
+    for (int t = t0; t < t1; ++t) {
+        const int c = cnt[t];
+        const int Pt = max(P, (c + kMaxSubPerTile - 1) / kMaxSubPerTile);
+        const int ns = (c + Pt - 1) / Pt;
+        off[t] = ea;
+        tsub[2 * t] = eb;
+        tsub[2 * t + 1] = ns;
+        for (int s = 0; s < ns; ++s) {
+            Sub w;
+            w.tile = t;
+            w.start = ea + s * Pt;
+            w.end = min(ea + (s + 1) * Pt, ea + c);
+            subs[eb + s] = w;
+        }
+        ea += c;
+        eb += ns;
+    }
+    if (tid == nt - 1) *nsub_out = sb[nt - 1];
+}
+
+// Strength (FP64 phase in turns, reduced), stencil offsets, and the sorted
+// position of each node.
+template <class R>
+__global__ void __launch_bounds__(256) k_bin_place(InstParams p0, const InstParams* __restrict__ table, int ninst,
+                                                   int64_t Ntot, GridGeom gg, const int* __restrict__ off,
+                                                   const int* __restrict__ rank, uint32_t* __restrict__ cell,
+                                                   typename V2<R>::T* __restrict__ dd,
+                                                   typename V2<R>::T* __restrict__ cc)
+{
+    const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (j >= Ntot) return;
+    const InstParams ip = table ? table[find_inst(table, ninst, j)] : p0;
+    const int64_t jj = j - ip.node_off;
+    const double x = ip.x[jj], y = ip.y[jj];
+    double w = ip.w[jj];
+    int l1, l2;
+    double d1, d2;
+    if (!node_cell(ip, gg, x, y, l1, l2, d1, d2)) w = 0.0;
+    const int tile = ip.tile_off + (l2 / gg.T) * gg.ntx + (l1 / gg.T);
+    const double t = ((x * x + y * y) * ip.pa + (x * ip.px + y * ip.py)) + ip.pc;
+    const double f = t - rint(t);
+    double s, c;
+    sincospi(2.0 * f, &s, &c);
+    const int pos = off[tile] + rank[j];
+    cell[pos] = (uint32_t)l1 | ((uint32_t)l2 << 16);
+    typename V2<R>::T dv, cv;
+    dv.x = (R)d1;
+    dv.y = (R)d2;
+    cv.x = (R)(w * c);
+    cv.y = (R)(w * s);
+    dd[pos] = dv;
+    cc[pos] = cv;
+}
+
+// ----------------------------------------------------------------- spread
+// Work item s covers the points [start, end) of one tile; its padded L x L
+// LDS tile (split re/im planes) is written to slot s.
+template <class R>
+__device__ __forceinline__ void store_slot(const R* sre, const R* sim, int LL, R* __restrict__ slot)
+{
+    for (int e = threadIdx.x; e < LL; e += blockDim.x) {
+        slot[e] = sre[e];
+        slot[LL + e] = sim[e];
+    }
+}
+
+template <class R>
+__device__ __forceinline__ void tile_origin(const Sub& sb, const GridGeom& gg, int tpi, int& ox, int& oy)
+{
+    const int inst = sb.tile / tpi;
+    const int tl = sb.tile - inst * tpi;
+    const int ty = tl / gg.ntx, tx = tl - ty * gg.ntx;
+    ox = tx * gg.T;
+    oy = ty * gg.T;
+}
+
+// Thread per point: each thread spreads whole points with LDS atomics.
+template <class R, int W>
+__global__ void __launch_bounds__(256) k_spread_thread(const Sub* __restrict__ subs, const int* __restrict__ nsub_ptr,
+                                                       const uint32_t* __restrict__ cell,
+                                                       const typename V2<R>::T* __restrict__ dd,
+                                                       const typename V2<R>::T* __restrict__ cc,
+                                                       R* __restrict__ slots, GridGeom gg, int tpi, R beta)
+{
+    extern __shared__ unsigned char smem_raw[];
+    R* sre = reinterpret_cast<R*>(smem_raw);
+    const int L = gg.L, LL = L * L;
+    R* sim = sre + LL;
+    const int nsub = *nsub_ptr;
+    for (int s = blockIdx.x; s < nsub; s += gridDim.x) {
+        const Sub sb = subs[s];
+        int ox, oy;
+        tile_origin<R>(sb, gg, tpi, ox, oy);
+        for (int e = threadIdx.x; e < LL; e += blockDim.x) {
+            sre[e] = R(0);
+            sim[e] = R(0);
+        }
+        __syncthreads();
+        for (int p = sb.start + (int)threadIdx.x; p < sb.end; p += blockDim.x) {
+            const uint32_t cp = cell[p];
+            const int l1 = (int)(cp & 0xffffu) - ox;
+            const int l2 = (int)(cp >> 16) - oy;
+            const typename V2<R>::T dv = dd[p];
+            const typename V2<R>::T cv = cc[p];
+            R k1[W], k2[W];
+            es_weights<R, W>(dv.x, beta, k1);
+            es_weights<R, W>(dv.y, beta, k2);
+#pragma unroll
+            for (int b = 0; b < W; ++b) {
+                const R vr = cv.x * k2[b], vi = cv.y * k2[b];
+                R* rr = sre + (l2 + b) * L + l1;
+                R* ri = sim + (l2 + b) * L + l1;
+#pragma unroll
+                for (int a = 0; a < W; ++a) {
+                    atomicAdd(rr + a, vr * k1[a]);
+                    atomicAdd(ri + a, vi * k1[a]);
+                }
+            }
+        }
+        __syncthreads();
+        store_slot(sre, sim, LL, slots + (size_t)s * 2 * LL);
+        __syncthreads();
+    }
+}
+
+// Wavefront per point.  A wavefront loads 64 points and stages their 2W
+// kernel values in LDS; it then walks the points one at a time with its lanes
+// laid over the W x W stencil (ceil(W^2/64) passes), so the LDS atomics of one
+// instruction never share an address however tightly the points cluster (the
+// dilation rule crowds nodes near the origin).
+template <class R, int W>
+__global__ void __launch_bounds__(256) k_spread_wave(const Sub* __restrict__ subs, const int* __restrict__ nsub_ptr,
+                                                     const uint32_t* __restrict__ cell,
+                                                     const typename V2<R>::T* __restrict__ dd,
+                                                     const typename V2<R>::T* __restrict__ cc,
+                                                     R* __restrict__ slots, GridGeom gg, int tpi, R beta)
+{
+    constexpr int KS = 2 * W + 1;             // staging stride per point
+    constexpr int NPASS = (W * W + 63) / 64;  // stencil passes per point
+    extern __shared__ unsigned char smem_raw[];
+    R* sre = reinterpret_cast<R*>(smem_raw);
+    const int L = gg.L, LL = L * L;
+    R* sim = sre + LL;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    R* kb = sim + LL + wv * 64 * KS;
+    int pa[NPASS], pb[NPASS];
+    bool pv[NPASS];
+#pragma unroll
+    for (int p = 0; p < NPASS; ++p) {
+        const int e = lane + 64 * p;
+        pv[p] = e < W * W;
+        pa[p] = pv[p] ? e % W : 0;
+        pb[p] = pv[p] ? e / W : 0;
+    }
+    const int nsub = *nsub_ptr;
+    for (int s = blockIdx.x; s < nsub; s += gridDim.x) {
+        const Sub sb = subs[s];
+        int ox, oy;
+        tile_origin<R>(sb, gg, tpi, ox, oy);
+        for (int e = threadIdx.x; e < LL; e += blockDim.x) {
+            sre[e] = R(0);
+            sim[e] = R(0);
+        }
+        __syncthreads();
+        for (int base = sb.start + wv * 64; base < sb.end; base += nw * 64) {
+            const int p = base + lane;
+            int l1 = 0, l2 = 0;
+            R cr = R(0), ci = R(0);
+            if (p < sb.end) {
+                const uint32_t cp = cell[p];
+                l1 = (int)(cp & 0xffffu) - ox;
+                l2 = (int)(cp >> 16) - oy;
+                const typename V2<R>::T dv = dd[p];
+                const typename V2<R>::T cv = cc[p];
+                cr = cv.x;
+                ci = cv.y;
+                R k[W];
+                es_weights<R, W>(dv.x, beta, k);
+#pragma unroll
+                for (int a = 0; a < W; ++a) kb[lane * KS + a] = k[a];
+                es_weights<R, W>(dv.y, beta, k);
+#pragma unroll
+                for (int b = 0; b < W; ++b) kb[lane * KS + W + b] = k[b];
+            }
+            // LDS traffic of one wavefront is processed in order; the fences
+            // keep the compiler from moving the staging reads above the writes.
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            const int np = min(64, sb.end - base);
+            for (int q = 0; q < np; ++q) {
+                const int ql1 = lane_val(l1, q), ql2 = lane_val(l2, q);
+                const R qr = lane_val(cr, q), qi = lane_val(ci, q);
+                const R* kq = kb + q * KS;
+#pragma unroll
+                for (int pp = 0; pp < NPASS; ++pp) {
+                    if (pv[pp]) {
+                        const R kv = kq[pa[pp]] * kq[W + pb[pp]];
+                        const int idx = (ql2 + pb[pp]) * L + ql1 + pa[pp];
+                        atomicAdd(sre + idx, qr * kv);
+                        atomicAdd(sim + idx, qi * kv);
+                    }
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+        __syncthreads();
+        store_slot(sre, sim, LL, slots + (size_t)s * 2 * LL);
+        __syncthreads();
+    }
+}
+
+// ----------------------------------------------------------------- reduce
+// Fine-grid cell (gx, gy) of tile (tx, ty) is covered by the padded tiles of
+// (tx - dx, ty - dy) for every dx, dy >= 0 with i + dx T < L and j + dy T < L
+// (periodic in x, and in y when the window is the whole grid; a padded tile
+// reaches ceil((W-1)/T) tiles on).  Each thread sums, in work-item order, the
+// slots of those tiles at its cell and writes the cell: every cell of the
+// held rows is written, zeros included.
+template <class R>
+__global__ void __launch_bounds__(256) k_reduce_tiles(const R* __restrict__ slots, const int* __restrict__ tsub,
+                                                      GridGeom gg, int tpi, R* __restrict__ F)
+{
+    const int T = gg.T, TT = T * T;
+    const int parts = (TT + 255) / 256;
+    const int tx = blockIdx.x, ty = blockIdx.y / parts, part = blockIdx.y - ty * parts, b = blockIdx.z;
+    const int e = part * 256 + threadIdx.x;
+    if (e >= TT) return;
+    const int i = e % T, j = e / T;
+    const int L = gg.L, LL = L * L;
+    R ar = R(0), ai = R(0);
+    for (int dy = 0; j + dy * T < L; ++dy) {
+        int sty = ty - dy;
+        if (sty < 0) {
+            if (!gg.wrap_y) break;
+            sty = ((sty % gg.nty) + gg.nty) % gg.nty;
+        }
+        const int ly = j + dy * T;
+        for (int dx = 0; i + dx * T < L; ++dx) {
+            const int stx = (((tx - dx) % gg.ntx) + gg.ntx) % gg.ntx;
+            const int lx = i + dx * T;
+            const int t = b * tpi + sty * gg.ntx + stx;
+            const int first = tsub[2 * t], cnt = tsub[2 * t + 1];
+            const R* sp = slots + (size_t)first * 2 * LL + ly * L + lx;
+            for (int k = 0; k < cnt; ++k) {
+                ar += sp[0];
+                ai += sp[LL];
+                sp += 2 * LL;
+            }
+        }
+    }
+    typename V2<R>::T v;
+    v.x = ar;
+    v.y = ai;
+    reinterpret_cast<typename V2<R>::T*>(F)[((size_t)b * gg.rows + ty * T + j) * gg.nf1 + tx * T + i] = v;
+}
+
+// --------------------------------------------------------- type-1 finish
+struct EpiInst {
+    double inv2lz;  // 1/(2 lambda z): target chirp in turns
+    double invlz;   // 1/(lambda z)
+    int occ;
+    int sh2;        // row shift of the instance's window
+};
+
+struct EpiParams {
+    int n1, n2, nf1, nf2;
+    double h1, h2, xc, yc;
+    const double* iphi1;
+    const double* iphi2;
+};
+
+// Z[b][c][r] = F[b][r][k1 mod nf1] with k1 = c - n1/2 for r < rows, 0 beyond:
+// the n1 needed columns after the first FFT pass, transposed and padded to
+// the full period for the second pass.
+template <class R>
+__global__ void __launch_bounds__(256) k_transpose_pad(const R* __restrict__ F, R* __restrict__ Z, int n1, int nf1,
+                                                       int nf2, int rows)
+{
+    using C2 = typename V2<R>::T;
+    __shared__ C2 t[32][33];
+    const int c0 = blockIdx.x * 32, r0 = blockIdx.y * 32, b = blockIdx.z;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    const C2* Fv = reinterpret_cast<const C2*>(F) + (size_t)b * rows * nf1;
+    for (int k = ty; k < 32; k += 8) {
+        const int r = r0 + k, cidx = c0 + tx;
+        C2 v;
+        v.x = R(0);
+        v.y = R(0);
+        if (r < rows && cidx < n1) {
+            int col = cidx - n1 / 2;
+            if (col < 0) col += nf1;
+            v = Fv[(size_t)r * nf1 + col];
+        }
+        t[k][tx] = v;
+    }
+    __syncthreads();
+    C2* Zv = reinterpret_cast<C2*>(Z) + (size_t)b * n1 * nf2;
+    for (int k = ty; k < 32; k += 8) {
+        const int cidx = c0 + k, r = r0 + tx;
+        if (cidx < n1 && r < nf2) Zv[(size_t)cidx * nf2 + r] = t[tx][k];
+    }
+}
+
+// u[b][k2][k1] from Z[b][k1 + n1/2][k2 mod nf2]: deconvolve by the kernel
+// transform, undo the window shift, apply the target chirp and 1/(i lambda z),
+// and Babinet.
+template <class R>
+__global__ void __launch_bounds__(256) k_epilogue_t1(const R* __restrict__ Z, R* __restrict__ u, EpiParams ep,
+                                                     EpiInst e0, const EpiInst* __restrict__ table)
+{
+    using C2 = typename V2<R>::T;
+    __shared__ C2 t[32][33];
+    const int k10 = blockIdx.x * 32, k20 = blockIdx.y * 32, b = blockIdx.z;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    const C2* Zv = reinterpret_cast<const C2*>(Z) + (size_t)b * ep.n1 * ep.nf2;
+    for (int k = ty; k < 32; k += 8) {
+        const int cidx = k10 + k, k2i = k20 + tx;
+        if (cidx < ep.n1 && k2i < ep.n2) {
+            int r = k2i - ep.n2 / 2;
+            if (r < 0) r += ep.nf2;
+            t[k][tx] = Zv[(size_t)cidx * ep.nf2 + r];
+        }
+    }
+    __syncthreads();
+    const EpiInst ei = table ? table[b] : e0;
+    for (int k = ty; k < 32; k += 8) {
+        const int k2i = k20 + k, k1i = k10 + tx;
+        if (k1i >= ep.n1 || k2i >= ep.n2) continue;
+        const C2 fv = t[tx][k];
+        const int k1 = k1i - ep.n1 / 2, k2 = k2i - ep.n2 / 2;
+        const double sc = ep.iphi1[k1i] * ep.iphi2[k2i];
+        const double vr = (double)fv.x * sc, vi = (double)fv.y * sc;
+        const double xi = ep.xc + ep.h1 * k1, eta = ep.yc + ep.h2 * k2;
+        // window shift: F_full[k2] = exp(-2 pi i k2 sh2/nf2) F_window[k2]
+        long long km = k2 % ep.nf2;
+        if (km < 0) km += ep.nf2;
+        long long sm = ei.sh2 % ep.nf2;
+        if (sm < 0) sm += ep.nf2;
+        const double shift = (double)((km * sm) % ep.nf2) / (double)ep.nf2;
+        const double tt = (xi * xi + eta * eta) * ei.inv2lz - shift;
+        const double f = tt - rint(tt);
+        double s, c;
+        sincospi(2.0 * f, &s, &c);
+        double re = (s * vr + c * vi) * ei.invlz;
+        double im = (s * vi - c * vr) * ei.invlz;
+        if (ei.occ) {
+            re = 1.0 - re;
+            im = -im;
+        }
+        C2 out;
+        out.x = (R)re;
+        out.y = (R)im;
+        reinterpret_cast<C2*>(u)[((size_t)b * ep.n2 + k2i) * ep.n1 + k1i] = out;
+    }
+}
+
+// --------------------------------------------------------- type-3 finish
+// Precorrect the spread grid b (modes l' in [-nf/2, nf/2)) by 1/Phi and
+// embed it in the upsampled grid G (every entry of G is written).
+template <class R>
+__global__ void k_t3_precorrect(const R* __restrict__ b, int nf1, int nf2, R* __restrict__ G, int m1, int m2,
+                                const double* __restrict__ ip1, const double* __restrict__ ip2)
+{
+    const int i1 = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i2 = blockIdx.y;
+    if (i1 >= m1) return;
+    const int k1 = i1 < m1 / 2 ? i1 : i1 - m1;
+    const int k2 = i2 < m2 / 2 ? i2 : i2 - m2;
+    typename V2<R>::T v;
+    v.x = R(0);
+    v.y = R(0);
+    if (k1 >= -(nf1 / 2) && k1 < nf1 - nf1 / 2 && k2 >= -(nf2 / 2) && k2 < nf2 - nf2 / 2) {
+        const int s1 = k1 < 0 ? k1 + nf1 : k1;
+        const int s2 = k2 < 0 ? k2 + nf2 : k2;
+        const typename V2<R>::T bv = reinterpret_cast<const typename V2<R>::T*>(b)[(size_t)s2 * nf1 + s1];
+        const double sc = ip1[k1 + nf1 / 2] * ip2[k2 + nf2 / 2];
+        v.x = (R)(bv.x * sc);
+        v.y = (R)(bv.y * sc);
+    }
+    reinterpret_cast<typename V2<R>::T*>(G)[(size_t)i2 * m1 + i1] = v;
+}
+
+struct T3Params {
+    int m1, m2;             // upsampled grid
+    double xic, etac;       // target centre
+    double g1, g2;          // interpolation grid coordinate per unit (xi - xic)
+    double th1, th2;        // theta per unit (xi - xic) for the 1/Phi correction
+    double inv2lz, invlz;   // target chirp (turns) and 1/(lambda z)
+    double Cx, Cy;          // source centre (post-phase exp(-i s.C))
+    int occ;
+    InvPhiCheb ch1, ch2;
+};
+
+template <class R, int W>
+__global__ void __launch_bounds__(256) k_t3_interp(const R* __restrict__ G, const double* __restrict__ xi,
+                                                   const double* __restrict__ eta, int64_t M, R beta,
+                                                   T3Params tp, R* __restrict__ u)
+{
+    const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (k >= M) return;
+    const double X = xi[k], Y = eta[k];
+    int l1, l2;
+    double d1, d2;
+    bool ok1, ok2;
+    cell_of((X - tp.xic) * tp.g1, tp.m1, W, l1, d1, ok1);
+    cell_of((Y - tp.etac) * tp.g2, tp.m2, W, l2, d2, ok2);
+    R k1[W], k2[W];
+    es_weights<R, W>((R)d1, beta, k1);
+    es_weights<R, W>((R)d2, beta, k2);
+    const typename V2<R>::T* Gv = reinterpret_cast<const typename V2<R>::T*>(G);
+    R sr = 0, si = 0;
+#pragma unroll
+    for (int b = 0; b < W; ++b) {
+        int row = l2 + b;
+        if (row >= tp.m2) row -= tp.m2;
+        const typename V2<R>::T* gr = Gv + (size_t)row * tp.m1;
+        R ar = 0, ai = 0;
+#pragma unroll
+        for (int a = 0; a < W; ++a) {
+            int col = l1 + a;
+            if (col >= tp.m1) col -= tp.m1;
+            const typename V2<R>::T gv = gr[col];
+            ar += gv.x * k1[a];
+            ai += gv.y * k1[a];
+        }
+        sr += ar * k2[b];
+        si += ai * k2[b];
+    }
+    const double corr = cheb_inv_phi(tp.ch1, (X - tp.xic) * tp.th1) * cheb_inv_phi(tp.ch2, (Y - tp.etac) * tp.th2);
+    const double vr = (double)sr * corr, vi = (double)si * corr;
+    const double t = (X * X + Y * Y) * tp.inv2lz - (X * tp.Cx + Y * tp.Cy) * tp.invlz;
+    const double f = t - rint(t);
+    double s, c;
+    sincospi(2.0 * f, &s, &c);
+    double re = (s * vr + c * vi) * tp.invlz;
+    double im = (s * vi - c * vr) * tp.invlz;
+    if (!(ok1 && ok2)) {
+        re = __builtin_nan("");
+        im = __builtin_nan("");
+    }
+    if (tp.occ) {
+        re = 1.0 - re;
+        im = -im;
+    }
+    u[2 * k] = (R)re;
+    u[2 * k + 1] = (R)im;
+}
+
+// ---------------------------------------------------------------- bbox
+__global__ void __launch_bounds__(256) k_bbox_partial(const double* __restrict__ x, const double* __restrict__ y,
+                                                      int64_t n, double* __restrict__ part)
+{
+    double v[4] = {INFINITY, -INFINITY, INFINITY, -INFINITY};
+    bool bad = false;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const double a = x[i], b = y[i];
+        bad |= !(isfinite(a) && isfinite(b));
+        v[0] = fmin(v[0], a);
+        v[1] = fmax(v[1], a);
+        v[2] = fmin(v[2], b);
+        v[3] = fmax(v[3], b);
+    }
+    __shared__ double s[4][256];
+    __shared__ int sbad;
+    if (threadIdx.x == 0) sbad = 0;
+    for (int q = 0; q < 4; ++q) s[q][threadIdx.x] = v[q];
+    __syncthreads();
+    if (bad) atomicOr(&sbad, 1);
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) {
+            s[0][threadIdx.x] = fmin(s[0][threadIdx.x], s[0][threadIdx.x + o]);
+            s[1][threadIdx.x] = fmax(s[1][threadIdx.x], s[1][threadIdx.x + o]);
+            s[2][threadIdx.x] = fmin(s[2][threadIdx.x], s[2][threadIdx.x + o]);
+            s[3][threadIdx.x] = fmax(s[3][threadIdx.x], s[3][threadIdx.x + o]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        for (int q = 0; q < 4; ++q) part[5 * blockIdx.x + q] = s[q][0];
+        part[5 * blockIdx.x + 4] = sbad ? 1.0 : 0.0;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_bbox_final(const double* __restrict__ part, int nparts,
+                                                    double* __restrict__ out)
+{
+    __shared__ double s[5][256];
+    double v[5] = {INFINITY, -INFINITY, INFINITY, -INFINITY, 0.0};
+    for (int p = threadIdx.x; p < nparts; p += blockDim.x) {
+        v[0] = fmin(v[0], part[5 * p]);
+        v[1] = fmax(v[1], part[5 * p + 1]);
+        v[2] = fmin(v[2], part[5 * p + 2]);
+        v[3] = fmax(v[3], part[5 * p + 3]);
+        v[4] = fmax(v[4], part[5 * p + 4]);
+    }
+    for (int q = 0; q < 5; ++q) s[q][threadIdx.x] = v[q];
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) {
+            const int t = threadIdx.x;
+            s[0][t] = fmin(s[0][t], s[0][t + o]);
+            s[1][t] = fmax(s[1][t], s[1][t + o]);
+            s[2][t] = fmin(s[2][t], s[2][t + o]);
+            s[3][t] = fmax(s[3][t], s[3][t + o]);
+            s[4][t] = fmax(s[4][t], s[4][t + o]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int q = 0; q < 5; ++q) out[q] = s[q][0];
+}
+
+// ------------------------------------------------------- launch helpers
+template <class R, int W>
+void launch_spread_w(fh_ctx* c, unsigned grid, const Sub* subs, const int* nsub, const uint32_t* cell,
+                     const void* dd, const void* cc, R* slots, const GridGeom& gg, int tpi, double beta)
+{
+    const size_t tile = 2 * sizeof(R) * (size_t)gg.L * gg.L;
+    if (gg.method == 1) {
+        hipLaunchKernelGGL((k_spread_thread<R, W>), dim3(grid), dim3(256), tile, c->stream, subs, nsub, cell,
+                           (const typename V2<R>::T*)dd, (const typename V2<R>::T*)cc, slots, gg, tpi, (R)beta);
+        return;
+    }
+    const size_t per_wave = sizeof(R) * 64 * (2 * W + 1);
+    int nw = 4;
+    while (nw > 1 && tile + nw * per_wave > kLdsBudget) --nw;
+    hipLaunchKernelGGL((k_spread_wave<R, W>), dim3(grid), dim3(64 * nw), tile + nw * per_wave, c->stream, subs,
+                       nsub, cell, (const typename V2<R>::T*)dd, (const typename V2<R>::T*)cc, slots, gg, tpi,
+                       (R)beta);
+}
+
+template <class R>
+fh_status launch_spread(fh_ctx* c, unsigned grid, const Sub* subs, const int* nsub, const uint32_t* cell,
+                        const void* dd, const void* cc, R* slots, const GridGeom& gg, int tpi, double beta)
+{
+    FH_ARG(2 * sizeof(R) * (size_t)gg.L * gg.L + sizeof(R) * 64 * (2 * gg.W + 1) <= kLdsBudget,
+           FH_ERR_UNSUPPORTED, "spread tile %d with width %d exceeds the LDS budget", gg.T, gg.W);
+    switch (gg.W) {
+#define FH_SPREAD_CASE(w) \
+    case w: launch_spread_w<R, w>(c, grid, subs, nsub, cell, dd, cc, slots, gg, tpi, beta); break;
+        FH_SPREAD_CASE(2) FH_SPREAD_CASE(3) FH_SPREAD_CASE(4) FH_SPREAD_CASE(5) FH_SPREAD_CASE(6)
+        FH_SPREAD_CASE(7) FH_SPREAD_CASE(8) FH_SPREAD_CASE(9) FH_SPREAD_CASE(10) FH_SPREAD_CASE(11)
+        FH_SPREAD_CASE(12) FH_SPREAD_CASE(13) FH_SPREAD_CASE(14) FH_SPREAD_CASE(15) FH_SPREAD_CASE(16)
+        FH_SPREAD_CASE(17) FH_SPREAD_CASE(18) FH_SPREAD_CASE(19) FH_SPREAD_CASE(20)
+#undef FH_SPREAD_CASE
+    default: set_error("kernel width %d unsupported", gg.W); return FH_ERR_UNSUPPORTED;
+    }
+    FH_HIP(hipGetLastError());
+    return FH_OK;
+}
+
+template <class R>
+fh_status launch_interp(fh_ctx* c, int W, const R* G, const double* xi, const double* eta, int64_t M,
+                        double beta, const T3Params& tp, R* u)
+{
+    const unsigned g = nblocks(M, 256);
+    switch (W) {
+#define FH_INTERP_CASE(w)                                                                           \
+    case w:                                                                                        \
+        hipLaunchKernelGGL((k_t3_interp<R, w>), dim3(g), dim3(256), 0, c->stream, G, xi, eta, M, (R)beta, \
+                           tp, u);                                                                 \
+        break;
+        FH_INTERP_CASE(2) FH_INTERP_CASE(3) FH_INTERP_CASE(4) FH_INTERP_CASE(5) FH_INTERP_CASE(6)
+        FH_INTERP_CASE(7) FH_INTERP_CASE(8) FH_INTERP_CASE(9) FH_INTERP_CASE(10) FH_INTERP_CASE(11)
+        FH_INTERP_CASE(12) FH_INTERP_CASE(13) FH_INTERP_CASE(14) FH_INTERP_CASE(15) FH_INTERP_CASE(16)
+        FH_INTERP_CASE(17) FH_INTERP_CASE(18) FH_INTERP_CASE(19) FH_INTERP_CASE(20)
+#undef FH_INTERP_CASE
+    default: set_error("kernel width %d unsupported", W); return FH_ERR_UNSUPPORTED;
+    }
+    FH_HIP(hipGetLastError());
+    return FH_OK;
+}
+
+// ------------------------------------------------------ spread pipeline
+// Buffers of one binned spread, carved from the arena.
+struct SpreadBufs {
+    int* cnt;       // points per tile
+    int* off;       // first sorted point of each tile
+    int* tsub;      // per tile: first work item, number of work items
+    int* rank;      // rank of each node within its tile
+    uint32_t* cell; // sorted: packed first stencil cell (x | y << 16)
+    void* dd;       // sorted: stencil offsets (2 reals)
+    void* cc;       // sorted: strengths (complex)
+    Sub* subs;      // work items
+    int* nsub;      // number of work items (device)
+    void* slots;    // one padded L x L complex tile per work item
+    int64_t max_sub;
+};
+
+// Type-1 geometry: kernel, fine grid and tiling.
+struct T1Plan {
+    EsKernel k;
+    GridGeom gg;
+};
+
+size_t spread_bytes(int64_t Ntot, const GridGeom& gg, int ntiles_total, size_t rsize)
+{
+    const int64_t max_sub = Ntot / gg.P + std::min<int64_t>(Ntot, ntiles_total) + 1;
+    return 2 * aligned_bytes(sizeof(int) * (size_t)ntiles_total) + aligned_bytes(2 * sizeof(int) * ntiles_total) +
+           aligned_bytes(sizeof(int) * Ntot) + aligned_bytes(sizeof(uint32_t) * Ntot) +
+           2 * aligned_bytes(2 * rsize * Ntot) + aligned_bytes(sizeof(Sub) * max_sub) + aligned_bytes(sizeof(int)) +
+           aligned_bytes(2 * rsize * (size_t)gg.L * gg.L * max_sub);
+}
+
+SpreadBufs spread_carve(fh_ctx* c, int64_t Ntot, const GridGeom& gg, int ntiles_total, size_t rsize)
+{
+    SpreadBufs b;
+    b.max_sub = Ntot / gg.P + std::min<int64_t>(Ntot, ntiles_total) + 1;
+    b.cnt = c->arena.take<int>(ntiles_total);
+    b.off = c->arena.take<int>(ntiles_total);
+    b.tsub = c->arena.take<int>(2 * (size_t)ntiles_total);
+    b.rank = c->arena.take<int>(Ntot);
+    b.cell = c->arena.take<uint32_t>(Ntot);
+    b.dd = c->arena.take<char>(2 * rsize * Ntot);
+    b.cc = c->arena.take<char>(2 * rsize * Ntot);
+    b.subs = c->arena.take<Sub>(b.max_sub);
+    b.nsub = c->arena.take<int>(1);
+    b.slots = c->arena.take<char>(2 * rsize * (size_t)gg.L * gg.L * b.max_sub);
+    return b;
+}
+
+// Bin, spread into slots, and reduce into F (B instances x rows x nf1).
+template <class R>
+fh_status run_spread(fh_ctx* c, const InstParams& p0, const InstParams* table, int ninst, int64_t Ntot,
+                     const GridGeom& gg, const SpreadBufs& b, R* F, double beta)
+{
+    const int tpi = gg.ntx * gg.nty;
+    const int ntiles_total = tpi * ninst;
+    FH_TRY(launch_zero(c, b.cnt, sizeof(int) * ntiles_total));
+    if (Ntot > 0) {
+        hipLaunchKernelGGL(k_bin_count, dim3(nblocks(Ntot, 256)), dim3(256), 0, c->stream, p0, table, ninst, Ntot,
+                           gg, b.cnt, b.rank);
+    }
+    hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, c->stream, b.cnt, ntiles_total, gg.P, b.off, b.tsub,
+                       b.subs, b.nsub);
+    if (Ntot > 0) {
+        hipLaunchKernelGGL((k_bin_place<R>), dim3(nblocks(Ntot, 256)), dim3(256), 0, c->stream, p0, table, ninst,
+                           Ntot, gg, b.off, b.rank, b.cell, (typename V2<R>::T*)b.dd, (typename V2<R>::T*)b.cc);
+    }
+    FH_HIP(hipGetLastError());
+    timing_mark(c, 1);
+    if (Ntot > 0) {
+        const unsigned grid =
+            (unsigned)std::max<int64_t>(1, std::min<int64_t>(b.max_sub, (int64_t)c->cu_count * 8));
+        FH_TRY(launch_spread<R>(c, grid, b.subs, b.nsub, b.cell, b.dd, b.cc, (R*)b.slots, gg, tpi, beta));
+    }
+    timing_mark(c, 2);
+    const int parts = (gg.T * gg.T + 255) / 256;
+    hipLaunchKernelGGL((k_reduce_tiles<R>), dim3(gg.ntx, gg.nty * parts, ninst), dim3(256), 0, c->stream,
+                       (const R*)b.slots, b.tsub, gg, tpi, F);
+    FH_HIP(hipGetLastError());
+    return FH_OK;
+}
+
+fh_status check_lz(double lambda, double z)
+{
+    FH_ARG(std::isfinite(lambda) && std::isfinite(z), FH_ERR_NONFINITE, "lambda or z not finite");
+    FH_ARG(lambda * z > 0 && std::isfinite(lambda * z), FH_ERR_NONPOSITIVE_LZ, "lambda * z must be > 0");
+    return FH_OK;
+}
+
+fh_status check_grid(int n1, int n2, double h1, double h2, double xc, double yc)
+{
+    FH_ARG(n1 > 0 && n2 > 0, FH_ERR_INVALID_ARG, "grid sizes must be positive");
+    FH_ARG(n1 % 2 == 0 && n2 % 2 == 0, FH_ERR_ODD_GRID, "grid sizes must be even (got %d x %d)", n1, n2);
+    FH_ARG(std::isfinite(h1) && std::isfinite(h2) && std::isfinite(xc) && std::isfinite(yc), FH_ERR_NONFINITE,
+           "grid spacing or centre not finite");
+    FH_ARG(h1 > 0 && h2 > 0, FH_ERR_INVALID_ARG, "grid spacing must be positive");
+    FH_ARG(n1 <= 32768 && n2 <= 32768, FH_ERR_UNSUPPORTED, "grid sides up to 32768");
+    return FH_OK;
+}
+
+// Spread method and work-item size: the wavefront-per-point spread is the
+// default (robust to the dense clusters of dilation rules); small work items
+// spread one crowded tile over many CUs.
+void spread_defaults(const fh_ctx* c, GridGeom& g)
+{
+    g.method = c->opt.spread_method > 0 ? c->opt.spread_method : 2;
+    g.P = c->opt.max_subproblem > 0 ? c->opt.max_subproblem : 256;
+}
+
+// Type-1 geometry for an n1 x n2 grid; the row window is set per call.
+T1Plan plan_t1(const fh_ctx* c, int n1, int n2)
+{
+    T1Plan p;
+    p.k = choose_kernel(c, std::max(n1, n2));
+    const int W = p.k.w;
+    const int need1 = std::max((int)std::ceil(p.k.sigma * n1), 2 * W);
+    const int need2 = std::max((int)std::ceil(p.k.sigma * n2), 2 * W);
+    int T = pick_tile(c, std::min(need1, need2));
+    if (c->prec == FH_FP64 && T > 32) T = 32;
+    GridGeom& g = p.gg;
+    g.T = T;
+    g.W = W;
+    g.L = T + W - 1;
+    g.nf1 = next_fft_size(std::max(need1, T + W), T);
+    g.nf2 = next_fft_size(std::max(need2, T + W), T);
+    g.ntx = g.nf1 / T;
+    g.nty = g.nf2 / T;
+    g.rows = g.nf2;
+    g.wrap_y = 1;
+    spread_defaults(c, g);
+    return p;
+}
+
+// Rows of the fine grid an instance's nodes can reach: first row (shift) and
+// count, from the rule's bounding box in y (s2 > 0).
+void window_rows(const double* bb, double s2, int W, int& lo, int& span)
+{
+    lo = (int)std::floor(bb[2] * s2 - 0.5 * W) - 1;
+    const int hi = (int)std::ceil(bb[3] * s2 - 0.5 * W) + W + 1;
+    span = hi - lo;
+}
+
+InstParams inst_t1(const fh_quad* q, double lambda, double z, double h1, double h2, double xc, double yc,
+                   const GridGeom& g)
+{
+    const double lz = lambda * z;
+    InstParams ip{};
+    ip.x = q->x;
+    ip.y = q->y;
+    ip.w = q->w;
+    ip.N = q->N;
+    // source chirp with the pre-phase of a grid centred at (xc, yc):
+    // pi (|x|^2 - 2 (xc x + yc y)) / (lambda z), in turns
+    ip.pa = 0.5 / lz;
+    ip.px = -xc / lz;
+    ip.py = -yc / lz;
+    ip.pc = 0.0;
+    // rescaled node x~ = 2 pi h x/(lambda z), in fine-grid cells of 2 pi/nf
+    ip.s1 = h1 * g.nf1 / lz;
+    ip.s2 = h2 * g.nf2 / lz;
+    return ip;
+}
+
+}  // namespace
+}  // namespace fh

@@ -140,6 +140,16 @@ __global__ void k_petals(PetalParams pp, const double* __restrict__ glm, const d
 
 inline unsigned nblocks(int64_t n, int bs) { return (unsigned)std::max<int64_t>(1, (n + bs - 1) / bs); }
 
+// A box that contains every node (used to size fine grids and row windows).
+void set_bbox(fh_quad* q, double x0, double x1, double y0, double y1)
+{
+    q->bbox[0] = x0;
+    q->bbox[1] = x1;
+    q->bbox[2] = y0;
+    q->bbox[3] = y1;
+    q->bbox_valid = true;
+}
+
 fh_status radial_into(fh_ctx* c, const RadialParams& rp, int64_t n, int m, double* x, double* y,
                       double* w)
 {
@@ -196,6 +206,10 @@ fh_status fh_quad_radial(fh_ctx* c, double r0, const double* a, const double* b,
             fh_quad_destroy(qd);
             return s;
         }
+        // every node is alpha x(t) with 0 < alpha < 1 and |x(t)| <= |r0| + sum |a_k| + |b_k|
+        double rmax = std::fabs(r0);
+        for (int k = 0; k < K; ++k) rmax += std::fabs(rp.a[k]) + std::fabs(rp.b[k]);
+        set_bbox(qd, -rmax, rmax, -rmax, rmax);
         *out = qd;
         return FH_OK;
     } catch (...) {
@@ -242,6 +256,15 @@ fh_status fh_quad_polygon(fh_ctx* c, const double* vx, const double* vy, int32_t
         FH_HIP(hipGetLastError());
         // the host vertex arrays may be released by the caller on return
         FH_HIP(hipStreamSynchronize(c->stream));
+        // nodes lie on segments from the origin to the boundary
+        double bb[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int i = 0; i < nv; ++i) {
+            bb[0] = std::min(bb[0], vx[i]);
+            bb[1] = std::max(bb[1], vx[i]);
+            bb[2] = std::min(bb[2], vy[i]);
+            bb[3] = std::max(bb[3], vy[i]);
+        }
+        set_bbox(qd, bb[0], bb[1], bb[2], bb[3]);
         *out = qd;
         return FH_OK;
     } catch (...) {
@@ -266,9 +289,37 @@ fh_status fh_quad_from_boundary(fh_ctx* c, const double* X, const double* Y, con
         fh_quad* qd = nullptr;
         FH_TRY(quad_alloc(c, n * m, &qd));
         if (n == 0) {
+            set_bbox(qd, 0.0, 0.0, 0.0, 0.0);
             *out = qd;
             return FH_OK;
         }
+        // nodes lie on segments from the origin to the boundary nodes
+        double bb[4] = {0.0, 0.0, 0.0, 0.0};
+        if (mem == FH_MEM_HOST) {
+            for (int64_t i = 0; i < n; ++i) {
+                if (!(std::isfinite(X[i]) && std::isfinite(Y[i]) && std::isfinite(W[i]) && std::isfinite(V[i]))) {
+                    fh_quad_destroy(qd);
+                    set_error("boundary node %lld not finite", (long long)i);
+                    return FH_ERR_NONFINITE;
+                }
+                bb[0] = std::min(bb[0], X[i]);
+                bb[1] = std::max(bb[1], X[i]);
+                bb[2] = std::min(bb[2], Y[i]);
+                bb[3] = std::max(bb[3], Y[i]);
+            }
+        } else {
+            double d[4];
+            fh_status s = device_bbox(c, X, Y, n, d);
+            if (s != FH_OK) {
+                fh_quad_destroy(qd);
+                return s;
+            }
+            bb[0] = std::min(0.0, d[0]);
+            bb[1] = std::max(0.0, d[1]);
+            bb[2] = std::min(0.0, d[2]);
+            bb[3] = std::max(0.0, d[3]);
+        }
+        set_bbox(qd, bb[0], bb[1], bb[2], bb[3]);
         const double *dX = X, *dY = Y, *dW = W, *dV = V;
         if (mem == FH_MEM_HOST) {
             fh_status s = arena_reserve(c, 4 * aligned_bytes(sizeof(double) * n));
@@ -356,6 +407,8 @@ fh_status fh_quad_starshade(fh_ctx* c, int32_t Np, double a, double R, double b,
                            pp, glm, gln, dcoef, qd->x, qd->y, qd->w);
         FH_HIP(hipGetLastError());
         if (coef && coef_mem == FH_MEM_HOST) FH_HIP(hipStreamSynchronize(c->stream));
+        // every node radius is at most R (edge perturbations move angles only)
+        set_bbox(qd, -R, R, -R, R);
         *out = qd;
         return FH_OK;
     } catch (...) {
@@ -382,6 +435,15 @@ fh_status fh_quad_from_nodes(fh_ctx* c, const double* x, const double* y, const 
             FH_HIP(hipMemcpyAsync(qd->y, y, sizeof(double) * N, kind, c->stream));
             FH_HIP(hipMemcpyAsync(qd->w, w, sizeof(double) * N, kind, c->stream));
             if (mem == FH_MEM_HOST) FH_HIP(hipStreamSynchronize(c->stream));
+            double bb[4];
+            fh_status s = device_bbox(c, qd->x, qd->y, N, bb);
+            if (s != FH_OK) {
+                fh_quad_destroy(qd);
+                return s;
+            }
+            set_bbox(qd, bb[0], bb[1], bb[2], bb[3]);
+        } else {
+            set_bbox(qd, 0.0, 0.0, 0.0, 0.0);
         }
         *out = qd;
         return FH_OK;
