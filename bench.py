@@ -10,13 +10,15 @@ coordinates are resident on the device before the timed region starts.
 
 value = targets per second of the FP64 path (tolerance 1e-9, relative L2
 against the exact quadrature sum); the mixed-precision path (tolerance 1e-5)
-is timed in the same run and reported beside it.
+is timed in the same run and reported beside it.  The roofline entry is for
+the kernel with the largest device time per step, timed live with HIP events
+on the library's stream over the timed region.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
-import math
 import os
 import sys
 import time
@@ -26,6 +28,11 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# LDS: 256 CUs x 128 bytes per clock x 2.4 GHz ("Rooflines")
+LDS_PEAK_GBS = 256 * 128 * 2.4
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_starfish_F20.json")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2010_05978_amd", "csrc", f)
+                  for f in ("fh_kernels.hpp", "fh_field.hip")]
 
 
 def parse():
@@ -36,7 +43,17 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle sample")
     ap.add_argument("--only", choices=["fp64", "mixed"], default=None, help="time one precision only")
+    ap.add_argument("--pmc-calib", action="store_true",
+                    help="also run a plain 256 MiB device copy (counter calibration for rocprofv3 --pmc)")
     return ap.parse_args()
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 class Step:
@@ -83,6 +100,44 @@ def time_steps(step, steps, warmup):
     return dt, [v / max(ngrid, 1) for v in grid_ms], [v / max(npts, 1) for v in pts_ms]
 
 
+def roofline(res, prec, wl):
+    """Roofline of the kernel with the most device time per step.
+
+    Candidates are the stages that bracket one kernel: the spread of each
+    call, the type-1 epilogue and the type-3 interpolation."""
+    r = res[prec]
+    p = r["params"]
+    W = p["width"]
+    rs = 8 if prec == "fp64" else 4
+    N = wl.shape.n_nodes
+    n1, n2 = wl.grid.n1, wl.grid.n2
+    M3 = len(wl.points[0])
+    g, pt = r["grid_stage_ms"], r["points_stage_ms"]
+    cands = {
+        # spread: 2 W^2 LDS atomic adds of one real each per node
+        "spread": {"kernel": f"k_spread_wave<{'double' if rs == 8 else 'float'}, {W}>", "ms": (g[1] + pt[1]) / 2,
+                   "launches": 2, "bound": "alu", "unit": "GB/s", "peak": LDS_PEAK_GBS,
+                   "bytes": N * W * W * 2 * rs},
+        # epilogue: read one complex fine-grid value and write one output per target
+        "epilogue": {"kernel": f"k_epilogue_t1<{'double' if rs == 8 else 'float'}>", "ms": g[3], "launches": 1,
+                     "bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK_GBS, "bytes": n1 * n2 * 4 * rs},
+        # interpolation: target coordinates and index in, one output out
+        "interp": {"kernel": f"k_t3_interp<{'double' if rs == 8 else 'float'}, {W}>", "ms": pt[3], "launches": 1,
+                   "bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK_GBS, "bytes": M3 * (16 + 4 + 2 * rs)},
+    }
+    name, c = max(cands.items(), key=lambda kv: kv[1]["ms"] * kv[1]["launches"])
+    achieved = c["bytes"] / (c["ms"] * 1e-3) / 1e9
+    out = {"bound": c["bound"], "achieved": achieved, "peak": c["peak"], "unit": c["unit"],
+           "frac": achieved / c["peak"], "traffic": None, "kernel": c["kernel"],
+           "avg_launch_ms": c["ms"], "algorithmic_bytes_per_launch": c["bytes"],
+           "per_step_ms": {k: v["ms"] * v["launches"] for k, v in cands.items()}}
+    if os.path.exists(TRAFFIC_FILE):
+        t = json.load(open(TRAFFIC_FILE))
+        if t.get("kernel") == c["kernel"] and t.get("source_hash") == kernel_source_hash():
+            out["traffic"] = t.get("bytes_per_launch")
+    return out
+
+
 def cpu_baseline(wl, seconds):
     """The oracle (direct FP64 sum) on a seeded sample of the step's targets."""
     import numpy as np
@@ -93,10 +148,10 @@ def cpu_baseline(wl, seconds):
     xi = np.concatenate([xi_g, wl.points[0]])
     eta = np.concatenate([eta_g, wl.points[1]])
     rng = np.random.Generator(np.random.PCG64(4242))
-    probe = rng.choice(len(xi), 512, replace=False)
+    probe = rng.choice(len(xi), 1024, replace=False)
     t0 = time.perf_counter()
     oracle.fresnel_direct(x, y, w, wl.lam, wl.z, xi[probe], eta[probe])
-    per = (time.perf_counter() - t0) / 512
+    per = (time.perf_counter() - t0) / 1024
     n = int(min(len(xi), max(1024, seconds / max(per, 1e-9))))
     idx = rng.choice(len(xi), n, replace=False)
     t0 = time.perf_counter()
@@ -128,6 +183,12 @@ def main():
                   "grid_stage_ms": gstage, "points_stage_ms": pstage,
                   "params": st.ctx.query_params(wl.grid.n1)}
         st.ctx.close()
+    if args.pmc_calib:
+        a = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
     main_p = precs[0]
     r = res[main_p]
     out = {
@@ -136,13 +197,14 @@ def main():
         "ms_per_step": r["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64" if main_p == "fp64" else "c64-f64phase", "data": "synthetic",
         "config": {"workload": "starfish r=1+0.3cos5t, Fresnel number 20, 40000 nodes; 1000x1000 grid "
-                               "(type 1) + 1e5 random targets (type 3)",
+                               "(type 1) + 1e5 random targets (type 3); quadrature generated each step",
                    "tolerance": 1e-9 if main_p == "fp64" else 1e-5, "targets_per_step": 1_100_000},
+        "roofline": roofline(res, main_p, wl),
         "stages_ms": {p: {"grid": res[p]["grid_stage_ms"], "points": res[p]["points_stage_ms"]} for p in precs},
     }
     if "mixed" in res and main_p != "mixed":
         out["mixed"] = {"value": res["mixed"]["value"], "ms_per_step": res["mixed"]["ms_per_step"],
-                        "dtype": "c64-f64phase", "tolerance": 1e-5}
+                        "dtype": "c64-f64phase", "tolerance": 1e-5, "roofline": roofline(res, "mixed", wl)}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
     print(json.dumps(out))

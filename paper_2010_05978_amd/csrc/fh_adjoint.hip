@@ -1,17 +1,446 @@
-// fh_adjoint.hip -- vector-Jacobian products (filled in below).
-#include "fh_common.hpp"
+// fh_adjoint.hip -- vector-Jacobian products of the grid field.
+//
+// For a real loss L with cotangent g_k = dL/dRe(u_k) + i dL/dIm(u_k) at the
+// grid targets xi_k, and a_k = s conj(g_k) (s = -1 for an occulter, since
+// u_oc = 1 - u_ap), the derivatives of the quadrature sum of eq. faq are
+//   dL/dw_j = Re[G_j/(i lambda z)],
+//   dL/dx_j = (2 pi w_j/(lambda z)^2) Re[x_j G_j - Hx_j],  y likewise,
+// with G_j = sum_k a_k E_kj, Hx_j = sum_k a_k E_kj xi_k, Hy_j likewise, and
+// E_kj = exp(i pi |xi_k - x_j|^2/(lambda z)).  Expanding the square as in eq.
+// split, with xi_k = (xc, yc) + (h1 k1, h2 k2):
+//   G_j = P_j sum_k b_k exp(-i (k1 x~_j + k2 y~_j)),  b_k = a_k exp(i pi |xi_k|^2/(lambda z)),
+// P_j = exp(i pi (|x_j|^2 - 2 (xc x_j + yc y_j))/(lambda z)) (the forward
+// strength phase), and x~ = 2 pi h1 x/(lambda z) as in the type-1 transform.
+// So G, Hx, Hy are three type-2 NUFFTs with coefficients b, xi b, eta b that
+// share one set of kernel weights at each node: deconvolve, a first FFT pass
+// over the n1 needed columns, a transpose that keeps only the fine-grid rows
+// the nodes can reach, a second pass over those rows, and an ES-kernel gather
+// at the nodes.  The starshade product then chains (dL/dx, dL/dy, dL/dw)
+// through the perturbed petal construction to the edge coefficients.
+#include "fh_kernels.hpp"
+
+namespace fh {
+namespace {
+
+struct AdjParams {
+    int n1, n2, nf1, nf2, rows, sh2;
+    double h1, h2, xc, yc;
+    double inv2lz;
+    double sign;  // +1 aperture, -1 occulter
+    const double* iphi1;
+    const double* iphi2;
+};
+
+// Zt[ch][c][r] (c = k1 + n1/2, r = k2 mod nf2, zero where |k2| is beyond the
+// grid) from the cotangent g[k2 + n2/2][k1 + n1/2]: channels b, xi b, eta b,
+// deconvolved by the kernel transform.
+template <class R>
+__global__ void __launch_bounds__(256) k_adj_prep(const R* __restrict__ gu, R* __restrict__ Zt, AdjParams ap)
+{
+    using C2 = typename V2<R>::T;
+    __shared__ C2 t[32][33];
+    const int c0 = blockIdx.x * 32, r0 = blockIdx.y * 32;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    const C2* g = reinterpret_cast<const C2*>(gu);
+    for (int k = ty; k < 32; k += 8) {
+        const int r = r0 + k, k1i = c0 + tx;
+        const int k2 = r < ap.nf2 / 2 ? r : r - ap.nf2;
+        C2 v;
+        v.x = R(0);
+        v.y = R(0);
+        if (r < ap.nf2 && k1i < ap.n1 && k2 >= -(ap.n2 / 2) && k2 < ap.n2 - ap.n2 / 2)
+            v = g[(size_t)(k2 + ap.n2 / 2) * ap.n1 + k1i];
+        t[k][tx] = v;
+    }
+    __syncthreads();
+    C2* Z = reinterpret_cast<C2*>(Zt);
+    const size_t plane = (size_t)ap.n1 * ap.nf2;
+    for (int k = ty; k < 32; k += 8) {
+        const int k1i = c0 + k, r = r0 + tx;
+        if (k1i >= ap.n1 || r >= ap.nf2) continue;
+        const int k2 = r < ap.nf2 / 2 ? r : r - ap.nf2;
+        C2 b0, b1, b2;
+        b0.x = b0.y = b1.x = b1.y = b2.x = b2.y = R(0);
+        if (k2 >= -(ap.n2 / 2) && k2 < ap.n2 - ap.n2 / 2) {
+            const C2 gv = t[tx][k];
+            const int k1 = k1i - ap.n1 / 2;
+            const double xi = ap.xc + ap.h1 * k1, eta = ap.yc + ap.h2 * k2;
+            // a = s conj(g); b = a exp(i pi |xi|^2/lz) / (Phi(k1) Phi(k2))
+            const double ar = ap.sign * (double)gv.x, ai = -ap.sign * (double)gv.y;
+            const double tt = (xi * xi + eta * eta) * ap.inv2lz;
+            const double f = tt - rint(tt);
+            double s, c;
+            sincospi(2.0 * f, &s, &c);
+            const double sc = ap.iphi1[k1i] * ap.iphi2[k2 + ap.n2 / 2];
+            const double br = (ar * c - ai * s) * sc, bi = (ar * s + ai * c) * sc;
+            b0.x = (R)br;
+            b0.y = (R)bi;
+            b1.x = (R)(xi * br);
+            b1.y = (R)(xi * bi);
+            b2.x = (R)(eta * br);
+            b2.y = (R)(eta * bi);
+        }
+        const size_t o = (size_t)k1i * ap.nf2 + r;
+        Z[o] = b0;
+        Z[plane + o] = b1;
+        Z[2 * plane + o] = b2;
+    }
+}
+
+// F1[ch][row][col] = Zt[ch][k1 + n1/2][(sh2 + row) mod nf2] for the fine-grid
+// columns col = k1 mod nf1 of the grid's modes, zero for the other columns.
+template <class R>
+__global__ void __launch_bounds__(256) k_adj_transpose(const R* __restrict__ Zt, R* __restrict__ F1, AdjParams ap)
+{
+    using C2 = typename V2<R>::T;
+    __shared__ C2 t[32][33];
+    const int col0 = blockIdx.x * 32, row0 = blockIdx.y * 32, ch = blockIdx.z;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    const C2* Z = reinterpret_cast<const C2*>(Zt) + (size_t)ch * ap.n1 * ap.nf2;
+    for (int k = ty; k < 32; k += 8) {
+        const int col = col0 + k, row = row0 + tx;
+        const int k1 = col < ap.nf1 / 2 ? col : col - ap.nf1;
+        C2 v;
+        v.x = R(0);
+        v.y = R(0);
+        if (col < ap.nf1 && row < ap.rows && k1 >= -(ap.n1 / 2) && k1 < ap.n1 - ap.n1 / 2) {
+            int r = (ap.sh2 + row) % ap.nf2;
+            if (r < 0) r += ap.nf2;
+            v = Z[(size_t)(k1 + ap.n1 / 2) * ap.nf2 + r];
+        }
+        t[k][tx] = v;
+    }
+    __syncthreads();
+    C2* F = reinterpret_cast<C2*>(F1) + (size_t)ch * ap.rows * ap.nf1;
+    for (int k = ty; k < 32; k += 8) {
+        const int row = row0 + k, col = col0 + tx;
+        if (row < ap.rows && col < ap.nf1) F[(size_t)row * ap.nf1 + col] = t[tx][k];
+    }
+}
+
+// Gather the three channels at each node with the ES kernel, then form the
+// node gradients.
+template <class R, int W>
+__global__ void __launch_bounds__(256) k_adj_gather(const R* __restrict__ F1, InstParams ip, GridGeom gg, R beta,
+                                                    double lz, double* __restrict__ gx, double* __restrict__ gy,
+                                                    double* __restrict__ gw)
+{
+    using C2 = typename V2<R>::T;
+    const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (j >= ip.N) return;
+    const double x = ip.x[j], y = ip.y[j], w = ip.w[j];
+    int l1, l2;
+    double d1, d2;
+    if (!node_cell(ip, gg, x, y, l1, l2, d1, d2)) {
+        gx[j] = 0.0;
+        gy[j] = 0.0;
+        gw[j] = 0.0;
+        return;
+    }
+    R k1[W];
+    es_weights<R, W>((R)d1, beta, k1);
+    const R s2 = R(2) / R(W);
+    const size_t plane = (size_t)gg.rows * gg.nf1;
+    const C2* F = reinterpret_cast<const C2*>(F1);
+    R t0r = 0, t0i = 0, t1r = 0, t1i = 0, t2r = 0, t2i = 0;
+#pragma unroll 1
+    for (int b = 0; b < W; ++b) {
+        int row = l2 + b;
+        if (row >= gg.rows) row -= gg.rows;  // periodic only when the rows are the whole period
+        const C2* fr = F + (size_t)row * gg.nf1;
+        R a0r = 0, a0i = 0, a1r = 0, a1i = 0, a2r = 0, a2i = 0;
+#pragma unroll
+        for (int a = 0; a < W; ++a) {
+            int col = l1 + a;
+            if (col >= gg.nf1) col -= gg.nf1;
+            const C2 v0 = fr[col], v1 = fr[plane + col], v2 = fr[2 * plane + col];
+            a0r += v0.x * k1[a];
+            a0i += v0.y * k1[a];
+            a1r += v1.x * k1[a];
+            a1i += v1.y * k1[a];
+            a2r += v2.x * k1[a];
+            a2i += v2.y * k1[a];
+        }
+        const R z = ((R)d2 + R(b)) * s2;
+        R kb;
+        if constexpr (sizeof(R) == 4)
+            kb = __expf(beta * (__fsqrt_rn(fmaxf(R(1) - z * z, 0.0f)) - 1.0f));
+        else
+            kb = exp(beta * (sqrt(fmax(R(1) - z * z, 0.0)) - 1.0));
+        t0r += a0r * kb;
+        t0i += a0i * kb;
+        t1r += a1r * kb;
+        t1i += a1i * kb;
+        t2r += a2r * kb;
+        t2i += a2i * kb;
+    }
+    // P_j = exp(2 pi i t), t = the forward strength phase in turns
+    const double t = ((x * x + y * y) * ip.pa + (x * ip.px + y * ip.py)) + ip.pc;
+    const double f = t - rint(t);
+    double s, c;
+    sincospi(2.0 * f, &s, &c);
+    const double Gr = c * t0r - s * t0i, Gi = s * t0r + c * t0i;
+    const double Hxr = c * t1r - s * t1i;
+    const double Hyr = c * t2r - s * t2i;
+    gw[j] = Gi / lz;
+    const double fac = 2.0 * kPi * w / (lz * lz);
+    gx[j] = fac * (x * Gr - Hxr);
+    gy[j] = fac * (y * Gr - Hyr);
+}
+
+template <class R>
+fh_status launch_gather(fh_ctx* c, int W, const R* F1, const InstParams& ip, const GridGeom& gg, double beta,
+                        double lz, double* gx, double* gy, double* gw)
+{
+    const unsigned g = nblocks(ip.N, 256);
+    switch (W) {
+#define FH_GATHER_CASE(w)                                                                                        \
+    case w:                                                                                                     \
+        hipLaunchKernelGGL((k_adj_gather<R, w>), dim3(g), dim3(256), 0, c->stream, F1, ip, gg, (R)beta, lz, gx, \
+                           gy, gw);                                                                             \
+        break;
+        FH_GATHER_CASE(2) FH_GATHER_CASE(3) FH_GATHER_CASE(4) FH_GATHER_CASE(5) FH_GATHER_CASE(6)
+        FH_GATHER_CASE(7) FH_GATHER_CASE(8) FH_GATHER_CASE(9) FH_GATHER_CASE(10) FH_GATHER_CASE(11)
+        FH_GATHER_CASE(12) FH_GATHER_CASE(13) FH_GATHER_CASE(14) FH_GATHER_CASE(15) FH_GATHER_CASE(16)
+        FH_GATHER_CASE(17) FH_GATHER_CASE(18) FH_GATHER_CASE(19) FH_GATHER_CASE(20)
+#undef FH_GATHER_CASE
+    default: set_error("kernel width %d unsupported", W); return FH_ERR_UNSUPPORTED;
+    }
+    FH_HIP(hipGetLastError());
+    return FH_OK;
+}
+
+__global__ void k_zero_doubles(double* __restrict__ p, int64_t n)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0.0;
+}
+
+template <class R>
+fh_status grid_vjp_impl(fh_ctx* c, const fh_quad* q, double lambda, double z, int n1, int n2, double h1, double h2,
+                        double xc, double yc, int occ, const void* g_u, double* g_x, double* g_y, double* g_w)
+{
+    const size_t rs = sizeof(R);
+    const double lz = lambda * z;
+    const int64_t N = q->N;
+    c->timing_kind = 2;
+    if (N == 0) return FH_OK;
+    T1Plan pl = plan_t1(c, n1, n2);
+    GridGeom gg = pl.gg;
+    InstParams ip = inst_t1(q, lambda, z, h1, h2, xc, yc, gg);
+    double bb[4];
+    FH_TRY(quad_bbox(c, q, bb));
+    int lo, span;
+    window_rows(bb, ip.s2, gg.W, lo, span);
+    const int rows = (span + gg.T - 1) / gg.T * gg.T;
+    if (rows + gg.T < gg.nf2 && span > 0) {
+        gg.rows = rows;
+        gg.wrap_y = 0;
+        ip.sh2 = lo;
+    } else {
+        gg.rows = gg.nf2;
+        gg.wrap_y = 1;
+        ip.sh2 = 0;
+    }
+    gg.nty = gg.rows / gg.T;
+    const double* ip1 = nullptr;
+    const double* ip2 = nullptr;
+    FH_TRY(iphi_table(c, pl.k, n1, gg.nf1, &ip1));
+    FH_TRY(iphi_table(c, pl.k, n2, gg.nf2, &ip2));
+    FftPlan* fa = nullptr;
+    FftPlan* fb = nullptr;
+    FH_TRY(fft_plan(c, gg.nf2, 0, 3 * n1, &fa));
+    FH_TRY(fft_plan(c, gg.nf1, 0, 3 * gg.rows, &fb));
+    const size_t Z_count = 2 * (size_t)3 * n1 * gg.nf2;
+    const size_t F_count = 2 * (size_t)3 * gg.rows * gg.nf1;
+    FH_TRY(arena_reserve(c, aligned_bytes(rs * Z_count) + aligned_bytes(rs * F_count)));
+    R* Zt = c->arena.take<R>(Z_count);
+    R* F1 = c->arena.take<R>(F_count);
+
+    AdjParams ap{n1, n2, gg.nf1, gg.nf2, gg.rows, ip.sh2, h1, h2, xc, yc, 0.5 / lz, occ ? -1.0 : 1.0, ip1, ip2};
+    timing_mark(c, 0);
+    hipLaunchKernelGGL((k_adj_prep<R>), dim3(nblocks(n1, 32), nblocks(gg.nf2, 32)), dim3(256), 0, c->stream,
+                       static_cast<const R*>(g_u), Zt, ap);
+    FH_HIP(hipGetLastError());
+    timing_mark(c, 1);
+    timing_mark(c, 2);
+    FH_TRY(fft_exec(c, fa, Zt));
+    hipLaunchKernelGGL((k_adj_transpose<R>), dim3(nblocks(gg.nf1, 32), nblocks(gg.rows, 32), 3), dim3(256), 0,
+                       c->stream, Zt, F1, ap);
+    FH_HIP(hipGetLastError());
+    FH_TRY(fft_exec(c, fb, F1));
+    timing_mark(c, 3);
+    FH_TRY(launch_gather<R>(c, gg.W, F1, ip, gg, pl.k.beta, lz, g_x, g_y, g_w));
+    timing_mark(c, 4);
+    timing_mark(c, 5);
+    return FH_OK;
+}
+
+// ---------------------------------------------------- starshade chain rule
+struct SsParams {
+    int Np, m, np, K;
+    double a, R, b, p;
+    int64_t off;   // first petal node
+    int chunk;     // petal nodes per block
+    int nchunks;
+};
+
+constexpr int kCoefGroup = 16;
+
+// Partial sums of dL/dc+-_{k,s} over one chunk of petal k's nodes, for the
+// coefficient group s in [s0, s0 + kCoefGroup).  With s_s(r) = sin(s pi
+// (r-a)/(R-a)): dphi/dc+_s = s_s (1 + tau)/(2r), dphi/dc-_s = s_s (tau - 1)/(2r),
+// dw/dc+-_s = w_r w_t s_s / 2, d(x, y)/dphi = (-y, x).
+__global__ void __launch_bounds__(128) k_ss_vjp_partial(SsParams sp, int s0, const double* __restrict__ glm,
+                                                        const double* __restrict__ gln,
+                                                        const double* __restrict__ coef,
+                                                        const double* __restrict__ gx, const double* __restrict__ gy,
+                                                        const double* __restrict__ gw, double* __restrict__ part)
+{
+    const int k = blockIdx.y, ch = blockIdx.x;
+    const int per = sp.np * sp.m;
+    const int t0 = ch * sp.chunk, t1 = min(per, t0 + sp.chunk);
+    const int ns = min(kCoefGroup, sp.K - s0);
+    double accp[kCoefGroup], accm[kCoefGroup];
+#pragma unroll
+    for (int s = 0; s < kCoefGroup; ++s) accp[s] = accm[s] = 0.0;
+    const double L = sp.R - sp.a;
+    const double* cp = coef + 2 * (int64_t)k * sp.K;
+    for (int t = t0 + (int)threadIdx.x; t < t1; t += blockDim.x) {
+        const int i = t / sp.m, l = t - i * sp.m;
+        const double r = sp.a + 0.5 * L * (1.0 + glm[l]);
+        const double wr = 0.5 * L * glm[sp.m + l];
+        const double tau = gln[i], wt = gln[sp.np + i];
+        const double A = exp(-pow((r - sp.a) / sp.b, sp.p));
+        double dp = 0.0, dm = 0.0;
+        for (int s = 1; s <= sp.K; ++s) {
+            const double sk = sin(s * kPi * (r - sp.a) / L);
+            dp += cp[s - 1] * sk;
+            dm += cp[sp.K + s - 1] * sk;
+        }
+        const double mid = (dp - dm) / (2.0 * r);
+        const double half = kPi * A / sp.Np + (dp + dm) / (2.0 * r);
+        const double phi = 2.0 * kPi * k / sp.Np + mid + half * tau;
+        double sn, cs;
+        sincos(phi, &sn, &cs);
+        const double x = r * cs, y = r * sn;
+        const int64_t j = sp.off + (int64_t)k * per + t;
+        const double dphi = gx[j] * (-y) + gy[j] * x;
+        const double dwc = gw[j] * wr * wt * 0.5;
+        const double up = dphi * (1.0 + tau) / (2.0 * r), um = dphi * (tau - 1.0) / (2.0 * r);
+#pragma unroll
+        for (int s = 0; s < kCoefGroup; ++s) {
+            if (s < ns) {
+                const double sk = sin((s0 + s + 1) * kPi * (r - sp.a) / L);
+                accp[s] += up * sk + dwc * sk;
+                accm[s] += um * sk + dwc * sk;
+            }
+        }
+    }
+    // block reduction of the 2 kCoefGroup sums (fixed order)
+    __shared__ double red[2 * kCoefGroup][128];
+#pragma unroll
+    for (int s = 0; s < kCoefGroup; ++s) {
+        red[s][threadIdx.x] = accp[s];
+        red[kCoefGroup + s][threadIdx.x] = accm[s];
+    }
+    __syncthreads();
+    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o)
+            for (int q = 0; q < 2 * kCoefGroup; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + o];
+        __syncthreads();
+    }
+    if ((int)threadIdx.x < 2 * ns) {
+        const int q = threadIdx.x;
+        const int s = q < ns ? q : q - ns;
+        const int sign = q < ns ? 0 : 1;  // 0: c+, 1: c-
+        const double v = red[sign ? kCoefGroup + s : s][0];
+        part[((int64_t)k * sp.nchunks + ch) * 2 * sp.K + sign * sp.K + s0 + s] = v;
+    }
+}
+
+// g_coef[2 k K + j] = sum over chunks (fixed order).
+__global__ void k_ss_vjp_final(SsParams sp, const double* __restrict__ part, double* __restrict__ gcoef)
+{
+    const int o = blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= sp.Np * 2 * sp.K) return;
+    const int k = o / (2 * sp.K), jj = o - k * 2 * sp.K;
+    double acc = 0.0;
+    for (int ch = 0; ch < sp.nchunks; ++ch) acc += part[((int64_t)k * sp.nchunks + ch) * 2 * sp.K + jj];
+    gcoef[o] = acc;
+}
+
+}  // namespace
+}  // namespace fh
+
 using namespace fh;
+
 extern "C" {
-fh_status fh_field_grid_vjp(fh_ctx*, const fh_quad*, double, double, int32_t, int32_t, double, double, double,
-                            double, int32_t, const void*, double*, double*, double*)
+
+fh_status fh_field_grid_vjp(fh_ctx* c, const fh_quad* q, double lambda, double z, int32_t n1, int32_t n2, double h1,
+                            double h2, double xc, double yc, int32_t occulter, const void* g_u, double* g_x,
+                            double* g_y, double* g_w)
 {
-    set_error("not implemented yet");
-    return FH_ERR_UNSUPPORTED;
+    try {
+        FH_ARG(c && q, FH_ERR_INVALID_ARG, "NULL argument");
+        FH_ARG(q->ctx == c, FH_ERR_INVALID_ARG, "quadrature belongs to another context");
+        FH_ARG(q->N == 0 || (g_u && g_x && g_y && g_w), FH_ERR_INVALID_ARG, "NULL array");
+        FH_TRY(check_lz(lambda, z));
+        FH_TRY(check_grid(n1, n2, h1, h2, xc, yc));
+        FH_ARG(q->N < ((int64_t)1 << 31), FH_ERR_UNSUPPORTED, "at most 2^31 - 1 nodes per call");
+        FH_HIP(hipSetDevice(c->device));
+        if (c->prec == FH_FP64)
+            return grid_vjp_impl<double>(c, q, lambda, z, n1, n2, h1, h2, xc, yc, occulter, g_u, g_x, g_y, g_w);
+        return grid_vjp_impl<float>(c, q, lambda, z, n1, n2, h1, h2, xc, yc, occulter, g_u, g_x, g_y, g_w);
+    } catch (...) {
+        set_error("host allocation failed");
+        return FH_ERR_ALLOC;
+    }
 }
-fh_status fh_starshade_vjp(fh_ctx*, int32_t, double, double, double, double, int32_t, int32_t, int32_t, int32_t,
-                           const double*, int32_t, const double*, const double*, const double*, double*)
+
+fh_status fh_starshade_vjp(fh_ctx* c, int32_t Np, double a, double R, double b, double p, int32_t m, int32_t np,
+                           int32_t nd, int32_t md, const double* coef, int32_t K, const double* g_x,
+                           const double* g_y, const double* g_w, double* g_coef)
 {
-    set_error("not implemented yet");
-    return FH_ERR_UNSUPPORTED;
+    try {
+        FH_ARG(c && coef && g_x && g_y && g_w && g_coef, FH_ERR_INVALID_ARG, "NULL argument");
+        FH_ARG(Np >= 1 && m >= 1 && np >= 1 && nd >= 0 && md >= 1, FH_ERR_INVALID_ARG,
+               "need Np, m, np, md >= 1 and nd >= 0");
+        FH_ARG(K >= 1 && K <= kMaxFourier, FH_ERR_INVALID_ARG, "K must be in [1, %d]", kMaxFourier);
+        FH_ARG(std::isfinite(a) && std::isfinite(R) && std::isfinite(b) && std::isfinite(p), FH_ERR_NONFINITE,
+               "starshade scalar not finite");
+        FH_ARG(a >= 0 && R > a && b > 0 && p > 0, FH_ERR_INVALID_ARG, "need 0 <= a < R, b > 0, p > 0");
+        FH_HIP(hipSetDevice(c->device));
+        const double* glm = nullptr;
+        const double* gln = nullptr;
+        FH_TRY(gl_table(c, m, &glm));
+        FH_TRY(gl_table(c, np, &gln));
+        SsParams sp;
+        sp.Np = Np;
+        sp.m = m;
+        sp.np = np;
+        sp.K = K;
+        sp.a = a;
+        sp.R = R;
+        sp.b = b;
+        sp.p = p;
+        sp.off = (int64_t)nd * md;
+        sp.chunk = 1024;
+        sp.nchunks = (np * m + sp.chunk - 1) / sp.chunk;
+        const size_t npart = (size_t)Np * sp.nchunks * 2 * K;
+        FH_TRY(arena_reserve(c, aligned_bytes(sizeof(double) * npart)));
+        double* part = c->arena.take<double>(npart);
+        for (int s0 = 0; s0 < K; s0 += kCoefGroup)
+            hipLaunchKernelGGL(k_ss_vjp_partial, dim3(sp.nchunks, Np), dim3(128), 0, c->stream, sp, s0, glm, gln,
+                               coef, g_x, g_y, g_w, part);
+        hipLaunchKernelGGL(k_ss_vjp_final, dim3(nblocks((int64_t)Np * 2 * K, 256)), dim3(256), 0, c->stream, sp, part,
+                           g_coef);
+        FH_HIP(hipGetLastError());
+        return FH_OK;
+    } catch (...) {
+        set_error("host allocation failed");
+        return FH_ERR_ALLOC;
+    }
 }
-}
+
+}  // extern "C"

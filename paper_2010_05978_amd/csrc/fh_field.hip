@@ -354,7 +354,7 @@ fh_status field_points_impl(fh_ctx* c, const fh_quad* q, double lambda, double z
     FH_HIP(hipGetLastError());
     FH_TRY(fft_exec(c, fp, up));
     timing_mark(c, 3);
-    FH_TRY(launch_interp<R>(c, k.w, up, dxi, deta, M, k.beta, tp, dout));
+    FH_TRY(launch_interp<R>(c, k.w, up, dxi, deta, M, k.beta, tp, nullptr, dout));
     timing_mark(c, 4);
     timing_mark(c, 5);
     if (mem == FH_MEM_HOST) {

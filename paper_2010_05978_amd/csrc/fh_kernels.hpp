@@ -398,17 +398,36 @@ __global__ void __launch_bounds__(256) k_spread_wave(const Sub* __restrict__ sub
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             const int np = min(64, sb.end - base);
-            for (int q = 0; q < np; ++q) {
-                const int ql1 = lane_val(l1, q), ql2 = lane_val(l2, q);
-                const R qr = lane_val(cr, q), qi = lane_val(ci, q);
-                const R* kq = kb + q * KS;
+            // four points per trip: their staging reads are issued together
+            // so one LDS round trip is paid per four points, not per point
+            constexpr int U = 4;
+            for (int q0 = 0; q0 < np; q0 += U) {
+                R kv[U][NPASS], vr[U], vi[U];
+                int idx[U][NPASS];
+                bool qv[U];
 #pragma unroll
-                for (int pp = 0; pp < NPASS; ++pp) {
-                    if (pv[pp]) {
-                        const R kv = kq[pa[pp]] * kq[W + pb[pp]];
-                        const int idx = (ql2 + pb[pp]) * L + ql1 + pa[pp];
-                        atomicAdd(sre + idx, qr * kv);
-                        atomicAdd(sim + idx, qi * kv);
+                for (int u = 0; u < U; ++u) {
+                    qv[u] = q0 + u < np;
+                    const int q = qv[u] ? q0 + u : q0;
+                    const int ql1 = lane_val(l1, q), ql2 = lane_val(l2, q);
+                    vr[u] = lane_val(cr, q);
+                    vi[u] = lane_val(ci, q);
+                    const R* kq = kb + q * KS;
+#pragma unroll
+                    for (int pp = 0; pp < NPASS; ++pp) {
+                        kv[u][pp] = kq[pa[pp]] * kq[W + pb[pp]];
+                        idx[u][pp] = (ql2 + pb[pp]) * L + ql1 + pa[pp];
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    if (!qv[u]) continue;
+#pragma unroll
+                    for (int pp = 0; pp < NPASS; ++pp) {
+                        if (pv[pp]) {
+                            atomicAdd(sre + idx[u][pp], vr[u] * kv[u][pp]);
+                            atomicAdd(sim + idx[u][pp], vi[u] * kv[u][pp]);
+                        }
                     }
                 }
             }
@@ -454,10 +473,23 @@ __global__ void __launch_bounds__(256) k_reduce_tiles(const R* __restrict__ slot
             const int t = b * tpi + sty * gg.ntx + stx;
             const int first = tsub[2 * t], cnt = tsub[2 * t + 1];
             const R* sp = slots + (size_t)first * 2 * LL + ly * L + lx;
-            for (int k = 0; k < cnt; ++k) {
-                ar += sp[0];
-                ai += sp[LL];
-                sp += 2 * LL;
+            const size_t st = 2 * (size_t)LL;
+            // four independent (guarded) loads in flight per trip; the sum
+            // order is fixed, so the result does not depend on scheduling
+            for (int k = 0; k < cnt; k += 4) {
+                R r[4], m[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const bool ok = k + u < cnt;
+                    r[u] = ok ? sp[u * st] : R(0);
+                    m[u] = ok ? sp[u * st + LL] : R(0);
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    ar += r[u];
+                    ai += m[u];
+                }
+                sp += 4 * st;
             }
         }
     }
@@ -607,22 +639,25 @@ struct T3Params {
 template <class R, int W>
 __global__ void __launch_bounds__(256) k_t3_interp(const R* __restrict__ G, const double* __restrict__ xi,
                                                    const double* __restrict__ eta, int64_t M, R beta,
-                                                   T3Params tp, R* __restrict__ u)
+                                                   T3Params tp, const int* __restrict__ perm, R* __restrict__ u)
 {
-    const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (k >= M) return;
+    const int64_t ks = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (ks >= M) return;
+    const int64_t k = perm ? (int64_t)perm[ks] : ks;
     const double X = xi[k], Y = eta[k];
     int l1, l2;
     double d1, d2;
     bool ok1, ok2;
     cell_of((X - tp.xic) * tp.g1, tp.m1, W, l1, d1, ok1);
     cell_of((Y - tp.etac) * tp.g2, tp.m2, W, l2, d2, ok2);
-    R k1[W], k2[W];
+    R k1[W];
     es_weights<R, W>((R)d1, beta, k1);
-    es_weights<R, W>((R)d2, beta, k2);
     const typename V2<R>::T* Gv = reinterpret_cast<const typename V2<R>::T*>(G);
+    // one stencil row per trip: W gathers in flight, the row weight computed
+    // in the loop (a fully unrolled W x W gather spills at W = 11)
+    const R s2 = R(2) / R(W);
     R sr = 0, si = 0;
-#pragma unroll
+#pragma unroll 1
     for (int b = 0; b < W; ++b) {
         int row = l2 + b;
         if (row >= tp.m2) row -= tp.m2;
@@ -636,8 +671,14 @@ __global__ void __launch_bounds__(256) k_t3_interp(const R* __restrict__ G, cons
             ar += gv.x * k1[a];
             ai += gv.y * k1[a];
         }
-        sr += ar * k2[b];
-        si += ai * k2[b];
+        const R z = ((R)d2 + R(b)) * s2;
+        R kb;
+        if constexpr (sizeof(R) == 4)
+            kb = __expf(beta * (__fsqrt_rn(fmaxf(R(1) - z * z, 0.0f)) - 1.0f));
+        else
+            kb = exp(beta * (sqrt(fmax(R(1) - z * z, 0.0)) - 1.0));
+        sr += ar * kb;
+        si += ai * kb;
     }
     const double corr = cheb_inv_phi(tp.ch1, (X - tp.xic) * tp.th1) * cheb_inv_phi(tp.ch2, (Y - tp.etac) * tp.th2);
     const double vr = (double)sr * corr, vi = (double)si * corr;
@@ -764,14 +805,14 @@ fh_status launch_spread(fh_ctx* c, unsigned grid, const Sub* subs, const int* ns
 
 template <class R>
 fh_status launch_interp(fh_ctx* c, int W, const R* G, const double* xi, const double* eta, int64_t M,
-                        double beta, const T3Params& tp, R* u)
+                        double beta, const T3Params& tp, const int* perm, R* u)
 {
     const unsigned g = nblocks(M, 256);
     switch (W) {
 #define FH_INTERP_CASE(w)                                                                           \
     case w:                                                                                        \
         hipLaunchKernelGGL((k_t3_interp<R, w>), dim3(g), dim3(256), 0, c->stream, G, xi, eta, M, (R)beta, \
-                           tp, u);                                                                 \
+                           tp, perm, u);                                                           \
         break;
         FH_INTERP_CASE(2) FH_INTERP_CASE(3) FH_INTERP_CASE(4) FH_INTERP_CASE(5) FH_INTERP_CASE(6)
         FH_INTERP_CASE(7) FH_INTERP_CASE(8) FH_INTERP_CASE(9) FH_INTERP_CASE(10) FH_INTERP_CASE(11)

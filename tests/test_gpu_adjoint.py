@@ -1,0 +1,180 @@
+"""The hand-written adjoint (type-2 NUFFT back to the nodes + starshade chain
+rule) against the CPU oracle's exact direct-sum gradient, finite differences
+and torch's autograd plumbing."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-9, "mixed": 1e-5}
+
+
+def relL2(a, b):
+    a = np.asarray(a).ravel()
+    b = np.asarray(b).ravel()
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def fh():
+    import paper_2010_05978_amd as fh
+    return fh
+
+
+@pytest.fixture(scope="module", params=["fp64", "mixed"])
+def ctx(request, fh):
+    c = fh.Context(request.param)
+    yield c
+    c.close()
+
+
+def cpu(t):
+    return t.detach().cpu().numpy()
+
+
+@pytest.mark.parametrize("occ,xc,yc,n1,n2,h", [
+    (False, 0.0, 0.0, 64, 48, 0.05),
+    (True, 0.21, -0.33, 40, 56, 0.045),
+    (False, 0.0, 0.0, 16, 16, 0.4),     # folded: rows cover the whole period
+])
+def test_grid_vjp_matches_oracle(ctx, occ, xc, yc, n1, n2, h):
+    a = np.zeros(5)
+    a[4] = 0.3
+    shape = workloads.RadialCurve(1.0, a, np.zeros(5), panels=10, q=16, m=30)
+    lam, z = 1.0, 0.12
+    q = ctx.quad_for(shape)
+    g = np.random.Generator(np.random.PCG64(21))
+    gu = (g.normal(size=(n2, n1)) + 1j * g.normal(size=(n2, n1)))
+    gu_t = torch.tensor(gu, dtype=ctx.cdtype, device="cuda")
+    gx, gy, gw = (cpu(t) for t in ctx.field_grid_vjp(q, lam, z, n1, n2, h, h, gu_t, xc, yc, occ))
+    x, y, w = oracle.quad_radial(shape.r0, shape.a, shape.b, shape.panels, shape.q, shape.m)
+    xi, eta = oracle.grid_targets(n1, n2, h, h, xc, yc)
+    gref = cpu(gu_t).astype(np.complex128).ravel()
+    rx, ry, rw = oracle.fresnel_direct_vjp(x, y, w, lam, z, xi, eta, gref, occ)
+    for got, ref, name in ((gx, rx, "x"), (gy, ry, "y"), (gw, rw, "w")):
+        err = relL2(got, ref)
+        print(f"  d/d{name}: rel L2 {err:.2e}", flush=True)
+        assert err <= TOL[ctx.precision], name
+
+
+def test_starshade_vjp_matches_oracle(fh):
+    c = fh.Context("fp64")
+    s = workloads.workload(5, reduced=True).shape
+    N = s.n_nodes
+    g = np.random.Generator(np.random.PCG64(22))
+    gx, gy, gw = g.normal(size=(3, N))
+    dev = lambda a: torch.tensor(a, dtype=torch.float64, device="cuda")
+    out = torch.empty(2 * s.Np * s.K, dtype=torch.float64, device="cuda")
+    from paper_2010_05978_amd import abi
+    abi.fh_starshade_vjp(c.handle, s.Np, s.a, s.R, s.b, s.p, s.m, s.np_, s.nd, s.md, dev(s.coef), s.K,
+                         dev(gx), dev(gy), dev(gw), out)
+    ref = oracle.starshade_vjp(s.Np, s.a, s.R, s.b, s.p, s.m, s.np_, s.nd, s.md, s.coef, s.K, gx, gy, gw)
+    assert relL2(cpu(out), ref) <= 1e-12
+    c.close()
+
+
+def _oracle_loss_and_grad(wl, mask):
+    s, gd = wl.shape, wl.grid
+    x, y, w = oracle.quad_starshade(s.Np, s.a, s.R, s.b, s.p, s.m, s.np_, s.nd, s.md, s.coef, s.K)
+    xi, eta = oracle.grid_targets(gd.n1, gd.n2, gd.h1, gd.h2)
+    xi, eta = xi[mask], eta[mask]
+    Min = int(mask.sum())
+    L = 0.0
+    gx = np.zeros_like(x); gy = np.zeros_like(x); gw = np.zeros_like(x)
+    uap_n, uoc_n = 0.0, 0.0
+    for lam in wl.lams:
+        u = oracle.fresnel_direct(x, y, w, lam, wl.z, xi, eta, occulter=True)
+        L += float((np.abs(u) ** 2).sum()) / (len(wl.lams) * Min)
+        g = 2.0 * u / (len(wl.lams) * Min)
+        a, b, cc = oracle.fresnel_direct_vjp(x, y, w, lam, wl.z, xi, eta, g, occulter=True)
+        gx += a; gy += b; gw += cc
+        uoc_n += float((np.abs(u) ** 2).sum())
+        uap_n += float((np.abs(1 - u) ** 2).sum())
+    gc = oracle.starshade_vjp(s.Np, s.a, s.R, s.b, s.p, s.m, s.np_, s.nd, s.md, s.coef, s.K, gx, gy, gw)
+    # errors in u_ap carry over to u_oc = 1 - u_ap absolutely: relative to the
+    # shadow field they are amplified by |u_ap|/|u_oc|
+    kappa = math.sqrt(uap_n / uoc_n)
+    return L, gc, kappa
+
+
+def _gpu_loss(fh_ctx, wl, coef, mask_t):
+    from paper_2010_05978_amd.autograd import starshade_field
+    gd = wl.grid
+    Min = int(mask_t.sum())
+    L = 0.0
+    for lam in wl.lams:
+        u = starshade_field(coef, fh_ctx, wl.shape, lam, wl.z, gd, occulter=True)
+        L = L + ((u.abs() ** 2).reshape(-1) * mask_t).sum() / (len(wl.lams) * Min)
+    return L
+
+
+def test_autograd_starshade_gradient_vs_direct_sum(ctx):
+    wl = workloads.workload(5, reduced=True)
+    mask = workloads.pupil_mask(wl.grid.n1)
+    mask_t = torch.tensor(mask, dtype=torch.float64 if ctx.precision == "fp64" else torch.float32, device="cuda")
+    coef = torch.tensor(wl.shape.coef, dtype=torch.float64, device="cuda", requires_grad=True)
+    print(f"autograd starshade {ctx.precision}", flush=True)
+    L = _gpu_loss(ctx, wl, coef, mask_t)
+    L.backward()
+    Lref, gref, kappa = _oracle_loss_and_grad(wl, mask)
+    errL = abs(float(L) - Lref) / Lref
+    errg = relL2(cpu(coef.grad), gref)
+    print(f"  loss {float(L):.6e} (oracle {Lref:.6e}, rel {errL:.2e}); grad rel L2 {errg:.2e}; "
+          f"shadow amplification {kappa:.1f}", flush=True)
+    bar = TOL[ctx.precision] * kappa
+    assert errL <= 2 * bar
+    assert errg <= 2 * bar
+
+
+def test_finite_differences(fh):
+    # central differences of the FP64 GPU loss, h = 1e-7 m, on a seeded subset
+    # of the 384 coefficients
+    c = fh.Context("fp64")
+    wl = workloads.workload(5, reduced=True)
+    mask_t = torch.tensor(workloads.pupil_mask(wl.grid.n1), dtype=torch.float64, device="cuda")
+    coef = torch.tensor(wl.shape.coef, dtype=torch.float64, device="cuda", requires_grad=True)
+    L = _gpu_loss(c, wl, coef, mask_t)
+    L.backward()
+    grad = cpu(coef.grad)
+    h = 1e-7
+    idx = np.random.Generator(np.random.PCG64(23)).choice(len(grad), 6, replace=False)
+    with torch.no_grad():
+        for i in idx:
+            cp = coef.detach().clone(); cp[i] += h
+            cm = coef.detach().clone(); cm[i] -= h
+            fd = (float(_gpu_loss(c, wl, cp, mask_t)) - float(_gpu_loss(c, wl, cm, mask_t))) / (2 * h)
+            print(f"  coef {i}: adjoint {grad[i]:.8e} fd {fd:.8e}", flush=True)
+            assert abs(fd - grad[i]) <= 1e-4 * np.abs(grad).max() + 1e-6 * abs(grad[i])
+    c.close()
+
+
+def test_node_autograd_matches_torch_direct(fh):
+    # gradients through NodeGridField vs torch autograd of the plain sum
+    from paper_2010_05978_amd.autograd import node_field
+    c = fh.Context("fp64")
+    g = np.random.Generator(np.random.PCG64(24))
+    N = 300
+    x = g.uniform(-0.8, 0.8, N); y = g.uniform(-0.8, 0.8, N); w = g.uniform(0.0, 0.01, N)
+    grid = workloads.Grid(24, 20, 0.07, 0.08, 0.1, -0.05)
+    lam, z = 1.0, 0.3
+    tx, ty, tw = (torch.tensor(v, device="cuda", requires_grad=True) for v in (x, y, w))
+    u = node_field(tx, ty, tw, c, lam, z, grid, occulter=True)
+    wt = torch.tensor(g.uniform(0.5, 1.5, (grid.n2, grid.n1)), device="cuda")
+    (wt * u.abs() ** 2).sum().backward()
+    # reference: torch autograd of the plain sum on the CPU in float64
+    cx, cy, cw = (torch.tensor(v, requires_grad=True) for v in (x, y, w))
+    xi, eta = oracle.grid_targets(grid.n1, grid.n2, grid.h1, grid.h2, grid.xc, grid.yc)
+    xi, eta = torch.tensor(xi), torch.tensor(eta)
+    ph = math.pi * ((xi[:, None] - cx[None]) ** 2 + (eta[:, None] - cy[None]) ** 2) / (lam * z)
+    E = torch.polar(torch.ones_like(ph), ph)
+    ur = 1 - (E * cw[None].to(E.dtype)).sum(1) / (1j * lam * z)
+    (wt.cpu().reshape(-1) * ur.abs() ** 2).sum().backward()
+    for got, ref in ((tx.grad, cx.grad), (ty.grad, cy.grad), (tw.grad, cw.grad)):
+        assert relL2(cpu(got), ref.numpy()) <= 1e-9
+    c.close()
