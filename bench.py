@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--only", choices=["fp64", "mixed"], default=None, help="time one precision only")
     ap.add_argument("--pmc-calib", action="store_true",
                     help="also run a plain 256 MiB device copy (counter calibration for rocprofv3 --pmc)")
+    ap.add_argument("--no-grad", action="store_true", help="skip the backward/forward ratio (workload 5)")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched workload 4")
     return ap.parse_args()
 
 
@@ -138,6 +140,78 @@ def roofline(res, prec, wl):
     return out
 
 
+def grad_ratio(fh, precision, steps, warmup):
+    """Backward/forward device time of the starshade shape-gradient problem
+    (workload 5: 998,400 nodes, 384 edge coefficients, 512^2 pupil grid with
+    the k1^2 + k2^2 < 256^2 mask, 3 wavelengths, loss = mean |u_oc|^2)."""
+    import torch
+    import workloads
+    from paper_2010_05978_amd.autograd import starshade_field
+    wl = workloads.workload(5)
+    ctx = fh.Context(precision)
+    rdt = torch.float64 if precision == "fp64" else torch.float32
+    mask = torch.tensor(workloads.pupil_mask(wl.grid.n1), dtype=rdt, device="cuda")
+    Min = float(mask.sum())
+    coef = torch.tensor(wl.shape.coef, dtype=torch.float64, device="cuda", requires_grad=True)
+
+    def forward():
+        L = 0.0
+        for lam in wl.lams:
+            u = starshade_field(coef, ctx, wl.shape, lam, wl.z, wl.grid, occulter=True)
+            L = L + ((u.abs() ** 2).reshape(-1) * mask).sum() / (len(wl.lams) * Min)
+        return L
+
+    for _ in range(warmup):
+        forward().backward()
+    fwd = bwd = 0.0
+    for _ in range(steps):
+        coef.grad = None
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        L = forward()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        L.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        fwd += t1 - t0
+        bwd += t2 - t1
+    ctx.close()
+    return {"fwd_ms": 1e3 * fwd / steps, "bwd_ms": 1e3 * bwd / steps, "ratio": bwd / fwd,
+            "workload": "24-petal starshade, 998400 nodes, 384 edge coefficients, 512^2 masked pupil, "
+                        "3 wavelengths; forward includes quadrature generation"}
+
+
+def batch_throughput(fh, steps, warmup):
+    """Workload 4: 256 random shapes (node counts uniform in [1e4, 4e5]), one
+    wavelength each from 64 log-spaced in [0.5, 1.0] um, 512^2 grids, mixed
+    precision; one batched call replayed from a hipGraph."""
+    import numpy as np
+    import torch
+    import workloads
+    ctx = fh.Context("mixed")
+    shapes = workloads.batch_shapes()
+    lams = workloads.batch_lambdas(64)
+    quads = [ctx.quad_for(s) for s in shapes]
+    B = len(quads)
+    lam = np.array([lams[i % 64] for i in range(B)])
+    zs = np.full(B, workloads.BATCH_Z)
+    g = workloads.BATCH_GRID
+    out = torch.empty((B, g.n2, g.n1), dtype=ctx.cdtype, device="cuda")
+    for _ in range(warmup):
+        ctx.field_grid_batch(quads, lam, zs, g.n1, g.n2, g.h1, g.h2, occulter=False, out=out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.field_grid_batch(quads, lam, zs, g.n1, g.n2, g.h1, g.h2, occulter=False, out=out)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    N = sum(q.N for q in quads)
+    ctx.close()
+    return {"value": B * g.M / dt, "unit": "targets/s", "ms_per_call": 1e3 * dt, "nodes_per_s": N / dt,
+            "instances": B, "nodes": N, "dtype": "c64-f64phase", "tolerance": 1e-5}
+
+
 def cpu_baseline(wl, seconds):
     """The oracle (direct FP64 sum) on a seeded sample of the step's targets."""
     import numpy as np
@@ -205,6 +279,10 @@ def main():
     if "mixed" in res and main_p != "mixed":
         out["mixed"] = {"value": res["mixed"]["value"], "ms_per_step": res["mixed"]["ms_per_step"],
                         "dtype": "c64-f64phase", "tolerance": 1e-5, "roofline": roofline(res, "mixed", wl)}
+    if not args.no_grad:
+        out["backward_forward"] = {p: grad_ratio(fh, p, 3, 1) for p in precs}
+    if not args.no_batch:
+        out["batch"] = batch_throughput(fh, 5, 2)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
     print(json.dumps(out))

@@ -132,6 +132,10 @@ class Context:
                               g_u.contiguous(), gx, gy, gw)
         return gx, gy, gw
 
+    def autotune_grid(self, quad: Quad, lam, z, n1, n2, h1, h2, cache_path=None) -> fh_options:
+        """Time the grid field over the tuning space and keep the fastest options."""
+        return abi.fh_autotune_grid(self.handle, quad.handle, lam, z, n1, n2, h1, h2, cache_path)
+
     def query_params(self, n):
         return abi.fh_query_params(self.handle, n)
 

@@ -1,11 +1,156 @@
-// fh_autotune.hip -- spread/FFT parameter search (filled in below).
+// fh_autotune.hip -- choice of spread method, work-item size, tile edge and
+// upsampling factor by timing the grid field on the device.
+//
+// Every candidate meets the context's tolerance (the kernel width follows
+// from sigma and the tolerance), so the search only trades spread work
+// against FFT size and parallelism.  Results are cached per context and,
+// optionally, in a JSON-lines file keyed by precision, tolerance, grid size
+// and the node count's power-of-two class.
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <sstream>
+#include <string>
+#include <vector>
+
 #include "fh_common.hpp"
-using namespace fh;
-extern "C" {
-fh_status fh_autotune_grid(fh_ctx*, const fh_quad*, double, double, int32_t, int32_t, double, double, const char*,
-                           fh_options*)
+
+namespace fh {
+namespace {
+
+std::string tune_key(const fh_ctx* c, int n1, int n2, int64_t N)
 {
-    set_error("not implemented yet");
-    return FH_ERR_UNSUPPORTED;
+    int cls = 0;
+    while (((int64_t)1 << cls) < std::max<int64_t>(N, 1)) ++cls;
+    char buf[160];
+    snprintf(buf, sizeof(buf), "%s|%.3e|%d|%d|%d", c->prec == FH_FP64 ? "fp64" : "mixed", c->tol, n1, n2, cls);
+    return buf;
 }
+
+bool cache_lookup(const char* path, const std::string& key, fh_options* o)
+{
+    if (!path) return false;
+    std::ifstream f(path);
+    if (!f) return false;
+    std::string line;
+    bool found = false;
+    while (std::getline(f, line)) {
+        const std::string tag = "\"key\": \"" + key + "\"";
+        if (line.find(tag) == std::string::npos) continue;
+        fh_options t{};
+        const char* p = std::strstr(line.c_str(), "\"sigma\":");
+        if (!p || std::sscanf(p, "\"sigma\": %lf, \"tile\": %d, \"max_subproblem\": %d, \"spread_method\": %d",
+                              &t.sigma, &t.tile, &t.max_subproblem, &t.spread_method) != 4)
+            continue;
+        *o = t;  // the last matching line wins
+        found = true;
+    }
+    return found;
 }
+
+void cache_append(const char* path, const std::string& key, const fh_options& o, double ms)
+{
+    if (!path) return;
+    std::ofstream f(path, std::ios::app);
+    if (!f) return;
+    char buf[400];
+    snprintf(buf, sizeof(buf),
+             "{\"key\": \"%s\", \"sigma\": %.2f, \"tile\": %d, \"max_subproblem\": %d, \"spread_method\": %d, "
+             "\"ms\": %.5f}\n",
+             key.c_str(), o.sigma, o.tile, o.max_subproblem, o.spread_method, ms);
+    f << buf;
+}
+
+}  // namespace
+}  // namespace fh
+
+using namespace fh;
+
+extern "C" {
+
+fh_status fh_autotune_grid(fh_ctx* c, const fh_quad* q, double lambda, double z, int32_t n1, int32_t n2, double h1,
+                           double h2, const char* cache_path, fh_options* best)
+{
+    try {
+        FH_ARG(c && q && best, FH_ERR_INVALID_ARG, "NULL argument");
+        FH_ARG(q->ctx == c, FH_ERR_INVALID_ARG, "quadrature belongs to another context");
+        FH_ARG(n1 > 0 && n2 > 0 && n1 % 2 == 0 && n2 % 2 == 0, FH_ERR_ODD_GRID, "grid sizes must be even");
+        FH_HIP(hipSetDevice(c->device));
+        const std::string key = tune_key(c, n1, n2, q->N);
+        fh_options hit{};
+        if (cache_lookup(cache_path, key, &hit)) {
+            c->opt = hit;
+            *best = hit;
+            return FH_OK;
+        }
+        const fh_options saved = c->opt;
+        const size_t ubytes = (c->prec == FH_FP64 ? 16 : 8) * (size_t)n1 * n2;
+        void* u = nullptr;
+        FH_TRY(dev_alloc(c, ubytes, &u));
+        hipEvent_t e0, e1;
+        FH_HIP(hipEventCreate(&e0));
+        FH_HIP(hipEventCreate(&e1));
+        const bool timing = c->timing;
+        c->timing = false;
+        double best_ms = 1e300;
+        fh_options best_o = saved;
+        fh_status st = FH_OK;
+        for (double sigma : {2.0, 1.25})
+            for (int method : {2, 1})
+                for (int tile : {16, 32})
+                    for (int P : {64, 128, 256, 512, 1024}) {
+                        fh_options o = saved;
+                        o.sigma = sigma;
+                        o.kernel_width = 0;
+                        o.beta = 0.0;
+                        o.tile = tile;
+                        o.max_subproblem = P;
+                        o.spread_method = method;
+                        c->opt = o;
+                        // the kernel must fit at this sigma without widening
+                        const EsKernel k = choose_kernel(c, std::max(n1, n2));
+                        if (k.sigma != sigma || k.clamped) continue;
+                        fh_status s = FH_OK;
+                        for (int w = 0; w < 2 && s == FH_OK; ++w)
+                            s = fh_field_grid(c, q, lambda, z, n1, n2, h1, h2, 0.0, 0.0, 0, u, FH_MEM_DEVICE);
+                        if (s == FH_ERR_UNSUPPORTED) continue;  // e.g. tile too large for the LDS budget
+                        if (s != FH_OK) {
+                            st = s;
+                            break;
+                        }
+                        const int reps = 5;
+                        FH_HIP(hipEventRecord(e0, c->stream));
+                        for (int r = 0; r < reps && s == FH_OK; ++r)
+                            s = fh_field_grid(c, q, lambda, z, n1, n2, h1, h2, 0.0, 0.0, 0, u, FH_MEM_DEVICE);
+                        FH_HIP(hipEventRecord(e1, c->stream));
+                        FH_HIP(hipEventSynchronize(e1));
+                        float ms = 0;
+                        FH_HIP(hipEventElapsedTime(&ms, e0, e1));
+                        if (s != FH_OK) {
+                            st = s;
+                            break;
+                        }
+                        if (ms / reps < best_ms) {
+                            best_ms = ms / reps;
+                            best_o = o;
+                        }
+                    }
+        c->timing = timing;
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        (void)dev_free(c, u);
+        if (st != FH_OK) {
+            c->opt = saved;
+            return st;
+        }
+        c->opt = best_o;
+        *best = best_o;
+        cache_append(cache_path, key, best_o, best_ms);
+        return FH_OK;
+    } catch (...) {
+        set_error("host allocation failed");
+        return FH_ERR_ALLOC;
+    }
+}
+
+}  // extern "C"

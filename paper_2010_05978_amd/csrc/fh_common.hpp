@@ -59,6 +59,7 @@ struct EsKernel {
     int w = 0;
     double beta = 0;
     double sigma = 2.0;
+    bool clamped = false;  // the tolerance needs a wider kernel than supported
 };
 
 // 1/Phi(theta) for |theta| <= theta_max as a Chebyshev series in
@@ -169,6 +170,8 @@ struct fh_ctx {
     std::map<std::tuple<int, int, int, int>, fh::FftPlan> fft_cache;
     std::map<size_t, std::vector<void*>> pool;  // freed quadrature buffers by size
     std::map<std::string, fh::GraphEntry> graph_cache;
+    hipStream_t gstream = nullptr;  // private stream for graph capture/replay
+    hipEvent_t gev_in = nullptr, gev_out = nullptr;
     std::map<std::tuple<int, long long, long long>, fh::InvPhiCheb> cheb_cache;
     std::map<void*, size_t> owned;  // every hipMalloc'd block and its size
     double* bbox_dev = nullptr;      // bounding-box reduction scratch

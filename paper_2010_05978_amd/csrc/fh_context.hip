@@ -172,6 +172,7 @@ EsKernel choose_kernel(const fh_ctx* c, int /*n_hint*/)
         k.sigma = 2.0;
         w = (int)std::ceil(std::log(1.0 / eps) / (kPi * std::sqrt(0.5)));
     }
+    k.clamped = w > kMaxWidth && c->opt.kernel_width <= 0;
     w = std::min(std::max(w, 2), kMaxWidth);
     k.w = w;
     k.beta = c->opt.beta > 0 ? c->opt.beta : 0.97 * kPi * w * (1.0 - 0.5 / k.sigma);
@@ -531,6 +532,12 @@ fh_status fh_destroy(fh_ctx* c)
     for (auto& kv : c->graph_cache) {
         if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
         if (kv.second.graph) (void)hipGraphDestroy(kv.second.graph);
+    }
+    if (c->gstream) {
+        (void)hipStreamSynchronize(c->gstream);
+        (void)hipStreamDestroy(c->gstream);
+        (void)hipEventDestroy(c->gev_in);
+        (void)hipEventDestroy(c->gev_out);
     }
     for (auto& kv : c->fft_cache) {
         if (kv.second.info) rocfft_execution_info_destroy(kv.second.info);

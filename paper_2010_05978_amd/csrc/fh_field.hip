@@ -37,6 +37,8 @@ fh_status t1_pipeline(fh_ctx* c, int B, const fh_quad* const* qs, const double* 
 {
     const size_t rs = sizeof(R);
     T1Plan pl = plan_t1(c, n1, n2);
+    FH_ARG(!pl.k.clamped, FH_ERR_UNSUPPORTED, "tolerance %g needs a kernel wider than %d at sigma %g", c->tol,
+           kMaxWidth, pl.k.sigma);
     GridGeom gg = pl.gg;
     std::vector<InstParams> inst(B);
     std::vector<EpiInst> epi(B);
@@ -130,19 +132,33 @@ fh_status t1_pipeline(fh_ctx* c, int B, const fh_quad* const* qs, const double* 
              gg.method, (void*)u);
     std::string k2(key);
     for (int b = 0; b < B; ++b) k2 += "|" + std::to_string(qs[b]->N);
+    // Graphs are captured and replayed on a private stream (the caller's may
+    // be the null stream, which cannot be captured), ordered after the
+    // caller's prior work and before its later work by events.
+    if (!c->gstream) {
+        FH_HIP(hipStreamCreateWithFlags(&c->gstream, hipStreamNonBlocking));
+        FH_HIP(hipEventCreateWithFlags(&c->gev_in, hipEventDisableTiming));
+        FH_HIP(hipEventCreateWithFlags(&c->gev_out, hipEventDisableTiming));
+    }
+    hipStream_t user = c->stream;
+    FH_HIP(hipEventRecord(c->gev_in, user));
+    FH_HIP(hipStreamWaitEvent(c->gstream, c->gev_in, 0));
     auto it = c->graph_cache.find(k2);
     if (it == c->graph_cache.end()) {
         GraphEntry ge;
-        FH_HIP(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-        fh_status s = run();
+        c->stream = c->gstream;
+        hipError_t eb = hipStreamBeginCapture(c->gstream, hipStreamCaptureModeThreadLocal);
+        fh_status s = FH_OK;
         hipGraph_t g = nullptr;
-        hipError_t e = hipStreamEndCapture(c->stream, &g);
-        if (s != FH_OK) {
-            if (g) (void)hipGraphDestroy(g);
-            return s;
+        hipError_t e = hipSuccess;
+        if (eb == hipSuccess) {
+            s = run();
+            e = hipStreamEndCapture(c->gstream, &g);
         }
-        if (e != hipSuccess || !g) {
-            // a library call refused capture: run eagerly instead
+        c->stream = user;
+        if (eb != hipSuccess || e != hipSuccess || !g || s != FH_OK) {
+            // capture refused (or a call failed inside it): run eagerly
+            if (g) (void)hipGraphDestroy(g);
             (void)hipGetLastError();
             return run();
         }
@@ -150,7 +166,9 @@ fh_status t1_pipeline(fh_ctx* c, int B, const fh_quad* const* qs, const double* 
         FH_HIP(hipGraphInstantiate(&ge.exec, g, nullptr, nullptr, 0));
         it = c->graph_cache.emplace(k2, ge).first;
     }
-    FH_HIP(hipGraphLaunch(it->second.exec, c->stream));
+    FH_HIP(hipGraphLaunch(it->second.exec, c->gstream));
+    FH_HIP(hipEventRecord(c->gev_out, c->gstream));
+    FH_HIP(hipStreamWaitEvent(user, c->gev_out, 0));
     return FH_OK;
 }
 
@@ -268,6 +286,8 @@ fh_status field_points_impl(fh_ctx* c, const fh_quad* q, double lambda, double z
     double sb[4];
     FH_TRY(quad_bbox(c, q, sb));
     EsKernel k = choose_kernel(c, 0);
+    FH_ARG(!k.clamped, FH_ERR_UNSUPPORTED, "tolerance %g needs a kernel wider than %d at sigma %g", c->tol, kMaxWidth,
+           k.sigma);
     const int T0 = c->opt.tile > 0 ? std::min(c->opt.tile, 32) : 16;
     T3Dim d1 = plan_t3_dim(sb[0], sb[1], tb[0], tb[1], lz, k, T0);
     T3Dim d2 = plan_t3_dim(sb[2], sb[3], tb[2], tb[3], lz, k, T0);

@@ -22,7 +22,7 @@ template <class R> struct V2;
 template <> struct V2<float> { using T = float2; };
 template <> struct V2<double> { using T = double2; };
 
-constexpr int kMaxSubPerTile = 64;  // work items per tile before items grow
+constexpr int kMaxSubPerTile = 512;  // work items per tile before items grow
 constexpr size_t kLdsBudget = 64 * 1024;
 
 // --------------------------------------------------------- device helpers
@@ -129,38 +129,28 @@ __global__ void k_fill_field(R* __restrict__ u, int64_t M, R re)
 }
 
 // ------------------------------------------------------------------- bin
-// Rank of each lane's key among all increments of cnt[key].  Lanes sharing a
-// key elect a leader; the leaders of all distinct keys in the wavefront issue
-// their atomics together (one round trip), and each lane adds its position
-// among the lanes with its key.  Quadrature nodes arrive in spoke order, so a
-// wavefront touches few tiles, while the crowded tiles near the origin would
-// otherwise serialise thousands of same-address atomics.
-__device__ __forceinline__ int wave_rank(int* __restrict__ cnt, int key, bool valid)
-{
-    const int lane = (int)__lane_id();
-    uint64_t remaining = __ballot(valid);
-    uint64_t mine = 0;
-    int leader = lane;
-    while (remaining) {
-        const int l = __ffsll((unsigned long long)remaining) - 1;
-        const int lkey = __shfl(key, l);
-        const uint64_t same = __ballot(valid && key == lkey) & remaining;
-        if ((same >> lane) & 1ull) {
-            mine = same;
-            leader = l;
-        }
-        remaining &= ~same;
-    }
-    int base = 0;
-    if (valid && leader == lane) base = atomicAdd(&cnt[key], __popcll(mine));
-    base = __shfl(base, leader);
-    return base + __popcll(mine & ((1ull << lane) - 1ull));
-}
+// Block-aggregated counting: the wavefronts of a block first combine their
+// per-tile counts in a small LDS table (tiles of one block are few, since
+// nodes arrive in spoke order), then one global atomic per distinct tile of
+// the block reserves the block's positions.  A table overflow falls back to
+// one global atomic per wavefront group.  When every node of a rule falls in
+// a couple of tiles (a starshade seen on a coarse pupil grid), this turns
+// one same-address atomic chain per wavefront into one per block.
+constexpr int kBinBlock = 1024;
+constexpr int kBinKeys = 128;
 
-__global__ void __launch_bounds__(256) k_bin_count(InstParams p0, const InstParams* __restrict__ table, int ninst,
-                                                   int64_t Ntot, GridGeom gg, int* __restrict__ cnt,
-                                                   int* __restrict__ rank)
+__global__ void __launch_bounds__(kBinBlock) k_bin_count(InstParams p0, const InstParams* __restrict__ table,
+                                                         int ninst, int64_t Ntot, GridGeom gg,
+                                                         int* __restrict__ cnt, int* __restrict__ rank)
 {
+    __shared__ int s_key[kBinKeys];
+    __shared__ int s_cnt[kBinKeys];
+    __shared__ int s_base[kBinKeys];
+    if (threadIdx.x < kBinKeys) {
+        s_key[threadIdx.x] = -1;
+        s_cnt[threadIdx.x] = 0;
+    }
+    __syncthreads();
     const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     const bool valid = j < Ntot;
     int tile = 0;
@@ -172,8 +162,46 @@ __global__ void __launch_bounds__(256) k_bin_count(InstParams p0, const InstPara
         node_cell(ip, gg, ip.x[jj], ip.y[jj], l1, l2, d1, d2);
         tile = ip.tile_off + (l2 / gg.T) * gg.ntx + (l1 / gg.T);
     }
-    const int r = wave_rank(cnt, tile, valid);
-    if (valid) rank[j] = r;
+    // groups of lanes with one tile; the lowest lane leads each group
+    const int lane = (int)__lane_id();
+    uint64_t remaining = __ballot(valid);
+    uint64_t mine = 0;
+    int leader = lane;
+    while (remaining) {
+        const int l = __ffsll((unsigned long long)remaining) - 1;
+        const int lkey = __shfl(tile, l);
+        const uint64_t same = __ballot(valid && tile == lkey) & remaining;
+        if ((same >> lane) & 1ull) {
+            mine = same;
+            leader = l;
+        }
+        remaining &= ~same;
+    }
+    const bool lead = valid && leader == lane;
+    int slot = -1, off = 0, gbase = 0;
+    if (lead) {
+        int h = (int)(((unsigned)tile * 2654435761u) >> 25) & (kBinKeys - 1);
+        for (int probe = 0; probe < kBinKeys; ++probe) {
+            const int prev = atomicCAS(&s_key[h], -1, tile);
+            if (prev == -1 || prev == tile) {
+                slot = h;
+                break;
+            }
+            h = (h + 1) & (kBinKeys - 1);
+        }
+        if (slot >= 0)
+            off = atomicAdd(&s_cnt[slot], __popcll(mine));
+        else
+            gbase = atomicAdd(&cnt[tile], __popcll(mine));
+    }
+    __syncthreads();
+    if (threadIdx.x < kBinKeys && s_key[threadIdx.x] >= 0)
+        s_base[threadIdx.x] = atomicAdd(&cnt[s_key[threadIdx.x]], s_cnt[threadIdx.x]);
+    __syncthreads();
+    int base = 0;
+    if (lead) base = slot >= 0 ? s_base[slot] + off : gbase;
+    base = __shfl(base, leader);
+    if (valid) rank[j] = base + __popcll(mine & ((1ull << lane) - 1ull));
 }
 
 // One block: exclusive scan of tile counts -> tile offsets, and the list of
@@ -333,6 +361,25 @@ __global__ void __launch_bounds__(256) k_spread_thread(const Sub* __restrict__ s
     }
 }
 
+// Add a run's register sums (lane (a, b) of pass pp holds stencil cell
+// (a, b) of the run's first cell) into the LDS tile and clear them.
+template <class R, int NPASS>
+__device__ __forceinline__ void flush_run(R* sre, R* sim, int L, int c1, int c2, const int* pa, const int* pb,
+                                          const bool* pv, R* accr, R* acci)
+{
+    if (c1 < 0) return;
+#pragma unroll
+    for (int pp = 0; pp < NPASS; ++pp) {
+        if (pv[pp]) {
+            const int idx = (c2 + pb[pp]) * L + c1 + pa[pp];
+            atomicAdd(sre + idx, accr[pp]);
+            atomicAdd(sim + idx, acci[pp]);
+        }
+        accr[pp] = R(0);
+        acci[pp] = R(0);
+    }
+}
+
 // Wavefront per point.  A wavefront loads 64 points and stages their 2W
 // kernel values in LDS; it then walks the points one at a time with its lanes
 // laid over the W x W stencil (ceil(W^2/64) passes), so the LDS atomics of one
@@ -372,6 +419,14 @@ __global__ void __launch_bounds__(256) k_spread_wave(const Sub* __restrict__ sub
             sim[e] = R(0);
         }
         __syncthreads();
+        // run of consecutive points with the same first stencil cell: summed
+        // in registers and added to LDS once when the cell changes (nodes in
+        // spoke order often share a cell for tens of points, and same-address
+        // LDS atomics in back-to-back instructions stall the atomic pipeline)
+        int cur1 = -1, cur2 = -1;
+        R accr[NPASS], acci[NPASS];
+#pragma unroll
+        for (int pp = 0; pp < NPASS; ++pp) accr[pp] = acci[pp] = R(0);
         for (int base = sb.start + wv * 64; base < sb.end; base += nw * 64) {
             const int p = base + lane;
             int l1 = 0, l2 = 0;
@@ -403,31 +458,32 @@ __global__ void __launch_bounds__(256) k_spread_wave(const Sub* __restrict__ sub
             constexpr int U = 4;
             for (int q0 = 0; q0 < np; q0 += U) {
                 R kv[U][NPASS], vr[U], vi[U];
-                int idx[U][NPASS];
+                int c1[U], c2[U];
                 bool qv[U];
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
                     qv[u] = q0 + u < np;
                     const int q = qv[u] ? q0 + u : q0;
-                    const int ql1 = lane_val(l1, q), ql2 = lane_val(l2, q);
+                    c1[u] = lane_val(l1, q);
+                    c2[u] = lane_val(l2, q);
                     vr[u] = lane_val(cr, q);
                     vi[u] = lane_val(ci, q);
                     const R* kq = kb + q * KS;
 #pragma unroll
-                    for (int pp = 0; pp < NPASS; ++pp) {
-                        kv[u][pp] = kq[pa[pp]] * kq[W + pb[pp]];
-                        idx[u][pp] = (ql2 + pb[pp]) * L + ql1 + pa[pp];
-                    }
+                    for (int pp = 0; pp < NPASS; ++pp) kv[u][pp] = kq[pa[pp]] * kq[W + pb[pp]];
                 }
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
                     if (!qv[u]) continue;
+                    if (c1[u] != cur1 || c2[u] != cur2) {
+                        flush_run<R, NPASS>(sre, sim, L, cur1, cur2, pa, pb, pv, accr, acci);
+                        cur1 = c1[u];
+                        cur2 = c2[u];
+                    }
 #pragma unroll
                     for (int pp = 0; pp < NPASS; ++pp) {
-                        if (pv[pp]) {
-                            atomicAdd(sre + idx[u][pp], vr[u] * kv[u][pp]);
-                            atomicAdd(sim + idx[u][pp], vi[u] * kv[u][pp]);
-                        }
+                        accr[pp] += vr[u] * kv[u][pp];
+                        acci[pp] += vi[u] * kv[u][pp];
                     }
                 }
             }
@@ -435,6 +491,7 @@ __global__ void __launch_bounds__(256) k_spread_wave(const Sub* __restrict__ sub
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         }
+        flush_run<R, NPASS>(sre, sim, L, cur1, cur2, pa, pb, pv, accr, acci);
         __syncthreads();
         store_slot(sre, sim, LL, slots + (size_t)s * 2 * LL);
         __syncthreads();
@@ -882,7 +939,8 @@ fh_status run_spread(fh_ctx* c, const InstParams& p0, const InstParams* table, i
     const int ntiles_total = tpi * ninst;
     FH_TRY(launch_zero(c, b.cnt, sizeof(int) * ntiles_total));
     if (Ntot > 0) {
-        hipLaunchKernelGGL(k_bin_count, dim3(nblocks(Ntot, 256)), dim3(256), 0, c->stream, p0, table, ninst, Ntot,
+        hipLaunchKernelGGL(k_bin_count, dim3(nblocks(Ntot, kBinBlock)), dim3(kBinBlock), 0, c->stream, p0, table,
+                           ninst, Ntot,
                            gg, b.cnt, b.rank);
     }
     hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, c->stream, b.cnt, ntiles_total, gg.P, b.off, b.tsub,

@@ -1,0 +1,128 @@
+"""Batched grid fields (one persistent spread over every instance's work
+items, one batched FFT, hipGraph capture and replay) and the autotuner."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-9, "mixed": 1e-5}
+
+
+def relL2(a, b):
+    a = np.asarray(a).ravel()
+    b = np.asarray(b).ravel()
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def fh():
+    import paper_2010_05978_amd as fh
+    return fh
+
+
+@pytest.fixture(scope="module", params=["fp64", "mixed"])
+def ctx(request, fh):
+    c = fh.Context(request.param)
+    yield c
+    c.close()
+
+
+def cpu(t):
+    return t.detach().cpu().numpy()
+
+
+def oracle_quad(s):
+    if type(s).__name__ == "RadialCurve":
+        return oracle.quad_radial(s.r0, s.a, s.b, s.panels, s.q, s.m)
+    return oracle.quad_polygon(s.vx, s.vy, s.q, s.m)
+
+
+def _batch_inputs(count=6):
+    shapes = workloads.batch_shapes(count=count, nmin=3000, nmax=12000)
+    lams = workloads.batch_lambdas(64)[:count] * 1.0
+    zs = np.full(count, workloads.BATCH_Z)
+    occ = np.array([0, 1, 0, 1, 1, 0][:count], dtype=np.int32)
+    n = 128
+    grid = workloads.Grid(n, n, 3.0 / n, 3.0 / n)
+    return shapes, lams, zs, occ, grid
+
+
+def test_batch_matches_single_and_oracle(ctx):
+    shapes, lams, zs, occ, g = _batch_inputs()
+    quads = [ctx.quad_for(s) for s in shapes]
+    print(f"batch {ctx.precision}: N = {[q.N for q in quads]}", flush=True)
+    ub = cpu(ctx.field_grid_batch(quads, lams, zs, g.n1, g.n2, g.h1, g.h2, occulter=occ))
+    xi, eta = oracle.grid_targets(g.n1, g.n2, g.h1, g.h2)
+    rng = np.random.Generator(np.random.PCG64(31))
+    for b, (s, q) in enumerate(zip(shapes, quads)):
+        us = cpu(ctx.field_grid(q, lams[b], zs[b], g.n1, g.n2, g.h1, g.h2, occulter=bool(occ[b])))
+        ap_b = 1 - ub[b] if occ[b] else ub[b]
+        ap_s = 1 - us if occ[b] else us
+        assert relL2(ap_b, ap_s) <= TOL[ctx.precision]
+        idx = rng.choice(g.M, 400, replace=False)
+        x, y, w = oracle_quad(s)
+        ref = oracle.fresnel_direct(x, y, w, lams[b], zs[b], xi[idx], eta[idx])
+        err = relL2(ap_b.ravel()[idx], ref)
+        print(f"  instance {b}: rel L2 vs oracle (400 samples) {err:.2e}", flush=True)
+        assert err <= TOL[ctx.precision]
+
+
+def test_batch_graph_replays(ctx, monkeypatch):
+    shapes, lams, zs, occ, g = _batch_inputs(4)
+    quads = [ctx.quad_for(s) for s in shapes]
+    out = torch.empty((len(quads), g.n2, g.n1), dtype=ctx.cdtype, device="cuda")
+    monkeypatch.setenv("FH_NO_GRAPH", "1")
+    eager = cpu(ctx.field_grid_batch(quads, lams, zs, g.n1, g.n2, g.h1, g.h2, occulter=occ, out=out)).copy()
+    monkeypatch.delenv("FH_NO_GRAPH")
+    scratch = torch.randn(1 << 20, device="cuda")
+    # LDS atomics of several wavefronts land in any order: replays agree with
+    # the eager run to the rounding of the working precision
+    rounding = 1e-12 if ctx.precision == "fp64" else 1e-6
+    for rep in range(4):
+        got = cpu(ctx.field_grid_batch(quads, lams, zs, g.n1, g.n2, g.h1, g.h2, occulter=occ, out=out))
+        assert relL2(got, eager) <= rounding, rep
+        # the program's own eager work between replays
+        scratch.mul_(1.0001)
+        ctx.field_grid(quads[0], lams[0], zs[0], g.n1, g.n2, g.h1, g.h2)
+        torch.cuda.synchronize()
+    # same node counts, different rules: the replay must read the new nodes
+    shapes2 = []
+    for s in shapes:
+        if type(s).__name__ == "RadialCurve":
+            shapes2.append(workloads.RadialCurve(0.9 * s.r0, 0.9 * s.a, 0.9 * s.b, s.panels, s.q, s.m))
+        else:
+            shapes2.append(workloads.Polygon(0.9 * s.vx, 0.9 * s.vy, s.q, s.m))
+    quads2 = [ctx.quad_for(s) for s in shapes2]
+    got = cpu(ctx.field_grid_batch(quads2, lams, zs, g.n1, g.n2, g.h1, g.h2, occulter=occ, out=out))
+    for b, q in enumerate(quads2):
+        us = cpu(ctx.field_grid(q, lams[b], zs[b], g.n1, g.n2, g.h1, g.h2, occulter=bool(occ[b])))
+        assert relL2(got[b] - (1 if occ[b] else 0), us - (1 if occ[b] else 0)) <= TOL[ctx.precision]
+
+
+def test_autotune_keeps_accuracy_and_caches(ctx, tmp_path):
+    wl = workloads.workload(2)
+    s = workloads.RadialCurve(1.0, wl.shape.a, wl.shape.b, panels=12, q=16, m=50)
+    q = ctx.quad_for(s)
+    n = 200
+    h = 0.015
+    path = str(tmp_path / "tune.jsonl")
+    best = ctx.autotune_grid(q, wl.lam, wl.z, n, n, h, h, cache_path=path)
+    print(f"  tuned {ctx.precision}: sigma {best.sigma} tile {best.tile} P {best.max_subproblem} "
+          f"method {best.spread_method}", flush=True)
+    assert best.spread_method in (1, 2) and best.sigma in (1.25, 2.0)
+    assert os.path.exists(path)
+    again = ctx.autotune_grid(q, wl.lam, wl.z, n, n, h, h, cache_path=path)
+    assert (again.sigma, again.tile, again.max_subproblem, again.spread_method) == \
+        (best.sigma, best.tile, best.max_subproblem, best.spread_method)
+    u = cpu(ctx.field_grid(q, wl.lam, wl.z, n, n, h, h))
+    x, y, w = oracle_quad(s)
+    xi, eta = oracle.grid_targets(n, n, h, h)
+    ref = oracle.fresnel_direct(x, y, w, wl.lam, wl.z, xi, eta)
+    assert relL2(u, ref) <= TOL[ctx.precision]
+    ctx.set_options(None)
