@@ -77,8 +77,12 @@ typedef struct fh_options {
     int32_t kernel_width;   /* 2..20 cells                                   */
     double beta;            /* kernel shape parameter                        */
     int32_t tile;           /* spread tile edge in cells: 8, 16, 32 or 64    */
-    int32_t max_subproblem; /* max nonuniform points per spread work item    */
-    int32_t spread_method;  /* 1: thread per point, 2: wavefront per point   */
+    int32_t max_subproblem; /* nonuniform points per spread work item (a     *
+                             * tile with more than 512 items' worth gets     *
+                             * larger items); 0: about 32 items per CU      */
+    int32_t spread_method;  /* 1: thread per point, shared LDS tile with     *
+                             * atomics; 2: wavefront per work item, lanes    *
+                             * over the stencil, private LDS tile            */
 } fh_options;
 
 /* ---------------------------------------------------------------- context */

@@ -122,8 +122,8 @@ __global__ void __launch_bounds__(256) k_adj_transpose(const R* __restrict__ Zt,
 // node gradients.
 template <class R, int W>
 __global__ void __launch_bounds__(256) k_adj_gather(const R* __restrict__ F1, InstParams ip, GridGeom gg, R beta,
-                                                    double lz, double* __restrict__ gx, double* __restrict__ gy,
-                                                    double* __restrict__ gw)
+                                                    const R* __restrict__ poly, double lz, double* __restrict__ gx,
+                                                    double* __restrict__ gy, double* __restrict__ gw)
 {
     using C2 = typename V2<R>::T;
     const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -138,8 +138,7 @@ __global__ void __launch_bounds__(256) k_adj_gather(const R* __restrict__ F1, In
         return;
     }
     R k1[W];
-    es_weights<R, W>((R)d1, beta, k1);
-    const R s2 = R(2) / R(W);
+    es_weights<R, W>((R)d1, beta, poly, k1);
     const size_t plane = (size_t)gg.rows * gg.nf1;
     const C2* F = reinterpret_cast<const C2*>(F1);
     R t0r = 0, t0i = 0, t1r = 0, t1i = 0, t2r = 0, t2i = 0;
@@ -161,12 +160,7 @@ __global__ void __launch_bounds__(256) k_adj_gather(const R* __restrict__ F1, In
             a2r += v2.x * k1[a];
             a2i += v2.y * k1[a];
         }
-        const R z = ((R)d2 + R(b)) * s2;
-        R kb;
-        if constexpr (sizeof(R) == 4)
-            kb = __expf(beta * (__fsqrt_rn(fmaxf(R(1) - z * z, 0.0f)) - 1.0f));
-        else
-            kb = exp(beta * (sqrt(fmax(R(1) - z * z, 0.0)) - 1.0));
+        const R kb = es_one<R, W>((R)d2, b, beta, poly);
         t0r += a0r * kb;
         t0i += a0i * kb;
         t1r += a1r * kb;
@@ -190,14 +184,14 @@ __global__ void __launch_bounds__(256) k_adj_gather(const R* __restrict__ F1, In
 
 template <class R>
 fh_status launch_gather(fh_ctx* c, int W, const R* F1, const InstParams& ip, const GridGeom& gg, double beta,
-                        double lz, double* gx, double* gy, double* gw)
+                        const void* poly, double lz, double* gx, double* gy, double* gw)
 {
     const unsigned g = nblocks(ip.N, 256);
     switch (W) {
 #define FH_GATHER_CASE(w)                                                                                        \
     case w:                                                                                                     \
-        hipLaunchKernelGGL((k_adj_gather<R, w>), dim3(g), dim3(256), 0, c->stream, F1, ip, gg, (R)beta, lz, gx, \
-                           gy, gw);                                                                             \
+        hipLaunchKernelGGL((k_adj_gather<R, w>), dim3(g), dim3(256), 0, c->stream, F1, ip, gg, (R)beta,         \
+                           (const R*)poly, lz, gx, gy, gw);                                                     \
         break;
         FH_GATHER_CASE(2) FH_GATHER_CASE(3) FH_GATHER_CASE(4) FH_GATHER_CASE(5) FH_GATHER_CASE(6)
         FH_GATHER_CASE(7) FH_GATHER_CASE(8) FH_GATHER_CASE(9) FH_GATHER_CASE(10) FH_GATHER_CASE(11)
@@ -272,7 +266,7 @@ fh_status grid_vjp_impl(fh_ctx* c, const fh_quad* q, double lambda, double z, in
     FH_HIP(hipGetLastError());
     FH_TRY(fft_exec(c, fb, F1));
     timing_mark(c, 3);
-    FH_TRY(launch_gather<R>(c, gg.W, F1, ip, gg, pl.k.beta, lz, g_x, g_y, g_w));
+    FH_TRY(launch_gather<R>(c, gg.W, F1, ip, gg, pl.k.beta, pl.k.poly, lz, g_x, g_y, g_w));
     timing_mark(c, 4);
     timing_mark(c, 5);
     return FH_OK;

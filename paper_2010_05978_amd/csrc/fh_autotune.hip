@@ -98,7 +98,7 @@ fh_status fh_autotune_grid(fh_ctx* c, const fh_quad* q, double lambda, double z,
         for (double sigma : {2.0, 1.25})
             for (int method : {2, 1})
                 for (int tile : {16, 32})
-                    for (int P : {64, 128, 256, 512, 1024}) {
+                    for (int P : {0, 64, 256, 1024, 4096}) {  // 0: sized from the node count
                         fh_options o = saved;
                         o.sigma = sigma;
                         o.kernel_width = 0;

@@ -59,8 +59,15 @@ struct EsKernel {
     int w = 0;
     double beta = 0;
     double sigma = 2.0;
-    bool clamped = false;  // the tolerance needs a wider kernel than supported
+    bool clamped = false;        // the tolerance needs a wider kernel than supported
+    const void* poly = nullptr;  // device polynomial table (es_poly_attach) or null
 };
+
+// The kernel on one stencil is evaluated as w polynomials of degree
+// w + kPolyExtra - 1 in t = 2 d + w - 1, d in [-w/2, -w/2 + 1) the offset of
+// the first stencil cell: poly[j * w + a] is the coefficient of t^(deg - j)
+// for stencil index a, in the working precision.
+constexpr int kPolyExtra = 4;
 
 // 1/Phi(theta) for |theta| <= theta_max as a Chebyshev series in
 // s = 2 (theta/theta_max)^2 - 1 (Phi is even and entire).
@@ -173,6 +180,7 @@ struct fh_ctx {
     hipStream_t gstream = nullptr;  // private stream for graph capture/replay
     hipEvent_t gev_in = nullptr, gev_out = nullptr;
     std::map<std::tuple<int, long long, long long>, fh::InvPhiCheb> cheb_cache;
+    std::map<std::tuple<int, long long, int>, void*> poly_cache;  // (w, beta bits, precision)
     std::map<void*, size_t> owned;  // every hipMalloc'd block and its size
     double* bbox_dev = nullptr;      // bounding-box reduction scratch
     double* bbox_host = nullptr;     // pinned readback of the box
@@ -198,7 +206,8 @@ fh_status arena_reserve(fh_ctx* c, size_t bytes);
 fh_status gl_table(fh_ctx* c, int q, const double** dev);  // x[q] then w[q]
 void gl_host(int q, std::vector<double>& x, std::vector<double>& w);
 EsKernel choose_kernel(const fh_ctx* c, int n_hint);
-int pick_tile(const fh_ctx* c, int nf);
+void es_poly_attach(fh_ctx* c, EsKernel& k);
+int pick_tile(const fh_ctx* c, int nf, int w);
 int next_fft_size(int n, int multiple);
 double phi_hat(const EsKernel& k, double theta);
 fh_status iphi_table(fh_ctx* c, const EsKernel& k, int n, int nf, const double** dev);

@@ -179,6 +179,81 @@ EsKernel choose_kernel(const fh_ctx* c, int /*n_hint*/)
     return k;
 }
 
+// Kernel polynomials: Chebyshev interpolation of each stencil index's piece
+// phi(((t + 1)/2 + a - w/2) 2/w), t in [-1, 1], at deg + 1 Chebyshev points,
+// rewritten in monomials (well conditioned: |coefficients| <= 1 here).  The
+// pieces at the stencil edges carry the square-root branch point of phi at
+// |z| = 1, so their error levels off near e^-beta / 2, below the kernel's own
+// truncation.  Every piece is checked against phi on a fine grid; if one is
+// off by more than the kernel tolerance over w, k.poly stays null and the
+// kernels evaluate phi directly.
+void es_poly_attach(fh_ctx* c, EsKernel& k)
+{
+    k.poly = nullptr;
+    long long bb;
+    std::memcpy(&bb, &k.beta, sizeof(bb));
+    const auto key = std::make_tuple(k.w, bb, (int)c->prec);
+    auto it = c->poly_cache.find(key);
+    if (it != c->poly_cache.end()) {
+        k.poly = it->second;
+        return;
+    }
+    const int W = k.w, np = W + kPolyExtra, deg = np - 1;
+    double eps = c->tol * 0.1;
+    if (c->prec == FH_MIXED) eps = std::max(eps, 2e-8);
+    const double tol_abs = std::max(eps / W, 1e-14);
+    auto phi = [&](double z) { return std::exp(k.beta * (std::sqrt(std::max(1.0 - z * z, 0.0)) - 1.0)); };
+    // monomial coefficients of T_0..T_deg
+    std::vector<std::vector<double>> T(np, std::vector<double>(np, 0.0));
+    T[0][0] = 1.0;
+    if (np > 1) T[1][1] = 1.0;
+    for (int q = 2; q < np; ++q)
+        for (int i = 0; i < np; ++i) T[q][i] = (i > 0 ? 2.0 * T[q - 1][i - 1] : 0.0) - T[q - 2][i];
+    std::vector<double> table((size_t)np * W);
+    bool ok = true;
+    for (int a = 0; a < W && ok; ++a) {
+        auto f = [&](double t) { return phi(((t + 1.0) / 2.0 + a - 0.5 * W) * 2.0 / W); };
+        std::vector<double> fv(np), ch(np, 0.0), mono(np, 0.0);
+        for (int j = 0; j < np; ++j) fv[j] = f(std::cos(kPi * (j + 0.5) / np));
+        for (int q = 0; q < np; ++q) {
+            double sum = 0.0;
+            for (int j = 0; j < np; ++j) sum += fv[j] * std::cos(kPi * q * (j + 0.5) / np);
+            ch[q] = (q == 0 ? 1.0 : 2.0) * sum / np;
+        }
+        for (int q = 0; q < np; ++q)
+            for (int i = 0; i < np; ++i) mono[i] += ch[q] * T[q][i];
+        for (int s = 0; s <= 512 && ok; ++s) {
+            const double t = -1.0 + 2.0 * s / 512;
+            double v = 0.0;
+            for (int i = deg; i >= 0; --i) v = v * t + mono[i];
+            ok = std::fabs(v - f(t)) <= tol_abs;
+        }
+        for (int j = 0; j < np; ++j) table[(size_t)j * W + a] = mono[deg - j];
+    }
+    void* dev = nullptr;
+    if (ok) {
+        const size_t rs = c->prec == FH_FP64 ? sizeof(double) : sizeof(float);
+        if (dev_alloc(c, rs * table.size(), &dev) == FH_OK) {
+            fh_status st = FH_OK;
+            if (c->prec == FH_FP64) {
+                st = hipMemcpy(dev, table.data(), rs * table.size(), hipMemcpyHostToDevice) == hipSuccess
+                         ? FH_OK
+                         : FH_ERR_HIP;
+            } else {
+                std::vector<float> tf(table.begin(), table.end());
+                st = hipMemcpy(dev, tf.data(), rs * tf.size(), hipMemcpyHostToDevice) == hipSuccess ? FH_OK
+                                                                                                   : FH_ERR_HIP;
+            }
+            if (st != FH_OK) {
+                dev_free(c, dev);
+                dev = nullptr;
+            }
+        }
+    }
+    c->poly_cache[key] = dev;
+    k.poly = dev;
+}
+
 // Largest 2,3,5,7-smooth multiple search: smallest m >= n that is smooth,
 // even and divisible by `multiple`.
 static bool smooth7(long long m)
@@ -196,9 +271,17 @@ int next_fft_size(int n, int multiple)
     return (int)m;
 }
 
-int pick_tile(const fh_ctx* c, int nf)
+// Spread tile edge: the option when set, else 32 when a wavefront's padded
+// tile and kernel staging fit in 24 KB of LDS (six or more wavefronts per
+// CU), else 16; halved while the fine grid is under four tiles across.
+int pick_tile(const fh_ctx* c, int nf, int w)
 {
-    int T = c->opt.tile > 0 ? c->opt.tile : 32;
+    int T = c->opt.tile;
+    if (T <= 0) {
+        const size_t rs = c->prec == FH_FP64 ? 8 : 4;
+        const size_t L = 32 + (size_t)w - 1;
+        T = 2 * rs * L * L + rs * 64 * (2 * (size_t)w + 1) <= 24 * 1024 ? 32 : 16;
+    }
     while (T > 8 && nf < 4 * T) T /= 2;
     return T;
 }
@@ -589,7 +672,7 @@ fh_status fh_query_params(const fh_ctx* c, int32_t n, int32_t* width, double* be
     if (sigma) *sigma = k.sigma;
     if (nf) {
         int need = std::max((int)std::ceil(k.sigma * n), 2 * k.w);
-        int T = pick_tile(c, need);
+        int T = pick_tile(c, need, k.w);
         *nf = next_fft_size(need, T);
     }
     return FH_OK;

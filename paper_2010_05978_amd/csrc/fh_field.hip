@@ -61,6 +61,7 @@ fh_status t1_pipeline(fh_ctx* c, int B, const fh_quad* const* qs, const double* 
     }
     FH_ARG(Ntot < ((int64_t)1 << 31), FH_ERR_UNSUPPORTED, "%lld nodes in one call; at most 2^31 - 1",
            (long long)Ntot);
+    size_items(c, gg, Ntot);
     // hold only the reachable rows unless they cover most of the period
     const int rows = (max_span + gg.T - 1) / gg.T * gg.T;
     if (rows + gg.T < gg.nf2 && max_span > 0) {
@@ -108,7 +109,7 @@ fh_status t1_pipeline(fh_ctx* c, int B, const fh_quad* const* qs, const double* 
 
     auto run = [&]() -> fh_status {
         timing_mark(c, 0);
-        FH_TRY(run_spread<R>(c, inst[0], batched ? dinst : nullptr, B, Ntot, gg, sb, F, pl.k.beta));
+        FH_TRY(run_spread<R>(c, inst[0], batched ? dinst : nullptr, B, Ntot, gg, sb, F, pl.k.beta, pl.k.poly));
         FH_TRY(fft_exec(c, fa, F));
         hipLaunchKernelGGL((k_transpose_pad<R>), dim3(nblocks(n1, 32), nblocks(gg.nf2, 32), B), dim3(256), 0,
                            c->stream, F, Z, n1, gg.nf1, gg.nf2, gg.rows);
@@ -288,12 +289,14 @@ fh_status field_points_impl(fh_ctx* c, const fh_quad* q, double lambda, double z
     EsKernel k = choose_kernel(c, 0);
     FH_ARG(!k.clamped, FH_ERR_UNSUPPORTED, "tolerance %g needs a kernel wider than %d at sigma %g", c->tol, kMaxWidth,
            k.sigma);
+    es_poly_attach(c, k);
     const int T0 = c->opt.tile > 0 ? std::min(c->opt.tile, 32) : 16;
     T3Dim d1 = plan_t3_dim(sb[0], sb[1], tb[0], tb[1], lz, k, T0);
     T3Dim d2 = plan_t3_dim(sb[2], sb[3], tb[2], tb[3], lz, k, T0);
     FH_ARG((int64_t)d1.m * d2.m <= (int64_t)1 << 31, FH_ERR_UNSUPPORTED,
            "type-3 fine grid %d x %d too large (space-bandwidth product too big)", d1.m, d2.m);
-    FH_ARG(d1.nf <= 65535 && d2.nf <= 65535, FH_ERR_UNSUPPORTED, "type-3 spread grid too large");
+    FH_ARG(d1.nf <= 65535 && d2.nf <= 65535 && d1.m <= 65535 && d2.m <= 65535, FH_ERR_UNSUPPORTED,
+           "type-3 grid side above 65535");
     GridGeom gg;
     gg.T = T0;
     gg.W = k.w;
@@ -305,6 +308,7 @@ fh_status field_points_impl(fh_ctx* c, const fh_quad* q, double lambda, double z
     gg.rows = d2.nf;
     gg.wrap_y = 1;
     spread_defaults(c, gg);
+    size_items(c, gg, N);
     const int ntiles = gg.ntx * gg.nty;
 
     const double* ip1 = nullptr;
@@ -368,13 +372,13 @@ fh_status field_points_impl(fh_ctx* c, const fh_quad* q, double lambda, double z
     tp.ch2 = inv_phi_cheb_cached(c, k, d2.theta_max);
 
     timing_mark(c, 0);
-    FH_TRY(run_spread<R>(c, ip, nullptr, 1, N, gg, sbuf, fine, k.beta));
+    FH_TRY(run_spread<R>(c, ip, nullptr, 1, N, gg, sbuf, fine, k.beta, k.poly));
     hipLaunchKernelGGL((k_t3_precorrect<R>), dim3(nblocks(d1.m, 256), d2.m), dim3(256), 0, c->stream, fine, d1.nf,
                        d2.nf, up, d1.m, d2.m, ip1, ip2);
     FH_HIP(hipGetLastError());
     FH_TRY(fft_exec(c, fp, up));
     timing_mark(c, 3);
-    FH_TRY(launch_interp<R>(c, k.w, up, dxi, deta, M, k.beta, tp, nullptr, dout));
+    FH_TRY(launch_interp<R>(c, k.w, up, dxi, deta, M, k.beta, k.poly, tp, nullptr, dout));
     timing_mark(c, 4);
     timing_mark(c, 5);
     if (mem == FH_MEM_HOST) {

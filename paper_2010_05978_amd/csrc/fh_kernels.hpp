@@ -22,8 +22,11 @@ template <class R> struct V2;
 template <> struct V2<float> { using T = float2; };
 template <> struct V2<double> { using T = double2; };
 
-constexpr int kMaxSubPerTile = 512;  // work items per tile before items grow
+constexpr int kMaxSubPerTile = 2048;  // work items per tile before items grow
+constexpr int kMergeG = 16;           // slots summed per merge group
+constexpr int kMergeLevels = 2;       // 16 * 16 * 16 >= kMaxSubPerTile
 constexpr size_t kLdsBudget = 64 * 1024;
+constexpr size_t kCuLds = 160 * 1024;  // LDS per CU
 
 // --------------------------------------------------------- device helpers
 __device__ __forceinline__ int find_inst(const InstParams* t, int n, int64_t j)
@@ -69,9 +72,24 @@ __device__ __forceinline__ bool node_cell(const InstParams& ip, const GridGeom& 
     return ok;
 }
 
+// ES kernel values k[a] = phi((d + a) 2/W), a < W, for the first-cell offset
+// d in [-W/2, -W/2 + 1): by the polynomial table when there is one (uniform
+// coefficients, W independent Horner chains), else directly.
 template <class R, int W>
-__device__ __forceinline__ void es_weights(R d, R beta, R* k)
+__device__ __forceinline__ void es_weights(R d, R beta, const R* __restrict__ poly, R* k)
 {
+    if (poly) {
+        constexpr int NP = W + kPolyExtra;
+        const R t = R(2) * d + R(W - 1);
+#pragma unroll
+        for (int a = 0; a < W; ++a) k[a] = poly[a];
+#pragma unroll
+        for (int j = 1; j < NP; ++j) {
+#pragma unroll
+            for (int a = 0; a < W; ++a) k[a] = k[a] * t + poly[j * W + a];
+        }
+        return;
+    }
     const R s = R(2) / R(W);
 #pragma unroll
     for (int a = 0; a < W; ++a) {
@@ -82,6 +100,26 @@ __device__ __forceinline__ void es_weights(R d, R beta, R* k)
         else
             k[a] = exp(beta * (sqrt(fmax(q, 0.0)) - 1.0));
     }
+}
+
+// One kernel value phi((d + a) 2/W) (a may vary across lanes).
+template <class R, int W>
+__device__ __forceinline__ R es_one(R d, int a, R beta, const R* __restrict__ poly)
+{
+    if (poly) {
+        constexpr int NP = W + kPolyExtra;
+        const R t = R(2) * d + R(W - 1);
+        R v = poly[a];
+#pragma unroll
+        for (int j = 1; j < NP; ++j) v = v * t + poly[j * W + a];
+        return v;
+    }
+    const R z = (d + R(a)) * (R(2) / R(W));
+    const R q = R(1) - z * z;
+    if constexpr (sizeof(R) == 4)
+        return __expf(beta * (__fsqrt_rn(fmaxf(q, 0.0f)) - 1.0f));
+    else
+        return exp(beta * (sqrt(fmax(q, 0.0)) - 1.0));
 }
 
 __device__ __forceinline__ double cheb_inv_phi(const InvPhiCheb& ch, double theta)
@@ -204,66 +242,85 @@ __global__ void __launch_bounds__(kBinBlock) k_bin_count(InstParams p0, const In
     if (valid) rank[j] = base + __popcll(mine & ((1ull << lane) - 1ull));
 }
 
-// One block: exclusive scan of tile counts -> tile offsets, and the list of
-// spread work items (tile, [start, end)).  A tile's items hold at least P
-// points and at most kMaxSubPerTile items are made per tile, so a crowded
-// tile is spread by many CUs while the reduce stays short.
+// Points per work item of a tile holding c points: at least P, and large
+// enough that the tile makes at most kMaxSubPerTile items, so a crowded tile
+// is spread by many CUs while its slots stay few enough to merge.
+__host__ __device__ __forceinline__ int tile_item_points(int c, int P)
+{
+    return max(P, (c + kMaxSubPerTile - 1) / kMaxSubPerTile);
+}
+
+// One block: exclusive scan of tile counts -> tile offsets (points) and the
+// first work item and item count of every tile; the items themselves are
+// written by k_bin_place.
 __global__ void __launch_bounds__(1024) k_scan_tiles(const int* __restrict__ cnt, int ntiles, int P,
                                                      int* __restrict__ off, int* __restrict__ tsub,
-                                                     Sub* __restrict__ subs, int* __restrict__ nsub_out)
+                                                     int* __restrict__ nsub_out)
 {
-    __shared__ int sa[1024];
-    __shared__ int sb[1024];
-    const int tid = threadIdx.x, nt = blockDim.x;
-    const int chunk = (ntiles + nt - 1) / nt;
+    __shared__ int wa[16], wb[16];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int chunk = (ntiles + 1023) / 1024;
     const int t0 = min(ntiles, tid * chunk), t1 = min(ntiles, t0 + chunk);
     int a = 0, b = 0;
     for (int t = t0; t < t1; ++t) {
         const int c = cnt[t];
-        const int Pt = max(P, (c + kMaxSubPerTile - 1) / kMaxSubPerTile);
         a += c;
-        b += (c + Pt - 1) / Pt;
+        b += (c + tile_item_points(c, P) - 1) / tile_item_points(c, P);
     }
-    sa[tid] = a;
-    sb[tid] = b;
+    // inclusive scan within the wavefront, then over the 16 wavefront totals
+    int ia = a, ib = b;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int va = __shfl_up(ia, o), vb = __shfl_up(ib, o);
+        if (lane >= o) {
+            ia += va;
+            ib += vb;
+        }
+    }
+    if (lane == 63) {
+        wa[wv] = ia;
+        wb[wv] = ib;
+    }
     __syncthreads();
-    for (int o = 1; o < nt; o <<= 1) {
-        const int va = tid >= o ? sa[tid - o] : 0;
-        const int vb = tid >= o ? sb[tid - o] : 0;
-        __syncthreads();
-        sa[tid] += va;
-        sb[tid] += vb;
-        __syncthreads();
+    if (wv == 0) {
+        int xa = lane < 16 ? wa[lane] : 0, xb = lane < 16 ? wb[lane] : 0;
+#pragma unroll
+        for (int o = 1; o < 16; o <<= 1) {
+            const int va = __shfl_up(xa, o), vb = __shfl_up(xb, o);
+            if (lane >= o) {
+                xa += va;
+                xb += vb;
+            }
+        }
+        if (lane < 16) {
+            wa[lane] = xa;
+            wb[lane] = xb;
+        }
     }
-    int ea = sa[tid] - a, eb = sb[tid] - b;
+    __syncthreads();
+    int ea = ia - a + (wv > 0 ? wa[wv - 1] : 0);
+    int eb = ib - b + (wv > 0 ? wb[wv - 1] : 0);
     for (int t = t0; t < t1; ++t) {
         const int c = cnt[t];
-        const int Pt = max(P, (c + kMaxSubPerTile - 1) / kMaxSubPerTile);
-        const int ns = (c + Pt - 1) / Pt;
+        const int ns = (c + tile_item_points(c, P) - 1) / tile_item_points(c, P);
         off[t] = ea;
         tsub[2 * t] = eb;
         tsub[2 * t + 1] = ns;
-        for (int s = 0; s < ns; ++s) {
-            Sub w;
-            w.tile = t;
-            w.start = ea + s * Pt;
-            w.end = min(ea + (s + 1) * Pt, ea + c);
-            subs[eb + s] = w;
-        }
         ea += c;
         eb += ns;
     }
-    if (tid == nt - 1) *nsub_out = sb[nt - 1];
+    if (tid == 1023) *nsub_out = wb[15];
 }
 
 // Strength (FP64 phase in turns, reduced), stencil offsets, and the sorted
 // position of each node.
 template <class R>
 __global__ void __launch_bounds__(256) k_bin_place(InstParams p0, const InstParams* __restrict__ table, int ninst,
-                                                   int64_t Ntot, GridGeom gg, const int* __restrict__ off,
+                                                   int64_t Ntot, GridGeom gg, const int* __restrict__ cnt,
+                                                   const int* __restrict__ off, const int* __restrict__ tsub,
                                                    const int* __restrict__ rank, uint32_t* __restrict__ cell,
                                                    typename V2<R>::T* __restrict__ dd,
-                                                   typename V2<R>::T* __restrict__ cc)
+                                                   typename V2<R>::T* __restrict__ cc, Sub* __restrict__ subs)
 {
     const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (j >= Ntot) return;
@@ -279,7 +336,8 @@ __global__ void __launch_bounds__(256) k_bin_place(InstParams p0, const InstPara
     const double f = t - rint(t);
     double s, c;
     sincospi(2.0 * f, &s, &c);
-    const int pos = off[tile] + rank[j];
+    const int rk = rank[j];
+    const int pos = off[tile] + rk;
     cell[pos] = (uint32_t)l1 | ((uint32_t)l2 << 16);
     typename V2<R>::T dv, cv;
     dv.x = (R)d1;
@@ -288,20 +346,21 @@ __global__ void __launch_bounds__(256) k_bin_place(InstParams p0, const InstPara
     cv.y = (R)(w * s);
     dd[pos] = dv;
     cc[pos] = cv;
+    // the point that opens a work item of its tile writes the item
+    const int ct = cnt[tile];
+    const int Pt = tile_item_points(ct, gg.P);
+    if (rk % Pt == 0) {
+        Sub it;
+        it.tile = tile;
+        it.start = pos;
+        it.end = min(pos + Pt, off[tile] + ct);
+        subs[tsub[2 * tile] + rk / Pt] = it;
+    }
 }
 
 // ----------------------------------------------------------------- spread
 // Work item s covers the points [start, end) of one tile; its padded L x L
-// LDS tile (split re/im planes) is written to slot s.
-template <class R>
-__device__ __forceinline__ void store_slot(const R* sre, const R* sim, int LL, R* __restrict__ slot)
-{
-    for (int e = threadIdx.x; e < LL; e += blockDim.x) {
-        slot[e] = sre[e];
-        slot[LL + e] = sim[e];
-    }
-}
-
+// complex tile is written to slot s (interleaved re/im).
 template <class R>
 __device__ __forceinline__ void tile_origin(const Sub& sb, const GridGeom& gg, int tpi, int& ox, int& oy)
 {
@@ -312,13 +371,15 @@ __device__ __forceinline__ void tile_origin(const Sub& sb, const GridGeom& gg, i
     oy = ty * gg.T;
 }
 
-// Thread per point: each thread spreads whole points with LDS atomics.
+// Thread per point: the threads of a block spread whole points into one
+// shared LDS tile with atomics (order of same-cell additions unspecified).
 template <class R, int W>
 __global__ void __launch_bounds__(256) k_spread_thread(const Sub* __restrict__ subs, const int* __restrict__ nsub_ptr,
                                                        const uint32_t* __restrict__ cell,
                                                        const typename V2<R>::T* __restrict__ dd,
                                                        const typename V2<R>::T* __restrict__ cc,
-                                                       R* __restrict__ slots, GridGeom gg, int tpi, R beta)
+                                                       typename V2<R>::T* __restrict__ slots, GridGeom gg, int tpi,
+                                                       R beta, const R* __restrict__ poly)
 {
     extern __shared__ unsigned char smem_raw[];
     R* sre = reinterpret_cast<R*>(smem_raw);
@@ -341,8 +402,8 @@ __global__ void __launch_bounds__(256) k_spread_thread(const Sub* __restrict__ s
             const typename V2<R>::T dv = dd[p];
             const typename V2<R>::T cv = cc[p];
             R k1[W], k2[W];
-            es_weights<R, W>(dv.x, beta, k1);
-            es_weights<R, W>(dv.y, beta, k2);
+            es_weights<R, W>(dv.x, beta, poly, k1);
+            es_weights<R, W>(dv.y, beta, poly, k2);
 #pragma unroll
             for (int b = 0; b < W; ++b) {
                 const R vr = cv.x * k2[b], vi = cv.y * k2[b];
@@ -356,51 +417,73 @@ __global__ void __launch_bounds__(256) k_spread_thread(const Sub* __restrict__ s
             }
         }
         __syncthreads();
-        store_slot(sre, sim, LL, slots + (size_t)s * 2 * LL);
+        typename V2<R>::T* slot = slots + (size_t)s * LL;
+        for (int e = threadIdx.x; e < LL; e += blockDim.x) {
+            typename V2<R>::T v;
+            v.x = sre[e];
+            v.y = sim[e];
+            slot[e] = v;
+        }
         __syncthreads();
     }
 }
 
 // Add a run's register sums (lane (a, b) of pass pp holds stencil cell
-// (a, b) of the run's first cell) into the LDS tile and clear them.
+// (a, b) of the run's first cell c) into the wavefront's own LDS tile and
+// clear them.  The cells of one flush are distinct and the LDS operations of
+// one wavefront complete in issue order, so a plain read-add-write is exact.
 template <class R, int NPASS>
-__device__ __forceinline__ void flush_run(R* sre, R* sim, int L, int c1, int c2, const int* pa, const int* pb,
-                                          const bool* pv, R* accr, R* acci)
+__device__ __forceinline__ void flush_run(typename V2<R>::T* tile, int c, const int* po, const bool* pv, R* accr,
+                                          R* acci)
 {
-    if (c1 < 0) return;
+    if (c < 0) return;
 #pragma unroll
     for (int pp = 0; pp < NPASS; ++pp) {
         if (pv[pp]) {
-            const int idx = (c2 + pb[pp]) * L + c1 + pa[pp];
-            atomicAdd(sre + idx, accr[pp]);
-            atomicAdd(sim + idx, acci[pp]);
+            typename V2<R>::T v = tile[c + po[pp]];
+            v.x += accr[pp];
+            v.y += acci[pp];
+            tile[c + po[pp]] = v;
         }
         accr[pp] = R(0);
         acci[pp] = R(0);
     }
 }
 
-// Wavefront per point.  A wavefront loads 64 points and stages their 2W
-// kernel values in LDS; it then walks the points one at a time with its lanes
-// laid over the W x W stencil (ceil(W^2/64) passes), so the LDS atomics of one
-// instruction never share an address however tightly the points cluster (the
-// dilation rule crowds nodes near the origin).
-template <class R, int W>
-__global__ void __launch_bounds__(256) k_spread_wave(const Sub* __restrict__ subs, const int* __restrict__ nsub_ptr,
-                                                     const uint32_t* __restrict__ cell,
-                                                     const typename V2<R>::T* __restrict__ dd,
-                                                     const typename V2<R>::T* __restrict__ cc,
-                                                     R* __restrict__ slots, GridGeom gg, int tpi, R beta)
+// LDS order point: keeps the compiler from moving LDS accesses of this
+// wavefront across it (the hardware already completes them in order).
+__device__ __forceinline__ void wave_lds_order()
 {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Wavefront per work item, lanes over the stencil.  The wavefront owns its
+// LDS tile (no atomics: LDS float atomics serialise badly when points
+// cluster), loads 64 points at a time and stages their 2W kernel values in
+// LDS, then walks the points one by one with lane (a, b) holding stencil
+// cell (a, b) (ceil(W^2/64) passes).  Consecutive points with the same first
+// cell (nodes in spoke order share one for tens of points near the origin)
+// are summed in registers and added to the tile once.  The summation order
+// is fixed, so the spread is deterministic.
+template <class R, int W>
+__global__ void __launch_bounds__(64) k_spread_wave(const Sub* __restrict__ subs, const int* __restrict__ nsub_ptr,
+                                                    const uint32_t* __restrict__ cell,
+                                                    const typename V2<R>::T* __restrict__ dd,
+                                                    const typename V2<R>::T* __restrict__ cc,
+                                                    typename V2<R>::T* __restrict__ slots, GridGeom gg, int tpi,
+                                                    R beta, const R* __restrict__ poly)
+{
+    using C = typename V2<R>::T;
     constexpr int KS = 2 * W + 1;             // staging stride per point
     constexpr int NPASS = (W * W + 63) / 64;  // stencil passes per point
     extern __shared__ unsigned char smem_raw[];
-    R* sre = reinterpret_cast<R*>(smem_raw);
     const int L = gg.L, LL = L * L;
-    R* sim = sre + LL;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    R* kb = sim + LL + wv * 64 * KS;
-    int pa[NPASS], pb[NPASS];
+    C* tile = reinterpret_cast<C*>(smem_raw);
+    R* kb = reinterpret_cast<R*>(tile + LL);
+    const int lane = threadIdx.x;
+    int pa[NPASS], pb[NPASS], po[NPASS];
     bool pv[NPASS];
 #pragma unroll
     for (int p = 0; p < NPASS; ++p) {
@@ -408,64 +491,51 @@ __global__ void __launch_bounds__(256) k_spread_wave(const Sub* __restrict__ sub
         pv[p] = e < W * W;
         pa[p] = pv[p] ? e % W : 0;
         pb[p] = pv[p] ? e / W : 0;
+        po[p] = pb[p] * L + pa[p];
     }
     const int nsub = *nsub_ptr;
     for (int s = blockIdx.x; s < nsub; s += gridDim.x) {
         const Sub sb = subs[s];
         int ox, oy;
         tile_origin<R>(sb, gg, tpi, ox, oy);
-        for (int e = threadIdx.x; e < LL; e += blockDim.x) {
-            sre[e] = R(0);
-            sim[e] = R(0);
-        }
-        __syncthreads();
-        // run of consecutive points with the same first stencil cell: summed
-        // in registers and added to LDS once when the cell changes (nodes in
-        // spoke order often share a cell for tens of points, and same-address
-        // LDS atomics in back-to-back instructions stall the atomic pipeline)
-        int cur1 = -1, cur2 = -1;
+        const uint32_t org = (uint32_t)ox | ((uint32_t)oy << 16);
+        for (int e = lane; e < LL; e += 64) tile[e] = C{R(0), R(0)};
+        int cur = -1;
         R accr[NPASS], acci[NPASS];
 #pragma unroll
         for (int pp = 0; pp < NPASS; ++pp) accr[pp] = acci[pp] = R(0);
-        for (int base = sb.start + wv * 64; base < sb.end; base += nw * 64) {
+        for (int base = sb.start; base < sb.end; base += 64) {
             const int p = base + lane;
-            int l1 = 0, l2 = 0;
+            int cl = 0;
             R cr = R(0), ci = R(0);
             if (p < sb.end) {
-                const uint32_t cp = cell[p];
-                l1 = (int)(cp & 0xffffu) - ox;
-                l2 = (int)(cp >> 16) - oy;
-                const typename V2<R>::T dv = dd[p];
-                const typename V2<R>::T cv = cc[p];
+                // tile-relative first cell as an LDS index (x, y < T)
+                const uint32_t rel = cell[p] - org;
+                cl = (int)(rel >> 16) * L + (int)(rel & 0xffffu);
+                const C dv = dd[p];
+                const C cv = cc[p];
                 cr = cv.x;
                 ci = cv.y;
                 R k[W];
-                es_weights<R, W>(dv.x, beta, k);
+                es_weights<R, W>(dv.x, beta, poly, k);
 #pragma unroll
                 for (int a = 0; a < W; ++a) kb[lane * KS + a] = k[a];
-                es_weights<R, W>(dv.y, beta, k);
+                es_weights<R, W>(dv.y, beta, poly, k);
 #pragma unroll
                 for (int b = 0; b < W; ++b) kb[lane * KS + W + b] = k[b];
             }
-            // LDS traffic of one wavefront is processed in order; the fences
-            // keep the compiler from moving the staging reads above the writes.
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            wave_lds_order();
             const int np = min(64, sb.end - base);
             // four points per trip: their staging reads are issued together
             // so one LDS round trip is paid per four points, not per point
             constexpr int U = 4;
             for (int q0 = 0; q0 < np; q0 += U) {
                 R kv[U][NPASS], vr[U], vi[U];
-                int c1[U], c2[U];
-                bool qv[U];
+                int cq[U];
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
-                    qv[u] = q0 + u < np;
-                    const int q = qv[u] ? q0 + u : q0;
-                    c1[u] = lane_val(l1, q);
-                    c2[u] = lane_val(l2, q);
+                    const int q = min(q0 + u, np - 1);
+                    cq[u] = lane_val(cl, q);
                     vr[u] = lane_val(cr, q);
                     vi[u] = lane_val(ci, q);
                     const R* kq = kb + q * KS;
@@ -474,11 +544,10 @@ __global__ void __launch_bounds__(256) k_spread_wave(const Sub* __restrict__ sub
                 }
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
-                    if (!qv[u]) continue;
-                    if (c1[u] != cur1 || c2[u] != cur2) {
-                        flush_run<R, NPASS>(sre, sim, L, cur1, cur2, pa, pb, pv, accr, acci);
-                        cur1 = c1[u];
-                        cur2 = c2[u];
+                    if (q0 + u >= np) break;
+                    if (cq[u] != cur) {
+                        flush_run<R, NPASS>(tile, cur, po, pv, accr, acci);
+                        cur = cq[u];
                     }
 #pragma unroll
                     for (int pp = 0; pp < NPASS; ++pp) {
@@ -487,28 +556,75 @@ __global__ void __launch_bounds__(256) k_spread_wave(const Sub* __restrict__ sub
                     }
                 }
             }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            wave_lds_order();
         }
-        flush_run<R, NPASS>(sre, sim, L, cur1, cur2, pa, pb, pv, accr, acci);
-        __syncthreads();
-        store_slot(sre, sim, LL, slots + (size_t)s * 2 * LL);
-        __syncthreads();
+        flush_run<R, NPASS>(tile, cur, po, pv, accr, acci);
+        wave_lds_order();
+        C* slot = slots + (size_t)s * LL;
+        for (int e = lane; e < LL; e += 64) slot[e] = tile[e];
+        wave_lds_order();
     }
 }
 
 // ----------------------------------------------------------------- reduce
+// A tile with cnt work items is merged in levels: level l sums, for every
+// item r (its index within the tile) divisible by G^l, the slots r + k G^(l-1)
+// (k < G, inside the tile) into slot r.  A tile takes merge_levels(cnt)
+// levels, which leaves at most G heads, at stride G^levels, for the reduce.
+// Groups are disjoint within a level and the order of every sum is fixed.
+__host__ __device__ __forceinline__ int merge_levels(int cnt)
+{
+    int l = 0;
+    for (int span = kMergeG; cnt > span && l < kMergeLevels; span *= kMergeG) ++l;
+    return l;
+}
+
+template <class R>
+__global__ void __launch_bounds__(256) k_merge_slots(typename V2<R>::T* __restrict__ slots,
+                                                     const Sub* __restrict__ subs, const int* __restrict__ nsub_ptr,
+                                                     const int* __restrict__ tsub, int LL, int level)
+{
+    using C = typename V2<R>::T;
+    const int nsub = *nsub_ptr;
+    int stride = 1;
+    for (int l = 1; l < level; ++l) stride *= kMergeG;
+    const int span = stride * kMergeG;
+    for (int i = blockIdx.x; i < nsub; i += gridDim.x) {
+        const int t = subs[i].tile;
+        const int first = tsub[2 * t], cnt = tsub[2 * t + 1];
+        const int r = i - first;
+        if (merge_levels(cnt) < level || r % span != 0) continue;
+        const int nk = min(kMergeG, (cnt - r + stride - 1) / stride);
+        const size_t st = (size_t)stride * LL;
+        for (int e = threadIdx.x; e < LL; e += blockDim.x) {
+            C* sp = slots + (size_t)i * LL + e;
+            // all loads of the group in flight at once, then summed in order
+            C v[kMergeG];
+#pragma unroll
+            for (int k = 0; k < kMergeG; ++k) v[k] = k < nk ? sp[k * st] : C{R(0), R(0)};
+            C acc = v[0];
+#pragma unroll
+            for (int k = 1; k < kMergeG; ++k) {
+                acc.x += v[k].x;
+                acc.y += v[k].y;
+            }
+            sp[0] = acc;
+        }
+    }
+}
+
 // Fine-grid cell (gx, gy) of tile (tx, ty) is covered by the padded tiles of
 // (tx - dx, ty - dy) for every dx, dy >= 0 with i + dx T < L and j + dy T < L
 // (periodic in x, and in y when the window is the whole grid; a padded tile
-// reaches ceil((W-1)/T) tiles on).  Each thread sums, in work-item order, the
-// slots of those tiles at its cell and writes the cell: every cell of the
-// held rows is written, zeros included.
+// reaches ceil((W-1)/T) tiles on).  Each thread sums, in item order, the
+// merged slots of those tiles at its cell and writes the cell: every cell of
+// the held rows is written, zeros included.
 template <class R>
-__global__ void __launch_bounds__(256) k_reduce_tiles(const R* __restrict__ slots, const int* __restrict__ tsub,
-                                                      GridGeom gg, int tpi, R* __restrict__ F)
+__global__ void __launch_bounds__(256) k_reduce_tiles(const typename V2<R>::T* __restrict__ slots,
+                                                      const int* __restrict__ tsub, GridGeom gg, int tpi,
+                                                      R* __restrict__ F)
 {
+    using C = typename V2<R>::T;
     const int T = gg.T, TT = T * T;
     const int parts = (TT + 255) / 256;
     const int tx = blockIdx.x, ty = blockIdx.y / parts, part = blockIdx.y - ty * parts, b = blockIdx.z;
@@ -529,31 +645,30 @@ __global__ void __launch_bounds__(256) k_reduce_tiles(const R* __restrict__ slot
             const int lx = i + dx * T;
             const int t = b * tpi + sty * gg.ntx + stx;
             const int first = tsub[2 * t], cnt = tsub[2 * t + 1];
-            const R* sp = slots + (size_t)first * 2 * LL + ly * L + lx;
-            const size_t st = 2 * (size_t)LL;
+            int stride = 1;
+            for (int l = merge_levels(cnt); l > 0; --l) stride *= kMergeG;
+            const int heads = (cnt + stride - 1) / stride;
+            const size_t st = (size_t)stride * LL;
+            const C* sp = slots + (size_t)first * LL + ly * L + lx;
             // four independent (guarded) loads in flight per trip; the sum
             // order is fixed, so the result does not depend on scheduling
-            for (int k = 0; k < cnt; k += 4) {
-                R r[4], m[4];
+            for (int k = 0; k < heads; k += 4) {
+                C r[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) r[u] = k + u < heads ? sp[u * st] : C{R(0), R(0)};
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
-                    const bool ok = k + u < cnt;
-                    r[u] = ok ? sp[u * st] : R(0);
-                    m[u] = ok ? sp[u * st + LL] : R(0);
-                }
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    ar += r[u];
-                    ai += m[u];
+                    ar += r[u].x;
+                    ai += r[u].y;
                 }
                 sp += 4 * st;
             }
         }
     }
-    typename V2<R>::T v;
+    C v;
     v.x = ar;
     v.y = ai;
-    reinterpret_cast<typename V2<R>::T*>(F)[((size_t)b * gg.rows + ty * T + j) * gg.nf1 + tx * T + i] = v;
+    reinterpret_cast<C*>(F)[((size_t)b * gg.rows + ty * T + j) * gg.nf1 + tx * T + i] = v;
 }
 
 // --------------------------------------------------------- type-1 finish
@@ -693,68 +808,111 @@ struct T3Params {
     InvPhiCheb ch1, ch2;
 };
 
+// Lanes per target in the interpolation: one stencil row per lane.
+template <int W>
+constexpr int interp_group() { return W <= 8 ? 8 : (W <= 16 ? 16 : 32); }
+
+// Wavefront per 64 targets.  Lane l first handles target l of the chunk on
+// its own: stencil cell, the 2W kernel values (staged in LDS), and the
+// 1/Phi correction, chirp and 1/(i lambda z) factor.  The wavefront then
+// gathers in trips of 64/GS targets: GS lanes per target, lane r taking
+// stencil row r with all W loads in flight, summed over the group by a fixed
+// butterfly.  Lane l finally scales its target's sum and writes it.
 template <class R, int W>
-__global__ void __launch_bounds__(256) k_t3_interp(const R* __restrict__ G, const double* __restrict__ xi,
-                                                   const double* __restrict__ eta, int64_t M, R beta,
-                                                   T3Params tp, const int* __restrict__ perm, R* __restrict__ u)
+__global__ void __launch_bounds__(64) k_t3_interp(const R* __restrict__ G, const double* __restrict__ xi,
+                                                  const double* __restrict__ eta, int64_t M, R beta,
+                                                  const R* __restrict__ poly, T3Params tp, const int* __restrict__ perm,
+                                                  R* __restrict__ u)
 {
-    const int64_t ks = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (ks >= M) return;
-    const int64_t k = perm ? (int64_t)perm[ks] : ks;
-    const double X = xi[k], Y = eta[k];
-    int l1, l2;
-    double d1, d2;
-    bool ok1, ok2;
-    cell_of((X - tp.xic) * tp.g1, tp.m1, W, l1, d1, ok1);
-    cell_of((Y - tp.etac) * tp.g2, tp.m2, W, l2, d2, ok2);
-    R k1[W];
-    es_weights<R, W>((R)d1, beta, k1);
-    const typename V2<R>::T* Gv = reinterpret_cast<const typename V2<R>::T*>(G);
-    // one stencil row per trip: W gathers in flight, the row weight computed
-    // in the loop (a fully unrolled W x W gather spills at W = 11)
-    const R s2 = R(2) / R(W);
-    R sr = 0, si = 0;
-#pragma unroll 1
-    for (int b = 0; b < W; ++b) {
-        int row = l2 + b;
-        if (row >= tp.m2) row -= tp.m2;
-        const typename V2<R>::T* gr = Gv + (size_t)row * tp.m1;
-        R ar = 0, ai = 0;
+    using C = typename V2<R>::T;
+    constexpr int GS = interp_group<W>();
+    constexpr int NT = 64 / GS;
+    constexpr int KS = 2 * W + 1;
+    __shared__ R ks[64 * KS];
+    __shared__ uint32_t cs[64];
+    __shared__ C res[64];
+    const int lane = threadIdx.x, g = lane / GS, r = lane % GS;
+    const C* Gv = reinterpret_cast<const C*>(G);
+    for (int64_t base = blockIdx.x * (int64_t)64; base < M; base += (int64_t)gridDim.x * 64) {
+        const int64_t t = base + lane;
+        const bool live = t < M;
+        const int64_t k = live ? (perm ? (int64_t)perm[t] : t) : 0;
+        const double X = xi[k], Y = eta[k];
+        int l1, l2;
+        double d1, d2;
+        bool ok1, ok2;
+        cell_of((X - tp.xic) * tp.g1, tp.m1, W, l1, d1, ok1);
+        cell_of((Y - tp.etac) * tp.g2, tp.m2, W, l2, d2, ok2);
+        cs[lane] = (uint32_t)l1 | ((uint32_t)l2 << 16);
+        {
+            R kv[W];
+            es_weights<R, W>((R)d1, beta, poly, kv);
 #pragma unroll
-        for (int a = 0; a < W; ++a) {
-            int col = l1 + a;
-            if (col >= tp.m1) col -= tp.m1;
-            const typename V2<R>::T gv = gr[col];
-            ar += gv.x * k1[a];
-            ai += gv.y * k1[a];
+            for (int a = 0; a < W; ++a) ks[lane * KS + a] = kv[a];
+            es_weights<R, W>((R)d2, beta, poly, kv);
+#pragma unroll
+            for (int b = 0; b < W; ++b) ks[lane * KS + W + b] = kv[b];
         }
-        const R z = ((R)d2 + R(b)) * s2;
-        R kb;
-        if constexpr (sizeof(R) == 4)
-            kb = __expf(beta * (__fsqrt_rn(fmaxf(R(1) - z * z, 0.0f)) - 1.0f));
-        else
-            kb = exp(beta * (sqrt(fmax(R(1) - z * z, 0.0)) - 1.0));
-        sr += ar * kb;
-        si += ai * kb;
+        // output factor: 1/Phi correction times the target chirp over i lambda z
+        const double corr =
+            cheb_inv_phi(tp.ch1, (X - tp.xic) * tp.th1) * cheb_inv_phi(tp.ch2, (Y - tp.etac) * tp.th2);
+        const double ph = (X * X + Y * Y) * tp.inv2lz - (X * tp.Cx + Y * tp.Cy) * tp.invlz;
+        double sn, cn;
+        sincospi(2.0 * (ph - rint(ph)), &sn, &cn);
+        const double fr = sn * corr * tp.invlz, fi = -cn * corr * tp.invlz;
+        wave_lds_order();
+        const int nq = (int)min<int64_t>(64, M - base);
+        for (int j = 0; j < nq; j += NT) {
+            const int q = j + g;
+            R sr = R(0), si = R(0);
+            if (q < nq && r < W) {
+                const uint32_t cp = cs[q];
+                const int c1 = (int)(cp & 0xffffu);
+                int row = (int)(cp >> 16) + r;
+                if (row >= tp.m2) row -= tp.m2;
+                const C* gr = Gv + (size_t)row * tp.m1;
+                C gv[W];
+#pragma unroll
+                for (int a = 0; a < W; ++a) {
+                    int col = c1 + a;
+                    if (col >= tp.m1) col -= tp.m1;
+                    gv[a] = gr[col];
+                }
+                const R* kq = ks + q * KS;
+#pragma unroll
+                for (int a = 0; a < W; ++a) {
+                    sr += gv[a].x * kq[a];
+                    si += gv[a].y * kq[a];
+                }
+                const R ky = kq[W + r];
+                sr *= ky;
+                si *= ky;
+            }
+#pragma unroll
+            for (int off = GS / 2; off > 0; off >>= 1) {
+                sr += __shfl_xor(sr, off, GS);
+                si += __shfl_xor(si, off, GS);
+            }
+            if (r == 0 && q < nq) res[q] = C{sr, si};
+        }
+        wave_lds_order();
+        if (live) {
+            const C v = res[lane];
+            double re = (double)v.x * fr - (double)v.y * fi;
+            double im = (double)v.x * fi + (double)v.y * fr;
+            if (!(ok1 && ok2)) {
+                re = __builtin_nan("");
+                im = __builtin_nan("");
+            }
+            if (tp.occ) {
+                re = 1.0 - re;
+                im = -im;
+            }
+            u[2 * k] = (R)re;
+            u[2 * k + 1] = (R)im;
+        }
+        wave_lds_order();
     }
-    const double corr = cheb_inv_phi(tp.ch1, (X - tp.xic) * tp.th1) * cheb_inv_phi(tp.ch2, (Y - tp.etac) * tp.th2);
-    const double vr = (double)sr * corr, vi = (double)si * corr;
-    const double t = (X * X + Y * Y) * tp.inv2lz - (X * tp.Cx + Y * tp.Cy) * tp.invlz;
-    const double f = t - rint(t);
-    double s, c;
-    sincospi(2.0 * f, &s, &c);
-    double re = (s * vr + c * vi) * tp.invlz;
-    double im = (s * vi - c * vr) * tp.invlz;
-    if (!(ok1 && ok2)) {
-        re = __builtin_nan("");
-        im = __builtin_nan("");
-    }
-    if (tp.occ) {
-        re = 1.0 - re;
-        im = -im;
-    }
-    u[2 * k] = (R)re;
-    u[2 * k + 1] = (R)im;
 }
 
 // ---------------------------------------------------------------- bbox
@@ -824,31 +982,38 @@ __global__ void __launch_bounds__(256) k_bbox_final(const double* __restrict__ p
 // ------------------------------------------------------- launch helpers
 template <class R, int W>
 void launch_spread_w(fh_ctx* c, unsigned grid, const Sub* subs, const int* nsub, const uint32_t* cell,
-                     const void* dd, const void* cc, R* slots, const GridGeom& gg, int tpi, double beta)
+                     const void* dd, const void* cc, typename V2<R>::T* slots, const GridGeom& gg, int tpi,
+                     double beta, const void* poly)
 {
-    const size_t tile = 2 * sizeof(R) * (size_t)gg.L * gg.L;
+    using C2 = typename V2<R>::T;
+    const size_t tile = sizeof(C2) * (size_t)gg.L * gg.L;
     if (gg.method == 1) {
         hipLaunchKernelGGL((k_spread_thread<R, W>), dim3(grid), dim3(256), tile, c->stream, subs, nsub, cell,
-                           (const typename V2<R>::T*)dd, (const typename V2<R>::T*)cc, slots, gg, tpi, (R)beta);
+                           (const C2*)dd, (const C2*)cc, slots, gg, tpi, (R)beta, (const R*)poly);
         return;
     }
-    const size_t per_wave = sizeof(R) * 64 * (2 * W + 1);
-    int nw = 4;
-    while (nw > 1 && tile + nw * per_wave > kLdsBudget) --nw;
-    hipLaunchKernelGGL((k_spread_wave<R, W>), dim3(grid), dim3(64 * nw), tile + nw * per_wave, c->stream, subs,
-                       nsub, cell, (const typename V2<R>::T*)dd, (const typename V2<R>::T*)cc, slots, gg, tpi,
-                       (R)beta);
+    const size_t staging = sizeof(R) * 64 * (2 * W + 1);
+    hipLaunchKernelGGL((k_spread_wave<R, W>), dim3(grid), dim3(64), tile + staging, c->stream, subs, nsub, cell,
+                       (const C2*)dd, (const C2*)cc, slots, gg, tpi, (R)beta, (const R*)poly);
+}
+
+// LDS bytes of one spread block.
+inline size_t spread_lds(const GridGeom& gg, size_t rsize)
+{
+    const size_t tile = 2 * rsize * (size_t)gg.L * gg.L;
+    return gg.method == 1 ? tile : tile + rsize * 64 * (2 * gg.W + 1);
 }
 
 template <class R>
 fh_status launch_spread(fh_ctx* c, unsigned grid, const Sub* subs, const int* nsub, const uint32_t* cell,
-                        const void* dd, const void* cc, R* slots, const GridGeom& gg, int tpi, double beta)
+                        const void* dd, const void* cc, typename V2<R>::T* slots, const GridGeom& gg, int tpi,
+                        double beta, const void* poly)
 {
-    FH_ARG(2 * sizeof(R) * (size_t)gg.L * gg.L + sizeof(R) * 64 * (2 * gg.W + 1) <= kLdsBudget,
-           FH_ERR_UNSUPPORTED, "spread tile %d with width %d exceeds the LDS budget", gg.T, gg.W);
+    FH_ARG(spread_lds(gg, sizeof(R)) <= kLdsBudget, FH_ERR_UNSUPPORTED,
+           "spread tile %d with width %d exceeds the LDS budget", gg.T, gg.W);
     switch (gg.W) {
 #define FH_SPREAD_CASE(w) \
-    case w: launch_spread_w<R, w>(c, grid, subs, nsub, cell, dd, cc, slots, gg, tpi, beta); break;
+    case w: launch_spread_w<R, w>(c, grid, subs, nsub, cell, dd, cc, slots, gg, tpi, beta, poly); break;
         FH_SPREAD_CASE(2) FH_SPREAD_CASE(3) FH_SPREAD_CASE(4) FH_SPREAD_CASE(5) FH_SPREAD_CASE(6)
         FH_SPREAD_CASE(7) FH_SPREAD_CASE(8) FH_SPREAD_CASE(9) FH_SPREAD_CASE(10) FH_SPREAD_CASE(11)
         FH_SPREAD_CASE(12) FH_SPREAD_CASE(13) FH_SPREAD_CASE(14) FH_SPREAD_CASE(15) FH_SPREAD_CASE(16)
@@ -862,14 +1027,13 @@ fh_status launch_spread(fh_ctx* c, unsigned grid, const Sub* subs, const int* ns
 
 template <class R>
 fh_status launch_interp(fh_ctx* c, int W, const R* G, const double* xi, const double* eta, int64_t M,
-                        double beta, const T3Params& tp, const int* perm, R* u)
+                        double beta, const void* poly, const T3Params& tp, const int* perm, R* u)
 {
-    const unsigned g = nblocks(M, 256);
     switch (W) {
 #define FH_INTERP_CASE(w)                                                                           \
     case w:                                                                                        \
-        hipLaunchKernelGGL((k_t3_interp<R, w>), dim3(g), dim3(256), 0, c->stream, G, xi, eta, M, (R)beta, \
-                           tp, perm, u);                                                           \
+        hipLaunchKernelGGL((k_t3_interp<R, w>), dim3(std::min<int64_t>(nblocks(M, 64), 1 << 20)), dim3(64), 0, \
+                           c->stream, G, xi, eta, M, (R)beta, (const R*)poly, tp, perm, u);          \
         break;
         FH_INTERP_CASE(2) FH_INTERP_CASE(3) FH_INTERP_CASE(4) FH_INTERP_CASE(5) FH_INTERP_CASE(6)
         FH_INTERP_CASE(7) FH_INTERP_CASE(8) FH_INTERP_CASE(9) FH_INTERP_CASE(10) FH_INTERP_CASE(11)
@@ -933,7 +1097,7 @@ SpreadBufs spread_carve(fh_ctx* c, int64_t Ntot, const GridGeom& gg, int ntiles_
 // Bin, spread into slots, and reduce into F (B instances x rows x nf1).
 template <class R>
 fh_status run_spread(fh_ctx* c, const InstParams& p0, const InstParams* table, int ninst, int64_t Ntot,
-                     const GridGeom& gg, const SpreadBufs& b, R* F, double beta)
+                     const GridGeom& gg, const SpreadBufs& b, R* F, double beta, const void* poly)
 {
     const int tpi = gg.ntx * gg.nty;
     const int ntiles_total = tpi * ninst;
@@ -944,22 +1108,36 @@ fh_status run_spread(fh_ctx* c, const InstParams& p0, const InstParams* table, i
                            gg, b.cnt, b.rank);
     }
     hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, c->stream, b.cnt, ntiles_total, gg.P, b.off, b.tsub,
-                       b.subs, b.nsub);
+                       b.nsub);
     if (Ntot > 0) {
         hipLaunchKernelGGL((k_bin_place<R>), dim3(nblocks(Ntot, 256)), dim3(256), 0, c->stream, p0, table, ninst,
-                           Ntot, gg, b.off, b.rank, b.cell, (typename V2<R>::T*)b.dd, (typename V2<R>::T*)b.cc);
+                           Ntot, gg, b.cnt, b.off, b.tsub, b.rank, b.cell, (typename V2<R>::T*)b.dd,
+                           (typename V2<R>::T*)b.cc, b.subs);
     }
     FH_HIP(hipGetLastError());
     timing_mark(c, 1);
     if (Ntot > 0) {
-        const unsigned grid =
-            (unsigned)std::max<int64_t>(1, std::min<int64_t>(b.max_sub, (int64_t)c->cu_count * 8));
-        FH_TRY(launch_spread<R>(c, grid, b.subs, b.nsub, b.cell, b.dd, b.cc, (R*)b.slots, gg, tpi, beta));
+        // one block per work item up to a few waves of the whole chip
+        // (wavefront blocks: as many as fit in LDS, at most 32 per CU)
+        const int64_t per_cu = gg.method == 1 ? 8 : std::min<int64_t>(32, kCuLds / spread_lds(gg, sizeof(R)));
+        const unsigned grid = (unsigned)std::max<int64_t>(
+            1, std::min<int64_t>(b.max_sub, (int64_t)c->cu_count * std::max<int64_t>(1, per_cu) * 4));
+        FH_TRY(launch_spread<R>(c, grid, b.subs, b.nsub, b.cell, b.dd, b.cc, (typename V2<R>::T*)b.slots, gg, tpi,
+                                beta, poly));
+    }
+    if (Ntot > 0) {
+        const int64_t LL = (int64_t)gg.L * gg.L;
+        const unsigned mgrid =
+            (unsigned)std::max<int64_t>(1, std::min<int64_t>(b.max_sub, (int64_t)c->cu_count * 16));
+        for (int level = 1; level <= kMergeLevels; ++level)
+            hipLaunchKernelGGL((k_merge_slots<R>), dim3(mgrid), dim3(256), 0, c->stream,
+                               (typename V2<R>::T*)b.slots, b.subs, b.nsub, b.tsub, (int)LL, level);
+        FH_HIP(hipGetLastError());
     }
     timing_mark(c, 2);
     const int parts = (gg.T * gg.T + 255) / 256;
     hipLaunchKernelGGL((k_reduce_tiles<R>), dim3(gg.ntx, gg.nty * parts, ninst), dim3(256), 0, c->stream,
-                       (const R*)b.slots, b.tsub, gg, tpi, F);
+                       (const typename V2<R>::T*)b.slots, b.tsub, gg, tpi, F);
     FH_HIP(hipGetLastError());
     return FH_OK;
 }
@@ -982,24 +1160,38 @@ fh_status check_grid(int n1, int n2, double h1, double h2, double xc, double yc)
     return FH_OK;
 }
 
-// Spread method and work-item size: the wavefront-per-point spread is the
-// default (robust to the dense clusters of dilation rules); small work items
-// spread one crowded tile over many CUs.
+// Spread method: the wavefront spread is the default (robust to the dense
+// clusters of dilation rules).  The work-item size is set per call.
 void spread_defaults(const fh_ctx* c, GridGeom& g)
 {
     g.method = c->opt.spread_method > 0 ? c->opt.spread_method : 2;
-    g.P = c->opt.max_subproblem > 0 ? c->opt.max_subproblem : 256;
+    g.P = c->opt.max_subproblem > 0 ? c->opt.max_subproblem : 0;
+}
+
+// Points per work item for Ntot nodes: the option when set, else enough for
+// about 32 work items per CU (at least 64 points): small rules then spread
+// over the whole chip, and large batches do not pay one slot per few hundred
+// points.  A tile's items still hold at least count / kMaxSubPerTile points.
+void size_items(const fh_ctx* c, GridGeom& g, int64_t Ntot)
+{
+    if (c->opt.max_subproblem > 0) {
+        g.P = c->opt.max_subproblem;
+        return;
+    }
+    const int64_t target = (int64_t)c->cu_count * 32;
+    g.P = (int)std::min<int64_t>(1 << 24, std::max<int64_t>(64, (Ntot + target - 1) / target));
 }
 
 // Type-1 geometry for an n1 x n2 grid; the row window is set per call.
-T1Plan plan_t1(const fh_ctx* c, int n1, int n2)
+T1Plan plan_t1(fh_ctx* c, int n1, int n2)
 {
     T1Plan p;
     p.k = choose_kernel(c, std::max(n1, n2));
+    if (!p.k.clamped) es_poly_attach(c, p.k);
     const int W = p.k.w;
     const int need1 = std::max((int)std::ceil(p.k.sigma * n1), 2 * W);
     const int need2 = std::max((int)std::ceil(p.k.sigma * n2), 2 * W);
-    int T = pick_tile(c, std::min(need1, need2));
+    int T = pick_tile(c, std::min(need1, need2), W);
     if (c->prec == FH_FP64 && T > 32) T = 32;
     GridGeom& g = p.gg;
     g.T = T;
