@@ -82,7 +82,9 @@ typedef struct fh_options {
                              * larger items); 0: about 32 items per CU      */
     int32_t spread_method;  /* 1: thread per point, shared LDS tile with     *
                              * atomics; 2: wavefront per work item, lanes    *
-                             * over the stencil, private LDS tile            */
+                             * over the stencil, private LDS tile updated    *
+                             * by read-add-write; 3: as 2, updated by LDS    *
+                             * atomics (both deterministic)                  */
 } fh_options;
 
 /* ---------------------------------------------------------------- context */
@@ -161,6 +163,12 @@ fh_status fh_quad_export(const fh_quad* q, double* x, double* y, double* w, fh_m
 /* Device pointers of the rule's arrays (owned by the object). */
 fh_status fh_quad_device_ptrs(const fh_quad* q, const double** x, const double** y,
                               const double** w);
+/* A rule may be passed to any context on the same device.  Its arrays are
+ * written on the stream of the context that made it; a call on another
+ * stream must be ordered after that (e.g. with an event), and
+ * fh_quad_destroy (which hands the memory back to the making context, to be
+ * reused on its stream) must come after every call reading the rule has been
+ * ordered before that stream's later work. */
 fh_status fh_quad_destroy(fh_quad* q);
 
 /* ------------------------------------------------------------------ fields */

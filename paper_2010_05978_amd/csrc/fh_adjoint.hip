@@ -379,7 +379,7 @@ fh_status fh_field_grid_vjp(fh_ctx* c, const fh_quad* q, double lambda, double z
 {
     try {
         FH_ARG(c && q, FH_ERR_INVALID_ARG, "NULL argument");
-        FH_ARG(q->ctx == c, FH_ERR_INVALID_ARG, "quadrature belongs to another context");
+        FH_ARG(q->ctx->device == c->device, FH_ERR_INVALID_ARG, "quadrature lives on another device");
         FH_ARG(q->N == 0 || (g_u && g_x && g_y && g_w), FH_ERR_INVALID_ARG, "NULL array");
         FH_TRY(check_lz(lambda, z));
         FH_TRY(check_grid(n1, n2, h1, h2, xc, yc));

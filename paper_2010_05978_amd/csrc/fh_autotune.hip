@@ -73,7 +73,7 @@ fh_status fh_autotune_grid(fh_ctx* c, const fh_quad* q, double lambda, double z,
 {
     try {
         FH_ARG(c && q && best, FH_ERR_INVALID_ARG, "NULL argument");
-        FH_ARG(q->ctx == c, FH_ERR_INVALID_ARG, "quadrature belongs to another context");
+        FH_ARG(q->ctx->device == c->device, FH_ERR_INVALID_ARG, "quadrature lives on another device");
         FH_ARG(n1 > 0 && n2 > 0 && n1 % 2 == 0 && n2 % 2 == 0, FH_ERR_ODD_GRID, "grid sizes must be even");
         FH_HIP(hipSetDevice(c->device));
         const std::string key = tune_key(c, n1, n2, q->N);
@@ -96,7 +96,7 @@ fh_status fh_autotune_grid(fh_ctx* c, const fh_quad* q, double lambda, double z,
         fh_options best_o = saved;
         fh_status st = FH_OK;
         for (double sigma : {2.0, 1.25})
-            for (int method : {2, 1})
+            for (int method : {2, 3, 1})
                 for (int tile : {16, 32})
                     for (int P : {0, 64, 256, 1024, 4096}) {  // 0: sized from the node count
                         fh_options o = saved;

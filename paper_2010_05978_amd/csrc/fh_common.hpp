@@ -69,6 +69,15 @@ struct EsKernel {
 // for stencil index a, in the working precision.
 constexpr int kPolyExtra = 4;
 
+// Wavefront spread staging: per point its 2w kernel values and its strength
+// (2 reals), for 64 points plus one trip of padding so a trip of points
+// never needs a clamped index.
+inline int spread_trip(size_t rsize) { return rsize == 8 ? 4 : 8; }
+inline size_t spread_staging_bytes(int w, size_t rsize)
+{
+    return rsize * (size_t)(64 + spread_trip(rsize)) * (2 * (size_t)w + 2);
+}
+
 // 1/Phi(theta) for |theta| <= theta_max as a Chebyshev series in
 // s = 2 (theta/theta_max)^2 - 1 (Phi is even and entire).
 constexpr int kMaxCheb = 96;

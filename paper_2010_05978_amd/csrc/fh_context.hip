@@ -280,7 +280,7 @@ int pick_tile(const fh_ctx* c, int nf, int w)
     if (T <= 0) {
         const size_t rs = c->prec == FH_FP64 ? 8 : 4;
         const size_t L = 32 + (size_t)w - 1;
-        T = 2 * rs * L * L + rs * 64 * (2 * (size_t)w + 1) <= 24 * 1024 ? 32 : 16;
+        T = 2 * rs * L * L + spread_staging_bytes(w, rs) <= 24 * 1024 ? 32 : 16;
     }
     while (T > 8 && nf < 4 * T) T /= 2;
     return T;
@@ -570,8 +570,8 @@ static fh_status check_options(const fh_options* o)
     FH_ARG(o->tile == 0 || o->tile == 8 || o->tile == 16 || o->tile == 32 || o->tile == 64,
            FH_ERR_INVALID_ARG, "tile must be 0, 8, 16, 32 or 64");
     FH_ARG(o->max_subproblem >= 0, FH_ERR_INVALID_ARG, "max_subproblem must be >= 0");
-    FH_ARG(o->spread_method >= 0 && o->spread_method <= 2, FH_ERR_INVALID_ARG,
-           "spread_method must be 0, 1 or 2");
+    FH_ARG(o->spread_method >= 0 && o->spread_method <= 3, FH_ERR_INVALID_ARG,
+           "spread_method must be 0, 1, 2 or 3");
     return FH_OK;
 }
 

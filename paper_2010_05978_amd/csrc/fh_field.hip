@@ -464,7 +464,7 @@ fh_status fh_field_grid(fh_ctx* c, const fh_quad* q, double lambda, double z, in
 {
     try {
         FH_ARG(c && q && u, FH_ERR_INVALID_ARG, "NULL argument");
-        FH_ARG(q->ctx == c, FH_ERR_INVALID_ARG, "quadrature belongs to another context");
+        FH_ARG(q->ctx->device == c->device, FH_ERR_INVALID_ARG, "quadrature lives on another device");
         FH_ARG(mem == FH_MEM_HOST || mem == FH_MEM_DEVICE, FH_ERR_INVALID_ARG, "bad memspace");
         FH_TRY(check_lz(lambda, z));
         FH_TRY(check_grid(n1, n2, h1, h2, xc, yc));
@@ -484,7 +484,7 @@ fh_status fh_field_points(fh_ctx* c, const fh_quad* q, double lambda, double z, 
 {
     try {
         FH_ARG(c && q, FH_ERR_INVALID_ARG, "NULL argument");
-        FH_ARG(q->ctx == c, FH_ERR_INVALID_ARG, "quadrature belongs to another context");
+        FH_ARG(q->ctx->device == c->device, FH_ERR_INVALID_ARG, "quadrature lives on another device");
         FH_ARG(M >= 0, FH_ERR_INVALID_ARG, "M must be >= 0");
         FH_ARG(M == 0 || (xi && eta && u), FH_ERR_INVALID_ARG, "NULL target or output array");
         FH_ARG(mem == FH_MEM_HOST || mem == FH_MEM_DEVICE, FH_ERR_INVALID_ARG, "bad memspace");
@@ -508,7 +508,7 @@ fh_status fh_field_grid_batch(fh_ctx* c, int32_t B, const fh_quad* const* q, con
         FH_ARG(B >= 1, FH_ERR_INVALID_ARG, "B must be >= 1");
         FH_TRY(check_grid(n1, n2, h1, h2, xc, yc));
         for (int b = 0; b < B; ++b) {
-            FH_ARG(q[b] && q[b]->ctx == c, FH_ERR_INVALID_ARG, "quadrature %d NULL or from another context", b);
+            FH_ARG(q[b] && q[b]->ctx->device == c->device, FH_ERR_INVALID_ARG, "quadrature %d NULL or on another device", b);
             FH_TRY(check_lz(lambda[b], z[b]));
         }
         FH_HIP(hipSetDevice(c->device));

@@ -431,8 +431,10 @@ __global__ void __launch_bounds__(256) k_spread_thread(const Sub* __restrict__ s
 // Add a run's register sums (lane (a, b) of pass pp holds stencil cell
 // (a, b) of the run's first cell c) into the wavefront's own LDS tile and
 // clear them.  The cells of one flush are distinct and the LDS operations of
-// one wavefront complete in issue order, so a plain read-add-write is exact.
-template <class R, int NPASS>
+// one wavefront complete in issue order, so either a plain read-add-write
+// (waits for the read) or non-returning LDS atomics (no wait, processed in
+// order) give the same, deterministic sums.
+template <class R, int NPASS, bool ATOMIC>
 __device__ __forceinline__ void flush_run(typename V2<R>::T* tile, int c, const int* po, const bool* pv, R* accr,
                                           R* acci)
 {
@@ -440,13 +442,18 @@ __device__ __forceinline__ void flush_run(typename V2<R>::T* tile, int c, const 
 #pragma unroll
     for (int pp = 0; pp < NPASS; ++pp) {
         if (pv[pp]) {
-            typename V2<R>::T v = tile[c + po[pp]];
-            v.x += accr[pp];
-            v.y += acci[pp];
-            tile[c + po[pp]] = v;
+            typename V2<R>::T* e = tile + c + po[pp];
+            if constexpr (ATOMIC) {
+                // no return value: the wavefront does not wait for the LDS
+                atomicAdd(&e->x, accr[pp]);
+                atomicAdd(&e->y, acci[pp]);
+            } else {
+                typename V2<R>::T v = *e;
+                v.x += accr[pp];
+                v.y += acci[pp];
+                *e = v;
+            }
         }
-        accr[pp] = R(0);
-        acci[pp] = R(0);
     }
 }
 
@@ -460,14 +467,17 @@ __device__ __forceinline__ void wave_lds_order()
 }
 
 // Wavefront per work item, lanes over the stencil.  The wavefront owns its
-// LDS tile (no atomics: LDS float atomics serialise badly when points
-// cluster), loads 64 points at a time and stages their 2W kernel values in
-// LDS, then walks the points one by one with lane (a, b) holding stencil
-// cell (a, b) (ceil(W^2/64) passes).  Consecutive points with the same first
-// cell (nodes in spoke order share one for tens of points near the origin)
-// are summed in registers and added to the tile once.  The summation order
-// is fixed, so the spread is deterministic.
-template <class R, int W>
+// LDS tile (no sharing: LDS float atomics serialise badly when points
+// cluster), loads 64 points at a time and stages their 2W kernel values and
+// strength in LDS, then walks the points one by one with lane (a, b) holding
+// stencil cell (a, b) (ceil(W^2/64) passes).  Consecutive points with the
+// same first cell (nodes in spoke order share one for tens of points near
+// the origin) are summed in registers and added to the tile once.  With few
+// wavefronts per SIMD every instruction of the point loop costs its issue
+// slot, so the loop is kept to the arithmetic, one lane read for the cell
+// and LDS reads at fixed offsets.  The summation order is fixed, so the
+// spread is deterministic.
+template <class R, int W, bool ATOMIC>
 __global__ void __launch_bounds__(64) k_spread_wave(const Sub* __restrict__ subs, const int* __restrict__ nsub_ptr,
                                                     const uint32_t* __restrict__ cell,
                                                     const typename V2<R>::T* __restrict__ dd,
@@ -476,8 +486,9 @@ __global__ void __launch_bounds__(64) k_spread_wave(const Sub* __restrict__ subs
                                                     R beta, const R* __restrict__ poly)
 {
     using C = typename V2<R>::T;
-    constexpr int KS = 2 * W + 1;             // staging stride per point
+    constexpr int KS = 2 * W + 2;             // staged reals per point
     constexpr int NPASS = (W * W + 63) / 64;  // stencil passes per point
+    constexpr int U = sizeof(R) == 8 ? 4 : 8; // points per trip (spread_trip)
     extern __shared__ unsigned char smem_raw[];
     const int L = gg.L, LL = L * L;
     C* tile = reinterpret_cast<C*>(smem_raw);
@@ -507,15 +518,12 @@ __global__ void __launch_bounds__(64) k_spread_wave(const Sub* __restrict__ subs
         for (int base = sb.start; base < sb.end; base += 64) {
             const int p = base + lane;
             int cl = 0;
-            R cr = R(0), ci = R(0);
             if (p < sb.end) {
                 // tile-relative first cell as an LDS index (x, y < T)
                 const uint32_t rel = cell[p] - org;
                 cl = (int)(rel >> 16) * L + (int)(rel & 0xffffu);
                 const C dv = dd[p];
                 const C cv = cc[p];
-                cr = cv.x;
-                ci = cv.y;
                 R k[W];
                 es_weights<R, W>(dv.x, beta, poly, k);
 #pragma unroll
@@ -523,42 +531,48 @@ __global__ void __launch_bounds__(64) k_spread_wave(const Sub* __restrict__ subs
                 es_weights<R, W>(dv.y, beta, poly, k);
 #pragma unroll
                 for (int b = 0; b < W; ++b) kb[lane * KS + W + b] = k[b];
+                kb[lane * KS + 2 * W] = cv.x;
+                kb[lane * KS + 2 * W + 1] = cv.y;
             }
             wave_lds_order();
             const int np = min(64, sb.end - base);
-            // four points per trip: their staging reads are issued together
-            // so one LDS round trip is paid per four points, not per point
-            constexpr int U = 4;
             for (int q0 = 0; q0 < np; q0 += U) {
+                // all LDS reads of the trip first (fixed offsets from one base)
                 R kv[U][NPASS], vr[U], vi[U];
                 int cq[U];
+                const R* kt = kb + q0 * KS;
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
-                    const int q = min(q0 + u, np - 1);
-                    cq[u] = lane_val(cl, q);
-                    vr[u] = lane_val(cr, q);
-                    vi[u] = lane_val(ci, q);
-                    const R* kq = kb + q * KS;
+                    cq[u] = lane_val(cl, (q0 + u) & 63);
+                    const R* kq = kt + u * KS;
 #pragma unroll
                     for (int pp = 0; pp < NPASS; ++pp) kv[u][pp] = kq[pa[pp]] * kq[W + pb[pp]];
+                    vr[u] = kq[2 * W];
+                    vi[u] = kq[2 * W + 1];
                 }
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
                     if (q0 + u >= np) break;
                     if (cq[u] != cur) {
-                        flush_run<R, NPASS>(tile, cur, po, pv, accr, acci);
+                        flush_run<R, NPASS, ATOMIC>(tile, cur, po, pv, accr, acci);
                         cur = cq[u];
-                    }
 #pragma unroll
-                    for (int pp = 0; pp < NPASS; ++pp) {
-                        accr[pp] += vr[u] * kv[u][pp];
-                        acci[pp] += vi[u] * kv[u][pp];
+                        for (int pp = 0; pp < NPASS; ++pp) {
+                            accr[pp] = vr[u] * kv[u][pp];
+                            acci[pp] = vi[u] * kv[u][pp];
+                        }
+                    } else {
+#pragma unroll
+                        for (int pp = 0; pp < NPASS; ++pp) {
+                            accr[pp] += vr[u] * kv[u][pp];
+                            acci[pp] += vi[u] * kv[u][pp];
+                        }
                     }
                 }
             }
             wave_lds_order();
         }
-        flush_run<R, NPASS>(tile, cur, po, pv, accr, acci);
+        flush_run<R, NPASS, ATOMIC>(tile, cur, po, pv, accr, acci);
         wave_lds_order();
         C* slot = slots + (size_t)s * LL;
         for (int e = lane; e < LL; e += 64) slot[e] = tile[e];
@@ -808,6 +822,42 @@ struct T3Params {
     InvPhiCheb ch1, ch2;
 };
 
+// Sum over aligned groups of GS lanes; lane 0 of each group gets the total,
+// always with the same association.  GS = 16 and 8 use DPP row operations
+// (no LDS round trip); other sizes use shuffles.
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v)
+{
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xf, 0xf, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_f(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffll), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xf, 0xf, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+template <int GS, class R>
+__device__ __forceinline__ R group_sum(R v)
+{
+    if constexpr (GS == 16) {
+        v += dpp_f<0x128>(v);  // row_ror:8
+        v += dpp_f<0x124>(v);  // row_ror:4
+        v += dpp_f<0x122>(v);  // row_ror:2
+        v += dpp_f<0x121>(v);  // row_ror:1
+    } else if constexpr (GS == 8) {
+        v += dpp_f<0x141>(v);  // row_half_mirror: lane i + lane 7 - i
+        v += dpp_f<0x4e>(v);   // quad_perm [2,3,0,1]
+        v += dpp_f<0xb1>(v);   // quad_perm [1,0,3,2]
+    } else {
+#pragma unroll
+        for (int off = GS / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, GS);
+    }
+    return v;
+}
+
 // Lanes per target in the interpolation: one stencil row per lane.
 template <int W>
 constexpr int interp_group() { return W <= 8 ? 8 : (W <= 16 ? 16 : 32); }
@@ -862,38 +912,49 @@ __global__ void __launch_bounds__(64) k_t3_interp(const R* __restrict__ G, const
         const double fr = sn * corr * tp.invlz, fi = -cn * corr * tp.invlz;
         wave_lds_order();
         const int nq = (int)min<int64_t>(64, M - base);
-        for (int j = 0; j < nq; j += NT) {
-            const int q = j + g;
-            R sr = R(0), si = R(0);
+        // gathers of the next trip are issued before the current one is summed
+        C cur[W], nxt[W];
+        auto gather = [&](int q, C* gv) {
             if (q < nq && r < W) {
                 const uint32_t cp = cs[q];
                 const int c1 = (int)(cp & 0xffffu);
                 int row = (int)(cp >> 16) + r;
                 if (row >= tp.m2) row -= tp.m2;
                 const C* gr = Gv + (size_t)row * tp.m1;
-                C gv[W];
+                if (c1 + W <= tp.m1) {
 #pragma unroll
-                for (int a = 0; a < W; ++a) {
-                    int col = c1 + a;
-                    if (col >= tp.m1) col -= tp.m1;
-                    gv[a] = gr[col];
+                    for (int a = 0; a < W; ++a) gv[a] = gr[c1 + a];
+                } else {
+#pragma unroll
+                    for (int a = 0; a < W; ++a) {
+                        int col = c1 + a;
+                        if (col >= tp.m1) col -= tp.m1;
+                        gv[a] = gr[col];
+                    }
                 }
+            }
+        };
+        gather(g, cur);
+        for (int j = 0; j < nq; j += NT) {
+            const int q = j + g;
+            gather(q + NT, nxt);
+            R sr = R(0), si = R(0);
+            if (q < nq && r < W) {
                 const R* kq = ks + q * KS;
 #pragma unroll
                 for (int a = 0; a < W; ++a) {
-                    sr += gv[a].x * kq[a];
-                    si += gv[a].y * kq[a];
+                    sr += cur[a].x * kq[a];
+                    si += cur[a].y * kq[a];
                 }
                 const R ky = kq[W + r];
                 sr *= ky;
                 si *= ky;
             }
-#pragma unroll
-            for (int off = GS / 2; off > 0; off >>= 1) {
-                sr += __shfl_xor(sr, off, GS);
-                si += __shfl_xor(si, off, GS);
-            }
+            sr = group_sum<GS>(sr);
+            si = group_sum<GS>(si);
             if (r == 0 && q < nq) res[q] = C{sr, si};
+#pragma unroll
+            for (int a = 0; a < W; ++a) cur[a] = nxt[a];
         }
         wave_lds_order();
         if (live) {
@@ -992,16 +1053,20 @@ void launch_spread_w(fh_ctx* c, unsigned grid, const Sub* subs, const int* nsub,
                            (const C2*)dd, (const C2*)cc, slots, gg, tpi, (R)beta, (const R*)poly);
         return;
     }
-    const size_t staging = sizeof(R) * 64 * (2 * W + 1);
-    hipLaunchKernelGGL((k_spread_wave<R, W>), dim3(grid), dim3(64), tile + staging, c->stream, subs, nsub, cell,
-                       (const C2*)dd, (const C2*)cc, slots, gg, tpi, (R)beta, (const R*)poly);
+    const size_t staging = spread_staging_bytes(W, sizeof(R));
+    if (gg.method == 3)
+        hipLaunchKernelGGL((k_spread_wave<R, W, true>), dim3(grid), dim3(64), tile + staging, c->stream, subs, nsub,
+                           cell, (const C2*)dd, (const C2*)cc, slots, gg, tpi, (R)beta, (const R*)poly);
+    else
+        hipLaunchKernelGGL((k_spread_wave<R, W, false>), dim3(grid), dim3(64), tile + staging, c->stream, subs, nsub,
+                           cell, (const C2*)dd, (const C2*)cc, slots, gg, tpi, (R)beta, (const R*)poly);
 }
 
 // LDS bytes of one spread block.
 inline size_t spread_lds(const GridGeom& gg, size_t rsize)
 {
     const size_t tile = 2 * rsize * (size_t)gg.L * gg.L;
-    return gg.method == 1 ? tile : tile + rsize * 64 * (2 * gg.W + 1);
+    return gg.method == 1 ? tile : tile + spread_staging_bytes(gg.W, rsize);
 }
 
 template <class R>

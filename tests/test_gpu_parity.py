@@ -138,7 +138,7 @@ def test_grid_shapes_and_translation(ctx, n1, n2, h1, h2, xc, yc):
 
 @pytest.mark.parametrize("method,tile,P,sigma", [
     (1, 16, 64, 0.0), (2, 16, 64, 0.0), (1, 32, 1024, 0.0), (2, 32, 4096, 0.0), (2, 8, 256, 0.0),
-    (2, 32, 256, 1.25), (1, 16, 512, 1.25),
+    (2, 32, 256, 1.25), (1, 16, 512, 1.25), (3, 16, 64, 0.0), (3, 32, 16, 1.25), (0, 0, 0, 0.0),
 ])
 def test_spread_variants(fh, ctx, method, tile, P, sigma):
     # every spread method / tile / work-item size / upsampling the autotuner
@@ -265,6 +265,44 @@ def test_points_equal_grid_at_grid_targets(ctx):
     xi, eta = oracle.grid_targets(g.n1, g.n2, g.h1, g.h2)
     up = cpu(ctx.field_points(q, wl.lam, wl.z, torch.tensor(xi, device="cuda"), torch.tensor(eta, device="cuda")))
     assert relL2(up, ug) <= 2 * TOL[ctx.precision]
+
+
+def test_rule_shared_by_contexts_on_two_streams(fh, ctx):
+    # a rule made by one context feeds another context on another stream,
+    # ordered by an event, as in a pipelined step
+    wl = workloads.workload(2)
+    g = wl.grid
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        other = fh.Context(ctx.precision)
+    try:
+        M = 5000
+        xi = torch.tensor(wl.points[0][:M], device="cuda")
+        eta = torch.tensor(wl.points[1][:M], device="cuda")
+        ref_pts = cpu(ctx.field_points(ctx.quad_for(wl.shape), wl.lam, wl.z, xi, eta))
+        ev_rule, ev_done = torch.cuda.Event(), torch.cuda.Event()
+        main = torch.cuda.current_stream()
+        up = torch.empty(M, dtype=ctx.cdtype, device="cuda")
+        for _ in range(3):
+            q = ctx.quad_for(wl.shape)
+            ev_rule.record(main)
+            ug = ctx.field_grid(q, wl.lam, wl.z, 200, 200, g.h1, g.h2)
+            side.wait_event(ev_rule)
+            other.field_points(q, wl.lam, wl.z, xi, eta, out=up)
+            ev_done.record(side)
+            main.wait_event(ev_done)
+            q.close()
+        torch.cuda.synchronize()
+        # same rule and targets: equal to the rounding of the summation order
+        assert relL2(cpu(up), ref_pts) <= (1e-12 if ctx.precision == "fp64" else 1e-6)
+        x, y, w = oracle_quad(wl.shape)
+        xs, ys = oracle.grid_targets(200, 200, g.h1, g.h2)
+        rng = np.random.Generator(np.random.PCG64(8))
+        idx = rng.choice(len(xs), 300, replace=False)
+        ref = oracle.fresnel_direct(x, y, w, wl.lam, wl.z, xs[idx], ys[idx])
+        assert relL2(cpu(ug).ravel()[idx], ref) <= TOL[ctx.precision]
+    finally:
+        other.close()
 
 
 def test_starshade_workload3_points_sampled(ctx):
