@@ -31,6 +31,7 @@ HBM_PEAK_GBS = 8000.0
 # LDS: 256 CUs x 128 bytes per clock x 2.4 GHz ("Rooflines")
 LDS_PEAK_GBS = 256 * 128 * 2.4
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_starfish_F20.json")
+METRIC = "target pts/s at 1e-9 (FP64) vs 1e-5 (mixed); backward/forward time ratio"
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2010_05978_amd", "csrc", f)
                   for f in ("fh_kernels.hpp", "fh_field.hip")]
 
@@ -47,6 +48,9 @@ def parse():
                     help="also run a plain 256 MiB device copy (counter calibration for rocprofv3 --pmc)")
     ap.add_argument("--no-grad", action="store_true", help="skip the backward/forward ratio (workload 5)")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched workload 4")
+    ap.add_argument("--parts", default="step,grad,batch",
+                    help="comma list of step, grad, batch to run (profiling one part alone; "
+                         "without step the line carries no value)")
     return ap.parse_args()
 
 
@@ -273,6 +277,15 @@ def main():
     dev = torch.device("cuda", 0)
     wl = workloads.workload(2)
     precs = [args.only] if args.only else ["fp64", "mixed"]
+    parts = set(args.parts.split(","))
+    if "step" not in parts:
+        out = {"metric": METRIC, "value": None, "unit": "targets/s", "n_gpus": 1, "parts": sorted(parts)}
+        if "grad" in parts and not args.no_grad:
+            out["backward_forward"] = {p: grad_ratio(fh, p, 3, 1) for p in precs}
+        if "batch" in parts and not args.no_batch:
+            out["batch"] = batch_throughput(fh, 5, 2)
+        print(json.dumps(out))
+        return
     res = {}
     for p in precs:
         st = Step(fh, p, wl, dev)
@@ -290,7 +303,7 @@ def main():
     main_p = precs[0]
     r = res[main_p]
     out = {
-        "metric": "target pts/s at 1e-9 (FP64) vs 1e-5 (mixed); backward/forward time ratio",
+        "metric": METRIC,
         "value": r["value"], "unit": "targets/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": r["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64" if main_p == "fp64" else "c64-f64phase", "data": "synthetic",
@@ -303,9 +316,9 @@ def main():
     if "mixed" in res and main_p != "mixed":
         out["mixed"] = {"value": res["mixed"]["value"], "ms_per_step": res["mixed"]["ms_per_step"],
                         "dtype": "c64-f64phase", "tolerance": 1e-5, "roofline": roofline(res, "mixed", wl)}
-    if not args.no_grad:
+    if not args.no_grad and "grad" in parts:
         out["backward_forward"] = {p: grad_ratio(fh, p, 3, 1) for p in precs}
-    if not args.no_batch:
+    if not args.no_batch and "batch" in parts:
         out["batch"] = batch_throughput(fh, 5, 2)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)

@@ -239,7 +239,8 @@ fh_status fh_autotune_grid(fh_ctx* ctx, const fh_quad* q, double lambda, double 
  * environment at fh_create) every fh_field_grid / fh_field_points /
  * fh_field_grid_vjp call records HIP events on the context stream around
  * its stages, without synchronising.  Stages: [0] strengths + binning,
- * [1] spread (or, for the adjoint, its gather), [2] FFT, [3] finish
+ * [1] the spread kernel alone (for the adjoint: empty), [2] slot merge and
+ * reduce + FFT (for the adjoint: its FFTs), [3] finish
  * (deconvolution epilogue, type-3 interpolation, or adjoint node
  * gradients), [4] whole call.  While timing is on, batched calls run
  * eagerly instead of as a hipGraph so that their stages can be timed.

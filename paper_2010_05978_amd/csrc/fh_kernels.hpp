@@ -734,15 +734,45 @@ __global__ void __launch_bounds__(256) k_transpose_pad(const R* __restrict__ F, 
 
 // u[b][k2][k1] from Z[b][k1 + n1/2][k2 mod nf2]: deconvolve by the kernel
 // transform, undo the window shift, apply the target chirp and 1/(i lambda z),
-// and Babinet.
+// and Babinet.  All factors but 1/(i lambda z) separate into a column factor
+// E1[k1] = exp(i pi xi^2/(lambda z)) / Phi1 and a row factor
+// E2[k2] = exp(i pi eta^2/(lambda z) - 2 pi i k2 sh2/nf2) / Phi2, computed
+// once per block (each phase reduced in turns in FP64 before sincospi).
 template <class R>
 __global__ void __launch_bounds__(256) k_epilogue_t1(const R* __restrict__ Z, R* __restrict__ u, EpiParams ep,
                                                      EpiInst e0, const EpiInst* __restrict__ table)
 {
     using C2 = typename V2<R>::T;
     __shared__ C2 t[32][33];
+    __shared__ double2 E1[32], E2[32];
     const int k10 = blockIdx.x * 32, k20 = blockIdx.y * 32, b = blockIdx.z;
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    const EpiInst ei = table ? table[b] : e0;
+    if (threadIdx.x < 64) {
+        const bool row = threadIdx.x >= 32;
+        const int ki = (row ? k20 : k10) + tx;
+        const int n = row ? ep.n2 : ep.n1;
+        double2 f = make_double2(0.0, 0.0);
+        if (ki < n) {
+            const int k = ki - n / 2;
+            const double x = row ? ep.yc + ep.h2 * k : ep.xc + ep.h1 * k;
+            double tt = x * x * ei.inv2lz;
+            if (row) {
+                // window shift: F_full[k2] = exp(-2 pi i k2 sh2/nf2) F_window[k2]
+                long long km = k % ep.nf2;
+                if (km < 0) km += ep.nf2;
+                long long sm = ei.sh2 % ep.nf2;
+                if (sm < 0) sm += ep.nf2;
+                tt = (tt - rint(tt)) - (double)((km * sm) % ep.nf2) / (double)ep.nf2;
+            }
+            const double ph = tt - rint(tt);
+            double sn, cs;
+            sincospi(2.0 * ph, &sn, &cs);
+            const double sc = row ? ep.iphi2[ki] : ep.iphi1[ki];
+            f = make_double2(cs * sc, sn * sc);
+        }
+        (row ? E2 : E1)[tx] = f;
+    }
     const C2* Zv = reinterpret_cast<const C2*>(Z) + (size_t)b * ep.n1 * ep.nf2;
     for (int k = ty; k < 32; k += 8) {
         const int cidx = k10 + k, k2i = k20 + tx;
@@ -753,27 +783,17 @@ __global__ void __launch_bounds__(256) k_epilogue_t1(const R* __restrict__ Z, R*
         }
     }
     __syncthreads();
-    const EpiInst ei = table ? table[b] : e0;
     for (int k = ty; k < 32; k += 8) {
         const int k2i = k20 + k, k1i = k10 + tx;
         if (k1i >= ep.n1 || k2i >= ep.n2) continue;
         const C2 fv = t[tx][k];
-        const int k1 = k1i - ep.n1 / 2, k2 = k2i - ep.n2 / 2;
-        const double sc = ep.iphi1[k1i] * ep.iphi2[k2i];
-        const double vr = (double)fv.x * sc, vi = (double)fv.y * sc;
-        const double xi = ep.xc + ep.h1 * k1, eta = ep.yc + ep.h2 * k2;
-        // window shift: F_full[k2] = exp(-2 pi i k2 sh2/nf2) F_window[k2]
-        long long km = k2 % ep.nf2;
-        if (km < 0) km += ep.nf2;
-        long long sm = ei.sh2 % ep.nf2;
-        if (sm < 0) sm += ep.nf2;
-        const double shift = (double)((km * sm) % ep.nf2) / (double)ep.nf2;
-        const double tt = (xi * xi + eta * eta) * ei.inv2lz - shift;
-        const double f = tt - rint(tt);
-        double s, c;
-        sincospi(2.0 * f, &s, &c);
-        double re = (s * vr + c * vi) * ei.invlz;
-        double im = (s * vi - c * vr) * ei.invlz;
+        const double2 a = E1[tx], c = E2[k];
+        const double ar = a.x * c.x - a.y * c.y, ai = a.x * c.y + a.y * c.x;
+        const double wr = (double)fv.x * ar - (double)fv.y * ai;
+        const double wi = (double)fv.x * ai + (double)fv.y * ar;
+        // times 1/(i lambda z)
+        double re = wi * ei.invlz;
+        double im = -wr * ei.invlz;
         if (ei.occ) {
             re = 1.0 - re;
             im = -im;
@@ -912,46 +932,37 @@ __global__ void __launch_bounds__(64) k_t3_interp(const R* __restrict__ G, const
         const double fr = sn * corr * tp.invlz, fi = -cn * corr * tp.invlz;
         wave_lds_order();
         const int nq = (int)min<int64_t>(64, M - base);
-        // gathers of the next trip are issued before the current one is summed
+        // gathers of the next trip are issued before the current one is
+        // summed; the gather has no branches (inactive lanes read a valid
+        // entry and get weight zero), so the loads can stay in flight
+        const int rr = min(r, W - 1);
         C cur[W], nxt[W];
         auto gather = [&](int q, C* gv) {
-            if (q < nq && r < W) {
-                const uint32_t cp = cs[q];
-                const int c1 = (int)(cp & 0xffffu);
-                int row = (int)(cp >> 16) + r;
-                if (row >= tp.m2) row -= tp.m2;
-                const C* gr = Gv + (size_t)row * tp.m1;
-                if (c1 + W <= tp.m1) {
+            const uint32_t cp = cs[min(q, nq - 1)];
+            const int c1 = (int)(cp & 0xffffu);
+            int row = (int)(cp >> 16) + rr;
+            row = row >= tp.m2 ? row - tp.m2 : row;
+            const C* gr = Gv + (size_t)row * tp.m1;
 #pragma unroll
-                    for (int a = 0; a < W; ++a) gv[a] = gr[c1 + a];
-                } else {
-#pragma unroll
-                    for (int a = 0; a < W; ++a) {
-                        int col = c1 + a;
-                        if (col >= tp.m1) col -= tp.m1;
-                        gv[a] = gr[col];
-                    }
-                }
+            for (int a = 0; a < W; ++a) {
+                const int col = c1 + a;
+                gv[a] = gr[col >= tp.m1 ? col - tp.m1 : col];
             }
         };
         gather(g, cur);
         for (int j = 0; j < nq; j += NT) {
             const int q = j + g;
             gather(q + NT, nxt);
+            const R* kq = ks + min(q, nq - 1) * KS;
             R sr = R(0), si = R(0);
-            if (q < nq && r < W) {
-                const R* kq = ks + q * KS;
 #pragma unroll
-                for (int a = 0; a < W; ++a) {
-                    sr += cur[a].x * kq[a];
-                    si += cur[a].y * kq[a];
-                }
-                const R ky = kq[W + r];
-                sr *= ky;
-                si *= ky;
+            for (int a = 0; a < W; ++a) {
+                sr += cur[a].x * kq[a];
+                si += cur[a].y * kq[a];
             }
-            sr = group_sum<GS>(sr);
-            si = group_sum<GS>(si);
+            const R ky = (q < nq && r < W) ? kq[W + rr] : R(0);
+            sr = group_sum<GS>(sr * ky);
+            si = group_sum<GS>(si * ky);
             if (r == 0 && q < nq) res[q] = C{sr, si};
 #pragma unroll
             for (int a = 0; a < W; ++a) cur[a] = nxt[a];
@@ -1190,6 +1201,7 @@ fh_status run_spread(fh_ctx* c, const InstParams& p0, const InstParams* table, i
         FH_TRY(launch_spread<R>(c, grid, b.subs, b.nsub, b.cell, b.dd, b.cc, (typename V2<R>::T*)b.slots, gg, tpi,
                                 beta, poly));
     }
+    timing_mark(c, 2);
     if (Ntot > 0) {
         const int64_t LL = (int64_t)gg.L * gg.L;
         const unsigned mgrid =
@@ -1199,7 +1211,6 @@ fh_status run_spread(fh_ctx* c, const InstParams& p0, const InstParams* table, i
                                (typename V2<R>::T*)b.slots, b.subs, b.nsub, b.tsub, (int)LL, level);
         FH_HIP(hipGetLastError());
     }
-    timing_mark(c, 2);
     const int parts = (gg.T * gg.T + 255) / 256;
     hipLaunchKernelGGL((k_reduce_tiles<R>), dim3(gg.ntx, gg.nty * parts, ninst), dim3(256), 0, c->stream,
                        (const typename V2<R>::T*)b.slots, b.tsub, gg, tpi, F);
