@@ -271,17 +271,14 @@ int next_fft_size(int n, int multiple)
     return (int)m;
 }
 
-// Spread tile edge: the option when set, else 32 when a wavefront's padded
-// tile and kernel staging fit in 24 KB of LDS (six or more wavefronts per
-// CU), else 16; halved while the fine grid is under four tiles across.
-int pick_tile(const fh_ctx* c, int nf, int w)
+// Spread tile edge: the option when set, else 16 (the wavefront spread keeps
+// a private padded tile in LDS, so small tiles leave room for more
+// wavefronts per CU, and the halo the reduce reads stays modest at the
+// kernel widths of 1e-5 and 1e-9); halved while the fine grid is under four
+// tiles across.
+int pick_tile(const fh_ctx* c, int nf, int /*w*/)
 {
-    int T = c->opt.tile;
-    if (T <= 0) {
-        const size_t rs = c->prec == FH_FP64 ? 8 : 4;
-        const size_t L = 32 + (size_t)w - 1;
-        T = 2 * rs * L * L + spread_staging_bytes(w, rs) <= 24 * 1024 ? 32 : 16;
-    }
+    int T = c->opt.tile > 0 ? c->opt.tile : 16;
     while (T > 8 && nf < 4 * T) T /= 2;
     return T;
 }

@@ -39,6 +39,25 @@ __device__ __forceinline__ int find_inst(const InstParams* t, int n, int64_t j)
     return lo;
 }
 
+// Instance of node j for a block of consecutive nodes: one search for the
+// block's first and last node (thread 0, through LDS; the caller
+// synchronises), and a per-node search only when the block straddles
+// instances.
+__device__ __forceinline__ void block_inst_bounds(const InstParams* t, int n, int64_t Ntot, int* s_inst)
+{
+    if (threadIdx.x == 0) {
+        const int64_t j0 = blockIdx.x * (int64_t)blockDim.x;
+        const int64_t j1 = min(j0 + (int64_t)blockDim.x, Ntot) - 1;
+        s_inst[0] = find_inst(t, n, j0);
+        s_inst[1] = find_inst(t, n, max(j0, j1));
+    }
+}
+__device__ __forceinline__ int node_inst(const InstParams* t, int n, int64_t j, const int* s_inst)
+{
+    const int a = s_inst[0], b = s_inst[1];
+    return a == b ? __builtin_amdgcn_readfirstlane(a) : find_inst(t, n, j);
+}
+
 // Fine-grid coordinate g -> first stencil cell (wrapped to [0, nf)) and the
 // offset d = cell - g in [-W/2, -W/2 + 1).  Non-finite g is mapped to cell 0
 // and flagged, so no index is ever out of range.
@@ -184,16 +203,18 @@ __global__ void __launch_bounds__(kBinBlock) k_bin_count(InstParams p0, const In
     __shared__ int s_key[kBinKeys];
     __shared__ int s_cnt[kBinKeys];
     __shared__ int s_base[kBinKeys];
+    __shared__ int s_inst[2];
     if (threadIdx.x < kBinKeys) {
         s_key[threadIdx.x] = -1;
         s_cnt[threadIdx.x] = 0;
     }
+    if (table) block_inst_bounds(table, ninst, Ntot, s_inst);
     __syncthreads();
     const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     const bool valid = j < Ntot;
     int tile = 0;
     if (valid) {
-        const InstParams ip = table ? table[find_inst(table, ninst, j)] : p0;
+        const InstParams ip = table ? table[node_inst(table, ninst, j, s_inst)] : p0;
         const int64_t jj = j - ip.node_off;
         int l1, l2;
         double d1, d2;
@@ -250,36 +271,31 @@ __host__ __device__ __forceinline__ int tile_item_points(int c, int P)
     return max(P, (c + kMaxSubPerTile - 1) / kMaxSubPerTile);
 }
 
-// One block: exclusive scan of tile counts -> tile offsets (points) and the
-// first work item and item count of every tile; the items themselves are
-// written by k_bin_place.
-__global__ void __launch_bounds__(1024) k_scan_tiles(const int* __restrict__ cnt, int ntiles, int P,
-                                                     int* __restrict__ off, int* __restrict__ tsub,
-                                                     int* __restrict__ nsub_out)
+// Exclusive scan of tile counts -> tile offsets (points) and, per tile, the
+// first work item and the item count; the items themselves are written by
+// k_bin_place.  Blocks of 1024 threads take 4096 consecutive tiles (4 per
+// thread); with more than one block, k_scan_sums first totals every block
+// and each block of k_scan_tiles adds the totals of the blocks before it.
+constexpr int kScanThreads = 1024;
+constexpr int kScanPer = 4;
+constexpr int kScanChunk = kScanThreads * kScanPer;
+
+// Inclusive scan of (a, b) over a block of 1024 threads (wavefront shuffles,
+// then the 16 wavefront totals); tot receives the block totals.
+__device__ __forceinline__ void block_scan2(int& a, int& b, int* wa, int* wb, int& ta, int& tb)
 {
-    __shared__ int wa[16], wb[16];
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int chunk = (ntiles + 1023) / 1024;
-    const int t0 = min(ntiles, tid * chunk), t1 = min(ntiles, t0 + chunk);
-    int a = 0, b = 0;
-    for (int t = t0; t < t1; ++t) {
-        const int c = cnt[t];
-        a += c;
-        b += (c + tile_item_points(c, P) - 1) / tile_item_points(c, P);
-    }
-    // inclusive scan within the wavefront, then over the 16 wavefront totals
-    int ia = a, ib = b;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
-        const int va = __shfl_up(ia, o), vb = __shfl_up(ib, o);
+        const int va = __shfl_up(a, o), vb = __shfl_up(b, o);
         if (lane >= o) {
-            ia += va;
-            ib += vb;
+            a += va;
+            b += vb;
         }
     }
     if (lane == 63) {
-        wa[wv] = ia;
-        wb[wv] = ib;
+        wa[wv] = a;
+        wb[wv] = b;
     }
     __syncthreads();
     if (wv == 0) {
@@ -298,18 +314,79 @@ __global__ void __launch_bounds__(1024) k_scan_tiles(const int* __restrict__ cnt
         }
     }
     __syncthreads();
-    int ea = ia - a + (wv > 0 ? wa[wv - 1] : 0);
-    int eb = ib - b + (wv > 0 ? wb[wv - 1] : 0);
-    for (int t = t0; t < t1; ++t) {
-        const int c = cnt[t];
-        const int ns = (c + tile_item_points(c, P) - 1) / tile_item_points(c, P);
-        off[t] = ea;
-        tsub[2 * t] = eb;
-        tsub[2 * t + 1] = ns;
-        ea += c;
+    if (wv > 0) {
+        a += wa[wv - 1];
+        b += wb[wv - 1];
+    }
+    ta = wa[15];
+    tb = wb[15];
+}
+
+__device__ __forceinline__ int tile_items(int c, int P)
+{
+    return (c + tile_item_points(c, P) - 1) / tile_item_points(c, P);
+}
+
+__global__ void __launch_bounds__(kScanThreads) k_scan_sums(const int* __restrict__ cnt, int ntiles, int P,
+                                                            int* __restrict__ bsum)
+{
+    __shared__ int wa[16], wb[16];
+    const int t0 = blockIdx.x * kScanChunk + threadIdx.x * kScanPer;
+    int a = 0, b = 0;
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+        const int c = t0 + k < ntiles ? cnt[t0 + k] : 0;
+        a += c;
+        b += tile_items(c, P);
+    }
+    int ta, tb;
+    block_scan2(a, b, wa, wb, ta, tb);
+    if (threadIdx.x == 0) {
+        bsum[2 * blockIdx.x] = ta;
+        bsum[2 * blockIdx.x + 1] = tb;
+    }
+}
+
+__global__ void __launch_bounds__(kScanThreads) k_scan_tiles(const int* __restrict__ cnt, int ntiles, int P,
+                                                             const int* __restrict__ bsum,
+                                                             int* __restrict__ off, int* __restrict__ tsub,
+                                                             int* __restrict__ nsub_out)
+{
+    __shared__ int wa[16], wb[16];
+    // totals of the blocks before this one
+    int base_a = 0, base_b = 0;
+    if (blockIdx.x > 0) {
+        int sa = 0, sb = 0;
+        for (int k = threadIdx.x; k < (int)blockIdx.x; k += kScanThreads) {
+            sa += bsum[2 * k];
+            sb += bsum[2 * k + 1];
+        }
+        block_scan2(sa, sb, wa, wb, base_a, base_b);
+        __syncthreads();
+    }
+    const int t0 = blockIdx.x * kScanChunk + threadIdx.x * kScanPer;
+    int c[kScanPer];
+    int a = 0, b = 0;
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+        c[k] = t0 + k < ntiles ? cnt[t0 + k] : 0;
+        a += c[k];
+        b += tile_items(c[k], P);
+    }
+    int ia = a, ib = b, ta, tb;
+    block_scan2(ia, ib, wa, wb, ta, tb);
+    int ea = ia - a + base_a, eb = ib - b + base_b;
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+        if (t0 + k >= ntiles) break;
+        const int ns = tile_items(c[k], P);
+        off[t0 + k] = ea;
+        tsub[2 * (t0 + k)] = eb;
+        tsub[2 * (t0 + k) + 1] = ns;
+        ea += c[k];
         eb += ns;
     }
-    if (tid == 1023) *nsub_out = wb[15];
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) *nsub_out = base_b + tb;
 }
 
 // Strength (FP64 phase in turns, reduced), stencil offsets, and the sorted
@@ -322,9 +399,14 @@ __global__ void __launch_bounds__(256) k_bin_place(InstParams p0, const InstPara
                                                    typename V2<R>::T* __restrict__ dd,
                                                    typename V2<R>::T* __restrict__ cc, Sub* __restrict__ subs)
 {
+    __shared__ int s_inst[2];
+    if (table) {
+        block_inst_bounds(table, ninst, Ntot, s_inst);
+        __syncthreads();
+    }
     const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (j >= Ntot) return;
-    const InstParams ip = table ? table[find_inst(table, ninst, j)] : p0;
+    const InstParams ip = table ? table[node_inst(table, ninst, j, s_inst)] : p0;
     const int64_t jj = j - ip.node_off;
     const double x = ip.x[jj], y = ip.y[jj];
     double w = ip.w[jj];
@@ -636,53 +718,90 @@ __global__ void __launch_bounds__(256) k_merge_slots(typename V2<R>::T* __restri
 template <class R>
 __global__ void __launch_bounds__(256) k_reduce_tiles(const typename V2<R>::T* __restrict__ slots,
                                                       const int* __restrict__ tsub, GridGeom gg, int tpi,
-                                                      R* __restrict__ F)
+                                                      int ntiles_total, R* __restrict__ F)
 {
     using C = typename V2<R>::T;
     const int T = gg.T, TT = T * T;
-    const int parts = (TT + 255) / 256;
-    const int tx = blockIdx.x, ty = blockIdx.y / parts, part = blockIdx.y - ty * parts, b = blockIdx.z;
-    const int e = part * 256 + threadIdx.x;
-    if (e >= TT) return;
-    const int i = e % T, j = e / T;
     const int L = gg.L, LL = L * L;
-    R ar = R(0), ai = R(0);
-    for (int dy = 0; j + dy * T < L; ++dy) {
-        int sty = ty - dy;
-        if (sty < 0) {
-            if (!gg.wrap_y) break;
-            sty = ((sty % gg.nty) + gg.nty) % gg.nty;
-        }
-        const int ly = j + dy * T;
-        for (int dx = 0; i + dx * T < L; ++dx) {
-            const int stx = (((tx - dx) % gg.ntx) + gg.ntx) % gg.ntx;
-            const int lx = i + dx * T;
-            const int t = b * tpi + sty * gg.ntx + stx;
-            const int first = tsub[2 * t], cnt = tsub[2 * t + 1];
-            int stride = 1;
-            for (int l = merge_levels(cnt); l > 0; --l) stride *= kMergeG;
-            const int heads = (cnt + stride - 1) / stride;
-            const size_t st = (size_t)stride * LL;
-            const C* sp = slots + (size_t)first * LL + ly * L + lx;
-            // four independent (guarded) loads in flight per trip; the sum
-            // order is fixed, so the result does not depend on scheduling
-            for (int k = 0; k < heads; k += 4) {
-                C r[4];
-#pragma unroll
-                for (int u = 0; u < 4; ++u) r[u] = k + u < heads ? sp[u * st] : C{R(0), R(0)};
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    ar += r[u].x;
-                    ai += r[u].y;
-                }
-                sp += 4 * st;
+    const int reach = (L - 1) / T;  // tiles back that a padded tile reaches
+    C* Fv = reinterpret_cast<C*>(F);
+    for (int tile = blockIdx.x; tile < ntiles_total; tile += gridDim.x) {
+        const int b = tile / tpi, tl = tile - b * tpi;
+        const int ty = tl / gg.ntx, tx = tl - ty * gg.ntx;
+        // does any work item cover this tile?  (uniform)
+        bool any = false;
+        for (int dy = 0; dy <= reach && !any; ++dy) {
+            int sty = ty - dy;
+            if (sty < 0) {
+                if (!gg.wrap_y) break;
+                sty = ((sty % gg.nty) + gg.nty) % gg.nty;
+            }
+            for (int dx = 0; dx <= reach && !any; ++dx) {
+                const int stx = (((tx - dx) % gg.ntx) + gg.ntx) % gg.ntx;
+                any = tsub[2 * (b * tpi + sty * gg.ntx + stx) + 1] > 0;
             }
         }
+        C* out = Fv + ((size_t)b * gg.rows + (size_t)ty * T) * gg.nf1 + (size_t)tx * T;
+        if (!any) {
+            for (int e = threadIdx.x; e < TT; e += blockDim.x) out[(size_t)(e / T) * gg.nf1 + e % T] = C{R(0), R(0)};
+            continue;
+        }
+        // a thread sums up to kCells cells (T = 32: 4; T <= 16: 1), and its
+        // loads for all of them are issued together on every trip; each
+        // cell sums its covering tiles and their merged slots in a fixed
+        // order
+        constexpr int kCells = 4;
+        R ar[kCells], ai[kCells];
+        int ci[kCells], cj[kCells];
+        bool cv[kCells];
+#pragma unroll
+        for (int k = 0; k < kCells; ++k) {
+            const int e = threadIdx.x + k * blockDim.x;
+            cv[k] = e < TT;
+            ci[k] = cv[k] ? e % T : 0;
+            cj[k] = cv[k] ? e / T : 0;
+            ar[k] = ai[k] = R(0);
+        }
+        for (int dy = 0; dy <= reach; ++dy) {
+            int sty = ty - dy;
+            if (sty < 0) {
+                if (!gg.wrap_y) break;
+                sty = ((sty % gg.nty) + gg.nty) % gg.nty;
+            }
+            for (int dx = 0; dx <= reach; ++dx) {
+                const int stx = (((tx - dx) % gg.ntx) + gg.ntx) % gg.ntx;
+                const int t = b * tpi + sty * gg.ntx + stx;
+                const int first = tsub[2 * t], cnt = tsub[2 * t + 1];
+                if (cnt == 0) continue;
+                int stride = 1;
+                for (int l = merge_levels(cnt); l > 0; --l) stride *= kMergeG;
+                const int heads = (cnt + stride - 1) / stride;
+                const size_t st = (size_t)stride * LL;
+                const C* s0 = slots + (size_t)first * LL;
+                for (int k = 0; k < heads; k += 4) {
+                    C r[kCells][4];
+#pragma unroll
+                    for (int q = 0; q < kCells; ++q) {
+                        const int lx = ci[q] + dx * T, ly = cj[q] + dy * T;
+                        const bool in = cv[q] && lx < L && ly < L;
+                        const C* sp = s0 + (size_t)k * st + (in ? ly * L + lx : 0);
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) r[q][u] = in && k + u < heads ? sp[u * st] : C{R(0), R(0)};
+                    }
+#pragma unroll
+                    for (int q = 0; q < kCells; ++q)
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            ar[q] += r[q][u].x;
+                            ai[q] += r[q][u].y;
+                        }
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < kCells; ++q)
+            if (cv[q]) out[(size_t)cj[q] * gg.nf1 + ci[q]] = C{ar[q], ai[q]};
     }
-    C v;
-    v.x = ar;
-    v.y = ai;
-    reinterpret_cast<C*>(F)[((size_t)b * gg.rows + ty * T + j) * gg.nf1 + tx * T + i] = v;
 }
 
 // --------------------------------------------------------- type-1 finish
@@ -1134,6 +1253,7 @@ struct SpreadBufs {
     void* cc;       // sorted: strengths (complex)
     Sub* subs;      // work items
     int* nsub;      // number of work items (device)
+    int* bsum;      // per scan block: points and work items
     void* slots;    // one padded L x L complex tile per work item
     int64_t max_sub;
 };
@@ -1148,6 +1268,7 @@ size_t spread_bytes(int64_t Ntot, const GridGeom& gg, int ntiles_total, size_t r
 {
     const int64_t max_sub = Ntot / gg.P + std::min<int64_t>(Ntot, ntiles_total) + 1;
     return 2 * aligned_bytes(sizeof(int) * (size_t)ntiles_total) + aligned_bytes(2 * sizeof(int) * ntiles_total) +
+           aligned_bytes(2 * sizeof(int) * (size_t)(ntiles_total / kScanChunk + 1)) +
            aligned_bytes(sizeof(int) * Ntot) + aligned_bytes(sizeof(uint32_t) * Ntot) +
            2 * aligned_bytes(2 * rsize * Ntot) + aligned_bytes(sizeof(Sub) * max_sub) + aligned_bytes(sizeof(int)) +
            aligned_bytes(2 * rsize * (size_t)gg.L * gg.L * max_sub);
@@ -1166,6 +1287,7 @@ SpreadBufs spread_carve(fh_ctx* c, int64_t Ntot, const GridGeom& gg, int ntiles_
     b.cc = c->arena.take<char>(2 * rsize * Ntot);
     b.subs = c->arena.take<Sub>(b.max_sub);
     b.nsub = c->arena.take<int>(1);
+    b.bsum = c->arena.take<int>(2 * (size_t)(ntiles_total / kScanChunk + 1));
     b.slots = c->arena.take<char>(2 * rsize * (size_t)gg.L * gg.L * b.max_sub);
     return b;
 }
@@ -1183,8 +1305,12 @@ fh_status run_spread(fh_ctx* c, const InstParams& p0, const InstParams* table, i
                            ninst, Ntot,
                            gg, b.cnt, b.rank);
     }
-    hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, c->stream, b.cnt, ntiles_total, gg.P, b.off, b.tsub,
-                       b.nsub);
+    const int nscan = std::max(1, (ntiles_total + kScanChunk - 1) / kScanChunk);
+    if (nscan > 1)
+        hipLaunchKernelGGL(k_scan_sums, dim3(nscan), dim3(kScanThreads), 0, c->stream, b.cnt, ntiles_total, gg.P,
+                           b.bsum);
+    hipLaunchKernelGGL(k_scan_tiles, dim3(nscan), dim3(kScanThreads), 0, c->stream, b.cnt, ntiles_total, gg.P,
+                       b.bsum, b.off, b.tsub, b.nsub);
     if (Ntot > 0) {
         hipLaunchKernelGGL((k_bin_place<R>), dim3(nblocks(Ntot, 256)), dim3(256), 0, c->stream, p0, table, ninst,
                            Ntot, gg, b.cnt, b.off, b.tsub, b.rank, b.cell, (typename V2<R>::T*)b.dd,
@@ -1211,9 +1337,10 @@ fh_status run_spread(fh_ctx* c, const InstParams& p0, const InstParams* table, i
                                (typename V2<R>::T*)b.slots, b.subs, b.nsub, b.tsub, (int)LL, level);
         FH_HIP(hipGetLastError());
     }
-    const int parts = (gg.T * gg.T + 255) / 256;
-    hipLaunchKernelGGL((k_reduce_tiles<R>), dim3(gg.ntx, gg.nty * parts, ninst), dim3(256), 0, c->stream,
-                       (const typename V2<R>::T*)b.slots, b.tsub, gg, tpi, F);
+    const unsigned rgrid = (unsigned)std::max<int64_t>(
+        1, std::min<int64_t>(ntiles_total, (int64_t)c->cu_count * 16));
+    hipLaunchKernelGGL((k_reduce_tiles<R>), dim3(rgrid), dim3(256), 0, c->stream,
+                       (const typename V2<R>::T*)b.slots, b.tsub, gg, tpi, ntiles_total, F);
     FH_HIP(hipGetLastError());
     return FH_OK;
 }
@@ -1245,7 +1372,7 @@ void spread_defaults(const fh_ctx* c, GridGeom& g)
 }
 
 // Points per work item for Ntot nodes: the option when set, else enough for
-// about 32 work items per CU (at least 64 points): small rules then spread
+// about 96 work items per CU (at least 64 points): small rules then spread
 // over the whole chip, and large batches do not pay one slot per few hundred
 // points.  A tile's items still hold at least count / kMaxSubPerTile points.
 void size_items(const fh_ctx* c, GridGeom& g, int64_t Ntot)
@@ -1254,7 +1381,7 @@ void size_items(const fh_ctx* c, GridGeom& g, int64_t Ntot)
         g.P = c->opt.max_subproblem;
         return;
     }
-    const int64_t target = (int64_t)c->cu_count * 32;
+    const int64_t target = (int64_t)c->cu_count * 96;
     g.P = (int)std::min<int64_t>(1 << 24, std::max<int64_t>(64, (Ntot + target - 1) / target));
 }
 
