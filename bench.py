@@ -12,7 +12,8 @@ value = targets per second of the FP64 path (tolerance 1e-9, relative L2
 against the exact quadrature sum); the mixed-precision path (tolerance 1e-5)
 is timed in the same run and reported beside it.  The roofline entry is for
 the kernel with the largest device time per step, timed live with HIP events
-on the library's stream over the timed region.
+on the library's streams over a second timed pass of the same steps (the
+events cost host time, so the throughput pass runs without them).
 """
 from __future__ import annotations
 
@@ -66,8 +67,10 @@ class Step:
     """One pass of the hot path for one precision: the rule, its field on the
     grid (type 1) and at the scattered targets (type 3).  The two field calls
     are independent, so they run on two streams (two contexts sharing the
-    rule): the type-3 call's bounding-box readback and its small, latency-bound
-    kernels then overlap the type-1 work."""
+    rule) and the type-3 call's small, latency-bound kernels overlap the
+    type-1 work.  The scattered targets become a target set every step
+    (device sort), planned on the pupil's box |x|, |y| <= 1.5 that the
+    workload draws them in, so no call reads anything back to the host."""
 
     def __init__(self, fh, precision, wl, dev):
         import torch
@@ -76,8 +79,6 @@ class Step:
         self.ctx = fh.Context(precision)
         with torch.cuda.stream(self.sB):
             self.ctx_pts = fh.Context(precision)
-        self.ev_rule = torch.cuda.Event()
-        self.ev_pts = torch.cuda.Event()
         self.wl = wl
         self.shape = wl.shape
         g = wl.grid
@@ -86,20 +87,22 @@ class Step:
         self.eta = torch.tensor(wl.points[1], device=dev)
         self.ugrid = torch.empty((g.n2, g.n1), dtype=self.ctx.cdtype, device=dev)
         self.upts = torch.empty(len(wl.points[0]), dtype=self.ctx.cdtype, device=dev)
+        self.box = (-wl.pupil, wl.pupil, -wl.pupil, wl.pupil)
         self.M = g.M + len(wl.points[0])
 
     def __call__(self):
         wl, g = self.wl, self.g
+        tg = self.ctx_pts.targets(self.xi, self.eta, box=self.box)
         q = self.ctx.quad_for(self.shape)
-        self.ev_rule.record(self.sA)
+        # the type-3 call reads the rule: order it after the rule's kernels
+        self.ctx_pts.order_after(self.ctx)
         self.ctx.field_grid(q, wl.lam, wl.z, g.n1, g.n2, g.h1, g.h2, out=self.ugrid)
-        self.sB.wait_event(self.ev_rule)
-        self.ctx_pts.field_points(q, wl.lam, wl.z, self.xi, self.eta, out=self.upts)
-        self.ev_pts.record(self.sB)
+        self.ctx_pts.field_targets(q, wl.lam, wl.z, tg, out=self.upts)
         # the rule's memory goes back to the first context's pool, reused on
         # its stream: order that after the type-3 call
-        self.sA.wait_event(self.ev_pts)
+        self.ctx.order_after(self.ctx_pts)
         q.close()
+        tg.close()
 
     def set_timing(self, on):
         self.ctx.set_timing(on)
@@ -111,19 +114,26 @@ class Step:
 
 
 def time_steps(step, steps, warmup):
+    """Wall time of `steps` steps, then the per-stage device times of another
+    `steps` steps timed with HIP events on the library's streams.  Recording
+    the events costs host time on every call, so the throughput pass runs
+    without them."""
     import torch
     for _ in range(warmup):
         step()
-    torch.cuda.synchronize()
-    step.set_timing(True)
-    step.ctx.timing_totals(0, reset=True)
-    step.ctx_pts.timing_totals(1, reset=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
         step()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    step.set_timing(True)
+    step.ctx.timing_totals(0, reset=True)
+    step.ctx_pts.timing_totals(1, reset=True)
+    torch.cuda.synchronize()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
     grid_ms, ngrid = step.ctx.timing_totals(0)
     pts_ms, npts = step.ctx_pts.timing_totals(1)
     step.set_timing(False)

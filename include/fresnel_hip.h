@@ -66,6 +66,7 @@ typedef enum fh_memspace { FH_MEM_HOST = 0, FH_MEM_DEVICE = 1 } fh_memspace;
 
 typedef struct fh_ctx fh_ctx;
 typedef struct fh_quad fh_quad;
+typedef struct fh_targets fh_targets;
 
 /* NUFFT and spreading options.  Zero in any field means "choose
  * automatically".  The exponential-of-semicircle kernel
@@ -102,6 +103,12 @@ fh_status fh_destroy(fh_ctx* ctx);
 fh_status fh_set_stream(fh_ctx* ctx, void* hip_stream);
 /* Block until all work enqueued by the context has finished. */
 fh_status fh_synchronize(fh_ctx* ctx);
+/* Make work enqueued later on `after` wait for all work enqueued so far on
+ * `before` (same device), with no host synchronisation: before's stream
+ * writes the next value of a counter in signal memory, after's stream waits
+ * for it.  This orders calls that share a rule or a target set across two
+ * contexts' streams.  Not for use inside a stream capture. */
+fh_status fh_order_after(fh_ctx* after, fh_ctx* before);
 /* Replace the NUFFT/spread options (NULL restores automatic choices). */
 fh_status fh_set_options(fh_ctx* ctx, const fh_options* opt);
 /* Report the kernel parameters a type-1 call with an n-point grid would
@@ -188,6 +195,35 @@ fh_status fh_field_grid(fh_ctx* ctx, const fh_quad* q, double lambda, double z,
 fh_status fh_field_points(fh_ctx* ctx, const fh_quad* q, double lambda, double z, int64_t M,
                           const double* xi, const double* eta, int32_t occulter, void* u,
                           fh_memspace mem);
+
+/* Scattered-target set for repeated type-3 evaluation (sec. 2.1's targets;
+ * the paper's sweeps evaluate many wavelengths and shapes at one fixed set of
+ * pupil points, sec. 4.3).  Copies the M targets (xi, eta in `mem`) into a
+ * library-owned object, sorted on the device into the Morton order of a
+ * 64 x 64 cell grid over the target box so that the interpolation of
+ * neighbouring targets reads neighbouring grid entries.
+ *   box (host, 4 doubles xmin, xmax, ymin, ymax, or NULL): the region the
+ *     type-3 grids are planned for.  With a box the call does not
+ *     synchronise (device arrays) and targets outside it, or with a
+ *     non-finite coordinate, get NaN from fh_field_targets.  With NULL the
+ *     bounding box is computed (device arrays: one readback, which
+ *     synchronises the stream) and a non-finite target is FH_ERR_NONFINITE.
+ *   M must be below 2^31; M = 0 gives an empty set.  Host arrays may be
+ *   released on return.  Ownership and stream ordering are as for rules:
+ *   fh_targets_destroy hands the memory back to the making context. */
+fh_status fh_targets_create(fh_ctx* ctx, int64_t M, const double* xi, const double* eta,
+                            const double* box, fh_memspace mem, fh_targets** out);
+fh_status fh_targets_size(const fh_targets* t, int64_t* M);
+/* The planning box (declared or computed), 4 doubles. */
+fh_status fh_targets_box(const fh_targets* t, double* box);
+fh_status fh_targets_destroy(fh_targets* t);
+
+/* Field at a target set (sec. 2.1, type-3 NUFFT), as fh_field_points but
+ * without a host synchronisation for device output: u (M complex in `mem`,
+ * in the order the targets were given to fh_targets_create) is written on
+ * the context stream.  Host output copies back and synchronises. */
+fh_status fh_field_targets(fh_ctx* ctx, const fh_quad* q, double lambda, double z,
+                           const fh_targets* t, int32_t occulter, void* u, fh_memspace mem);
 
 /* B grid fields in one batched pass: instance b uses rule q[b], lambda[b],
  * z[b] and occulter[b] (host arrays of length B), all on the same grid

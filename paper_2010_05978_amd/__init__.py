@@ -16,7 +16,7 @@ from ._binding import (  # noqa: F401
 )
 from . import _binding as abi  # noqa: F401
 
-__all__ = ["Context", "Quad", "FresnelError", "fh_options", "abi", "lib", "LIB_PATH"]
+__all__ = ["Context", "Quad", "Targets", "FresnelError", "fh_options", "abi", "lib", "LIB_PATH"]
 
 
 class Quad:
@@ -43,6 +43,33 @@ class Quad:
         # gone there is nothing left to release
         if self.handle is not None and self.ctx.handle is not None:
             abi.fh_quad_destroy(self.handle)
+        self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Targets:
+    """A device-resident, spatially sorted set of scattered targets."""
+
+    def __init__(self, ctx: "Context", handle):
+        self.ctx = ctx
+        self.handle = handle
+
+    @property
+    def M(self) -> int:
+        return abi.fh_targets_size(self.handle)
+
+    @property
+    def box(self):
+        return abi.fh_targets_box(self.handle)
+
+    def close(self):
+        if self.handle is not None and self.ctx.handle is not None:
+            abi.fh_targets_destroy(self.handle)
         self.handle = None
 
     def __del__(self):
@@ -100,6 +127,11 @@ class Context:
                                        shape.nd, shape.md, shape.coef, shape.K)
         raise TypeError(f"unknown shape {kind}")
 
+    def targets(self, xi, eta, box=None) -> Targets:
+        """Target set for repeated type-3 calls; box = (xmin, xmax, ymin, ymax)
+        declares the region (no readback), None computes it."""
+        return Targets(self, abi.fh_targets_create(self.handle, xi, eta, box))
+
     # ------------------------------------------------------------ fields
     def field_grid(self, quad: Quad, lam, z, n1, n2, h1, h2, xc=0.0, yc=0.0, occulter=False, out=None):
         import torch
@@ -114,6 +146,13 @@ class Context:
             dev = xi.device if hasattr(xi, "device") else self.device
             out = torch.empty(len(xi), dtype=self.cdtype, device=dev)
         abi.fh_field_points(self.handle, quad.handle, lam, z, xi, eta, occulter, out)
+        return out
+
+    def field_targets(self, quad: Quad, lam, z, targets: Targets, occulter=False, out=None):
+        import torch
+        if out is None:
+            out = torch.empty(targets.M, dtype=self.cdtype, device=self.device)
+        abi.fh_field_targets(self.handle, quad.handle, lam, z, targets.handle, occulter, out)
         return out
 
     def field_grid_batch(self, quads, lams, zs, n1, n2, h1, h2, xc=0.0, yc=0.0, occulter=False, out=None):
@@ -144,6 +183,10 @@ class Context:
 
     def synchronize(self):
         abi.fh_synchronize(self.handle)
+
+    def order_after(self, other: "Context"):
+        """Work enqueued later here waits for the work enqueued so far on other."""
+        abi.fh_order_after(self.handle, other.handle)
 
     def last_timing(self):
         return abi.fh_last_timing(self.handle)

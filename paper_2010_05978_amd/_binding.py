@@ -31,10 +31,11 @@ FH_MEM_HOST = 0
 FH_MEM_DEVICE = 1
 
 EXPORTED = [
-    "fh_create", "fh_destroy", "fh_set_stream", "fh_synchronize", "fh_set_options", "fh_query_params",
+    "fh_create", "fh_destroy", "fh_set_stream", "fh_synchronize", "fh_order_after", "fh_set_options", "fh_query_params",
     "fh_status_string", "fh_last_error", "fh_quad_from_boundary", "fh_quad_radial", "fh_quad_polygon",
     "fh_quad_starshade", "fh_quad_from_nodes", "fh_quad_size", "fh_quad_export", "fh_quad_device_ptrs",
-    "fh_quad_destroy", "fh_field_grid", "fh_field_points", "fh_field_grid_batch", "fh_field_grid_vjp",
+    "fh_quad_destroy", "fh_targets_create", "fh_targets_size", "fh_targets_box", "fh_targets_destroy",
+    "fh_field_grid", "fh_field_points", "fh_field_targets", "fh_field_grid_batch", "fh_field_grid_vjp",
     "fh_starshade_vjp", "fh_autotune_grid", "fh_set_timing", "fh_last_timing", "fh_timing_totals",
 ]
 
@@ -68,6 +69,7 @@ def lib():
             "fh_destroy": [vp],
             "fh_set_stream": [vp, vp],
             "fh_synchronize": [vp],
+            "fh_order_after": [vp, vp],
             "fh_set_options": [vp, ctypes.POINTER(fh_options)],
             "fh_query_params": [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(d), ctypes.POINTER(d),
                                 ctypes.POINTER(i32)],
@@ -82,6 +84,11 @@ def lib():
             "fh_quad_destroy": [vp],
             "fh_field_grid": [vp, vp, d, d, i32, i32, d, d, d, d, i32, vp, ctypes.c_int],
             "fh_field_points": [vp, vp, d, d, i64, vp, vp, i32, vp, ctypes.c_int],
+            "fh_targets_create": [vp, i64, vp, vp, ctypes.POINTER(d), ctypes.c_int, pvp],
+            "fh_targets_size": [vp, ctypes.POINTER(i64)],
+            "fh_targets_box": [vp, ctypes.POINTER(d)],
+            "fh_targets_destroy": [vp],
+            "fh_field_targets": [vp, vp, d, d, vp, i32, vp, ctypes.c_int],
             "fh_field_grid_batch": [vp, i32, vp, vp, vp, i32, i32, d, d, d, d, vp, vp],
             "fh_field_grid_vjp": [vp, vp, d, d, i32, i32, d, d, d, d, i32, vp, vp, vp, vp],
             "fh_starshade_vjp": [vp, i32, d, d, d, d, i32, i32, i32, i32, vp, i32, vp, vp, vp, vp],
@@ -162,6 +169,10 @@ def fh_set_stream(ctx, stream):
 
 def fh_synchronize(ctx):
     _check(lib().fh_synchronize(ctx))
+
+
+def fh_order_after(after, before):
+    _check(lib().fh_order_after(after, before))
 
 
 def fh_set_options(ctx, options: fh_options | None):
@@ -262,6 +273,38 @@ def fh_field_points(ctx, q, lam, z, xi, eta, occulter, u):
     mem = _same_mem(xi, eta, u)
     _check(lib().fh_field_points(ctx, q, lam, z, len(xi), _ptr_mem(xi)[0], _ptr_mem(eta)[0],
                                  int(bool(occulter)), _ptr_mem(u)[0], mem))
+
+
+def fh_targets_create(ctx, xi, eta, box=None):
+    """box: None (bounding box computed) or (xmin, xmax, ymin, ymax)."""
+    mem = _same_mem(xi, eta)
+    if len(xi) != len(eta):
+        raise ValueError("xi and eta must have the same length")
+    bx = None if box is None else (ctypes.c_double * 4)(*[float(v) for v in box])
+    h = ctypes.c_void_p()
+    _check(lib().fh_targets_create(ctx, len(xi), _ptr_mem(xi)[0], _ptr_mem(eta)[0], bx, mem, ctypes.byref(h)))
+    return h
+
+
+def fh_targets_size(t) -> int:
+    n = ctypes.c_int64()
+    _check(lib().fh_targets_size(t, ctypes.byref(n)))
+    return n.value
+
+
+def fh_targets_box(t):
+    arr = (ctypes.c_double * 4)()
+    _check(lib().fh_targets_box(t, arr))
+    return tuple(arr)
+
+
+def fh_targets_destroy(t):
+    _check(lib().fh_targets_destroy(t))
+
+
+def fh_field_targets(ctx, q, lam, z, t, occulter, u):
+    ptr, mem = _ptr_mem(u)
+    _check(lib().fh_field_targets(ctx, q, lam, z, t, int(bool(occulter)), ptr, mem))
 
 
 def fh_field_grid_batch(ctx, quads, lams, zs, n1, n2, h1, h2, xc, yc, occulter, u):

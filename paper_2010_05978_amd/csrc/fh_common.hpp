@@ -193,6 +193,18 @@ struct fh_ctx {
     std::map<void*, size_t> owned;  // every hipMalloc'd block and its size
     double* bbox_dev = nullptr;      // bounding-box reduction scratch
     double* bbox_host = nullptr;     // pinned readback of the box
+    // Binning counters kept at zero between calls: the tile counts of the
+    // spread (zeroed again by the reduce that ends each spread) and the cell
+    // counts of the target sort (zeroed by its scan).  A call that stops
+    // between the count and the reset marks them dirty, and the next call
+    // clears them first.
+    int* tile_cnt = nullptr;
+    int64_t tile_cnt_cap = 0;
+    bool tile_cnt_dirty = false;
+    int* tgt_cnt = nullptr;
+    bool tgt_cnt_dirty = false;
+    uint64_t* order_sig = nullptr;   // fh_order_after: counter written by this stream
+    uint64_t order_seq = 0;          // last value enqueued for it
 };
 
 struct fh_quad {
@@ -205,6 +217,20 @@ struct fh_quad {
     double* w = nullptr;
     bool bbox_valid = false;
     double bbox[4] = {0, 0, 0, 0};  // xmin, xmax, ymin, ymax
+};
+
+// A scattered-target set: coordinates in a spatially sorted order (Morton
+// order of a 64 x 64 cell grid over the box), the original index of every
+// sorted target, and the box the type-3 grids are planned from.
+struct fh_targets {
+    fh_ctx* ctx = nullptr;
+    int64_t M = 0;
+    void* buf = nullptr;  // xs[M], ys[M] (double) then perm[M] (int)
+    size_t buf_bytes = 0;
+    double* xs = nullptr;
+    double* ys = nullptr;
+    int* perm = nullptr;
+    double box[4] = {0, 0, 0, 0};  // xmin, xmax, ymin, ymax
 };
 
 namespace fh {
@@ -236,4 +262,7 @@ void timing_finish(fh_ctx* c);
 
 // kernel launchers shared across translation units (fh_field.hip)
 fh_status launch_zero(fh_ctx* c, void* p, size_t bytes);
+// Make the persistent tile counters hold n zeros (grow, or clear if dirty);
+// call before carving a spread and outside any stream capture.
+fh_status counters_ready(fh_ctx* c, int64_t n);
 }  // namespace fh

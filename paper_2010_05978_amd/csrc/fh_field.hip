@@ -88,6 +88,7 @@ fh_status t1_pipeline(fh_ctx* c, int B, const fh_quad* const* qs, const double* 
     FH_TRY(fft_plan(c, gg.nf1, 0, gg.rows * B, &fa));
     FH_TRY(fft_plan(c, gg.nf2, 0, n1 * B, &fb));
 
+    FH_TRY(counters_ready(c, (int64_t)tpi * B));
     const size_t F_count = 2 * (size_t)B * gg.rows * gg.nf1;
     const size_t Z_count = 2 * (size_t)B * n1 * gg.nf2;
     size_t need = aligned_bytes(rs * F_count) + aligned_bytes(rs * Z_count) +
@@ -128,9 +129,9 @@ fh_status t1_pipeline(fh_ctx* c, int B, const fh_quad* const* qs, const double* 
 
     // graph key: every pointer and size baked into the launches
     char key[512];
-    snprintf(key, sizeof(key), "%p|%zu|%d|%lld|%d|%d|%d|%d|%d|%d|%a|%a|%a|%a|%d|%d|%d|%p", (void*)c->arena.base,
+    snprintf(key, sizeof(key), "%p|%zu|%d|%lld|%d|%d|%d|%d|%d|%d|%a|%a|%a|%a|%d|%d|%d|%p|%p", (void*)c->arena.base,
              c->arena.cap, B, (long long)Ntot, n1, n2, gg.nf1, gg.nf2, gg.W, gg.rows, h1, h2, xc, yc, gg.T, gg.P,
-             gg.method, (void*)u);
+             gg.method, (void*)u, (void*)c->tile_cnt);
     std::string k2(key);
     for (int b = 0; b < B; ++b) k2 += "|" + std::to_string(qs[b]->N);
     // Graphs are captured and replayed on a private stream (the caller's may
@@ -244,44 +245,31 @@ fh_status field_grid_impl(fh_ctx* c, const fh_quad* q, double lambda, double z, 
     return FH_OK;
 }
 
+// Type-3 evaluation at targets (xi_t, eta_t), t < M, all inside the box tb
+// (xmin, xmax, ymin, ymax) the grids are planned from; the value of target t
+// goes to dout[perm[t]] (dout[t] without perm).  With `host`, xi and eta are
+// host arrays copied into the arena; with `host` or `stage_out` the field is
+// written to arena staging returned in *staged, for the caller to copy back.
 template <class R>
-fh_status field_points_impl(fh_ctx* c, const fh_quad* q, double lambda, double z, int64_t M, const double* xi,
-                            const double* eta, int occ, void* u, fh_memspace mem)
+fh_status t3_core(fh_ctx* c, const fh_quad* q, double lambda, double z, int64_t M, const double* xi,
+                  const double* eta, const int* perm, const double* tb, int occ, R* dout, bool host,
+                  bool stage_out, R** staged)
 {
+    stage_out = stage_out || host;
     const size_t rs = sizeof(R);
     const double lz = lambda * z;
     const int64_t N = q->N;
-    if (M == 0) return FH_OK;
-    // target bounding box
-    double tb[4];
-    if (mem == FH_MEM_HOST) {
-        tb[0] = tb[2] = INFINITY;
-        tb[1] = tb[3] = -INFINITY;
-        for (int64_t k = 0; k < M; ++k) {
-            FH_ARG(std::isfinite(xi[k]) && std::isfinite(eta[k]), FH_ERR_NONFINITE, "target %lld not finite",
-                   (long long)k);
-            tb[0] = std::min(tb[0], xi[k]);
-            tb[1] = std::max(tb[1], xi[k]);
-            tb[2] = std::min(tb[2], eta[k]);
-            tb[3] = std::max(tb[3], eta[k]);
-        }
-    } else {
-        FH_TRY(device_bbox(c, xi, eta, M, tb));
-    }
+    const size_t cbytes = aligned_bytes(sizeof(double) * M);
+    const size_t obytes = aligned_bytes(2 * rs * M);
     c->timing_kind = 1;
     if (N == 0) {
-        size_t need = mem == FH_MEM_HOST ? aligned_bytes(2 * rs * M) : 0;
-        FH_TRY(arena_reserve(c, need));
-        R* dout = mem == FH_MEM_HOST ? c->arena.take<R>(2 * M) : static_cast<R*>(u);
+        FH_TRY(arena_reserve(c, stage_out ? obytes : 0));
+        if (stage_out) *staged = dout = c->arena.take<R>(2 * M);
         timing_mark(c, 0);
         hipLaunchKernelGGL((k_fill_field<R>), dim3(nblocks(M, 256)), dim3(256), 0, c->stream, dout, M,
                            (R)(occ ? 1.0 : 0.0));
         FH_HIP(hipGetLastError());
         for (int i = 1; i <= 5; ++i) timing_mark(c, i);
-        if (mem == FH_MEM_HOST) {
-            FH_HIP(hipMemcpyAsync(u, dout, 2 * rs * M, hipMemcpyDeviceToHost, c->stream));
-            FH_HIP(hipStreamSynchronize(c->stream));
-        }
         return FH_OK;
     }
     double sb[4];
@@ -317,26 +305,27 @@ fh_status field_points_impl(fh_ctx* c, const fh_quad* q, double lambda, double z
     FH_TRY(iphi_table(c, k, d2.nf, d2.m, &ip2));
     FftPlan* fp = nullptr;
     FH_TRY(fft_plan(c, d1.m, d2.m, 1, &fp));
+    FH_TRY(counters_ready(c, ntiles));
     const size_t fine_count = 2 * (size_t)d1.nf * d2.nf;
     const size_t up_count = 2 * (size_t)d1.m * d2.m;
-    size_t need = aligned_bytes(rs * fine_count) + aligned_bytes(rs * up_count) + spread_bytes(N, gg, ntiles, rs);
-    if (mem == FH_MEM_HOST) need += 2 * aligned_bytes(sizeof(double) * M) + aligned_bytes(2 * rs * M);
+    const size_t need = aligned_bytes(rs * fine_count) + aligned_bytes(rs * up_count) +
+                        spread_bytes(N, gg, ntiles, rs) + (host ? 2 * cbytes : 0) +
+                        (stage_out ? obytes : 0);
     FH_TRY(arena_reserve(c, need));
     R* fine = c->arena.take<R>(fine_count);
     R* up = c->arena.take<R>(up_count);
     SpreadBufs sbuf = spread_carve(c, N, gg, ntiles, rs);
     const double* dxi = xi;
     const double* deta = eta;
-    R* dout = static_cast<R*>(u);
-    if (mem == FH_MEM_HOST) {
+    if (host) {
         double* a = c->arena.take<double>(M);
         double* b = c->arena.take<double>(M);
         FH_HIP(hipMemcpyAsync(a, xi, sizeof(double) * M, hipMemcpyHostToDevice, c->stream));
         FH_HIP(hipMemcpyAsync(b, eta, sizeof(double) * M, hipMemcpyHostToDevice, c->stream));
         dxi = a;
         deta = b;
-        dout = c->arena.take<R>(2 * M);
     }
+    if (stage_out) *staged = dout = c->arena.take<R>(2 * M);
 
     InstParams ip{};
     ip.x = q->x;
@@ -367,6 +356,7 @@ fh_status field_points_impl(fh_ctx* c, const fh_quad* q, double lambda, double z
     tp.invlz = 1.0 / lz;
     tp.Cx = d1.C;
     tp.Cy = d2.C;
+    for (int i = 0; i < 4; ++i) tp.box[i] = tb[i];
     tp.occ = occ ? 1 : 0;
     tp.ch1 = inv_phi_cheb_cached(c, k, d1.theta_max);
     tp.ch2 = inv_phi_cheb_cached(c, k, d2.theta_max);
@@ -378,13 +368,60 @@ fh_status field_points_impl(fh_ctx* c, const fh_quad* q, double lambda, double z
     FH_HIP(hipGetLastError());
     FH_TRY(fft_exec(c, fp, up));
     timing_mark(c, 3);
-    FH_TRY(launch_interp<R>(c, k.w, up, dxi, deta, M, k.beta, k.poly, tp, nullptr, dout));
+    FH_TRY(launch_interp<R>(c, k.w, up, dxi, deta, M, k.beta, k.poly, tp, perm, dout));
     timing_mark(c, 4);
     timing_mark(c, 5);
+    return FH_OK;
+}
+
+template <class R>
+fh_status field_points_impl(fh_ctx* c, const fh_quad* q, double lambda, double z, int64_t M, const double* xi,
+                            const double* eta, int occ, void* u, fh_memspace mem)
+{
+    const size_t rs = sizeof(R);
+    if (M == 0) return FH_OK;
+    // target bounding box
+    double tb[4];
     if (mem == FH_MEM_HOST) {
-        FH_HIP(hipMemcpyAsync(u, dout, 2 * rs * M, hipMemcpyDeviceToHost, c->stream));
-        FH_HIP(hipStreamSynchronize(c->stream));
+        tb[0] = tb[2] = INFINITY;
+        tb[1] = tb[3] = -INFINITY;
+        for (int64_t k = 0; k < M; ++k) {
+            FH_ARG(std::isfinite(xi[k]) && std::isfinite(eta[k]), FH_ERR_NONFINITE, "target %lld not finite",
+                   (long long)k);
+            tb[0] = std::min(tb[0], xi[k]);
+            tb[1] = std::max(tb[1], xi[k]);
+            tb[2] = std::min(tb[2], eta[k]);
+            tb[3] = std::max(tb[3], eta[k]);
+        }
+    } else {
+        FH_TRY(device_bbox(c, xi, eta, M, tb));
     }
+    if (mem == FH_MEM_DEVICE)
+        return t3_core<R>(c, q, lambda, z, M, xi, eta, nullptr, tb, occ, static_cast<R*>(u), false, false,
+                          nullptr);
+    R* staged = nullptr;
+    FH_TRY(t3_core<R>(c, q, lambda, z, M, xi, eta, nullptr, tb, occ, nullptr, true, true, &staged));
+    FH_HIP(hipMemcpyAsync(u, staged, 2 * rs * M, hipMemcpyDeviceToHost, c->stream));
+    FH_HIP(hipStreamSynchronize(c->stream));
+    return FH_OK;
+}
+
+// Field at a target set (sorted device coordinates, output scattered back
+// to the caller's order through perm); no host synchronisation unless the
+// output is host memory.
+template <class R>
+fh_status field_targets_impl(fh_ctx* c, const fh_quad* q, double lambda, double z, const fh_targets* t, int occ,
+                             void* u, fh_memspace mem)
+{
+    const int64_t M = t->M;
+    if (M == 0) return FH_OK;
+    if (mem == FH_MEM_DEVICE)
+        return t3_core<R>(c, q, lambda, z, M, t->xs, t->ys, t->perm, t->box, occ, static_cast<R*>(u), false,
+                          false, nullptr);
+    R* staged = nullptr;
+    FH_TRY(t3_core<R>(c, q, lambda, z, M, t->xs, t->ys, t->perm, t->box, occ, nullptr, false, true, &staged));
+    FH_HIP(hipMemcpyAsync(u, staged, 2 * sizeof(R) * M, hipMemcpyDeviceToHost, c->stream));
+    FH_HIP(hipStreamSynchronize(c->stream));
     return FH_OK;
 }
 
@@ -398,6 +435,30 @@ fh_status launch_zero(fh_ctx* c, void* p, size_t bytes)
     const unsigned g = (unsigned)std::min<size_t>((n16 + 255) / 256, (size_t)c->cu_count * 16);
     hipLaunchKernelGGL(k_zero16, dim3(g), dim3(256), 0, c->stream, static_cast<uint4*>(p), n16);
     FH_HIP(hipGetLastError());
+    return FH_OK;
+}
+
+fh_status counters_ready(fh_ctx* c, int64_t n)
+{
+    n = std::max<int64_t>(n, 1);
+    if (n > c->tile_cnt_cap) {
+        if (c->tile_cnt) {
+            FH_HIP(hipStreamSynchronize(c->stream));
+            FH_TRY(dev_free(c, c->tile_cnt));
+            c->tile_cnt = nullptr;
+            c->tile_cnt_cap = 0;
+        }
+        const int64_t cap = std::max<int64_t>(n + n / 4, 4096);
+        void* p = nullptr;
+        FH_TRY(dev_alloc(c, sizeof(int) * (size_t)cap, &p));
+        c->tile_cnt = static_cast<int*>(p);
+        c->tile_cnt_cap = cap;
+        c->tile_cnt_dirty = true;
+    }
+    if (c->tile_cnt_dirty) {
+        FH_TRY(launch_zero(c, c->tile_cnt, sizeof(int) * (size_t)c->tile_cnt_cap));
+        c->tile_cnt_dirty = false;
+    }
     return FH_OK;
 }
 
@@ -493,6 +554,165 @@ fh_status fh_field_points(fh_ctx* c, const fh_quad* q, double lambda, double z, 
         FH_HIP(hipSetDevice(c->device));
         if (c->prec == FH_FP64) return field_points_impl<double>(c, q, lambda, z, M, xi, eta, occulter, u, mem);
         return field_points_impl<float>(c, q, lambda, z, M, xi, eta, occulter, u, mem);
+    } catch (...) {
+        set_error("host allocation failed");
+        return FH_ERR_ALLOC;
+    }
+}
+
+fh_status fh_targets_create(fh_ctx* c, int64_t M, const double* xi, const double* eta, const double* box,
+                            fh_memspace mem, fh_targets** out)
+{
+    try {
+        FH_ARG(c && out, FH_ERR_INVALID_ARG, "NULL argument");
+        *out = nullptr;
+        FH_ARG(M >= 0 && M < ((int64_t)1 << 31), FH_ERR_INVALID_ARG, "M must be in [0, 2^31)");
+        FH_ARG(M == 0 || (xi && eta), FH_ERR_INVALID_ARG, "NULL target array");
+        FH_ARG(mem == FH_MEM_HOST || mem == FH_MEM_DEVICE, FH_ERR_INVALID_ARG, "bad memspace");
+        if (box) {
+            for (int i = 0; i < 4; ++i) FH_ARG(std::isfinite(box[i]), FH_ERR_NONFINITE, "box not finite");
+            FH_ARG(box[0] <= box[1] && box[2] <= box[3], FH_ERR_INVALID_ARG, "box needs xmin <= xmax, ymin <= ymax");
+        }
+        FH_HIP(hipSetDevice(c->device));
+        std::unique_ptr<fh_targets> t(new fh_targets());
+        t->ctx = c;
+        t->M = M;
+        const size_t cb = aligned_bytes(sizeof(double) * (size_t)std::max<int64_t>(M, 1));
+        const size_t pb = aligned_bytes(sizeof(int) * (size_t)std::max<int64_t>(M, 1));
+        t->buf_bytes = 2 * cb + pb;
+        auto it = c->pool.find(t->buf_bytes);
+        if (it != c->pool.end() && !it->second.empty()) {
+            t->buf = it->second.back();
+            it->second.pop_back();
+        } else {
+            FH_TRY(dev_alloc(c, t->buf_bytes, &t->buf));
+        }
+        t->xs = static_cast<double*>(t->buf);
+        t->ys = reinterpret_cast<double*>(static_cast<char*>(t->buf) + cb);
+        t->perm = reinterpret_cast<int*>(static_cast<char*>(t->buf) + 2 * cb);
+        auto fail = [&](fh_status s) {
+            c->pool[t->buf_bytes].push_back(t->buf);
+            return s;
+        };
+        if (M == 0) {
+            if (box)
+                for (int i = 0; i < 4; ++i) t->box[i] = box[i];
+            *out = t.release();
+            return FH_OK;
+        }
+        // box: declared, or the bounding box (host loop, or a device
+        // reduction read back once)
+        double tb[4];
+        if (box) {
+            for (int i = 0; i < 4; ++i) tb[i] = box[i];
+        } else if (mem == FH_MEM_HOST) {
+            tb[0] = tb[2] = INFINITY;
+            tb[1] = tb[3] = -INFINITY;
+            for (int64_t k = 0; k < M; ++k) {
+                if (!(std::isfinite(xi[k]) && std::isfinite(eta[k]))) {
+                    set_error("target %lld not finite", (long long)k);
+                    return fail(FH_ERR_NONFINITE);
+                }
+                tb[0] = std::min(tb[0], xi[k]);
+                tb[1] = std::max(tb[1], xi[k]);
+                tb[2] = std::min(tb[2], eta[k]);
+                tb[3] = std::max(tb[3], eta[k]);
+            }
+        } else {
+            fh_status s = device_bbox(c, xi, eta, M, tb);
+            if (s != FH_OK) return fail(s);
+        }
+        for (int i = 0; i < 4; ++i) t->box[i] = tb[i];
+        // sort by cell: counts, ranks and offsets in the arena
+        if (!c->tgt_cnt) {
+            void* p = nullptr;
+            fh_status s0 = dev_alloc(c, sizeof(int) * kTgtKeys, &p);
+            if (s0 != FH_OK) return fail(s0);
+            c->tgt_cnt = static_cast<int*>(p);
+            c->tgt_cnt_dirty = true;
+        }
+        if (c->tgt_cnt_dirty) {
+            fh_status s0 = launch_zero(c, c->tgt_cnt, sizeof(int) * kTgtKeys);
+            if (s0 != FH_OK) return fail(s0);
+            c->tgt_cnt_dirty = false;
+        }
+        const size_t need = (mem == FH_MEM_HOST ? 2 * cb : 0) + aligned_bytes(sizeof(int) * kTgtKeys) + 2 * pb;
+        fh_status s = arena_reserve(c, need);
+        if (s != FH_OK) return fail(s);
+        const double* dxi = xi;
+        const double* deta = eta;
+        if (mem == FH_MEM_HOST) {
+            double* a = c->arena.take<double>(M);
+            double* b = c->arena.take<double>(M);
+            FH_HIP(hipMemcpyAsync(a, xi, sizeof(double) * M, hipMemcpyHostToDevice, c->stream));
+            FH_HIP(hipMemcpyAsync(b, eta, sizeof(double) * M, hipMemcpyHostToDevice, c->stream));
+            dxi = a;
+            deta = b;
+        }
+        int* cnt = c->tgt_cnt;  // zero here; the scan zeroes it again
+        int* off = c->arena.take<int>(kTgtKeys);
+        int* key = c->arena.take<int>(M);
+        int* rank = c->arena.take<int>(M);
+        const double ex = tb[1] - tb[0], ey = tb[3] - tb[2];
+        const double ix = ex > 0 ? kTgtSide / ex : 0.0, iy = ey > 0 ? kTgtSide / ey : 0.0;
+        c->tgt_cnt_dirty = true;
+        hipLaunchKernelGGL(k_tgt_count, dim3(nblocks(M, 256)), dim3(256), 0, c->stream, dxi, deta, M, tb[0], ix,
+                           tb[2], iy, cnt, key, rank);
+        hipLaunchKernelGGL(k_tgt_scan, dim3(1), dim3(1024), 0, c->stream, cnt, off);
+        hipLaunchKernelGGL(k_tgt_place, dim3(nblocks(M, 256)), dim3(256), 0, c->stream, dxi, deta, M, key, rank,
+                           off, t->xs, t->ys, t->perm);
+        FH_HIP(hipGetLastError());
+        c->tgt_cnt_dirty = false;
+        // host arrays may be released by the caller on return
+        if (mem == FH_MEM_HOST) FH_HIP(hipStreamSynchronize(c->stream));
+        *out = t.release();
+        return FH_OK;
+    } catch (...) {
+        set_error("host allocation failed");
+        return FH_ERR_ALLOC;
+    }
+}
+
+fh_status fh_targets_size(const fh_targets* t, int64_t* M)
+{
+    FH_ARG(t && M, FH_ERR_INVALID_ARG, "NULL argument");
+    *M = t->M;
+    return FH_OK;
+}
+
+fh_status fh_targets_box(const fh_targets* t, double* box)
+{
+    FH_ARG(t && box, FH_ERR_INVALID_ARG, "NULL argument");
+    for (int i = 0; i < 4; ++i) box[i] = t->box[i];
+    return FH_OK;
+}
+
+fh_status fh_targets_destroy(fh_targets* t)
+{
+    if (!t) return FH_OK;
+    try {
+        t->ctx->pool[t->buf_bytes].push_back(t->buf);
+    } catch (...) {
+        (void)dev_free(t->ctx, t->buf);
+    }
+    delete t;
+    return FH_OK;
+}
+
+fh_status fh_field_targets(fh_ctx* c, const fh_quad* q, double lambda, double z, const fh_targets* t,
+                           int32_t occulter, void* u, fh_memspace mem)
+{
+    try {
+        FH_ARG(c && q && t, FH_ERR_INVALID_ARG, "NULL argument");
+        FH_ARG(q->ctx->device == c->device, FH_ERR_INVALID_ARG, "quadrature lives on another device");
+        FH_ARG(t->ctx->device == c->device, FH_ERR_INVALID_ARG, "target set lives on another device");
+        FH_ARG(t->M == 0 || u, FH_ERR_INVALID_ARG, "NULL output array");
+        FH_ARG(mem == FH_MEM_HOST || mem == FH_MEM_DEVICE, FH_ERR_INVALID_ARG, "bad memspace");
+        FH_TRY(check_lz(lambda, z));
+        FH_ARG(q->N < ((int64_t)1 << 31), FH_ERR_UNSUPPORTED, "at most 2^31 - 1 nodes per call");
+        FH_HIP(hipSetDevice(c->device));
+        if (c->prec == FH_FP64) return field_targets_impl<double>(c, q, lambda, z, t, occulter, u, mem);
+        return field_targets_impl<float>(c, q, lambda, z, t, occulter, u, mem);
     } catch (...) {
         set_error("host allocation failed");
         return FH_ERR_ALLOC;

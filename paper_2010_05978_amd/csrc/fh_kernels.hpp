@@ -718,7 +718,7 @@ __global__ void __launch_bounds__(256) k_merge_slots(typename V2<R>::T* __restri
 template <class R>
 __global__ void __launch_bounds__(256) k_reduce_tiles(const typename V2<R>::T* __restrict__ slots,
                                                       const int* __restrict__ tsub, GridGeom gg, int tpi,
-                                                      int ntiles_total, R* __restrict__ F)
+                                                      int ntiles_total, R* __restrict__ F, int* __restrict__ cnt)
 {
     using C = typename V2<R>::T;
     const int T = gg.T, TT = T * T;
@@ -726,6 +726,9 @@ __global__ void __launch_bounds__(256) k_reduce_tiles(const typename V2<R>::T* _
     const int reach = (L - 1) / T;  // tiles back that a padded tile reaches
     C* Fv = reinterpret_cast<C*>(F);
     for (int tile = blockIdx.x; tile < ntiles_total; tile += gridDim.x) {
+        // the binning counters of the call are spent: leave them at zero
+        // for the next one
+        if (threadIdx.x == 0) cnt[tile] = 0;
         const int b = tile / tpi, tl = tile - b * tpi;
         const int ty = tl / gg.ntx, tx = tl - ty * gg.ntx;
         // does any work item cover this tile?  (uniform)
@@ -957,6 +960,7 @@ struct T3Params {
     double th1, th2;        // theta per unit (xi - xic) for the 1/Phi correction
     double inv2lz, invlz;   // target chirp (turns) and 1/(lambda z)
     double Cx, Cy;          // source centre (post-phase exp(-i s.C))
+    double box[4];          // targets the grids were planned for; others give NaN
     int occ;
     InvPhiCheb ch1, ch2;
 };
@@ -1001,7 +1005,9 @@ __device__ __forceinline__ R group_sum(R v)
 template <int W>
 constexpr int interp_group() { return W <= 8 ? 8 : (W <= 16 ? 16 : 32); }
 
-// Wavefront per 64 targets.  Lane l first handles target l of the chunk on
+// Wavefront per 64 targets, read at index t of (xi, eta) and written to
+// u[perm[t]] (u[t] without perm); a target outside tp.box, or with a
+// non-finite coordinate, gets NaN.  Lane l first handles target l of the chunk on
 // its own: stencil cell, the 2W kernel values (staged in LDS), and the
 // 1/Phi correction, chirp and 1/(i lambda z) factor.  The wavefront then
 // gathers in trips of 64/GS targets: GS lanes per target, lane r taking
@@ -1025,8 +1031,10 @@ __global__ void __launch_bounds__(64) k_t3_interp(const R* __restrict__ G, const
     for (int64_t base = blockIdx.x * (int64_t)64; base < M; base += (int64_t)gridDim.x * 64) {
         const int64_t t = base + lane;
         const bool live = t < M;
-        const int64_t k = live ? (perm ? (int64_t)perm[t] : t) : 0;
-        const double X = xi[k], Y = eta[k];
+        const int64_t ti = live ? t : 0;
+        const int64_t k = perm ? (int64_t)perm[ti] : ti;  // output index
+        const double X = xi[ti], Y = eta[ti];
+        const bool inbox = X >= tp.box[0] && X <= tp.box[1] && Y >= tp.box[2] && Y <= tp.box[3];
         int l1, l2;
         double d1, d2;
         bool ok1, ok2;
@@ -1091,7 +1099,7 @@ __global__ void __launch_bounds__(64) k_t3_interp(const R* __restrict__ G, const
             const C v = res[lane];
             double re = (double)v.x * fr - (double)v.y * fi;
             double im = (double)v.x * fi + (double)v.y * fr;
-            if (!(ok1 && ok2)) {
+            if (!(ok1 && ok2 && inbox)) {
                 re = __builtin_nan("");
                 im = __builtin_nan("");
             }
@@ -1168,6 +1176,99 @@ __global__ void __launch_bounds__(256) k_bbox_final(const double* __restrict__ p
     }
     if (threadIdx.x == 0)
         for (int q = 0; q < 5; ++q) out[q] = s[q][0];
+}
+
+// --------------------------------------------------------- target sets
+// Counting sort of scattered targets by the Morton index of their cell in a
+// kTgtSide x kTgtSide grid over the target box: consecutive sorted targets
+// are spatially close, so the type-3 interpolation of one wavefront reads
+// overlapping stencils of the upsampled grid.  The order within a cell is
+// arbitrary; every target's value is computed on its own, so results do not
+// depend on it.
+constexpr int kTgtBits = 6;
+constexpr int kTgtSide = 1 << kTgtBits;
+constexpr int kTgtKeys = kTgtSide * kTgtSide;
+
+__device__ __forceinline__ uint32_t spread_bits8(uint32_t v)
+{
+    v = (v | (v << 4)) & 0x0f0fu;
+    v = (v | (v << 2)) & 0x3333u;
+    v = (v | (v << 1)) & 0x5555u;
+    return v;
+}
+
+__device__ __forceinline__ int tgt_cell(double v, double lo, double inv)
+{
+    const double q = (v - lo) * inv;
+    // NaN and out-of-box coordinates land in an edge cell
+    return q >= 0.0 ? (q < (double)(kTgtSide - 1) ? (int)q : kTgtSide - 1) : 0;
+}
+
+__global__ void __launch_bounds__(256) k_tgt_count(const double* __restrict__ xi, const double* __restrict__ eta,
+                                                   int64_t M, double x0, double ix, double y0, double iy,
+                                                   int* __restrict__ cnt, int* __restrict__ key,
+                                                   int* __restrict__ rank)
+{
+    const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (k >= M) return;
+    const uint32_t cx = (uint32_t)tgt_cell(xi[k], x0, ix), cy = (uint32_t)tgt_cell(eta[k], y0, iy);
+    const int kk = (int)(spread_bits8(cx) | (spread_bits8(cy) << 1));
+    key[k] = kk;
+    rank[k] = atomicAdd(&cnt[kk], 1);
+}
+
+// Exclusive scan of kTgtKeys counts by one block of 1024 threads; the
+// counts are left at zero for the next sort.
+__global__ void __launch_bounds__(1024) k_tgt_scan(int* __restrict__ cnt, int* __restrict__ off)
+{
+    constexpr int per = kTgtKeys / 1024;
+    __shared__ int wsum[16];
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    int cv[per];
+    int loc = 0;
+#pragma unroll
+    for (int i = 0; i < per; ++i) {
+        cv[i] = cnt[t * per + i];
+        cnt[t * per + i] = 0;
+        loc += cv[i];
+    }
+    int inc = loc;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int v = __shfl_up(inc, o);
+        if (lane >= o) inc += v;
+    }
+    if (lane == 63) wsum[wv] = inc;
+    __syncthreads();
+    if (t == 0) {
+        int a = 0;
+        for (int i = 0; i < 16; ++i) {
+            const int v = wsum[i];
+            wsum[i] = a;
+            a += v;
+        }
+    }
+    __syncthreads();
+    int run = inc - loc + wsum[wv];
+#pragma unroll
+    for (int i = 0; i < per; ++i) {
+        off[t * per + i] = run;
+        run += cv[i];
+    }
+}
+
+__global__ void __launch_bounds__(256) k_tgt_place(const double* __restrict__ xi, const double* __restrict__ eta,
+                                                   int64_t M, const int* __restrict__ key,
+                                                   const int* __restrict__ rank, const int* __restrict__ off,
+                                                   double* __restrict__ xs, double* __restrict__ ys,
+                                                   int* __restrict__ perm)
+{
+    const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (k >= M) return;
+    const int64_t p = (int64_t)off[key[k]] + rank[k];
+    xs[p] = xi[k];
+    ys[p] = eta[k];
+    perm[p] = (int)k;
 }
 
 // ------------------------------------------------------- launch helpers
@@ -1267,7 +1368,7 @@ struct T1Plan {
 size_t spread_bytes(int64_t Ntot, const GridGeom& gg, int ntiles_total, size_t rsize)
 {
     const int64_t max_sub = Ntot / gg.P + std::min<int64_t>(Ntot, ntiles_total) + 1;
-    return 2 * aligned_bytes(sizeof(int) * (size_t)ntiles_total) + aligned_bytes(2 * sizeof(int) * ntiles_total) +
+    return aligned_bytes(sizeof(int) * (size_t)ntiles_total) + aligned_bytes(2 * sizeof(int) * ntiles_total) +
            aligned_bytes(2 * sizeof(int) * (size_t)(ntiles_total / kScanChunk + 1)) +
            aligned_bytes(sizeof(int) * Ntot) + aligned_bytes(sizeof(uint32_t) * Ntot) +
            2 * aligned_bytes(2 * rsize * Ntot) + aligned_bytes(sizeof(Sub) * max_sub) + aligned_bytes(sizeof(int)) +
@@ -1278,7 +1379,7 @@ SpreadBufs spread_carve(fh_ctx* c, int64_t Ntot, const GridGeom& gg, int ntiles_
 {
     SpreadBufs b;
     b.max_sub = Ntot / gg.P + std::min<int64_t>(Ntot, ntiles_total) + 1;
-    b.cnt = c->arena.take<int>(ntiles_total);
+    b.cnt = c->tile_cnt;  // persistent, zero between calls (counters_ready)
     b.off = c->arena.take<int>(ntiles_total);
     b.tsub = c->arena.take<int>(2 * (size_t)ntiles_total);
     b.rank = c->arena.take<int>(Ntot);
@@ -1299,7 +1400,9 @@ fh_status run_spread(fh_ctx* c, const InstParams& p0, const InstParams* table, i
 {
     const int tpi = gg.ntx * gg.nty;
     const int ntiles_total = tpi * ninst;
-    FH_TRY(launch_zero(c, b.cnt, sizeof(int) * ntiles_total));
+    // the counters are zero on entry (counters_ready) and k_reduce_tiles
+    // zeroes them again; until it is enqueued they count as dirty
+    c->tile_cnt_dirty = true;
     if (Ntot > 0) {
         hipLaunchKernelGGL(k_bin_count, dim3(nblocks(Ntot, kBinBlock)), dim3(kBinBlock), 0, c->stream, p0, table,
                            ninst, Ntot,
@@ -1340,8 +1443,9 @@ fh_status run_spread(fh_ctx* c, const InstParams& p0, const InstParams* table, i
     const unsigned rgrid = (unsigned)std::max<int64_t>(
         1, std::min<int64_t>(ntiles_total, (int64_t)c->cu_count * 16));
     hipLaunchKernelGGL((k_reduce_tiles<R>), dim3(rgrid), dim3(256), 0, c->stream,
-                       (const typename V2<R>::T*)b.slots, b.tsub, gg, tpi, ntiles_total, F);
+                       (const typename V2<R>::T*)b.slots, b.tsub, gg, tpi, ntiles_total, F, b.cnt);
     FH_HIP(hipGetLastError());
+    c->tile_cnt_dirty = false;
     return FH_OK;
 }
 

@@ -115,6 +115,7 @@ class Workload:
     z: float
     grid: Grid | None = None
     points: tuple | None = None            # (xi, eta) float64 arrays
+    pupil: float | None = None             # the points lie in the disk |x| < pupil
     occulter: bool = False
     lams: list = field(default_factory=list)
 
@@ -142,13 +143,13 @@ def workload(wid: int, reduced: bool = False) -> Workload:
         pts = disk_points_uniform(100_000, 1.5, g)
         # Fresnel number 20 at the maximum radius 1.3 -> lambda z = 1.69/20
         return Workload("starfish_F20", shape, lam=5.0e-7, z=0.0845 / 5.0e-7,
-                        grid=Grid(1000, 1000, 0.003, 0.003), points=pts)
+                        grid=Grid(1000, 1000, 0.003, 0.003), points=pts, pupil=1.5)
     if wid == 3:
         shape = Starshade(24, 6.0, 12.0, 6.0, 6.0, m=320, np_=100, nd=720, md=320)
         g = rng(3)
         pts = disk_points_uniform(1_000_000, 2.4, g)
         return Workload("starshade24", shape, lam=0.5e-6, z=3.7e7,
-                        grid=Grid(2048, 2048, 4.8 / 2048, 4.8 / 2048), points=pts,
+                        grid=Grid(2048, 2048, 4.8 / 2048, 4.8 / 2048), points=pts, pupil=2.4,
                         occulter=True, lams=[0.5e-6, 0.75e-6, 1.0e-6])
     if wid == 5:
         K = 8
