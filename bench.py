@@ -158,9 +158,10 @@ def roofline(res, prec, wl):
         "spread": {"kernel": f"k_spread_wave<{'double' if rs == 8 else 'float'}, {W}, false>", "ms": (g[1] + pt[1]) / 2,
                    "launches": 2, "bound": "alu", "unit": "GB/s", "peak": LDS_PEAK_GBS,
                    "bytes": N * W * W * 2 * rs},
-        # epilogue: read one complex fine-grid value and write one output per target
-        "epilogue": {"kernel": f"k_epilogue_t1<{'double' if rs == 8 else 'float'}>", "ms": g[3], "launches": 1,
-                     "bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK_GBS, "bytes": n1 * n2 * 4 * rs},
+        # type-1 column pass + epilogue: at least one complex output written per
+        # target (the band it reads is not counted)
+        "t1_cols": {"kernel": f"k_t1_cols<{'double' if rs == 8 else 'float'}>", "ms": g[3], "launches": 1,
+                    "bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK_GBS, "bytes": n1 * n2 * 2 * rs},
         # interpolation: target coordinates and index in, one output out
         "interp": {"kernel": f"k_t3_interp<{'double' if rs == 8 else 'float'}, {W}>", "ms": pt[3], "launches": 1,
                    "bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK_GBS, "bytes": M3 * (16 + 4 + 2 * rs)},

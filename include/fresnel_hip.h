@@ -74,7 +74,9 @@ typedef struct fh_targets fh_targets;
  * fine-grid cells; sigma is the fine-grid upsampling factor (2 or 1.25, the
  * two factors the paper reports for its FFTs, sec. 3.1). */
 typedef struct fh_options {
-    double sigma;           /* 2.0 or 1.25                                   */
+    double sigma;           /* 2.0 or 1.25 (in FH_MIXED, 1.25 amplifies the  *
+                             * FP32 rounding near the band edge and suits    *
+                             * tolerances of 1e-4 and looser)                */
     int32_t kernel_width;   /* 2..20 cells                                   */
     double beta;            /* kernel shape parameter                        */
     int32_t tile;           /* spread tile edge in cells: 8, 16, 32 or 64    */

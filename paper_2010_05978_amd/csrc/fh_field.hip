@@ -27,6 +27,55 @@
 
 namespace fh {
 
+// Sequences per workgroup for an LDS FFT of length n over `count`
+// sequences: as many as give `min_bytes` of contiguous output per row segment
+// (64 bytes, or `min_c` sequences), more while there are over two
+// workgroups per CU, within the LDS budget and the 16-sequence limit of the
+// column kernel.  C = 0 when one sequence does not fit or n has a prime
+// factor above 7.
+struct LdsCols {
+    int C = 0;
+    size_t lds = 0;
+    bool small = false;  // C n <= kLdsFftSmall: the 256-thread shape
+    LdsFftPlan plan;
+};
+
+LdsCols lds_cols_plan(const fh_ctx* c, int n, int64_t count, size_t rs, int min_c = 0)
+{
+    LdsCols r;
+    // FH_FFT=rocfft in the environment keeps every transform on rocFFT
+    static const bool force_rocfft = [] {
+        const char* e = std::getenv("FH_FFT");
+        return e && std::strcmp(e, "rocfft") == 0;
+    }();
+    if (force_rocfft) return r;
+    const size_t cb = 2 * rs;
+    if (!lds_fft_plan(n, r.plan)) return r;
+    // data of C sequences and the twiddle table in one block's LDS
+    const int cap = (int)((kLdsFftBytes - 512 - cb * (size_t)r.plan.ntw) / (cb * (size_t)n));
+    if (cap < 1) return r;
+    int C = min_c > 0 ? min_c : std::max(1, (int)(64 / cb));
+    const int64_t want = std::max<int64_t>(1, count / (2 * (int64_t)c->cu_count));
+    C = (int)std::max<int64_t>(C, std::min<int64_t>(want, 16));
+    C = std::min({C, cap, 16});
+    // rather fewer sequences per block than the 512-thread shape
+    while (C > 1 && n * C > kLdsFftSmall && n * (C / 2) >= 1 && n <= kLdsFftSmall) C /= 2;
+    r.C = C;
+    r.lds = cb * ((size_t)n * C + r.plan.ntw);
+    r.small = n * C <= kLdsFftSmall;
+    return r;
+}
+
+// Launch one of the LDS FFT kernels in the block shape that `lc` picked.
+#define FH_LDS_LAUNCH(KERNEL, R, lc, grid, stream, ...)                                                        \
+    do {                                                                                                         \
+        if ((lc).small)                                                                                          \
+            hipLaunchKernelGGL((KERNEL<R, kLdsFftSmall, 256>), grid, dim3(256), (lc).lds, stream, __VA_ARGS__);  \
+        else                                                                                                     \
+            hipLaunchKernelGGL((KERNEL<R, (int)(kLdsFftBytes / (2 * sizeof(R))), 512>), grid, dim3(512), (lc).lds, \
+                               stream, __VA_ARGS__);                                                             \
+    } while (0)
+
 // The type-1 pipeline for B instances sharing one grid geometry; u is device
 // memory (B x n2 x n1).  With `capture`, the launch sequence is recorded into
 // a hipGraph keyed by everything baked into it and replayed.
@@ -86,11 +135,15 @@ fh_status t1_pipeline(fh_ctx* c, int B, const fh_quad* const* qs, const double* 
     FftPlan* fa = nullptr;
     FftPlan* fb = nullptr;
     FH_TRY(fft_plan(c, gg.nf1, 0, gg.rows * B, &fa));
-    FH_TRY(fft_plan(c, gg.nf2, 0, n1 * B, &fb));
+    // second pass: in LDS, fused with the epilogue, when a column fits
+    LdsCols lc = lds_cols_plan(c, gg.nf2, (int64_t)n1 * B, rs);
+    // its epilogue keeps a row factor (16 bytes) per unread mode of a column
+    if ((size_t)(gg.nf2 - n2) * 2 * rs < 16) lc.C = 0;
+    if (lc.C == 0) FH_TRY(fft_plan(c, gg.nf2, 0, n1 * B, &fb));
 
     FH_TRY(counters_ready(c, (int64_t)tpi * B));
     const size_t F_count = 2 * (size_t)B * gg.rows * gg.nf1;
-    const size_t Z_count = 2 * (size_t)B * n1 * gg.nf2;
+    const size_t Z_count = lc.C > 0 ? 0 : 2 * (size_t)B * n1 * gg.nf2;
     size_t need = aligned_bytes(rs * F_count) + aligned_bytes(rs * Z_count) +
                   spread_bytes(Ntot, gg, tpi * B, rs) + aligned_bytes(sizeof(InstParams) * B) +
                   aligned_bytes(sizeof(EpiInst) * B) + aligned_bytes(extra_bytes);
@@ -112,16 +165,25 @@ fh_status t1_pipeline(fh_ctx* c, int B, const fh_quad* const* qs, const double* 
         timing_mark(c, 0);
         FH_TRY(run_spread<R>(c, inst[0], batched ? dinst : nullptr, B, Ntot, gg, sb, F, pl.k.beta, pl.k.poly));
         FH_TRY(fft_exec(c, fa, F));
-        hipLaunchKernelGGL((k_transpose_pad<R>), dim3(nblocks(n1, 32), nblocks(gg.nf2, 32), B), dim3(256), 0,
-                           c->stream, F, Z, n1, gg.nf1, gg.nf2, gg.rows);
-        FH_HIP(hipGetLastError());
-        FH_TRY(fft_exec(c, fb, Z));
-        timing_mark(c, 3);
         EpiParams ep{n1, n2, gg.nf1, gg.nf2, h1, h2, xc, yc, ip1, ip2};
-        hipLaunchKernelGGL((k_epilogue_t1<R>), dim3(nblocks(n1, 32), nblocks(n2, 32), B), dim3(256), 0, c->stream,
-                           Z, u, ep, epi[0], batched ? (const EpiInst*)depi : nullptr);
-        FH_HIP(hipGetLastError());
-        timing_mark(c, 4);
+        if (lc.C > 0) {
+            timing_mark(c, 3);
+            const int groups = (n1 + lc.C - 1) / lc.C;
+            FH_LDS_LAUNCH(k_t1_cols, R, lc, dim3(xcd_blocks(groups), B), c->stream, F, u, gg.rows, lc.C, groups,
+                          lc.plan, ep, epi[0], batched ? (const EpiInst*)depi : nullptr);
+            FH_HIP(hipGetLastError());
+            timing_mark(c, 4);
+        } else {
+            hipLaunchKernelGGL((k_transpose_pad<R>), dim3(nblocks(n1, 32), nblocks(gg.nf2, 32), B), dim3(256), 0,
+                               c->stream, F, Z, n1, gg.nf1, gg.nf2, gg.rows);
+            FH_HIP(hipGetLastError());
+            FH_TRY(fft_exec(c, fb, Z));
+            timing_mark(c, 3);
+            hipLaunchKernelGGL((k_epilogue_t1<R>), dim3(nblocks(n1, 32), nblocks(n2, 32), B), dim3(256), 0,
+                               c->stream, Z, u, ep, epi[0], batched ? (const EpiInst*)depi : nullptr);
+            FH_HIP(hipGetLastError());
+            timing_mark(c, 4);
+        }
         timing_mark(c, 5);
         return FH_OK;
     };
@@ -304,7 +366,12 @@ fh_status t3_core(fh_ctx* c, const fh_quad* q, double lambda, double z, int64_t 
     FH_TRY(iphi_table(c, k, d1.nf, d1.m, &ip1));
     FH_TRY(iphi_table(c, k, d2.nf, d2.m, &ip2));
     FftPlan* fp = nullptr;
-    FH_TRY(fft_plan(c, d1.m, d2.m, 1, &fp));
+    // upsampled 2D FFT: rows (with the precorrection) and columns in LDS
+    // when a row and a column fit, else rocFFT
+    LdsCols lr = lds_cols_plan(c, d1.m, d2.m, rs, 1);
+    LdsCols lcol = lds_cols_plan(c, d2.m, d1.m, rs);
+    const bool lds2d = lr.C > 0 && lcol.C > 0;
+    if (!lds2d) FH_TRY(fft_plan(c, d1.m, d2.m, 1, &fp));
     FH_TRY(counters_ready(c, ntiles));
     const size_t fine_count = 2 * (size_t)d1.nf * d2.nf;
     const size_t up_count = 2 * (size_t)d1.m * d2.m;
@@ -363,10 +430,18 @@ fh_status t3_core(fh_ctx* c, const fh_quad* q, double lambda, double z, int64_t 
 
     timing_mark(c, 0);
     FH_TRY(run_spread<R>(c, ip, nullptr, 1, N, gg, sbuf, fine, k.beta, k.poly));
-    hipLaunchKernelGGL((k_t3_precorrect<R>), dim3(nblocks(d1.m, 256), d2.m), dim3(256), 0, c->stream, fine, d1.nf,
-                       d2.nf, up, d1.m, d2.m, ip1, ip2);
-    FH_HIP(hipGetLastError());
-    FH_TRY(fft_exec(c, fp, up));
+    if (lds2d) {
+        const int gr = (d2.m + lr.C - 1) / lr.C, gc = (d1.m + lcol.C - 1) / lcol.C;
+        FH_LDS_LAUNCH(k_t3_rows, R, lr, dim3(xcd_blocks(gr)), c->stream, fine, d1.nf, d2.nf, up, d1.m, d2.m, lr.C,
+                      gr, lr.plan, ip1, ip2);
+        FH_LDS_LAUNCH(k_t3_cols, R, lcol, dim3(xcd_blocks(gc)), c->stream, up, d1.m, d2.m, lcol.C, gc, lcol.plan);
+        FH_HIP(hipGetLastError());
+    } else {
+        hipLaunchKernelGGL((k_t3_precorrect<R>), dim3(nblocks(d1.m, 256), d2.m), dim3(256), 0, c->stream, fine,
+                           d1.nf, d2.nf, up, d1.m, d2.m, ip1, ip2);
+        FH_HIP(hipGetLastError());
+        FH_TRY(fft_exec(c, fp, up));
+    }
     timing_mark(c, 3);
     FH_TRY(launch_interp<R>(c, k.w, up, dxi, deta, M, k.beta, k.poly, tp, perm, dout));
     timing_mark(c, 4);

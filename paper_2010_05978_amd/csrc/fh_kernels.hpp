@@ -12,6 +12,7 @@
 #include <cstring>
 
 #include "fh_common.hpp"
+#include "fh_fft.hpp"
 
 namespace fh {
 namespace {
@@ -924,6 +925,196 @@ __global__ void __launch_bounds__(256) k_epilogue_t1(const R* __restrict__ Z, R*
         out.x = (R)re;
         out.y = (R)im;
         reinterpret_cast<C2*>(u)[((size_t)b * ep.n2 + k2i) * ep.n1 + k1i] = out;
+    }
+}
+
+// Type-1 second pass and epilogue in one kernel.  Workgroup (group g,
+// instance b) takes the C output columns k1 + n1/2 in [g C, g C + C): it
+// loads their band of `rows` values from F (after the first pass over the
+// rows), zero-pads each to nf2 in LDS, transforms, and writes
+// u[b][k2][k1] = epilogue(column value at k2 mod nf2) for every k2, with the
+// factors of k_epilogue_t1 (each phase reduced in turns before sincospi).
+template <class R, int MAXE, int NT>
+__global__ void __launch_bounds__(NT) k_t1_cols(const R* __restrict__ F, R* __restrict__ u, int rows,
+                                                            int C, int groups, LdsFftPlan plan, EpiParams ep,
+                                                            EpiInst e0, const EpiInst* __restrict__ table)
+{
+    using C2 = typename V2<R>::T;
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    C2* buf = reinterpret_cast<C2*>(lds_raw);
+    __shared__ double2 E1[16];
+    const int g = xcd_group(groups);
+    if (g >= groups) return;
+    const int b = blockIdx.y;
+    const EpiInst ei = table ? table[b] : e0;
+    const int nf2 = plan.n;
+    const int col0 = g * C;
+    const int ncol = min(C, ep.n1 - col0);
+    // column factors: target chirp over 1/Phi
+    if ((int)threadIdx.x < C) {
+        double2 f = make_double2(0.0, 0.0);
+        const int ki = col0 + threadIdx.x;
+        if (ki < ep.n1) {
+            const double x = ep.xc + ep.h1 * (ki - ep.n1 / 2);
+            double tt = x * x * ei.inv2lz;
+            tt -= rint(tt);
+            double sn, cs;
+            sincospi(2.0 * tt, &sn, &cs);
+            const double sc = ep.iphi1[ki];
+            f = make_double2(cs * sc, sn * sc);
+        }
+        E1[threadIdx.x] = f;
+    }
+    // band of the C columns (adjacent lanes read adjacent columns of a row)
+    const C2* Fv = reinterpret_cast<const C2*>(F) + (size_t)b * rows * ep.nf1;
+    for (int e = threadIdx.x; e < C * nf2; e += NT) {
+        const int r = e / C, c = e - r * C;
+        C2 v;
+        v.x = R(0);
+        v.y = R(0);
+        if (r < rows && c < ncol) {
+            int col = col0 + c - ep.n1 / 2;
+            if (col < 0) col += ep.nf1;
+            v = Fv[(size_t)r * ep.nf1 + col];
+        }
+        buf[c * nf2 + r] = v;
+    }
+    __syncthreads();
+    lds_fft<MAXE, NT>(buf, plan, C, buf + (size_t)C * plan.n);
+    // Epilogue in chunks of rows.  The row factors (target chirp, window
+    // shift exp(-2 pi i k2 sh2/nf2), 1/Phi2) of a chunk are computed once
+    // into entries of the column buffers that no output reads (modes n2/2
+    // to nf2 - n2/2 - 1 of every column), then C lanes write C consecutive
+    // outputs of each row.  `cap` row factors (two doubles each) fit in one
+    // column's unread entries; the host only picks this kernel when cap >= 1.
+    const int sm = (int)(((long long)ei.sh2 % nf2 + nf2) % nf2);
+    const int cap = (int)((size_t)(nf2 - ep.n2) * sizeof(C2) / (2 * sizeof(double)));
+    const int chunk = min(ep.n2, cap * C);
+    auto slot = [&](int t) -> double* {
+        const int col = t / cap, off = t - col * cap;
+        return reinterpret_cast<double*>(buf + (size_t)col * nf2 + ep.n2 / 2) + 2 * off;
+    };
+    C2* uv = reinterpret_cast<C2*>(u) + (size_t)b * ep.n2 * ep.n1;
+    for (int r0 = 0; r0 < ep.n2; r0 += chunk) {
+        const int nr = min(chunk, ep.n2 - r0);
+        __syncthreads();
+        for (int t = threadIdx.x; t < nr; t += NT) {
+            const int k2i = r0 + t;
+            const int k2 = k2i - ep.n2 / 2;
+            const double y = ep.yc + ep.h2 * k2;
+            double tt = y * y * ei.inv2lz;
+            const unsigned km = (unsigned)(k2 < 0 ? k2 + nf2 : k2);
+            const unsigned ph = (km * (unsigned)sm) % (unsigned)nf2;
+            tt = (tt - rint(tt)) - (double)ph / (double)nf2;
+            tt -= rint(tt);
+            double sn, cs;
+            sincospi(2.0 * tt, &sn, &cs);
+            const double sc = ep.iphi2[k2i];
+            double* p = slot(t);
+            p[0] = cs * sc;
+            p[1] = sn * sc;
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < nr * C; e += NT) {
+            const int t = e / C, c = e - t * C;
+            if (c >= ncol) continue;
+            const int k2i = r0 + t;
+            const int k2 = k2i - ep.n2 / 2;
+            const int r = k2 < 0 ? k2 + nf2 : k2;
+            const C2 fv = buf[(size_t)c * nf2 + r];
+            const double* p = slot(t);
+            const double erx = p[0], ery = p[1];
+            const double2 a = E1[c];
+            const double ar = a.x * erx - a.y * ery, ai = a.x * ery + a.y * erx;
+            const double wr = (double)fv.x * ar - (double)fv.y * ai;
+            const double wi = (double)fv.x * ai + (double)fv.y * ar;
+            // times 1/(i lambda z)
+            double re = wi * ei.invlz;
+            double im = -wr * ei.invlz;
+            if (ei.occ) {
+                re = 1.0 - re;
+                im = -im;
+            }
+            C2 out;
+            out.x = (R)re;
+            out.y = (R)im;
+            uv[(size_t)k2i * ep.n1 + col0 + c] = out;
+        }
+    }
+}
+
+// Type-3 precorrection and row pass.  Workgroup g takes the C rows
+// [g C, g C + C) of the m1 x m2 upsampled grid G: entry (k1, k2) is
+// b[k2 mod nf2][k1 mod nf1] / (Phi1 Phi2) for modes inside the spread grid
+// (-nf/2 <= k < nf - nf/2), zero outside; each row is transformed and
+// written back to G.
+template <class R, int MAXE, int NT>
+__global__ void __launch_bounds__(NT) k_t3_rows(const R* __restrict__ bgrid, int nf1, int nf2,
+                                                            R* __restrict__ G, int m1, int m2, int C, int groups,
+                                                            LdsFftPlan plan, const double* __restrict__ ip1,
+                                                            const double* __restrict__ ip2)
+{
+    using C2 = typename V2<R>::T;
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    C2* buf = reinterpret_cast<C2*>(lds_raw);
+    const int g = xcd_group(groups);
+    if (g >= groups) return;
+    const int row0 = g * C;
+    const int nrow = min(C, m2 - row0);
+    const C2* bv = reinterpret_cast<const C2*>(bgrid);
+    for (int e = threadIdx.x; e < C * m1; e += NT) {
+        const int c = e / m1, i1 = e - c * m1;
+        C2 v;
+        v.x = R(0);
+        v.y = R(0);
+        if (c < nrow) {
+            const int i2 = row0 + c;
+            const int k1 = i1 < m1 / 2 ? i1 : i1 - m1;
+            const int k2 = i2 < m2 / 2 ? i2 : i2 - m2;
+            if (k1 >= -(nf1 / 2) && k1 < nf1 - nf1 / 2 && k2 >= -(nf2 / 2) && k2 < nf2 - nf2 / 2) {
+                const int s1 = k1 < 0 ? k1 + nf1 : k1;
+                const int s2 = k2 < 0 ? k2 + nf2 : k2;
+                const C2 x = bv[(size_t)s2 * nf1 + s1];
+                const double sc = ip1[k1 + nf1 / 2] * ip2[k2 + nf2 / 2];
+                v.x = (R)(x.x * sc);
+                v.y = (R)(x.y * sc);
+            }
+        }
+        buf[e] = v;
+    }
+    __syncthreads();
+    lds_fft<MAXE, NT>(buf, plan, C, buf + (size_t)C * plan.n);
+    C2* Gv = reinterpret_cast<C2*>(G);
+    for (int e = threadIdx.x; e < nrow * m1; e += NT) Gv[(size_t)row0 * m1 + e] = buf[e];
+}
+
+// Type-3 column pass, in place: workgroup g transforms the C columns
+// [g C, g C + C) of G (length m2 each).
+template <class R, int MAXE, int NT>
+__global__ void __launch_bounds__(NT) k_t3_cols(R* __restrict__ G, int m1, int m2, int C, int groups,
+                                                            LdsFftPlan plan)
+{
+    using C2 = typename V2<R>::T;
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    C2* buf = reinterpret_cast<C2*>(lds_raw);
+    const int g = xcd_group(groups);
+    if (g >= groups) return;
+    const int col0 = g * C;
+    const int ncol = min(C, m1 - col0);
+    C2* Gv = reinterpret_cast<C2*>(G);
+    for (int e = threadIdx.x; e < C * m2; e += NT) {
+        const int i2 = e / C, c = e - i2 * C;
+        C2 v;
+        v.x = R(0);
+        v.y = R(0);
+        if (c < ncol) v = Gv[(size_t)i2 * m1 + col0 + c];
+        buf[c * m2 + i2] = v;
+    }
+    __syncthreads();
+    lds_fft<MAXE, NT>(buf, plan, C, buf + (size_t)C * plan.n);
+    for (int e = threadIdx.x; e < C * m2; e += NT) {
+        const int i2 = e / C, c = e - i2 * C;
+        if (c < ncol) Gv[(size_t)i2 * m1 + col0 + c] = buf[c * m2 + i2];
     }
 }
 

@@ -5,8 +5,9 @@
 // trapezoid rule), the periodic trapezoid rule (eq. ptr), and Gauss-Legendre
 // nodes along polygon edges.  The dilation areal rule (eqs. aqnod/aqwei,
 // sec. 3.1) and the starshade disc + petal rule (sec. 3.2) turn them into
-// areal nodes and weights.  One thread per boundary node, then one thread per
-// areal node; every coordinate is double.
+// areal nodes and weights.  Generated rules run as one kernel, a block of
+// areal nodes evaluating the boundary nodes it needs into LDS first; every
+// coordinate is double.
 #include <algorithm>
 #include <cstring>
 
@@ -24,21 +25,17 @@ struct RadialParams {
     double b[kMaxFourier];
 };
 
-// Boundary node i of the star-shaped curve r(t)(cos t, sin t).
-__global__ void k_bdry_radial(RadialParams rp, const double* __restrict__ gl, int64_t n,
-                              double* __restrict__ X, double* __restrict__ Y,
-                              double* __restrict__ Wv, double* __restrict__ Vv)
+// Boundary node i of the star-shaped curve r(t)(cos t, sin t) and its
+// vector weight (W, V) = x'(t) omega.
+__device__ __forceinline__ void radial_node(const RadialParams& rp, const double* __restrict__ gl, int64_t n,
+                                            int64_t i, double& X, double& Y, double& W, double& V)
 {
-    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= n) return;
     double t, om;
     if (rp.panels > 0) {
         const int p = (int)(i / rp.q), k = (int)(i % rp.q);
-        const double xg = gl[k], wg = gl[rp.q + k];
-        t = (2.0 * kPi / rp.panels) * (p + 0.5 * (1.0 + xg));
-        om = (kPi / rp.panels) * wg;
+        t = (2.0 * kPi / rp.panels) * (p + 0.5 * (1.0 + gl[k]));
+        om = (kPi / rp.panels) * gl[rp.q + k];
     } else {
-        // trapezoid nodes t_i = 2 pi i / n, i = 1..n
         t = 2.0 * kPi * (double)(i + 1) / (double)n;
         om = 2.0 * kPi / (double)n;
     }
@@ -51,10 +48,44 @@ __global__ void k_bdry_radial(RadialParams rp, const double* __restrict__ gl, in
     }
     double st, ct;
     sincos(t, &st, &ct);
-    X[i] = r * ct;
-    Y[i] = r * st;
-    Wv[i] = om * (dr * ct - r * st);
-    Vv[i] = om * (dr * st + r * ct);
+    X = r * ct;
+    Y = r * st;
+    W = om * (dr * ct - r * st);
+    V = om * (dr * st + r * ct);
+}
+
+// Boundary rule and dilation in one pass: a block of 256 areal nodes
+// j = l + i m first evaluates the boundary nodes i it touches (one thread
+// each, through LDS), then every thread dilates its own node.
+__global__ void __launch_bounds__(256) k_radial_rule(RadialParams rp, const double* __restrict__ glq, int64_t n,
+                                                     int m, const double* __restrict__ glm, double* __restrict__ x,
+                                                     double* __restrict__ y, double* __restrict__ w)
+{
+    __shared__ double sb[4][256];
+    const int64_t j0 = blockIdx.x * (int64_t)blockDim.x;
+    const int64_t i0 = j0 / m;
+    const int64_t jl = min(j0 + (int64_t)blockDim.x, n * m) - 1;
+    const int nb = (int)(jl / m - i0) + 1;  // at most 256 boundary nodes
+    if ((int)threadIdx.x < nb) {
+        double X, Y, W, V;
+        radial_node(rp, glq, n, i0 + threadIdx.x, X, Y, W, V);
+        sb[0][threadIdx.x] = X;
+        sb[1][threadIdx.x] = Y;
+        sb[2][threadIdx.x] = W;
+        sb[3][threadIdx.x] = V;
+    }
+    __syncthreads();
+    const int64_t j = j0 + threadIdx.x;
+    if (j >= n * m) return;
+    const int64_t i = j / m;
+    const int l = (int)(j - i * m);
+    const int bi = (int)(i - i0);
+    const double al = 0.5 * (1.0 + glm[l]);
+    const double wl = 0.5 * glm[m + l];
+    const double Xi = sb[0][bi], Yi = sb[1][bi];
+    x[j] = al * Xi;
+    y[j] = al * Yi;
+    w[j] = al * wl * (Xi * sb[3][bi] - Yi * sb[2][bi]);
 }
 
 // Gauss-Legendre nodes along each straight edge of a CCW polygon.
@@ -74,6 +105,51 @@ __global__ void k_bdry_polygon(const double* __restrict__ vx, const double* __re
     Y[i] = vy[e] + s * ey;
     Wv[i] = hw * ex;
     Vv[i] = hw * ey;
+}
+
+// Polygons of up to this many vertices travel in the kernel arguments.
+constexpr int kPolyByValue = 128;
+struct PolyParams {
+    int nv, q;
+    double vx[kPolyByValue];
+    double vy[kPolyByValue];
+};
+
+// Polygon edge rule and dilation in one pass (as k_radial_rule).
+__global__ void __launch_bounds__(256) k_polygon_rule(PolyParams pp, const double* __restrict__ glq, int m,
+                                                      const double* __restrict__ glm, double* __restrict__ x,
+                                                      double* __restrict__ y, double* __restrict__ w)
+{
+    __shared__ double sb[4][256];
+    const int64_t n = (int64_t)pp.nv * pp.q;
+    const int64_t j0 = blockIdx.x * (int64_t)blockDim.x;
+    const int64_t i0 = j0 / m;
+    const int64_t jl = min(j0 + (int64_t)blockDim.x, n * m) - 1;
+    const int nb = (int)(jl / m - i0) + 1;
+    if ((int)threadIdx.x < nb) {
+        const int64_t i = i0 + threadIdx.x;
+        const int e = (int)(i / pp.q), k = (int)(i % pp.q);
+        const int f = (e + 1 == pp.nv) ? 0 : e + 1;
+        const double ex = pp.vx[f] - pp.vx[e], ey = pp.vy[f] - pp.vy[e];
+        const double sg = 0.5 * (1.0 + glq[k]);
+        const double hw = 0.5 * glq[pp.q + k];
+        sb[0][threadIdx.x] = pp.vx[e] + sg * ex;
+        sb[1][threadIdx.x] = pp.vy[e] + sg * ey;
+        sb[2][threadIdx.x] = hw * ex;
+        sb[3][threadIdx.x] = hw * ey;
+    }
+    __syncthreads();
+    const int64_t j = j0 + threadIdx.x;
+    if (j >= n * m) return;
+    const int64_t i = j / m;
+    const int l = (int)(j - i * m);
+    const int bi = (int)(i - i0);
+    const double al = 0.5 * (1.0 + glm[l]);
+    const double wl = 0.5 * glm[m + l];
+    const double Xi = sb[0][bi], Yi = sb[1][bi];
+    x[j] = al * Xi;
+    y[j] = al * Yi;
+    w[j] = al * wl * (Xi * sb[3][bi] - Yi * sb[2][bi]);
 }
 
 // Dilation rule: node j = l + i m takes alpha_l (X_i, Y_i) with weight
@@ -157,15 +233,8 @@ fh_status radial_into(fh_ctx* c, const RadialParams& rp, int64_t n, int m, doubl
     const double* glm = nullptr;
     if (rp.panels > 0) FH_TRY(gl_table(c, rp.q, &glq));
     FH_TRY(gl_table(c, m, &glm));
-    FH_TRY(arena_reserve(c, 4 * aligned_bytes(sizeof(double) * n)));
-    double* X = c->arena.take<double>(n);
-    double* Y = c->arena.take<double>(n);
-    double* Wv = c->arena.take<double>(n);
-    double* Vv = c->arena.take<double>(n);
-    hipLaunchKernelGGL(k_bdry_radial, dim3(nblocks(n, 256)), dim3(256), 0, c->stream, rp, glq, n, X,
-                       Y, Wv, Vv);
-    hipLaunchKernelGGL(k_dilation, dim3(nblocks(n * m, 256)), dim3(256), 0, c->stream, X, Y, Wv, Vv,
-                       n, m, glm, x, y, w);
+    hipLaunchKernelGGL(k_radial_rule, dim3(nblocks(n * m, 256)), dim3(256), 0, c->stream, rp, glq, n, m, glm, x, y,
+                       w);
     FH_HIP(hipGetLastError());
     return FH_OK;
 }
@@ -235,6 +304,30 @@ fh_status fh_quad_polygon(fh_ctx* c, const double* vx, const double* vy, int32_t
         const int64_t n = (int64_t)nv * q;
         fh_quad* qd = nullptr;
         FH_TRY(quad_alloc(c, n * m, &qd));
+        // nodes lie on segments from the origin to the boundary
+        double bb[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int i = 0; i < nv; ++i) {
+            bb[0] = std::min(bb[0], vx[i]);
+            bb[1] = std::max(bb[1], vx[i]);
+            bb[2] = std::min(bb[2], vy[i]);
+            bb[3] = std::max(bb[3], vy[i]);
+        }
+        if (nv <= kPolyByValue) {
+            // vertices in the kernel arguments: no copy, no synchronisation
+            PolyParams pp{};
+            pp.nv = nv;
+            pp.q = q;
+            for (int i = 0; i < nv; ++i) {
+                pp.vx[i] = vx[i];
+                pp.vy[i] = vy[i];
+            }
+            hipLaunchKernelGGL(k_polygon_rule, dim3(nblocks(n * m, 256)), dim3(256), 0, c->stream, pp, glq, m, glm,
+                               qd->x, qd->y, qd->w);
+            FH_HIP(hipGetLastError());
+            set_bbox(qd, bb[0], bb[1], bb[2], bb[3]);
+            *out = qd;
+            return FH_OK;
+        }
         fh_status s = arena_reserve(c, 4 * aligned_bytes(sizeof(double) * n) +
                                            2 * aligned_bytes(sizeof(double) * nv));
         if (s != FH_OK) {
@@ -256,14 +349,6 @@ fh_status fh_quad_polygon(fh_ctx* c, const double* vx, const double* vy, int32_t
         FH_HIP(hipGetLastError());
         // the host vertex arrays may be released by the caller on return
         FH_HIP(hipStreamSynchronize(c->stream));
-        // nodes lie on segments from the origin to the boundary
-        double bb[4] = {0.0, 0.0, 0.0, 0.0};
-        for (int i = 0; i < nv; ++i) {
-            bb[0] = std::min(bb[0], vx[i]);
-            bb[1] = std::max(bb[1], vx[i]);
-            bb[2] = std::min(bb[2], vy[i]);
-            bb[3] = std::max(bb[3], vy[i]);
-        }
         set_bbox(qd, bb[0], bb[1], bb[2], bb[3]);
         *out = qd;
         return FH_OK;
@@ -374,16 +459,11 @@ fh_status fh_quad_starshade(fh_ctx* c, int32_t Np, double a, double R, double b,
         fh_quad* qd = nullptr;
         FH_TRY(quad_alloc(c, N, &qd));
         const size_t ncoef = coef ? (size_t)2 * Np * K : 0;
-        fh_status s = arena_reserve(c, 4 * aligned_bytes(sizeof(double) * std::max(nd, 1)) +
-                                           aligned_bytes(sizeof(double) * std::max<size_t>(ncoef, 1)));
+        fh_status s = arena_reserve(c, aligned_bytes(sizeof(double) * std::max<size_t>(ncoef, 1)));
         if (s != FH_OK) {
             fh_quad_destroy(qd);
             return s;
         }
-        double* X = c->arena.take<double>(nd);
-        double* Y = c->arena.take<double>(nd);
-        double* Wv = c->arena.take<double>(nd);
-        double* Vv = c->arena.take<double>(nd);
         const double* dcoef = coef;
         if (coef && coef_mem == FH_MEM_HOST) {
             double* dc = c->arena.take<double>(ncoef);
@@ -397,10 +477,8 @@ fh_status fh_quad_starshade(fh_ctx* c, int32_t Np, double a, double R, double b,
             rp.K = 0;
             rp.panels = 0;
             rp.q = nd;
-            hipLaunchKernelGGL(k_bdry_radial, dim3(nblocks(nd, 256)), dim3(256), 0, c->stream, rp,
-                               (const double*)nullptr, (int64_t)nd, X, Y, Wv, Vv);
-            hipLaunchKernelGGL(k_dilation, dim3(nblocks(Nd, 256)), dim3(256), 0, c->stream, X, Y, Wv, Vv,
-                               (int64_t)nd, md, glmd, qd->x, qd->y, qd->w);
+            hipLaunchKernelGGL(k_radial_rule, dim3(nblocks(Nd, 256)), dim3(256), 0, c->stream, rp,
+                               (const double*)nullptr, (int64_t)nd, md, glmd, qd->x, qd->y, qd->w);
         }
         PetalParams pp{Np, m, np, coef ? K : 0, a, R, b, p, Nd};
         hipLaunchKernelGGL(k_petals, dim3(nblocks((int64_t)Np * np * m, 256)), dim3(256), 0, c->stream,

@@ -98,6 +98,24 @@ def test_quadrature_polygon_perturbed_starshade_and_boundary(fh):
     c.close()
 
 
+@pytest.mark.parametrize("nv", [3, 128, 129, 300])
+def test_quadrature_polygon_vertex_counts(fh, nv):
+    # up to 128 vertices travel in the kernel arguments, more go through
+    # device memory: both give the oracle's rule
+    c = fh.Context("fp64")
+    g = np.random.Generator(np.random.PCG64(300 + nv))
+    t = np.sort(g.uniform(0, 2 * math.pi, nv))
+    r = 1.0 + 0.2 * g.uniform(-1, 1, nv)
+    vx, vy = r * np.cos(t), r * np.sin(t)
+    q = c.quad_polygon(vx, vy, 5, 7)
+    x, y, w = (cpu(a) for a in q.export())
+    xo, yo, wo = oracle.quad_polygon(vx, vy, 5, 7)
+    assert len(x) == nv * 35
+    assert np.abs(x - xo).max() <= 1e-14 and np.abs(y - yo).max() <= 1e-14
+    assert np.abs(w - wo).max() <= 1e-14 * np.abs(wo).max()
+    c.close()
+
+
 # --------------------------------------------------------------- type 1
 def test_grid_workload1_full(ctx):
     wl = workloads.workload(1)
