@@ -68,9 +68,9 @@ class Step:
     grid (type 1) and at the scattered targets (type 3).  The two field calls
     are independent, so they run on two streams (two contexts sharing the
     rule) and the type-3 call's small, latency-bound kernels overlap the
-    type-1 work.  The scattered targets become a target set every step
-    (device sort), planned on the pupil's box |x|, |y| <= 1.5 that the
-    workload draws them in, so no call reads anything back to the host."""
+    type-1 work.  The scattered targets become a target set every step,
+    planned on the pupil's box |x|, |y| <= 1.5 that the workload draws them
+    in, so no call reads anything back to the host."""
 
     def __init__(self, fh, precision, wl, dev):
         import torch

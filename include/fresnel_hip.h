@@ -200,19 +200,21 @@ fh_status fh_field_points(fh_ctx* ctx, const fh_quad* q, double lambda, double z
 
 /* Scattered-target set for repeated type-3 evaluation (sec. 2.1's targets;
  * the paper's sweeps evaluate many wavelengths and shapes at one fixed set of
- * pupil points, sec. 4.3).  Copies the M targets (xi, eta in `mem`) into a
- * library-owned object, sorted on the device into the Morton order of a
- * 64 x 64 cell grid over the target box so that the interpolation of
- * neighbouring targets reads neighbouring grid entries.
- *   box (host, 4 doubles xmin, xmax, ymin, ymax, or NULL): the region the
- *     type-3 grids are planned for.  With a box the call does not
- *     synchronise (device arrays) and targets outside it, or with a
- *     non-finite coordinate, get NaN from fh_field_targets.  With NULL the
- *     bounding box is computed (device arrays: one readback, which
- *     synchronises the stream) and a non-finite target is FH_ERR_NONFINITE.
- *   M must be below 2^31; M = 0 gives an empty set.  Host arrays may be
- *   released on return.  Ownership and stream ordering are as for rules:
- *   fh_targets_destroy hands the memory back to the making context. */
+ * pupil points, sec. 4.3): the M targets (xi, eta in `mem`) and the box the
+ * type-3 grids are planned for.
+ *   Device arrays are used in place: they must stay allocated and unchanged
+ *   while the set is in use (stream order as for any input).  Host arrays
+ *   are copied to library memory (one synchronisation) and may be released
+ *   on return.
+ *   box (host, 4 doubles xmin, xmax, ymin, ymax, or NULL): with a box the
+ *     call does no device work and no synchronisation, and targets outside
+ *     it, or with a non-finite coordinate, get NaN from fh_field_targets.
+ *     With NULL the bounding box is computed (device arrays: one readback,
+ *     which synchronises the stream) and a non-finite target is
+ *     FH_ERR_NONFINITE.
+ *   M must be below 2^31; M = 0 gives an empty set.  fh_targets_destroy
+ *   hands any copy back to the making context's memory pool (stream order
+ *   as for rules). */
 fh_status fh_targets_create(fh_ctx* ctx, int64_t M, const double* xi, const double* eta,
                             const double* box, fh_memspace mem, fh_targets** out);
 fh_status fh_targets_size(const fh_targets* t, int64_t* M);

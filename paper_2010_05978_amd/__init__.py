@@ -53,7 +53,8 @@ class Quad:
 
 
 class Targets:
-    """A device-resident, spatially sorted set of scattered targets."""
+    """Scattered targets and their planning box for repeated type-3 calls
+    (device arrays are referenced: keep them alive and unchanged)."""
 
     def __init__(self, ctx: "Context", handle):
         self.ctx = ctx
@@ -130,7 +131,9 @@ class Context:
     def targets(self, xi, eta, box=None) -> Targets:
         """Target set for repeated type-3 calls; box = (xmin, xmax, ymin, ymax)
         declares the region (no readback), None computes it."""
-        return Targets(self, abi.fh_targets_create(self.handle, xi, eta, box))
+        t = Targets(self, abi.fh_targets_create(self.handle, xi, eta, box))
+        t._keep = (xi, eta)  # device arrays are used in place
+        return t
 
     # ------------------------------------------------------------ fields
     def field_grid(self, quad: Quad, lam, z, n1, n2, h1, h2, xc=0.0, yc=0.0, occulter=False, out=None):

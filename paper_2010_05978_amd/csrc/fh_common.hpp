@@ -194,15 +194,12 @@ struct fh_ctx {
     double* bbox_dev = nullptr;      // bounding-box reduction scratch
     double* bbox_host = nullptr;     // pinned readback of the box
     // Binning counters kept at zero between calls: the tile counts of the
-    // spread (zeroed again by the reduce that ends each spread) and the cell
-    // counts of the target sort (zeroed by its scan).  A call that stops
-    // between the count and the reset marks them dirty, and the next call
-    // clears them first.
+    // spread, zeroed again by the reduce that ends each spread.  A call that
+    // stops between the count and the reset leaves them dirty, and the next
+    // call clears them first.
     int* tile_cnt = nullptr;
     int64_t tile_cnt_cap = 0;
     bool tile_cnt_dirty = false;
-    int* tgt_cnt = nullptr;
-    bool tgt_cnt_dirty = false;
     uint64_t* order_sig = nullptr;   // fh_order_after: counter written by this stream
     uint64_t order_seq = 0;          // last value enqueued for it
 };
@@ -219,17 +216,15 @@ struct fh_quad {
     double bbox[4] = {0, 0, 0, 0};  // xmin, xmax, ymin, ymax
 };
 
-// A scattered-target set: coordinates in a spatially sorted order (Morton
-// order of a 64 x 64 cell grid over the box), the original index of every
-// sorted target, and the box the type-3 grids are planned from.
+// A scattered-target set: the device coordinates (the caller's arrays, or a
+// library copy of host arrays) and the box the type-3 grids are planned from.
 struct fh_targets {
     fh_ctx* ctx = nullptr;
     int64_t M = 0;
-    void* buf = nullptr;  // xs[M], ys[M] (double) then perm[M] (int)
+    void* buf = nullptr;  // library copy (host input): xs[M], ys[M]
     size_t buf_bytes = 0;
-    double* xs = nullptr;
-    double* ys = nullptr;
-    int* perm = nullptr;
+    const double* xs = nullptr;
+    const double* ys = nullptr;
     double box[4] = {0, 0, 0, 0};  // xmin, xmax, ymin, ymax
 };
 

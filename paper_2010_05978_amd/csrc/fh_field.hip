@@ -309,12 +309,12 @@ fh_status field_grid_impl(fh_ctx* c, const fh_quad* q, double lambda, double z, 
 
 // Type-3 evaluation at targets (xi_t, eta_t), t < M, all inside the box tb
 // (xmin, xmax, ymin, ymax) the grids are planned from; the value of target t
-// goes to dout[perm[t]] (dout[t] without perm).  With `host`, xi and eta are
+// goes to dout[t].  With `host`, xi and eta are
 // host arrays copied into the arena; with `host` or `stage_out` the field is
 // written to arena staging returned in *staged, for the caller to copy back.
 template <class R>
 fh_status t3_core(fh_ctx* c, const fh_quad* q, double lambda, double z, int64_t M, const double* xi,
-                  const double* eta, const int* perm, const double* tb, int occ, R* dout, bool host,
+                  const double* eta, const double* tb, int occ, R* dout, bool host,
                   bool stage_out, R** staged)
 {
     stage_out = stage_out || host;
@@ -443,7 +443,7 @@ fh_status t3_core(fh_ctx* c, const fh_quad* q, double lambda, double z, int64_t 
         FH_TRY(fft_exec(c, fp, up));
     }
     timing_mark(c, 3);
-    FH_TRY(launch_interp<R>(c, k.w, up, dxi, deta, M, k.beta, k.poly, tp, perm, dout));
+    FH_TRY(launch_interp<R>(c, k.w, up, dxi, deta, M, k.beta, k.poly, tp, dout));
     timing_mark(c, 4);
     timing_mark(c, 5);
     return FH_OK;
@@ -472,18 +472,17 @@ fh_status field_points_impl(fh_ctx* c, const fh_quad* q, double lambda, double z
         FH_TRY(device_bbox(c, xi, eta, M, tb));
     }
     if (mem == FH_MEM_DEVICE)
-        return t3_core<R>(c, q, lambda, z, M, xi, eta, nullptr, tb, occ, static_cast<R*>(u), false, false,
+        return t3_core<R>(c, q, lambda, z, M, xi, eta, tb, occ, static_cast<R*>(u), false, false,
                           nullptr);
     R* staged = nullptr;
-    FH_TRY(t3_core<R>(c, q, lambda, z, M, xi, eta, nullptr, tb, occ, nullptr, true, true, &staged));
+    FH_TRY(t3_core<R>(c, q, lambda, z, M, xi, eta, tb, occ, nullptr, true, true, &staged));
     FH_HIP(hipMemcpyAsync(u, staged, 2 * rs * M, hipMemcpyDeviceToHost, c->stream));
     FH_HIP(hipStreamSynchronize(c->stream));
     return FH_OK;
 }
 
-// Field at a target set (sorted device coordinates, output scattered back
-// to the caller's order through perm); no host synchronisation unless the
-// output is host memory.
+// Field at a target set; no host synchronisation unless the output is host
+// memory.
 template <class R>
 fh_status field_targets_impl(fh_ctx* c, const fh_quad* q, double lambda, double z, const fh_targets* t, int occ,
                              void* u, fh_memspace mem)
@@ -491,10 +490,10 @@ fh_status field_targets_impl(fh_ctx* c, const fh_quad* q, double lambda, double 
     const int64_t M = t->M;
     if (M == 0) return FH_OK;
     if (mem == FH_MEM_DEVICE)
-        return t3_core<R>(c, q, lambda, z, M, t->xs, t->ys, t->perm, t->box, occ, static_cast<R*>(u), false,
+        return t3_core<R>(c, q, lambda, z, M, t->xs, t->ys, t->box, occ, static_cast<R*>(u), false,
                           false, nullptr);
     R* staged = nullptr;
-    FH_TRY(t3_core<R>(c, q, lambda, z, M, t->xs, t->ys, t->perm, t->box, occ, nullptr, false, true, &staged));
+    FH_TRY(t3_core<R>(c, q, lambda, z, M, t->xs, t->ys, t->box, occ, nullptr, false, true, &staged));
     FH_HIP(hipMemcpyAsync(u, staged, 2 * sizeof(R) * M, hipMemcpyDeviceToHost, c->stream));
     FH_HIP(hipStreamSynchronize(c->stream));
     return FH_OK;
@@ -652,94 +651,56 @@ fh_status fh_targets_create(fh_ctx* c, int64_t M, const double* xi, const double
         std::unique_ptr<fh_targets> t(new fh_targets());
         t->ctx = c;
         t->M = M;
-        const size_t cb = aligned_bytes(sizeof(double) * (size_t)std::max<int64_t>(M, 1));
-        const size_t pb = aligned_bytes(sizeof(int) * (size_t)std::max<int64_t>(M, 1));
-        t->buf_bytes = 2 * cb + pb;
-        auto it = c->pool.find(t->buf_bytes);
-        if (it != c->pool.end() && !it->second.empty()) {
-            t->buf = it->second.back();
-            it->second.pop_back();
-        } else {
-            FH_TRY(dev_alloc(c, t->buf_bytes, &t->buf));
-        }
-        t->xs = static_cast<double*>(t->buf);
-        t->ys = reinterpret_cast<double*>(static_cast<char*>(t->buf) + cb);
-        t->perm = reinterpret_cast<int*>(static_cast<char*>(t->buf) + 2 * cb);
-        auto fail = [&](fh_status s) {
-            c->pool[t->buf_bytes].push_back(t->buf);
-            return s;
-        };
-        if (M == 0) {
-            if (box)
-                for (int i = 0; i < 4; ++i) t->box[i] = box[i];
-            *out = t.release();
-            return FH_OK;
-        }
-        // box: declared, or the bounding box (host loop, or a device
-        // reduction read back once)
-        double tb[4];
+        double tb[4] = {0.0, 0.0, 0.0, 0.0};
         if (box) {
             for (int i = 0; i < 4; ++i) tb[i] = box[i];
-        } else if (mem == FH_MEM_HOST) {
+        } else if (M > 0 && mem == FH_MEM_HOST) {
             tb[0] = tb[2] = INFINITY;
             tb[1] = tb[3] = -INFINITY;
             for (int64_t k = 0; k < M; ++k) {
-                if (!(std::isfinite(xi[k]) && std::isfinite(eta[k]))) {
-                    set_error("target %lld not finite", (long long)k);
-                    return fail(FH_ERR_NONFINITE);
-                }
+                FH_ARG(std::isfinite(xi[k]) && std::isfinite(eta[k]), FH_ERR_NONFINITE, "target %lld not finite",
+                       (long long)k);
                 tb[0] = std::min(tb[0], xi[k]);
                 tb[1] = std::max(tb[1], xi[k]);
                 tb[2] = std::min(tb[2], eta[k]);
                 tb[3] = std::max(tb[3], eta[k]);
             }
-        } else {
-            fh_status s = device_bbox(c, xi, eta, M, tb);
-            if (s != FH_OK) return fail(s);
+        } else if (M > 0) {
+            FH_TRY(device_bbox(c, xi, eta, M, tb));
         }
         for (int i = 0; i < 4; ++i) t->box[i] = tb[i];
-        // sort by cell: counts, ranks and offsets in the arena
-        if (!c->tgt_cnt) {
-            void* p = nullptr;
-            fh_status s0 = dev_alloc(c, sizeof(int) * kTgtKeys, &p);
-            if (s0 != FH_OK) return fail(s0);
-            c->tgt_cnt = static_cast<int*>(p);
-            c->tgt_cnt_dirty = true;
+        if (mem == FH_MEM_DEVICE || M == 0) {
+            // device arrays are used in place
+            t->xs = xi;
+            t->ys = eta;
+            *out = t.release();
+            return FH_OK;
         }
-        if (c->tgt_cnt_dirty) {
-            fh_status s0 = launch_zero(c, c->tgt_cnt, sizeof(int) * kTgtKeys);
-            if (s0 != FH_OK) return fail(s0);
-            c->tgt_cnt_dirty = false;
+        // host arrays: a library copy (the caller may release them on return)
+        const size_t cb = aligned_bytes(sizeof(double) * (size_t)M);
+        t->buf_bytes = 2 * cb;
+        auto it = c->pool.find(t->buf_bytes);
+        void* p = nullptr;
+        if (it != c->pool.end() && !it->second.empty()) {
+            p = it->second.back();
+            it->second.pop_back();
+        } else {
+            FH_TRY(dev_alloc(c, t->buf_bytes, &p));
         }
-        const size_t need = (mem == FH_MEM_HOST ? 2 * cb : 0) + aligned_bytes(sizeof(int) * kTgtKeys) + 2 * pb;
-        fh_status s = arena_reserve(c, need);
-        if (s != FH_OK) return fail(s);
-        const double* dxi = xi;
-        const double* deta = eta;
-        if (mem == FH_MEM_HOST) {
-            double* a = c->arena.take<double>(M);
-            double* b = c->arena.take<double>(M);
-            FH_HIP(hipMemcpyAsync(a, xi, sizeof(double) * M, hipMemcpyHostToDevice, c->stream));
-            FH_HIP(hipMemcpyAsync(b, eta, sizeof(double) * M, hipMemcpyHostToDevice, c->stream));
-            dxi = a;
-            deta = b;
+        t->buf = p;
+        double* dx = static_cast<double*>(p);
+        double* dy = reinterpret_cast<double*>(static_cast<char*>(p) + cb);
+        hipError_t e1 = hipMemcpyAsync(dx, xi, sizeof(double) * M, hipMemcpyHostToDevice, c->stream);
+        hipError_t e2 = hipMemcpyAsync(dy, eta, sizeof(double) * M, hipMemcpyHostToDevice, c->stream);
+        hipError_t e3 = hipStreamSynchronize(c->stream);
+        if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
+            c->pool[t->buf_bytes].push_back(p);
+            (void)hipGetLastError();
+            set_error("copying the targets to the device failed");
+            return FH_ERR_HIP;
         }
-        int* cnt = c->tgt_cnt;  // zero here; the scan zeroes it again
-        int* off = c->arena.take<int>(kTgtKeys);
-        int* key = c->arena.take<int>(M);
-        int* rank = c->arena.take<int>(M);
-        const double ex = tb[1] - tb[0], ey = tb[3] - tb[2];
-        const double ix = ex > 0 ? kTgtSide / ex : 0.0, iy = ey > 0 ? kTgtSide / ey : 0.0;
-        c->tgt_cnt_dirty = true;
-        hipLaunchKernelGGL(k_tgt_count, dim3(nblocks(M, 256)), dim3(256), 0, c->stream, dxi, deta, M, tb[0], ix,
-                           tb[2], iy, cnt, key, rank);
-        hipLaunchKernelGGL(k_tgt_scan, dim3(1), dim3(1024), 0, c->stream, cnt, off);
-        hipLaunchKernelGGL(k_tgt_place, dim3(nblocks(M, 256)), dim3(256), 0, c->stream, dxi, deta, M, key, rank,
-                           off, t->xs, t->ys, t->perm);
-        FH_HIP(hipGetLastError());
-        c->tgt_cnt_dirty = false;
-        // host arrays may be released by the caller on return
-        if (mem == FH_MEM_HOST) FH_HIP(hipStreamSynchronize(c->stream));
+        t->xs = dx;
+        t->ys = dy;
         *out = t.release();
         return FH_OK;
     } catch (...) {
@@ -765,10 +726,12 @@ fh_status fh_targets_box(const fh_targets* t, double* box)
 fh_status fh_targets_destroy(fh_targets* t)
 {
     if (!t) return FH_OK;
-    try {
-        t->ctx->pool[t->buf_bytes].push_back(t->buf);
-    } catch (...) {
-        (void)dev_free(t->ctx, t->buf);
+    if (t->buf) {
+        try {
+            t->ctx->pool[t->buf_bytes].push_back(t->buf);
+        } catch (...) {
+            (void)dev_free(t->ctx, t->buf);
+        }
     }
     delete t;
     return FH_OK;

@@ -1196,9 +1196,8 @@ __device__ __forceinline__ R group_sum(R v)
 template <int W>
 constexpr int interp_group() { return W <= 8 ? 8 : (W <= 16 ? 16 : 32); }
 
-// Wavefront per 64 targets, read at index t of (xi, eta) and written to
-// u[perm[t]] (u[t] without perm); a target outside tp.box, or with a
-// non-finite coordinate, gets NaN.  Lane l first handles target l of the chunk on
+// Wavefront per 64 targets; a target outside tp.box, or with a non-finite
+// coordinate, gets NaN.  Lane l first handles target l of the chunk on
 // its own: stencil cell, the 2W kernel values (staged in LDS), and the
 // 1/Phi correction, chirp and 1/(i lambda z) factor.  The wavefront then
 // gathers in trips of 64/GS targets: GS lanes per target, lane r taking
@@ -1207,7 +1206,7 @@ constexpr int interp_group() { return W <= 8 ? 8 : (W <= 16 ? 16 : 32); }
 template <class R, int W>
 __global__ void __launch_bounds__(64) k_t3_interp(const R* __restrict__ G, const double* __restrict__ xi,
                                                   const double* __restrict__ eta, int64_t M, R beta,
-                                                  const R* __restrict__ poly, T3Params tp, const int* __restrict__ perm,
+                                                  const R* __restrict__ poly, T3Params tp,
                                                   R* __restrict__ u)
 {
     using C = typename V2<R>::T;
@@ -1222,9 +1221,8 @@ __global__ void __launch_bounds__(64) k_t3_interp(const R* __restrict__ G, const
     for (int64_t base = blockIdx.x * (int64_t)64; base < M; base += (int64_t)gridDim.x * 64) {
         const int64_t t = base + lane;
         const bool live = t < M;
-        const int64_t ti = live ? t : 0;
-        const int64_t k = perm ? (int64_t)perm[ti] : ti;  // output index
-        const double X = xi[ti], Y = eta[ti];
+        const int64_t k = live ? t : 0;
+        const double X = xi[k], Y = eta[k];
         const bool inbox = X >= tp.box[0] && X <= tp.box[1] && Y >= tp.box[2] && Y <= tp.box[3];
         int l1, l2;
         double d1, d2;
@@ -1369,99 +1367,6 @@ __global__ void __launch_bounds__(256) k_bbox_final(const double* __restrict__ p
         for (int q = 0; q < 5; ++q) out[q] = s[q][0];
 }
 
-// --------------------------------------------------------- target sets
-// Counting sort of scattered targets by the Morton index of their cell in a
-// kTgtSide x kTgtSide grid over the target box: consecutive sorted targets
-// are spatially close, so the type-3 interpolation of one wavefront reads
-// overlapping stencils of the upsampled grid.  The order within a cell is
-// arbitrary; every target's value is computed on its own, so results do not
-// depend on it.
-constexpr int kTgtBits = 6;
-constexpr int kTgtSide = 1 << kTgtBits;
-constexpr int kTgtKeys = kTgtSide * kTgtSide;
-
-__device__ __forceinline__ uint32_t spread_bits8(uint32_t v)
-{
-    v = (v | (v << 4)) & 0x0f0fu;
-    v = (v | (v << 2)) & 0x3333u;
-    v = (v | (v << 1)) & 0x5555u;
-    return v;
-}
-
-__device__ __forceinline__ int tgt_cell(double v, double lo, double inv)
-{
-    const double q = (v - lo) * inv;
-    // NaN and out-of-box coordinates land in an edge cell
-    return q >= 0.0 ? (q < (double)(kTgtSide - 1) ? (int)q : kTgtSide - 1) : 0;
-}
-
-__global__ void __launch_bounds__(256) k_tgt_count(const double* __restrict__ xi, const double* __restrict__ eta,
-                                                   int64_t M, double x0, double ix, double y0, double iy,
-                                                   int* __restrict__ cnt, int* __restrict__ key,
-                                                   int* __restrict__ rank)
-{
-    const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (k >= M) return;
-    const uint32_t cx = (uint32_t)tgt_cell(xi[k], x0, ix), cy = (uint32_t)tgt_cell(eta[k], y0, iy);
-    const int kk = (int)(spread_bits8(cx) | (spread_bits8(cy) << 1));
-    key[k] = kk;
-    rank[k] = atomicAdd(&cnt[kk], 1);
-}
-
-// Exclusive scan of kTgtKeys counts by one block of 1024 threads; the
-// counts are left at zero for the next sort.
-__global__ void __launch_bounds__(1024) k_tgt_scan(int* __restrict__ cnt, int* __restrict__ off)
-{
-    constexpr int per = kTgtKeys / 1024;
-    __shared__ int wsum[16];
-    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-    int cv[per];
-    int loc = 0;
-#pragma unroll
-    for (int i = 0; i < per; ++i) {
-        cv[i] = cnt[t * per + i];
-        cnt[t * per + i] = 0;
-        loc += cv[i];
-    }
-    int inc = loc;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const int v = __shfl_up(inc, o);
-        if (lane >= o) inc += v;
-    }
-    if (lane == 63) wsum[wv] = inc;
-    __syncthreads();
-    if (t == 0) {
-        int a = 0;
-        for (int i = 0; i < 16; ++i) {
-            const int v = wsum[i];
-            wsum[i] = a;
-            a += v;
-        }
-    }
-    __syncthreads();
-    int run = inc - loc + wsum[wv];
-#pragma unroll
-    for (int i = 0; i < per; ++i) {
-        off[t * per + i] = run;
-        run += cv[i];
-    }
-}
-
-__global__ void __launch_bounds__(256) k_tgt_place(const double* __restrict__ xi, const double* __restrict__ eta,
-                                                   int64_t M, const int* __restrict__ key,
-                                                   const int* __restrict__ rank, const int* __restrict__ off,
-                                                   double* __restrict__ xs, double* __restrict__ ys,
-                                                   int* __restrict__ perm)
-{
-    const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (k >= M) return;
-    const int64_t p = (int64_t)off[key[k]] + rank[k];
-    xs[p] = xi[k];
-    ys[p] = eta[k];
-    perm[p] = (int)k;
-}
-
 // ------------------------------------------------------- launch helpers
 template <class R, int W>
 void launch_spread_w(fh_ctx* c, unsigned grid, const Sub* subs, const int* nsub, const uint32_t* cell,
@@ -1514,13 +1419,13 @@ fh_status launch_spread(fh_ctx* c, unsigned grid, const Sub* subs, const int* ns
 
 template <class R>
 fh_status launch_interp(fh_ctx* c, int W, const R* G, const double* xi, const double* eta, int64_t M,
-                        double beta, const void* poly, const T3Params& tp, const int* perm, R* u)
+                        double beta, const void* poly, const T3Params& tp, R* u)
 {
     switch (W) {
 #define FH_INTERP_CASE(w)                                                                           \
     case w:                                                                                        \
         hipLaunchKernelGGL((k_t3_interp<R, w>), dim3(std::min<int64_t>(nblocks(M, 64), 1 << 20)), dim3(64), 0, \
-                           c->stream, G, xi, eta, M, (R)beta, (const R*)poly, tp, perm, u);          \
+                           c->stream, G, xi, eta, M, (R)beta, (const R*)poly, tp, u);          \
         break;
         FH_INTERP_CASE(2) FH_INTERP_CASE(3) FH_INTERP_CASE(4) FH_INTERP_CASE(5) FH_INTERP_CASE(6)
         FH_INTERP_CASE(7) FH_INTERP_CASE(8) FH_INTERP_CASE(9) FH_INTERP_CASE(10) FH_INTERP_CASE(11)

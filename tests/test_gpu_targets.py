@@ -1,9 +1,9 @@
 """Target sets (fh_targets_create / fh_field_targets) vs the CPU FP64 oracle.
 
-A target set holds scattered targets sorted on the device for the type-3
-interpolation, with a planning box that is either declared (no host
-synchronisation) or computed.  Outputs come back in the caller's order, so
-every comparison is element by element.  Bars as in test_gpu_parity.py.
+A target set holds scattered targets (device arrays in place, or a copy of
+host arrays) with a planning box that is either declared (no device work and
+no host synchronisation) or computed.  Every comparison is element by
+element.  Bars as in test_gpu_parity.py.
 """
 import math
 
@@ -71,8 +71,7 @@ def test_workload2_declared_box_sampled(ctx):
 
 @pytest.mark.parametrize("M", [1, 63, 64, 65, 777, 4099])
 def test_small_sets_full(ctx, M):
-    # ragged sizes around the 64-target wavefront chunk; the whole output is
-    # compared, so a wrong permutation shows as a mismatch
+    # ragged sizes around the 64-target wavefront chunk, whole output compared
     wl = workloads.workload(1)
     g = np.random.Generator(np.random.PCG64(1000 + M))
     xi = g.uniform(-1.7, 0.9, M)
