@@ -1206,7 +1206,7 @@ constexpr int interp_group() { return W <= 8 ? 8 : (W <= 16 ? 16 : 32); }
 template <class R, int W>
 __global__ void __launch_bounds__(64) k_t3_interp(const R* __restrict__ G, const double* __restrict__ xi,
                                                   const double* __restrict__ eta, int64_t M, R beta,
-                                                  const R* __restrict__ poly, T3Params tp,
+                                                  const R* __restrict__ poly, T3Params tp, int tpw,
                                                   R* __restrict__ u)
 {
     using C = typename V2<R>::T;
@@ -1218,9 +1218,9 @@ __global__ void __launch_bounds__(64) k_t3_interp(const R* __restrict__ G, const
     __shared__ C res[64];
     const int lane = threadIdx.x, g = lane / GS, r = lane % GS;
     const C* Gv = reinterpret_cast<const C*>(G);
-    for (int64_t base = blockIdx.x * (int64_t)64; base < M; base += (int64_t)gridDim.x * 64) {
+    for (int64_t base = blockIdx.x * (int64_t)tpw; base < M; base += (int64_t)gridDim.x * tpw) {
         const int64_t t = base + lane;
-        const bool live = t < M;
+        const bool live = lane < tpw && t < M;
         const int64_t k = live ? t : 0;
         const double X = xi[k], Y = eta[k];
         const bool inbox = X >= tp.box[0] && X <= tp.box[1] && Y >= tp.box[2] && Y <= tp.box[3];
@@ -1247,7 +1247,7 @@ __global__ void __launch_bounds__(64) k_t3_interp(const R* __restrict__ G, const
         sincospi(2.0 * (ph - rint(ph)), &sn, &cn);
         const double fr = sn * corr * tp.invlz, fi = -cn * corr * tp.invlz;
         wave_lds_order();
-        const int nq = (int)min<int64_t>(64, M - base);
+        const int nq = (int)min<int64_t>(tpw, M - base);
         // gathers of the next trip are issued before the current one is
         // summed; the gather has no branches (inactive lanes read a valid
         // entry and get weight zero), so the loads can stay in flight
@@ -1417,15 +1417,21 @@ fh_status launch_spread(fh_ctx* c, unsigned grid, const Sub* subs, const int* ns
     return FH_OK;
 }
 
+// Targets per wavefront: 64, halved (down to one gather trip's worth) while
+// that leaves fewer than about 24 wavefronts per CU, so that small target
+// sets still spread their gather trips over many wavefronts.
 template <class R>
 fh_status launch_interp(fh_ctx* c, int W, const R* G, const double* xi, const double* eta, int64_t M,
                         double beta, const void* poly, const T3Params& tp, R* u)
 {
+    const int per_trip = W <= 8 ? 8 : (W <= 16 ? 4 : 2);
+    int tpw = 64;
+    while (tpw > per_trip && M / tpw < (int64_t)c->cu_count * 24) tpw /= 2;
     switch (W) {
 #define FH_INTERP_CASE(w)                                                                           \
     case w:                                                                                        \
-        hipLaunchKernelGGL((k_t3_interp<R, w>), dim3(std::min<int64_t>(nblocks(M, 64), 1 << 20)), dim3(64), 0, \
-                           c->stream, G, xi, eta, M, (R)beta, (const R*)poly, tp, u);          \
+        hipLaunchKernelGGL((k_t3_interp<R, w>), dim3(std::min<int64_t>(nblocks(M, tpw), 1 << 20)), dim3(64), 0, \
+                           c->stream, G, xi, eta, M, (R)beta, (const R*)poly, tp, tpw, u);     \
         break;
         FH_INTERP_CASE(2) FH_INTERP_CASE(3) FH_INTERP_CASE(4) FH_INTERP_CASE(5) FH_INTERP_CASE(6)
         FH_INTERP_CASE(7) FH_INTERP_CASE(8) FH_INTERP_CASE(9) FH_INTERP_CASE(10) FH_INTERP_CASE(11)
