@@ -1249,10 +1249,11 @@ __global__ void __launch_bounds__(64) k_t3_interp(const R* __restrict__ G, const
         wave_lds_order();
         const int nq = (int)min<int64_t>(tpw, M - base);
         // gathers of the next trip are issued before the current one is
-        // summed; the gather has no branches (inactive lanes read a valid
-        // entry and get weight zero), so the loads can stay in flight
+        // summed, alternating between two register buffers; the gather has
+        // no branches (inactive lanes read a valid entry and get weight
+        // zero), so the loads can stay in flight
         const int rr = min(r, W - 1);
-        C cur[W], nxt[W];
+        C bufA[W], bufB[W];
         auto gather = [&](int q, C* gv) {
             const uint32_t cp = cs[min(q, nq - 1)];
             const int c1 = (int)(cp & 0xffffu);
@@ -1265,23 +1266,26 @@ __global__ void __launch_bounds__(64) k_t3_interp(const R* __restrict__ G, const
                 gv[a] = gr[col >= tp.m1 ? col - tp.m1 : col];
             }
         };
-        gather(g, cur);
-        for (int j = 0; j < nq; j += NT) {
-            const int q = j + g;
-            gather(q + NT, nxt);
+        auto trip_sum = [&](int q, const C* gv) {
             const R* kq = ks + min(q, nq - 1) * KS;
             R sr = R(0), si = R(0);
 #pragma unroll
             for (int a = 0; a < W; ++a) {
-                sr += cur[a].x * kq[a];
-                si += cur[a].y * kq[a];
+                sr += gv[a].x * kq[a];
+                si += gv[a].y * kq[a];
             }
             const R ky = (q < nq && r < W) ? kq[W + rr] : R(0);
             sr = group_sum<GS>(sr * ky);
             si = group_sum<GS>(si * ky);
             if (r == 0 && q < nq) res[q] = C{sr, si};
-#pragma unroll
-            for (int a = 0; a < W; ++a) cur[a] = nxt[a];
+        };
+        gather(g, bufA);
+        for (int j = 0; j < nq; j += 2 * NT) {
+            gather(j + NT + g, bufB);
+            trip_sum(j + g, bufA);
+            if (j + NT >= nq) break;
+            gather(j + 2 * NT + g, bufA);
+            trip_sum(j + NT + g, bufB);
         }
         wave_lds_order();
         if (live) {
