@@ -34,7 +34,7 @@ LDS_PEAK_GBS = 256 * 128 * 2.4
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_starfish_F20.json")
 METRIC = "target pts/s at 1e-9 (FP64) vs 1e-5 (mixed); backward/forward time ratio"
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2010_05978_amd", "csrc", f)
-                  for f in ("fh_kernels.hpp", "fh_field.hip")]
+                  for f in ("fh_kernels.hpp", "fh_fft.hpp", "fh_field.hip")]
 
 
 def parse():

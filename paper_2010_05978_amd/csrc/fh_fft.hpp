@@ -3,7 +3,7 @@
 //
 // A workgroup transforms several sequences of one length n (a product of
 // 2, 3, 5 and 7, with all sequences together at most kLdsFftBytes) in place
-// in LDS: self-sorting (Stockham) radix passes of 8, 4, 2, 3, 5 and 7, each
+// in LDS: self-sorting (Stockham) radix passes of 16, 8, 4, 2, 3, 5 and 7, each
 // pass gathering its butterflies' inputs into registers, one barrier, and
 // scattering the outputs, so that the result is in natural order.  A
 // butterfly's twiddles are powers of one root of unity, read from a table of
@@ -38,7 +38,7 @@ struct LdsFftPlan {
     int ntw = 0;  // twiddle table entries: sum over passes of Ns
 };
 
-// Radix passes for n (8s first, then 4, 2, 3, 5, 7); false if n has another
+// Radix passes for n (16s first, then 8, 4, 2, 3, 5, 7); false if n has another
 // prime factor.
 inline bool lds_fft_plan(int n, LdsFftPlan& p)
 {
@@ -52,6 +52,7 @@ inline bool lds_fft_plan(int n, LdsFftPlan& p)
             m /= r;
         }
     };
+    take(16);
     take(8);
     take(4);
     take(2);
@@ -144,6 +145,65 @@ __device__ __forceinline__ void dft_small(const C2* t, C2* X)
         X[6] = csub(e[2], w2);
         X[3] = cadd(e[3], w3);
         X[7] = csub(e[3], w3);
+    } else if constexpr (R == 16) {
+        // four length-4 DFTs of the entries r = 4 j + m, twiddled by
+        // exp(-2 pi i m q/16), then length-4 DFTs across m
+        C2 y[4][4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) dft4(t[m], t[m + 4], t[m + 8], t[m + 12], y[m][0], y[m][1], y[m][2], y[m][3]);
+        const Rl c1 = (Rl)0.92387953251128675613, s1 = (Rl)0.38268343236508977173;
+        const Rl h = (Rl)0.70710678118654752440;
+        // y[m][q] *= exp(-2 pi i m q/16), m, q = 1..3
+        auto rot = [&](C2 v, Rl c, Rl sn) {  // v exp(-i theta), cos c, sin sn
+            C2 o;
+            o.x = v.x * c + v.y * sn;
+            o.y = v.y * c - v.x * sn;
+            return o;
+        };
+        y[1][1] = rot(y[1][1], c1, s1);
+        y[1][2] = rot(y[1][2], h, h);
+        y[1][3] = rot(y[1][3], s1, c1);
+        y[2][1] = rot(y[2][1], h, h);
+        y[2][2] = cmul_negi(y[2][2]);
+        y[2][3] = rot(y[2][3], -h, h);
+        y[3][1] = rot(y[3][1], s1, c1);
+        y[3][2] = rot(y[3][2], -h, h);
+        y[3][3] = rot(y[3][3], -c1, -s1);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) dft4(y[0][q], y[1][q], y[2][q], y[3][q], X[q], X[q + 4], X[q + 8], X[q + 12]);
+    } else if constexpr (R == 3) {
+        // X1, X2 = x0 - (x1 + x2)/2 -/+ i (sqrt(3)/2)(x1 - x2)
+        const Rl s3 = (Rl)0.86602540378443864676;
+        const C2 sum = cadd(t[1], t[2]), dif = csub(t[1], t[2]);
+        C2 a, d;
+        a.x = t[0].x - (Rl)0.5 * sum.x;
+        a.y = t[0].y - (Rl)0.5 * sum.y;
+        d.x = s3 * dif.x;
+        d.y = s3 * dif.y;
+        X[0] = cadd(t[0], sum);
+        X[1] = cadd(a, cmul_negi(d));
+        X[2] = csub(a, cmul_negi(d));
+    } else if constexpr (R == 5) {
+        // with c1, s1 = cos, sin(2 pi/5), c2, s2 = cos, sin(4 pi/5):
+        // X1, X4 = x0 + c1 (x1 + x4) + c2 (x2 + x3) -/+ i (s1 (x1 - x4) + s2 (x2 - x3))
+        // X2, X3 = x0 + c2 (x1 + x4) + c1 (x2 + x3) -/+ i (s2 (x1 - x4) - s1 (x2 - x3))
+        const Rl c1 = (Rl)0.30901699437494742410, c2 = (Rl)-0.80901699437494742410;
+        const Rl s1 = (Rl)0.95105651629515357212, s2 = (Rl)0.58778525229247312917;
+        const C2 t1 = cadd(t[1], t[4]), t2 = cadd(t[2], t[3]), t3 = csub(t[1], t[4]), t4 = csub(t[2], t[3]);
+        C2 a, b, d, e;
+        a.x = t[0].x + c1 * t1.x + c2 * t2.x;
+        a.y = t[0].y + c1 * t1.y + c2 * t2.y;
+        b.x = t[0].x + c2 * t1.x + c1 * t2.x;
+        b.y = t[0].y + c2 * t1.y + c1 * t2.y;
+        d.x = s1 * t3.x + s2 * t4.x;
+        d.y = s1 * t3.y + s2 * t4.y;
+        e.x = s2 * t3.x - s1 * t4.x;
+        e.y = s2 * t3.y - s1 * t4.y;
+        X[0] = cadd(t[0], cadd(t1, t2));
+        X[1] = cadd(a, cmul_negi(d));
+        X[4] = csub(a, cmul_negi(d));
+        X[2] = cadd(b, cmul_negi(e));
+        X[3] = csub(b, cmul_negi(e));
     } else {
         // cos and sin of 2 pi m/R, m = 0..R-1
         constexpr double c3[3] = {1.0, -0.5, -0.5};
@@ -276,6 +336,7 @@ __device__ void lds_fft(C2* buf, const LdsFftPlan& p, int nseq, C2* twl)
     for (int st = 0; st < p.nst; ++st) {
         const int R = p.radix[st];
         switch (R) {
+        case 16: lds_fft_pass<16, MAXE, NT>(buf, p.n, nseq, Ns, tw); break;
         case 8: lds_fft_pass<8, MAXE, NT>(buf, p.n, nseq, Ns, tw); break;
         case 4: lds_fft_pass<4, MAXE, NT>(buf, p.n, nseq, Ns, tw); break;
         case 2: lds_fft_pass<2, MAXE, NT>(buf, p.n, nseq, Ns, tw); break;

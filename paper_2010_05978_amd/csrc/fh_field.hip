@@ -28,10 +28,10 @@
 namespace fh {
 
 // Sequences per workgroup for an LDS FFT of length n over `count`
-// sequences: as many as give `min_bytes` of contiguous output per row segment
-// (64 bytes, or `min_c` sequences), more while there are over two
-// workgroups per CU, within the LDS budget and the 16-sequence limit of the
-// column kernel.  C = 0 when one sequence does not fit or n has a prime
+// sequences: as many as give 64 bytes of contiguous output per row segment
+// (or `min_c` sequences), more while there are over two workgroups per CU,
+// fewer while there are under two, within the LDS budget and the
+// 16-sequence limit of the column kernel.  C = 0 when one sequence does not fit or n has a prime
 // factor above 7.
 struct LdsCols {
     int C = 0;
@@ -58,6 +58,8 @@ LdsCols lds_cols_plan(const fh_ctx* c, int n, int64_t count, size_t rs, int min_
     const int64_t want = std::max<int64_t>(1, count / (2 * (int64_t)c->cu_count));
     C = (int)std::max<int64_t>(C, std::min<int64_t>(want, 16));
     C = std::min({C, cap, 16});
+    // but keep at least two workgroups per CU where the count allows
+    while (C > 1 && count / C < 2 * (int64_t)c->cu_count) C /= 2;
     // rather fewer sequences per block than the 512-thread shape
     while (C > 1 && n * C > kLdsFftSmall && n * (C / 2) >= 1 && n <= kLdsFftSmall) C /= 2;
     r.C = C;
@@ -137,19 +139,19 @@ fh_status t1_pipeline(fh_ctx* c, int B, const fh_quad* const* qs, const double* 
     FH_TRY(fft_plan(c, gg.nf1, 0, gg.rows * B, &fa));
     // second pass: in LDS, fused with the epilogue, when a column fits
     LdsCols lc = lds_cols_plan(c, gg.nf2, (int64_t)n1 * B, rs);
-    // its epilogue keeps a row factor (16 bytes) per unread mode of a column
-    if ((size_t)(gg.nf2 - n2) * 2 * rs < 16) lc.C = 0;
     if (lc.C == 0) FH_TRY(fft_plan(c, gg.nf2, 0, n1 * B, &fb));
 
     FH_TRY(counters_ready(c, (int64_t)tpi * B));
     const size_t F_count = 2 * (size_t)B * gg.rows * gg.nf1;
     const size_t Z_count = lc.C > 0 ? 0 : 2 * (size_t)B * n1 * gg.nf2;
-    size_t need = aligned_bytes(rs * F_count) + aligned_bytes(rs * Z_count) +
+    const size_t E2_bytes = lc.C > 0 ? aligned_bytes(sizeof(double2) * (size_t)B * n2) : 0;
+    size_t need = aligned_bytes(rs * F_count) + aligned_bytes(rs * Z_count) + E2_bytes +
                   spread_bytes(Ntot, gg, tpi * B, rs) + aligned_bytes(sizeof(InstParams) * B) +
                   aligned_bytes(sizeof(EpiInst) * B) + aligned_bytes(extra_bytes);
     FH_TRY(arena_reserve(c, need));
     R* F = c->arena.take<R>(F_count);
     R* Z = c->arena.take<R>(Z_count);
+    double2* E2 = lc.C > 0 ? c->arena.take<double2>((size_t)B * n2) : nullptr;
     SpreadBufs sb = spread_carve(c, Ntot, gg, tpi * B, rs);
     InstParams* dinst = c->arena.take<InstParams>(B);
     EpiInst* depi = c->arena.take<EpiInst>(B);
@@ -167,10 +169,12 @@ fh_status t1_pipeline(fh_ctx* c, int B, const fh_quad* const* qs, const double* 
         FH_TRY(fft_exec(c, fa, F));
         EpiParams ep{n1, n2, gg.nf1, gg.nf2, h1, h2, xc, yc, ip1, ip2};
         if (lc.C > 0) {
+            hipLaunchKernelGGL(k_t1_rowfactors, dim3(nblocks(n2, 256), B), dim3(256), 0, c->stream, ep, epi[0],
+                               batched ? (const EpiInst*)depi : nullptr, E2);
             timing_mark(c, 3);
             const int groups = (n1 + lc.C - 1) / lc.C;
             FH_LDS_LAUNCH(k_t1_cols, R, lc, dim3(xcd_blocks(groups), B), c->stream, F, u, gg.rows, lc.C, groups,
-                          lc.plan, ep, epi[0], batched ? (const EpiInst*)depi : nullptr);
+                          lc.plan, ep, epi[0], batched ? (const EpiInst*)depi : nullptr, (const double2*)E2);
             FH_HIP(hipGetLastError());
             timing_mark(c, 4);
         } else {

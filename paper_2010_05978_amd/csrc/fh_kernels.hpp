@@ -928,16 +928,42 @@ __global__ void __launch_bounds__(256) k_epilogue_t1(const R* __restrict__ Z, R*
     }
 }
 
+// Row factors of the type-1 epilogue, once per call: for instance b and
+// output row k2, E2 = exp(i pi eta^2/(lambda z) - 2 pi i k2 sh2/nf2)/Phi2(k2)
+// with each phase reduced in turns before sincospi.
+__global__ void __launch_bounds__(256) k_t1_rowfactors(EpiParams ep, EpiInst e0, const EpiInst* __restrict__ table,
+                                                       double2* __restrict__ E2)
+{
+    const int k2i = blockIdx.x * blockDim.x + threadIdx.x, b = blockIdx.y;
+    if (k2i >= ep.n2) return;
+    const EpiInst ei = table ? table[b] : e0;
+    const int nf2 = ep.nf2;
+    const int sm = (int)(((long long)ei.sh2 % nf2 + nf2) % nf2);
+    const int k2 = k2i - ep.n2 / 2;
+    const double y = ep.yc + ep.h2 * k2;
+    double tt = y * y * ei.inv2lz;
+    const unsigned km = (unsigned)(k2 < 0 ? k2 + nf2 : k2);
+    const unsigned ph = (km * (unsigned)sm) % (unsigned)nf2;
+    tt = (tt - rint(tt)) - (double)ph / (double)nf2;
+    tt -= rint(tt);
+    double sn, cs;
+    sincospi(2.0 * tt, &sn, &cs);
+    const double sc = ep.iphi2[k2i];
+    E2[(size_t)b * ep.n2 + k2i] = make_double2(cs * sc, sn * sc);
+}
+
 // Type-1 second pass and epilogue in one kernel.  Workgroup (group g,
 // instance b) takes the C output columns k1 + n1/2 in [g C, g C + C): it
 // loads their band of `rows` values from F (after the first pass over the
 // rows), zero-pads each to nf2 in LDS, transforms, and writes
 // u[b][k2][k1] = epilogue(column value at k2 mod nf2) for every k2, with the
-// factors of k_epilogue_t1 (each phase reduced in turns before sincospi).
+// factors of k_epilogue_t1: its column factors here, its row factors from
+// k_t1_rowfactors.
 template <class R, int MAXE, int NT>
 __global__ void __launch_bounds__(NT) k_t1_cols(const R* __restrict__ F, R* __restrict__ u, int rows,
                                                             int C, int groups, LdsFftPlan plan, EpiParams ep,
-                                                            EpiInst e0, const EpiInst* __restrict__ table)
+                                                            EpiInst e0, const EpiInst* __restrict__ table,
+                                                            const double2* __restrict__ E2all)
 {
     using C2 = typename V2<R>::T;
     extern __shared__ __align__(16) unsigned char lds_raw[];
@@ -981,65 +1007,32 @@ __global__ void __launch_bounds__(NT) k_t1_cols(const R* __restrict__ F, R* __re
     }
     __syncthreads();
     lds_fft<MAXE, NT>(buf, plan, C, buf + (size_t)C * plan.n);
-    // Epilogue in chunks of rows.  The row factors (target chirp, window
-    // shift exp(-2 pi i k2 sh2/nf2), 1/Phi2) of a chunk are computed once
-    // into entries of the column buffers that no output reads (modes n2/2
-    // to nf2 - n2/2 - 1 of every column), then C lanes write C consecutive
-    // outputs of each row.  `cap` row factors (two doubles each) fit in one
-    // column's unread entries; the host only picks this kernel when cap >= 1.
-    const int sm = (int)(((long long)ei.sh2 % nf2 + nf2) % nf2);
-    const int cap = (int)((size_t)(nf2 - ep.n2) * sizeof(C2) / (2 * sizeof(double)));
-    const int chunk = min(ep.n2, cap * C);
-    auto slot = [&](int t) -> double* {
-        const int col = t / cap, off = t - col * cap;
-        return reinterpret_cast<double*>(buf + (size_t)col * nf2 + ep.n2 / 2) + 2 * off;
-    };
+    // epilogue: C lanes write C consecutive outputs of a row, with the row
+    // factors of k_t1_rowfactors and the column factors above
+    const double2* E2 = E2all + (size_t)b * ep.n2;
     C2* uv = reinterpret_cast<C2*>(u) + (size_t)b * ep.n2 * ep.n1;
-    for (int r0 = 0; r0 < ep.n2; r0 += chunk) {
-        const int nr = min(chunk, ep.n2 - r0);
-        __syncthreads();
-        for (int t = threadIdx.x; t < nr; t += NT) {
-            const int k2i = r0 + t;
-            const int k2 = k2i - ep.n2 / 2;
-            const double y = ep.yc + ep.h2 * k2;
-            double tt = y * y * ei.inv2lz;
-            const unsigned km = (unsigned)(k2 < 0 ? k2 + nf2 : k2);
-            const unsigned ph = (km * (unsigned)sm) % (unsigned)nf2;
-            tt = (tt - rint(tt)) - (double)ph / (double)nf2;
-            tt -= rint(tt);
-            double sn, cs;
-            sincospi(2.0 * tt, &sn, &cs);
-            const double sc = ep.iphi2[k2i];
-            double* p = slot(t);
-            p[0] = cs * sc;
-            p[1] = sn * sc;
+    for (int e = threadIdx.x; e < ep.n2 * C; e += NT) {
+        const int k2i = e / C, c = e - k2i * C;
+        if (c >= ncol) continue;
+        const int k2 = k2i - ep.n2 / 2;
+        const int r = k2 < 0 ? k2 + nf2 : k2;
+        const C2 fv = buf[(size_t)c * nf2 + r];
+        const double2 er = E2[k2i];
+        const double2 a = E1[c];
+        const double ar = a.x * er.x - a.y * er.y, ai = a.x * er.y + a.y * er.x;
+        const double wr = (double)fv.x * ar - (double)fv.y * ai;
+        const double wi = (double)fv.x * ai + (double)fv.y * ar;
+        // times 1/(i lambda z)
+        double re = wi * ei.invlz;
+        double im = -wr * ei.invlz;
+        if (ei.occ) {
+            re = 1.0 - re;
+            im = -im;
         }
-        __syncthreads();
-        for (int e = threadIdx.x; e < nr * C; e += NT) {
-            const int t = e / C, c = e - t * C;
-            if (c >= ncol) continue;
-            const int k2i = r0 + t;
-            const int k2 = k2i - ep.n2 / 2;
-            const int r = k2 < 0 ? k2 + nf2 : k2;
-            const C2 fv = buf[(size_t)c * nf2 + r];
-            const double* p = slot(t);
-            const double erx = p[0], ery = p[1];
-            const double2 a = E1[c];
-            const double ar = a.x * erx - a.y * ery, ai = a.x * ery + a.y * erx;
-            const double wr = (double)fv.x * ar - (double)fv.y * ai;
-            const double wi = (double)fv.x * ai + (double)fv.y * ar;
-            // times 1/(i lambda z)
-            double re = wi * ei.invlz;
-            double im = -wr * ei.invlz;
-            if (ei.occ) {
-                re = 1.0 - re;
-                im = -im;
-            }
-            C2 out;
-            out.x = (R)re;
-            out.y = (R)im;
-            uv[(size_t)k2i * ep.n1 + col0 + c] = out;
-        }
+        C2 out;
+        out.x = (R)re;
+        out.y = (R)im;
+        uv[(size_t)k2i * ep.n1 + col0 + c] = out;
     }
 }
 
