@@ -1414,16 +1414,17 @@ fh_status launch_spread(fh_ctx* c, unsigned grid, const Sub* subs, const int* ns
     return FH_OK;
 }
 
-// Targets per wavefront: 64, halved (down to one gather trip's worth) while
-// that leaves fewer than about 24 wavefronts per CU, so that small target
-// sets still spread their gather trips over many wavefronts.
+// Targets per wavefront: 64 (the per-target setup then uses every lane),
+// halved (down to one gather trip's worth) while that leaves fewer than
+// about 4 wavefronts per CU, so that small target sets still spread their
+// gather trips over many wavefronts.
 template <class R>
 fh_status launch_interp(fh_ctx* c, int W, const R* G, const double* xi, const double* eta, int64_t M,
                         double beta, const void* poly, const T3Params& tp, R* u)
 {
     const int per_trip = W <= 8 ? 8 : (W <= 16 ? 4 : 2);
     int tpw = 64;
-    while (tpw > per_trip && M / tpw < (int64_t)c->cu_count * 24) tpw /= 2;
+    while (tpw > per_trip && M / tpw < (int64_t)c->cu_count * 4) tpw /= 2;
     switch (W) {
 #define FH_INTERP_CASE(w)                                                                           \
     case w:                                                                                        \
