@@ -87,7 +87,10 @@ typedef struct fh_options {
                              * atomics; 2: wavefront per work item, lanes    *
                              * over the stencil, private LDS tile updated    *
                              * by read-add-write; 3: as 2, updated by LDS    *
-                             * atomics (both deterministic)                  */
+                             * atomics; 4: four wavefronts per work item,    *
+                             * each with the padded tile in registers (lane  *
+                             * per column and row bank), tiles 8 or 16 only  *
+                             * (else 2); 2, 3 and 4 are deterministic        */
 } fh_options;
 
 /* ---------------------------------------------------------------- context */

@@ -663,6 +663,135 @@ __global__ void __launch_bounds__(64) k_spread_wave(const Sub* __restrict__ subs
     }
 }
 
+// Register-tile spread (method 4), for tiles of TT = 8 or 16 cells.  A block
+// of NW wavefronts takes one work item at a time; each wavefront keeps a
+// padded L x L tile (L = TT + W - 1) in registers, lane (x, bank) owning
+// column x of the rows [bank RB, bank RB + RB).  The block stages PC points
+// at a time in LDS (kernel values along x, kernel values along y inside a
+// zero border wide enough for every row a lane owns, strength and first
+// cell), and wavefront v adds points v, v + NW, ...: every lane adds
+// strength x kx[x - cx] x ky[y - cy] to its RB cells, with reads at fixed
+// offsets from one base and no branches (lanes outside the stencil add
+// zeros).  At the end of the item the NW tiles are summed through LDS in a
+// fixed order into the item's slot, so the spread is deterministic.
+template <int TT, int W>
+struct RegTile {
+    static constexpr int L = TT + W - 1;
+    static constexpr int NB = 64 / L;                // banks (rows split over NB lane groups)
+    static constexpr int RB = (L + NB - 1) / NB;     // rows per bank
+    static constexpr int PADL = TT - 1;              // y - cy >= -(TT - 1)
+    static constexpr int KYP = PADL + NB * RB;       // padded y values per point
+    static constexpr int PC = 32;                    // points staged at a time
+    static constexpr int NW = 4;                     // wavefronts per block
+};
+
+template <class R, int TT, int W>
+constexpr size_t reg_spread_lds()
+{
+    using RT = RegTile<TT, W>;
+    return sizeof(R) * ((size_t)RT::PC * (W + RT::KYP + 2)) + 2 * sizeof(int) * RT::PC +
+           2 * sizeof(R) * (size_t)RT::NW * RT::L * RT::L;
+}
+
+template <class R, int W, int TT>
+__global__ void __launch_bounds__(256) k_spread_reg(const Sub* __restrict__ subs, const int* __restrict__ nsub_ptr,
+                                                    const uint32_t* __restrict__ cell,
+                                                    const typename V2<R>::T* __restrict__ dd,
+                                                    const typename V2<R>::T* __restrict__ cc,
+                                                    typename V2<R>::T* __restrict__ slots, GridGeom gg, int tpi,
+                                                    R beta, const R* __restrict__ poly)
+{
+    using C = typename V2<R>::T;
+    using RT = RegTile<TT, W>;
+    constexpr int L = RT::L, NB = RT::NB, RB = RT::RB, KYP = RT::KYP, PC = RT::PC, NW = RT::NW, LL = L * L;
+    static_assert(NB >= 1, "tile too wide for one wavefront");
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    R* skx = reinterpret_cast<R*>(smem_raw);
+    R* sky = skx + PC * W;
+    R* scr = sky + PC * KYP;
+    R* sci = scr + PC;
+    R* stile = sci + PC;                            // NW tiles, planar re/im
+    int* scx = reinterpret_cast<int*>(stile + 2 * NW * LL);
+    int* scy = scx + PC;
+    const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
+    const int bank = lane / L;
+    const int x = lane - bank * L;                // column (lanes past NB L repeat bank NB - 1's rows)
+    const int y0 = min(bank, NB - 1) * RB;
+    // the y border stays zero; only the W middle values of a point change
+    for (int e = tid; e < PC * KYP; e += 64 * NW) sky[e] = R(0);
+    const int nsub = *nsub_ptr;
+    for (int s = blockIdx.x; s < nsub; s += gridDim.x) {
+        const Sub sb = subs[s];
+        int ox, oy;
+        tile_origin<R>(sb, gg, tpi, ox, oy);
+        const uint32_t org = (uint32_t)ox | ((uint32_t)oy << 16);
+        R accr[RB], acci[RB];
+#pragma unroll
+        for (int j = 0; j < RB; ++j) accr[j] = acci[j] = R(0);
+        for (int base = sb.start; base < sb.end; base += PC) {
+            const int np = min(PC, sb.end - base);
+            __syncthreads();
+            if (tid < np) {
+                const int p = base + tid;
+                const uint32_t rel = cell[p] - org;  // tile-relative first cell (x, y < TT)
+                const C dv = dd[p];
+                const C cv = cc[p];
+                R k[W];
+                es_weights<R, W>(dv.x, beta, poly, k);
+#pragma unroll
+                for (int a = 0; a < W; ++a) skx[tid * W + a] = k[a];
+                es_weights<R, W>(dv.y, beta, poly, k);
+#pragma unroll
+                for (int b = 0; b < W; ++b) sky[tid * KYP + RT::PADL + b] = k[b];
+                scr[tid] = cv.x;
+                sci[tid] = cv.y;
+                scx[tid] = (int)(rel & 0xffffu);
+                scy[tid] = (int)(rel >> 16);
+            }
+            __syncthreads();
+            for (int q = wv; q < np; q += NW) {
+                const int ax = x - scx[q];
+                const bool in = (unsigned)ax < (unsigned)W;
+                const R kx = skx[q * W + (in ? ax : 0)];
+                const R vr = in ? scr[q] * kx : R(0);
+                const R vi = in ? sci[q] * kx : R(0);
+                const R* ky = sky + q * KYP + RT::PADL + y0 - scy[q];
+#pragma unroll
+                for (int j = 0; j < RB; ++j) {
+                    const R w = ky[j];
+                    accr[j] += vr * w;
+                    acci[j] += vi * w;
+                }
+            }
+            // the y values of the next chunk overwrite this chunk's
+            __syncthreads();
+            if (tid < np)
+#pragma unroll
+                for (int b = 0; b < W; ++b) sky[tid * KYP + RT::PADL + b] = R(0);
+        }
+        // sum the NW register tiles in wavefront order into the slot
+        if (lane < NB * L) {
+#pragma unroll
+            for (int j = 0; j < RB; ++j)
+                if (y0 + j < L) {
+                    stile[wv * 2 * LL + (y0 + j) * L + x] = accr[j];
+                    stile[wv * 2 * LL + LL + (y0 + j) * L + x] = acci[j];
+                }
+        }
+        __syncthreads();
+        C* slot = slots + (size_t)s * LL;
+        for (int e = tid; e < LL; e += 64 * NW) {
+            R vr = R(0), vi = R(0);
+#pragma unroll
+            for (int w = 0; w < NW; ++w) {
+                vr += stile[w * 2 * LL + e];
+                vi += stile[w * 2 * LL + LL + e];
+            }
+            slot[e] = C{vr, vi};
+        }
+    }
+}
+
 // ----------------------------------------------------------------- reduce
 // A tile with cnt work items is merged in levels: level l sums, for every
 // item r (its index within the tile) divisible by G^l, the slots r + k G^(l-1)
@@ -1377,6 +1506,17 @@ void launch_spread_w(fh_ctx* c, unsigned grid, const Sub* subs, const int* nsub,
                            (const C2*)dd, (const C2*)cc, slots, gg, tpi, (R)beta, (const R*)poly);
         return;
     }
+    if (gg.method == 4) {
+        if (gg.T == 16)
+            hipLaunchKernelGGL((k_spread_reg<R, W, 16>), dim3(grid), dim3(256), (reg_spread_lds<R, 16, W>()),
+                               c->stream, subs, nsub, cell, (const C2*)dd, (const C2*)cc, slots, gg, tpi, (R)beta,
+                               (const R*)poly);
+        else
+            hipLaunchKernelGGL((k_spread_reg<R, W, 8>), dim3(grid), dim3(256), (reg_spread_lds<R, 8, W>()),
+                               c->stream, subs, nsub, cell, (const C2*)dd, (const C2*)cc, slots, gg, tpi, (R)beta,
+                               (const R*)poly);
+        return;
+    }
     const size_t staging = spread_staging_bytes(W, sizeof(R));
     if (gg.method == 3)
         hipLaunchKernelGGL((k_spread_wave<R, W, true>), dim3(grid), dim3(64), tile + staging, c->stream, subs, nsub,
@@ -1389,6 +1529,13 @@ void launch_spread_w(fh_ctx* c, unsigned grid, const Sub* subs, const int* nsub,
 // LDS bytes of one spread block.
 inline size_t spread_lds(const GridGeom& gg, size_t rsize)
 {
+    if (gg.method == 4) {
+        // staging of 32 points (W + KYP + 2 reals and 2 ints each) and the 4
+        // wavefront tiles (see RegTile and reg_spread_lds)
+        const int L = gg.L, NB = 64 / L, RB = (L + NB - 1) / NB;
+        const size_t kyp = (size_t)(gg.T - 1 + NB * RB);
+        return 32 * (rsize * ((size_t)gg.W + kyp + 2) + 2 * sizeof(int)) + 2 * rsize * 4 * (size_t)L * L;
+    }
     const size_t tile = 2 * rsize * (size_t)gg.L * gg.L;
     return gg.method == 1 ? tile : tile + spread_staging_bytes(gg.W, rsize);
 }
@@ -1572,6 +1719,11 @@ fh_status check_grid(int n1, int n2, double h1, double h2, double xc, double yc)
 void spread_defaults(const fh_ctx* c, GridGeom& g)
 {
     g.method = c->opt.spread_method > 0 ? c->opt.spread_method : 2;
+    // the register tile needs T = 8 or 16, a padded tile row within one
+    // wavefront and its four tiles within the LDS budget
+    if (g.method == 4 && !((g.T == 8 || g.T == 16) && g.L <= 64 &&
+                           spread_lds(g, c->prec == FH_FP64 ? 8 : 4) <= kLdsBudget))
+        g.method = 2;
     g.P = c->opt.max_subproblem > 0 ? c->opt.max_subproblem : 0;
 }
 

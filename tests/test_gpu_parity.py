@@ -157,6 +157,8 @@ def test_grid_shapes_and_translation(ctx, n1, n2, h1, h2, xc, yc):
 @pytest.mark.parametrize("method,tile,P,sigma", [
     (1, 16, 64, 0.0), (2, 16, 64, 0.0), (1, 32, 1024, 0.0), (2, 32, 4096, 0.0), (2, 8, 256, 0.0),
     (2, 32, 256, 1.25), (1, 16, 512, 1.25), (3, 16, 64, 0.0), (3, 32, 16, 1.25), (0, 0, 0, 0.0),
+    (4, 16, 64, 0.0), (4, 8, 256, 0.0), (4, 16, 32, 1.25), (4, 32, 64, 0.0), (4, 16, 4096, 0.0),
+    (4, 8, 16, 0.0),
 ])
 def test_spread_variants(fh, ctx, method, tile, P, sigma):
     # every spread method / tile / work-item size / upsampling the autotuner
