@@ -115,7 +115,7 @@ def test_autotune_keeps_accuracy_and_caches(ctx, tmp_path):
     best = ctx.autotune_grid(q, wl.lam, wl.z, n, n, h, h, cache_path=path)
     print(f"  tuned {ctx.precision}: sigma {best.sigma} tile {best.tile} P {best.max_subproblem} "
           f"method {best.spread_method}", flush=True)
-    assert best.spread_method in (1, 2, 3) and best.sigma in (1.25, 2.0)
+    assert best.spread_method in (1, 2, 3, 4) and best.sigma in (1.25, 2.0)
     assert os.path.exists(path)
     again = ctx.autotune_grid(q, wl.lam, wl.z, n, n, h, h, cache_path=path)
     assert (again.sigma, again.tile, again.max_subproblem, again.spread_method) == \
