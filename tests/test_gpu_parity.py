@@ -380,3 +380,31 @@ def test_error_statuses(fh):
     v = c.field_grid(q, 1.0, 1.0, 4, 4, 0.1, 0.1)
     assert torch.isfinite(torch.view_as_real(v)).all()
     c.close()
+
+
+# ------------------------------------------------- transform length sweep
+def test_many_transform_lengths(fh, ctx):
+    # grids and target extents chosen so that the fine grids and upsampled
+    # grids take many 2-3-5-7-smooth lengths (LDS FFT radix passes 16, 8, 4,
+    # 2, 3, 5, 7 in many combinations), each against the oracle
+    shape = workloads.RadialCurve(0.7, np.array([0.0, 0.1]), np.array([0.05, 0.0]), panels=4, q=12, m=10)
+    x, y, w = oracle_quad(shape)
+    lam, z = 1.0, 0.05
+    seen = set()
+    for n in (6, 10, 22, 30, 46, 62, 98, 126, 190, 250, 334):
+        h = 1.2 / n
+        u = cpu(ctx.field_grid(ctx.quad_for(shape), lam, z, n, n + 4, h, 0.9 * h))
+        xi, eta = oracle.grid_targets(n, n + 4, h, 0.9 * h)
+        ref = oracle.fresnel_direct(x, y, w, lam, z, xi, eta)
+        assert relL2(u, ref) <= TOL[ctx.precision], n
+        seen.add(ctx.query_params(n)["nf"])
+    assert len(seen) >= 8
+    g = np.random.Generator(np.random.PCG64(31))
+    q = ctx.quad_for(shape)
+    for ext in (0.05, 0.2, 0.45, 0.8, 1.3, 2.1):
+        M = 300
+        xi = g.uniform(-ext, ext, M)
+        eta = g.uniform(-0.6 * ext, ext, M)
+        up = cpu(ctx.field_points(q, lam, z, torch.tensor(xi, device="cuda"), torch.tensor(eta, device="cuda")))
+        ref = oracle.fresnel_direct(x, y, w, lam, z, xi, eta)
+        assert relL2(up, ref) <= TOL[ctx.precision], ext
