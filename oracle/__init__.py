@@ -12,7 +12,9 @@ What it computes (Barnett, arXiv:2010.05978):
     disc + petal rule (sec. 3.2), optionally with lateral edge perturbations;
   * the direct quadrature sum (eq. faq) with the Babinet complement (eq. bab);
   * the exact gradient of that sum with respect to nodes and weights, and its
-    chain rule through the perturbed starshade construction.
+    chain rule through the perturbed starshade construction;
+  * the non-singular line integral over a boundary rule (appendix, eq. nsli),
+    with the deep-shadow option of eq. li, and the starshade outline rule.
 """
 from __future__ import annotations
 
@@ -62,10 +64,13 @@ def _load():
                                                _dp, _dp, _dp, _dp]
         lib.orc_starshade_vjp.argtypes = [i32, d, d, d, d, i32, i32, i32, i32, _dp, i32,
                                           _dp, _dp, _dp, _dp]
+        lib.orc_bdry_starshade.argtypes = [i32, d, d, d, d, i32, i32, i32, _dp, _dp, _dp, _dp]
+        lib.orc_nsli.argtypes = [_dp, _dp, _dp, _dp, i64, d, d, _dp, _dp, i64, d, i32, _dp]
         lib.orc_num_threads.restype = i32
         for name in ("orc_gauss_legendre", "orc_bdry_radial_gl", "orc_bdry_radial_ptr",
                      "orc_bdry_polygon", "orc_dilation", "orc_starshade",
-                     "orc_fresnel_direct", "orc_fresnel_direct_vjp", "orc_starshade_vjp"):
+                     "orc_fresnel_direct", "orc_fresnel_direct_vjp", "orc_starshade_vjp",
+                     "orc_bdry_starshade", "orc_nsli"):
             getattr(lib, name).restype = i32
         _lib = lib
     return _lib
@@ -136,6 +141,19 @@ def boundary_polygon(vx, vy, q):
     _check(_load().orc_bdry_polygon(_p(vx), _p(vy), len(vx), q,
                                      _p(out[0]), _p(out[1]), _p(out[2]), _p(out[3])),
            "boundary_polygon")
+    return out[0], out[1], out[2], out[3]
+
+
+def boundary_starshade(Np, a, R, b, p, m, ntip=4, ngap=0):
+    """Outline rule of the starshade (sec. 3.2's petal shape, HG apodisation):
+    per petal the lower edge (m GL radii, outward), the tip arc (ntip GL
+    angles), the upper edge (inward) and the gap arc at r = a (ngap).
+    Returns X, Y, W, V with n = Np (2 m + ntip + ngap)."""
+    n = Np * (2 * m + ntip + ngap)
+    out = np.empty((4, n))
+    _check(_load().orc_bdry_starshade(Np, a, R, b, p, m, ntip, ngap,
+                                       _p(out[0]), _p(out[1]), _p(out[2]), _p(out[3])),
+           "boundary_starshade")
     return out[0], out[1], out[2], out[3]
 
 
@@ -219,3 +237,16 @@ def starshade_vjp(Np, a, R, b, p, m, np_, nd, md, coef, K, gx, gy, gw):
     _check(_load().orc_starshade_vjp(Np, a, R, b, p, m, np_, nd, md, _p(coef), K,
                                       _p(gx), _p(gy), _p(gw), _p(out)), "starshade_vjp")
     return out
+
+
+def nsli(X, Y, W, V, lam, z, xi, eta, far=0.0, occulter=False):
+    """Non-singular line integral (appendix, eq. nsli) at targets (xi, eta)
+    from a CCW vector line rule (X, Y, W, V); with far > 0, targets at least
+    that far from every node use eq. li with the integer winding number
+    (the deep-shadow remark).  Babinet if occulter; complex128 array."""
+    X, Y, W, V, xi, eta = (_f64(t) for t in (X, Y, W, V, xi, eta))
+    M = len(xi)
+    u = np.empty(2 * M)
+    _check(_load().orc_nsli(_p(X), _p(Y), _p(W), _p(V), len(X), lam, z, _p(xi), _p(eta), M,
+                            float(far), int(bool(occulter)), _p(u)), "nsli")
+    return u.view(np.complex128)

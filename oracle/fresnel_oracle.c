@@ -17,6 +17,9 @@
  *   - the direct areal-quadrature sum (eq. faq), un-factorised, phase carried
  *     in turns and reduced before cos/sin, pairwise summation over nodes,
  *   - the Babinet complement u_oc = 1 - u_ap (eq. bab),
+ *   - the non-singular line integral over a boundary rule (appendix, eq.
+ *     nsli), with the deep-shadow option of eq. li, and the starshade
+ *     outline rule it is fed with,
  *   - the exact gradient of the quadrature sum with respect to node
  *     coordinates and weights, and its chain rule through the perturbed
  *     starshade construction.
@@ -397,6 +400,174 @@ int orc_starshade_vjp(int Np, double a, double R, double b, double p,
             gcoef[2 * k * K + K + (s - 1)] = accm;
         }
     free(rx); free(rw); free(tx); free(tw); free(x);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Starshade boundary rule for the edge integral (eq. vliq on the outline   */
+/* of sec. 3.2's petal shape, A(r) = exp(-((r-a)/b)^p) on (a, R)).          */
+/* Petal k (centre theta_k = 2 pi k/Np), half-width angle h(r) = pi A(r)/Np: */
+/*   lower edge  phi = theta_k - h(r), r from a to R, m GL nodes in r;      */
+/*   tip arc     r = R, phi from theta_k - h(R) to theta_k + h(R), ntip GL; */
+/*   upper edge  phi = theta_k + h(r), r from R to a, m GL nodes in r;      */
+/*   gap arc     r = a, phi from theta_k + h(a) to theta_{k+1} - h(a),      */
+/*               ngap GL nodes (zero width, so zero weights, when A(a) = 1, */
+/*               as for this profile family).                               */
+/* An edge point is P(r) = r (cos phi, sin phi) with                        */
+/* P'(r) = (cos phi, sin phi) + r phi'(r) (-sin phi, cos phi),              */
+/* phi' = -+ pi A'(r)/Np, A'(r) = -(p/b) ((r-a)/b)^(p-1) A(r); the vector   */
+/* weight is P'(r) times the GL weight in r, negated on the upper edge      */
+/* (traversed inward), so the outline is counter-clockwise.                 */
+/* Node order per petal: lower, tip, upper (outward-to-inward), gap;        */
+/* n = Np (2 m + ntip + ngap).                                              */
+/* ------------------------------------------------------------------------ */
+static double hg_profile_deriv(double r, double a, double b, double p)
+{
+    if (r <= a) return 0.0;
+    double s = (r - a) / b;
+    return -(p / b) * pow(s, p - 1.0) * exp(-pow(s, p));
+}
+
+static void arc_nodes(double rad, double phi0, double phi1, int nq, const double* gx,
+                      const double* gw, double* X, double* Y, double* W, double* V)
+{
+    double half = 0.5 * (phi1 - phi0);
+    for (int i = 0; i < nq; i++) {
+        double phi = phi0 + half * (1.0 + gx[i]);
+        double om = half * gw[i];
+        X[i] = rad * cos(phi);
+        Y[i] = rad * sin(phi);
+        W[i] = -om * rad * sin(phi);
+        V[i] = om * rad * cos(phi);
+    }
+}
+
+int orc_bdry_starshade(int Np, double a, double R, double b, double p, int m, int ntip,
+                       int ngap, double* X, double* Y, double* W, double* V)
+{
+    if (Np < 1 || m < 1 || ntip < 0 || ngap < 0 || !(R > a) || !(a >= 0)) return 1;
+    int nmax = m > ntip ? m : ntip;
+    if (ngap > nmax) nmax = ngap;
+    double* gx = (double*)malloc(sizeof(double) * nmax);
+    double* gw = (double*)malloc(sizeof(double) * nmax);
+    int64_t per = 2 * (int64_t)m + ntip + ngap;
+    for (int k = 0; k < Np; k++) {
+        double thk = 2.0 * ORC_PI * k / Np;
+        int64_t o = (int64_t)k * per;
+        orc_gauss_legendre(m, gx, gw);
+        for (int l = 0; l < m; l++) {
+            double r = a + 0.5 * (R - a) * (1.0 + gx[l]);
+            double wr = 0.5 * (R - a) * gw[l];
+            double h = ORC_PI * hg_profile(r, a, b, p) / Np;
+            double dh = ORC_PI * hg_profile_deriv(r, a, b, p) / Np;
+            /* lower edge, outward: phi = thk - h, phi' = -dh */
+            double pl = thk - h;
+            X[o + l] = r * cos(pl);
+            Y[o + l] = r * sin(pl);
+            W[o + l] = wr * (cos(pl) + r * dh * sin(pl));
+            V[o + l] = wr * (sin(pl) - r * dh * cos(pl));
+            /* upper edge, inward: phi = thk + h, phi' = dh, node order R -> a */
+            double pu = thk + h;
+            int64_t iu = o + m + ntip + (m - 1 - l);
+            X[iu] = r * cos(pu);
+            Y[iu] = r * sin(pu);
+            W[iu] = -wr * (cos(pu) - r * dh * sin(pu));
+            V[iu] = -wr * (sin(pu) + r * dh * cos(pu));
+        }
+        if (ntip > 0) {
+            orc_gauss_legendre(ntip, gx, gw);
+            double hR = ORC_PI * hg_profile(R, a, b, p) / Np;
+            arc_nodes(R, thk - hR, thk + hR, ntip, gx, gw, X + o + m, Y + o + m, W + o + m, V + o + m);
+        }
+        if (ngap > 0) {
+            orc_gauss_legendre(ngap, gx, gw);
+            double ha = ORC_PI * hg_profile(a, a, b, p) / Np;
+            double thn = 2.0 * ORC_PI * (k + 1) / Np;
+            int64_t og = o + 2 * (int64_t)m + ntip;
+            arc_nodes(a, thk + ha, thn - ha, ngap, gx, gw, X + og, Y + og, W + og, V + og);
+        }
+    }
+    free(gx); free(gw);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Non-singular line integral (appendix, eq. nsli): with r_i = (X_i - xi,   */
+/* Y_i - eta) and ds_i = (W_i, V_i) a CCW vector line rule on the boundary, */
+/*   u_ap = (1/2pi) sum_i (1 - exp(i pi r_i^2/(lambda z))) (r_i x ds_i)/r_i^2 */
+/* with r x ds = r_x V - r_y W and the term taken as 0 when r_i^2 = 0 (the  */
+/* cross product vanishes there too).  With t = r^2/(2 lambda z) turns and  */
+/* f = t - rint(t), 1 - exp(2 pi i f) = 2 sin(pi f) (sin(pi f) - i cos(pi f)) */
+/* (the half-angle identities), which has no cancellation as r -> 0.        */
+/* Shadow option (the appendix's remark on deep shadows, with eq. li): when */
+/* far > 0 and every node is at distance >= far from the target,            */
+/*   u_ap = u_geom - (1/2pi) sum_i exp(i pi r_i^2/(lambda z)) (r_i x ds_i)/r_i^2, */
+/* u_geom = 1 inside, 0 outside, taken as the nearest integer to the        */
+/* winding number (1/2pi) sum_i (r_i x ds_i)/r_i^2 (u_geom as the integral   */
+/* of d theta over 2pi, evaluated with the same rule).                      */
+/* Sums over i are pairwise.  u_oc = 1 - u_ap.                              */
+/* ------------------------------------------------------------------------ */
+typedef struct { double s_re, s_im, e_re, e_im, wind, d2min; } nsli_acc;
+
+static nsli_acc nsli_terms(const double* X, const double* Y, const double* W, const double* V,
+                           int64_t i0, int64_t i1, double xi, double eta, double inv2lz)
+{
+    nsli_acc s = {0.0, 0.0, 0.0, 0.0, 0.0, INFINITY};
+    if (i1 - i0 <= 16) {
+        for (int64_t i = i0; i < i1; i++) {
+            double rx = X[i] - xi, ry = Y[i] - eta;
+            double r2 = rx * rx + ry * ry;
+            if (r2 < s.d2min) s.d2min = r2;
+            if (r2 == 0.0) continue;
+            double c = (rx * V[i] - ry * W[i]) / r2;
+            double t = r2 * inv2lz;
+            double f = t - rint(t);
+            double sn = sin(ORC_PI * f), cs = cos(ORC_PI * f);
+            s.s_re += 2.0 * sn * sn * c;
+            s.s_im += -2.0 * sn * cs * c;
+            s.e_re += cos(2.0 * ORC_PI * f) * c;
+            s.e_im += sin(2.0 * ORC_PI * f) * c;
+            s.wind += c;
+        }
+        return s;
+    }
+    int64_t im = i0 + (i1 - i0) / 2;
+    nsli_acc a = nsli_terms(X, Y, W, V, i0, im, xi, eta, inv2lz);
+    nsli_acc b = nsli_terms(X, Y, W, V, im, i1, xi, eta, inv2lz);
+    s.s_re = a.s_re + b.s_re;
+    s.s_im = a.s_im + b.s_im;
+    s.e_re = a.e_re + b.e_re;
+    s.e_im = a.e_im + b.e_im;
+    s.wind = a.wind + b.wind;
+    s.d2min = a.d2min < b.d2min ? a.d2min : b.d2min;
+    return s;
+}
+
+int orc_nsli(const double* X, const double* Y, const double* W, const double* V, int64_t n,
+             double lambda, double z, const double* xi, const double* eta, int64_t M,
+             double far, int occulter, double* u)
+{
+    double lz = lambda * z;
+    if (!(lz > 0.0)) return 2;
+    double inv2lz = 1.0 / (2.0 * lz);
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t k = 0; k < M; k++) {
+        double re = 0.0, im = 0.0;
+        if (n > 0) {
+            nsli_acc s = nsli_terms(X, Y, W, V, 0, n, xi[k], eta[k], inv2lz);
+            if (far > 0.0 && s.d2min >= far * far) {
+                double geom = rint(s.wind / (2.0 * ORC_PI));
+                re = geom - s.e_re / (2.0 * ORC_PI);
+                im = -s.e_im / (2.0 * ORC_PI);
+            } else {
+                re = s.s_re / (2.0 * ORC_PI);
+                im = s.s_im / (2.0 * ORC_PI);
+            }
+        }
+        if (occulter) { re = 1.0 - re; im = -im; }
+        u[2 * k] = re;
+        u[2 * k + 1] = im;
+    }
     return 0;
 }
 
