@@ -266,6 +266,51 @@ fh_status fh_starshade_vjp(fh_ctx* ctx, int32_t Np, double a, double R, double b
                            int32_t K, const double* g_x, const double* g_y, const double* g_w,
                            double* g_coef);
 
+/* ----------------------------------------------------------- edge integral
+ * The non-singular line integral of the appendix (eq. nsli): an O(n M) direct
+ * method from a boundary rule alone, accurate for targets inside, outside and
+ * on the boundary; the paper's reference for its error tables. */
+
+/* Boundary vector line-integral rules (eq. vliq), written to caller arrays
+ * X, Y, W, V (n doubles each, in `mem`; host output synchronises):
+ *   fh_boundary_radial: the star-shaped curve of fh_quad_radial (same
+ *     parameters without m), n = panels q (or q with panels = 0);
+ *   fh_boundary_polygon: q Gauss-Legendre nodes per edge of the CCW polygon
+ *     (host vertex arrays), n = nv q;
+ *   fh_boundary_starshade: the outline of fh_quad_starshade's petal shape
+ *     (sec. 3.2; unperturbed): per petal, in this order, the lower edge
+ *     theta_k - pi A(r)/Np for r from a to R (m Gauss-Legendre radii), the
+ *     tip arc at r = R (ntip Gauss-Legendre angles), the upper edge
+ *     theta_k + pi A(r)/Np from R back to a, and the arc at r = a to the next
+ *     petal (ngap nodes; zero weights for this profile, whose A(a) = 1);
+ *     n = Np (2 m + ntip + ngap).  The paper's HG outline is m = 60,
+ *     ntip = ngap = 4 (n = 2048 for 16 petals). */
+fh_status fh_boundary_radial(fh_ctx* ctx, double r0, const double* a, const double* b, int32_t K,
+                             int32_t panels, int32_t q, double* X, double* Y, double* W, double* V,
+                             fh_memspace mem);
+fh_status fh_boundary_polygon(fh_ctx* ctx, const double* vx, const double* vy, int32_t nv, int32_t q,
+                              double* X, double* Y, double* W, double* V, fh_memspace mem);
+fh_status fh_boundary_starshade(fh_ctx* ctx, int32_t Np, double a, double R, double b, double p,
+                                int32_t m, int32_t ntip, int32_t ngap, double* X, double* Y, double* W,
+                                double* V, fh_memspace mem);
+
+/* Field at M targets by the edge integral (appendix, eq. nsli) over a CCW
+ * boundary rule (X_i, Y_i) with vector weights (W_i, V_i), i < n:
+ *   u_ap = (1/2pi) sum_i (1 - exp(i pi r_i^2/(lambda z))) (r_i x ds_i)/r_i^2,
+ *   r_i = (X_i - xi, Y_i - eta), r x ds = r_x V_i - r_y W_i,
+ * a term being 0 when r_i = 0 (a target on a node).  far > 0 selects, for
+ * targets at least `far` from every node, the form of eq. li with the exact
+ * geometric term (the nearest integer to the rule's winding number), which
+ * removes a low-order rule's error from that term in deep shadow (the
+ * appendix's remark); far = 0 uses eq. nsli everywhere.  All arrays are in
+ * `mem`; u gets M complex values in the context's precision (u_oc = 1 - u_ap
+ * if occulter).  The arithmetic is FP64 in both precisions.  n = 0 gives
+ * u_ap = 0; M = 0 is a no-op.  Device memory: enqueued on the context stream
+ * without synchronising; host memory: copies and synchronises. */
+fh_status fh_field_nsli(fh_ctx* ctx, const double* X, const double* Y, const double* W, const double* V,
+                        int64_t n, double lambda, double z, int64_t M, const double* xi,
+                        const double* eta, double far, int32_t occulter, void* u, fh_memspace mem);
+
 /* --------------------------------------------------------------- autotuner */
 
 /* Time fh_field_grid for this rule and grid over a set of tile sizes,

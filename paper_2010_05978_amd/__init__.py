@@ -128,6 +128,27 @@ class Context:
                                        shape.nd, shape.md, shape.coef, shape.K)
         raise TypeError(f"unknown shape {kind}")
 
+    # ------------------------------------------------- boundary rules
+    # A boundary rule is a (4, n) float64 device tensor: rows X, Y, W, V.
+    def _bdry(self, n):
+        import torch
+        return torch.empty((4, n), dtype=torch.float64, device=self.device)
+
+    def boundary_radial(self, r0, a=None, b=None, panels=1, q=20):
+        B = self._bdry(panels * q if panels > 0 else q)
+        abi.fh_boundary_radial(self.handle, r0, a, b, panels, q, B)
+        return B
+
+    def boundary_polygon(self, vx, vy, q):
+        B = self._bdry(len(vx) * q)
+        abi.fh_boundary_polygon(self.handle, vx, vy, q, B)
+        return B
+
+    def boundary_starshade(self, Np, a, R, b, p, m, ntip=4, ngap=0):
+        B = self._bdry(Np * (2 * m + ntip + ngap))
+        abi.fh_boundary_starshade(self.handle, Np, a, R, b, p, m, ntip, ngap, B)
+        return B
+
     def targets(self, xi, eta, box=None) -> Targets:
         """Target set for repeated type-3 calls; box = (xmin, xmax, ymin, ymax)
         declares the region (no readback), None computes it."""
@@ -156,6 +177,15 @@ class Context:
         if out is None:
             out = torch.empty(targets.M, dtype=self.cdtype, device=self.device)
         abi.fh_field_targets(self.handle, quad.handle, lam, z, targets.handle, occulter, out)
+        return out
+
+    def field_nsli(self, B, lam, z, xi, eta, far=0.0, occulter=False, out=None):
+        """Edge-integral field (eq. nsli) from a boundary rule B (4 x n)."""
+        import torch
+        if out is None:
+            dev = xi.device if hasattr(xi, "device") else self.device
+            out = torch.empty(len(xi), dtype=self.cdtype, device=dev)
+        abi.fh_field_nsli(self.handle, B, lam, z, xi, eta, far, occulter, out)
         return out
 
     def field_grid_batch(self, quads, lams, zs, n1, n2, h1, h2, xc=0.0, yc=0.0, occulter=False, out=None):

@@ -37,6 +37,7 @@ EXPORTED = [
     "fh_quad_destroy", "fh_targets_create", "fh_targets_size", "fh_targets_box", "fh_targets_destroy",
     "fh_field_grid", "fh_field_points", "fh_field_targets", "fh_field_grid_batch", "fh_field_grid_vjp",
     "fh_starshade_vjp", "fh_autotune_grid", "fh_set_timing", "fh_last_timing", "fh_timing_totals",
+    "fh_boundary_radial", "fh_boundary_polygon", "fh_boundary_starshade", "fh_field_nsli",
 ]
 
 
@@ -96,6 +97,10 @@ def lib():
             "fh_set_timing": [vp, i32],
             "fh_last_timing": [vp, ctypes.POINTER(d)],
             "fh_timing_totals": [vp, i32, ctypes.POINTER(d), ctypes.POINTER(i64), i32],
+            "fh_boundary_radial": [vp, d, vp, vp, i32, i32, i32, vp, vp, vp, vp, ctypes.c_int],
+            "fh_boundary_polygon": [vp, vp, vp, i32, i32, vp, vp, vp, vp, ctypes.c_int],
+            "fh_boundary_starshade": [vp, i32, d, d, d, d, i32, i32, i32, vp, vp, vp, vp, ctypes.c_int],
+            "fh_field_nsli": [vp, vp, vp, vp, vp, i64, d, d, i64, vp, vp, d, i32, vp, ctypes.c_int],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -273,6 +278,50 @@ def fh_field_points(ctx, q, lam, z, xi, eta, occulter, u):
     mem = _same_mem(xi, eta, u)
     _check(lib().fh_field_points(ctx, q, lam, z, len(xi), _ptr_mem(xi)[0], _ptr_mem(eta)[0],
                                  int(bool(occulter)), _ptr_mem(u)[0], mem))
+
+
+def _rows4(B):
+    """The four rows (X, Y, W, V) of a boundary rule: a (4, n) array or tensor."""
+    if B.shape[0] != 4:
+        raise ValueError("a boundary rule is a (4, n) array: X, Y, W, V")
+    return B[0], B[1], B[2], B[3]
+
+
+def fh_boundary_radial(ctx, r0, a, b, panels, q, B):
+    """Fill B (4 x n doubles, n = panels q or q) with the curve's boundary rule."""
+    K = 0 if a is None else len(a)
+    a = None if a is None else np.ascontiguousarray(a, dtype=np.float64)
+    b = None if b is None else np.ascontiguousarray(b, dtype=np.float64)
+    X, Y, W, V = _rows4(B)
+    mem = _same_mem(X, Y, W, V)
+    _check(lib().fh_boundary_radial(ctx, r0, _ptr_mem(a)[0], _ptr_mem(b)[0], K, panels, q, _ptr_mem(X)[0],
+                                    _ptr_mem(Y)[0], _ptr_mem(W)[0], _ptr_mem(V)[0], mem))
+
+
+def fh_boundary_polygon(ctx, vx, vy, q, B):
+    vx = np.ascontiguousarray(vx, dtype=np.float64)
+    vy = np.ascontiguousarray(vy, dtype=np.float64)
+    X, Y, W, V = _rows4(B)
+    mem = _same_mem(X, Y, W, V)
+    _check(lib().fh_boundary_polygon(ctx, _ptr_mem(vx)[0], _ptr_mem(vy)[0], len(vx), q, _ptr_mem(X)[0],
+                                     _ptr_mem(Y)[0], _ptr_mem(W)[0], _ptr_mem(V)[0], mem))
+
+
+def fh_boundary_starshade(ctx, Np, a, R, b, p, m, ntip, ngap, B):
+    X, Y, W, V = _rows4(B)
+    mem = _same_mem(X, Y, W, V)
+    _check(lib().fh_boundary_starshade(ctx, Np, a, R, b, p, m, ntip, ngap, _ptr_mem(X)[0], _ptr_mem(Y)[0],
+                                       _ptr_mem(W)[0], _ptr_mem(V)[0], mem))
+
+
+def fh_field_nsli(ctx, B, lam, z, xi, eta, far, occulter, u):
+    X, Y, W, V = _rows4(B)
+    if len(xi) != len(eta):
+        raise ValueError("xi and eta must have the same length")
+    mem = _same_mem(X, Y, W, V, xi, eta, u)
+    _check(lib().fh_field_nsli(ctx, _ptr_mem(X)[0], _ptr_mem(Y)[0], _ptr_mem(W)[0], _ptr_mem(V)[0], X.shape[0],
+                               lam, z, len(xi), _ptr_mem(xi)[0], _ptr_mem(eta)[0], float(far),
+                               int(bool(occulter)), _ptr_mem(u)[0], mem))
 
 
 def fh_targets_create(ctx, xi, eta, box=None):

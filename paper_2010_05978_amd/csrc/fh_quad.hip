@@ -214,6 +214,89 @@ __global__ void k_petals(PetalParams pp, const double* __restrict__ glm, const d
     w[j] = r * wr * half * wt;
 }
 
+// Boundary rule alone (for the edge integral): one thread per node.
+__global__ void k_bdry_radial(RadialParams rp, const double* __restrict__ glq, int64_t n, double* __restrict__ X,
+                              double* __restrict__ Y, double* __restrict__ Wv, double* __restrict__ Vv)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double x, y, w, v;
+    radial_node(rp, glq, n, i, x, y, w, v);
+    X[i] = x;
+    Y[i] = y;
+    Wv[i] = w;
+    Vv[i] = v;
+}
+
+// Starshade outline (sec. 3.2's petal shape): per petal k, with half-width
+// angle h(r) = pi A(r)/Np about theta_k = 2 pi k/Np, the lower edge
+// theta_k - h(r) for r from a to R (m GL radii), the tip arc at r = R
+// (ntip GL angles), the upper edge theta_k + h(r) from R back to a, and the
+// arc at r = a to the next petal (ngap GL angles; of zero width when
+// A(a) = 1).  Edge weights are P'(r) w_r with P(r) = r (cos phi, sin phi)
+// and phi'(r) = -+ pi A'(r)/Np, negated on the inward upper edge.
+struct OutlineParams {
+    int Np, m, ntip, ngap;
+    double a, R, b, p;
+};
+
+__device__ __forceinline__ void arc_node(double rad, double phi0, double phi1, double x, double wq, double& X,
+                                         double& Y, double& W, double& V)
+{
+    const double half = 0.5 * (phi1 - phi0);
+    double s, c;
+    sincos(phi0 + half * (1.0 + x), &s, &c);
+    X = rad * c;
+    Y = rad * s;
+    W = -half * wq * rad * s;
+    V = half * wq * rad * c;
+}
+
+__global__ void k_bdry_starshade(OutlineParams op, const double* __restrict__ glm, const double* __restrict__ glt,
+                                 const double* __restrict__ glg, double* __restrict__ X, double* __restrict__ Y,
+                                 double* __restrict__ Wv, double* __restrict__ Vv)
+{
+    const int per = 2 * op.m + op.ntip + op.ngap;
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= (int64_t)per * op.Np) return;
+    const int k = (int)(i / per);
+    const int j = (int)(i - (int64_t)k * per);
+    const double thk = 2.0 * kPi * k / op.Np;
+    double x, y, w, v;
+    if (j < op.m || (j >= op.m + op.ntip && j < 2 * op.m + op.ntip)) {
+        const bool lower = j < op.m;
+        const int l = lower ? j : 2 * op.m + op.ntip - 1 - j;
+        const double L = op.R - op.a;
+        const double r = op.a + 0.5 * L * (1.0 + glm[l]);
+        const double wr = 0.5 * L * glm[op.m + l];
+        const double sr = (r - op.a) / op.b;
+        const double A = exp(-pow(sr, op.p));
+        const double dA = r > op.a ? -(op.p / op.b) * pow(sr, op.p - 1.0) * A : 0.0;
+        const double sg = lower ? -1.0 : 1.0;  // phi = thk + sg h(r)
+        const double phi = thk + sg * kPi * A / op.Np;
+        const double dphi = sg * kPi * dA / op.Np;
+        double s, c;
+        sincos(phi, &s, &c);
+        const double ww = lower ? wr : -wr;
+        x = r * c;
+        y = r * s;
+        w = ww * (c - r * dphi * s);
+        v = ww * (s + r * dphi * c);
+    } else if (j < op.m + op.ntip) {
+        const int t = j - op.m;
+        const double h = kPi * exp(-pow((op.R - op.a) / op.b, op.p)) / op.Np;
+        arc_node(op.R, thk - h, thk + h, glt[t], glt[op.ntip + t], x, y, w, v);
+    } else {
+        const int t = j - 2 * op.m - op.ntip;
+        const double h = kPi / op.Np;  // A(a) = 1
+        arc_node(op.a, thk + h, thk + 2.0 * kPi / op.Np - h, glg[t], glg[op.ngap + t], x, y, w, v);
+    }
+    X[i] = x;
+    Y[i] = y;
+    Wv[i] = w;
+    Vv[i] = v;
+}
+
 inline unsigned nblocks(int64_t n, int bs) { return (unsigned)std::max<int64_t>(1, (n + bs - 1) / bs); }
 
 // A box that contains every node (used to size fine grids and row windows).
@@ -236,6 +319,39 @@ fh_status radial_into(fh_ctx* c, const RadialParams& rp, int64_t n, int m, doubl
     hipLaunchKernelGGL(k_radial_rule, dim3(nblocks(n * m, 256)), dim3(256), 0, c->stream, rp, glq, n, m, glm, x, y,
                        w);
     FH_HIP(hipGetLastError());
+    return FH_OK;
+}
+
+// Boundary-rule outputs: device arrays are written in place; host arrays go
+// through the arena and are copied back (one synchronisation).  The arena is
+// reserved once for those and for `extra` bytes the caller takes afterwards.
+struct BdryOut {
+    double* d[4];
+};
+
+fh_status bdry_begin(fh_ctx* c, int64_t n, double* X, double* Y, double* W, double* V, fh_memspace mem,
+                     size_t extra, BdryOut* o)
+{
+    const size_t nb = aligned_bytes(sizeof(double) * std::max<int64_t>(n, 1));
+    FH_TRY(arena_reserve(c, (mem == FH_MEM_HOST ? 4 * nb : 0) + extra));
+    if (mem == FH_MEM_DEVICE) {
+        o->d[0] = X; o->d[1] = Y; o->d[2] = W; o->d[3] = V;
+        return FH_OK;
+    }
+    for (int k = 0; k < 4; ++k) o->d[k] = c->arena.take<double>(std::max<int64_t>(n, 1));
+    return FH_OK;
+}
+
+fh_status bdry_end(fh_ctx* c, int64_t n, double* X, double* Y, double* W, double* V, fh_memspace mem,
+                   const BdryOut& o)
+{
+    FH_HIP(hipGetLastError());
+    if (mem == FH_MEM_HOST) {
+        double* h[4] = {X, Y, W, V};
+        for (int k = 0; k < 4; ++k)
+            FH_HIP(hipMemcpyAsync(h[k], o.d[k], sizeof(double) * n, hipMemcpyDeviceToHost, c->stream));
+        FH_HIP(hipStreamSynchronize(c->stream));
+    }
     return FH_OK;
 }
 
@@ -525,6 +641,105 @@ fh_status fh_quad_from_nodes(fh_ctx* c, const double* x, const double* y, const 
         }
         *out = qd;
         return FH_OK;
+    } catch (...) {
+        set_error("host allocation failed");
+        return FH_ERR_ALLOC;
+    }
+}
+
+fh_status fh_boundary_radial(fh_ctx* c, double r0, const double* a, const double* b, int32_t K,
+                             int32_t panels, int32_t q, double* X, double* Y, double* W, double* V,
+                             fh_memspace mem)
+{
+    try {
+        FH_ARG(c && X && Y && W && V, FH_ERR_INVALID_ARG, "NULL argument");
+        FH_ARG(K >= 0 && K <= kMaxFourier, FH_ERR_INVALID_ARG, "K must be in [0, %d]", kMaxFourier);
+        FH_ARG(panels >= 0 && q >= 1, FH_ERR_INVALID_ARG, "need panels >= 0, q >= 1");
+        FH_ARG(mem == FH_MEM_HOST || mem == FH_MEM_DEVICE, FH_ERR_INVALID_ARG, "bad memspace");
+        FH_ARG(std::isfinite(r0), FH_ERR_NONFINITE, "r0 not finite");
+        RadialParams rp{};
+        rp.r0 = r0;
+        rp.K = K;
+        rp.panels = panels;
+        rp.q = q;
+        for (int k = 0; k < K; ++k) {
+            rp.a[k] = a ? a[k] : 0.0;
+            rp.b[k] = b ? b[k] : 0.0;
+            FH_ARG(std::isfinite(rp.a[k]) && std::isfinite(rp.b[k]), FH_ERR_NONFINITE,
+                   "Fourier coefficient %d not finite", k + 1);
+        }
+        const int64_t n = panels > 0 ? (int64_t)panels * q : q;
+        FH_HIP(hipSetDevice(c->device));
+        const double* glq = nullptr;
+        if (panels > 0) FH_TRY(gl_table(c, q, &glq));
+        BdryOut o;
+        FH_TRY(bdry_begin(c, n, X, Y, W, V, mem, 0, &o));
+        hipLaunchKernelGGL(k_bdry_radial, dim3(nblocks(n, 256)), dim3(256), 0, c->stream, rp, glq, n, o.d[0], o.d[1],
+                           o.d[2], o.d[3]);
+        return bdry_end(c, n, X, Y, W, V, mem, o);
+    } catch (...) {
+        set_error("host allocation failed");
+        return FH_ERR_ALLOC;
+    }
+}
+
+fh_status fh_boundary_polygon(fh_ctx* c, const double* vx, const double* vy, int32_t nv, int32_t q, double* X,
+                              double* Y, double* W, double* V, fh_memspace mem)
+{
+    try {
+        FH_ARG(c && vx && vy && X && Y && W && V, FH_ERR_INVALID_ARG, "NULL argument");
+        FH_ARG(nv >= 3 && q >= 1, FH_ERR_INVALID_ARG, "need nv >= 3, q >= 1");
+        FH_ARG(mem == FH_MEM_HOST || mem == FH_MEM_DEVICE, FH_ERR_INVALID_ARG, "bad memspace");
+        for (int i = 0; i < nv; ++i)
+            FH_ARG(std::isfinite(vx[i]) && std::isfinite(vy[i]), FH_ERR_NONFINITE, "vertex %d not finite", i);
+        FH_HIP(hipSetDevice(c->device));
+        const double* glq = nullptr;
+        FH_TRY(gl_table(c, q, &glq));
+        const int64_t n = (int64_t)nv * q;
+        BdryOut o;
+        FH_TRY(bdry_begin(c, n, X, Y, W, V, mem, 2 * aligned_bytes(sizeof(double) * nv), &o));
+        double* dvx = c->arena.take<double>(nv);
+        double* dvy = c->arena.take<double>(nv);
+        FH_HIP(hipMemcpyAsync(dvx, vx, sizeof(double) * nv, hipMemcpyHostToDevice, c->stream));
+        FH_HIP(hipMemcpyAsync(dvy, vy, sizeof(double) * nv, hipMemcpyHostToDevice, c->stream));
+        hipLaunchKernelGGL(k_bdry_polygon, dim3(nblocks(n, 256)), dim3(256), 0, c->stream, dvx, dvy, nv, q, glq,
+                           o.d[0], o.d[1], o.d[2], o.d[3]);
+        fh_status s = bdry_end(c, n, X, Y, W, V, mem, o);
+        // the host vertex arrays may be released by the caller on return
+        if (s == FH_OK && mem == FH_MEM_DEVICE) FH_HIP(hipStreamSynchronize(c->stream));
+        return s;
+    } catch (...) {
+        set_error("host allocation failed");
+        return FH_ERR_ALLOC;
+    }
+}
+
+fh_status fh_boundary_starshade(fh_ctx* c, int32_t Np, double a, double R, double b, double p, int32_t m,
+                                int32_t ntip, int32_t ngap, double* X, double* Y, double* W, double* V,
+                                fh_memspace mem)
+{
+    try {
+        FH_ARG(c && X && Y && W && V, FH_ERR_INVALID_ARG, "NULL argument");
+        FH_ARG(Np >= 1 && m >= 1 && ntip >= 0 && ngap >= 0, FH_ERR_INVALID_ARG,
+               "need Np, m >= 1 and ntip, ngap >= 0");
+        FH_ARG(std::isfinite(a) && std::isfinite(R) && std::isfinite(b) && std::isfinite(p),
+               FH_ERR_NONFINITE, "starshade scalar not finite");
+        FH_ARG(a >= 0 && R > a && b > 0 && p > 0, FH_ERR_INVALID_ARG, "need 0 <= a < R, b > 0, p > 0");
+        FH_ARG(mem == FH_MEM_HOST || mem == FH_MEM_DEVICE, FH_ERR_INVALID_ARG, "bad memspace");
+        FH_HIP(hipSetDevice(c->device));
+        const double* glm = nullptr;
+        const double* glt = nullptr;
+        const double* glg = nullptr;
+        FH_TRY(gl_table(c, m, &glm));
+        if (ntip > 0) FH_TRY(gl_table(c, ntip, &glt));
+        if (ngap > 0) FH_TRY(gl_table(c, ngap, &glg));
+        const int64_t n = (int64_t)Np * (2 * (int64_t)m + ntip + ngap);
+        BdryOut o;
+        FH_TRY(bdry_begin(c, n, X, Y, W, V, mem, 0, &o));
+        OutlineParams op{Np, m, ntip, ngap, a, R, b, p};
+        hipLaunchKernelGGL(k_bdry_starshade, dim3(nblocks(n, 256)), dim3(256), 0, c->stream, op, glm, glt, glg,
+                           o.d[0], o.d[1], o.d[2], o.d[3]);
+        return bdry_end(c, n, X, Y, W, V, mem, o);
     } catch (...) {
         set_error("host allocation failed");
         return FH_ERR_ALLOC;
