@@ -49,8 +49,8 @@ def parse():
                     help="also run a plain 256 MiB device copy (counter calibration for rocprofv3 --pmc)")
     ap.add_argument("--no-grad", action="store_true", help="skip the backward/forward ratio (workload 5)")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched workload 4")
-    ap.add_argument("--parts", default="step,grad,batch",
-                    help="comma list of step, grad, batch to run (profiling one part alone; "
+    ap.add_argument("--parts", default="step,grad,batch,nsli",
+                    help="comma list of step, grad, batch, nsli to run (profiling one part alone; "
                          "without step the line carries no value)")
     return ap.parse_args()
 
@@ -253,6 +253,74 @@ def batch_throughput(fh, steps, warmup):
             "instances": B, "nodes": N, "dtype": "c64-f64phase", "tolerance": 1e-5}
 
 
+# FP64 flops per node-target pair of the edge-integral kernel (an FMA counts
+# 2): the inner loop of k_nsli as built, per pair 31 FMAs and 9 adds or
+# multiplies (displacement, r^2, cross product, turns and their reduction,
+# the two Taylor series of sin/cos(pi f), the refined reciprocal of r^2 and
+# the three accumulations).
+NSLI_FLOPS_PER_PAIR = 71
+FP64_PEAK_TFLOPS = 78.6
+
+
+def nsli_throughput(fh, wl, steps, warmup, cpu_seconds):
+    """Edge integral (eq. nsli) over the starfish outline (20 GL panels x 20 =
+    400 boundary nodes) at the step's 1.1e6 targets (the 1000^2 grid and the
+    1e5 scattered points), FP64; one kernel launch per call, timed with HIP
+    events on the context's stream.  The oracle's edge integral is timed on a
+    seeded sample of the same targets."""
+    import numpy as np
+    import torch
+    import oracle
+    ctx = fh.Context("fp64")
+    s = wl.shape
+    B = ctx.boundary_radial(s.r0, s.a, s.b, s.panels, s.q)
+    g = wl.grid
+    k1 = torch.arange(-(g.n1 // 2), g.n1 - g.n1 // 2, dtype=torch.float64, device="cuda") * g.h1
+    k2 = torch.arange(-(g.n2 // 2), g.n2 - g.n2 // 2, dtype=torch.float64, device="cuda") * g.h2
+    XI, ETA = torch.meshgrid(k1, k2, indexing="xy")
+    xi = torch.cat([XI.reshape(-1), torch.tensor(wl.points[0], device="cuda")]).contiguous()
+    eta = torch.cat([ETA.reshape(-1), torch.tensor(wl.points[1], device="cuda")]).contiguous()
+    M, n = xi.numel(), B.shape[1]
+    u = torch.empty(M, dtype=torch.complex128, device="cuda")
+    for _ in range(warmup):
+        ctx.field_nsli(B, wl.lam, wl.z, xi, eta, occulter=True, out=u)
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    torch.cuda.synchronize()
+    ev[0].record(stream)
+    for k in range(steps):
+        ctx.field_nsli(B, wl.lam, wl.z, xi, eta, occulter=True, out=u)
+        ev[k + 1].record(stream)
+    torch.cuda.synchronize()
+    per = [ev[k].elapsed_time(ev[k + 1]) for k in range(steps)]
+    ms = sum(per) / steps
+    ctx.close()
+    achieved = NSLI_FLOPS_PER_PAIR * M * n / (ms * 1e-3) / 1e12
+    out = {"value": M / (ms * 1e-3), "unit": "targets/s", "ms_per_call": ms, "pairs_per_s": M * n / (ms * 1e-3),
+           "nodes": n, "targets": M, "dtype": "f64",
+           "workload": "starfish outline, 20 GL panels x 20 nodes; the step's 1000x1000 grid + 1e5 random targets",
+           "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                        "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None, "kernel": "k_nsli<2, double>",
+                        "flops_per_pair": NSLI_FLOPS_PER_PAIR, "avg_launch_ms": ms}}
+    if cpu_seconds > 0:
+        X, Y, W, V = oracle.boundary_radial_gl(s.r0, s.a, s.b, s.panels, s.q)
+        xh, eh = xi.cpu().numpy(), eta.cpu().numpy()
+        rng = np.random.Generator(np.random.PCG64(4343))
+        probe = rng.choice(M, 2048, replace=False)
+        t0 = time.perf_counter()
+        oracle.nsli(X, Y, W, V, wl.lam, wl.z, xh[probe], eh[probe], occulter=True)
+        per_t = (time.perf_counter() - t0) / 2048
+        m = int(min(M, max(2048, cpu_seconds / max(per_t, 1e-9))))
+        idx = rng.choice(M, m, replace=False)
+        t0 = time.perf_counter()
+        oracle.nsli(X, Y, W, V, wl.lam, wl.z, xh[idx], eh[idx], occulter=True)
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": m / dt, "unit": "targets/s", "cores": oracle.num_threads(),
+                               "kind": "oracle", "sample": f"{m} of the {M} targets, oracle edge integral "
+                                                           f"over all {n} nodes, {dt:.1f} s"}
+    return out
+
+
 def cpu_baseline(wl, seconds):
     """The oracle (direct FP64 sum) on a seeded sample of the step's targets."""
     import numpy as np
@@ -297,6 +365,9 @@ def main():
             out["backward_forward"] = {p: grad_ratio(fh, p, 3, 1) for p in precs}
         if "batch" in parts and not args.no_batch:
             out["batch"] = batch_throughput(fh, 5, 2)
+        if "nsli" in parts:
+            out["nsli"] = nsli_throughput(fh, wl, args.steps, args.warmup,
+                                          0.0 if args.no_cpu_baseline else 3.0)
         print(json.dumps(out))
         return
     res = {}
@@ -334,6 +405,8 @@ def main():
         out["backward_forward"] = {p: grad_ratio(fh, p, 3, 1) for p in precs}
     if not args.no_batch and "batch" in parts:
         out["batch"] = batch_throughput(fh, 5, 2)
+    if "nsli" in parts:
+        out["nsli"] = nsli_throughput(fh, wl, args.steps, args.warmup, 0.0 if args.no_cpu_baseline else 3.0)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
     print(json.dumps(out))

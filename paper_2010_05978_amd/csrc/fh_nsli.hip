@@ -31,7 +31,7 @@ namespace fh {
 namespace {
 
 constexpr int kNsliBlock = 256;
-constexpr double kNsliTiny = 1e-280;  // r^2 below this: the term is below any result's rounding
+constexpr double kNsliTiny = 1e-280;  // floor of r^2 before its reciprocal
 
 struct NsliParams {
     const double* X;
@@ -65,6 +65,50 @@ __device__ __forceinline__ double rcp_f64(double x)
     return fma(y, e, y);
 }
 
+// Taylor coefficients of sin(pi f) = f sum_k s_k f^(2k) and
+// cos(pi f) = sum_k c_k f^(2k): s_k = (-1)^k pi^(2k+1)/(2k+1)!,
+// c_k = (-1)^k pi^(2k)/(2k)!.  On |f| <= 1/2 the first 11 and 12 terms leave
+// a truncation error below 1e-18 (the next terms are (pi/2)^23/23! and
+// (pi/2)^24/24!), so the sums are good to rounding.
+constexpr int kSinTerms = 11, kCosTerms = 12;
+struct PiSeries {
+    double s[kSinTerms];
+    double c[kCosTerms];
+    constexpr PiSeries() : s(), c()
+    {
+        const double pi2 = kPi * kPi;
+        double t = kPi;
+        for (int k = 0; k < kSinTerms; ++k) {
+            s[k] = t;
+            t *= -pi2 / ((2.0 * k + 2.0) * (2.0 * k + 3.0));
+        }
+        t = 1.0;
+        for (int k = 0; k < kCosTerms; ++k) {
+            c[k] = t;
+            t *= -pi2 / ((2.0 * k + 1.0) * (2.0 * k + 2.0));
+        }
+    }
+};
+constexpr PiSeries kPiSeries{};
+
+// sin(pi f) and cos(pi f) for |f| <= 1/2 (Horner in f^2).
+__device__ __forceinline__ void sincospi_half(double f, double& sn, double& cs)
+{
+    const double f2 = f * f;
+    double ps = kPiSeries.s[kSinTerms - 1];
+#pragma unroll
+    for (int k = kSinTerms - 2; k >= 0; --k) ps = fma(ps, f2, kPiSeries.s[k]);
+    double pc = kPiSeries.c[kCosTerms - 1];
+#pragma unroll
+    for (int k = kCosTerms - 2; k >= 0; --k) pc = fma(pc, f2, kPiSeries.c[k]);
+    sn = f * ps;
+    cs = pc;
+}
+
+// One node's term.  The accumulators hold half the NSLI sum (the factor 2 of
+// the half-angle form is applied once at the end).  r^2 is floored at a tiny
+// value before the reciprocal: a target on a node has r x ds = 0 there, so
+// its term is 0; nearer than 1e-140 the term is below any rounding.
 __device__ __forceinline__ void nsli_term(double bx, double by, double bw, double bv, double xi, double eta,
                                           double inv2lz, NsliAcc& a)
 {
@@ -75,25 +119,25 @@ __device__ __forceinline__ void nsli_term(double bx, double by, double bw, doubl
     const double t = r2 * inv2lz;
     const double f = t - rint(t);
     double sn, cs;
-    sincospi(f, &sn, &cs);
-    const double inv = r2 > kNsliTiny ? rcp_f64(r2) : 0.0;
-    const double c = cr * inv;
-    const double g = 2.0 * sn * c;
-    a.sre = fma(g, sn, a.sre);
-    a.sim = fma(-g, cs, a.sim);
+    sincospi_half(f, sn, cs);
+    const double c = cr * rcp_f64(fmax(r2, kNsliTiny));
+    const double h = sn * c;
+    a.sre = fma(h, sn, a.sre);
+    a.sim = fma(-h, cs, a.sim);
     a.wnd += c;
 }
 
 template <class OUT>
 __device__ __forceinline__ void nsli_store(const NsliParams& p, int64_t k, const NsliAcc& a, OUT* __restrict__ u)
 {
-    constexpr double inv2pi = 0.15915494309189533577;
-    double re, im = a.sim * inv2pi;
+    // sre, sim hold half of the NSLI sum (see nsli_term)
+    constexpr double inv2pi = 0.5 / kPi, invpi = 1.0 / kPi;
+    double re, im = a.sim * invpi;
     if (p.shadow && a.d2 >= p.far2) {
         const double geom = rint(a.wnd * inv2pi);
-        re = geom - (a.wnd - a.sre) * inv2pi;
+        re = geom - a.wnd * inv2pi + a.sre * invpi;
     } else {
-        re = a.sre * inv2pi;
+        re = a.sre * invpi;
     }
     if (p.occulter) {
         re = 1.0 - re;
