@@ -7,6 +7,7 @@ over targets) through ctypes and shares no source with the GPU library.
 What it computes (Barnett, arXiv:2010.05978):
   * Gauss-Legendre rules and the boundary vector line-integral rules (eq. vliq:
     Gauss-Legendre panels in angle, the periodic trapezoid rule of eq. ptr,
+    for radial curves and general Fourier curves such as the kite of sec. 3.1;
     polygons with Gauss-Legendre nodes per edge);
   * the dilation areal rule (eqs. aqnod/aqwei, sec. 3.1) and the starshade
     disc + petal rule (sec. 3.2), optionally with lateral edge perturbations;
@@ -64,13 +65,14 @@ def _load():
                                                _dp, _dp, _dp, _dp]
         lib.orc_starshade_vjp.argtypes = [i32, d, d, d, d, i32, i32, i32, i32, _dp, i32,
                                           _dp, _dp, _dp, _dp]
+        lib.orc_bdry_fourier.argtypes = [_dp, _dp, _dp, _dp, i32, i32, i32, _dp, _dp, _dp, _dp]
         lib.orc_bdry_starshade.argtypes = [i32, d, d, d, d, i32, i32, i32, _dp, _dp, _dp, _dp]
         lib.orc_nsli.argtypes = [_dp, _dp, _dp, _dp, i64, d, d, _dp, _dp, i64, d, i32, _dp]
         lib.orc_num_threads.restype = i32
         for name in ("orc_gauss_legendre", "orc_bdry_radial_gl", "orc_bdry_radial_ptr",
                      "orc_bdry_polygon", "orc_dilation", "orc_starshade",
                      "orc_fresnel_direct", "orc_fresnel_direct_vjp", "orc_starshade_vjp",
-                     "orc_bdry_starshade", "orc_nsli"):
+                     "orc_bdry_starshade", "orc_nsli", "orc_bdry_fourier"):
             getattr(lib, name).restype = i32
         _lib = lib
     return _lib
@@ -141,6 +143,22 @@ def boundary_polygon(vx, vy, q):
     _check(_load().orc_bdry_polygon(_p(vx), _p(vy), len(vx), q,
                                      _p(out[0]), _p(out[1]), _p(out[2]), _p(out[3])),
            "boundary_polygon")
+    return out[0], out[1], out[2], out[3]
+
+
+def boundary_fourier(ax, bx, ay, by, panels=0, q=100):
+    """Vector line rule (eq. vliq1) for the closed curve X(t) = sum_k ax_k cos kt
+    + bx_k sin kt, Y(t) likewise, k = 0..K (arrays of length K+1): panels = 0
+    is the periodic trapezoid rule of eq. ptr with q nodes, else GL panels."""
+    ax, bx, ay, by = (_f64(t) for t in (ax, bx, ay, by))
+    K = len(ax) - 1
+    if not (len(bx) == len(ay) == len(by) == K + 1):
+        raise ValueError("coefficient arrays must have the same length K+1")
+    n = panels * q if panels > 0 else q
+    out = np.empty((4, n))
+    _check(_load().orc_bdry_fourier(_p(ax), _p(bx), _p(ay), _p(by), K, panels, q,
+                                     _p(out[0]), _p(out[1]), _p(out[2]), _p(out[3])),
+           "boundary_fourier")
     return out[0], out[1], out[2], out[3]
 
 

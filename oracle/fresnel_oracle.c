@@ -159,6 +159,54 @@ int orc_bdry_polygon(const double* vx, const double* vy, int nv, int q,
     return 0;
 }
 
+/* General smooth closed curve given by its Fourier series, eq. vliq1:      */
+/*   X(t) = sum_{k=0}^K ax_k cos kt + bx_k sin kt,  Y(t) likewise (ay, by), */
+/* CCW in t.  P > 0: P Gauss-Legendre panels of q nodes in t (as for the    */
+/* radial curve); P = 0: the periodic trapezoid rule of eq. ptr with q      */
+/* nodes t_i = 2 pi i/q, i = 1..q.  (W, V) = weight * x'(t).                */
+static void fourier_curve(const double* ax, const double* bx, const double* ay, const double* by,
+                          int K, double t, double* X, double* Y, double* dX, double* dY)
+{
+    double x = 0.0, y = 0.0, dx = 0.0, dy = 0.0;
+    for (int k = 0; k <= K; k++) {
+        double c = cos(k * t), s = sin(k * t);
+        x += ax[k] * c + bx[k] * s;
+        y += ay[k] * c + by[k] * s;
+        dx += k * (-ax[k] * s + bx[k] * c);
+        dy += k * (-ay[k] * s + by[k] * c);
+    }
+    *X = x; *Y = y; *dX = dx; *dY = dy;
+}
+
+int orc_bdry_fourier(const double* ax, const double* bx, const double* ay, const double* by, int K,
+                     int P, int q, double* X, double* Y, double* W, double* V)
+{
+    if (K < 0 || P < 0 || q < 1) return 1;
+    if (P == 0) {
+        for (int i = 1; i <= q; i++) {
+            double t = 2.0 * ORC_PI * i / q, om = 2.0 * ORC_PI / q;
+            double x, y, dx, dy;
+            fourier_curve(ax, bx, ay, by, K, t, &x, &y, &dx, &dy);
+            X[i - 1] = x; Y[i - 1] = y; W[i - 1] = om * dx; V[i - 1] = om * dy;
+        }
+        return 0;
+    }
+    double* gx = (double*)malloc(sizeof(double) * q);
+    double* gw = (double*)malloc(sizeof(double) * q);
+    orc_gauss_legendre(q, gx, gw);
+    for (int p = 0; p < P; p++)
+        for (int i = 0; i < q; i++) {
+            double t = (2.0 * ORC_PI / P) * (p + 0.5 * (1.0 + gx[i]));
+            double om = (ORC_PI / P) * gw[i];
+            double x, y, dx, dy;
+            fourier_curve(ax, bx, ay, by, K, t, &x, &y, &dx, &dy);
+            int64_t ii = (int64_t)p * q + i;
+            X[ii] = x; Y[ii] = y; W[ii] = om * dx; V[ii] = om * dy;
+        }
+    free(gx); free(gw);
+    return 0;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Dilation areal rule, eqs. aqnod / aqwei (sec. 3.1):                      */
 /*   alpha_l, wt_l = m-node GL on (0,1);                                    */

@@ -181,3 +181,35 @@ def test_nsli_empty_rule_and_babinet():
     assert uo[0] == 1
     with pytest.raises(ValueError):
         oracle.nsli([0.0], [1.0], [0.1], [0.0], 1.0, 0.0, [0.0], [0.0])
+
+
+def _kite():
+    import json, os
+    with open(os.path.join(os.path.dirname(__file__), "golden", "kite_table.json")) as f:
+        return json.load(f)
+
+
+def test_kite_rule_area_and_direct_sum_vs_edge_integral():
+    # sec. 3.1's kite, trapezoid boundary rule: Green's area pi/2 exactly (the
+    # integrand X Y' is a trigonometric polynomial), and the direct areal sum
+    # agrees with the edge integral to 13-14 digits at the converged
+    # parameters of Table t:kite, as the paper reports
+    kt = _kite()
+    k = kt["kite"]
+    for row in kt["rows"]:
+        X, Y, W, V = oracle.boundary_fourier(k["ax"], k["bx"], k["ay"], k["by"], 0, row["n"])
+        assert abs(0.5 * np.sum(X * V - Y * W) - math.pi / 2) < 1e-14
+    row = kt["rows"][0]
+    X, Y, W, V = oracle.boundary_fourier(k["ax"], k["bx"], k["ay"], k["by"], 0, row["n"])
+    x, y, w = oracle.dilation(X, Y, W, V, row["m"])
+    assert abs(w.sum() - math.pi / 2) < 1e-14
+    g = np.random.Generator(np.random.PCG64(1))
+    b = kt["targets_box"]
+    xi = np.concatenate([g.uniform(-b, b, 500), [-b]]); eta = np.concatenate([g.uniform(-b, b, 500), [-b]])
+    ua = oracle.fresnel_direct(x, y, w, 1.0, row["lambda_z"], xi, eta, occulter=True)
+    ue = oracle.nsli(X, Y, W, V, 1.0, row["lambda_z"], xi, eta, occulter=True)
+    assert np.abs(ua - ue).max() < 1e-13
+    # the Fourier-curve rule reproduces the radial-curve rule for a circle
+    X1, Y1, W1, V1 = oracle.boundary_fourier([0, 1.3], [0, 0], [0, 0], [0, 1.3], 4, 20)
+    X2, Y2, W2, V2 = oracle.boundary_radial_gl(1.3, panels=4, q=20)
+    assert max(np.abs(X1 - X2).max(), np.abs(Y1 - Y2).max(), np.abs(W1 - W2).max(), np.abs(V1 - V2).max()) < 1e-15
