@@ -49,8 +49,8 @@ def parse():
                     help="also run a plain 256 MiB device copy (counter calibration for rocprofv3 --pmc)")
     ap.add_argument("--no-grad", action="store_true", help="skip the backward/forward ratio (workload 5)")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched workload 4")
-    ap.add_argument("--parts", default="step,grad,batch,nsli",
-                    help="comma list of step, grad, batch, nsli to run (profiling one part alone; "
+    ap.add_argument("--parts", default="step,grad,batch,nsli,kite",
+                    help="comma list of step, grad, batch, nsli, kite to run (profiling one part alone; "
                          "without step the line carries no value)")
     return ap.parse_args()
 
@@ -321,6 +321,69 @@ def nsli_throughput(fh, wl, steps, warmup, cpu_seconds):
     return out
 
 
+def kite_table(fh, steps, warmup):
+    """Table t:kite's timing tasks (sec. 3.1) at the paper's converged
+    parameters: the kite with the n-node trapezoid boundary rule and m radial
+    nodes, the type-3 field at 1e6 random targets in [-3/2, 3/2]^2 (a target
+    set with that declared box), the type-1 field on the 1000^2 grid with
+    h = 0.003, FP64 contexts at NUFFT tolerances 1e-6 and 1e-12, and the edge
+    integral at the same 1e6 random targets.  As in the paper, the quadrature
+    is built before the timed calls.  The paper's CPU seconds (4-core laptop)
+    are reported beside each time as context."""
+    import numpy as np
+    import torch
+    with open(os.path.join(ROOT, "tests", "golden", "kite_table.json")) as f:
+        kt = json.load(f)
+    k = kt["kite"]
+    b = kt["targets_box"]
+    G = kt["grid"]
+    rows = []
+    for ri, r in enumerate(kt["rows"]):
+        g = np.random.Generator(np.random.PCG64(31 + ri))
+        M = r["t3"]["M"]
+        xi = torch.tensor(g.uniform(-b, b, M), device="cuda")
+        eta = torch.tensor(g.uniform(-b, b, M), device="cuda")
+        stream = torch.cuda.current_stream()
+
+        def timed(fn):
+            for _ in range(warmup):
+                fn()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record(stream)
+            for _ in range(steps):
+                fn()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            return e0.elapsed_time(e1) / steps
+
+        entry = {"lambda_z": r["lambda_z"], "fresnel": r["fresnel"], "n": r["n"], "m": r["m"],
+                 "N": r["n"] * r["m"], "M": M, "by_eps": []}
+        for ke, eps in enumerate(r["t3"]["eps"]):
+            ctx = fh.Context("fp64", tol=eps)
+            q = ctx.quad_fourier(k["ax"], k["bx"], k["ay"], k["by"], 0, r["n"], r["m"])
+            tg = ctx.targets(xi, eta, box=(-b, b, -b, b))
+            u3 = torch.empty(M, dtype=torch.complex128, device="cuda")
+            u1 = torch.empty((G["n"], G["n"]), dtype=torch.complex128, device="cuda")
+            t3 = timed(lambda: ctx.field_targets(q, 1.0, r["lambda_z"], tg, occulter=True, out=u3))
+            t1 = timed(lambda: ctx.field_grid(q, 1.0, r["lambda_z"], G["n"], G["n"], G["h"], G["h"],
+                                              occulter=True, out=u1))
+            entry["by_eps"].append({"eps": eps, "t3_ms": t3, "t1_ms": t1,
+                                    "paper_t3_s": r["t3"]["cpu_s"][ke], "paper_t1_s": r["t1"]["cpu_s"][ke]})
+            tg.close()
+            q.close()
+            ctx.close()
+        ctx = fh.Context("fp64")
+        B = ctx.boundary_fourier(k["ax"], k["bx"], k["ay"], k["by"], 0, r["n"])
+        un = torch.empty(M, dtype=torch.complex128, device="cuda")
+        entry["nsli_ms"] = timed(lambda: ctx.field_nsli(B, 1.0, r["lambda_z"], xi, eta, occulter=True, out=un))
+        entry["paper_nsli_s"] = r["nsli_cpu_s"]
+        ctx.close()
+        rows.append(entry)
+    return {"workload": "kite of sec. 3.1, Table t:kite tasks (quadrature built before timing, as in the paper)",
+            "rows": rows}
+
+
 def cpu_baseline(wl, seconds):
     """The oracle (direct FP64 sum) on a seeded sample of the step's targets."""
     import numpy as np
@@ -368,6 +431,8 @@ def main():
         if "nsli" in parts:
             out["nsli"] = nsli_throughput(fh, wl, args.steps, args.warmup,
                                           0.0 if args.no_cpu_baseline else 3.0)
+        if "kite" in parts:
+            out["kite_table"] = kite_table(fh, 5, 2)
         print(json.dumps(out))
         return
     res = {}
@@ -407,6 +472,8 @@ def main():
         out["batch"] = batch_throughput(fh, 5, 2)
     if "nsli" in parts:
         out["nsli"] = nsli_throughput(fh, wl, args.steps, args.warmup, 0.0 if args.no_cpu_baseline else 3.0)
+    if "kite" in parts:
+        out["kite_table"] = kite_table(fh, 5, 2)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
     print(json.dumps(out))

@@ -144,6 +144,17 @@ fh_status fh_quad_from_boundary(fh_ctx* ctx, const double* X, const double* Y,
 fh_status fh_quad_radial(fh_ctx* ctx, double r0, const double* a, const double* b,
                          int32_t K, int32_t panels, int32_t q, int32_t m, fh_quad** out);
 
+/* General smooth closed CCW curve X(t) = sum_{k=0}^{K} ax[k] cos kt +
+ * bx[k] sin kt, Y(t) = sum ay[k] cos kt + by[k] sin kt (host arrays of K + 1
+ * doubles, K <= 64; bx and by may be NULL for zeros; bx[0], by[0] are
+ * ignored), e.g. the kite of sec. 3.1 (ax = {0, 0.5, 0.5}, by = {0, 1, 0}).
+ * Boundary rule as for fh_quad_radial (panels = 0: the trapezoid rule of
+ * eq. ptr with q nodes), then the dilation rule about the origin with m
+ * radial nodes (sec. 3.1; the weights may be negative where the curve is
+ * not star-shaped about the origin).  N = panels q m (or q m). */
+fh_status fh_quad_fourier(fh_ctx* ctx, int32_t K, const double* ax, const double* bx, const double* ay,
+                          const double* by, int32_t panels, int32_t q, int32_t m, fh_quad** out);
+
 /* Polygon with nv >= 3 CCW vertices (host arrays), q Gauss-Legendre nodes
  * per edge, m radial nodes.  N = nv q m. */
 fh_status fh_quad_polygon(fh_ctx* ctx, const double* vx, const double* vy, int32_t nv,
@@ -275,6 +286,8 @@ fh_status fh_starshade_vjp(fh_ctx* ctx, int32_t Np, double a, double R, double b
  * X, Y, W, V (n doubles each, in `mem`; host output synchronises):
  *   fh_boundary_radial: the star-shaped curve of fh_quad_radial (same
  *     parameters without m), n = panels q (or q with panels = 0);
+ *   fh_boundary_fourier: the curve of fh_quad_fourier (same parameters
+ *     without m), n = panels q (or q with panels = 0);
  *   fh_boundary_polygon: q Gauss-Legendre nodes per edge of the CCW polygon
  *     (host vertex arrays), n = nv q;
  *   fh_boundary_starshade: the outline of fh_quad_starshade's petal shape
@@ -288,6 +301,9 @@ fh_status fh_starshade_vjp(fh_ctx* ctx, int32_t Np, double a, double R, double b
 fh_status fh_boundary_radial(fh_ctx* ctx, double r0, const double* a, const double* b, int32_t K,
                              int32_t panels, int32_t q, double* X, double* Y, double* W, double* V,
                              fh_memspace mem);
+fh_status fh_boundary_fourier(fh_ctx* ctx, int32_t K, const double* ax, const double* bx,
+                              const double* ay, const double* by, int32_t panels, int32_t q, double* X,
+                              double* Y, double* W, double* V, fh_memspace mem);
 fh_status fh_boundary_polygon(fh_ctx* ctx, const double* vx, const double* vy, int32_t nv, int32_t q,
                               double* X, double* Y, double* W, double* V, fh_memspace mem);
 fh_status fh_boundary_starshade(fh_ctx* ctx, int32_t Np, double a, double R, double b, double p,

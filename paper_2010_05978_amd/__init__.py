@@ -101,6 +101,10 @@ class Context:
     def quad_radial(self, r0, a=None, b=None, panels=1, q=20, m=10) -> Quad:
         return Quad(self, abi.fh_quad_radial(self.handle, r0, a, b, panels, q, m))
 
+    def quad_fourier(self, ax, bx, ay, by, panels=0, q=100, m=10) -> Quad:
+        """Rule for the closed curve X = sum ax_k cos kt + bx_k sin kt, Y likewise."""
+        return Quad(self, abi.fh_quad_fourier(self.handle, ax, bx, ay, by, panels, q, m))
+
     def quad_polygon(self, vx, vy, q, m) -> Quad:
         return Quad(self, abi.fh_quad_polygon(self.handle, vx, vy, q, m))
 
@@ -137,6 +141,11 @@ class Context:
     def boundary_radial(self, r0, a=None, b=None, panels=1, q=20):
         B = self._bdry(panels * q if panels > 0 else q)
         abi.fh_boundary_radial(self.handle, r0, a, b, panels, q, B)
+        return B
+
+    def boundary_fourier(self, ax, bx, ay, by, panels=0, q=100):
+        B = self._bdry(panels * q if panels > 0 else q)
+        abi.fh_boundary_fourier(self.handle, ax, bx, ay, by, panels, q, B)
         return B
 
     def boundary_polygon(self, vx, vy, q):

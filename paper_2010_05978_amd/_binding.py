@@ -38,6 +38,7 @@ EXPORTED = [
     "fh_field_grid", "fh_field_points", "fh_field_targets", "fh_field_grid_batch", "fh_field_grid_vjp",
     "fh_starshade_vjp", "fh_autotune_grid", "fh_set_timing", "fh_last_timing", "fh_timing_totals",
     "fh_boundary_radial", "fh_boundary_polygon", "fh_boundary_starshade", "fh_field_nsli",
+    "fh_quad_fourier", "fh_boundary_fourier",
 ]
 
 
@@ -101,6 +102,8 @@ def lib():
             "fh_boundary_polygon": [vp, vp, vp, i32, i32, vp, vp, vp, vp, ctypes.c_int],
             "fh_boundary_starshade": [vp, i32, d, d, d, d, i32, i32, i32, vp, vp, vp, vp, ctypes.c_int],
             "fh_field_nsli": [vp, vp, vp, vp, vp, i64, d, d, i64, vp, vp, d, i32, vp, ctypes.c_int],
+            "fh_quad_fourier": [vp, i32, vp, vp, vp, vp, i32, i32, i32, pvp],
+            "fh_boundary_fourier": [vp, i32, vp, vp, vp, vp, i32, i32, vp, vp, vp, vp, ctypes.c_int],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -296,6 +299,33 @@ def fh_boundary_radial(ctx, r0, a, b, panels, q, B):
     mem = _same_mem(X, Y, W, V)
     _check(lib().fh_boundary_radial(ctx, r0, _ptr_mem(a)[0], _ptr_mem(b)[0], K, panels, q, _ptr_mem(X)[0],
                                     _ptr_mem(Y)[0], _ptr_mem(W)[0], _ptr_mem(V)[0], mem))
+
+
+def _fourier_coefs(ax, bx, ay, by):
+    ax = np.ascontiguousarray(ax, dtype=np.float64)
+    K = len(ax) - 1
+    out = [ax]
+    for a in (bx, ay, by):
+        a = np.zeros(K + 1) if a is None else np.ascontiguousarray(a, dtype=np.float64)
+        if len(a) != K + 1:
+            raise ValueError("Fourier coefficient arrays must all have length K + 1")
+        out.append(a)
+    return K, out
+
+
+def fh_quad_fourier(ctx, ax, bx, ay, by, panels, q, m):
+    K, cs = _fourier_coefs(ax, bx, ay, by)
+    h = _new_quad()
+    _check(lib().fh_quad_fourier(ctx, K, *[_ptr_mem(a)[0] for a in cs], panels, q, m, ctypes.byref(h)))
+    return h
+
+
+def fh_boundary_fourier(ctx, ax, bx, ay, by, panels, q, B):
+    K, cs = _fourier_coefs(ax, bx, ay, by)
+    X, Y, W, V = _rows4(B)
+    mem = _same_mem(X, Y, W, V)
+    _check(lib().fh_boundary_fourier(ctx, K, *[_ptr_mem(a)[0] for a in cs], panels, q, _ptr_mem(X)[0],
+                                     _ptr_mem(Y)[0], _ptr_mem(W)[0], _ptr_mem(V)[0], mem))
 
 
 def fh_boundary_polygon(ctx, vx, vy, q, B):

@@ -54,12 +54,59 @@ __device__ __forceinline__ void radial_node(const RadialParams& rp, const double
     V = om * (dr * st + r * ct);
 }
 
+// General closed curve X(t) = sum_{k=0}^{K} ax_k cos kt + bx_k sin kt, Y(t)
+// likewise (the kite of sec. 3.1 is X = 0.5 cos t + 0.5 cos 2t, Y = sin t),
+// with the same panel or trapezoid rule in t as the star-shaped curve.
+struct FourierParams {
+    int K;
+    int panels;  // 0: periodic trapezoid rule with q nodes
+    int q;
+    double ax[kMaxFourier + 1];
+    double bx[kMaxFourier + 1];
+    double ay[kMaxFourier + 1];
+    double by[kMaxFourier + 1];
+};
+
+__device__ __forceinline__ void bdry_node(const RadialParams& rp, const double* __restrict__ gl, int64_t n,
+                                          int64_t i, double& X, double& Y, double& W, double& V)
+{
+    radial_node(rp, gl, n, i, X, Y, W, V);
+}
+
+__device__ __forceinline__ void bdry_node(const FourierParams& fp, const double* __restrict__ gl, int64_t n,
+                                          int64_t i, double& X, double& Y, double& W, double& V)
+{
+    double t, om;
+    if (fp.panels > 0) {
+        const int p = (int)(i / fp.q), k = (int)(i % fp.q);
+        t = (2.0 * kPi / fp.panels) * (p + 0.5 * (1.0 + gl[k]));
+        om = (kPi / fp.panels) * gl[fp.q + k];
+    } else {
+        t = 2.0 * kPi * (double)(i + 1) / (double)n;
+        om = 2.0 * kPi / (double)n;
+    }
+    double x = 0.0, y = 0.0, dx = 0.0, dy = 0.0;
+    for (int k = 0; k <= fp.K; ++k) {
+        double s, c;
+        sincos(k * t, &s, &c);
+        x += fp.ax[k] * c + fp.bx[k] * s;
+        y += fp.ay[k] * c + fp.by[k] * s;
+        dx += k * (fp.bx[k] * c - fp.ax[k] * s);
+        dy += k * (fp.by[k] * c - fp.ay[k] * s);
+    }
+    X = x;
+    Y = y;
+    W = om * dx;
+    V = om * dy;
+}
+
 // Boundary rule and dilation in one pass: a block of 256 areal nodes
 // j = l + i m first evaluates the boundary nodes i it touches (one thread
 // each, through LDS), then every thread dilates its own node.
-__global__ void __launch_bounds__(256) k_radial_rule(RadialParams rp, const double* __restrict__ glq, int64_t n,
-                                                     int m, const double* __restrict__ glm, double* __restrict__ x,
-                                                     double* __restrict__ y, double* __restrict__ w)
+template <class P>
+__device__ __forceinline__ void curve_rule(const P& rp, const double* __restrict__ glq, int64_t n, int m,
+                                           const double* __restrict__ glm, double* __restrict__ x,
+                                           double* __restrict__ y, double* __restrict__ w)
 {
     __shared__ double sb[4][256];
     const int64_t j0 = blockIdx.x * (int64_t)blockDim.x;
@@ -68,7 +115,7 @@ __global__ void __launch_bounds__(256) k_radial_rule(RadialParams rp, const doub
     const int nb = (int)(jl / m - i0) + 1;  // at most 256 boundary nodes
     if ((int)threadIdx.x < nb) {
         double X, Y, W, V;
-        radial_node(rp, glq, n, i0 + threadIdx.x, X, Y, W, V);
+        bdry_node(rp, glq, n, i0 + threadIdx.x, X, Y, W, V);
         sb[0][threadIdx.x] = X;
         sb[1][threadIdx.x] = Y;
         sb[2][threadIdx.x] = W;
@@ -86,6 +133,20 @@ __global__ void __launch_bounds__(256) k_radial_rule(RadialParams rp, const doub
     x[j] = al * Xi;
     y[j] = al * Yi;
     w[j] = al * wl * (Xi * sb[3][bi] - Yi * sb[2][bi]);
+}
+
+__global__ void __launch_bounds__(256) k_radial_rule(RadialParams rp, const double* __restrict__ glq, int64_t n,
+                                                     int m, const double* __restrict__ glm, double* __restrict__ x,
+                                                     double* __restrict__ y, double* __restrict__ w)
+{
+    curve_rule(rp, glq, n, m, glm, x, y, w);
+}
+
+__global__ void __launch_bounds__(256) k_fourier_rule(FourierParams fp, const double* __restrict__ glq, int64_t n,
+                                                      int m, const double* __restrict__ glm, double* __restrict__ x,
+                                                      double* __restrict__ y, double* __restrict__ w)
+{
+    curve_rule(fp, glq, n, m, glm, x, y, w);
 }
 
 // Gauss-Legendre nodes along each straight edge of a CCW polygon.
@@ -228,6 +289,19 @@ __global__ void k_bdry_radial(RadialParams rp, const double* __restrict__ glq, i
     Vv[i] = v;
 }
 
+__global__ void k_bdry_fourier(FourierParams fp, const double* __restrict__ glq, int64_t n, double* __restrict__ X,
+                               double* __restrict__ Y, double* __restrict__ Wv, double* __restrict__ Vv)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double x, y, w, v;
+    bdry_node(fp, glq, n, i, x, y, w, v);
+    X[i] = x;
+    Y[i] = y;
+    Wv[i] = w;
+    Vv[i] = v;
+}
+
 // Starshade outline (sec. 3.2's petal shape): per petal k, with half-width
 // angle h(r) = pi A(r)/Np about theta_k = 2 pi k/Np, the lower edge
 // theta_k - h(r) for r from a to R (m GL radii), the tip arc at r = R
@@ -319,6 +393,40 @@ fh_status radial_into(fh_ctx* c, const RadialParams& rp, int64_t n, int m, doubl
     hipLaunchKernelGGL(k_radial_rule, dim3(nblocks(n * m, 256)), dim3(256), 0, c->stream, rp, glq, n, m, glm, x, y,
                        w);
     FH_HIP(hipGetLastError());
+    return FH_OK;
+}
+
+// Fourier-curve parameters from host coefficient arrays (K + 1 each; bx[0],
+// by[0] multiply sin 0 and are ignored); also returns a box holding the curve
+// and the origin (the dilation nodes lie on segments from the origin).
+fh_status fourier_params(const double* ax, const double* bx, const double* ay, const double* by, int K, int panels,
+                         int q, FourierParams* fp, double* box)
+{
+    FH_ARG(ax && ay, FH_ERR_INVALID_ARG, "NULL coefficient array");
+    FH_ARG(K >= 0 && K <= kMaxFourier, FH_ERR_INVALID_ARG, "K must be in [0, %d]", kMaxFourier);
+    FH_ARG(panels >= 0 && q >= 1, FH_ERR_INVALID_ARG, "need panels >= 0, q >= 1");
+    *fp = FourierParams{};
+    fp->K = K;
+    fp->panels = panels;
+    fp->q = q;
+    double ex = 0.0, ey = 0.0;
+    for (int k = 0; k <= K; ++k) {
+        fp->ax[k] = ax[k];
+        fp->bx[k] = (bx && k > 0) ? bx[k] : 0.0;
+        fp->ay[k] = ay[k];
+        fp->by[k] = (by && k > 0) ? by[k] : 0.0;
+        FH_ARG(std::isfinite(fp->ax[k]) && std::isfinite(fp->bx[k]) && std::isfinite(fp->ay[k]) &&
+                   std::isfinite(fp->by[k]),
+               FH_ERR_NONFINITE, "Fourier coefficient %d not finite", k);
+        if (k > 0) {
+            ex += std::fabs(fp->ax[k]) + std::fabs(fp->bx[k]);
+            ey += std::fabs(fp->ay[k]) + std::fabs(fp->by[k]);
+        }
+    }
+    box[0] = std::min(0.0, fp->ax[0] - ex);
+    box[1] = std::max(0.0, fp->ax[0] + ex);
+    box[2] = std::min(0.0, fp->ay[0] - ey);
+    box[3] = std::max(0.0, fp->ay[0] + ey);
     return FH_OK;
 }
 
@@ -641,6 +749,66 @@ fh_status fh_quad_from_nodes(fh_ctx* c, const double* x, const double* y, const 
         }
         *out = qd;
         return FH_OK;
+    } catch (...) {
+        set_error("host allocation failed");
+        return FH_ERR_ALLOC;
+    }
+}
+
+fh_status fh_quad_fourier(fh_ctx* c, int32_t K, const double* ax, const double* bx, const double* ay,
+                          const double* by, int32_t panels, int32_t q, int32_t m, fh_quad** out)
+{
+    try {
+        FH_ARG(c && out, FH_ERR_INVALID_ARG, "NULL argument");
+        *out = nullptr;
+        FH_ARG(m >= 1, FH_ERR_INVALID_ARG, "need m >= 1");
+        FourierParams fp;
+        double box[4];
+        FH_TRY(fourier_params(ax, bx, ay, by, K, panels, q, &fp, box));
+        const int64_t n = panels > 0 ? (int64_t)panels * q : q;
+        FH_HIP(hipSetDevice(c->device));
+        const double* glq = nullptr;
+        const double* glm = nullptr;
+        if (panels > 0) FH_TRY(gl_table(c, q, &glq));
+        FH_TRY(gl_table(c, m, &glm));
+        fh_quad* qd = nullptr;
+        FH_TRY(quad_alloc(c, n * m, &qd));
+        hipLaunchKernelGGL(k_fourier_rule, dim3(nblocks(n * m, 256)), dim3(256), 0, c->stream, fp, glq, n, m, glm,
+                           qd->x, qd->y, qd->w);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) {
+            fh_quad_destroy(qd);
+            set_error("k_fourier_rule launch failed: %s", hipGetErrorString(e));
+            return FH_ERR_HIP;
+        }
+        set_bbox(qd, box[0], box[1], box[2], box[3]);
+        *out = qd;
+        return FH_OK;
+    } catch (...) {
+        set_error("host allocation failed");
+        return FH_ERR_ALLOC;
+    }
+}
+
+fh_status fh_boundary_fourier(fh_ctx* c, int32_t K, const double* ax, const double* bx, const double* ay,
+                              const double* by, int32_t panels, int32_t q, double* X, double* Y, double* W, double* V,
+                              fh_memspace mem)
+{
+    try {
+        FH_ARG(c && X && Y && W && V, FH_ERR_INVALID_ARG, "NULL argument");
+        FH_ARG(mem == FH_MEM_HOST || mem == FH_MEM_DEVICE, FH_ERR_INVALID_ARG, "bad memspace");
+        FourierParams fp;
+        double box[4];
+        FH_TRY(fourier_params(ax, bx, ay, by, K, panels, q, &fp, box));
+        const int64_t n = panels > 0 ? (int64_t)panels * q : q;
+        FH_HIP(hipSetDevice(c->device));
+        const double* glq = nullptr;
+        if (panels > 0) FH_TRY(gl_table(c, q, &glq));
+        BdryOut o;
+        FH_TRY(bdry_begin(c, n, X, Y, W, V, mem, 0, &o));
+        hipLaunchKernelGGL(k_bdry_fourier, dim3(nblocks(n, 256)), dim3(256), 0, c->stream, fp, glq, n, o.d[0], o.d[1],
+                           o.d[2], o.d[3]);
+        return bdry_end(c, n, X, Y, W, V, mem, o);
     } catch (...) {
         set_error("host allocation failed");
         return FH_ERR_ALLOC;
