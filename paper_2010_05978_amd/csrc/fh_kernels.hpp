@@ -1323,7 +1323,10 @@ constexpr int interp_group() { return W <= 8 ? 8 : (W <= 16 ? 16 : 32); }
 // its own: stencil cell, the 2W kernel values (staged in LDS), and the
 // 1/Phi correction, chirp and 1/(i lambda z) factor.  The wavefront then
 // gathers in trips of 64/GS targets: GS lanes per target, lane r taking
-// stencil row r with all W loads in flight, summed over the group by a fixed
+// stencil column r down all W rows (so each load instruction reads, per
+// target, one contiguous run of the row: a few cache lines rather than one
+// line per lane), all W loads in flight; the column is weighted down its
+// rows, then by its own kernel value, and summed over the group by a fixed
 // butterfly.  Lane l finally scales its target's sum and writes it.
 template <class R, int W>
 __global__ void __launch_bounds__(64) k_t3_interp(const R* __restrict__ G, const double* __restrict__ xi,
@@ -1378,27 +1381,27 @@ __global__ void __launch_bounds__(64) k_t3_interp(const R* __restrict__ G, const
         C bufA[W], bufB[W];
         auto gather = [&](int q, C* gv) {
             const uint32_t cp = cs[min(q, nq - 1)];
-            const int c1 = (int)(cp & 0xffffu);
-            int row = (int)(cp >> 16) + rr;
-            row = row >= tp.m2 ? row - tp.m2 : row;
-            const C* gr = Gv + (size_t)row * tp.m1;
+            int col = (int)(cp & 0xffffu) + rr;
+            col = col >= tp.m1 ? col - tp.m1 : col;
+            const int row0 = (int)(cp >> 16);
+            const C* gc = Gv + col;
 #pragma unroll
-            for (int a = 0; a < W; ++a) {
-                const int col = c1 + a;
-                gv[a] = gr[col >= tp.m1 ? col - tp.m1 : col];
+            for (int b = 0; b < W; ++b) {
+                const int row = row0 + b;
+                gv[b] = gc[(size_t)(row >= tp.m2 ? row - tp.m2 : row) * tp.m1];
             }
         };
         auto trip_sum = [&](int q, const C* gv) {
             const R* kq = ks + min(q, nq - 1) * KS;
             R sr = R(0), si = R(0);
 #pragma unroll
-            for (int a = 0; a < W; ++a) {
-                sr += gv[a].x * kq[a];
-                si += gv[a].y * kq[a];
+            for (int b = 0; b < W; ++b) {
+                sr += gv[b].x * kq[W + b];
+                si += gv[b].y * kq[W + b];
             }
-            const R ky = (q < nq && r < W) ? kq[W + rr] : R(0);
-            sr = group_sum<GS>(sr * ky);
-            si = group_sum<GS>(si * ky);
+            const R kx = (q < nq && r < W) ? kq[rr] : R(0);
+            sr = group_sum<GS>(sr * kx);
+            si = group_sum<GS>(si * kx);
             if (r == 0 && q < nq) res[q] = C{sr, si};
         };
         gather(g, bufA);

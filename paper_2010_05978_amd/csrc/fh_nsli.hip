@@ -21,8 +21,8 @@
 // The work is O(n M) FP64 arithmetic with a few bytes per target: every
 // thread owns targets and walks all boundary nodes (read as wavefront-uniform
 // scalar loads), so the kernel is bound by FP64 VALU throughput.  When the
-// targets alone give too few workgroups, the nodes are split into groups
-// whose partial sums a second kernel adds in a fixed order.
+// targets alone give fewer than two workgroups per CU, the nodes are split
+// into groups whose partial sums a second kernel adds in a fixed order.
 #include <algorithm>
 
 #include "fh_common.hpp"
@@ -271,12 +271,13 @@ fh_status fh_field_nsli(fh_ctx* c, const double* X, const double* Y, const doubl
         const bool mixed = c->prec == FH_MIXED;
         const size_t usz = (mixed ? sizeof(float) : sizeof(double)) * 2 * (size_t)M;
 
-        // node groups: enough workgroups to fill the chip, at least 64 nodes each
+        // node groups: split the nodes only when the targets alone give fewer
+        // than two workgroups per CU (then aim at four), at least 64 nodes each;
+        // otherwise the partial sums would cost a second pass for nothing
         const int64_t bx = (M + kNsliBlock * kNsliTpt - 1) / (kNsliBlock * kNsliTpt);
-        const int64_t want = 8LL * c->cu_count;
         int groups = 1;
-        if (bx < want && n > 128)
-            groups = (int)std::min<int64_t>({(want + bx - 1) / bx, n / 64, 1024});
+        if (bx < 2LL * c->cu_count && n > 128)
+            groups = (int)std::min<int64_t>({(4LL * c->cu_count + bx - 1) / bx, n / 64, 1024});
         groups = std::max(groups, 1);
         // nodes per group (at least 1, also for an empty rule), then the
         // number of non-empty groups
