@@ -65,6 +65,11 @@ def _load():
                                                _dp, _dp, _dp, _dp]
         lib.orc_starshade_vjp.argtypes = [i32, d, d, d, d, i32, i32, i32, i32, _dp, i32,
                                           _dp, _dp, _dp, _dp]
+        ip = ctypes.POINTER(ctypes.c_int)
+        lib.orc_koch_size.argtypes = [i32, ip]
+        lib.orc_koch_size.restype = i64
+        lib.orc_koch.argtypes = [i32, ip, _dp, _dp, _dp]
+        lib.orc_koch_outline.argtypes = [i32, _dp, _dp]
         lib.orc_bdry_fourier.argtypes = [_dp, _dp, _dp, _dp, i32, i32, i32, _dp, _dp, _dp, _dp]
         lib.orc_bdry_starshade.argtypes = [i32, d, d, d, d, i32, i32, i32, _dp, _dp, _dp, _dp]
         lib.orc_nsli.argtypes = [_dp, _dp, _dp, _dp, i64, d, d, _dp, _dp, i64, d, i32, _dp]
@@ -72,7 +77,8 @@ def _load():
         for name in ("orc_gauss_legendre", "orc_bdry_radial_gl", "orc_bdry_radial_ptr",
                      "orc_bdry_polygon", "orc_dilation", "orc_starshade",
                      "orc_fresnel_direct", "orc_fresnel_direct_vjp", "orc_starshade_vjp",
-                     "orc_bdry_starshade", "orc_nsli", "orc_bdry_fourier"):
+                     "orc_bdry_starshade", "orc_nsli", "orc_bdry_fourier", "orc_koch",
+                     "orc_koch_outline"):
             getattr(lib, name).restype = i32
         _lib = lib
     return _lib
@@ -173,6 +179,36 @@ def boundary_starshade(Np, a, R, b, p, m, ntip=4, ngap=0):
                                        _p(out[0]), _p(out[1]), _p(out[2]), _p(out[3])),
            "boundary_starshade")
     return out[0], out[1], out[2], out[3]
+
+
+def _ints(p):
+    a = np.ascontiguousarray(np.asarray(p, dtype=np.intc))
+    return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+
+
+def koch_size(L, p):
+    a, pa = _ints(p)
+    if len(a) != L + 1:
+        raise ValueError("p needs L + 1 entries")
+    return int(_load().orc_koch_size(L, pa))
+
+
+def quad_koch(L, p):
+    """Koch snowflake rule of sec. 4.4: level-L construction, the p[k] x p[k]
+    dilation rule from a vertex on every level-k triangle; returns x, y, w."""
+    a, pa = _ints(p)
+    N = koch_size(L, a)
+    out = np.empty((3, N))
+    _check(_load().orc_koch(L, pa, _p(out[0]), _p(out[1]), _p(out[2])), "koch")
+    return out[0], out[1], out[2]
+
+
+def koch_outline(L):
+    """CCW vertices of the level-L snowflake's outline (3 4^L of them)."""
+    n = 3 * 4 ** L
+    vx, vy = np.empty(n), np.empty(n)
+    _check(_load().orc_koch_outline(L, _p(vx), _p(vy)), "koch_outline")
+    return vx, vy
 
 
 def dilation(X, Y, W, V, m):

@@ -17,6 +17,8 @@
  *   - the direct areal-quadrature sum (eq. faq), un-factorised, phase carried
  *     in turns and reduced before cos/sin, pairwise summation over nodes,
  *   - the Babinet complement u_oc = 1 - u_ap (eq. bab),
+ *   - the Koch snowflake rule of sec. 4.4 (a p x p dilation rule per
+ *     triangle of the level-L construction),
  *   - the non-singular line integral over a boundary rule (appendix, eq.
  *     nsli), with the deep-shadow option of eq. li, and the starshade
  *     outline rule it is fed with,
@@ -448,6 +450,124 @@ int orc_starshade_vjp(int Np, double a, double R, double b, double p,
             gcoef[2 * k * K + K + (s - 1)] = accm;
         }
     free(rx); free(rw); free(tx); free(tw); free(x);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Koch snowflake (sec. 4.4): Omega_0 is the equilateral triangle inscribed */
+/* in the unit circle, vertices at angles 90, 210, 330 degrees (CCW, side   */
+/* sqrt 3, maximum radius 1); Omega_k adds, on the middle third of every    */
+/* edge of Omega_{k-1}, the outward equilateral triangle.  Every triangle   */
+/* (A, B, C), CCW, gets the p x p rule of the paper: translate A to the     */
+/* origin and apply the dilation rule (eqs. aqnod/aqwei) to the p-node GL   */
+/* vector line rule on the edge B -> C.  Node order: Omega_0's triangle,    */
+/* then level 1's triangles in the order of Omega_0's edges, and so on;     */
+/* within a triangle edge index outer, radial index inner.  p[k] is the     */
+/* rule order at level k (k = 0..L).                                        */
+/* The boundary vertices of Omega_k are kept as a CCW list and each edge    */
+/* P -> Q is replaced by P, P + d, P + d + R(-60) d, P + 2d (d = (Q-P)/3);  */
+/* for a CCW outline the outward side is to the right, hence R(-60).        */
+/* ------------------------------------------------------------------------ */
+static void koch_vertices0(double* vx, double* vy)
+{
+    for (int m = 0; m < 3; m++) {
+        double a = 0.5 * ORC_PI + 2.0 * ORC_PI * m / 3.0;
+        vx[m] = cos(a);
+        vy[m] = sin(a);
+    }
+}
+
+int64_t orc_koch_size(int L, const int* p)
+{
+    if (L < 0) return -1;
+    int64_t N = 0, ntri = 1;
+    for (int k = 0; k <= L; k++) {
+        if (p[k] < 1) return -1;
+        N += ntri * (int64_t)p[k] * p[k];
+        ntri = (k == 0) ? 3 : ntri * 4;
+    }
+    return N;
+}
+
+static int64_t koch_triangle(double ax, double ay, double bx, double by, double cx, double cy, int p,
+                             const double* gx, const double* gw, double* x, double* y, double* w, int64_t j)
+{
+    double ex = cx - bx, ey = cy - by;
+    for (int i = 0; i < p; i++) {
+        double t = 0.5 * (1.0 + gx[i]);
+        double X = bx + t * ex - ax, Y = by + t * ey - ay;
+        double W = 0.5 * gw[i] * ex, V = 0.5 * gw[i] * ey;
+        double cross = X * V - Y * W;
+        for (int l = 0; l < p; l++) {
+            double al = 0.5 * (1.0 + gx[l]);
+            double wl = 0.5 * gw[l];
+            x[j] = ax + al * X;
+            y[j] = ay + al * Y;
+            w[j] = al * wl * cross;
+            j++;
+        }
+    }
+    return j;
+}
+
+/* Vertices of Omega_L's outline (3 4^L of them, CCW) into vx, vy. */
+int orc_koch_outline(int L, double* vx, double* vy)
+{
+    if (L < 0) return 1;
+    int64_t nv = 3;
+    koch_vertices0(vx, vy);
+    const double c60 = 0.5, s60 = 0.86602540378443864676;
+    double* tx = (double*)malloc(sizeof(double) * 3 * ((int64_t)1 << (2 * L)));
+    double* ty = (double*)malloc(sizeof(double) * 3 * ((int64_t)1 << (2 * L)));
+    for (int k = 1; k <= L; k++) {
+        int64_t o = 0;
+        for (int64_t e = 0; e < nv; e++) {
+            double px = vx[e], py = vy[e];
+            double qx = vx[(e + 1) % nv], qy = vy[(e + 1) % nv];
+            double dx = (qx - px) / 3.0, dy = (qy - py) / 3.0;
+            tx[o] = px; ty[o] = py; o++;
+            tx[o] = px + dx; ty[o] = py + dy; o++;
+            tx[o] = px + dx + (c60 * dx + s60 * dy); ty[o] = py + dy + (-s60 * dx + c60 * dy); o++;
+            tx[o] = px + 2.0 * dx; ty[o] = py + 2.0 * dy; o++;
+        }
+        memcpy(vx, tx, sizeof(double) * o);
+        memcpy(vy, ty, sizeof(double) * o);
+        nv = o;
+    }
+    free(tx); free(ty);
+    return 0;
+}
+
+int orc_koch(int L, const int* p, double* x, double* y, double* w)
+{
+    if (orc_koch_size(L, p) < 0) return 1;
+    int pmax = 1;
+    for (int k = 0; k <= L; k++) if (p[k] > pmax) pmax = p[k];
+    double* gx = (double*)malloc(sizeof(double) * pmax);
+    double* gw = (double*)malloc(sizeof(double) * pmax);
+    int64_t cap = 3 * ((int64_t)1 << (2 * (L > 0 ? L - 1 : 0)));
+    double* vx = (double*)malloc(sizeof(double) * cap);
+    double* vy = (double*)malloc(sizeof(double) * cap);
+    const double c60 = 0.5, s60 = 0.86602540378443864676;
+    koch_vertices0(vx, vy);
+    orc_gauss_legendre(p[0], gx, gw);
+    int64_t j = koch_triangle(vx[0], vy[0], vx[1], vy[1], vx[2], vy[2], p[0], gx, gw, x, y, w, 0);
+    for (int k = 1; k <= L; k++) {
+        /* the outline of Omega_{k-1}: its edges carry level k's triangles */
+        orc_koch_outline(k - 1, vx, vy);
+        int64_t nv = 3 * ((int64_t)1 << (2 * (k - 1)));
+        orc_gauss_legendre(p[k], gx, gw);
+        for (int64_t e = 0; e < nv; e++) {
+            double px = vx[e], py = vy[e];
+            double qx = vx[(e + 1) % nv], qy = vy[(e + 1) % nv];
+            double dx = (qx - px) / 3.0, dy = (qy - py) / 3.0;
+            double ax = px + dx, ay = py + dy;
+            double bx = ax + (c60 * dx + s60 * dy), by = ay + (-s60 * dx + c60 * dy);
+            double cx = px + 2.0 * dx, cy = py + 2.0 * dy;
+            j = koch_triangle(ax, ay, bx, by, cx, cy, p[k], gx, gw, x, y, w, j);
+        }
+    }
+    free(gx); free(gw); free(vx); free(vy);
     return 0;
 }
 
