@@ -49,8 +49,8 @@ def parse():
                     help="also run a plain 256 MiB device copy (counter calibration for rocprofv3 --pmc)")
     ap.add_argument("--no-grad", action="store_true", help="skip the backward/forward ratio (workload 5)")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched workload 4")
-    ap.add_argument("--parts", default="step,grad,batch,nsli,kite",
-                    help="comma list of step, grad, batch, nsli, kite to run (profiling one part alone; "
+    ap.add_argument("--parts", default="step,grad,batch,nsli,kite,koch",
+                    help="comma list of step, grad, batch, nsli, kite, koch to run (profiling one part alone; "
                          "without step the line carries no value)")
     return ap.parse_args()
 
@@ -384,6 +384,50 @@ def kite_table(fh, steps, warmup):
             "rows": rows}
 
 
+def koch_orders(L):
+    """Rule orders per level of the paper-scale snowflake: 217 on the first
+    triangle, halving per level with a floor of 2, and 1 from level 10 on
+    (sec. 4.4 gives the two ends of the range)."""
+    import math
+    return [max(2, math.ceil(217 / 2 ** k)) if k <= 9 else 1 for k in range(L + 1)]
+
+
+def koch_snowflake(fh, steps, warmup):
+    """Sec. 4.4's fractal aperture: the level-13 Koch snowflake (about 68
+    million areal nodes, built on the device each call) and its type-1 field
+    at lambda z = 0.01 on a 1000^2 grid of spacing 0.003, FP64 at NUFFT
+    tolerance 1e-6 as in the paper.  Build and field are timed separately
+    with HIP events; the paper's laptop took about 4 minutes to build the
+    rule and 4.6 s per field."""
+    import torch
+    L, lz, n, h = 13, 0.01, 1000, 0.003
+    p = koch_orders(L)
+    ctx = fh.Context("fp64", tol=1e-6)
+    u = torch.empty((n, n), dtype=torch.complex128, device="cuda")
+    stream = torch.cuda.current_stream()
+    build_ms, field_ms = [], []
+    N = 0
+    for it in range(warmup + steps):
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        e[0].record(stream)
+        q = ctx.quad_koch(L, p)
+        e[1].record(stream)
+        ctx.field_grid(q, 1.0, lz, n, n, h, h, out=u)
+        e[2].record(stream)
+        torch.cuda.synchronize()
+        N = q.N
+        q.close()
+        if it >= warmup:
+            build_ms.append(e[0].elapsed_time(e[1]))
+            field_ms.append(e[1].elapsed_time(e[2]))
+    ctx.close()
+    b, f = sum(build_ms) / steps, sum(field_ms) / steps
+    return {"workload": "Koch snowflake level 13 (sec. 4.4), lambda z = 0.01, 1000^2 grid, h = 0.003, "
+                        "FP64 at tolerance 1e-6", "levels": L, "orders": p, "nodes": N,
+            "build_ms": b, "field_ms": f, "nodes_per_s_field": N / (f * 1e-3),
+            "paper_build_s": 240, "paper_field_s": 4.6}
+
+
 def cpu_baseline(wl, seconds):
     """The oracle (direct FP64 sum) on a seeded sample of the step's targets."""
     import numpy as np
@@ -433,6 +477,8 @@ def main():
                                           0.0 if args.no_cpu_baseline else 3.0)
         if "kite" in parts:
             out["kite_table"] = kite_table(fh, 5, 2)
+        if "koch" in parts:
+            out["koch"] = koch_snowflake(fh, 3, 1)
         print(json.dumps(out))
         return
     res = {}
@@ -474,6 +520,8 @@ def main():
         out["nsli"] = nsli_throughput(fh, wl, args.steps, args.warmup, 0.0 if args.no_cpu_baseline else 3.0)
     if "kite" in parts:
         out["kite_table"] = kite_table(fh, 5, 2)
+    if "koch" in parts:
+        out["koch"] = koch_snowflake(fh, 3, 1)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
     print(json.dumps(out))

@@ -155,6 +155,19 @@ fh_status fh_quad_radial(fh_ctx* ctx, double r0, const double* a, const double* 
 fh_status fh_quad_fourier(fh_ctx* ctx, int32_t K, const double* ax, const double* bx, const double* ay,
                           const double* by, int32_t panels, int32_t q, int32_t m, fh_quad** out);
 
+/* Koch snowflake of sec. 4.4, level L <= 15: the equilateral triangle of
+ * side sqrt 3 inscribed in the unit circle (vertices at 90, 210 and 330
+ * degrees) plus, at each level k = 1..L, the outward triangles on the middle
+ * thirds of the previous outline's edges (1 + 3 (4^L - 1)/3 triangles).
+ * Every level-k triangle gets the p[k] x p[k] rule of the paper: one vertex
+ * moved to the origin and the dilation rule applied to the p[k]-node
+ * Gauss-Legendre line rule on the opposite edge.  p: host array of L + 1
+ * orders in [1, 1024].  N = sum_k ntri_k p[k]^2 (level 13 with p = 1 from
+ * level 10 on is the paper's ~69 million nodes).  Node order: level by
+ * level, triangles in the order of the previous outline's edges starting
+ * from the 90-degree vertex, edge index outer, radial index inner. */
+fh_status fh_quad_koch(fh_ctx* ctx, int32_t L, const int32_t* p, fh_quad** out);
+
 /* Polygon with nv >= 3 CCW vertices (host arrays), q Gauss-Legendre nodes
  * per edge, m radial nodes.  N = nv q m. */
 fh_status fh_quad_polygon(fh_ctx* ctx, const double* vx, const double* vy, int32_t nv,

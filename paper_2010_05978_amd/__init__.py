@@ -105,6 +105,10 @@ class Context:
         """Rule for the closed curve X = sum ax_k cos kt + bx_k sin kt, Y likewise."""
         return Quad(self, abi.fh_quad_fourier(self.handle, ax, bx, ay, by, panels, q, m))
 
+    def quad_koch(self, L, p) -> Quad:
+        """Koch snowflake rule (level L, p[k] x p[k] nodes per level-k triangle)."""
+        return Quad(self, abi.fh_quad_koch(self.handle, L, p))
+
     def quad_polygon(self, vx, vy, q, m) -> Quad:
         return Quad(self, abi.fh_quad_polygon(self.handle, vx, vy, q, m))
 

@@ -149,6 +149,98 @@ __global__ void __launch_bounds__(256) k_fourier_rule(FourierParams fp, const do
     curve_rule(fp, glq, n, m, glm, x, y, w);
 }
 
+// Koch snowflake (sec. 4.4): Omega_0 is the equilateral triangle inscribed in
+// the unit circle (vertices at 90, 210, 330 degrees, CCW); level k >= 1 adds
+// the outward equilateral triangle on the middle third of every edge of
+// Omega_{k-1}.  Each triangle (A, B, C) gets the p_k x p_k rule obtained by
+// translating A to the origin and dilating the p_k-node GL line rule on the
+// edge B -> C (eqs. aqnod/aqwei).  One thread per node: the level from the
+// node offsets, the triangle from its edge index, whose base-4 digits (most
+// significant first) walk the construction down from one of the three
+// sides: digit 0 keeps the first third, 1 turns -60 degrees after it, 2 turns
+// +60 degrees after the bump's apex, 3 takes the last third.
+constexpr int kKochMaxLevel = 15;
+struct KochParams {
+    int L;
+    int p[kKochMaxLevel + 1];
+    int64_t off[kKochMaxLevel + 2];        // first node of each level, off[L + 1] = N
+    const double* gl[kKochMaxLevel + 1];   // GL rule of order p[k]: x then w
+};
+
+__device__ __forceinline__ void rot60(double x, double y, double sg, double& rx, double& ry)
+{
+    constexpr double c = 0.5, s = 0.86602540378443864676;  // cos, sin of 60 degrees
+    rx = c * x - sg * s * y;
+    ry = sg * s * x + c * y;
+}
+
+__global__ void __launch_bounds__(256) k_koch_rule(KochParams kp, double* __restrict__ x, double* __restrict__ y,
+                                                   double* __restrict__ w)
+{
+    const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (j >= kp.off[kp.L + 1]) return;
+    int k = 0;
+    while (j >= kp.off[k + 1]) ++k;
+    const int pk = kp.p[k];
+    const int64_t local = j - kp.off[k];
+    const int64_t pp = (int64_t)pk * pk;
+    const int64_t tri = local / pp;
+    const int r = (int)(local - tri * pp);
+    const int i = r / pk, l = r - i * pk;
+    double V[3][2];
+    for (int m = 0; m < 3; ++m) sincos(0.5 * kPi + 2.0 * kPi * m / 3.0, &V[m][1], &V[m][0]);
+    double ax, ay, bx, by, cx, cy;
+    if (k == 0) {
+        ax = V[0][0]; ay = V[0][1];
+        bx = V[1][0]; by = V[1][1];
+        cx = V[2][0]; cy = V[2][1];
+    } else {
+        // edge `tri` of Omega_{k-1}: side b, then k - 1 base-4 digits
+        int64_t nb = (int64_t)1 << (2 * (k - 1));
+        const int b = (int)(tri / nb);
+        int64_t rem = tri - (int64_t)b * nb;
+        double px = V[b][0], py = V[b][1];
+        double dx = V[(b + 1) % 3][0] - px, dy = V[(b + 1) % 3][1] - py;
+        for (int t = k - 2; t >= 0; --t) {
+            nb >>= 2;
+            const int d = (int)(rem / nb);
+            rem -= (int64_t)d * nb;
+            dx /= 3.0;
+            dy /= 3.0;
+            double rx, ry;
+            if (d == 1) {
+                px += dx; py += dy;
+                rot60(dx, dy, -1.0, rx, ry);
+                dx = rx; dy = ry;
+            } else if (d == 2) {
+                rot60(dx, dy, -1.0, rx, ry);
+                px += dx + rx; py += dy + ry;
+                rot60(dx, dy, 1.0, rx, ry);
+                dx = rx; dy = ry;
+            } else if (d == 3) {
+                px += 2.0 * dx; py += 2.0 * dy;
+            }
+        }
+        // the outward triangle on the middle third of the edge (P, P + D)
+        dx /= 3.0;
+        dy /= 3.0;
+        double rx, ry;
+        rot60(dx, dy, -1.0, rx, ry);
+        ax = px + dx; ay = py + dy;
+        bx = ax + rx; by = ay + ry;
+        cx = px + 2.0 * dx; cy = py + 2.0 * dy;
+    }
+    const double* g = kp.gl[k];
+    const double ex = cx - bx, ey = cy - by;
+    const double t = 0.5 * (1.0 + g[i]);
+    const double X = bx + t * ex - ax, Y = by + t * ey - ay;
+    const double cross = X * (0.5 * g[pk + i] * ey) - Y * (0.5 * g[pk + i] * ex);
+    const double al = 0.5 * (1.0 + g[l]);
+    x[j] = ax + al * X;
+    y[j] = ay + al * Y;
+    w[j] = al * (0.5 * g[pk + l]) * cross;
+}
+
 // Gauss-Legendre nodes along each straight edge of a CCW polygon.
 __global__ void k_bdry_polygon(const double* __restrict__ vx, const double* __restrict__ vy, int nv,
                                int q, const double* __restrict__ gl, double* __restrict__ X,
@@ -747,6 +839,44 @@ fh_status fh_quad_from_nodes(fh_ctx* c, const double* x, const double* y, const 
         } else {
             set_bbox(qd, 0.0, 0.0, 0.0, 0.0);
         }
+        *out = qd;
+        return FH_OK;
+    } catch (...) {
+        set_error("host allocation failed");
+        return FH_ERR_ALLOC;
+    }
+}
+
+fh_status fh_quad_koch(fh_ctx* c, int32_t L, const int32_t* p, fh_quad** out)
+{
+    try {
+        FH_ARG(c && out && p, FH_ERR_INVALID_ARG, "NULL argument");
+        *out = nullptr;
+        FH_ARG(L >= 0 && L <= kKochMaxLevel, FH_ERR_INVALID_ARG, "L must be in [0, %d]", kKochMaxLevel);
+        KochParams kp{};
+        kp.L = L;
+        int64_t N = 0, ntri = 1;
+        FH_HIP(hipSetDevice(c->device));
+        for (int k = 0; k <= L; ++k) {
+            FH_ARG(p[k] >= 1 && p[k] <= 1024, FH_ERR_INVALID_ARG, "p[%d] must be in [1, 1024]", k);
+            kp.p[k] = p[k];
+            kp.off[k] = N;
+            N += ntri * (int64_t)p[k] * p[k];
+            ntri = k == 0 ? 3 : ntri * 4;
+            FH_TRY(gl_table(c, p[k], &kp.gl[k]));
+        }
+        kp.off[L + 1] = N;
+        fh_quad* qd = nullptr;
+        FH_TRY(quad_alloc(c, N, &qd));
+        hipLaunchKernelGGL(k_koch_rule, dim3(nblocks(N, 256)), dim3(256), 0, c->stream, kp, qd->x, qd->y, qd->w);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) {
+            fh_quad_destroy(qd);
+            set_error("k_koch_rule launch failed: %s", hipGetErrorString(e));
+            return FH_ERR_HIP;
+        }
+        // the snowflake lies in the unit disc
+        set_bbox(qd, -1.0, 1.0, -1.0, 1.0);
         *out = qd;
         return FH_OK;
     } catch (...) {
