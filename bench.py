@@ -49,9 +49,9 @@ def parse():
                     help="also run a plain 256 MiB device copy (counter calibration for rocprofv3 --pmc)")
     ap.add_argument("--no-grad", action="store_true", help="skip the backward/forward ratio (workload 5)")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched workload 4")
-    ap.add_argument("--parts", default="step,grad,batch,nsli,kite,koch",
-                    help="comma list of step, grad, batch, nsli, kite, koch to run (profiling one part alone; "
-                         "without step the line carries no value)")
+    ap.add_argument("--parts", default="step,grad,batch,nsli,kite,koch,hg",
+                    help="comma list of step, grad, batch, nsli, kite, koch, hg to run (profiling one part "
+                         "alone; without step the line carries no value)")
     return ap.parse_args()
 
 
@@ -428,6 +428,77 @@ def koch_snowflake(fh, steps, warmup):
             "paper_build_s": 240, "paper_field_s": 4.6}
 
 
+def hg_starshade(fh, steps, warmup):
+    """The HG starshade of sec. 4.2 (16 petals, 37,440 nodes): Table t:star's
+    type-1 task at tolerance 1e-8 on a 1000^2 grid over [-16, 16)^2 m, and
+    the sec. 4.3 wavelength sweep -- 50 wavelengths in [0.4, 1.0] um, at each
+    the type-3 field at 200 radii x 300 angles (60,000 targets, one target
+    set) and the maximum intensity over the angles at each radius.  The
+    sweep is timed whole, including building the quadrature once.  The
+    paper's laptop took 0.042 s for the grid task and 6 s for the sweeps of
+    two starshades."""
+    import numpy as np
+    import torch
+    with open(os.path.join(ROOT, "tests", "golden", "hg_starshade.json")) as f:
+        hg = json.load(f)
+    half = 16.0
+    stream = torch.cuda.current_stream()
+    args = (hg["Np"], hg["a"], hg["R"], hg["b"], hg["p"], hg["m"], hg["np"], hg["nd"], hg["md"])
+    ctx = fh.Context("fp64", tol=hg["table_t_star"]["t1_eps"])
+    q = ctx.quad_starshade(*args)
+    n = 1000
+    h = 2 * half / n
+    u = torch.empty((n, n), dtype=torch.complex128, device="cuda")
+    for _ in range(warmup):
+        ctx.field_grid(q, hg["lambda"], hg["z"], n, n, h, h, occulter=True, out=u)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(steps):
+        ctx.field_grid(q, hg["lambda"], hg["z"], n, n, h, h, occulter=True, out=u)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t1_ms = e0.elapsed_time(e1) / steps
+    q.close()
+    ctx.close()
+    sw = hg["sweep"]
+    rho = half * np.arange(1, sw["n_radii"] + 1) / sw["n_radii"]
+    th = 2 * np.pi * np.arange(sw["n_angles"]) / sw["n_angles"]
+    R, T = np.meshgrid(rho, th, indexing="ij")
+    xi = torch.tensor((R * np.cos(T)).ravel(), device="cuda")
+    eta = torch.tensor((R * np.sin(T)).ravel(), device="cuda")
+    lams = np.linspace(0.4e-6, 1.0e-6, sw["n_lambda"])
+    ctx = fh.Context("fp64", tol=1e-9)
+    M = xi.numel()
+    uo = torch.empty(M, dtype=torch.complex128, device="cuda")
+    peak = torch.empty((len(lams), sw["n_radii"]), dtype=torch.float64, device="cuda")
+
+    def sweep():
+        qq = ctx.quad_starshade(*args)
+        tg = ctx.targets(xi, eta, box=(-half, half, -half, half))
+        for i, lam in enumerate(lams):
+            ctx.field_targets(qq, float(lam), hg["z"], tg, occulter=True, out=uo)
+            peak[i] = uo.abs().square().view(sw["n_radii"], sw["n_angles"]).amax(dim=1)
+        tg.close()
+        qq.close()
+
+    sweep()
+    torch.cuda.synchronize()
+    e0.record(stream)
+    sweep()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    sweep_ms = e0.elapsed_time(e1)
+    ctx.close()
+    return {"workload": "HG starshade (sec. 4.2), 37440 nodes, z = 8e7 m", "grid_t1": {
+                "lambda": hg["lambda"], "n": n, "extent_m": [-half, half], "tol": hg["table_t_star"]["t1_eps"],
+                "ms": t1_ms, "paper_s": hg["table_t_star"]["t1_cpu_s"]},
+            "sweep_t3": {"wavelengths": len(lams), "lambda_range_m": [lams[0], lams[-1]], "targets": M,
+                         "tol": 1e-9, "ms_total": sweep_ms, "ms_per_wavelength": sweep_ms / len(lams),
+                         "paper_s_two_starshades": sw["cpu_s_both_starshades"],
+                         "max_intensity_in_shadow": float(peak[:, : int(0.6 * sw["n_radii"])].max())}}
+
+
 def cpu_baseline(wl, seconds):
     """The oracle (direct FP64 sum) on a seeded sample of the step's targets."""
     import numpy as np
@@ -479,6 +550,8 @@ def main():
             out["kite_table"] = kite_table(fh, 5, 2)
         if "koch" in parts:
             out["koch"] = koch_snowflake(fh, 3, 1)
+        if "hg" in parts:
+            out["hg"] = hg_starshade(fh, 5, 2)
         print(json.dumps(out))
         return
     res = {}
@@ -522,6 +595,8 @@ def main():
         out["kite_table"] = kite_table(fh, 5, 2)
     if "koch" in parts:
         out["koch"] = koch_snowflake(fh, 3, 1)
+    if "hg" in parts:
+        out["hg"] = hg_starshade(fh, 5, 2)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
     print(json.dumps(out))
