@@ -11,7 +11,8 @@ What it computes (Barnett, arXiv:2010.05978):
     polygons with Gauss-Legendre nodes per edge);
   * the dilation areal rule (eqs. aqnod/aqwei, sec. 3.1) and the starshade
     disc + petal rule (sec. 3.2), optionally with lateral edge perturbations;
-  * the direct quadrature sum (eq. faq) with the Babinet complement (eq. bab);
+  * the direct quadrature sum (eq. faq) with the Babinet complement (eq. bab),
+    also with a source term per node and a spherical incident wave;
   * the exact gradient of that sum with respect to nodes and weights, and its
     chain rule through the perturbed starshade construction;
   * the non-singular line integral over a boundary rule (appendix, eq. nsli),
@@ -61,6 +62,7 @@ def _load():
         lib.orc_starshade_size.restype = i64
         lib.orc_starshade.argtypes = [i32, d, d, d, d, i32, i32, i32, i32, _dp, i32, _dp, _dp, _dp]
         lib.orc_fresnel_direct.argtypes = [_dp, _dp, _dp, i64, d, d, _dp, _dp, i64, i32, _dp]
+        lib.orc_fresnel_direct_src.argtypes = [_dp, _dp, _dp, _dp, i64, d, d, d, _dp, _dp, i64, i32, _dp]
         lib.orc_fresnel_direct_vjp.argtypes = [_dp, _dp, _dp, i64, d, d, _dp, _dp, i64, i32,
                                                _dp, _dp, _dp, _dp]
         lib.orc_starshade_vjp.argtypes = [i32, d, d, d, d, i32, i32, i32, i32, _dp, i32,
@@ -77,7 +79,7 @@ def _load():
         for name in ("orc_gauss_legendre", "orc_bdry_radial_gl", "orc_bdry_radial_ptr",
                      "orc_bdry_polygon", "orc_dilation", "orc_starshade",
                      "orc_fresnel_direct", "orc_fresnel_direct_vjp", "orc_starshade_vjp",
-                     "orc_bdry_starshade", "orc_nsli", "orc_bdry_fourier", "orc_koch",
+                     "orc_bdry_starshade", "orc_nsli", "orc_bdry_fourier", "orc_koch", "orc_fresnel_direct_src",
                      "orc_koch_outline"):
             getattr(lib, name).restype = i32
         _lib = lib
@@ -266,6 +268,23 @@ def fresnel_direct(x, y, w, lam, z, xi, eta, occulter=False):
     _check(_load().orc_fresnel_direct(_p(x), _p(y), _p(w), len(x), lam, z,
                                        _p(xi), _p(eta), M, int(bool(occulter)), _p(u)),
            "fresnel_direct")
+    return u.view(np.complex128)
+
+
+def fresnel_direct_src(x, y, w, lam, z, xi, eta, src=None, D=0.0, occulter=False):
+    """Direct sum with a complex source term s_j per node (None: 1) and a
+    spherical incident wave exp(i pi |x|^2/(lam D)) (D <= 0: plane wave)."""
+    x, y, w, xi, eta = (_f64(t) for t in (x, y, w, xi, eta))
+    sp = None
+    if src is not None:
+        sp = np.ascontiguousarray(np.asarray(src, dtype=np.complex128)).view(np.float64)
+        if sp.size != 2 * len(x):
+            raise ValueError("src needs one complex value per node")
+    M = len(xi)
+    u = np.empty(2 * M)
+    _check(_load().orc_fresnel_direct_src(_p(x), _p(y), _p(w), _p(sp), len(x), lam, z, float(D),
+                                           _p(xi), _p(eta), M, int(bool(occulter)), _p(u)),
+           "fresnel_direct_src")
     return u.view(np.complex128)
 
 

@@ -17,6 +17,8 @@
  *   - the direct areal-quadrature sum (eq. faq), un-factorised, phase carried
  *     in turns and reduced before cos/sin, pairwise summation over nodes,
  *   - the Babinet complement u_oc = 1 - u_ap (eq. bab),
+ *   - the same sum with a source term per node and a spherical incident
+ *     wave (secs. 1 and 5),
  *   - the Koch snowflake rule of sec. 4.4 (a p x p dilation rule per
  *     triangle of the level-L construction),
  *   - the non-singular line integral over a boundary rule (appendix, eq.
@@ -359,6 +361,63 @@ int orc_fresnel_direct(const double* x, const double* y, const double* w, int64_
         cplx s = {0.0, 0.0};
         if (N > 0) s = pairwise_terms(x, y, w, 0, N, xi[k], eta[k], inv2lz);
         /* multiply by 1/(i lz) = -i/lz */
+        double re = s.im / lz, im = -s.re / lz;
+        if (occulter) { re = 1.0 - re; im = -im; }
+        u[2 * k] = re;
+        u[2 * k + 1] = im;
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Source-plane variations (sec. 5: a smooth source amplitude/phase enters  */
+/* by multiplying each areal weight by the source term at its node) and a  */
+/* spherical incident wave from a point source at distance D before the     */
+/* aperture (sec. 1: z^-1 becomes z^-1 + D^-1; in the Fresnel approximation */
+/* the incident wave at the aperture is exp(i pi |x|^2/(lambda D))):        */
+/*  u_ap(k) = 1/(i lambda z) sum_j w_j s_j exp(i pi |x_j|^2/(lambda D))     */
+/*                                      exp(i pi |xi_k - x_j|^2/(lambda z)) */
+/* src: N interleaved complex s_j, or NULL for s_j = 1; D <= 0 or infinite: */
+/* plane wave.  Phase in turns t = |xi-x|^2/(2 lambda z) + |x|^2/(2 lambda D) */
+/* reduced by rint; pairwise sum over j.                                    */
+/* ------------------------------------------------------------------------ */
+static cplx pairwise_src(const double* x, const double* y, const double* w, const double* src,
+                         int64_t j0, int64_t j1, double xi, double eta, double inv2lz, double inv2lD)
+{
+    cplx s = {0.0, 0.0};
+    if (j1 - j0 <= 16) {
+        for (int64_t j = j0; j < j1; j++) {
+            double dx = xi - x[j], dy = eta - y[j];
+            double t = (dx * dx + dy * dy) * inv2lz + (x[j] * x[j] + y[j] * y[j]) * inv2lD;
+            double f = t - rint(t);
+            double c = cos(2.0 * ORC_PI * f), sn = sin(2.0 * ORC_PI * f);
+            double ar = w[j], ai = 0.0;
+            if (src) { ar = w[j] * src[2 * j]; ai = w[j] * src[2 * j + 1]; }
+            s.re += c * ar - sn * ai;
+            s.im += sn * ar + c * ai;
+        }
+        return s;
+    }
+    int64_t jm = j0 + (j1 - j0) / 2;
+    cplx a = pairwise_src(x, y, w, src, j0, jm, xi, eta, inv2lz, inv2lD);
+    cplx b = pairwise_src(x, y, w, src, jm, j1, xi, eta, inv2lz, inv2lD);
+    s.re = a.re + b.re;
+    s.im = a.im + b.im;
+    return s;
+}
+
+int orc_fresnel_direct_src(const double* x, const double* y, const double* w, const double* src, int64_t N,
+                           double lambda, double z, double D, const double* xi, const double* eta, int64_t M,
+                           int occulter, double* u)
+{
+    double lz = lambda * z;
+    if (!(lz > 0.0)) return 2;
+    double inv2lz = 1.0 / (2.0 * lz);
+    double inv2lD = (D > 0.0 && isfinite(D)) ? 1.0 / (2.0 * lambda * D) : 0.0;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t k = 0; k < M; k++) {
+        cplx s = {0.0, 0.0};
+        if (N > 0) s = pairwise_src(x, y, w, src, 0, N, xi[k], eta[k], inv2lz, inv2lD);
         double re = s.im / lz, im = -s.re / lz;
         if (occulter) { re = 1.0 - re; im = -im; }
         u[2 * k] = re;

@@ -383,3 +383,41 @@ def test_starshade_vjp_chain_rule():
         xm, ym, wm = oracle.quad_starshade(Np, s.a, s.R, s.b, s.p, m, np_, nd, md, cm, K)
         fd = ((gx * (xp - xm)).sum() + (gy * (yp - ym)).sum() + (gw * (wp - wm)).sum()) / (2 * h)
         assert abs(fd - gc[idx]) < 1e-7 * max(1.0, abs(gc[idx])), idx
+
+
+# ------------------------------------------ source terms and spherical incidence
+def test_source_term_tilt_and_spherical_incidence_identities():
+    # a source term s_j multiplies each areal weight (sec. 5).  A tilted plane
+    # wave s = exp(2 pi i x.s/(lambda z)) shifts the pattern:
+    #   u_tilt(xi) = exp(i pi (2 xi.s - |s|^2)/(lambda z)) u(xi - s);
+    # a point source at distance D (sec. 1: z^-1 -> z^-1 + D^-1) satisfies, with
+    # 1/z' = 1/z + 1/D,  u_D(xi) = (z'/z) exp(i pi |xi|^2/(lambda (z + D))) u_z'(xi z'/z).
+    s = workloads.workload(2).shape
+    x, y, w = oracle.quad_radial(s.r0, s.a, s.b, 8, 20, 40)
+    lam, z = 1.0, 0.2
+    lz = lam * z
+    g = np.random.Generator(np.random.PCG64(3))
+    xi, eta = g.uniform(-1, 1, 50), g.uniform(-1, 1, 50)
+    u0 = oracle.fresnel_direct(x, y, w, lam, z, xi, eta)
+    assert np.abs(oracle.fresnel_direct_src(x, y, w, lam, z, xi, eta) - u0).max() == 0
+    assert np.abs(oracle.fresnel_direct_src(x, y, w, lam, z, xi, eta, src=np.ones(len(x))) - u0).max() == 0
+    sv = np.array([0.13, -0.07])
+    src = np.exp(2j * np.pi * (x * sv[0] + y * sv[1]) / lz)
+    ut = oracle.fresnel_direct_src(x, y, w, lam, z, xi, eta, src=src)
+    us = oracle.fresnel_direct(x, y, w, lam, z, xi - sv[0], eta - sv[1])
+    pred = np.exp(1j * np.pi * (2 * (xi * sv[0] + eta * sv[1]) - sv @ sv) / lz) * us
+    assert np.abs(ut - pred).max() < 1e-13
+    for D in (0.7, 3.0, -2.5):
+        zp = 1 / (1 / z + 1 / D)
+        uD = oracle.fresnel_direct_src(x, y, w, lam, z, xi, eta, D=D)
+        if D < 0:  # D <= 0 selects the plane wave
+            assert np.abs(uD - u0).max() == 0
+            continue
+        uP = oracle.fresnel_direct(x, y, w, lam, zp, xi * zp / z, eta * zp / z)
+        pred = (zp / z) * np.exp(1j * np.pi * (xi ** 2 + eta ** 2) / (lam * (z + D))) * uP
+        assert np.abs(uD - pred).max() < 1e-13, D
+    # an amplitude term is linear in the weights
+    amp = 0.5 + 0.25 * np.cos(3 * x)
+    ua = oracle.fresnel_direct_src(x, y, w, lam, z, xi, eta, src=amp.astype(complex))
+    ub = oracle.fresnel_direct(x, y, w * amp, lam, z, xi, eta)
+    assert np.abs(ua - ub).max() < 1e-13
