@@ -261,8 +261,9 @@ fh_status fh_field_targets(fh_ctx* ctx, const fh_quad* q, double lambda, double 
  * parameters.  u (device, B n1 n2 complex) is written instance-major.  All
  * instances share one fine-grid size; the spread runs as one persistent
  * launch over every instance's work items, the FFT is one batched rocFFT
- * call, and the sequence is captured once into a hipGraph keyed by the batch
- * signature and replayed on later calls with the same signature. */
+ * call, and for B > 1 the sequence is captured once into a hipGraph keyed by
+ * the batch signature and replayed on later calls with the same signature
+ * (B = 1 runs eagerly, as fh_field_grid). */
 fh_status fh_field_grid_batch(fh_ctx* ctx, int32_t B, const fh_quad* const* q,
                               const double* lambda, const double* z, int32_t n1, int32_t n2,
                               double h1, double h2, double xc, double yc,

@@ -191,7 +191,10 @@ fh_status t1_pipeline(fh_ctx* c, int B, const fh_quad* const* qs, const double* 
         timing_mark(c, 5);
         return FH_OK;
     };
-    if (!capture || c->timing || std::getenv("FH_NO_GRAPH")) return run();
+    // A single instance passes its parameters to the kernels by value (no
+    // device table), so a graph would bake in this call's quadrature and
+    // wavelength: it runs eagerly, exactly as fh_field_grid does.
+    if (!capture || B == 1 || c->timing || std::getenv("FH_NO_GRAPH")) return run();
 
     // graph key: every pointer and size baked into the launches
     char key[512];
