@@ -62,6 +62,7 @@ def _load():
         lib.orc_starshade_size.restype = i64
         lib.orc_starshade.argtypes = [i32, d, d, d, d, i32, i32, i32, i32, _dp, i32, _dp, _dp, _dp]
         lib.orc_fresnel_direct.argtypes = [_dp, _dp, _dp, i64, d, d, _dp, _dp, i64, i32, _dp]
+        lib.orc_starshade_rigid.argtypes = [i32, d, d, d, d, i32, i32, i32, i32, _dp, i32, i32, _dp, _dp, _dp]
         lib.orc_fresnel_direct_src.argtypes = [_dp, _dp, _dp, _dp, i64, d, d, d, _dp, _dp, i64, i32, _dp]
         lib.orc_fresnel_direct_vjp.argtypes = [_dp, _dp, _dp, i64, d, d, _dp, _dp, i64, i32,
                                                _dp, _dp, _dp, _dp]
@@ -79,7 +80,7 @@ def _load():
         for name in ("orc_gauss_legendre", "orc_bdry_radial_gl", "orc_bdry_radial_ptr",
                      "orc_bdry_polygon", "orc_dilation", "orc_starshade",
                      "orc_fresnel_direct", "orc_fresnel_direct_vjp", "orc_starshade_vjp",
-                     "orc_bdry_starshade", "orc_nsli", "orc_bdry_fourier", "orc_koch", "orc_fresnel_direct_src",
+                     "orc_bdry_starshade", "orc_nsli", "orc_bdry_fourier", "orc_koch", "orc_fresnel_direct_src", "orc_starshade_rigid",
                      "orc_koch_outline"):
             getattr(lib, name).restype = i32
         _lib = lib
@@ -247,6 +248,20 @@ def quad_starshade(Np, a, R, b, p, m, np_, nd, md, coef=None, K=0):
     _check(_load().orc_starshade(Np, a, R, b, p, m, np_, nd, md, _p(coef),
                                   K if coef is not None else 0,
                                   _p(out[0]), _p(out[1]), _p(out[2])), "starshade")
+    return out[0], out[1], out[2]
+
+
+def quad_starshade_rigid(Np, a, R, b, p, m, np_, nd, md, motion, nb, mb):
+    """Starshade rule with misaligned rigid petals (sec. 5): motion = Np rows of
+    (rotation angle about the origin, tx, ty); the signed bridges between each
+    petal's root arc and its moved image get nb x mb GL nodes."""
+    motion = _f64(motion).reshape(-1)
+    if motion.size != 3 * Np:
+        raise ValueError("motion needs 3 values per petal")
+    N = starshade_size(Np, m, np_, nd, md) + Np * nb * mb
+    out = np.empty((3, N))
+    _check(_load().orc_starshade_rigid(Np, a, R, b, p, m, np_, nd, md, _p(motion), nb, mb,
+                                        _p(out[0]), _p(out[1]), _p(out[2])), "starshade_rigid")
     return out[0], out[1], out[2]
 
 

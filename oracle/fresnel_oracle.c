@@ -13,7 +13,8 @@
  *     periodic trapezoid variant, Gauss-Legendre panels otherwise),
  *   - the "dilation" areal rule (eqs. aqnod / aqwei, sec. 3.1),
  *   - the starshade disc + petal rule (sec. 3.2, with the weight's A(r) taken
- *     at the radial node, i.e. the Jacobian of theta = A(r) t),
+ *     at the radial node, i.e. the Jacobian of theta = A(r) t), also with
+ *     misaligned rigid petals and the signed bridges to the disc (sec. 5),
  *   - the direct areal-quadrature sum (eq. faq), un-factorised, phase carried
  *     in turns and reduced before cos/sin, pairwise summation over nodes,
  *   - the Babinet complement u_oc = 1 - u_ap (eq. bab),
@@ -423,6 +424,70 @@ int orc_fresnel_direct_src(const double* x, const double* y, const double* w, co
         u[2 * k] = re;
         u[2 * k + 1] = im;
     }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Misaligned rigid petals (sec. 5): petal k's nodes undergo the rigid      */
+/* motion x -> Rot(d_k) x + (tx_k, ty_k) (rotation about the origin, then   */
+/* translation), weights unchanged; motion = 3 Np doubles (d_k, tx_k, ty_k). */
+/* The signed region between the petal's root arc on the disc,              */
+/* P(tau) = a (cos phi, sin phi), phi = theta_k + (pi/Np) tau, tau in       */
+/* [-1, 1] (the petals meet the disc along the whole circle, A(a) = 1), and */
+/* its moved image M(tau) is covered by the map                              */
+/* X(tau, t) = P(tau) + t (M(tau) - P(tau)), t in [0, 1], with nb GL nodes  */
+/* in tau and mb on (0, 1) in t and weight                                  */
+/* omega_tau v_t (dX/dt x dX/dtau): positive where the petal moved outward  */
+/* (area added), negative where it moved into the disc (area counted twice). */
+/* Node order: the unperturbed starshade rule (disc, then petals), then the */
+/* bridges, petal k outer, tau index, then t index inner.                   */
+/* N = nd md + Np np m + Np nb mb.                                          */
+/* ------------------------------------------------------------------------ */
+int orc_starshade_rigid(int Np, double a, double R, double b, double p, int m, int np, int nd, int md,
+                        const double* motion, int nb, int mb, double* x, double* y, double* w)
+{
+    if (nb < 1 || mb < 1) return 1;
+    int rc = orc_starshade(Np, a, R, b, p, m, np, nd, md, NULL, 0, x, y, w);
+    if (rc) return rc;
+    int64_t off = (int64_t)nd * md;
+    for (int k = 0; k < Np; k++) {
+        double c = cos(motion[3 * k]), sn = sin(motion[3 * k]);
+        double tx = motion[3 * k + 1], ty = motion[3 * k + 2];
+        for (int64_t j = off + (int64_t)k * np * m; j < off + (int64_t)(k + 1) * np * m; j++) {
+            double xx = x[j], yy = y[j];
+            x[j] = c * xx - sn * yy + tx;
+            y[j] = sn * xx + c * yy + ty;
+        }
+    }
+    double* tg = (double*)malloc(sizeof(double) * nb);
+    double* tw = (double*)malloc(sizeof(double) * nb);
+    double* ug = (double*)malloc(sizeof(double) * mb);
+    double* uw = (double*)malloc(sizeof(double) * mb);
+    orc_gauss_legendre(nb, tg, tw);
+    orc_gauss_legendre(mb, ug, uw);
+    int64_t j = off + (int64_t)Np * np * m;
+    for (int k = 0; k < Np; k++) {
+        double c = cos(motion[3 * k]), sn = sin(motion[3 * k]);
+        double tx = motion[3 * k + 1], ty = motion[3 * k + 2];
+        double thk = 2.0 * ORC_PI * k / Np, h = ORC_PI / Np;
+        for (int i = 0; i < nb; i++) {
+            double phi = thk + h * tg[i];
+            double Px = a * cos(phi), Py = a * sin(phi);
+            double dPx = -a * h * sin(phi), dPy = a * h * cos(phi);  /* dP/dtau */
+            double Mx = c * Px - sn * Py + tx, My = sn * Px + c * Py + ty;
+            double dMx = c * dPx - sn * dPy, dMy = sn * dPx + c * dPy;
+            for (int l = 0; l < mb; l++) {
+                double t = 0.5 * (1.0 + ug[l]), vt = 0.5 * uw[l];
+                double Xt = Mx - Px, Yt = My - Py;                  /* dX/dt */
+                double Xs = dPx + t * (dMx - dPx), Ys = dPy + t * (dMy - dPy); /* dX/dtau */
+                x[j] = Px + t * Xt;
+                y[j] = Py + t * Yt;
+                w[j] = tw[i] * vt * (Xt * Ys - Yt * Xs);
+                j++;
+            }
+        }
+    }
+    free(tg); free(tw); free(ug); free(uw);
     return 0;
 }
 

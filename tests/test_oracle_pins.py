@@ -421,3 +421,70 @@ def test_source_term_tilt_and_spherical_incidence_identities():
     ua = oracle.fresnel_direct_src(x, y, w, lam, z, xi, eta, src=amp.astype(complex))
     ub = oracle.fresnel_direct(x, y, w * amp, lam, z, xi, eta)
     assert np.abs(ua - ub).max() < 1e-13
+
+
+# ------------------------------------------------ misaligned rigid petals (sec. 5)
+def _bridge_area_green(Np, a, motion, nq=200):
+    """Signed area covered by the bridges, from their boundaries by Green's
+    theorem (1D Gauss-Legendre on each side), with the rule's orientation."""
+    xg, wg = np.polynomial.legendre.leggauss(nq)
+    tot = 0.0
+    for k in range(Np):
+        d, tx, ty = motion[k]
+        c, s = math.cos(d), math.sin(d)
+        thk, h = 2 * math.pi * k / Np, math.pi / Np
+
+        def P(tau):
+            return a * np.cos(thk + h * tau), a * np.sin(thk + h * tau)
+
+        def M(tau):
+            px, py = P(tau)
+            return c * px - s * py + tx, s * px + c * py + ty
+
+        def seg(fx, fy, dfx, dfy):
+            return np.sum(wg * fx * dfy)
+
+        # root arc tau -1 -> 1 (t = 0), moved arc tau 1 -> -1 (t = 1)
+        px, py = P(xg)
+        dpx, dpy = -a * h * np.sin(thk + h * xg), a * h * np.cos(thk + h * xg)
+        mx, my = M(xg)
+        dmx, dmy = c * dpx - s * dpy, s * dpx + c * dpy
+        ring = seg(px, py, dpx, dpy) - seg(mx, my, dmx, dmy)
+        # straight sides: tau = 1 (t 0 -> 1) and tau = -1 (t 1 -> 0)
+        for tau, sign in ((1.0, 1.0), (-1.0, -1.0)):
+            (ax, ay), (bx, by) = P(tau), M(tau)
+            t = 0.5 * (1 + xg)
+            ring += sign * np.sum(0.5 * wg * (ax + t * (bx - ax)) * (by - ay))
+        tot += -ring
+    return tot
+
+
+def test_rigid_petals_rule():
+    Np, a, R, b, p = 12, 6.0, 12.0, 6.0, 6.0
+    m, np_, nd, md = 40, 20, 200, 40
+    x0, y0, w0 = oracle.quad_starshade(Np, a, R, b, p, m, np_, nd, md)
+    N0 = len(x0)
+    # no motion: the ideal rule plus bridges of zero weight
+    x, y, w = oracle.quad_starshade_rigid(Np, a, R, b, p, m, np_, nd, md, np.zeros((Np, 3)), 8, 4)
+    assert np.array_equal(x[:N0], x0) and np.array_equal(w[:N0], w0) and np.abs(w[N0:]).max() == 0
+    # random small motions: the bridges' weights sum to their signed area
+    g = np.random.Generator(np.random.PCG64(12))
+    motion = np.column_stack([g.normal(0, 2e-3, Np), g.normal(0, 0.03, Np), g.normal(0, 0.03, Np)])
+    x, y, w = oracle.quad_starshade_rigid(Np, a, R, b, p, m, np_, nd, md, motion, 12, 3)
+    assert abs(w[N0:].sum() - _bridge_area_green(Np, a, motion)) < 1e-13
+    assert abs(w.sum() - (_starshade_area(Np, a, R, b, p) + _bridge_area_green(Np, a, motion))) < 1e-9
+    # moved petal nodes keep their weights and distances to each other
+    assert np.array_equal(w[nd * md:N0], w0[nd * md:])
+    k0 = nd * md
+    d0 = math.hypot(x0[k0 + 5] - x0[k0], y0[k0 + 5] - y0[k0])
+    assert abs(math.hypot(x[k0 + 5] - x[k0], y[k0 + 5] - y[k0]) - d0) < 1e-13
+    # the same rotation of every petal about the centre: the bridges cancel
+    # around the disc and the field is the ideal one at rotated targets
+    d = 0.01
+    motion = np.zeros((Np, 3)); motion[:, 0] = d
+    x, y, w = oracle.quad_starshade_rigid(Np, a, R, b, p, m, np_, nd, md, motion, 16, 4)
+    xi, eta = g.uniform(-8, 8, 20), g.uniform(-8, 8, 20)
+    u = oracle.fresnel_direct(x, y, w, 1.0, 20.0, xi, eta)
+    c, s = math.cos(-d), math.sin(-d)
+    ur = oracle.fresnel_direct(x0, y0, w0, 1.0, 20.0, c * xi - s * eta, s * xi + c * eta)
+    assert np.abs(u - ur).max() < 1e-12
