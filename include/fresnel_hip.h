@@ -189,6 +189,20 @@ fh_status fh_quad_starshade(fh_ctx* ctx, int32_t Np, double a, double R, double 
                             const double* coef, int32_t K, fh_memspace coef_mem,
                             fh_quad** out);
 
+/* Starshade with misaligned rigid petals (sec. 5): the unperturbed rule of
+ * fh_quad_starshade (same parameters, no edge perturbation), then petal k's
+ * nodes move by x -> Rot(d_k) x + (tx_k, ty_k) (rotation about the centre,
+ * then translation) with unchanged weights, and the signed region between
+ * the petal's root arc on the disc (r = a, angles theta_k +- pi/Np) and its
+ * moved image is covered by the map X(tau, t) = P(tau) + t (M(tau) - P(tau))
+ * with nb Gauss-Legendre nodes along the arc and mb across: positive weights
+ * where the petal moved outward, negative where it moved into the disc.
+ * motion: 3 Np host doubles (d_k, tx_k, ty_k), Np <= 64.
+ * N = nd md + Np np m + Np nb mb (disc, moved petals, then the bridges). */
+fh_status fh_quad_starshade_rigid(fh_ctx* ctx, int32_t Np, double a, double R, double b, double p,
+                                  int32_t m, int32_t np, int32_t nd, int32_t md, const double* motion,
+                                  int32_t nb, int32_t mb, fh_quad** out);
+
 /* Raw areal rule (eq. aq): N nodes and weights, copied into a new object. */
 fh_status fh_quad_from_nodes(fh_ctx* ctx, const double* x, const double* y, const double* w,
                              int64_t N, fh_memspace mem, fh_quad** out);

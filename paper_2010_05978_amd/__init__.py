@@ -105,6 +105,10 @@ class Context:
         """Rule for the closed curve X = sum ax_k cos kt + bx_k sin kt, Y likewise."""
         return Quad(self, abi.fh_quad_fourier(self.handle, ax, bx, ay, by, panels, q, m))
 
+    def quad_starshade_rigid(self, Np, a, R, b, p, m, np_, nd, md, motion, nb=16, mb=4) -> Quad:
+        """Starshade whose petals moved rigidly (motion: Np rows of angle, tx, ty)."""
+        return Quad(self, abi.fh_quad_starshade_rigid(self.handle, Np, a, R, b, p, m, np_, nd, md, motion, nb, mb))
+
     def quad_koch(self, L, p) -> Quad:
         """Koch snowflake rule (level L, p[k] x p[k] nodes per level-k triangle)."""
         return Quad(self, abi.fh_quad_koch(self.handle, L, p))

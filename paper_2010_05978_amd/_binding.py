@@ -38,7 +38,7 @@ EXPORTED = [
     "fh_field_grid", "fh_field_points", "fh_field_targets", "fh_field_grid_batch", "fh_field_grid_vjp",
     "fh_starshade_vjp", "fh_autotune_grid", "fh_set_timing", "fh_last_timing", "fh_timing_totals",
     "fh_boundary_radial", "fh_boundary_polygon", "fh_boundary_starshade", "fh_field_nsli",
-    "fh_quad_fourier", "fh_boundary_fourier", "fh_quad_koch",
+    "fh_quad_fourier", "fh_boundary_fourier", "fh_quad_koch", "fh_quad_starshade_rigid",
 ]
 
 
@@ -104,6 +104,7 @@ def lib():
             "fh_field_nsli": [vp, vp, vp, vp, vp, i64, d, d, i64, vp, vp, d, i32, vp, ctypes.c_int],
             "fh_quad_fourier": [vp, i32, vp, vp, vp, vp, i32, i32, i32, pvp],
             "fh_quad_koch": [vp, i32, vp, pvp],
+            "fh_quad_starshade_rigid": [vp, i32, d, d, d, d, i32, i32, i32, i32, vp, i32, i32, pvp],
             "fh_boundary_fourier": [vp, i32, vp, vp, vp, vp, i32, i32, vp, vp, vp, vp, ctypes.c_int],
         }
         for name, args in sig.items():
@@ -318,6 +319,16 @@ def fh_quad_fourier(ctx, ax, bx, ay, by, panels, q, m):
     K, cs = _fourier_coefs(ax, bx, ay, by)
     h = _new_quad()
     _check(lib().fh_quad_fourier(ctx, K, *[_ptr_mem(a)[0] for a in cs], panels, q, m, ctypes.byref(h)))
+    return h
+
+
+def fh_quad_starshade_rigid(ctx, Np, a, R, b, p, m, np_, nd, md, motion, nb, mb):
+    motion = np.ascontiguousarray(motion, dtype=np.float64).reshape(-1)
+    if motion.size != 3 * Np:
+        raise ValueError("motion needs 3 values per petal")
+    h = _new_quad()
+    _check(lib().fh_quad_starshade_rigid(ctx, Np, a, R, b, p, m, np_, nd, md, ctypes.c_void_p(motion.ctypes.data),
+                                         nb, mb, ctypes.byref(h)))
     return h
 
 

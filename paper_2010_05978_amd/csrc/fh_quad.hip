@@ -463,6 +463,62 @@ __global__ void k_bdry_starshade(OutlineParams op, const double* __restrict__ gl
     Vv[i] = v;
 }
 
+// Misaligned rigid petals (sec. 5): petal k's nodes move by
+// x -> Rot(d_k) x + (tx_k, ty_k), weights unchanged, and the signed region
+// between its root arc P(tau) = a (cos phi, sin phi), phi = theta_k +
+// (pi/Np) tau, and the moved arc M(tau) is covered by
+// X(tau, t) = P + t (M - P) with weight w_tau v_t (dX/dt x dX/dtau).
+constexpr int kRigidMaxPetals = 64;
+struct RigidParams {
+    int Np, np, m, nb, mb;
+    double a;
+    int64_t petal_off;   // first petal node
+    int64_t bridge_off;  // first bridge node
+    double motion[3 * kRigidMaxPetals];  // per petal: angle, tx, ty
+};
+
+__global__ void k_rigid_move(RigidParams rp, double* __restrict__ x, double* __restrict__ y)
+{
+    const int64_t per = (int64_t)rp.np * rp.m;
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= per * rp.Np) return;
+    const int k = (int)(t / per);
+    const int64_t j = rp.petal_off + t;
+    double s, c;
+    sincos(rp.motion[3 * k], &s, &c);
+    const double xx = x[j], yy = y[j];
+    x[j] = c * xx - s * yy + rp.motion[3 * k + 1];
+    y[j] = s * xx + c * yy + rp.motion[3 * k + 2];
+}
+
+__global__ void k_rigid_bridges(RigidParams rp, const double* __restrict__ glb, const double* __restrict__ glt,
+                                double* __restrict__ x, double* __restrict__ y, double* __restrict__ w)
+{
+    const int64_t per = (int64_t)rp.nb * rp.mb;
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= per * rp.Np) return;
+    const int k = (int)(t / per);
+    const int r = (int)(t - (int64_t)k * per);
+    const int i = r / rp.mb, l = r - i * rp.mb;
+    double s, c;
+    sincos(rp.motion[3 * k], &s, &c);
+    const double h = kPi / rp.Np;
+    const double phi = 2.0 * kPi * k / rp.Np + h * glb[i];
+    double sp, cp;
+    sincos(phi, &sp, &cp);
+    const double px = rp.a * cp, py = rp.a * sp;
+    const double dpx = -rp.a * h * sp, dpy = rp.a * h * cp;
+    const double mx = c * px - s * py + rp.motion[3 * k + 1], my = s * px + c * py + rp.motion[3 * k + 2];
+    const double dmx = c * dpx - s * dpy, dmy = s * dpx + c * dpy;
+    const double tt = 0.5 * (1.0 + glt[l]);
+    const double xt = mx - px, yt = my - py;
+    const double xs = dpx + tt * (dmx - dpx), ys = dpy + tt * (dmy - dpy);
+    const int64_t j = rp.bridge_off + t;
+    x[j] = px + tt * xt;
+    y[j] = py + tt * yt;
+    w[j] = glb[rp.nb + i] * (0.5 * glt[rp.mb + l]) * (xt * ys - yt * xs);
+}
+
 inline unsigned nblocks(int64_t n, int bs) { return (unsigned)std::max<int64_t>(1, (n + bs - 1) / bs); }
 
 // A box that contains every node (used to size fine grids and row windows).
@@ -803,6 +859,73 @@ fh_status fh_quad_starshade(fh_ctx* c, int32_t Np, double a, double R, double b,
         if (coef && coef_mem == FH_MEM_HOST) FH_HIP(hipStreamSynchronize(c->stream));
         // every node radius is at most R (edge perturbations move angles only)
         set_bbox(qd, -R, R, -R, R);
+        *out = qd;
+        return FH_OK;
+    } catch (...) {
+        set_error("host allocation failed");
+        return FH_ERR_ALLOC;
+    }
+}
+
+fh_status fh_quad_starshade_rigid(fh_ctx* c, int32_t Np, double a, double R, double b, double p, int32_t m,
+                                  int32_t np, int32_t nd, int32_t md, const double* motion, int32_t nb, int32_t mb,
+                                  fh_quad** out)
+{
+    try {
+        FH_ARG(c && out && motion, FH_ERR_INVALID_ARG, "NULL argument");
+        *out = nullptr;
+        FH_ARG(Np >= 1 && Np <= kRigidMaxPetals, FH_ERR_INVALID_ARG, "Np must be in [1, %d]", kRigidMaxPetals);
+        FH_ARG(m >= 1 && np >= 1 && nd >= 0 && md >= 1 && nb >= 1 && mb >= 1, FH_ERR_INVALID_ARG,
+               "need Np, m, np, md, nb, mb >= 1 and nd >= 0");
+        FH_ARG(std::isfinite(a) && std::isfinite(R) && std::isfinite(b) && std::isfinite(p), FH_ERR_NONFINITE,
+               "starshade scalar not finite");
+        FH_ARG(a > 0 && R > a && b > 0 && p > 0, FH_ERR_INVALID_ARG, "need 0 < a < R, b > 0, p > 0");
+        RigidParams rp{};
+        double shift = 0.0;
+        for (int k = 0; k < 3 * Np; ++k) {
+            FH_ARG(std::isfinite(motion[k]), FH_ERR_NONFINITE, "motion entry %d not finite", k);
+            rp.motion[k] = motion[k];
+        }
+        for (int k = 0; k < Np; ++k) shift = std::max(shift, std::hypot(motion[3 * k + 1], motion[3 * k + 2]));
+        FH_HIP(hipSetDevice(c->device));
+        const double *glm = nullptr, *gln = nullptr, *glmd = nullptr, *glb = nullptr, *glt = nullptr;
+        FH_TRY(gl_table(c, m, &glm));
+        FH_TRY(gl_table(c, np, &gln));
+        FH_TRY(gl_table(c, md, &glmd));
+        FH_TRY(gl_table(c, nb, &glb));
+        FH_TRY(gl_table(c, mb, &glt));
+        const int64_t Nd = (int64_t)nd * md, Npet = (int64_t)Np * np * m, Nb = (int64_t)Np * nb * mb;
+        fh_quad* qd = nullptr;
+        FH_TRY(quad_alloc(c, Nd + Npet + Nb, &qd));
+        if (nd > 0) {
+            RadialParams dp{};
+            dp.r0 = a;
+            dp.q = nd;
+            hipLaunchKernelGGL(k_radial_rule, dim3(nblocks(Nd, 256)), dim3(256), 0, c->stream, dp,
+                               (const double*)nullptr, (int64_t)nd, md, glmd, qd->x, qd->y, qd->w);
+        }
+        PetalParams pp{Np, m, np, 0, a, R, b, p, Nd};
+        hipLaunchKernelGGL(k_petals, dim3(nblocks(Npet, 256)), dim3(256), 0, c->stream, pp, glm, gln,
+                           (const double*)nullptr, qd->x, qd->y, qd->w);
+        rp.Np = Np;
+        rp.np = np;
+        rp.m = m;
+        rp.nb = nb;
+        rp.mb = mb;
+        rp.a = a;
+        rp.petal_off = Nd;
+        rp.bridge_off = Nd + Npet;
+        hipLaunchKernelGGL(k_rigid_move, dim3(nblocks(Npet, 256)), dim3(256), 0, c->stream, rp, qd->x, qd->y);
+        hipLaunchKernelGGL(k_rigid_bridges, dim3(nblocks(Nb, 256)), dim3(256), 0, c->stream, rp, glb, glt, qd->x,
+                           qd->y, qd->w);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) {
+            fh_quad_destroy(qd);
+            set_error("rigid-petal rule launch failed: %s", hipGetErrorString(e));
+            return FH_ERR_HIP;
+        }
+        // rotations about the centre keep radii; translations add at most `shift`
+        set_bbox(qd, -R - shift, R + shift, -R - shift, R + shift);
         *out = qd;
         return FH_OK;
     } catch (...) {

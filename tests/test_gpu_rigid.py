@@ -1,0 +1,64 @@
+"""Starshade with misaligned rigid petals (sec. 5) on the GPU vs the CPU oracle.
+
+The device rule (fh_quad_starshade_rigid) node by node against the oracle's
+construction for random petal motions, and its type-1 and type-3 fields
+element by element against the oracle's direct sum.
+"""
+import numpy as np
+import pytest
+
+import oracle
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-9, "mixed": 1e-5}
+SHAPE = (12, 6.0, 12.0, 6.0, 6.0, 40, 20, 200, 40)  # Np, a, R, b, p, m, np, nd, md
+
+
+def relL2(a, b):
+    return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / max(np.linalg.norm(np.ravel(b)), 1e-300))
+
+
+def cpu(t):
+    return t.detach().cpu().numpy()
+
+
+def motions(Np, seed):
+    g = np.random.Generator(np.random.PCG64(seed))
+    return np.column_stack([g.normal(0, 2e-3, Np), g.normal(0, 0.03, Np), g.normal(0, 0.03, Np)])
+
+
+@pytest.fixture(scope="module")
+def fh():
+    import paper_2010_05978_amd as fh
+    return fh
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_rigid_petals_rule_and_fields(fh, prec):
+    print(f"rigid petals {prec}", flush=True)
+    ctx = fh.Context(prec)
+    mo = motions(SHAPE[0], 5)
+    q = ctx.quad_starshade_rigid(*SHAPE, mo, 12, 3)
+    x, y, w = oracle.quad_starshade_rigid(*SHAPE, mo, 12, 3)
+    gx, gy, gw = (cpu(t) for t in q.export())
+    assert len(gx) == len(x)
+    assert max(np.abs(gx - x).max(), np.abs(gy - y).max()) < 1e-13
+    assert np.abs(gw - w).max() < 1e-13 * np.abs(w).max()
+    lam, z = 5e-7, 3.7e7
+    n, h = 128, 4.8 / 128
+    u = cpu(ctx.field_grid(q, lam, z, n, n, h, h, occulter=True)).ravel()
+    xi, eta = oracle.grid_targets(n, n, h, h)
+    ref = oracle.fresnel_direct(x, y, w, lam, z, xi, eta, occulter=True)
+    assert relL2(1 - u, 1 - ref) < TOL[prec]
+    g = np.random.Generator(np.random.PCG64(6))
+    xr, er = g.uniform(-3, 3, 3000), g.uniform(-3, 3, 3000)
+    v = cpu(ctx.field_points(q, lam, z, torch.tensor(xr, device="cuda"), torch.tensor(er, device="cuda"),
+                             occulter=True))
+    refp = oracle.fresnel_direct(x, y, w, lam, z, xr, er, occulter=True)
+    assert relL2(1 - v, 1 - refp) < TOL[prec]
+    q.close()
+    with pytest.raises(fh.FresnelError, match="FH_ERR_INVALID_ARG"):
+        ctx.quad_starshade_rigid(65, *SHAPE[1:], np.zeros((65, 3)), 4, 2)
+    ctx.close()
