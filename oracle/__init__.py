@@ -62,6 +62,7 @@ def _load():
         lib.orc_starshade_size.restype = i64
         lib.orc_starshade.argtypes = [i32, d, d, d, d, i32, i32, i32, i32, _dp, i32, _dp, _dp, _dp]
         lib.orc_fresnel_direct.argtypes = [_dp, _dp, _dp, i64, d, d, _dp, _dp, i64, i32, _dp]
+        lib.orc_starshade_tab.argtypes = [i32, d, d, _dp, i32, i32, i32, i32, _dp, i32, _dp, _dp, _dp]
         lib.orc_starshade_rigid.argtypes = [i32, d, d, d, d, i32, i32, i32, i32, _dp, i32, i32, _dp, _dp, _dp]
         lib.orc_fresnel_direct_src.argtypes = [_dp, _dp, _dp, _dp, i64, d, d, d, _dp, _dp, i64, i32, _dp]
         lib.orc_fresnel_direct_vjp.argtypes = [_dp, _dp, _dp, i64, d, d, _dp, _dp, i64, i32,
@@ -80,7 +81,7 @@ def _load():
         for name in ("orc_gauss_legendre", "orc_bdry_radial_gl", "orc_bdry_radial_ptr",
                      "orc_bdry_polygon", "orc_dilation", "orc_starshade",
                      "orc_fresnel_direct", "orc_fresnel_direct_vjp", "orc_starshade_vjp",
-                     "orc_bdry_starshade", "orc_nsli", "orc_bdry_fourier", "orc_koch", "orc_fresnel_direct_src", "orc_starshade_rigid",
+                     "orc_bdry_starshade", "orc_nsli", "orc_bdry_fourier", "orc_koch", "orc_fresnel_direct_src", "orc_starshade_rigid", "orc_starshade_tab",
                      "orc_koch_outline"):
             getattr(lib, name).restype = i32
         _lib = lib
@@ -248,6 +249,20 @@ def quad_starshade(Np, a, R, b, p, m, np_, nd, md, coef=None, K=0):
     _check(_load().orc_starshade(Np, a, R, b, p, m, np_, nd, md, _p(coef),
                                   K if coef is not None else 0,
                                   _p(out[0]), _p(out[1]), _p(out[2])), "starshade")
+    return out[0], out[1], out[2]
+
+
+def quad_starshade_tab(Np, a, R, A, m, np_, nd, md, coef=None, K=0):
+    """Starshade rule with a tabulated apodisation: A[l] = A(r_l) at the m
+    Gauss-Legendre radii r_l on (a, R)."""
+    A = _f64(A)
+    if A.size != m:
+        raise ValueError("A needs one value per radial node")
+    N = starshade_size(Np, m, np_, nd, md)
+    coef = None if coef is None else _f64(coef)
+    out = np.empty((3, N))
+    _check(_load().orc_starshade_tab(Np, a, R, _p(A), m, np_, nd, md, _p(coef), K if coef is not None else 0,
+                                      _p(out[0]), _p(out[1]), _p(out[2])), "starshade_tab")
     return out[0], out[1], out[2]
 
 

@@ -272,9 +272,11 @@ int64_t orc_starshade_size(int Np, int m, int np, int nd, int md)
     return (int64_t)nd * md + (int64_t)Np * np * m;
 }
 
-int orc_starshade(int Np, double a, double R, double b, double p,
-                  int m, int np, int nd, int md, const double* coef, int K,
-                  double* x, double* y, double* w)
+/* The rule with the apodisation given either by the HG family (Atab NULL) */
+/* or as a table Atab[l] = A(r_l) at the m GL radii r_l on (a, R).          */
+static int starshade_impl(int Np, double a, double R, double b, double p, const double* Atab,
+                          int m, int np, int nd, int md, const double* coef, int K,
+                          double* x, double* y, double* w)
 {
     if (Np < 1 || m < 1 || np < 1 || nd < 0 || md < 1 || !(R > a) || !(a >= 0)) return 1;
     /* disc */
@@ -305,7 +307,8 @@ int orc_starshade(int Np, double a, double R, double b, double p,
                         dm += coef[2 * k * K + K + (s - 1)] * sk;
                     }
                 double mid = (dp - dm) / (2.0 * r);
-                double half = ORC_PI * hg_profile(r, a, b, p) / Np + (dp + dm) / (2.0 * r);
+                double A = Atab ? Atab[l] : hg_profile(r, a, b, p);
+                double half = ORC_PI * A / Np + (dp + dm) / (2.0 * r);
                 double phi = thk + mid + half * tx[i];
                 int64_t j = off + (int64_t)k * np * m + (int64_t)i * m + l;
                 x[j] = r * cos(phi);
@@ -315,6 +318,23 @@ int orc_starshade(int Np, double a, double R, double b, double p,
     }
     free(rx); free(rw); free(tx); free(tw);
     return 0;
+}
+
+int orc_starshade(int Np, double a, double R, double b, double p,
+                  int m, int np, int nd, int md, const double* coef, int K,
+                  double* x, double* y, double* w)
+{
+    if (!(b > 0) || !(p > 0)) return 1;
+    return starshade_impl(Np, a, R, b, p, NULL, m, np, nd, md, coef, K, x, y, w);
+}
+
+/* Tabulated apodisation (the paper's NI2 design comes as samples of A(r),  */
+/* interpolated to the m radial Gauss nodes, sec. 4.2): Atab[l] = A(r_l).   */
+int orc_starshade_tab(int Np, double a, double R, const double* Atab, int m, int np, int nd, int md,
+                      const double* coef, int K, double* x, double* y, double* w)
+{
+    if (!Atab) return 1;
+    return starshade_impl(Np, a, R, 1.0, 1.0, Atab, m, np, nd, md, coef, K, x, y, w);
 }
 
 /* ------------------------------------------------------------------------ */

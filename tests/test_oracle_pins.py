@@ -488,3 +488,30 @@ def test_rigid_petals_rule():
     c, s = math.cos(-d), math.sin(-d)
     ur = oracle.fresnel_direct(x0, y0, w0, 1.0, 20.0, c * xi - s * eta, s * xi + c * eta)
     assert np.abs(u - ur).max() < 1e-12
+
+
+# --------------------------------------------- tabulated starshade apodisation
+def test_starshade_tabulated_profile():
+    Np, a, R, b, p = 16, 12.5, 31.0, 12.5, 6.0
+    m, np_, nd, md = 60, 30, 144, 60
+    xg, wg = oracle.gauss_legendre(m)
+    r = a + 0.5 * (R - a) * (1 + xg)
+    wr = 0.5 * (R - a) * wg
+    # the HG values at the radial nodes reproduce the HG rule, also perturbed
+    A = np.exp(-((r - a) / b) ** p)
+    coef = np.random.Generator(np.random.PCG64(8)).normal(0, 1e-3, 2 * Np * 4)
+    for cf, K in ((None, 0), (coef, 4)):
+        x0, y0, w0 = oracle.quad_starshade(Np, a, R, b, p, m, np_, nd, md, cf, K)
+        x1, y1, w1 = oracle.quad_starshade_tab(Np, a, R, A, m, np_, nd, md, cf, K)
+        assert max(np.abs(x0 - x1).max(), np.abs(y0 - y1).max()) < 1e-12
+        assert np.abs(w0 - w1).max() < 1e-15 * np.abs(w0).max() * 10
+    # a cubic taper: the m-node rule integrates r A(r) exactly, so the area is
+    # pi a^2 + 2 pi int_a^R r A(r) dr in closed form
+    s = (r - a) / (R - a)
+    At = 1 - 3 * s ** 2 + 2 * s ** 3
+    x, y, w = oracle.quad_starshade_tab(Np, a, R, At, m, np_, nd, md)
+    L = R - a
+    # int_0^1 (a + L s)(1 - 3 s^2 + 2 s^3) L ds = L (a / 2 + L (1/2 - 3/4 + 2/5))
+    exact = math.pi * a * a + 2 * math.pi * L * (a * 0.5 + L * (0.5 - 0.75 + 0.4))
+    assert abs(w.sum() - exact) < 1e-11
+    assert abs(w.sum() - (math.pi * a * a + 2 * math.pi * np.sum(wr * r * At))) < 1e-11
