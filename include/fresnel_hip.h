@@ -189,6 +189,15 @@ fh_status fh_quad_starshade(fh_ctx* ctx, int32_t Np, double a, double R, double 
                             const double* coef, int32_t K, fh_memspace coef_mem,
                             fh_quad** out);
 
+/* As fh_quad_starshade with a tabulated apodisation instead of the HG family
+ * (the paper's NI2 design is given as samples of A(r), interpolated to the
+ * radial Gauss nodes, sec. 4.2): A holds m host doubles, A[l] = A(r_l) at
+ * r_l = a + (R - a)(1 + x_l)/2, x_l the m-node Gauss-Legendre nodes on
+ * [-1, 1] ascending.  fh_starshade_vjp covers the HG family only. */
+fh_status fh_quad_starshade_tab(fh_ctx* ctx, int32_t Np, double a, double R, const double* A, int32_t m,
+                                int32_t np, int32_t nd, int32_t md, const double* coef, int32_t K,
+                                fh_memspace coef_mem, fh_quad** out);
+
 /* Starshade with misaligned rigid petals (sec. 5): the unperturbed rule of
  * fh_quad_starshade (same parameters, no edge perturbation), then petal k's
  * nodes move by x -> Rot(d_k) x + (tx_k, ty_k) (rotation about the centre,

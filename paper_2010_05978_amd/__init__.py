@@ -105,6 +105,10 @@ class Context:
         """Rule for the closed curve X = sum ax_k cos kt + bx_k sin kt, Y likewise."""
         return Quad(self, abi.fh_quad_fourier(self.handle, ax, bx, ay, by, panels, q, m))
 
+    def quad_starshade_tab(self, Np, a, R, A, m, np_, nd, md, coef=None, K=0) -> Quad:
+        """Starshade with a tabulated apodisation A[l] = A(r_l) at the m radial Gauss nodes."""
+        return Quad(self, abi.fh_quad_starshade_tab(self.handle, Np, a, R, A, m, np_, nd, md, coef, K))
+
     def quad_starshade_rigid(self, Np, a, R, b, p, m, np_, nd, md, motion, nb=16, mb=4) -> Quad:
         """Starshade whose petals moved rigidly (motion: Np rows of angle, tx, ty)."""
         return Quad(self, abi.fh_quad_starshade_rigid(self.handle, Np, a, R, b, p, m, np_, nd, md, motion, nb, mb))

@@ -39,6 +39,7 @@ EXPORTED = [
     "fh_starshade_vjp", "fh_autotune_grid", "fh_set_timing", "fh_last_timing", "fh_timing_totals",
     "fh_boundary_radial", "fh_boundary_polygon", "fh_boundary_starshade", "fh_field_nsli",
     "fh_quad_fourier", "fh_boundary_fourier", "fh_quad_koch", "fh_quad_starshade_rigid",
+    "fh_quad_starshade_tab",
 ]
 
 
@@ -105,6 +106,7 @@ def lib():
             "fh_quad_fourier": [vp, i32, vp, vp, vp, vp, i32, i32, i32, pvp],
             "fh_quad_koch": [vp, i32, vp, pvp],
             "fh_quad_starshade_rigid": [vp, i32, d, d, d, d, i32, i32, i32, i32, vp, i32, i32, pvp],
+            "fh_quad_starshade_tab": [vp, i32, d, d, vp, i32, i32, i32, i32, vp, i32, ctypes.c_int, pvp],
             "fh_boundary_fourier": [vp, i32, vp, vp, vp, vp, i32, i32, vp, vp, vp, vp, ctypes.c_int],
         }
         for name, args in sig.items():
@@ -319,6 +321,21 @@ def fh_quad_fourier(ctx, ax, bx, ay, by, panels, q, m):
     K, cs = _fourier_coefs(ax, bx, ay, by)
     h = _new_quad()
     _check(lib().fh_quad_fourier(ctx, K, *[_ptr_mem(a)[0] for a in cs], panels, q, m, ctypes.byref(h)))
+    return h
+
+
+def fh_quad_starshade_tab(ctx, Np, a, R, A, m, np_, nd, md, coef=None, K=0):
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    if A.size != m:
+        raise ValueError("A needs one value per radial node")
+    cptr, cmem = (None, FH_MEM_HOST)
+    if coef is not None:
+        if not _is_torch(coef):
+            coef = np.ascontiguousarray(coef, dtype=np.float64)
+        cptr, cmem = _ptr_mem(coef)
+    h = _new_quad()
+    _check(lib().fh_quad_starshade_tab(ctx, Np, a, R, ctypes.c_void_p(A.ctypes.data), m, np_, nd, md, cptr,
+                                       K if coef is not None else 0, cmem, ctypes.byref(h)))
     return h
 
 

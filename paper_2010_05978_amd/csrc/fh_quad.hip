@@ -331,8 +331,10 @@ struct PetalParams {
 };
 
 // Petal node j = off + k np m + i m + l.
+// The apodisation is the HG family A(r) = exp(-((r-a)/b)^p), or, with
+// Atab, the table Atab[l] = A(r_l) at the radial nodes.
 __global__ void k_petals(PetalParams pp, const double* __restrict__ glm, const double* __restrict__ gln,
-                         const double* __restrict__ coef, double* __restrict__ x,
+                         const double* __restrict__ coef, const double* __restrict__ Atab, double* __restrict__ x,
                          double* __restrict__ y, double* __restrict__ w)
 {
     const int64_t per = (int64_t)pp.np * pp.m;
@@ -346,7 +348,7 @@ __global__ void k_petals(PetalParams pp, const double* __restrict__ glm, const d
     const double r = pp.a + 0.5 * L * (1.0 + glm[l]);
     const double wr = 0.5 * L * glm[pp.m + l];
     const double tau = gln[i], wt = gln[pp.np + i];
-    const double A = exp(-pow((r - pp.a) / pp.b, pp.p));
+    const double A = Atab ? Atab[l] : exp(-pow((r - pp.a) / pp.b, pp.p));
     double dp = 0.0, dm = 0.0;
     if (coef) {
         const double* cp = coef + 2 * (int64_t)k * pp.K;
@@ -614,6 +616,82 @@ fh_status bdry_end(fh_ctx* c, int64_t n, double* X, double* Y, double* W, double
 }  // namespace
 }  // namespace fh
 
+namespace fh {
+namespace {
+
+// The disc + petal rule; Atab (m host values at the radial nodes) replaces
+// the HG family when not null.
+fh_status starshade_build(fh_ctx* c, int32_t Np, double a, double R, double b, double p, const double* Atab,
+                          int32_t m, int32_t np, int32_t nd, int32_t md, const double* coef, int32_t K,
+                          fh_memspace coef_mem, fh_quad** out)
+{
+    FH_ARG(c && out, FH_ERR_INVALID_ARG, "NULL argument");
+    *out = nullptr;
+    FH_ARG(Np >= 1 && m >= 1 && np >= 1 && nd >= 0 && md >= 1, FH_ERR_INVALID_ARG,
+           "need Np, m, np, md >= 1 and nd >= 0");
+    FH_ARG(std::isfinite(a) && std::isfinite(R) && std::isfinite(b) && std::isfinite(p), FH_ERR_NONFINITE,
+           "starshade scalar not finite");
+    FH_ARG(a >= 0 && R > a && b > 0 && p > 0, FH_ERR_INVALID_ARG, "need 0 <= a < R, b > 0, p > 0");
+    FH_ARG(!coef || (K >= 1 && K <= kMaxFourier), FH_ERR_INVALID_ARG, "K must be in [1, %d]", kMaxFourier);
+    FH_ARG(coef_mem == FH_MEM_HOST || coef_mem == FH_MEM_DEVICE, FH_ERR_INVALID_ARG, "bad memspace");
+    if (Atab)
+        for (int l = 0; l < m; ++l)
+            FH_ARG(std::isfinite(Atab[l]), FH_ERR_NONFINITE, "apodisation value %d not finite", l);
+    FH_HIP(hipSetDevice(c->device));
+    const double* glm = nullptr;
+    const double* gln = nullptr;
+    const double* glmd = nullptr;
+    FH_TRY(gl_table(c, m, &glm));
+    FH_TRY(gl_table(c, np, &gln));
+    FH_TRY(gl_table(c, md, &glmd));
+    const int64_t Nd = (int64_t)nd * md;
+    const int64_t N = Nd + (int64_t)Np * np * m;
+    fh_quad* qd = nullptr;
+    FH_TRY(quad_alloc(c, N, &qd));
+    const size_t ncoef = coef ? (size_t)2 * Np * K : 0;
+    fh_status s = arena_reserve(c, aligned_bytes(sizeof(double) * std::max<size_t>(ncoef, 1)) +
+                                       aligned_bytes(sizeof(double) * (Atab ? (size_t)m : 1)));
+    if (s != FH_OK) {
+        fh_quad_destroy(qd);
+        return s;
+    }
+    const double* dcoef = coef;
+    if (coef && coef_mem == FH_MEM_HOST) {
+        double* dc = c->arena.take<double>(ncoef);
+        FH_HIP(hipMemcpyAsync(dc, coef, sizeof(double) * ncoef, hipMemcpyHostToDevice, c->stream));
+        dcoef = dc;
+    }
+    const double* dA = nullptr;
+    if (Atab) {
+        double* da = c->arena.take<double>((size_t)m);
+        FH_HIP(hipMemcpyAsync(da, Atab, sizeof(double) * m, hipMemcpyHostToDevice, c->stream));
+        dA = da;
+    }
+    if (nd > 0) {
+        // disc of radius a: trapezoid boundary rule (eq. ptr) + dilation
+        RadialParams rp{};
+        rp.r0 = a;
+        rp.K = 0;
+        rp.panels = 0;
+        rp.q = nd;
+        hipLaunchKernelGGL(k_radial_rule, dim3(nblocks(Nd, 256)), dim3(256), 0, c->stream, rp,
+                           (const double*)nullptr, (int64_t)nd, md, glmd, qd->x, qd->y, qd->w);
+    }
+    PetalParams pp{Np, m, np, coef ? K : 0, a, R, b, p, Nd};
+    hipLaunchKernelGGL(k_petals, dim3(nblocks((int64_t)Np * np * m, 256)), dim3(256), 0, c->stream, pp, glm, gln,
+                       dcoef, dA, qd->x, qd->y, qd->w);
+    FH_HIP(hipGetLastError());
+    // host inputs may be released by the caller on return
+    if ((coef && coef_mem == FH_MEM_HOST) || Atab) FH_HIP(hipStreamSynchronize(c->stream));
+    // every node radius is at most R (edge perturbations move angles only)
+    set_bbox(qd, -R, R, -R, R);
+    *out = qd;
+    return FH_OK;
+}
+
+}  // namespace
+}  // namespace fh
+
 using namespace fh;
 
 extern "C" {
@@ -804,63 +882,26 @@ fh_status fh_quad_from_boundary(fh_ctx* c, const double* X, const double* Y, con
     }
 }
 
+
 fh_status fh_quad_starshade(fh_ctx* c, int32_t Np, double a, double R, double b, double p, int32_t m,
                             int32_t np, int32_t nd, int32_t md, const double* coef, int32_t K,
                             fh_memspace coef_mem, fh_quad** out)
 {
     try {
-        FH_ARG(c && out, FH_ERR_INVALID_ARG, "NULL argument");
-        *out = nullptr;
-        FH_ARG(Np >= 1 && m >= 1 && np >= 1 && nd >= 0 && md >= 1, FH_ERR_INVALID_ARG,
-               "need Np, m, np, md >= 1 and nd >= 0");
-        FH_ARG(std::isfinite(a) && std::isfinite(R) && std::isfinite(b) && std::isfinite(p),
-               FH_ERR_NONFINITE, "starshade scalar not finite");
-        FH_ARG(a >= 0 && R > a && b > 0 && p > 0, FH_ERR_INVALID_ARG, "need 0 <= a < R, b > 0, p > 0");
-        FH_ARG(!coef || (K >= 1 && K <= kMaxFourier), FH_ERR_INVALID_ARG, "K must be in [1, %d]",
-               kMaxFourier);
-        FH_ARG(coef_mem == FH_MEM_HOST || coef_mem == FH_MEM_DEVICE, FH_ERR_INVALID_ARG, "bad memspace");
-        FH_HIP(hipSetDevice(c->device));
-        const double* glm = nullptr;
-        const double* gln = nullptr;
-        const double* glmd = nullptr;
-        FH_TRY(gl_table(c, m, &glm));
-        FH_TRY(gl_table(c, np, &gln));
-        FH_TRY(gl_table(c, md, &glmd));
-        const int64_t Nd = (int64_t)nd * md;
-        const int64_t N = Nd + (int64_t)Np * np * m;
-        fh_quad* qd = nullptr;
-        FH_TRY(quad_alloc(c, N, &qd));
-        const size_t ncoef = coef ? (size_t)2 * Np * K : 0;
-        fh_status s = arena_reserve(c, aligned_bytes(sizeof(double) * std::max<size_t>(ncoef, 1)));
-        if (s != FH_OK) {
-            fh_quad_destroy(qd);
-            return s;
-        }
-        const double* dcoef = coef;
-        if (coef && coef_mem == FH_MEM_HOST) {
-            double* dc = c->arena.take<double>(ncoef);
-            FH_HIP(hipMemcpyAsync(dc, coef, sizeof(double) * ncoef, hipMemcpyHostToDevice, c->stream));
-            dcoef = dc;
-        }
-        if (nd > 0) {
-            // disc of radius a: trapezoid boundary rule (eq. ptr) + dilation
-            RadialParams rp{};
-            rp.r0 = a;
-            rp.K = 0;
-            rp.panels = 0;
-            rp.q = nd;
-            hipLaunchKernelGGL(k_radial_rule, dim3(nblocks(Nd, 256)), dim3(256), 0, c->stream, rp,
-                               (const double*)nullptr, (int64_t)nd, md, glmd, qd->x, qd->y, qd->w);
-        }
-        PetalParams pp{Np, m, np, coef ? K : 0, a, R, b, p, Nd};
-        hipLaunchKernelGGL(k_petals, dim3(nblocks((int64_t)Np * np * m, 256)), dim3(256), 0, c->stream,
-                           pp, glm, gln, dcoef, qd->x, qd->y, qd->w);
-        FH_HIP(hipGetLastError());
-        if (coef && coef_mem == FH_MEM_HOST) FH_HIP(hipStreamSynchronize(c->stream));
-        // every node radius is at most R (edge perturbations move angles only)
-        set_bbox(qd, -R, R, -R, R);
-        *out = qd;
-        return FH_OK;
+        return starshade_build(c, Np, a, R, b, p, nullptr, m, np, nd, md, coef, K, coef_mem, out);
+    } catch (...) {
+        set_error("host allocation failed");
+        return FH_ERR_ALLOC;
+    }
+}
+
+fh_status fh_quad_starshade_tab(fh_ctx* c, int32_t Np, double a, double R, const double* A, int32_t m,
+                                int32_t np, int32_t nd, int32_t md, const double* coef, int32_t K,
+                                fh_memspace coef_mem, fh_quad** out)
+{
+    try {
+        FH_ARG(A, FH_ERR_INVALID_ARG, "NULL apodisation table");
+        return starshade_build(c, Np, a, R, 1.0, 1.0, A, m, np, nd, md, coef, K, coef_mem, out);
     } catch (...) {
         set_error("host allocation failed");
         return FH_ERR_ALLOC;
@@ -906,7 +947,7 @@ fh_status fh_quad_starshade_rigid(fh_ctx* c, int32_t Np, double a, double R, dou
         }
         PetalParams pp{Np, m, np, 0, a, R, b, p, Nd};
         hipLaunchKernelGGL(k_petals, dim3(nblocks(Npet, 256)), dim3(256), 0, c->stream, pp, glm, gln,
-                           (const double*)nullptr, qd->x, qd->y, qd->w);
+                           (const double*)nullptr, (const double*)nullptr, qd->x, qd->y, qd->w);
         rp.Np = Np;
         rp.np = np;
         rp.m = m;

@@ -1,7 +1,8 @@
-"""Starshade with misaligned rigid petals (sec. 5) on the GPU vs the CPU oracle.
+"""Starshade variants on the GPU vs the CPU oracle: misaligned rigid petals
+(sec. 5) and a tabulated apodisation (sec. 4.2's NI2-style designs).
 
-The device rule (fh_quad_starshade_rigid) node by node against the oracle's
-construction for random petal motions, and its type-1 and type-3 fields
+The device rules (fh_quad_starshade_rigid, fh_quad_starshade_tab) node by
+node against the oracle's constructions, and their type-1 and type-3 fields
 element by element against the oracle's direct sum.
 """
 import numpy as np
@@ -61,4 +62,36 @@ def test_rigid_petals_rule_and_fields(fh, prec):
     q.close()
     with pytest.raises(fh.FresnelError, match="FH_ERR_INVALID_ARG"):
         ctx.quad_starshade_rigid(65, *SHAPE[1:], np.zeros((65, 3)), 4, 2)
+    ctx.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_tabulated_apodisation(fh, prec):
+    print(f"tabulated apodisation {prec}", flush=True)
+    ctx = fh.Context(prec)
+    Np, a, R, b, p, m, np_, nd, md = SHAPE
+    xg, _ = oracle.gauss_legendre(m)
+    r = a + 0.5 * (R - a) * (1 + xg)
+    s = (r - a) / (R - a)
+    A = (1 - 3 * s ** 2 + 2 * s ** 3) * (1 + 0.05 * np.sin(9 * s))  # a rippled taper
+    coef = np.random.Generator(np.random.PCG64(9)).normal(0, 1e-3, 2 * Np * 3)
+    q = ctx.quad_starshade_tab(Np, a, R, A, m, np_, nd, md, coef, 3)
+    x, y, w = oracle.quad_starshade_tab(Np, a, R, A, m, np_, nd, md, coef, 3)
+    gx, gy, gw = (cpu(t) for t in q.export())
+    assert max(np.abs(gx - x).max(), np.abs(gy - y).max()) < 1e-13
+    assert np.abs(gw - w).max() < 1e-13 * np.abs(w).max()
+    lam, z = 5e-7, 3.7e7
+    n, h = 128, 4.8 / 128
+    u = cpu(ctx.field_grid(q, lam, z, n, n, h, h, occulter=True)).ravel()
+    xi, eta = oracle.grid_targets(n, n, h, h)
+    ref = oracle.fresnel_direct(x, y, w, lam, z, xi, eta, occulter=True)
+    assert relL2(1 - u, 1 - ref) < TOL[prec]
+    # the HG values at the nodes give the HG rule
+    q2 = ctx.quad_starshade_tab(Np, a, R, np.exp(-((r - a) / b) ** p), m, np_, nd, md)
+    q3 = ctx.quad_starshade(Np, a, R, b, p, m, np_, nd, md)
+    w2, w3 = cpu(q2.export()[2]), cpu(q3.export()[2])
+    assert np.abs(w2 - w3).max() < 1e-13 * np.abs(w3).max()
+    with pytest.raises(fh.FresnelError, match="FH_ERR_NONFINITE"):
+        ctx.quad_starshade_tab(Np, a, R, np.full(m, np.nan), m, np_, nd, md)
+    q.close(); q2.close(); q3.close()
     ctx.close()
