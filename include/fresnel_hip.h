@@ -267,6 +267,14 @@ fh_status fh_field_points(fh_ctx* ctx, const fh_quad* q, double lambda, double z
  *   as for rules). */
 fh_status fh_targets_create(fh_ctx* ctx, int64_t M, const double* xi, const double* eta,
                             const double* box, fh_memspace mem, fh_targets** out);
+/* Evaluate the set's targets in spatial (Morton) order within its box from
+ * now on, for cache locality on large type-3 grids; fh_field_targets still
+ * writes u in the order the targets were given.  Enqueues the sort on the
+ * making context's stream (no synchronisation) and keeps a sorted copy in
+ * library memory, so the caller's device arrays are no longer read after
+ * the call's work has run.  A one-time cost for sets evaluated many times;
+ * M < 2, or a sorted set, is a no-op. */
+fh_status fh_targets_sort(fh_targets* t);
 fh_status fh_targets_size(const fh_targets* t, int64_t* M);
 /* The planning box (declared or computed), 4 doubles. */
 fh_status fh_targets_box(const fh_targets* t, double* box);

@@ -68,6 +68,11 @@ class Targets:
     def box(self):
         return abi.fh_targets_box(self.handle)
 
+    def sort(self):
+        """Evaluate in spatial order from now on (results keep the given order)."""
+        abi.fh_targets_sort(self.handle)
+        return self
+
     def close(self):
         if self.handle is not None and self.ctx.handle is not None:
             abi.fh_targets_destroy(self.handle)

@@ -39,7 +39,7 @@ EXPORTED = [
     "fh_starshade_vjp", "fh_autotune_grid", "fh_set_timing", "fh_last_timing", "fh_timing_totals",
     "fh_boundary_radial", "fh_boundary_polygon", "fh_boundary_starshade", "fh_field_nsli",
     "fh_quad_fourier", "fh_boundary_fourier", "fh_quad_koch", "fh_quad_starshade_rigid",
-    "fh_quad_starshade_tab",
+    "fh_quad_starshade_tab", "fh_targets_sort",
 ]
 
 
@@ -89,6 +89,7 @@ def lib():
             "fh_field_points": [vp, vp, d, d, i64, vp, vp, i32, vp, ctypes.c_int],
             "fh_targets_create": [vp, i64, vp, vp, ctypes.POINTER(d), ctypes.c_int, pvp],
             "fh_targets_size": [vp, ctypes.POINTER(i64)],
+            "fh_targets_sort": [vp],
             "fh_targets_box": [vp, ctypes.POINTER(d)],
             "fh_targets_destroy": [vp],
             "fh_field_targets": [vp, vp, d, d, vp, i32, vp, ctypes.c_int],
@@ -401,6 +402,10 @@ def fh_targets_create(ctx, xi, eta, box=None):
     h = ctypes.c_void_p()
     _check(lib().fh_targets_create(ctx, len(xi), _ptr_mem(xi)[0], _ptr_mem(eta)[0], bx, mem, ctypes.byref(h)))
     return h
+
+
+def fh_targets_sort(t):
+    _check(lib().fh_targets_sort(t))
 
 
 def fh_targets_size(t) -> int:

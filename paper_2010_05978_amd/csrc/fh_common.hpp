@@ -221,10 +221,11 @@ struct fh_quad {
 struct fh_targets {
     fh_ctx* ctx = nullptr;
     int64_t M = 0;
-    void* buf = nullptr;  // library copy (host input): xs[M], ys[M]
+    void* buf = nullptr;  // library copy (host input, or sorted): xs[M], ys[M] (and perm[M] if sorted)
     size_t buf_bytes = 0;
     const double* xs = nullptr;
     const double* ys = nullptr;
+    const int* perm = nullptr;     // after fh_targets_sort: caller index of each (sorted) target
     double box[4] = {0, 0, 0, 0};  // xmin, xmax, ymin, ymax
 };
 

@@ -25,6 +25,8 @@
 // pass and the epilogue work on those columns only.
 #include "fh_kernels.hpp"
 
+#include <hipcub/device/device_radix_sort.hpp>
+
 namespace fh {
 
 // Sequences per workgroup for an LDS FFT of length n over `count`
@@ -322,7 +324,7 @@ fh_status field_grid_impl(fh_ctx* c, const fh_quad* q, double lambda, double z, 
 template <class R>
 fh_status t3_core(fh_ctx* c, const fh_quad* q, double lambda, double z, int64_t M, const double* xi,
                   const double* eta, const double* tb, int occ, R* dout, bool host,
-                  bool stage_out, R** staged)
+                  bool stage_out, R** staged, const int* perm = nullptr)
 {
     stage_out = stage_out || host;
     const size_t rs = sizeof(R);
@@ -450,7 +452,7 @@ fh_status t3_core(fh_ctx* c, const fh_quad* q, double lambda, double z, int64_t 
         FH_TRY(fft_exec(c, fp, up));
     }
     timing_mark(c, 3);
-    FH_TRY(launch_interp<R>(c, k.w, up, dxi, deta, M, k.beta, k.poly, tp, dout));
+    FH_TRY(launch_interp<R>(c, k.w, up, dxi, deta, M, k.beta, k.poly, tp, dout, perm));
     timing_mark(c, 4);
     timing_mark(c, 5);
     return FH_OK;
@@ -488,6 +490,33 @@ fh_status field_points_impl(fh_ctx* c, const fh_quad* q, double lambda, double z
     return FH_OK;
 }
 
+// Morton key of each target inside the set's box (16 bits per axis, clamped;
+// non-finite coordinates key to 0) and its index.
+__global__ void k_target_keys(const double* __restrict__ xs, const double* __restrict__ ys, int64_t M, double x0,
+                              double sx, double y0, double sy, uint32_t* __restrict__ keys, int* __restrict__ idx)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= M) return;
+    double fx = (xs[i] - x0) * sx, fy = (ys[i] - y0) * sy;
+    fx = fx >= 0.0 ? fmin(fx, 65535.0) : 0.0;  // also maps NaN to 0
+    fy = fy >= 0.0 ? fmin(fy, 65535.0) : 0.0;
+    uint32_t qx = (uint32_t)fx, qy = (uint32_t)fy, key = 0;
+    for (int b = 0; b < 16; ++b) key |= (((qx >> b) & 1u) << (2 * b)) | (((qy >> b) & 1u) << (2 * b + 1));
+    keys[i] = key;
+    idx[i] = (int)i;
+}
+
+__global__ void k_target_gather(const double* __restrict__ xs, const double* __restrict__ ys,
+                                const int* __restrict__ perm, int64_t M, double* __restrict__ ox,
+                                double* __restrict__ oy)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= M) return;
+    const int k = perm[i];
+    ox[i] = xs[k];
+    oy[i] = ys[k];
+}
+
 // Field at a target set; no host synchronisation unless the output is host
 // memory.
 template <class R>
@@ -498,9 +527,9 @@ fh_status field_targets_impl(fh_ctx* c, const fh_quad* q, double lambda, double 
     if (M == 0) return FH_OK;
     if (mem == FH_MEM_DEVICE)
         return t3_core<R>(c, q, lambda, z, M, t->xs, t->ys, t->box, occ, static_cast<R*>(u), false,
-                          false, nullptr);
+                          false, nullptr, t->perm);
     R* staged = nullptr;
-    FH_TRY(t3_core<R>(c, q, lambda, z, M, t->xs, t->ys, t->box, occ, nullptr, false, true, &staged));
+    FH_TRY(t3_core<R>(c, q, lambda, z, M, t->xs, t->ys, t->box, occ, nullptr, false, true, &staged, t->perm));
     FH_HIP(hipMemcpyAsync(u, staged, 2 * sizeof(R) * M, hipMemcpyDeviceToHost, c->stream));
     FH_HIP(hipStreamSynchronize(c->stream));
     return FH_OK;
@@ -728,6 +757,67 @@ fh_status fh_targets_box(const fh_targets* t, double* box)
     FH_ARG(t && box, FH_ERR_INVALID_ARG, "NULL argument");
     for (int i = 0; i < 4; ++i) box[i] = t->box[i];
     return FH_OK;
+}
+
+fh_status fh_targets_sort(fh_targets* t)
+{
+    try {
+        FH_ARG(t, FH_ERR_INVALID_ARG, "NULL target set");
+        const int64_t M = t->M;
+        if (M < 2 || t->perm) return FH_OK;
+        fh_ctx* c = t->ctx;
+        FH_HIP(hipSetDevice(c->device));
+        const double* box = t->box;
+        const double sx = box[1] > box[0] ? 65535.0 / (box[1] - box[0]) : 0.0;
+        const double sy = box[3] > box[2] ? 65535.0 / (box[3] - box[2]) : 0.0;
+        // the sorted copy and the permutation live in one library buffer
+        const size_t cb = aligned_bytes(sizeof(double) * (size_t)M);
+        const size_t pb = aligned_bytes(sizeof(int) * (size_t)M);
+        const size_t bytes = 2 * cb + pb;
+        void* nb = nullptr;
+        auto it = c->pool.find(bytes);
+        if (it != c->pool.end() && !it->second.empty()) {
+            nb = it->second.back();
+            it->second.pop_back();
+        } else {
+            FH_TRY(dev_alloc(c, bytes, &nb));
+        }
+        double* ox = static_cast<double*>(nb);
+        double* oy = reinterpret_cast<double*>(static_cast<char*>(nb) + cb);
+        int* perm = reinterpret_cast<int*>(static_cast<char*>(nb) + 2 * cb);
+        size_t temp = 0;
+        FH_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, temp, (const uint32_t*)nullptr, (uint32_t*)nullptr,
+                                                  (const int*)nullptr, (int*)nullptr, (int)M, 0, 32, c->stream));
+        const size_t kb = aligned_bytes(sizeof(uint32_t) * (size_t)M);
+        fh_status s = arena_reserve(c, 2 * kb + pb + aligned_bytes(std::max<size_t>(temp, 1)));
+        if (s != FH_OK) {
+            c->pool[bytes].push_back(nb);
+            return s;
+        }
+        uint32_t* kin = c->arena.take<uint32_t>((size_t)M);
+        uint32_t* kout = c->arena.take<uint32_t>((size_t)M);
+        int* iin = c->arena.take<int>((size_t)M);
+        void* tmp = c->arena.take<char>(std::max<size_t>(temp, 1));
+        hipLaunchKernelGGL(k_target_keys, dim3(nblocks(M, 256)), dim3(256), 0, c->stream, t->xs, t->ys, M, box[0],
+                           sx, box[2], sy, kin, iin);
+        FH_HIP(hipGetLastError());
+        FH_HIP(hipcub::DeviceRadixSort::SortPairs(tmp, temp, kin, kout, iin, perm, (int)M, 0, 32, c->stream));
+        hipLaunchKernelGGL(k_target_gather, dim3(nblocks(M, 256)), dim3(256), 0, c->stream, t->xs, t->ys, perm, M,
+                           ox, oy);
+        FH_HIP(hipGetLastError());
+        // a previous library copy goes back to the pool (stream order keeps
+        // the gather above before any reuse)
+        if (t->buf) c->pool[t->buf_bytes].push_back(t->buf);
+        t->buf = nb;
+        t->buf_bytes = bytes;
+        t->xs = ox;
+        t->ys = oy;
+        t->perm = perm;
+        return FH_OK;
+    } catch (...) {
+        set_error("host allocation failed");
+        return FH_ERR_ALLOC;
+    }
 }
 
 fh_status fh_targets_destroy(fh_targets* t)

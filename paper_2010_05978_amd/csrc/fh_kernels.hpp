@@ -1332,7 +1332,7 @@ template <class R, int W>
 __global__ void __launch_bounds__(64) k_t3_interp(const R* __restrict__ G, const double* __restrict__ xi,
                                                   const double* __restrict__ eta, int64_t M, R beta,
                                                   const R* __restrict__ poly, T3Params tp, int tpw,
-                                                  R* __restrict__ u)
+                                                  R* __restrict__ u, const int* __restrict__ perm)
 {
     using C = typename V2<R>::T;
     constexpr int GS = interp_group<W>();
@@ -1425,8 +1425,10 @@ __global__ void __launch_bounds__(64) k_t3_interp(const R* __restrict__ G, const
                 re = 1.0 - re;
                 im = -im;
             }
-            u[2 * k] = (R)re;
-            u[2 * k + 1] = (R)im;
+            // a sorted target set writes back to the caller's order
+            const int64_t ko = perm ? (int64_t)perm[k] : k;
+            u[2 * ko] = (R)re;
+            u[2 * ko + 1] = (R)im;
         }
         wave_lds_order();
     }
@@ -1570,7 +1572,7 @@ fh_status launch_spread(fh_ctx* c, unsigned grid, const Sub* subs, const int* ns
 // gather trips over many wavefronts.
 template <class R>
 fh_status launch_interp(fh_ctx* c, int W, const R* G, const double* xi, const double* eta, int64_t M,
-                        double beta, const void* poly, const T3Params& tp, R* u)
+                        double beta, const void* poly, const T3Params& tp, R* u, const int* perm)
 {
     const int per_trip = W <= 8 ? 8 : (W <= 16 ? 4 : 2);
     int tpw = 64;
@@ -1579,7 +1581,7 @@ fh_status launch_interp(fh_ctx* c, int W, const R* G, const double* xi, const do
 #define FH_INTERP_CASE(w)                                                                           \
     case w:                                                                                        \
         hipLaunchKernelGGL((k_t3_interp<R, w>), dim3(std::min<int64_t>(nblocks(M, tpw), 1 << 20)), dim3(64), 0, \
-                           c->stream, G, xi, eta, M, (R)beta, (const R*)poly, tp, tpw, u);     \
+                           c->stream, G, xi, eta, M, (R)beta, (const R*)poly, tp, tpw, u, perm); \
         break;
         FH_INTERP_CASE(2) FH_INTERP_CASE(3) FH_INTERP_CASE(4) FH_INTERP_CASE(5) FH_INTERP_CASE(6)
         FH_INTERP_CASE(7) FH_INTERP_CASE(8) FH_INTERP_CASE(9) FH_INTERP_CASE(10) FH_INTERP_CASE(11)

@@ -210,3 +210,44 @@ def test_pipelined_contexts_with_order_after(fh, ctx):
         assert relL2(cpu(ug).ravel()[idx], refg) <= TOL[ctx.precision]
     finally:
         other.close()
+
+
+def test_sorted_target_sets(ctx):
+    # fh_targets_sort: evaluation in spatial order, results in the caller's order
+    print(f"sorted target sets {ctx.precision}", flush=True)
+    wl = workloads.workload(2)
+    q = ctx.quad_for(wl.shape)
+    g = np.random.Generator(np.random.PCG64(321))
+    M = 20011
+    xi, eta = g.uniform(-1.5, 1.5, M), g.uniform(-1.5, 1.5, M)
+    xi[7], eta[7] = 2.5, 0.0        # outside the declared box: NaN
+    xi[8] = np.nan                  # non-finite: NaN
+    dxi, deta = torch.tensor(xi, device="cuda"), torch.tensor(eta, device="cuda")
+    box = (-1.5, 1.5, -1.5, 1.5)
+    plain = cpu(ctx.field_targets(q, wl.lam, wl.z, ctx.targets(dxi, deta, box=box)))
+    tg = ctx.targets(dxi, deta, box=box).sort()
+    tg.sort()  # a second sort is a no-op
+    u = cpu(ctx.field_targets(q, wl.lam, wl.z, tg))
+    ok = np.ones(M, bool)
+    ok[[7, 8]] = False
+    assert np.isnan(u[~ok]).all() and np.isfinite(u[ok]).all()
+    assert relL2(u[ok], plain[ok]) < (1e-14 if ctx.precision == "fp64" else 1e-6)
+    idx = np.random.Generator(np.random.PCG64(5)).choice(np.flatnonzero(ok), 1500, replace=False)
+    x, y, w = rule(wl.shape)
+    ref = oracle.fresnel_direct(x, y, w, wl.lam, wl.z, xi[idx], eta[idx])
+    assert relL2(u[idx], ref) < TOL[ctx.precision]
+    # the sorted set keeps its own copy: the caller's arrays may change
+    dxi.fill_(0.0)
+    u2 = cpu(ctx.field_targets(q, wl.lam, wl.z, tg, occulter=True))
+    assert relL2(1 - u2[ok], u[ok]) < (1e-14 if ctx.precision == "fp64" else 1e-6)
+    tg.close()
+    # host arrays, and tiny sets
+    th = ctx.targets(xi[:1000].copy(), eta[:1000].copy(), box=box).sort()
+    uh = cpu(ctx.field_targets(q, wl.lam, wl.z, th))
+    fin = np.isfinite(plain[:1000])
+    assert relL2(uh[fin], plain[:1000][fin]) < (1e-14 if ctx.precision == "fp64" else 1e-6)
+    th.close()
+    t1 = ctx.targets(dxi[:1], deta[:1], box=box).sort()
+    assert t1.M == 1
+    t1.close()
+    q.close()
