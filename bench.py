@@ -142,6 +142,16 @@ def time_steps(step, steps, warmup):
     return dt, [v / max(ngrid, 1) for v in grid_ms], [v / max(npts, 1) for v in pts_ms]
 
 
+def spread_waves(W, rs, T=16):
+    """Wavefronts per spread work item at tile T: two when their two tiles
+    (one spare cell each), the staging of 64 points and the kernel
+    coefficients fit in 64 KiB of LDS."""
+    L = T + W - 1
+    tile = 2 * rs * (L * L + 1)
+    staging = rs * (64 * (2 * W + 2) + ((W + 4) * W + 1) // 2 * 2)
+    return 2 if 2 * tile + staging <= 64 * 1024 else 1
+
+
 def roofline(res, prec, wl):
     """Roofline of the kernel with the most device time per step.
 
@@ -157,7 +167,8 @@ def roofline(res, prec, wl):
     g, pt = r["grid_stage_ms"], r["points_stage_ms"]
     cands = {
         # spread: 2 W^2 LDS atomic adds of one real each per node
-        "spread": {"kernel": f"k_spread_wave<{'double' if rs == 8 else 'float'}, {W}, false>", "ms": (g[1] + pt[1]) / 2,
+        "spread": {"kernel": f"k_spread_wave<{'double' if rs == 8 else 'float'}, {W}, false, {spread_waves(W, rs)}>",
+                   "ms": (g[1] + pt[1]) / 2,
                    "launches": 2, "bound": "alu", "unit": "GB/s", "peak": LDS_PEAK_GBS,
                    "bytes": N * W * W * 2 * rs},
         # type-1 column pass + epilogue: at least one complex output written per

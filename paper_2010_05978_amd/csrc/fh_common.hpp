@@ -70,12 +70,12 @@ struct EsKernel {
 constexpr int kPolyExtra = 4;
 
 // Wavefront spread staging: per point its 2w kernel values and its strength
-// (2 reals), for 64 points plus one trip of padding so a trip of points
-// never needs a clamped index.
-inline int spread_trip(size_t rsize) { return rsize == 8 ? 4 : 8; }
+// (2 reals), for 64 points, and the (w + kPolyExtra) x w coefficients of the
+// kernel's piecewise polynomial (rounded up to whole complex cells).
 inline size_t spread_staging_bytes(int w, size_t rsize)
 {
-    return rsize * (size_t)(64 + spread_trip(rsize)) * (2 * (size_t)w + 2);
+    const size_t npw = ((size_t)w + kPolyExtra) * (size_t)w;
+    return rsize * ((size_t)64 * (2 * (size_t)w + 2) + (npw + 1) / 2 * 2);
 }
 
 // 1/Phi(theta) for |theta| <= theta_max as a Chebyshev series in

@@ -122,6 +122,35 @@ __device__ __forceinline__ void es_weights(R d, R beta, const R* __restrict__ po
     }
 }
 
+// es_weights with the coefficient table in LDS: the reads of coefficient
+// row j + 1 are issued before the multiply-adds of row j (the scheduling
+// barriers keep them there), so each read's latency is covered by a row of
+// arithmetic instead of stalling every second multiply-add.
+template <class R, int W>
+__device__ __forceinline__ void es_weights_lds(R d, const R* pl, R* k)
+{
+    constexpr int NP = W + kPolyExtra;
+    const R t = R(2) * d + R(W - 1);
+    R c[W], n[W];
+#pragma unroll
+    for (int a = 0; a < W; ++a) k[a] = pl[a];
+#pragma unroll
+    for (int a = 0; a < W; ++a) c[a] = pl[W + a];
+#pragma unroll
+    for (int j = 1; j < NP; ++j) {
+        if (j + 1 < NP) {
+#pragma unroll
+            for (int a = 0; a < W; ++a) n[a] = pl[(j + 1) * W + a];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int a = 0; a < W; ++a) k[a] = k[a] * t + c[a];
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int a = 0; a < W; ++a) c[a] = n[a];
+    }
+}
+
 // One kernel value phi((d + a) 2/W) (a may vary across lanes).
 template <class R, int W>
 __device__ __forceinline__ R es_one(R d, int a, R beta, const R* __restrict__ poly)
@@ -511,35 +540,6 @@ __global__ void __launch_bounds__(256) k_spread_thread(const Sub* __restrict__ s
     }
 }
 
-// Add a run's register sums (lane (a, b) of pass pp holds stencil cell
-// (a, b) of the run's first cell c) into the wavefront's own LDS tile and
-// clear them.  The cells of one flush are distinct and the LDS operations of
-// one wavefront complete in issue order, so either a plain read-add-write
-// (waits for the read) or non-returning LDS atomics (no wait, processed in
-// order) give the same, deterministic sums.
-template <class R, int NPASS, bool ATOMIC>
-__device__ __forceinline__ void flush_run(typename V2<R>::T* tile, int c, const int* po, const bool* pv, R* accr,
-                                          R* acci)
-{
-    if (c < 0) return;
-#pragma unroll
-    for (int pp = 0; pp < NPASS; ++pp) {
-        if (pv[pp]) {
-            typename V2<R>::T* e = tile + c + po[pp];
-            if constexpr (ATOMIC) {
-                // no return value: the wavefront does not wait for the LDS
-                atomicAdd(&e->x, accr[pp]);
-                atomicAdd(&e->y, acci[pp]);
-            } else {
-                typename V2<R>::T v = *e;
-                v.x += accr[pp];
-                v.y += acci[pp];
-                *e = v;
-            }
-        }
-    }
-}
-
 // LDS order point: keeps the compiler from moving LDS accesses of this
 // wavefront across it (the hardware already completes them in order).
 __device__ __forceinline__ void wave_lds_order()
@@ -549,117 +549,223 @@ __device__ __forceinline__ void wave_lds_order()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Wavefront per work item, lanes over the stencil.  The wavefront owns its
-// LDS tile (no sharing: LDS float atomics serialise badly when points
-// cluster), loads 64 points at a time and stages their 2W kernel values and
-// strength in LDS, then walks the points one by one with lane (a, b) holding
-// stencil cell (a, b) (ceil(W^2/64) passes).  Consecutive points with the
-// same first cell (nodes in spoke order share one for tens of points near
-// the origin) are summed in registers and added to the tile once.  With few
-// wavefronts per SIMD every instruction of the point loop costs its issue
-// slot, so the loop is kept to the arithmetic, one lane read for the cell
-// and LDS reads at fixed offsets.  The summation order is fixed, so the
-// spread is deterministic.
-template <class R, int W, bool ATOMIC>
-__global__ void __launch_bounds__(64) k_spread_wave(const Sub* __restrict__ subs, const int* __restrict__ nsub_ptr,
-                                                    const uint32_t* __restrict__ cell,
-                                                    const typename V2<R>::T* __restrict__ dd,
-                                                    const typename V2<R>::T* __restrict__ cc,
-                                                    typename V2<R>::T* __restrict__ slots, GridGeom gg, int tpi,
-                                                    R beta, const R* __restrict__ poly)
+// NV (1 or 2) wavefronts per work item, lanes over the stencil.  Each
+// wavefront owns an LDS tile (no sharing: LDS float atomics serialise badly
+// when points cluster).  The block loads 64 points at a time and stages their
+// 2W kernel values and strength in LDS (with two wavefronts, one evaluates
+// the kernel along x and the other along y), then wavefront v walks its
+// share of the 64 (a contiguous half when NV = 2) one point at a time with
+// lane (a, b) holding stencil cell (a, b) (ceil(W^2/64) passes).  Consecutive
+// points with the same first cell form a run (nodes in spoke order share one
+// for tens of points near the origin), summed in registers and added to the
+// tile once.  The tile values under a run are read when the run starts and
+// the sums written back when it ends, so the read's latency is covered by
+// the run's own points rather than stalling the wavefront; the LDS
+// operations of one wavefront complete in issue order, so a run's read sees
+// the previous run's write.  Lanes past W^2 in the last pass read and write a
+// spare cell after the tile instead of branching (each lane's cell address
+// is one multiply-add from the run's cell), the staged values of a
+// trip of points are all read before the first is added, and points past
+// the end of the item are staged as zeros, so the only branch per point is
+// the (wavefront-uniform) start of a run.  The slot receives the sum of the
+// NV tiles in wavefront order.  The summation order is fixed, so the spread
+// is deterministic.  ATOMIC adds each run with non-returning LDS atomics
+// instead of the read and write.
+template <class R, int W, bool ATOMIC, int NV>
+__global__ void __launch_bounds__(64 * NV) k_spread_wave(const Sub* __restrict__ subs,
+                                                         const int* __restrict__ nsub_ptr,
+                                                         const uint32_t* __restrict__ cell,
+                                                         const typename V2<R>::T* __restrict__ dd,
+                                                         const typename V2<R>::T* __restrict__ cc,
+                                                         typename V2<R>::T* __restrict__ slots, GridGeom gg,
+                                                         int tpi, R beta, const R* __restrict__ poly)
 {
+    static_assert(NV == 1 || NV == 2, "one or two wavefronts per work item");
     using C = typename V2<R>::T;
     constexpr int KS = 2 * W + 2;             // staged reals per point
     constexpr int NPASS = (W * W + 63) / 64;  // stencil passes per point
-    constexpr int U = sizeof(R) == 8 ? 4 : 8; // points per trip (spread_trip)
+    constexpr int U = sizeof(R) == 8 ? 4 : 8; // points per trip
+    constexpr int QW = 64 / NV;               // points of a batch per wavefront
+    constexpr int NPW = (W + kPolyExtra) * W;  // kernel polynomial coefficients
     extern __shared__ unsigned char smem_raw[];
     const int L = gg.L, LL = L * L;
-    C* tile = reinterpret_cast<C*>(smem_raw);
-    R* kb = reinterpret_cast<R*>(tile + LL);
-    const int lane = threadIdx.x;
-    int pa[NPASS], pb[NPASS], po[NPASS];
-    bool pv[NPASS];
+    // the wavefront index, marked wavefront-uniform for the compiler (the
+    // share bounds and run starts derived from it stay scalar)
+    const int wv = NV == 1 ? 0 : __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int lane = threadIdx.x & 63;
+    // LDS: the kernel coefficients first (at a fixed address, so that every
+    // coefficient read takes an immediate offset), then NV tiles of LL cells
+    // and a spare cell each, then the staging of 64 points
+    constexpr int NPWC = (NPW * (int)sizeof(R) + (int)sizeof(C) - 1) / (int)sizeof(C);
+    R* pl = reinterpret_cast<R*>(smem_raw);
+    C* tiles = reinterpret_cast<C*>(smem_raw) + NPWC;
+    C* tile = tiles + wv * (LL + 1);
+    R* kb = reinterpret_cast<R*>(tiles + NV * (LL + 1));
+    // the block's first work item is loaded without waiting for the item
+    // count (the grid never exceeds the item capacity), and the coefficient
+    // table is copied to LDS meanwhile: a wavefront evaluating the kernel
+    // then reads each coefficient with an LDS broadcast instead of a chain
+    // of dependent scalar loads
+    const Sub first = subs[blockIdx.x];
+    const bool has_poly = poly != nullptr;
+    if (has_poly) {
+#pragma unroll
+        for (int i = threadIdx.x; i < NPW; i += 64 * NV) pl[i] = poly[i];
+    }
+    __syncthreads();
+    // lane (a, b) of pass p: its kernel values, and the LDS byte offset of
+    // its cell for a run at tile cell c, tb[p] + tm[p] c (lanes past W^2:
+    // the spare cell whatever c)
+    int pa[NPASS], pb[NPASS];
+    uint32_t tb[NPASS], tm[NPASS];
 #pragma unroll
     for (int p = 0; p < NPASS; ++p) {
         const int e = lane + 64 * p;
-        pv[p] = e < W * W;
-        pa[p] = pv[p] ? e % W : 0;
-        pb[p] = pv[p] ? e / W : 0;
-        po[p] = pb[p] * L + pa[p];
+        const bool valid = e < W * W;
+        pa[p] = valid ? e % W : 0;
+        pb[p] = valid ? e / W : 0;
+        const C* cp = tile + (valid ? pb[p] * L + pa[p] : LL);
+        tb[p] = (uint32_t)(reinterpret_cast<const unsigned char*>(cp) - smem_raw);
+        tm[p] = valid ? (uint32_t)sizeof(C) : 0u;
     }
     const int nsub = *nsub_ptr;
     for (int s = blockIdx.x; s < nsub; s += gridDim.x) {
-        const Sub sb = subs[s];
+        const Sub sb = s == (int)blockIdx.x ? first : subs[s];
         int ox, oy;
         tile_origin<R>(sb, gg, tpi, ox, oy);
         const uint32_t org = (uint32_t)ox | ((uint32_t)oy << 16);
         for (int e = lane; e < LL; e += 64) tile[e] = C{R(0), R(0)};
-        int cur = -1;
+        // the run before the first point: cell 0 with zero sums (its write
+        // stores zeros over zeros)
+        int cur = 0;
         R accr[NPASS], acci[NPASS];
+        C bs[NPASS];  // tile values under the current run
 #pragma unroll
-        for (int pp = 0; pp < NPASS; ++pp) accr[pp] = acci[pp] = R(0);
+        for (int pp = 0; pp < NPASS; ++pp) {
+            accr[pp] = acci[pp] = R(0);
+            bs[pp] = C{R(0), R(0)};
+        }
         for (int base = sb.start; base < sb.end; base += 64) {
             const int p = base + lane;
             int cl = 0;
+            R* kp = kb + lane * KS;
             if (p < sb.end) {
                 // tile-relative first cell as an LDS index (x, y < T)
                 const uint32_t rel = cell[p] - org;
                 cl = (int)(rel >> 16) * L + (int)(rel & 0xffffu);
                 const C dv = dd[p];
-                const C cv = cc[p];
-                R k[W];
-                es_weights<R, W>(dv.x, beta, poly, k);
+                // the strength is loaded with the offsets, not after the
+                // kernel values (its latency would add to theirs)
+                const C cv = wv == NV - 1 ? cc[p] : C{R(0), R(0)};
 #pragma unroll
-                for (int a = 0; a < W; ++a) kb[lane * KS + a] = k[a];
-                es_weights<R, W>(dv.y, beta, poly, k);
+                for (int d = 0; d < 2; ++d) {
+                    if (NV == 2 && d != wv) continue;
+                    R k[W];
+                    if (has_poly)
+                        es_weights_lds<R, W>(d == 0 ? dv.x : dv.y, pl, k);
+                    else
+                        es_weights<R, W>(d == 0 ? dv.x : dv.y, beta, nullptr, k);
 #pragma unroll
-                for (int b = 0; b < W; ++b) kb[lane * KS + W + b] = k[b];
-                kb[lane * KS + 2 * W] = cv.x;
-                kb[lane * KS + 2 * W + 1] = cv.y;
+                    for (int a = 0; a < W; ++a) kp[d * W + a] = k[a];
+                }
+                if (wv == NV - 1) {
+                    kp[2 * W] = cv.x;
+                    kp[2 * W + 1] = cv.y;
+                }
+            } else {
+                // points past the item: zeros (they add exact zeros)
+                constexpr int nz = NV == 1 ? KS : W;
+#pragma unroll
+                for (int a = 0; a < nz; ++a) kp[wv * W + a] = R(0);
+                if (NV == 2 && wv == 1) {
+                    kp[2 * W] = R(0);
+                    kp[2 * W + 1] = R(0);
+                }
             }
-            wave_lds_order();
+            __syncthreads();
             const int np = min(64, sb.end - base);
-            for (int q0 = 0; q0 < np; q0 += U) {
+            const int qs = wv * QW, qe = min(np, qs + QW);
+            for (int q0 = qs; q0 < qe; q0 += U) {
                 // all LDS reads of the trip first (fixed offsets from one base)
-                R kv[U][NPASS], vr[U], vi[U];
+                R ka[U][NPASS], kc[U][NPASS], vr[U], vi[U];
                 int cq[U];
                 const R* kt = kb + q0 * KS;
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
-                    cq[u] = lane_val(cl, (q0 + u) & 63);
+                    cq[u] = lane_val(cl, q0 + u);
                     const R* kq = kt + u * KS;
 #pragma unroll
-                    for (int pp = 0; pp < NPASS; ++pp) kv[u][pp] = kq[pa[pp]] * kq[W + pb[pp]];
+                    for (int pp = 0; pp < NPASS; ++pp) {
+                        ka[u][pp] = kq[pa[pp]];
+                        kc[u][pp] = kq[W + pb[pp]];
+                    }
                     vr[u] = kq[2 * W];
                     vi[u] = kq[2 * W + 1];
                 }
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
-                    if (q0 + u >= np) break;
-                    if (cq[u] != cur) {
-                        flush_run<R, NPASS, ATOMIC>(tile, cur, po, pv, accr, acci);
-                        cur = cq[u];
+                    // points of the trip past the wavefront's share add
+                    // zeros to the current run (they were staged as zeros)
+                    // or are never reached (a share is a whole number of
+                    // trips); neither starts a run
+                    const int c = q0 + u < qe ? cq[u] : cur;
+                    if (c != cur) {
+                        // the sums of the run that ends
 #pragma unroll
                         for (int pp = 0; pp < NPASS; ++pp) {
-                            accr[pp] = vr[u] * kv[u][pp];
-                            acci[pp] = vi[u] * kv[u][pp];
+                            C* e = reinterpret_cast<C*>(smem_raw + (tb[pp] + tm[pp] * (uint32_t)cur));
+                            if constexpr (ATOMIC) {
+                                // no return value: the wavefront does not wait for the LDS
+                                atomicAdd(&e->x, accr[pp]);
+                                atomicAdd(&e->y, acci[pp]);
+                            } else {
+                                *e = C{bs[pp].x + accr[pp], bs[pp].y + acci[pp]};
+                            }
+                            accr[pp] = acci[pp] = R(0);
                         }
-                    } else {
+                        // every pass's write precedes the new run's reads:
+                        // the two runs' stencils may overlap across passes
+                        if constexpr (!ATOMIC) {
 #pragma unroll
-                        for (int pp = 0; pp < NPASS; ++pp) {
-                            accr[pp] += vr[u] * kv[u][pp];
-                            acci[pp] += vi[u] * kv[u][pp];
+                            for (int pp = 0; pp < NPASS; ++pp)
+                                bs[pp] = *reinterpret_cast<const C*>(smem_raw + (tb[pp] + tm[pp] * (uint32_t)c));
                         }
+                        cur = c;
+                    }
+#pragma unroll
+                    for (int pp = 0; pp < NPASS; ++pp) {
+                        const R kv = ka[u][pp] * kc[u][pp];
+                        accr[pp] += vr[u] * kv;
+                        acci[pp] += vi[u] * kv;
                     }
                 }
             }
-            wave_lds_order();
+            // the next batch rewrites the staging
+            __syncthreads();
         }
-        flush_run<R, NPASS, ATOMIC>(tile, cur, po, pv, accr, acci);
-        wave_lds_order();
+#pragma unroll
+        for (int pp = 0; pp < NPASS; ++pp) {
+            C* e = reinterpret_cast<C*>(smem_raw + (tb[pp] + tm[pp] * (uint32_t)cur));
+            if constexpr (ATOMIC) {
+                atomicAdd(&e->x, accr[pp]);
+                atomicAdd(&e->y, acci[pp]);
+            } else {
+                *e = C{bs[pp].x + accr[pp], bs[pp].y + acci[pp]};
+            }
+        }
+        __syncthreads();
         C* slot = slots + (size_t)s * LL;
-        for (int e = lane; e < LL; e += 64) slot[e] = tile[e];
-        wave_lds_order();
+        for (int e = threadIdx.x; e < LL; e += 64 * NV) {
+            C v = tiles[e];
+            if constexpr (NV == 2) {
+                const C v1 = tiles[LL + 1 + e];
+                v.x += v1.x;
+                v.y += v1.y;
+            }
+            slot[e] = v;
+        }
+        // the tiles are cleared for the next item
+        __syncthreads();
     }
 }
 
@@ -1499,6 +1605,29 @@ __global__ void __launch_bounds__(256) k_bbox_final(const double* __restrict__ p
 }
 
 // ------------------------------------------------------- launch helpers
+// Wavefronts per work item of the wavefront spread: two when their two tiles
+// fit the LDS budget with the staging.
+inline int spread_waves(const GridGeom& gg, size_t rsize)
+{
+    const size_t tile = 2 * rsize * ((size_t)gg.L * gg.L + 1);
+    return 2 * tile + spread_staging_bytes(gg.W, rsize) <= kLdsBudget ? 2 : 1;
+}
+
+// LDS bytes of one spread block.
+inline size_t spread_lds(const GridGeom& gg, size_t rsize)
+{
+    if (gg.method == 4) {
+        // staging of 32 points (W + KYP + 2 reals and 2 ints each) and the 4
+        // wavefront tiles (see RegTile and reg_spread_lds)
+        const int L = gg.L, NB = 64 / L, RB = (L + NB - 1) / NB;
+        const size_t kyp = (size_t)(gg.T - 1 + NB * RB);
+        return 32 * (rsize * ((size_t)gg.W + kyp + 2) + 2 * sizeof(int)) + 2 * rsize * 4 * (size_t)L * L;
+    }
+    const size_t tile = 2 * rsize * (size_t)gg.L * gg.L;
+    if (gg.method == 1) return tile;
+    return (size_t)spread_waves(gg, rsize) * (tile + 2 * rsize) + spread_staging_bytes(gg.W, rsize);
+}
+
 template <class R, int W>
 void launch_spread_w(fh_ctx* c, unsigned grid, const Sub* subs, const int* nsub, const uint32_t* cell,
                      const void* dd, const void* cc, typename V2<R>::T* slots, const GridGeom& gg, int tpi,
@@ -1522,27 +1651,26 @@ void launch_spread_w(fh_ctx* c, unsigned grid, const Sub* subs, const int* nsub,
                                (const R*)poly);
         return;
     }
-    const size_t staging = spread_staging_bytes(W, sizeof(R));
-    if (gg.method == 3)
-        hipLaunchKernelGGL((k_spread_wave<R, W, true>), dim3(grid), dim3(64), tile + staging, c->stream, subs, nsub,
-                           cell, (const C2*)dd, (const C2*)cc, slots, gg, tpi, (R)beta, (const R*)poly);
-    else
-        hipLaunchKernelGGL((k_spread_wave<R, W, false>), dim3(grid), dim3(64), tile + staging, c->stream, subs, nsub,
-                           cell, (const C2*)dd, (const C2*)cc, slots, gg, tpi, (R)beta, (const R*)poly);
-}
-
-// LDS bytes of one spread block.
-inline size_t spread_lds(const GridGeom& gg, size_t rsize)
-{
-    if (gg.method == 4) {
-        // staging of 32 points (W + KYP + 2 reals and 2 ints each) and the 4
-        // wavefront tiles (see RegTile and reg_spread_lds)
-        const int L = gg.L, NB = 64 / L, RB = (L + NB - 1) / NB;
-        const size_t kyp = (size_t)(gg.T - 1 + NB * RB);
-        return 32 * (rsize * ((size_t)gg.W + kyp + 2) + 2 * sizeof(int)) + 2 * rsize * 4 * (size_t)L * L;
+    // the tiles with their spare cells, the point staging and the kernel
+    // coefficients (spread_lds)
+    const int nv = spread_waves(gg, sizeof(R));
+    const size_t lds = spread_lds(gg, sizeof(R));
+    const bool at = gg.method == 3;
+#define FH_WAVE_LAUNCH(A, N)                                                                                      \
+    hipLaunchKernelGGL((k_spread_wave<R, W, A, N>), dim3(grid), dim3(64 * N), lds, c->stream, subs, nsub, cell,  \
+                       (const C2*)dd, (const C2*)cc, slots, gg, tpi, (R)beta, (const R*)poly)
+    if (nv == 2) {
+        if (at)
+            FH_WAVE_LAUNCH(true, 2);
+        else
+            FH_WAVE_LAUNCH(false, 2);
+    } else {
+        if (at)
+            FH_WAVE_LAUNCH(true, 1);
+        else
+            FH_WAVE_LAUNCH(false, 1);
     }
-    const size_t tile = 2 * rsize * (size_t)gg.L * gg.L;
-    return gg.method == 1 ? tile : tile + spread_staging_bytes(gg.W, rsize);
+#undef FH_WAVE_LAUNCH
 }
 
 template <class R>
