@@ -79,7 +79,7 @@ typedef struct fh_options {
                              * tolerances of 1e-4 and looser)                */
     int32_t kernel_width;   /* 2..20 cells                                   */
     double beta;            /* kernel shape parameter                        */
-    int32_t tile;           /* spread tile edge in cells: 8, 16, 32 or 64    */
+    int32_t tile;           /* spread tile edge in cells: 8, 16 or 32        */
     int32_t max_subproblem; /* nonuniform points per spread work item (a     *
                              * tile with more than 512 items' worth gets     *
                              * larger items); 0: about 32 items per CU      */

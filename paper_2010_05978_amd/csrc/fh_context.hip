@@ -564,8 +564,8 @@ static fh_status check_options(const fh_options* o)
     FH_ARG(o->kernel_width == 0 || (o->kernel_width >= 2 && o->kernel_width <= kMaxWidth),
            FH_ERR_INVALID_ARG, "kernel_width must be 0 or in [2, %d]", kMaxWidth);
     FH_ARG(o->beta >= 0 && std::isfinite(o->beta), FH_ERR_INVALID_ARG, "beta must be >= 0");
-    FH_ARG(o->tile == 0 || o->tile == 8 || o->tile == 16 || o->tile == 32 || o->tile == 64,
-           FH_ERR_INVALID_ARG, "tile must be 0, 8, 16, 32 or 64");
+    FH_ARG(o->tile == 0 || o->tile == 8 || o->tile == 16 || o->tile == 32, FH_ERR_INVALID_ARG,
+           "tile must be 0, 8, 16 or 32");
     FH_ARG(o->max_subproblem >= 0, FH_ERR_INVALID_ARG, "max_subproblem must be >= 0");
     FH_ARG(o->spread_method >= 0 && o->spread_method <= 4, FH_ERR_INVALID_ARG,
            "spread_method must be 0, 1, 2, 3 or 4");

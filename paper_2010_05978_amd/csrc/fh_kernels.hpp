@@ -951,95 +951,108 @@ __global__ void __launch_bounds__(256) k_merge_slots(typename V2<R>::T* __restri
 // reaches ceil((W-1)/T) tiles on).  Each thread sums, in item order, the
 // merged slots of those tiles at its cell and writes the cell: every cell of
 // the held rows is written, zeros included.
-template <class R>
+// The (first, count) pairs of all covering tiles are loaded at once, then
+// the first kRedU merged slots of every covering tile, and only then summed
+// (covering tiles in (dy, dx) order, slots in item order; any further slots
+// of a tile follow its first kRedU), so a tile costs two memory latencies
+// rather than two per covering tile.  REACH = (L - 1)/T; KC cells per thread.
+constexpr int kRedU = 2;
+
+template <class R, int REACH, int KC>
 __global__ void __launch_bounds__(256) k_reduce_tiles(const typename V2<R>::T* __restrict__ slots,
                                                       const int* __restrict__ tsub, GridGeom gg, int tpi,
                                                       int ntiles_total, R* __restrict__ F, int* __restrict__ cnt)
 {
     using C = typename V2<R>::T;
+    constexpr int NC = (REACH + 1) * (REACH + 1);  // covering tiles
     const int T = gg.T, TT = T * T;
     const int L = gg.L, LL = L * L;
-    const int reach = (L - 1) / T;  // tiles back that a padded tile reaches
     C* Fv = reinterpret_cast<C*>(F);
+    int ci[KC], cj[KC];
+    bool cv[KC];
+#pragma unroll
+    for (int k = 0; k < KC; ++k) {
+        const int e = threadIdx.x + k * blockDim.x;
+        cv[k] = e < TT;
+        ci[k] = cv[k] ? e % T : 0;
+        cj[k] = cv[k] ? e / T : 0;
+    }
     for (int tile = blockIdx.x; tile < ntiles_total; tile += gridDim.x) {
         // the binning counters of the call are spent: leave them at zero
         // for the next one
         if (threadIdx.x == 0) cnt[tile] = 0;
         const int b = tile / tpi, tl = tile - b * tpi;
         const int ty = tl / gg.ntx, tx = tl - ty * gg.ntx;
-        // does any work item cover this tile?  (uniform)
+        // covering tile i = (dy, dx): its first merged slot, slot stride
+        // and number of merged slots (0 where no tile reaches)
+        int first[NC], stride[NC], heads[NC];
         bool any = false;
-        for (int dy = 0; dy <= reach && !any; ++dy) {
+#pragma unroll
+        for (int i = 0; i < NC; ++i) {
+            const int dy = i / (REACH + 1), dx = i % (REACH + 1);
             int sty = ty - dy;
-            if (sty < 0) {
-                if (!gg.wrap_y) break;
-                sty = ((sty % gg.nty) + gg.nty) % gg.nty;
-            }
-            for (int dx = 0; dx <= reach && !any; ++dx) {
-                const int stx = (((tx - dx) % gg.ntx) + gg.ntx) % gg.ntx;
-                any = tsub[2 * (b * tpi + sty * gg.ntx + stx) + 1] > 0;
-            }
+            const bool ok = sty >= 0 || gg.wrap_y;
+            if (sty < 0) sty = ((sty % gg.nty) + gg.nty) % gg.nty;
+            const int stx = (((tx - dx) % gg.ntx) + gg.ntx) % gg.ntx;
+            const int t = b * tpi + sty * gg.ntx + stx;
+            const int n = ok ? tsub[2 * t + 1] : 0;
+            first[i] = ok ? tsub[2 * t] : 0;
+            int st = 1;
+            for (int l = merge_levels(n); l > 0; --l) st *= kMergeG;
+            stride[i] = st;
+            heads[i] = (n + st - 1) / st;
+            any = any || n > 0;
         }
         C* out = Fv + ((size_t)b * gg.rows + (size_t)ty * T) * gg.nf1 + (size_t)tx * T;
         if (!any) {
             for (int e = threadIdx.x; e < TT; e += blockDim.x) out[(size_t)(e / T) * gg.nf1 + e % T] = C{R(0), R(0)};
             continue;
         }
-        // a thread sums up to kCells cells (T = 32: 4; T <= 16: 1), and its
-        // loads for all of them are issued together on every trip; each
-        // cell sums its covering tiles and their merged slots in a fixed
-        // order
-        constexpr int kCells = 4;
-        R ar[kCells], ai[kCells];
-        int ci[kCells], cj[kCells];
-        bool cv[kCells];
+        // the first kRedU slots of every covering tile at each cell
+        C r[KC][NC][kRedU];
 #pragma unroll
-        for (int k = 0; k < kCells; ++k) {
-            const int e = threadIdx.x + k * blockDim.x;
-            cv[k] = e < TT;
-            ci[k] = cv[k] ? e % T : 0;
-            cj[k] = cv[k] ? e / T : 0;
-            ar[k] = ai[k] = R(0);
-        }
-        for (int dy = 0; dy <= reach; ++dy) {
-            int sty = ty - dy;
-            if (sty < 0) {
-                if (!gg.wrap_y) break;
-                sty = ((sty % gg.nty) + gg.nty) % gg.nty;
+        for (int q = 0; q < KC; ++q)
+#pragma unroll
+            for (int i = 0; i < NC; ++i) {
+                const int dy = i / (REACH + 1), dx = i % (REACH + 1);
+                const int lx = ci[q] + dx * T, ly = cj[q] + dy * T;
+                const bool in = cv[q] && lx < L && ly < L;
+                const C* sp = slots + (size_t)first[i] * LL + (in ? ly * L + lx : 0);
+#pragma unroll
+                for (int u = 0; u < kRedU; ++u)
+                    r[q][i][u] = in && u < heads[i] ? sp[(size_t)u * stride[i] * LL] : C{R(0), R(0)};
             }
-            for (int dx = 0; dx <= reach; ++dx) {
-                const int stx = (((tx - dx) % gg.ntx) + gg.ntx) % gg.ntx;
-                const int t = b * tpi + sty * gg.ntx + stx;
-                const int first = tsub[2 * t], cnt = tsub[2 * t + 1];
-                if (cnt == 0) continue;
-                int stride = 1;
-                for (int l = merge_levels(cnt); l > 0; --l) stride *= kMergeG;
-                const int heads = (cnt + stride - 1) / stride;
-                const size_t st = (size_t)stride * LL;
-                const C* s0 = slots + (size_t)first * LL;
-                for (int k = 0; k < heads; k += 4) {
-                    C r[kCells][4];
 #pragma unroll
-                    for (int q = 0; q < kCells; ++q) {
-                        const int lx = ci[q] + dx * T, ly = cj[q] + dy * T;
-                        const bool in = cv[q] && lx < L && ly < L;
-                        const C* sp = s0 + (size_t)k * st + (in ? ly * L + lx : 0);
+        for (int q = 0; q < KC; ++q) {
+            R ar = R(0), ai = R(0);
 #pragma unroll
-                        for (int u = 0; u < 4; ++u) r[q][u] = in && k + u < heads ? sp[u * st] : C{R(0), R(0)};
-                    }
+            for (int i = 0; i < NC; ++i) {
 #pragma unroll
-                    for (int q = 0; q < kCells; ++q)
+                for (int u = 0; u < kRedU; ++u) {
+                    ar += r[q][i][u].x;
+                    ai += r[q][i][u].y;
+                }
+                if (heads[i] > kRedU) {
+                    // merged slots past the first kRedU (clustered tiles)
+                    const int dy = i / (REACH + 1), dx = i % (REACH + 1);
+                    const int lx = ci[q] + dx * T, ly = cj[q] + dy * T;
+                    const bool in = cv[q] && lx < L && ly < L;
+                    const size_t st = (size_t)stride[i] * LL;
+                    const C* sp = slots + (size_t)first[i] * LL + (in ? ly * L + lx : 0);
+                    for (int k = kRedU; k < heads[i]; k += 4) {
+                        C v[4];
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) v[u] = in && k + u < heads[i] ? sp[(k + u) * st] : C{R(0), R(0)};
 #pragma unroll
                         for (int u = 0; u < 4; ++u) {
-                            ar[q] += r[q][u].x;
-                            ai[q] += r[q][u].y;
+                            ar += v[u].x;
+                            ai += v[u].y;
                         }
+                    }
                 }
             }
+            if (cv[q]) out[(size_t)cj[q] * gg.nf1 + ci[q]] = C{ar, ai};
         }
-#pragma unroll
-        for (int q = 0; q < kCells; ++q)
-            if (cv[q]) out[(size_t)cj[q] * gg.nf1 + ci[q]] = C{ar[q], ai[q]};
     }
 }
 
@@ -1822,8 +1835,22 @@ fh_status run_spread(fh_ctx* c, const InstParams& p0, const InstParams* table, i
     }
     const unsigned rgrid = (unsigned)std::max<int64_t>(
         1, std::min<int64_t>(ntiles_total, (int64_t)c->cu_count * 16));
-    hipLaunchKernelGGL((k_reduce_tiles<R>), dim3(rgrid), dim3(256), 0, c->stream,
-                       (const typename V2<R>::T*)b.slots, b.tsub, gg, tpi, ntiles_total, F, b.cnt);
+    const int reach = (gg.L - 1) / gg.T;
+    const int TT = gg.T * gg.T;
+    const unsigned rthreads = (unsigned)std::min(256, TT);
+    FH_ARG(reach >= 1 && reach <= (TT > 256 ? 1 : 2) && TT <= 1024, FH_ERR_UNSUPPORTED,
+           "tile %d with width %d", gg.T, gg.W);
+#define FH_REDUCE(RE, K)                                                                                     \
+    hipLaunchKernelGGL((k_reduce_tiles<R, RE, K>), dim3(rgrid), dim3(rthreads), 0, c->stream,                \
+                       (const typename V2<R>::T*)b.slots, b.tsub, gg, tpi, ntiles_total, F, b.cnt)
+    if (TT > 256) {
+        // T = 32: a padded tile reaches one tile on for every width
+        FH_REDUCE(1, 4);
+    } else {
+        if (reach == 1) FH_REDUCE(1, 1);
+        else FH_REDUCE(2, 1);
+    }
+#undef FH_REDUCE
     FH_HIP(hipGetLastError());
     c->tile_cnt_dirty = false;
     return FH_OK;
