@@ -318,7 +318,11 @@ __device__ __forceinline__ void lds_fft_pass(C2* buf, int n, int nseq, int Ns, c
 // Whole-block forward FFT of nseq sequences (n nseq <= MAXE) in LDS; the
 // caller synchronises before (data written) and may read right after.
 // twl: LDS room for p.ntw entries, filled here with every pass's roots.
-template <int MAXE, int NT, class C2>
+// R7: the radix-7 pass is compiled in.  Its pass holds two 7-point
+// butterflies per thread, and in double precision a kernel with it needs 152
+// registers per lane (three waves per SIMD) where the other passes need 90,
+// so kernels are built with and without it and the plan picks (lds_has7).
+template <int MAXE, int NT, bool R7, class C2>
 __device__ void lds_fft(C2* buf, const LdsFftPlan& p, int nseq, C2* twl)
 {
     {
@@ -342,11 +346,21 @@ __device__ void lds_fft(C2* buf, const LdsFftPlan& p, int nseq, C2* twl)
         case 2: lds_fft_pass<2, MAXE, NT>(buf, p.n, nseq, Ns, tw); break;
         case 3: lds_fft_pass<3, MAXE, NT>(buf, p.n, nseq, Ns, tw); break;
         case 5: lds_fft_pass<5, MAXE, NT>(buf, p.n, nseq, Ns, tw); break;
-        default: lds_fft_pass<7, MAXE, NT>(buf, p.n, nseq, Ns, tw); break;
+        default:
+            if constexpr (R7) lds_fft_pass<7, MAXE, NT>(buf, p.n, nseq, Ns, tw);
+            break;
         }
         tw += Ns;
         Ns *= R;
     }
+}
+
+// Whether a plan has a radix-7 pass (its kernels must be built with R7).
+inline bool lds_has7(const LdsFftPlan& p)
+{
+    for (int i = 0; i < p.nst; ++i)
+        if (p.radix[i] == 7) return true;
+    return false;
 }
 
 // Workgroup b of a launch over `groups` column groups, with consecutive

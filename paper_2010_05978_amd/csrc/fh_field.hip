@@ -71,13 +71,21 @@ LdsCols lds_cols_plan(const fh_ctx* c, int n, int64_t count, size_t rs, int min_
 }
 
 // Launch one of the LDS FFT kernels in the block shape that `lc` picked.
-#define FH_LDS_LAUNCH(KERNEL, R, lc, grid, stream, ...)                                                        \
+#define FH_LDS_LAUNCH_R7(KERNEL, R, R7, lc, grid, stream, ...)                                                \
     do {                                                                                                         \
         if ((lc).small)                                                                                          \
-            hipLaunchKernelGGL((KERNEL<R, kLdsFftSmall, 256>), grid, dim3(256), (lc).lds, stream, __VA_ARGS__);  \
+            hipLaunchKernelGGL((KERNEL<R, kLdsFftSmall, 256, R7>), grid, dim3(256), (lc).lds, stream,            \
+                               __VA_ARGS__);                                                                     \
         else                                                                                                     \
-            hipLaunchKernelGGL((KERNEL<R, (int)(kLdsFftBytes / (2 * sizeof(R))), 512>), grid, dim3(512), (lc).lds, \
-                               stream, __VA_ARGS__);                                                             \
+            hipLaunchKernelGGL((KERNEL<R, (int)(kLdsFftBytes / (2 * sizeof(R))), 512, R7>), grid, dim3(512),     \
+                               (lc).lds, stream, __VA_ARGS__);                                                   \
+    } while (0)
+#define FH_LDS_LAUNCH(KERNEL, R, lc, grid, stream, ...)                                                        \
+    do {                                                                                                         \
+        if (lds_has7((lc).plan))                                                                                 \
+            FH_LDS_LAUNCH_R7(KERNEL, R, true, lc, grid, stream, __VA_ARGS__);                                    \
+        else                                                                                                     \
+            FH_LDS_LAUNCH_R7(KERNEL, R, false, lc, grid, stream, __VA_ARGS__);                                   \
     } while (0)
 
 // The type-1 pipeline for B instances sharing one grid geometry; u is device

@@ -1207,7 +1207,7 @@ __global__ void __launch_bounds__(256) k_t1_rowfactors(EpiParams ep, EpiInst e0,
 // u[b][k2][k1] = epilogue(column value at k2 mod nf2) for every k2, with the
 // factors of k_epilogue_t1: its column factors here, its row factors from
 // k_t1_rowfactors.
-template <class R, int MAXE, int NT>
+template <class R, int MAXE, int NT, bool R7>
 __global__ void __launch_bounds__(NT) k_t1_cols(const R* __restrict__ F, R* __restrict__ u, int rows,
                                                             int C, int groups, LdsFftPlan plan, EpiParams ep,
                                                             EpiInst e0, const EpiInst* __restrict__ table,
@@ -1254,7 +1254,7 @@ __global__ void __launch_bounds__(NT) k_t1_cols(const R* __restrict__ F, R* __re
         buf[c * nf2 + r] = v;
     }
     __syncthreads();
-    lds_fft<MAXE, NT>(buf, plan, C, buf + (size_t)C * plan.n);
+    lds_fft<MAXE, NT, R7>(buf, plan, C, buf + (size_t)C * plan.n);
     // epilogue: C lanes write C consecutive outputs of a row, with the row
     // factors of k_t1_rowfactors and the column factors above
     const double2* E2 = E2all + (size_t)b * ep.n2;
@@ -1289,7 +1289,7 @@ __global__ void __launch_bounds__(NT) k_t1_cols(const R* __restrict__ F, R* __re
 // b[k2 mod nf2][k1 mod nf1] / (Phi1 Phi2) for modes inside the spread grid
 // (-nf/2 <= k < nf - nf/2), zero outside; each row is transformed and
 // written back to G.
-template <class R, int MAXE, int NT>
+template <class R, int MAXE, int NT, bool R7>
 __global__ void __launch_bounds__(NT) k_t3_rows(const R* __restrict__ bgrid, int nf1, int nf2,
                                                             R* __restrict__ G, int m1, int m2, int C, int groups,
                                                             LdsFftPlan plan, const double* __restrict__ ip1,
@@ -1324,14 +1324,14 @@ __global__ void __launch_bounds__(NT) k_t3_rows(const R* __restrict__ bgrid, int
         buf[e] = v;
     }
     __syncthreads();
-    lds_fft<MAXE, NT>(buf, plan, C, buf + (size_t)C * plan.n);
+    lds_fft<MAXE, NT, R7>(buf, plan, C, buf + (size_t)C * plan.n);
     C2* Gv = reinterpret_cast<C2*>(G);
     for (int e = threadIdx.x; e < nrow * m1; e += NT) Gv[(size_t)row0 * m1 + e] = buf[e];
 }
 
 // Type-3 column pass, in place: workgroup g transforms the C columns
 // [g C, g C + C) of G (length m2 each).
-template <class R, int MAXE, int NT>
+template <class R, int MAXE, int NT, bool R7>
 __global__ void __launch_bounds__(NT) k_t3_cols(R* __restrict__ G, int m1, int m2, int C, int groups,
                                                             LdsFftPlan plan)
 {
@@ -1352,7 +1352,7 @@ __global__ void __launch_bounds__(NT) k_t3_cols(R* __restrict__ G, int m1, int m
         buf[c * m2 + i2] = v;
     }
     __syncthreads();
-    lds_fft<MAXE, NT>(buf, plan, C, buf + (size_t)C * plan.n);
+    lds_fft<MAXE, NT, R7>(buf, plan, C, buf + (size_t)C * plan.n);
     for (int e = threadIdx.x; e < C * m2; e += NT) {
         const int i2 = e / C, c = e - i2 * C;
         if (c < ncol) Gv[(size_t)i2 * m1 + col0 + c] = buf[c * m2 + i2];
