@@ -38,8 +38,13 @@ struct LdsFftPlan {
     int ntw = 0;  // twiddle table entries: sum over passes of Ns
 };
 
-// Radix passes for n (16s first, then 8, 4, 2, 3, 5, 7); false if n has another
-// prime factor.
+// Radix passes for n (7s, 5s and 3s first, then 16, 8, 4, 2); false if n has
+// another prime factor.  A pass with Ns = 1 writes each thread's R outputs
+// side by side, so neighbouring lanes write R elements apart: with R a power
+// of two every lane of a write instruction lands in the same LDS banks,
+// with R odd they spread over all of them; the later passes (Ns > 1) write
+// runs of Ns consecutive elements.  Odd radices first also keep the twiddle
+// table (the sum of Ns over the passes) small.
 inline bool lds_fft_plan(int n, LdsFftPlan& p)
 {
     p = LdsFftPlan{};
@@ -52,13 +57,13 @@ inline bool lds_fft_plan(int n, LdsFftPlan& p)
             m /= r;
         }
     };
+    take(7);
+    take(5);
+    take(3);
     take(16);
     take(8);
     take(4);
     take(2);
-    take(3);
-    take(5);
-    take(7);
     int Ns = 1;
     for (int i = 0; i < p.nst; ++i) {
         p.ntw += Ns;
