@@ -31,10 +31,13 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 # LDS: 256 CUs x 128 bytes per clock x 2.4 GHz ("Rooflines")
 LDS_PEAK_GBS = 256 * 128 * 2.4
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_starfish_F20.json")
+# HBM traffic of the step's candidate dominant kernels (rocprofv3 FETCH_SIZE and
+# WRITE_SIZE, copy-calibrated), each tied to the kernel sources it was taken on
+TRAFFIC_FILES = [os.path.join(ROOT, "profiles", f)
+                 for f in ("traffic_starfish_F20.json", "traffic_starfish_F20_t1cols.json")]
 METRIC = "target pts/s at 1e-9 (FP64) vs 1e-5 (mixed); backward/forward time ratio"
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2010_05978_amd", "csrc", f)
-                  for f in ("fh_kernels.hpp", "fh_fft.hpp", "fh_field.hip")]
+                  for f in ("fh_kernels.hpp", "fh_fft.hpp", "fh_field.hip", "fh_common.hpp")]
 
 
 def parse():
@@ -185,8 +188,10 @@ def roofline(res, prec, wl):
            "frac": achieved / c["peak"], "traffic": None, "kernel": c["kernel"],
            "avg_launch_ms": c["ms"], "algorithmic_bytes_per_launch": c["bytes"],
            "per_step_ms": {k: v["ms"] * v["launches"] for k, v in cands.items()}}
-    if os.path.exists(TRAFFIC_FILE):
-        t = json.load(open(TRAFFIC_FILE))
+    for path in TRAFFIC_FILES:
+        if not os.path.exists(path):
+            continue
+        t = json.load(open(path))
         if t.get("kernel") == c["kernel"] and t.get("source_hash") == kernel_source_hash():
             out["traffic"] = t.get("bytes_per_launch")
     return out
