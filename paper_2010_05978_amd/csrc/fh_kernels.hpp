@@ -1457,11 +1457,21 @@ __global__ void __launch_bounds__(64) k_t3_interp(const R* __restrict__ G, const
     constexpr int GS = interp_group<W>();
     constexpr int NT = 64 / GS;
     constexpr int KS = 2 * W + 1;
+    constexpr int NPW = (W + kPolyExtra) * W;
+    __shared__ R pls[NPW];
     __shared__ R ks[64 * KS];
     __shared__ uint32_t cs[64];
     __shared__ C res[64];
     const int lane = threadIdx.x, g = lane / GS, r = lane % GS;
     const C* Gv = reinterpret_cast<const C*>(G);
+    // the kernel coefficients in LDS, once per block (read through LDS
+    // broadcasts rather than chains of dependent scalar loads)
+    const bool has_poly = poly != nullptr;
+    if (has_poly) {
+#pragma unroll
+        for (int i = lane; i < NPW; i += 64) pls[i] = poly[i];
+    }
+    wave_lds_order();
     for (int64_t base = blockIdx.x * (int64_t)tpw; base < M; base += (int64_t)gridDim.x * tpw) {
         const int64_t t = base + lane;
         const bool live = lane < tpw && t < M;
@@ -1476,10 +1486,16 @@ __global__ void __launch_bounds__(64) k_t3_interp(const R* __restrict__ G, const
         cs[lane] = (uint32_t)l1 | ((uint32_t)l2 << 16);
         {
             R kv[W];
-            es_weights<R, W>((R)d1, beta, poly, kv);
+            if (has_poly)
+                es_weights_lds<R, W>((R)d1, pls, kv);
+            else
+                es_weights<R, W>((R)d1, beta, nullptr, kv);
 #pragma unroll
             for (int a = 0; a < W; ++a) ks[lane * KS + a] = kv[a];
-            es_weights<R, W>((R)d2, beta, poly, kv);
+            if (has_poly)
+                es_weights_lds<R, W>((R)d2, pls, kv);
+            else
+                es_weights<R, W>((R)d2, beta, nullptr, kv);
 #pragma unroll
             for (int b = 0; b < W; ++b) ks[lane * KS + W + b] = kv[b];
         }

@@ -376,6 +376,14 @@ def test_error_statuses(fh):
     with pytest.raises(fh.FresnelError) as e:
         abi.fh_quad_radial(c.handle, 1.0, np.zeros(65), None, 1, 4, 3)
     assert e.value.status == fh.FH_ERR_INVALID_ARG
+    # spread tiles of 8, 16 or 32 cells only (the tile reduce covers at most
+    # 1024 cells per tile)
+    for bad in (4, 64):
+        with pytest.raises(fh.FresnelError) as e:
+            c.set_options(fh.fh_options(sigma=0, kernel_width=0, beta=0.0, tile=bad, max_subproblem=0,
+                                        spread_method=0))
+        assert e.value.status == fh.FH_ERR_INVALID_ARG
+    c.set_options(None)
     # the context stays usable after errors
     v = c.field_grid(q, 1.0, 1.0, 4, 4, 0.1, 0.1)
     assert torch.isfinite(torch.view_as_real(v)).all()
