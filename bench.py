@@ -147,11 +147,11 @@ def time_steps(step, steps, warmup):
 
 def spread_waves(W, rs, T=16):
     """Wavefronts per spread work item at tile T: two when their two tiles
-    (one spare cell each), the staging of 64 points and the kernel
-    coefficients fit in 64 KiB of LDS."""
+    (one spare cell each), the staging of 64 points and two wavefronts'
+    kernel arguments fit in 64 KiB of LDS."""
     L = T + W - 1
     tile = 2 * rs * (L * L + 1)
-    staging = rs * (64 * (2 * W + 2) + ((W + 4) * W + 1) // 2 * 2)
+    staging = rs * (64 * (2 * W + 2) + 128)
     return 2 if 2 * tile + staging <= 64 * 1024 else 1
 
 

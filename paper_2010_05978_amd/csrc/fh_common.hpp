@@ -70,12 +70,11 @@ struct EsKernel {
 constexpr int kPolyExtra = 4;
 
 // Wavefront spread staging: per point its 2w kernel values and its strength
-// (2 reals), for 64 points, and the (w + kPolyExtra) x w coefficients of the
-// kernel's piecewise polynomial (rounded up to whole complex cells).
+// (2 reals), for 64 points, and the kernel arguments of 64 points for each of
+// up to two wavefronts.
 inline size_t spread_staging_bytes(int w, size_t rsize)
 {
-    const size_t npw = ((size_t)w + kPolyExtra) * (size_t)w;
-    return rsize * ((size_t)64 * (2 * (size_t)w + 2) + (npw + 1) / 2 * 2);
+    return rsize * ((size_t)64 * (2 * (size_t)w + 2) + 128);
 }
 
 // 1/Phi(theta) for |theta| <= theta_max as a Chebyshev series in

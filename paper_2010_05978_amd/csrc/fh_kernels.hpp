@@ -586,33 +586,35 @@ __global__ void __launch_bounds__(64 * NV) k_spread_wave(const Sub* __restrict__
     constexpr int NPASS = (W * W + 63) / 64;  // stencil passes per point
     constexpr int U = sizeof(R) == 8 ? 4 : 8; // points per trip
     constexpr int QW = 64 / NV;               // points of a batch per wavefront
-    constexpr int NPW = (W + kPolyExtra) * W;  // kernel polynomial coefficients
+    constexpr int NP = W + kPolyExtra;        // coefficients per kernel polynomial
+    constexpr int KG = 64 / W;                // lane groups evaluating the kernel
     extern __shared__ unsigned char smem_raw[];
     const int L = gg.L, LL = L * L;
     // the wavefront index, marked wavefront-uniform for the compiler (the
     // share bounds and run starts derived from it stay scalar)
     const int wv = NV == 1 ? 0 : __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
-    // LDS: the kernel coefficients first (at a fixed address, so that every
-    // coefficient read takes an immediate offset), then NV tiles of LL cells
-    // and a spare cell each, then the staging of 64 points
-    constexpr int NPWC = (NPW * (int)sizeof(R) + (int)sizeof(C) - 1) / (int)sizeof(C);
-    R* pl = reinterpret_cast<R*>(smem_raw);
-    C* tiles = reinterpret_cast<C*>(smem_raw) + NPWC;
+    // LDS: each wavefront's 64 kernel arguments first (at a fixed address),
+    // then NV tiles of LL cells and a spare cell each, then the staging of 64
+    // points
+    constexpr int TTC = (NV * 64 * (int)sizeof(R) + (int)sizeof(C) - 1) / (int)sizeof(C);
+    R* tt = reinterpret_cast<R*>(smem_raw) + wv * 64;
+    C* tiles = reinterpret_cast<C*>(smem_raw) + TTC;
     C* tile = tiles + wv * (LL + 1);
     R* kb = reinterpret_cast<R*>(tiles + NV * (LL + 1));
     // the block's first work item is loaded without waiting for the item
-    // count (the grid never exceeds the item capacity), and the coefficient
-    // table is copied to LDS meanwhile: a wavefront evaluating the kernel
-    // then reads each coefficient with an LDS broadcast instead of a chain
-    // of dependent scalar loads
+    // count (the grid never exceeds the item capacity)
     const Sub first = subs[blockIdx.x];
     const bool has_poly = poly != nullptr;
-    if (has_poly) {
+    // kernel values by lanes over the value index: lane (kg, ka), ka =
+    // lane % W, keeps the coefficients of cell ka's polynomial in registers
+    // (loaded once) and evaluates it at points kg, kg + KG, ... of a batch.
+    // A coefficient shared by all lanes would cost a full 64-lane LDS or
+    // scalar-load delivery per use; held per lane it costs nothing.
+    const int ka = lane % W, kg = lane / W;
+    R coef[NP];
 #pragma unroll
-        for (int i = threadIdx.x; i < NPW; i += 64 * NV) pl[i] = poly[i];
-    }
-    __syncthreads();
+    for (int j = 0; j < NP; ++j) coef[j] = has_poly ? poly[j * W + ka] : R(0);
     // lane (a, b) of pass p: its kernel values, and the LDS byte offset of
     // its cell for a run at tile cell c, tb[p] + tm[p] c (lanes past W^2:
     // the spare cell whatever c)
@@ -647,39 +649,51 @@ __global__ void __launch_bounds__(64 * NV) k_spread_wave(const Sub* __restrict__
         }
         for (int base = sb.start; base < sb.end; base += 64) {
             const int p = base + lane;
+            const bool live = p < sb.end;
             int cl = 0;
             R* kp = kb + lane * KS;
-            if (p < sb.end) {
+            // points past the item stage zeros (they add exact zeros)
+            C dv{R(0), R(0)}, cv{R(0), R(0)};
+            if (live) {
                 // tile-relative first cell as an LDS index (x, y < T)
                 const uint32_t rel = cell[p] - org;
                 cl = (int)(rel >> 16) * L + (int)(rel & 0xffffu);
-                const C dv = dd[p];
+                dv = dd[p];
                 // the strength is loaded with the offsets, not after the
                 // kernel values (its latency would add to theirs)
-                const C cv = wv == NV - 1 ? cc[p] : C{R(0), R(0)};
+                if (wv == NV - 1) cv = cc[p];
+            }
+            if (wv == NV - 1) {
+                kp[2 * W] = cv.x;
+                kp[2 * W + 1] = cv.y;
+            }
 #pragma unroll
-                for (int d = 0; d < 2; ++d) {
-                    if (NV == 2 && d != wv) continue;
+            for (int d = 0; d < 2; ++d) {
+                if (NV == 2 && d != wv) continue;
+                const R off = d == 0 ? dv.x : dv.y;
+                if (has_poly) {
+                    // the batch's polynomial arguments (es_weights' t), then
+                    // the evaluations (es_weights' Horner steps, in order)
+                    tt[lane] = R(2) * off + R(W - 1);
+                    wave_lds_order();
+#pragma unroll
+                    for (int r = 0; r < (64 + KG - 1) / KG; ++r) {
+                        const int q = r * KG + kg;
+                        if (kg < KG && q < 64) {
+                            const R t = tt[q];
+                            R k = coef[0];
+#pragma unroll
+                            for (int j = 1; j < NP; ++j) k = k * t + coef[j];
+                            kb[q * KS + d * W + ka] = base + q < sb.end ? k : R(0);
+                        }
+                    }
+                    // tt is rewritten for the next dimension or batch
+                    wave_lds_order();
+                } else {
                     R k[W];
-                    if (has_poly)
-                        es_weights_lds<R, W>(d == 0 ? dv.x : dv.y, pl, k);
-                    else
-                        es_weights<R, W>(d == 0 ? dv.x : dv.y, beta, nullptr, k);
+                    es_weights<R, W>(off, beta, nullptr, k);
 #pragma unroll
-                    for (int a = 0; a < W; ++a) kp[d * W + a] = k[a];
-                }
-                if (wv == NV - 1) {
-                    kp[2 * W] = cv.x;
-                    kp[2 * W + 1] = cv.y;
-                }
-            } else {
-                // points past the item: zeros (they add exact zeros)
-                constexpr int nz = NV == 1 ? KS : W;
-#pragma unroll
-                for (int a = 0; a < nz; ++a) kp[wv * W + a] = R(0);
-                if (NV == 2 && wv == 1) {
-                    kp[2 * W] = R(0);
-                    kp[2 * W + 1] = R(0);
+                    for (int a = 0; a < W; ++a) kp[d * W + a] = live ? k[a] : R(0);
                 }
             }
             __syncthreads();
