@@ -122,35 +122,6 @@ __device__ __forceinline__ void es_weights(R d, R beta, const R* __restrict__ po
     }
 }
 
-// es_weights with the coefficient table in LDS: the reads of coefficient
-// row j + 1 are issued before the multiply-adds of row j (the scheduling
-// barriers keep them there), so each read's latency is covered by a row of
-// arithmetic instead of stalling every second multiply-add.
-template <class R, int W>
-__device__ __forceinline__ void es_weights_lds(R d, const R* pl, R* k)
-{
-    constexpr int NP = W + kPolyExtra;
-    const R t = R(2) * d + R(W - 1);
-    R c[W], n[W];
-#pragma unroll
-    for (int a = 0; a < W; ++a) k[a] = pl[a];
-#pragma unroll
-    for (int a = 0; a < W; ++a) c[a] = pl[W + a];
-#pragma unroll
-    for (int j = 1; j < NP; ++j) {
-        if (j + 1 < NP) {
-#pragma unroll
-            for (int a = 0; a < W; ++a) n[a] = pl[(j + 1) * W + a];
-        }
-        __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-        for (int a = 0; a < W; ++a) k[a] = k[a] * t + c[a];
-        __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-        for (int a = 0; a < W; ++a) c[a] = n[a];
-    }
-}
-
 // One kernel value phi((d + a) 2/W) (a may vary across lanes).
 template <class R, int W>
 __device__ __forceinline__ R es_one(R d, int a, R beta, const R* __restrict__ poly)
@@ -1471,21 +1442,22 @@ __global__ void __launch_bounds__(64) k_t3_interp(const R* __restrict__ G, const
     constexpr int GS = interp_group<W>();
     constexpr int NT = 64 / GS;
     constexpr int KS = 2 * W + 1;
-    constexpr int NPW = (W + kPolyExtra) * W;
-    __shared__ R pls[NPW];
+    constexpr int NP = W + kPolyExtra;  // coefficients per kernel polynomial
+    constexpr int KG = 64 / W;          // lane groups evaluating the kernel
+    __shared__ R tt[64];
     __shared__ R ks[64 * KS];
     __shared__ uint32_t cs[64];
     __shared__ C res[64];
     const int lane = threadIdx.x, g = lane / GS, r = lane % GS;
     const C* Gv = reinterpret_cast<const C*>(G);
-    // the kernel coefficients in LDS, once per block (read through LDS
-    // broadcasts rather than chains of dependent scalar loads)
+    // kernel values by lanes over the value index (as in the spread): lane
+    // (kg, ka) keeps cell ka's polynomial coefficients in registers and
+    // evaluates it for targets kg, kg + KG, ... of a chunk
     const bool has_poly = poly != nullptr;
-    if (has_poly) {
+    const int ka = lane % W, kg = lane / W;
+    R coef[NP];
 #pragma unroll
-        for (int i = lane; i < NPW; i += 64) pls[i] = poly[i];
-    }
-    wave_lds_order();
+    for (int j = 0; j < NP; ++j) coef[j] = has_poly ? poly[j * W + ka] : R(0);
     for (int64_t base = blockIdx.x * (int64_t)tpw; base < M; base += (int64_t)gridDim.x * tpw) {
         const int64_t t = base + lane;
         const bool live = lane < tpw && t < M;
@@ -1498,20 +1470,32 @@ __global__ void __launch_bounds__(64) k_t3_interp(const R* __restrict__ G, const
         cell_of((X - tp.xic) * tp.g1, tp.m1, W, l1, d1, ok1);
         cell_of((Y - tp.etac) * tp.g2, tp.m2, W, l2, d2, ok2);
         cs[lane] = (uint32_t)l1 | ((uint32_t)l2 << 16);
-        {
-            R kv[W];
-            if (has_poly)
-                es_weights_lds<R, W>((R)d1, pls, kv);
-            else
-                es_weights<R, W>((R)d1, beta, nullptr, kv);
 #pragma unroll
-            for (int a = 0; a < W; ++a) ks[lane * KS + a] = kv[a];
-            if (has_poly)
-                es_weights_lds<R, W>((R)d2, pls, kv);
-            else
-                es_weights<R, W>((R)d2, beta, nullptr, kv);
+        for (int d = 0; d < 2; ++d) {
+            const R off = (R)(d == 0 ? d1 : d2);
+            if (has_poly) {
+                // es_weights' argument and Horner steps, in the same order
+                tt[lane] = R(2) * off + R(W - 1);
+                wave_lds_order();
 #pragma unroll
-            for (int b = 0; b < W; ++b) ks[lane * KS + W + b] = kv[b];
+                for (int rd = 0; rd < (64 + KG - 1) / KG; ++rd) {
+                    const int q = rd * KG + kg;
+                    if (kg < KG && q < 64) {
+                        const R t = tt[q];
+                        R k = coef[0];
+#pragma unroll
+                        for (int j = 1; j < NP; ++j) k = k * t + coef[j];
+                        ks[q * KS + d * W + ka] = k;
+                    }
+                }
+                // tt is rewritten for the next dimension or chunk
+                wave_lds_order();
+            } else {
+                R kv[W];
+                es_weights<R, W>(off, beta, nullptr, kv);
+#pragma unroll
+                for (int a = 0; a < W; ++a) ks[lane * KS + d * W + a] = kv[a];
+            }
         }
         // output factor: 1/Phi correction times the target chirp over i lambda z
         const double corr =
