@@ -189,6 +189,7 @@ struct fh_ctx {
     hipEvent_t gev_in = nullptr, gev_out = nullptr;
     std::map<std::tuple<int, long long, long long>, fh::InvPhiCheb> cheb_cache;
     std::map<std::tuple<int, long long, int>, void*> poly_cache;  // (w, beta bits, precision)
+    std::map<std::pair<int, int>, void*> lds_tw_cache;             // (LDS FFT length, real size)
     std::map<void*, size_t> owned;  // every hipMalloc'd block and its size
     double* bbox_dev = nullptr;      // bounding-box reduction scratch
     double* bbox_host = nullptr;     // pinned readback of the box

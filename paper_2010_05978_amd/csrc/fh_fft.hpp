@@ -35,7 +35,9 @@ struct LdsFftPlan {
     int n = 0;
     int nst = 0;
     int radix[kLdsFftMaxStages] = {};
-    int ntw = 0;  // twiddle table entries: sum over passes of Ns
+    int ntw = 0;               // twiddle table entries: sum over passes of Ns
+    const void* tw = nullptr;  // the table in device memory (complex, the kernel's precision), or
+                               // null: each workgroup computes it
 };
 
 // Radix passes for n (7s, 5s and 3s first, then 16, 8, 4, 2); false if n has
@@ -322,7 +324,8 @@ __device__ __forceinline__ void lds_fft_pass(C2* buf, int n, int nseq, int Ns, c
 
 // Whole-block forward FFT of nseq sequences (n nseq <= MAXE) in LDS; the
 // caller synchronises before (data written) and may read right after.
-// twl: LDS room for p.ntw entries, filled here with every pass's roots.
+// twl: LDS room for p.ntw entries, filled here with every pass's roots
+// (copied from p.tw when the plan has a precomputed table).
 // R7: the radix-7 pass is compiled in.  Its pass holds two 7-point
 // butterflies per thread, and in double precision a kernel with it needs 152
 // registers per lane (three waves per SIMD) where the other passes need 90,
@@ -330,7 +333,10 @@ __device__ __forceinline__ void lds_fft_pass(C2* buf, int n, int nseq, int Ns, c
 template <int MAXE, int NT, bool R7, class C2>
 __device__ void lds_fft(C2* buf, const LdsFftPlan& p, int nseq, C2* twl)
 {
-    {
+    if (p.tw) {
+        const C2* tg = static_cast<const C2*>(p.tw);
+        for (int k = threadIdx.x; k < p.ntw; k += NT) twl[k] = tg[k];
+    } else {
         int off = 0, Ns = 1;
         for (int st = 0; st < p.nst; ++st) {
             const int L = Ns * p.radix[st];

@@ -42,7 +42,48 @@ struct LdsCols {
     LdsFftPlan plan;
 };
 
-LdsCols lds_cols_plan(const fh_ctx* c, int n, int64_t count, size_t rs, int min_c = 0)
+// The LDS FFT twiddle table of plan p (every pass's roots exp(-2 pi i k/L),
+// k < Ns, L = Ns R, in pass order) in device memory, computed on the host
+// in long double once per context, length and precision: otherwise every
+// workgroup of an FFT launch evaluates the same sincospi values.  Null when
+// the allocation or copy fails (the kernels then compute the table).
+const void* lds_twiddles(fh_ctx* c, const LdsFftPlan& p, size_t rs)
+{
+    const auto key = std::make_pair(p.n, (int)rs);
+    auto it = c->lds_tw_cache.find(key);
+    if (it != c->lds_tw_cache.end()) return it->second;
+    const long double two_pi = 6.283185307179586476925286766559005768L;
+    std::vector<double> t(2 * (size_t)p.ntw);
+    int off = 0, Ns = 1;
+    for (int st = 0; st < p.nst; ++st) {
+        const int L = Ns * p.radix[st];
+        for (int k = 0; k < Ns; ++k) {
+            const long double a = two_pi * (long double)k / (long double)L;
+            t[2 * (size_t)(off + k)] = (double)cosl(a);
+            t[2 * (size_t)(off + k) + 1] = (double)-sinl(a);
+        }
+        off += Ns;
+        Ns = L;
+    }
+    void* dev = nullptr;
+    if (dev_alloc(c, rs * t.size(), &dev) == FH_OK) {
+        hipError_t e;
+        if (rs == sizeof(double)) {
+            e = hipMemcpy(dev, t.data(), rs * t.size(), hipMemcpyHostToDevice);
+        } else {
+            std::vector<float> tf(t.begin(), t.end());
+            e = hipMemcpy(dev, tf.data(), rs * tf.size(), hipMemcpyHostToDevice);
+        }
+        if (e != hipSuccess) {
+            dev_free(c, dev);
+            dev = nullptr;
+        }
+    }
+    c->lds_tw_cache[key] = dev;
+    return dev;
+}
+
+LdsCols lds_cols_plan(fh_ctx* c, int n, int64_t count, size_t rs, int min_c = 0)
 {
     LdsCols r;
     // FH_FFT=rocfft in the environment keeps every transform on rocFFT
@@ -65,6 +106,7 @@ LdsCols lds_cols_plan(const fh_ctx* c, int n, int64_t count, size_t rs, int min_
     // rather fewer sequences per block than the 512-thread shape
     while (C > 1 && n * C > kLdsFftSmall && n * (C / 2) >= 1 && n <= kLdsFftSmall) C /= 2;
     r.C = C;
+    r.plan.tw = lds_twiddles(c, r.plan, rs);
     r.lds = cb * ((size_t)n * C + r.plan.ntw);
     r.small = n * C <= kLdsFftSmall;
     return r;
