@@ -1442,22 +1442,11 @@ __global__ void __launch_bounds__(64) k_t3_interp(const R* __restrict__ G, const
     constexpr int GS = interp_group<W>();
     constexpr int NT = 64 / GS;
     constexpr int KS = 2 * W + 1;
-    constexpr int NP = W + kPolyExtra;  // coefficients per kernel polynomial
-    constexpr int KG = 64 / W;          // lane groups evaluating the kernel
-    __shared__ R tt[64];
     __shared__ R ks[64 * KS];
     __shared__ uint32_t cs[64];
     __shared__ C res[64];
     const int lane = threadIdx.x, g = lane / GS, r = lane % GS;
     const C* Gv = reinterpret_cast<const C*>(G);
-    // kernel values by lanes over the value index (as in the spread): lane
-    // (kg, ka) keeps cell ka's polynomial coefficients in registers and
-    // evaluates it for targets kg, kg + KG, ... of a chunk
-    const bool has_poly = poly != nullptr;
-    const int ka = lane % W, kg = lane / W;
-    R coef[NP];
-#pragma unroll
-    for (int j = 0; j < NP; ++j) coef[j] = has_poly ? poly[j * W + ka] : R(0);
     for (int64_t base = blockIdx.x * (int64_t)tpw; base < M; base += (int64_t)gridDim.x * tpw) {
         const int64_t t = base + lane;
         const bool live = lane < tpw && t < M;
@@ -1470,32 +1459,14 @@ __global__ void __launch_bounds__(64) k_t3_interp(const R* __restrict__ G, const
         cell_of((X - tp.xic) * tp.g1, tp.m1, W, l1, d1, ok1);
         cell_of((Y - tp.etac) * tp.g2, tp.m2, W, l2, d2, ok2);
         cs[lane] = (uint32_t)l1 | ((uint32_t)l2 << 16);
+        {
+            R kv[W];
+            es_weights<R, W>((R)d1, beta, poly, kv);
 #pragma unroll
-        for (int d = 0; d < 2; ++d) {
-            const R off = (R)(d == 0 ? d1 : d2);
-            if (has_poly) {
-                // es_weights' argument and Horner steps, in the same order
-                tt[lane] = R(2) * off + R(W - 1);
-                wave_lds_order();
+            for (int a = 0; a < W; ++a) ks[lane * KS + a] = kv[a];
+            es_weights<R, W>((R)d2, beta, poly, kv);
 #pragma unroll
-                for (int rd = 0; rd < (64 + KG - 1) / KG; ++rd) {
-                    const int q = rd * KG + kg;
-                    if (kg < KG && q < 64) {
-                        const R t = tt[q];
-                        R k = coef[0];
-#pragma unroll
-                        for (int j = 1; j < NP; ++j) k = k * t + coef[j];
-                        ks[q * KS + d * W + ka] = k;
-                    }
-                }
-                // tt is rewritten for the next dimension or chunk
-                wave_lds_order();
-            } else {
-                R kv[W];
-                es_weights<R, W>(off, beta, nullptr, kv);
-#pragma unroll
-                for (int a = 0; a < W; ++a) ks[lane * KS + d * W + a] = kv[a];
-            }
+            for (int b = 0; b < W; ++b) ks[lane * KS + W + b] = kv[b];
         }
         // output factor: 1/Phi correction times the target chirp over i lambda z
         const double corr =
