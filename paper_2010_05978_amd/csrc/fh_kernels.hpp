@@ -601,13 +601,16 @@ __global__ void __launch_bounds__(64 * NV) k_spread_wave(const Sub* __restrict__
         tb[p] = (uint32_t)(reinterpret_cast<const unsigned char*>(cp) - smem_raw);
         tm[p] = valid ? (uint32_t)sizeof(C) : 0u;
     }
+    // the first item's tile is cleared while the item and its count load
+    for (int e = lane; e < LL; e += 64) tile[e] = C{R(0), R(0)};
     const int nsub = *nsub_ptr;
     for (int s = blockIdx.x; s < nsub; s += gridDim.x) {
+        if (s != (int)blockIdx.x)
+            for (int e = lane; e < LL; e += 64) tile[e] = C{R(0), R(0)};
         const Sub sb = s == (int)blockIdx.x ? first : subs[s];
         int ox, oy;
         tile_origin<R>(sb, gg, tpi, ox, oy);
         const uint32_t org = (uint32_t)ox | ((uint32_t)oy << 16);
-        for (int e = lane; e < LL; e += 64) tile[e] = C{R(0), R(0)};
         // the run before the first point: cell 0 with zero sums (its write
         // stores zeros over zeros)
         int cur = 0;
