@@ -81,16 +81,20 @@ typedef struct fh_options {
     double beta;            /* kernel shape parameter                        */
     int32_t tile;           /* spread tile edge in cells: 8, 16 or 32        */
     int32_t max_subproblem; /* nonuniform points per spread work item (a     *
-                             * tile with more than 512 items' worth gets     *
-                             * larger items); 0: about 32 items per CU      */
+                             * tile with more than 2048 items' worth gets    *
+                             * larger items); 0: about 96 items per CU,      *
+                             * at least 64 points each                       */
     int32_t spread_method;  /* 1: thread per point, shared LDS tile with     *
-                             * atomics; 2: wavefront per work item, lanes    *
-                             * over the stencil, private LDS tile updated    *
-                             * by read-add-write; 3: as 2, updated by LDS    *
-                             * atomics; 4: four wavefronts per work item,    *
-                             * each with the padded tile in registers (lane  *
-                             * per column and row bank), tiles 8 or 16 only  *
-                             * (else 2); 2, 3 and 4 are deterministic        */
+                             * atomics; 2: one or two wavefronts per work    *
+                             * item, lanes over the stencil, a private LDS   *
+                             * tile each, runs of points with one first cell *
+                             * summed in registers and added to the tile     *
+                             * (read when the run starts, written when it    *
+                             * ends); 3: as 2, runs added by LDS atomics;    *
+                             * 4: four wavefronts per work item, each with   *
+                             * the padded tile in registers (lane per column *
+                             * and row bank), tiles 8 or 16 only (else 2);   *
+                             * 2, 3 and 4 are deterministic                  */
 } fh_options;
 
 /* ---------------------------------------------------------------- context */
