@@ -94,7 +94,9 @@ typedef struct fh_options {
                              * 4: four wavefronts per work item, each with   *
                              * the padded tile in registers (lane per column *
                              * and row bank), tiles 8 or 16 only (else 2);   *
-                             * 2, 3 and 4 are deterministic                  */
+                             * 2, 3 and 4 sum a work item's points in a      *
+                             * fixed order (the point order within a tile    *
+                             * comes from atomic counters in the binning)    */
 } fh_options;
 
 /* ---------------------------------------------------------------- context */

@@ -539,8 +539,10 @@ __device__ __forceinline__ void wave_lds_order()
 // trip of points are all read before the first is added, and points past
 // the end of the item are staged as zeros, so the only branch per point is
 // the (wavefront-uniform) start of a run.  The slot receives the sum of the
-// NV tiles in wavefront order.  The summation order is fixed, so the spread
-// is deterministic.  ATOMIC adds each run with non-returning LDS atomics
+// NV tiles in wavefront order.  For a given order of the item's points the
+// summation order is fixed (the order of points within a tile comes from the
+// binning's atomic counters, so it, and the last bits of the sums, can change
+// from call to call).  ATOMIC adds each run with non-returning LDS atomics
 // instead of the read and write.
 template <class R, int W, bool ATOMIC, int NV>
 __global__ void __launch_bounds__(64 * NV) k_spread_wave(const Sub* __restrict__ subs,
@@ -767,7 +769,7 @@ __global__ void __launch_bounds__(64 * NV) k_spread_wave(const Sub* __restrict__
 // strength x kx[x - cx] x ky[y - cy] to its RB cells, with reads at fixed
 // offsets from one base and no branches (lanes outside the stencil add
 // zeros).  At the end of the item the NW tiles are summed through LDS in a
-// fixed order into the item's slot, so the spread is deterministic.
+// fixed order into the item's slot.
 template <int TT, int W>
 struct RegTile {
     static constexpr int L = TT + W - 1;

@@ -1,0 +1,55 @@
+"""Run-to-run variation of the field (sec. 2.1's NUFFT step as built here).
+
+Every work item's points are summed in a fixed order and the slots reduced in
+a fixed order, but the binning ranks the points of a tile with atomic
+counters, so their order within a tile -- and the last bits of the sums --
+can change between calls.  The starfish field of the benchmark step (40,000
+nodes whose spokes crowd the tiles near the origin, so runs of points share a
+first cell) computed twice, with each spread method, must then agree to
+rounding: relative L2 difference below 1e-13 in FP64 and 2e-6 in mixed
+precision, far below the tolerances (1e-9, 1e-5) and far above what an
+unordered race between LDS updates would leave.
+"""
+import pytest
+
+import workloads
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+BOUND = {"fp64": 1e-13, "mixed": 2e-6}
+
+
+@pytest.fixture(scope="module")
+def fh():
+    import paper_2010_05978_amd as fh
+    return fh
+
+
+def rel(a, b):
+    return float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_spread_repeatable_to_rounding(fh, prec):
+    wl = workloads.workload(2)
+    g = wl.grid
+    ctx = fh.Context(prec)
+    q = ctx.quad_for(wl.shape)
+    out = {}
+    for method in (2, 3, 4):
+        ctx.set_options(fh.fh_options(sigma=0, kernel_width=0, beta=0.0, tile=16, max_subproblem=0,
+                                      spread_method=method))
+        a = ctx.field_grid(q, wl.lam, wl.z, g.n1, g.n2, g.h1, g.h2).clone()
+        b = ctx.field_grid(q, wl.lam, wl.z, g.n1, g.n2, g.h1, g.h2).clone()
+        d = rel(a, b)
+        print(f"{prec} method {method}: two calls differ by {d:.2e} (relative L2)", flush=True)
+        assert d < BOUND[prec], method
+        out[method] = a
+    for m in (3, 4):
+        d = rel(out[m], out[2])
+        print(f"{prec} method {m} vs 2: {d:.2e}", flush=True)
+        assert d < BOUND[prec], m
+    ctx.set_options(None)
+    q.close()
+    ctx.close()
