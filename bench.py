@@ -1,19 +1,28 @@
 #!/usr/bin/env python3
 """Throughput of the fast Fresnel-diffraction path on one MI355X.
 
-A step is one pass of the whole hot path over the starfish workload (Fresnel
-number 20; workload 2 of workloads.py): device quadrature generation (20 GL
-panels x 20 nodes on the boundary, dilation with 100 radial nodes: 40,000
-nodes), the type-1 field on the 1000 x 1000 target grid, and the type-3 field
-at 1e5 scattered targets in the disk |x| < 1.5.  Shape parameters and target
-coordinates are resident on the device before the timed region starts.
+Headline step: the batched workload (workload 4 of workloads.py) -- 256
+random shapes (smooth radial Fourier curves and polygons, node counts uniform
+in [1e4, 4e5], 51.7 million nodes in all), one wavelength each from 64
+log-spaced in [0.5, 1.0] um, z = 1e5 m, every shape's field on a 512 x 512
+grid over [-1.5, 1.5)^2 (67.1 million targets), as one batched call: strengths
+and binning, the spread over every instance's work items, the row FFTs, the
+column FFTs with the deconvolving epilogue, replayed from a hipGraph.  As in
+the paper's timings, the rules are built before the timed region; a second
+figure builds all 256 rules on the device in every step.
 
-value = targets per second of the FP64 path (tolerance 1e-9, relative L2
-against the exact quadrature sum); the mixed-precision path (tolerance 1e-5)
-is timed in the same run and reported beside it.  The roofline entry is for
-the kernel with the largest device time per step, timed live with HIP events
-on the library's streams over a second timed pass of the same steps (the
-events cost host time, so the throughput pass runs without them).
+value = targets/s of the FP64 path (tolerance 1e-9, relative L2 against the
+exact quadrature sum); beside it the mixed-precision path (tolerance 1e-5) and
+the plain FP64 single-instance form (256 separate calls).  Shape parameters
+and rules are resident on the device before the timed region starts.
+
+The roofline entry is for the kernel with the most device time in the
+headline step (the spread), from its average launch time measured live with
+HIP events on the library's stream over a second pass of the same steps, with
+denominators measured on the device (fh_probe_ceilings).  Further legs: the
+starshade of workload 3 (2048^2 grid and 1e6 pupil points at 3 wavelengths),
+the starfish of workload 2, the shape gradient of workload 5, the edge
+integral and the paper's own tasks (kite, HG starshade, Koch snowflake).
 """
 from __future__ import annotations
 
@@ -22,22 +31,21 @@ import hashlib
 import json
 import os
 import sys
+import tempfile
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-HBM_PEAK_GBS = 8000.0
-# LDS: 256 CUs x 128 bytes per clock x 2.4 GHz ("Rooflines")
-LDS_PEAK_GBS = 256 * 128 * 2.4
-# HBM traffic of the step's candidate dominant kernels (rocprofv3 FETCH_SIZE and
-# WRITE_SIZE, copy-calibrated), each tied to the kernel sources it was taken on
-TRAFFIC_FILES = [os.path.join(ROOT, "profiles", f)
-                 for f in ("traffic_starfish_F20.json", "traffic_starfish_F20_t1cols.json")]
 METRIC = "target pts/s at 1e-9 (FP64) vs 1e-5 (mixed); backward/forward time ratio"
+# HBM traffic of the headline's spread (rocprofv3 FETCH_SIZE and WRITE_SIZE,
+# copy-calibrated), tied to the kernel sources it was taken on
+TRAFFIC_FILES = [os.path.join(ROOT, "profiles", f)
+                 for f in ("traffic_batch256_spread_fp64.json", "traffic_batch256_spread_mixed.json")]
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2010_05978_amd", "csrc", f)
                   for f in ("fh_kernels.hpp", "fh_fft.hpp", "fh_field.hip", "fh_common.hpp")]
+ALL_PARTS = "batch,single,starshade,starfish,grad,nsli,kite,koch,hg"
 
 
 def parse():
@@ -46,15 +54,13 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle sample")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the headline oracle sample")
     ap.add_argument("--only", choices=["fp64", "mixed"], default=None, help="time one precision only")
     ap.add_argument("--pmc-calib", action="store_true",
                     help="also run a plain 256 MiB device copy (counter calibration for rocprofv3 --pmc)")
-    ap.add_argument("--no-grad", action="store_true", help="skip the backward/forward ratio (workload 5)")
-    ap.add_argument("--no-batch", action="store_true", help="skip the batched workload 4")
-    ap.add_argument("--parts", default="step,grad,batch,nsli,kite,koch,hg",
-                    help="comma list of step, grad, batch, nsli, kite, koch, hg to run (profiling one part "
-                         "alone; without step the line carries no value)")
+    ap.add_argument("--parts", default=ALL_PARTS,
+                    help="comma list of " + ALL_PARTS + " (profiling one part alone; without batch the line "
+                         "carries no value)")
     return ap.parse_args()
 
 
@@ -66,15 +72,272 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
+def cuda_ms(fn, steps, warmup):
+    """Average milliseconds of fn() over `steps` calls after `warmup`, by host
+    wall clock with a device synchronisation on both sides."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return 1e3 * (time.perf_counter() - t0) / steps
+
+
+# ------------------------------------------------------------ headline leg
+class Batch:
+    """Workload 4: 256 rules resident on the device, one batched grid call."""
+
+    def __init__(self, fh, precision):
+        import numpy as np
+        import torch
+        import workloads
+        self.ctx = fh.Context(precision)
+        self.shapes = workloads.batch_shapes()
+        self.B = len(self.shapes)
+        lam64 = workloads.batch_lambdas(64)
+        self.lams = np.array([lam64[i % 64] for i in range(self.B)])
+        self.zs = np.full(self.B, workloads.BATCH_Z)
+        self.g = workloads.BATCH_GRID
+        self.quads = [self.ctx.quad_for(s) for s in self.shapes]
+        self.N = sum(q.N for q in self.quads)
+        self.M = self.B * self.g.M
+        self.out = torch.empty((self.B, self.g.n2, self.g.n1), dtype=self.ctx.cdtype, device="cuda")
+
+    def field(self, quads=None):
+        g = self.g
+        self.ctx.field_grid_batch(quads or self.quads, self.lams, self.zs, g.n1, g.n2, g.h1, g.h2, out=self.out)
+
+    def with_rules(self):
+        """Build all 256 rules on the device, then the batched field."""
+        quads = [self.ctx.quad_for(s) for s in self.shapes]
+        self.field(quads)
+        for q in quads:
+            q.close()
+
+    def close(self):
+        for q in self.quads:
+            q.close()
+        self.ctx.close()
+
+
+def spread_name(prec, W, T=16):
+    """Kernel name of the wavefront spread for width W at tile T: two
+    wavefronts per work item when their two tiles (one spare cell each), the
+    staging of 64 points and two wavefronts' kernel arguments fit 64 KiB."""
+    rs = 8 if prec == "fp64" else 4
+    L = T + W - 1
+    tile = 2 * rs * (L * L + 1)
+    staging = rs * (64 * (2 * W + 2) + 128)
+    nv = 2 if 2 * tile + staging <= 64 * 1024 else 1
+    return f"k_spread_wave<{'double' if rs == 8 else 'float'}, {W}, false, {nv}>"
+
+
+def batch_leg(fh, prec, steps, warmup, ceilings):
+    """Throughput of the batched call, the same steps with the rules built in
+    each, and the spread's average launch time from HIP events on the
+    library's stream (timing on: the batch then runs eagerly, stage [1]
+    brackets the spread kernel alone)."""
+    b = Batch(fh, prec)
+    ms = cuda_ms(b.field, steps, warmup)
+    ms_rules = cuda_ms(b.with_rules, max(3, steps // 4), 1)
+    b.ctx.set_timing(True)
+    b.ctx.timing_totals(3, reset=True)
+    for _ in range(steps):
+        b.field()
+    tot, n = b.ctx.timing_totals(3)
+    b.ctx.set_timing(False)
+    stages = [v / max(n, 1) for v in tot]
+    p = b.ctx.query_params(b.g.n1)
+    rs = 8 if prec == "fp64" else 4
+    W = p["width"]
+    t_spread = stages[1] * 1e-3
+    # one complex add per stencil cell and node, as the read and the write of
+    # the cell in LDS (the operations a run flush issues)
+    lds_bytes = b.N * W * W * 4 * rs
+    hbm_bytes = b.N * (4 + 4 * rs)             # packed cell, offsets and strength per node
+    lds_peak = ceilings["lds_rmw_c128_gbs" if prec == "fp64" else "lds_rmw_c64_gbs"]
+    kern = spread_name(prec, W)
+    roof = {"bound": "lds", "achieved": lds_bytes / t_spread / 1e9, "peak": lds_peak, "unit": "GB/s",
+            "frac": lds_bytes / t_spread / 1e9 / lds_peak, "traffic": None, "kernel": kern,
+            "avg_launch_ms": stages[1], "algorithmic_bytes_per_launch": lds_bytes,
+            "peak_source": "fh_probe_ceilings: LDS read-modify-write of complex " +
+                           ("double" if rs == 8 else "float") + " cells",
+            "hbm": {"achieved": hbm_bytes / t_spread / 1e9, "peak": ceilings["hbm_copy_gbs"], "unit": "GB/s",
+                    "frac": hbm_bytes / t_spread / 1e9 / ceilings["hbm_copy_gbs"],
+                    "algorithmic_bytes_per_launch": hbm_bytes,
+                    "peak_source": "fh_probe_ceilings: device copy"}}
+    for path in TRAFFIC_FILES:
+        if os.path.exists(path):
+            t = json.load(open(path))
+            if t.get("kernel") == kern and t.get("source_hash") == kernel_source_hash():
+                roof["traffic"] = t.get("bytes_per_launch")
+    out = {"value": b.M / (ms * 1e-3), "unit": "targets/s", "ms_per_call": ms, "nodes_per_s": b.N / (ms * 1e-3),
+           "instances": b.B, "nodes": b.N, "targets": b.M, "tolerance": b.ctx.tol,
+           "dtype": "f64" if prec == "fp64" else "c64-f64phase", "params": p,
+           "stages_ms": {"strengths_and_binning": stages[0], "spread": stages[1],
+                         "slot_merge_reduce_row_fft": stages[2], "column_fft_epilogue": stages[3],
+                         "whole_call_eager": stages[4]},
+           "with_rules": {"ms_per_step": ms_rules, "value": b.M / (ms_rules * 1e-3),
+                          "note": "256 device rule builds (one launch each) plus the batched call per step"},
+           "roofline": roof}
+    b.close()
+    return out
+
+
+def single_leg(fh, steps, warmup):
+    """The plain FP64 single-instance form of workload 4: the same 256 rules
+    and grids, one fh_field_grid call each."""
+    b = Batch(fh, "fp64")
+    g = b.g
+    u = b.out
+
+    def step():
+        for i, q in enumerate(b.quads):
+            b.ctx.field_grid(q, b.lams[i], b.zs[i], g.n1, g.n2, g.h1, g.h2, out=u[i])
+
+    ms = cuda_ms(step, steps, warmup)
+    out = {"value": b.M / (ms * 1e-3), "unit": "targets/s", "ms_per_step": ms, "calls_per_step": b.B,
+           "dtype": "f64", "tolerance": 1e-9}
+    b.close()
+    return out
+
+
+# --------------------------------------------------------- CPU baselines
+def oracle_rules(shape):
+    import oracle
+    if type(shape).__name__ == "RadialCurve":
+        return oracle.quad_radial(shape.r0, shape.a, shape.b, shape.panels, shape.q, shape.m)
+    if type(shape).__name__ == "Polygon":
+        return oracle.quad_polygon(shape.vx, shape.vy, shape.q, shape.m)
+    s = shape
+    return oracle.quad_starshade(s.Np, s.a, s.R, s.b, s.p, s.m, s.np_, s.nd, s.md, s.coef, s.K)
+
+
+def oracle_sample(cases, seconds, seed):
+    """Time the oracle's direct sum over cases [(rule, lam, z, xi, eta)] on
+    seeded target samples, case by case, until about `seconds` of CPU time;
+    returns (targets, node-target pairs, seconds)."""
+    import numpy as np
+    import oracle
+    rng = np.random.Generator(np.random.PCG64(seed))
+    done_t = done_p = 0
+    spent = 0.0
+    order = rng.permutation(len(cases))
+    k = 0
+    while spent < seconds:
+        (x, y, w), lam, z, xi, eta = cases[order[k % len(cases)]]
+        # about 0.5 s per case at ~1e9 pairs/s
+        m = int(max(64, min(len(xi), 5e8 / max(len(x), 1))))
+        idx = rng.choice(len(xi), m, replace=False)
+        t0 = time.perf_counter()
+        oracle.fresnel_direct(x, y, w, lam, z, xi[idx], eta[idx])
+        spent += time.perf_counter() - t0
+        done_t += m
+        done_p += m * len(x)
+        k += 1
+    return done_t, done_p, spent
+
+
+def cpu_baseline_batch(seconds):
+    """The oracle (direct FP64 sum, -O3 -march=native, every host core) on a
+    seeded sample of workload 4's targets; the full workload's time is
+    extrapolated from the measured node-target pair rate.  A 1-core figure
+    comes from a shorter run of the same sample kind."""
+    import oracle
+    import workloads
+    shapes = workloads.batch_shapes()
+    lam64 = workloads.batch_lambdas(64)
+    g = workloads.BATCH_GRID
+    xi, eta = oracle.grid_targets(g.n1, g.n2, g.h1, g.h2)
+    import numpy as np
+    rng = np.random.Generator(np.random.PCG64(4242))
+    pick = rng.choice(len(shapes), 24, replace=False)
+    cases = [(oracle_rules(shapes[i]), lam64[i % 64], workloads.BATCH_Z, xi, eta) for i in pick]
+    total_pairs = sum(s.n_nodes for s in shapes) * g.M
+    cores = oracle.num_threads()
+    t, pairs, dt = oracle_sample(cases, seconds, 7)
+    rate = pairs / dt
+    oracle.set_threads(1)
+    t1, pairs1, dt1 = oracle_sample(cases, max(1.0, seconds / 4), 8)
+    oracle.set_threads(cores)
+    return {"value": t / dt, "unit": "targets/s", "cores": cores, "kind": "oracle",
+            "sample": f"{t} grid targets of 24 of the 256 instances (seeded), direct FP64 sum over each "
+                      f"instance's nodes, {dt:.1f} s; -O3 -march=native",
+            "pairs_per_s": rate, "extrapolated_full_workload_s": total_pairs / rate,
+            "extrapolated_targets_per_s": len(shapes) * g.M / (total_pairs / rate),
+            "one_core": {"value": t1 / dt1, "unit": "targets/s", "pairs_per_s": pairs1 / dt1,
+                         "sample": f"{t1} targets, {dt1:.1f} s"}}
+
+
+# -------------------------------------------------------- starshade leg
+def starshade_leg(fh, prec, steps, warmup, cpu_seconds):
+    """Workload 3: the 24-petal starshade (998,400 nodes, z = 3.7e7 m) at
+    lambda = 0.5, 0.75 and 1.0 um; per wavelength the type-1 field on the
+    2048^2 grid over [-2.4, 2.4)^2 and the type-3 field at 1e6 uniform points
+    in the 2.4 m pupil (a target set planned on the pupil box).  The rule is
+    built once before the timed region (reused across wavelengths, sec.
+    4.3)."""
+    import torch
+    import workloads
+    wl = workloads.workload(3)
+    ctx = fh.Context(prec)
+    q = ctx.quad_for(wl.shape)
+    g = wl.grid
+    xi = torch.tensor(wl.points[0], device="cuda")
+    eta = torch.tensor(wl.points[1], device="cuda")
+    P = wl.pupil
+    tg = ctx.targets(xi, eta, box=(-P, P, -P, P))
+    ug = torch.empty((g.n2, g.n1), dtype=ctx.cdtype, device="cuda")
+    up = torch.empty(xi.numel(), dtype=ctx.cdtype, device="cuda")
+
+    def grid_only():
+        for lam in wl.lams:
+            ctx.field_grid(q, lam, wl.z, g.n1, g.n2, g.h1, g.h2, occulter=True, out=ug)
+
+    def pts_only():
+        for lam in wl.lams:
+            ctx.field_targets(q, lam, wl.z, tg, occulter=True, out=up)
+
+    ms_g = cuda_ms(grid_only, steps, warmup)
+    ms_p = cuda_ms(pts_only, steps, warmup)
+    nl = len(wl.lams)
+    out = {"workload": "24-petal starshade, 998400 nodes, 3 wavelengths; 2048^2 grid (type 1) and 1e6 pupil "
+                       "points (type 3), rule built once",
+           "dtype": "f64" if prec == "fp64" else "c64-f64phase", "tolerance": ctx.tol,
+           "grid": {"ms_per_step": ms_g, "value": nl * g.M / (ms_g * 1e-3), "unit": "targets/s"},
+           "points": {"ms_per_step": ms_p, "value": nl * xi.numel() / (ms_p * 1e-3), "unit": "targets/s"},
+           "value": nl * (g.M + xi.numel()) / ((ms_g + ms_p) * 1e-3), "unit": "targets/s"}
+    tg.close()
+    q.close()
+    ctx.close()
+    if cpu_seconds > 0:
+        import oracle
+        rule = oracle_rules(wl.shape)
+        xg, eg = oracle.grid_targets(g.n1, g.n2, g.h1, g.h2)
+        cases = [(rule, lam, wl.z, xg, eg) for lam in wl.lams] + \
+                [(rule, lam, wl.z, wl.points[0], wl.points[1]) for lam in wl.lams]
+        t, pairs, dt = oracle_sample(cases, cpu_seconds, 11)
+        full = nl * (g.M + xi.numel()) * wl.shape.n_nodes / (pairs / dt)
+        out["cpu_baseline"] = {"value": t / dt, "unit": "targets/s", "cores": oracle.num_threads(),
+                               "kind": "oracle", "sample": f"{t} grid and pupil targets (seeded), direct FP64 "
+                                                           f"sum over all 998400 nodes, {dt:.1f} s",
+                               "extrapolated_full_workload_s": full}
+    return out
+
+
+# --------------------------------------------------------- starfish leg
 class Step:
-    """One pass of the hot path for one precision: the quadrature rule, its
-    field on the grid (type 1) and at the scattered targets (type 3).  The two
-    field calls are independent and run on two streams, each context building
-    its own copy of the rule (one kernel, a few microseconds) so that nothing
-    orders one stream after the other: a cross-stream wait costs more than the
-    rule.  The scattered targets become a target set every step, planned on the
-    pupil's box |x|, |y| <= 1.5 that the workload draws them in, so no call
-    reads anything back to the host."""
+    """Workload 2, one pass: the quadrature rule, its field on the grid (type
+    1) and at the scattered targets (type 3).  The two field calls are
+    independent and run on two streams, each context building its own copy of
+    the rule (one kernel, a few microseconds) so that nothing orders one
+    stream after the other: a cross-stream wait costs more than the rule.  The
+    scattered targets become a target set every step, planned on the pupil's
+    box |x|, |y| <= 1.5 that the workload draws them in, so no call reads
+    anything back to the host."""
 
     def __init__(self, fh, precision, wl, dev):
         import torch
@@ -96,104 +359,44 @@ class Step:
 
     def __call__(self):
         wl, g = self.wl, self.g
-        # type 3 on stream B (enqueued first: its chain is the longer one)
         qb = self.ctx_pts.quad_for(self.shape)
         tg = self.ctx_pts.targets(self.xi, self.eta, box=self.box)
         self.ctx_pts.field_targets(qb, wl.lam, wl.z, tg, out=self.upts)
-        # each rule's memory goes back to its own context's pool, reused on
-        # the same stream
         qb.close()
         tg.close()
-        # type 1 on stream A
         qa = self.ctx.quad_for(self.shape)
         self.ctx.field_grid(qa, wl.lam, wl.z, g.n1, g.n2, g.h1, g.h2, out=self.ugrid)
         qa.close()
-
-    def set_timing(self, on):
-        self.ctx.set_timing(on)
-        self.ctx_pts.set_timing(on)
 
     def close(self):
         self.ctx.close()
         self.ctx_pts.close()
 
 
-def time_steps(step, steps, warmup):
-    """Wall time of `steps` steps, then the per-stage device times of another
-    `steps` steps timed with HIP events on the library's streams.  Recording
-    the events costs host time on every call, so the throughput pass runs
-    without them."""
+def starfish_leg(fh, prec, steps, warmup, cpu_seconds):
+    """Workload 2 (starfish, Fresnel number 20, 40,000 nodes): the rule built
+    each step on each of two streams, the 1000^2 grid (type 1) and 1e5
+    random points (type 3)."""
     import torch
-    for _ in range(warmup):
-        step()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        step()
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    step.set_timing(True)
-    step.ctx.timing_totals(0, reset=True)
-    step.ctx_pts.timing_totals(1, reset=True)
-    torch.cuda.synchronize()
-    for _ in range(steps):
-        step()
-    torch.cuda.synchronize()
-    grid_ms, ngrid = step.ctx.timing_totals(0)
-    pts_ms, npts = step.ctx_pts.timing_totals(1)
-    step.set_timing(False)
-    return dt, [v / max(ngrid, 1) for v in grid_ms], [v / max(npts, 1) for v in pts_ms]
-
-
-def spread_waves(W, rs, T=16):
-    """Wavefronts per spread work item at tile T: two when their two tiles
-    (one spare cell each), the staging of 64 points and two wavefronts'
-    kernel arguments fit in 64 KiB of LDS."""
-    L = T + W - 1
-    tile = 2 * rs * (L * L + 1)
-    staging = rs * (64 * (2 * W + 2) + 128)
-    return 2 if 2 * tile + staging <= 64 * 1024 else 1
-
-
-def roofline(res, prec, wl):
-    """Roofline of the kernel with the most device time per step.
-
-    Candidates are the stages that bracket one kernel: the spread of each
-    call, the type-1 epilogue and the type-3 interpolation."""
-    r = res[prec]
-    p = r["params"]
-    W = p["width"]
-    rs = 8 if prec == "fp64" else 4
-    N = wl.shape.n_nodes
-    n1, n2 = wl.grid.n1, wl.grid.n2
-    M3 = len(wl.points[0])
-    g, pt = r["grid_stage_ms"], r["points_stage_ms"]
-    cands = {
-        # spread: 2 W^2 LDS atomic adds of one real each per node
-        "spread": {"kernel": f"k_spread_wave<{'double' if rs == 8 else 'float'}, {W}, false, {spread_waves(W, rs)}>",
-                   "ms": (g[1] + pt[1]) / 2,
-                   "launches": 2, "bound": "alu", "unit": "GB/s", "peak": LDS_PEAK_GBS,
-                   "bytes": N * W * W * 2 * rs},
-        # type-1 column pass + epilogue: at least one complex output written per
-        # target (the band it reads is not counted)
-        "t1_cols": {"kernel": f"k_t1_cols<{'double' if rs == 8 else 'float'}>", "ms": g[3], "launches": 1,
-                    "bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK_GBS, "bytes": n1 * n2 * 2 * rs},
-        # interpolation: target coordinates and index in, one output out
-        "interp": {"kernel": f"k_t3_interp<{'double' if rs == 8 else 'float'}, {W}>", "ms": pt[3], "launches": 1,
-                   "bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK_GBS, "bytes": M3 * (16 + 4 + 2 * rs)},
-    }
-    name, c = max(cands.items(), key=lambda kv: kv[1]["ms"] * kv[1]["launches"])
-    achieved = c["bytes"] / (c["ms"] * 1e-3) / 1e9
-    out = {"bound": c["bound"], "achieved": achieved, "peak": c["peak"], "unit": c["unit"],
-           "frac": achieved / c["peak"], "traffic": None, "kernel": c["kernel"],
-           "avg_launch_ms": c["ms"], "algorithmic_bytes_per_launch": c["bytes"],
-           "per_step_ms": {k: v["ms"] * v["launches"] for k, v in cands.items()}}
-    for path in TRAFFIC_FILES:
-        if not os.path.exists(path):
-            continue
-        t = json.load(open(path))
-        if t.get("kernel") == c["kernel"] and t.get("source_hash") == kernel_source_hash():
-            out["traffic"] = t.get("bytes_per_launch")
+    import workloads
+    wl = workloads.workload(2)
+    st = Step(fh, prec, wl, torch.device("cuda", 0))
+    ms = cuda_ms(st, steps, warmup)
+    out = {"workload": "starfish r = 1 + 0.3 cos 5t, Fresnel number 20, 40000 nodes; 1000^2 grid + 1e5 random "
+                       "targets on two streams; rule built each step",
+           "dtype": "f64" if prec == "fp64" else "c64-f64phase", "tolerance": st.ctx.tol,
+           "ms_per_step": ms, "value": st.M / (ms * 1e-3), "unit": "targets/s"}
+    st.close()
+    if cpu_seconds > 0:
+        import oracle
+        import numpy as np
+        rule = oracle_rules(wl.shape)
+        xg, eg = oracle.grid_targets(wl.grid.n1, wl.grid.n2, wl.grid.h1, wl.grid.h2)
+        cases = [(rule, wl.lam, wl.z, np.concatenate([xg, wl.points[0]]), np.concatenate([eg, wl.points[1]]))]
+        t, pairs, dt = oracle_sample(cases, cpu_seconds, 13)
+        out["cpu_baseline"] = {"value": t / dt, "unit": "targets/s", "cores": oracle.num_threads(),
+                               "kind": "oracle", "sample": f"{t} of the step's targets (seeded), direct FP64 sum "
+                                                           f"over all 40000 nodes, {dt:.1f} s"}
     return out
 
 
@@ -237,36 +440,6 @@ def grad_ratio(fh, precision, steps, warmup):
     return {"fwd_ms": 1e3 * fwd / steps, "bwd_ms": 1e3 * bwd / steps, "ratio": bwd / fwd,
             "workload": "24-petal starshade, 998400 nodes, 384 edge coefficients, 512^2 masked pupil, "
                         "3 wavelengths; forward includes quadrature generation"}
-
-
-def batch_throughput(fh, steps, warmup):
-    """Workload 4: 256 random shapes (node counts uniform in [1e4, 4e5]), one
-    wavelength each from 64 log-spaced in [0.5, 1.0] um, 512^2 grids, mixed
-    precision; one batched call replayed from a hipGraph."""
-    import numpy as np
-    import torch
-    import workloads
-    ctx = fh.Context("mixed")
-    shapes = workloads.batch_shapes()
-    lams = workloads.batch_lambdas(64)
-    quads = [ctx.quad_for(s) for s in shapes]
-    B = len(quads)
-    lam = np.array([lams[i % 64] for i in range(B)])
-    zs = np.full(B, workloads.BATCH_Z)
-    g = workloads.BATCH_GRID
-    out = torch.empty((B, g.n2, g.n1), dtype=ctx.cdtype, device="cuda")
-    for _ in range(warmup):
-        ctx.field_grid_batch(quads, lam, zs, g.n1, g.n2, g.h1, g.h2, occulter=False, out=out)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        ctx.field_grid_batch(quads, lam, zs, g.n1, g.n2, g.h1, g.h2, occulter=False, out=out)
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / steps
-    N = sum(q.N for q in quads)
-    ctx.close()
-    return {"value": B * g.M / dt, "unit": "targets/s", "ms_per_call": 1e3 * dt, "nodes_per_s": N / dt,
-            "instances": B, "nodes": N, "dtype": "c64-f64phase", "tolerance": 1e-5}
 
 
 # FP64 flops per node-target pair of the edge-integral kernel (an FMA counts
@@ -518,30 +691,6 @@ def hg_starshade(fh, steps, warmup):
                          "max_intensity_in_shadow": float(peak[:, : int(0.6 * sw["n_radii"])].max())}}
 
 
-def cpu_baseline(wl, seconds):
-    """The oracle (direct FP64 sum) on a seeded sample of the step's targets."""
-    import numpy as np
-    import oracle
-    s = wl.shape
-    x, y, w = oracle.quad_radial(s.r0, s.a, s.b, s.panels, s.q, s.m)
-    xi_g, eta_g = oracle.grid_targets(wl.grid.n1, wl.grid.n2, wl.grid.h1, wl.grid.h2)
-    xi = np.concatenate([xi_g, wl.points[0]])
-    eta = np.concatenate([eta_g, wl.points[1]])
-    rng = np.random.Generator(np.random.PCG64(4242))
-    probe = rng.choice(len(xi), 1024, replace=False)
-    t0 = time.perf_counter()
-    oracle.fresnel_direct(x, y, w, wl.lam, wl.z, xi[probe], eta[probe])
-    per = (time.perf_counter() - t0) / 1024
-    n = int(min(len(xi), max(1024, seconds / max(per, 1e-9))))
-    idx = rng.choice(len(xi), n, replace=False)
-    t0 = time.perf_counter()
-    oracle.fresnel_direct(x, y, w, wl.lam, wl.z, xi[idx], eta[idx])
-    dt = time.perf_counter() - t0
-    return {"value": n / dt, "unit": "targets/s", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"{n} of the step's {len(xi)} targets (grid and scattered, seeded), "
-                      f"direct FP64 sum over all {len(x)} nodes, {dt:.1f} s"}
-
-
 def main():
     args = parse()
     if args.gpus != 1:
@@ -550,74 +699,65 @@ def main():
         sys.exit(2)
     import torch
     import paper_2010_05978_amd as fh
-    import workloads
 
-    dev = torch.device("cuda", 0)
-    wl = workloads.workload(2)
     precs = [args.only] if args.only else ["fp64", "mixed"]
     parts = set(args.parts.split(","))
-    if "step" not in parts:
-        out = {"metric": METRIC, "value": None, "unit": "targets/s", "n_gpus": 1, "parts": sorted(parts)}
-        if "grad" in parts and not args.no_grad:
-            out["backward_forward"] = {p: grad_ratio(fh, p, 3, 1) for p in precs}
-        if "batch" in parts and not args.no_batch:
-            out["batch"] = batch_throughput(fh, 5, 2)
-        if "nsli" in parts:
-            out["nsli"] = nsli_throughput(fh, wl, args.steps, args.warmup,
-                                          0.0 if args.no_cpu_baseline else 3.0)
-        if "kite" in parts:
-            out["kite_table"] = kite_table(fh, 5, 2)
-        if "koch" in parts:
-            out["koch"] = koch_snowflake(fh, 3, 1)
-        if "hg" in parts:
-            out["hg"] = hg_starshade(fh, 5, 2)
-        print(json.dumps(out))
-        return
-    res = {}
-    for p in precs:
-        st = Step(fh, p, wl, dev)
-        dt, gstage, pstage = time_steps(st, args.steps, args.warmup)
-        res[p] = {"ms_per_step": 1e3 * dt / args.steps, "value": st.M * args.steps / dt,
-                  "grid_stage_ms": gstage, "points_stage_ms": pstage,
-                  "params": st.ctx.query_params(wl.grid.n1)}
-        st.close()
+    cpu = not args.no_cpu_baseline
+    if cpu:
+        import oracle
+        oracle.build_native(os.path.join(tempfile.gettempdir(), "fh_oracle_native"))
+    pc = fh.Context("fp64")
+    ceilings = pc.probe_ceilings()
+    pc.close()
+    out = {"metric": METRIC, "value": None, "unit": "targets/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64" if precs[0] == "fp64" else "c64-f64phase", "data": "synthetic"}
+    if "batch" in parts:
+        res = {p: batch_leg(fh, p, args.steps, args.warmup, ceilings) for p in precs}
+        r = res[precs[0]]
+        out.update({
+            "value": r["value"], "ms_per_step": r["ms_per_call"],
+            "config": {"workload": "256 random shapes (smooth radial Fourier curves and polygons, 8-32 modes), "
+                                   "node counts uniform in [1e4, 4e5], one wavelength each from 64 log-spaced in "
+                                   "[0.5, 1.0] um, z = 1e5 m; 512x512 grid on [-1.5, 1.5)^2 per shape; one "
+                                   "batched call replayed from a hipGraph; rules built before the timed region",
+                       "instances": r["instances"], "nodes": r["nodes"], "targets_per_step": r["targets"],
+                       "tolerance": r["tolerance"]},
+            "roofline": r["roofline"],
+        })
+        out["batch"] = res
+        if len(precs) > 1:
+            out["mixed"] = {"value": res["mixed"]["value"], "ms_per_step": res["mixed"]["ms_per_call"],
+                            "dtype": "c64-f64phase", "tolerance": res["mixed"]["tolerance"],
+                            "roofline": res["mixed"]["roofline"]}
+    out["ceilings"] = ceilings
     if args.pmc_calib:
-        a = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device=dev)
+        a = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)
         for _ in range(3):
             b.copy_(a)
         torch.cuda.synchronize()
-    main_p = precs[0]
-    r = res[main_p]
-    out = {
-        "metric": METRIC,
-        "value": r["value"], "unit": "targets/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": r["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64" if main_p == "fp64" else "c64-f64phase", "data": "synthetic",
-        "config": {"workload": "starfish r=1+0.3cos5t, Fresnel number 20, 40000 nodes; 1000x1000 grid "
-                               "(type 1) + 1e5 random targets (type 3) on two streams; quadrature generated each "
-                               "step (once per stream)",
-                   "tolerance": 1e-9 if main_p == "fp64" else 1e-5, "targets_per_step": 1_100_000},
-        "roofline": roofline(res, main_p, wl),
-        "stages_ms": {p: {"grid": res[p]["grid_stage_ms"], "points": res[p]["points_stage_ms"]} for p in precs},
-    }
-    if "mixed" in res and main_p != "mixed":
-        out["mixed"] = {"value": res["mixed"]["value"], "ms_per_step": res["mixed"]["ms_per_step"],
-                        "dtype": "c64-f64phase", "tolerance": 1e-5, "roofline": roofline(res, "mixed", wl)}
-    if not args.no_grad and "grad" in parts:
+    if "single" in parts and "fp64" in precs:
+        out["fp64_single_instance"] = single_leg(fh, 3, 1)
+    if "starshade" in parts:
+        out["starshade"] = {p: starshade_leg(fh, p, args.steps, args.warmup, 6.0 if cpu and p == precs[0] else 0.0)
+                            for p in precs}
+    if "starfish" in parts:
+        out["starfish"] = {p: starfish_leg(fh, p, args.steps, args.warmup, 4.0 if cpu and p == precs[0] else 0.0)
+                           for p in precs}
+    if "grad" in parts:
         out["backward_forward"] = {p: grad_ratio(fh, p, 3, 1) for p in precs}
-    if not args.no_batch and "batch" in parts:
-        out["batch"] = batch_throughput(fh, 5, 2)
     if "nsli" in parts:
-        out["nsli"] = nsli_throughput(fh, wl, args.steps, args.warmup, 0.0 if args.no_cpu_baseline else 3.0)
+        import workloads
+        out["nsli"] = nsli_throughput(fh, workloads.workload(2), args.steps, args.warmup, 3.0 if cpu else 0.0)
     if "kite" in parts:
         out["kite_table"] = kite_table(fh, 5, 2)
     if "koch" in parts:
         out["koch"] = koch_snowflake(fh, 3, 1)
     if "hg" in parts:
         out["hg"] = hg_starshade(fh, 5, 2)
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
+    if cpu and "batch" in parts:
+        out["cpu_baseline"] = cpu_baseline_batch(args.cpu_seconds)
     print(json.dumps(out))
 
 

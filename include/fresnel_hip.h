@@ -407,6 +407,24 @@ fh_status fh_set_timing(fh_ctx* ctx, int32_t enable);
 fh_status fh_last_timing(fh_ctx* ctx, double* ms5);
 fh_status fh_timing_totals(fh_ctx* ctx, int32_t kind, double* ms5, int64_t* ncalls, int32_t reset);
 
+/* ------------------------------------------------------------ diagnostics */
+
+/* Measured ceilings of the device the context runs on, for roofline
+ * fractions (not part of any field computation).  out (host, 5 doubles):
+ *   out[0] HBM bandwidth of a device-to-device copy of 1 GiB (the faster of
+ *          a plain and a four-loads-in-flight copy), in GB/s of bytes read
+ *          plus bytes written;
+ *   out[1] LDS atomic adds of float (non-returning, conflict-free cells,
+ *          every CU), in GB/s of operands;
+ *   out[2] the same for double;
+ *   out[3] LDS read-modify-write of complex doubles (16-byte cells), in GB/s
+ *          of bytes read plus written;
+ *   out[4] the same for complex floats (8-byte cells).
+ * Each is the best of five timed launches.  Allocates 2 GiB of device memory
+ * for the duration of the call (FH_ERR_ALLOC if that fails) and synchronises
+ * the context stream. */
+fh_status fh_probe_ceilings(fh_ctx* ctx, double* out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -34,14 +34,33 @@ _dp = ctypes.POINTER(ctypes.c_double)
 
 
 def build(force: bool = True) -> str:
-    """Compile the oracle shared library in place (gcc, -O2, OpenMP)."""
+    """Compile the oracle shared library in place (gcc -O3, OpenMP).  The
+    in-tree library targets x86-64-v3 (AVX2), so that a copy built on one
+    host runs on another; the benchmark's CPU baseline builds its own copy
+    with -march=native on the host it runs on (build_native)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp"
-        cmd = ["gcc", "-O2", "-march=x86-64-v2", "-fopenmp", "-fPIC", "-shared",
-               "-std=c99", "-D_GNU_SOURCE", _SRC, "-o", tmp, "-lm"]
-        subprocess.check_call(cmd)
-        os.replace(tmp, _LIB)
+        _compile(_LIB, "x86-64-v3")
     return _LIB
+
+
+def _compile(path: str, march: str) -> None:
+    tmp = path + ".tmp"
+    cmd = ["gcc", "-O3", f"-march={march}", "-fopenmp", "-fPIC", "-shared",
+           "-std=c99", "-D_GNU_SOURCE", _SRC, "-o", tmp, "-lm"]
+    subprocess.check_call(cmd)
+    os.replace(tmp, path)
+
+
+def build_native(directory: str) -> str:
+    """Compile a -O3 -march=native copy of the oracle into `directory` and use
+    it for every later call of this module (the CPU-baseline timing)."""
+    global _lib, _LIB
+    os.makedirs(directory, exist_ok=True)
+    path = os.path.join(directory, "libfresnel_oracle_native.so")
+    _compile(path, "native")
+    _LIB = path
+    _lib = None
+    return path
 
 
 _lib = None
@@ -78,6 +97,8 @@ def _load():
         lib.orc_bdry_starshade.argtypes = [i32, d, d, d, d, i32, i32, i32, _dp, _dp, _dp, _dp]
         lib.orc_nsli.argtypes = [_dp, _dp, _dp, _dp, i64, d, d, _dp, _dp, i64, d, i32, _dp]
         lib.orc_num_threads.restype = i32
+        lib.orc_set_threads.argtypes = [i32]
+        lib.orc_set_threads.restype = i32
         for name in ("orc_gauss_legendre", "orc_bdry_radial_gl", "orc_bdry_radial_ptr",
                      "orc_bdry_polygon", "orc_dilation", "orc_starshade",
                      "orc_fresnel_direct", "orc_fresnel_direct_vjp", "orc_starshade_vjp",
@@ -103,6 +124,11 @@ def _check(rc, what):
 
 def num_threads() -> int:
     return int(_load().orc_num_threads())
+
+
+def set_threads(n: int) -> None:
+    """Run the OpenMP loops on n threads from now on."""
+    _load().orc_set_threads(int(n))
 
 
 # ---------------------------------------------------------------- 1D rules

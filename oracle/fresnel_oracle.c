@@ -893,3 +893,15 @@ int orc_num_threads(void)
     return 1;
 #endif
 }
+
+/* Use n threads from now on (n >= 1; ignored without OpenMP). */
+int orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    extern void omp_set_num_threads(int);
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+    return 0;
+}

@@ -256,6 +256,10 @@ class Context:
     def timing_totals(self, kind: int, reset: bool = False):
         return abi.fh_timing_totals(self.handle, kind, reset)
 
+    def probe_ceilings(self):
+        """Measured HBM copy and LDS rates of this device (roofline denominators)."""
+        return abi.fh_probe_ceilings(self.handle)
+
     def close(self):
         if self.handle is not None:
             abi.fh_destroy(self.handle)

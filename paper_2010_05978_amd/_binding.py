@@ -39,7 +39,7 @@ EXPORTED = [
     "fh_starshade_vjp", "fh_autotune_grid", "fh_set_timing", "fh_last_timing", "fh_timing_totals",
     "fh_boundary_radial", "fh_boundary_polygon", "fh_boundary_starshade", "fh_field_nsli",
     "fh_quad_fourier", "fh_boundary_fourier", "fh_quad_koch", "fh_quad_starshade_rigid",
-    "fh_quad_starshade_tab", "fh_targets_sort",
+    "fh_quad_starshade_tab", "fh_targets_sort", "fh_probe_ceilings",
 ]
 
 
@@ -109,6 +109,7 @@ def lib():
             "fh_quad_starshade_rigid": [vp, i32, d, d, d, d, i32, i32, i32, i32, vp, i32, i32, pvp],
             "fh_quad_starshade_tab": [vp, i32, d, d, vp, i32, i32, i32, i32, vp, i32, ctypes.c_int, pvp],
             "fh_boundary_fourier": [vp, i32, vp, vp, vp, vp, i32, i32, vp, vp, vp, vp, ctypes.c_int],
+            "fh_probe_ceilings": [vp, ctypes.POINTER(d)],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -484,3 +485,12 @@ def fh_timing_totals(ctx, kind: int, reset: bool = False):
     n = ctypes.c_int64()
     _check(lib().fh_timing_totals(ctx, kind, arr, ctypes.byref(n), int(bool(reset))))
     return list(arr), n.value
+
+
+def fh_probe_ceilings(ctx):
+    """Measured ceilings: {'hbm_copy_gbs', 'lds_add_f32_gbs', 'lds_add_f64_gbs', 'lds_rmw_c128_gbs',
+    'lds_rmw_c64_gbs'}."""
+    arr = (ctypes.c_double * 5)()
+    _check(lib().fh_probe_ceilings(ctx, arr))
+    return {"hbm_copy_gbs": arr[0], "lds_add_f32_gbs": arr[1], "lds_add_f64_gbs": arr[2],
+            "lds_rmw_c128_gbs": arr[3], "lds_rmw_c64_gbs": arr[4]}

@@ -16,7 +16,8 @@ INCLUDE = os.path.join(ROOT, "include")
 OBJDIR = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libfresnel_hip.so")
 
-SOURCES = ["fh_context.hip", "fh_quad.hip", "fh_field.hip", "fh_adjoint.hip", "fh_autotune.hip", "fh_nsli.hip"]
+SOURCES = ["fh_context.hip", "fh_quad.hip", "fh_field.hip", "fh_adjoint.hip", "fh_autotune.hip", "fh_nsli.hip",
+           "fh_probe.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

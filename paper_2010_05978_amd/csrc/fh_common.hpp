@@ -50,6 +50,8 @@ void set_error(const char* fmt, ...) __attribute__((format(printf, 1, 2)));
     } while (0)
 
 constexpr double kPi = 3.14159265358979323846264338327950288;
+constexpr unsigned kInjectFftPlan = 1u;
+constexpr unsigned kInjectCapture = 2u;
 constexpr int kMaxWidth = 20;
 constexpr int kMaxFourier = 64;
 
@@ -179,6 +181,10 @@ struct fh_ctx {
     fh::Arena arena;
     size_t alloc_cap = 0;  // optional cap on device bytes (testing)
     size_t alloc_total = 0;
+    // Failures forced from the host for tests (FH_INJECT_FAULT at creation):
+    // kInjectFftPlan makes every new rocFFT plan fail, kInjectCapture makes
+    // every graph capture be refused.
+    unsigned inject = 0;
 
     std::map<int, double*> gl_cache;  // device GL tables: x[q], w[q]
     std::map<std::tuple<int, int, int, long long>, double*> iphi_cache;

@@ -406,6 +406,10 @@ fh_status fft_plan(fh_ctx* c, int nf1, int nf2, int batch, FftPlan** out)
         *out = &it->second;
         return FH_OK;
     }
+    if (c->inject & kInjectFftPlan) {
+        set_error("rocfft_plan_create(%d x %d, batch %d) failed (forced by FH_INJECT_FAULT)", nf1, nf2, batch);
+        return FH_ERR_FFT;
+    }
     FftPlan p;
     size_t lengths[2] = {(size_t)nf1, (size_t)nf2};
     rocfft_precision pr = c->prec == FH_FP64 ? rocfft_precision_double : rocfft_precision_single;
@@ -596,6 +600,10 @@ fh_status fh_create(fh_ctx** out, int device, fh_precision prec, double tol, con
         c->cu_count = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
         if (const char* cap = std::getenv("FH_ALLOC_CAP_BYTES")) c->alloc_cap = std::strtoull(cap, nullptr, 10);
         if (const char* t = std::getenv("FH_TIMING")) c->timing = std::atoi(t) != 0;
+        if (const char* f = std::getenv("FH_INJECT_FAULT")) {
+            if (std::strstr(f, "fft_plan")) c->inject |= kInjectFftPlan;
+            if (std::strstr(f, "graph_capture")) c->inject |= kInjectCapture;
+        }
         *out = c.release();
         return FH_OK;
     } catch (...) {

@@ -11,7 +11,9 @@
 //        spread:  exponential-of-semicircle (ES) kernel into a (T+W-1)^2 LDS
 //                 tile per work item, written out as one slot per work item,
 //        reduce:  every fine-grid cell sums the slots that cover it (no
-//                 global atomics, no separate zero fill, deterministic order),
+//                 global atomics, no separate zero fill; a fixed order of
+//                 slots, though the binning's atomic counters may order a
+//                 tile's points differently from call to call),
 //        FFT:     rocFFT,
 //        finish:  deconvolution by the kernel's Fourier transform (type 1), or
 //                 precorrection, a second FFT and kernel interpolation at the
@@ -270,7 +272,9 @@ fh_status t1_pipeline(fh_ctx* c, int B, const fh_quad* const* qs, const double* 
     if (it == c->graph_cache.end()) {
         GraphEntry ge;
         c->stream = c->gstream;
-        hipError_t eb = hipStreamBeginCapture(c->gstream, hipStreamCaptureModeThreadLocal);
+        hipError_t eb = (c->inject & kInjectCapture)
+                            ? hipErrorStreamCaptureUnsupported
+                            : hipStreamBeginCapture(c->gstream, hipStreamCaptureModeThreadLocal);
         fh_status s = FH_OK;
         hipGraph_t g = nullptr;
         hipError_t e = hipSuccess;

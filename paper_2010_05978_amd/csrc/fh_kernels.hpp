@@ -714,8 +714,12 @@ __global__ void __launch_bounds__(64 * NV) k_spread_wave(const Sub* __restrict__
                             accr[pp] = acci[pp] = R(0);
                         }
                         // every pass's write precedes the new run's reads:
-                        // the two runs' stencils may overlap across passes
+                        // the two runs' stencils may overlap across passes,
+                        // and another lane may read a cell this lane wrote
+                        // (the order point keeps the compiler from moving
+                        // those reads above the writes)
                         if constexpr (!ATOMIC) {
+                            wave_lds_order();
 #pragma unroll
                             for (int pp = 0; pp < NPASS; ++pp)
                                 bs[pp] = *reinterpret_cast<const C*>(smem_raw + (tb[pp] + tm[pp] * (uint32_t)c));

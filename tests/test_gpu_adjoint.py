@@ -127,14 +127,21 @@ def test_autograd_starshade_gradient_vs_direct_sum(ctx):
     errg = relL2(cpu(coef.grad), gref)
     print(f"  loss {float(L):.6e} (oracle {Lref:.6e}, rel {errL:.2e}); grad rel L2 {errg:.2e}; "
           f"shadow amplification {kappa:.1f}", flush=True)
-    bar = TOL[ctx.precision] * kappa
-    assert errL <= 2 * bar
-    assert errg <= 2 * bar
+    # the bar is the stated tolerance itself; kappa (how much the u_ap
+    # tolerance could be amplified in the shadow) is reported beside it
+    assert errL <= TOL[ctx.precision]
+    assert errg <= TOL[ctx.precision]
 
 
 def test_finite_differences(fh):
-    # central differences of the FP64 GPU loss, h = 1e-7 m, on a seeded subset
-    # of the 384 coefficients
+    """Central differences of the FP64 GPU loss against the adjoint, on 32
+    seeded coefficients and one seeded random direction of all 384.  The bar
+    follows from the step: the truncation error of the h-difference is
+    estimated from the 2h-difference (their gap is 3/4 of the h^2 term's
+    growth), and the rounding noise of the loss, measured from two
+    evaluations at the same point (floored at 1e-15 |L|), enters as 2 e_L/h;
+    the adjoint's own error enters as the FP64 tolerance times the larger of
+    |g| and the gradient's rms component."""
     c = fh.Context("fp64")
     wl = workloads.workload(5, reduced=True)
     mask_t = torch.tensor(workloads.pupil_mask(wl.grid.n1), dtype=torch.float64, device="cuda")
@@ -142,15 +149,38 @@ def test_finite_differences(fh):
     L = _gpu_loss(c, wl, coef, mask_t)
     L.backward()
     grad = cpu(coef.grad)
-    h = 1e-7
-    idx = np.random.Generator(np.random.PCG64(23)).choice(len(grad), 6, replace=False)
+    base = coef.detach().clone()
     with torch.no_grad():
+        L0 = float(L)
+        L1 = float(_gpu_loss(c, wl, base, mask_t))
+        noise = max(abs(L1 - L0), 1e-15 * abs(L0))
+        h = 1e-7
+
+        def fd(d, step):
+            return (float(_gpu_loss(c, wl, base + step * d, mask_t)) -
+                    float(_gpu_loss(c, wl, base - step * d, mask_t))) / (2 * step)
+
+        rng = np.random.Generator(np.random.PCG64(23))
+        idx = rng.choice(len(grad), 32, replace=False)
+        dirs = []
         for i in idx:
-            cp = coef.detach().clone(); cp[i] += h
-            cm = coef.detach().clone(); cm[i] -= h
-            fd = (float(_gpu_loss(c, wl, cp, mask_t)) - float(_gpu_loss(c, wl, cm, mask_t))) / (2 * h)
-            print(f"  coef {i}: adjoint {grad[i]:.8e} fd {fd:.8e}", flush=True)
-            assert abs(fd - grad[i]) <= 1e-4 * np.abs(grad).max() + 1e-6 * abs(grad[i])
+            d = torch.zeros_like(base)
+            d[i] = 1.0
+            dirs.append((f"coef {i}", d, grad[i]))
+        v = rng.normal(size=len(grad))
+        v /= np.linalg.norm(v)
+        dirs.append(("random direction", torch.tensor(v, device="cuda"), float(grad @ v)))
+        # the adjoint's own error: the FP64 tolerance relative to the
+        # gradient's rms component (the bar of the parity test is relative L2)
+        g_rms = float(np.sqrt(np.mean(grad ** 2)))
+        worst = 0.0
+        for name, d, g in dirs:
+            f1, f2 = fd(d, h), fd(d, 2 * h)
+            bar = abs(f2 - f1) + 2 * noise / h + 1e-9 * max(abs(g), g_rms)
+            worst = max(worst, abs(f1 - g) / bar)
+            print(f"  {name}: adjoint {g:.10e} fd {f1:.10e} |diff| {abs(f1 - g):.2e} bar {bar:.2e}", flush=True)
+            assert abs(f1 - g) <= bar, name
+        print(f"  worst |diff|/bar {worst:.2f}", flush=True)
     c.close()
 
 

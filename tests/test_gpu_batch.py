@@ -126,3 +126,29 @@ def test_autotune_keeps_accuracy_and_caches(ctx, tmp_path):
     ref = oracle.fresnel_direct(x, y, w, wl.lam, wl.z, xi, eta)
     assert relL2(u, ref) <= TOL[ctx.precision]
     ctx.set_options(None)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_single_instance_batches_use_each_calls_parameters(fh, prec):
+    """Batched calls with one instance run eagerly: each call must use its
+    own rule and wavelength, not those of an earlier call with the same
+    shape of arguments (a captured graph would have baked them in)."""
+    ctx = fh.Context(prec)
+    s = workloads.workload(2).shape
+    n, h = 64, 0.03
+    xi, eta = oracle.grid_targets(n, n, h, h)
+    qa = ctx.quad_radial(s.r0, s.a, s.b, 8, 20, 40)
+    qb = ctx.quad_radial(0.8 * s.r0, 0.8 * s.a, 0.8 * s.b, 8, 20, 40)
+    xa, ya, wa = oracle.quad_radial(s.r0, s.a, s.b, 8, 20, 40)
+    xb, yb, wb = oracle.quad_radial(0.8 * s.r0, 0.8 * s.a, 0.8 * s.b, 8, 20, 40)
+    rules = {id(qa): (xa, ya, wa), id(qb): (xb, yb, wb)}
+    for q, lam, occ in ((qa, 1.0, 0), (qb, 0.7, 1), (qa, 0.9, 0), (qb, 1.1, 0)):
+        u = cpu(ctx.field_grid_batch([q], np.array([lam]), np.array([0.2]), n, n, h, h,
+                                     occulter=np.array([occ], dtype=np.int32)))
+        x, y, w = rules[id(q)]
+        ref = oracle.fresnel_direct(x, y, w, lam, 0.2, xi, eta)
+        got = 1 - u[0].ravel() if occ else u[0].ravel()
+        assert relL2(got, ref) <= TOL[prec], lam
+    qa.close()
+    qb.close()
+    ctx.close()
