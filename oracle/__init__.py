@@ -10,7 +10,9 @@ What it computes (Barnett, arXiv:2010.05978):
     for radial curves and general Fourier curves such as the kite of sec. 3.1;
     polygons with Gauss-Legendre nodes per edge);
   * the dilation areal rule (eqs. aqnod/aqwei, sec. 3.1) and the starshade
-    disc + petal rule (sec. 3.2), optionally with lateral edge perturbations;
+    disc + petal rule (sec. 3.2), optionally with lateral edge perturbations,
+    either deforming the petals or as the ideal rule plus signed ribbons
+    along the edges (sec. 5);
   * the direct quadrature sum (eq. faq) with the Babinet complement (eq. bab),
     also with a source term per node and a spherical incident wave;
   * the exact gradient of that sum with respect to nodes and weights, and its
@@ -82,6 +84,9 @@ def _load():
         lib.orc_starshade.argtypes = [i32, d, d, d, d, i32, i32, i32, i32, _dp, i32, _dp, _dp, _dp]
         lib.orc_fresnel_direct.argtypes = [_dp, _dp, _dp, i64, d, d, _dp, _dp, i64, i32, _dp]
         lib.orc_starshade_tab.argtypes = [i32, d, d, _dp, i32, i32, i32, i32, _dp, i32, _dp, _dp, _dp]
+        lib.orc_starshade_ribbon_size.argtypes = [i32, i32, i32, i32, i32, i32]
+        lib.orc_starshade_ribbon_size.restype = i64
+        lib.orc_starshade_ribbon.argtypes = [i32, d, d, d, d, i32, i32, i32, i32, _dp, i32, i32, _dp, _dp, _dp]
         lib.orc_starshade_rigid.argtypes = [i32, d, d, d, d, i32, i32, i32, i32, _dp, i32, i32, _dp, _dp, _dp]
         lib.orc_fresnel_direct_src.argtypes = [_dp, _dp, _dp, _dp, i64, d, d, d, _dp, _dp, i64, i32, _dp]
         lib.orc_fresnel_direct_vjp.argtypes = [_dp, _dp, _dp, i64, d, d, _dp, _dp, i64, i32,
@@ -103,7 +108,7 @@ def _load():
                      "orc_bdry_polygon", "orc_dilation", "orc_starshade",
                      "orc_fresnel_direct", "orc_fresnel_direct_vjp", "orc_starshade_vjp",
                      "orc_bdry_starshade", "orc_nsli", "orc_bdry_fourier", "orc_koch", "orc_fresnel_direct_src", "orc_starshade_rigid", "orc_starshade_tab",
-                     "orc_koch_outline"):
+                     "orc_koch_outline", "orc_starshade_ribbon"):
             getattr(lib, name).restype = i32
         _lib = lib
     return _lib
@@ -289,6 +294,19 @@ def quad_starshade_tab(Np, a, R, A, m, np_, nd, md, coef=None, K=0):
     out = np.empty((3, N))
     _check(_load().orc_starshade_tab(Np, a, R, _p(A), m, np_, nd, md, _p(coef), K if coef is not None else 0,
                                       _p(out[0]), _p(out[1]), _p(out[2])), "starshade_tab")
+    return out[0], out[1], out[2]
+
+
+def quad_starshade_ribbon(Np, a, R, b, p, m, np_, nd, md, coef, K, mr):
+    """Ideal starshade plus the signed ribbons between each petal's ideal
+    edges and its laterally displaced edges (sec. 5's ribbon construction);
+    mr Gauss-Legendre nodes across each ribbon, or mr = 0 for the line
+    integral on the ideal edge."""
+    coef = _f64(coef)
+    N = _load().orc_starshade_ribbon_size(Np, m, np_, nd, md, mr)
+    out = np.empty((3, N))
+    _check(_load().orc_starshade_ribbon(Np, a, R, b, p, m, np_, nd, md, _p(coef), K, mr,
+                                        _p(out[0]), _p(out[1]), _p(out[2])), "starshade_ribbon")
     return out[0], out[1], out[2]
 
 

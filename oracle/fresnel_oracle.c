@@ -20,6 +20,9 @@
  *   - the Babinet complement u_oc = 1 - u_ap (eq. bab),
  *   - the same sum with a source term per node and a spherical incident
  *     wave (secs. 1 and 5),
+ *   - the ribbon construction of sec. 5 (the ideal starshade plus signed
+ *     ribbons between each petal's ideal and displaced edges, with Gauss-
+ *     Legendre nodes across, or the line integral on the ideal edge),
  *   - the Koch snowflake rule of sec. 4.4 (a p x p dilation rule per
  *     triangle of the level-L construction),
  *   - the non-singular line integral over a boundary rule (appendix, eq.
@@ -335,6 +338,77 @@ int orc_starshade_tab(int Np, double a, double R, const double* Atab, int m, int
 {
     if (!Atab) return 1;
     return starshade_impl(Np, a, R, 1.0, 1.0, Atab, m, np, nd, md, coef, K, x, y, w);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Ribbon quadrature (sec. 5, the third construction): a perturbed shape is  */
+/* the ideal shape plus a narrow signed "ribbon" along its boundary.  For    */
+/* the starshade with the lateral edge displacements of orc_starshade (the   */
+/* upper edge of petal k moves outward by the arc length d+(r), the lower   */
+/* by d-(r)), the ribbon of the upper edge is the set of angles between the  */
+/* ideal edge theta_k + pi A(r)/Np and that angle plus d+(r)/r, the lower   */
+/* edge's between theta_k - pi A(r)/Np - d-(r)/r and the ideal edge.  The    */
+/* area element is r dr dphi, so with the petal's m Gauss-Legendre radii     */
+/* (weights wr_l) and mr Gauss-Legendre nodes tau_j on (0, 1) (weights v_j)  */
+/* across the ribbon: node r_l (cos phi, sin phi), phi = ideal edge angle   */
+/* +- tau_j d(r_l)/r_l, weight wr_l d(r_l) v_j, negative where the edge     */
+/* moved inward.  mr = 0 is the paper's line integral on the ideal boundary: */
+/* one node on the edge (tau = 0) with weight wr_l d(r_l), first order in    */
+/* the ribbon's width.  Rule: the unperturbed starshade (orc_starshade with  */
+/* no coefficients), then per petal the upper edge's ribbon and the lower    */
+/* edge's, each with the radial index inner and the across index outer.     */
+/* N = nd md + Np np m + 2 Np m max(mr, 1).                                 */
+/* ------------------------------------------------------------------------ */
+int64_t orc_starshade_ribbon_size(int Np, int m, int np, int nd, int md, int mr)
+{
+    return (int64_t)nd * md + (int64_t)Np * np * m + 2 * (int64_t)Np * m * (mr > 0 ? mr : 1);
+}
+
+int orc_starshade_ribbon(int Np, double a, double R, double b, double p, int m, int np, int nd, int md,
+                         const double* coef, int K, int mr, double* x, double* y, double* w)
+{
+    if (mr < 0 || !coef || K < 1) return 1;
+    int rc = orc_starshade(Np, a, R, b, p, m, np, nd, md, NULL, 0, x, y, w);
+    if (rc) return rc;
+    int nt = mr > 0 ? mr : 1;
+    double* rx = (double*)malloc(sizeof(double) * m);
+    double* rw = (double*)malloc(sizeof(double) * m);
+    double* tx = (double*)malloc(sizeof(double) * nt);
+    double* tw = (double*)malloc(sizeof(double) * nt);
+    orc_gauss_legendre(m, rx, rw);
+    if (mr > 0) {
+        orc_gauss_legendre(mr, tx, tw);
+        for (int j = 0; j < mr; j++) {  /* map [-1, 1] to (0, 1) */
+            tx[j] = 0.5 * (1.0 + tx[j]);
+            tw[j] = 0.5 * tw[j];
+        }
+    } else {
+        tx[0] = 0.0;  /* the node on the ideal edge */
+        tw[0] = 1.0;
+    }
+    int64_t j = (int64_t)nd * md + (int64_t)Np * np * m;
+    for (int k = 0; k < Np; k++) {
+        double thk = 2.0 * ORC_PI * k / Np;
+        for (int e = 0; e < 2; e++) {            /* 0: upper edge, 1: lower edge */
+            double sg = e == 0 ? 1.0 : -1.0;     /* outward is +phi above, -phi below */
+            for (int i = 0; i < nt; i++)
+                for (int l = 0; l < m; l++) {
+                    double r = a + 0.5 * (R - a) * (1.0 + rx[l]);
+                    double wr = 0.5 * (R - a) * rw[l];
+                    double d = 0.0;
+                    for (int s = 1; s <= K; s++)
+                        d += coef[2 * k * K + e * K + (s - 1)] * sin(s * ORC_PI * (r - a) / (R - a));
+                    double edge = thk + sg * ORC_PI * hg_profile(r, a, b, p) / Np;
+                    double phi = edge + sg * tx[i] * d / r;
+                    x[j] = r * cos(phi);
+                    y[j] = r * sin(phi);
+                    w[j] = wr * d * tw[i];
+                    j++;
+                }
+        }
+    }
+    free(rx); free(rw); free(tx); free(tw);
+    return 0;
 }
 
 /* ------------------------------------------------------------------------ */
