@@ -222,6 +222,24 @@ fh_status fh_quad_starshade_rigid(fh_ctx* ctx, int32_t Np, double a, double R, d
 fh_status fh_quad_from_nodes(fh_ctx* ctx, const double* x, const double* y, const double* w,
                              int64_t N, fh_memspace mem, fh_quad** out);
 
+/* Illumination of a rule (sec. 1 and sec. 5's source-plane extension):
+ *   src: a complex source term s_j per node multiplying its weight (a smooth
+ *     amplitude and phase over the source plane), N interleaved complex in
+ *     `mem`, or NULL for s_j = 1;
+ *   D: distance of a point source before the aperture (D > 0), whose
+ *     spherical incident wave exp(i pi |x|^2/(lambda D)) multiplies the
+ *     source chirp (z^-1 becomes z^-1 + D^-1 there, sec. 1); 0 for a plane
+ *     wave.
+ * Every later field call with the rule (grid, points, target sets, batches)
+ * evaluates u_ap = 1/(i lambda z) sum_j w_j s_j exp(i pi |x_j|^2/(lambda D))
+ * exp(i pi |xi - x_j|^2/(lambda z)); fh_field_grid_vjp refuses a rule with
+ * either (FH_ERR_UNSUPPORTED).  The call waits for all device work first
+ * (earlier calls may still read the old terms), copies src into library
+ * memory owned by the rule (released by fh_quad_destroy or a NULL src) and
+ * returns with the copy done; src may be released on return.  A non-finite
+ * host term is FH_ERR_NONFINITE; D < 0 is FH_ERR_INVALID_ARG. */
+fh_status fh_quad_set_illumination(fh_ctx* ctx, fh_quad* q, const double* src, double D, fh_memspace mem);
+
 fh_status fh_quad_size(const fh_quad* q, int64_t* N);
 /* Copy the rule out (x, y, w each N doubles; any may be NULL). */
 fh_status fh_quad_export(const fh_quad* q, double* x, double* y, double* w, fh_memspace mem);

@@ -30,6 +30,13 @@ class Quad:
     def N(self) -> int:
         return abi.fh_quad_size(self.handle)
 
+    def set_illumination(self, src=None, D: float = 0.0):
+        """Source term per node (N complex, or None) and point-source distance D (0: plane wave)."""
+        if src is not None and len(src) != self.N:
+            raise ValueError(f"src needs {self.N} values")
+        abi.fh_quad_set_illumination(self.ctx.handle, self.handle, src, D)
+        return self
+
     def export(self):
         """(x, y, w) as float64 device tensors (copies)."""
         import torch

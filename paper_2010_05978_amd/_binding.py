@@ -39,7 +39,7 @@ EXPORTED = [
     "fh_starshade_vjp", "fh_autotune_grid", "fh_set_timing", "fh_last_timing", "fh_timing_totals",
     "fh_boundary_radial", "fh_boundary_polygon", "fh_boundary_starshade", "fh_field_nsli",
     "fh_quad_fourier", "fh_boundary_fourier", "fh_quad_koch", "fh_quad_starshade_rigid",
-    "fh_quad_starshade_tab", "fh_targets_sort", "fh_probe_ceilings",
+    "fh_quad_starshade_tab", "fh_targets_sort", "fh_probe_ceilings", "fh_quad_set_illumination",
 ]
 
 
@@ -110,6 +110,7 @@ def lib():
             "fh_quad_starshade_tab": [vp, i32, d, d, vp, i32, i32, i32, i32, vp, i32, ctypes.c_int, pvp],
             "fh_boundary_fourier": [vp, i32, vp, vp, vp, vp, i32, i32, vp, vp, vp, vp, ctypes.c_int],
             "fh_probe_ceilings": [vp, ctypes.POINTER(d)],
+            "fh_quad_set_illumination": [vp, vp, vp, d, ctypes.c_int],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -272,6 +273,21 @@ def fh_quad_device_ptrs(q):
     x, y, w = ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_void_p()
     _check(lib().fh_quad_device_ptrs(q, ctypes.byref(x), ctypes.byref(y), ctypes.byref(w)))
     return x.value, y.value, w.value
+
+
+def fh_quad_set_illumination(ctx, q, src=None, D=0.0):
+    """src: None, or N complex128 values (numpy array or torch tensor); D: point-source distance (0: plane)."""
+    if src is None:
+        _check(lib().fh_quad_set_illumination(ctx, q, None, float(D), FH_MEM_HOST))
+        return
+    if _is_torch(src):
+        import torch
+        t = src.detach().to(torch.complex128).contiguous()
+        ptr, mem = _ptr_mem(torch.view_as_real(t))
+        _check(lib().fh_quad_set_illumination(ctx, q, ptr, float(D), mem))
+        return
+    a = np.ascontiguousarray(np.asarray(src, dtype=np.complex128))
+    _check(lib().fh_quad_set_illumination(ctx, q, a.ctypes.data_as(ctypes.c_void_p), float(D), FH_MEM_HOST))
 
 
 def fh_quad_destroy(q):

@@ -384,6 +384,8 @@ fh_status fh_field_grid_vjp(fh_ctx* c, const fh_quad* q, double lambda, double z
         FH_TRY(check_lz(lambda, z));
         FH_TRY(check_grid(n1, n2, h1, h2, xc, yc));
         FH_ARG(q->N < ((int64_t)1 << 31), FH_ERR_UNSUPPORTED, "at most 2^31 - 1 nodes per call");
+        FH_ARG(!q->src && !(q->D > 0.0), FH_ERR_UNSUPPORTED,
+               "the adjoint covers plane-wave illumination without source terms");
         FH_HIP(hipSetDevice(c->device));
         if (c->prec == FH_FP64)
             return grid_vjp_impl<double>(c, q, lambda, z, n1, n2, h1, h2, xc, yc, occulter, g_u, g_x, g_y, g_w);

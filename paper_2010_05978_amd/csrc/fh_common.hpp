@@ -93,6 +93,7 @@ struct InvPhiCheb {
 //   phase in turns: t = (x^2 + y^2) pa + x px + y py + pc
 //   fine-grid coordinate: g1 = (x - cx) s1, g2 = (y - cy) s2 - sh2, where the
 //   integer sh2 is the first fine-grid row of the instance's window
+//   src: the rule's source term per node (N interleaved complex), or null
 struct InstParams {
     const double* x;
     const double* y;
@@ -103,6 +104,7 @@ struct InstParams {
     int32_t sh2;
     double pa, px, py, pc;
     double cx, cy, s1, s2;
+    const double* src;
 };
 
 struct GridGeom {
@@ -218,6 +220,11 @@ struct fh_quad {
     double* x = nullptr;
     double* y = nullptr;
     double* w = nullptr;
+    // Illumination (fh_quad_set_illumination): a source term per node (N
+    // interleaved complex in its own allocation, never pooled) or null, and
+    // the distance D of a point source (0: plane wave).
+    double* src = nullptr;
+    double D = 0.0;
     bool bbox_valid = false;
     double bbox[4] = {0, 0, 0, 0};  // xmin, xmax, ymin, ymax
 };

@@ -462,8 +462,10 @@ fh_status t3_core(fh_ctx* c, const fh_quad* q, double lambda, double z, int64_t 
     ip.y = q->y;
     ip.w = q->w;
     ip.N = N;
-    // chirp and pre-phase exp(-i D.(x - C)), D = 2 pi (target centre)/(lambda z)
-    ip.pa = 0.5 / lz;
+    // chirp and pre-phase exp(-i D.(x - C)), D = 2 pi (target centre)/(lambda z),
+    // and the incident wave of a point source at the rule's distance
+    ip.pa = 0.5 / lz + (q->D > 0.0 ? 0.5 / (lambda * q->D) : 0.0);
+    ip.src = q->src;
     ip.px = -d1.ctr / lz;
     ip.py = -d2.ctr / lz;
     ip.pc = (d1.ctr * d1.C + d2.ctr * d2.C) / lz;

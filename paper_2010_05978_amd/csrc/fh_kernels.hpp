@@ -390,8 +390,8 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_tiles(const int* __restri
     if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) *nsub_out = base_b + tb;
 }
 
-// Strength (FP64 phase in turns, reduced), stencil offsets, and the sorted
-// position of each node.
+// Strength (FP64 phase in turns, reduced, times the node's source term when
+// the rule has one), stencil offsets, and the sorted position of each node.
 template <class R>
 __global__ void __launch_bounds__(256) k_bin_place(InstParams p0, const InstParams* __restrict__ table, int ninst,
                                                    int64_t Ntot, GridGeom gg, const int* __restrict__ cnt,
@@ -419,14 +419,23 @@ __global__ void __launch_bounds__(256) k_bin_place(InstParams p0, const InstPara
     const double f = t - rint(t);
     double s, c;
     sincospi(2.0 * f, &s, &c);
+    double cr = w * c, ci = w * s;
+    if (ip.src && jj < ip.N) {
+        // the node's source term multiplies its strength (jj < N always
+        // holds: j lies in this instance's node range)
+        const double sr = ip.src[2 * jj], si = ip.src[2 * jj + 1];
+        const double tr = cr * sr - ci * si;
+        ci = cr * si + ci * sr;
+        cr = tr;
+    }
     const int rk = rank[j];
     const int pos = off[tile] + rk;
     cell[pos] = (uint32_t)l1 | ((uint32_t)l2 << 16);
     typename V2<R>::T dv, cv;
     dv.x = (R)d1;
     dv.y = (R)d2;
-    cv.x = (R)(w * c);
-    cv.y = (R)(w * s);
+    cv.x = (R)cr;
+    cv.y = (R)ci;
     dd[pos] = dv;
     cc[pos] = cv;
     // the point that opens a work item of its tile writes the item
@@ -1939,8 +1948,10 @@ InstParams inst_t1(const fh_quad* q, double lambda, double z, double h1, double 
     ip.w = q->w;
     ip.N = q->N;
     // source chirp with the pre-phase of a grid centred at (xc, yc):
-    // pi (|x|^2 - 2 (xc x + yc y)) / (lambda z), in turns
-    ip.pa = 0.5 / lz;
+    // pi (|x|^2 - 2 (xc x + yc y)) / (lambda z), in turns; a point source at
+    // distance D adds pi |x|^2/(lambda D) (its incident wave)
+    ip.pa = 0.5 / lz + (q->D > 0.0 ? 0.5 / (lambda * q->D) : 0.0);
+    ip.src = q->src;
     ip.px = -xc / lz;
     ip.py = -yc / lz;
     ip.pc = 0.0;

@@ -533,6 +533,82 @@ void set_bbox(fh_quad* q, double x0, double x1, double y0, double y1)
     q->bbox_valid = true;
 }
 
+// A box holding every node of a dilation rule: each node is alpha (X_i, Y_i)
+// with 0 < alpha < 1, so the box of the boundary nodes and the origin holds
+// them all.  The boundary nodes are evaluated on the host at the rule's own
+// parameters t_i (Gauss-Legendre panels, or the trapezoid rule when panels is
+// 0), curve(t, X, Y) giving the point; the box is widened by a relative 1e-9
+// for the rounding of either side.  A tight box keeps the type-1 row window
+// (and with it the FFT and the column pass) as small as the shape allows.
+template <class Curve>
+void boundary_box(int64_t n, int panels, int q, Curve curve, double* box)
+{
+    std::vector<double> gx, gw;
+    if (panels > 0) gl_host(q, gx, gw);
+    double b[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t i = 0; i < n; ++i) {
+        double t;
+        if (panels > 0) {
+            const int64_t p = i / q;
+            const int k = (int)(i - p * q);
+            t = (2.0 * kPi / panels) * ((double)p + 0.5 * (1.0 + gx[k]));
+        } else {
+            t = 2.0 * kPi * (double)(i + 1) / (double)n;
+        }
+        double X, Y;
+        curve(t, X, Y);
+        b[0] = std::min(b[0], X);
+        b[1] = std::max(b[1], X);
+        b[2] = std::min(b[2], Y);
+        b[3] = std::max(b[3], Y);
+    }
+    const double pad = 1e-9 * (std::max({-b[0], b[1], -b[2], b[3]}) + 1.0);
+    box[0] = b[0] - pad;
+    box[1] = b[1] + pad;
+    box[2] = b[2] - pad;
+    box[3] = b[3] + pad;
+}
+
+// cos kt and sin kt for k = 1..K by the rotation recurrence, into c[], s[].
+inline void harmonics(double t, int K, double* c, double* s)
+{
+    const double c1 = std::cos(t), s1 = std::sin(t);
+    double ck = 1.0, sk = 0.0;
+    for (int k = 1; k <= K; ++k) {
+        const double cn = ck * c1 - sk * s1;
+        sk = sk * c1 + ck * s1;
+        ck = cn;
+        c[k] = ck;
+        s[k] = sk;
+    }
+}
+
+void radial_box(const RadialParams& rp, int64_t n, double* box)
+{
+    boundary_box(n, rp.panels, rp.q, [&](double t, double& X, double& Y) {
+        double c[kMaxFourier + 1], s[kMaxFourier + 1];
+        harmonics(t, rp.K, c, s);
+        double r = rp.r0;
+        for (int k = 1; k <= rp.K; ++k) r += rp.a[k - 1] * c[k] + rp.b[k - 1] * s[k];
+        X = r * std::cos(t);
+        Y = r * std::sin(t);
+    }, box);
+}
+
+void fourier_box(const FourierParams& fp, int64_t n, double* box)
+{
+    boundary_box(n, fp.panels, fp.q, [&](double t, double& X, double& Y) {
+        double c[kMaxFourier + 1], s[kMaxFourier + 1];
+        harmonics(t, fp.K, c, s);
+        X = fp.ax[0];
+        Y = fp.ay[0];
+        for (int k = 1; k <= fp.K; ++k) {
+            X += fp.ax[k] * c[k] + fp.bx[k] * s[k];
+            Y += fp.ay[k] * c[k] + fp.by[k] * s[k];
+        }
+    }, box);
+}
+
 fh_status radial_into(fh_ctx* c, const RadialParams& rp, int64_t n, int m, double* x, double* y,
                       double* w)
 {
@@ -725,10 +801,9 @@ fh_status fh_quad_radial(fh_ctx* c, double r0, const double* a, const double* b,
             fh_quad_destroy(qd);
             return s;
         }
-        // every node is alpha x(t) with 0 < alpha < 1 and |x(t)| <= |r0| + sum |a_k| + |b_k|
-        double rmax = std::fabs(r0);
-        for (int k = 0; k < K; ++k) rmax += std::fabs(rp.a[k]) + std::fabs(rp.b[k]);
-        set_bbox(qd, -rmax, rmax, -rmax, rmax);
+        double box[4];
+        radial_box(rp, n, box);
+        set_bbox(qd, box[0], box[1], box[2], box[3]);
         *out = qd;
         return FH_OK;
     } catch (...) {
@@ -1060,6 +1135,7 @@ fh_status fh_quad_fourier(fh_ctx* c, int32_t K, const double* ax, const double* 
         double box[4];
         FH_TRY(fourier_params(ax, bx, ay, by, K, panels, q, &fp, box));
         const int64_t n = panels > 0 ? (int64_t)panels * q : q;
+        fourier_box(fp, n, box);
         FH_HIP(hipSetDevice(c->device));
         const double* glq = nullptr;
         const double* glm = nullptr;
@@ -1241,9 +1317,54 @@ fh_status fh_quad_device_ptrs(const fh_quad* q, const double** x, const double**
     return FH_OK;
 }
 
+fh_status fh_quad_set_illumination(fh_ctx* c, fh_quad* q, const double* src, double D, fh_memspace mem)
+{
+    try {
+        FH_ARG(c && q, FH_ERR_INVALID_ARG, "NULL argument");
+        FH_ARG(q->ctx->device == c->device, FH_ERR_INVALID_ARG, "quadrature lives on another device");
+        FH_ARG(mem == FH_MEM_HOST || mem == FH_MEM_DEVICE, FH_ERR_INVALID_ARG, "bad memspace");
+        FH_ARG(std::isfinite(D), FH_ERR_NONFINITE, "D not finite");
+        FH_ARG(D >= 0.0, FH_ERR_INVALID_ARG, "D must be >= 0 (0: plane wave)");
+        FH_HIP(hipSetDevice(c->device));
+        const size_t bytes = 2 * sizeof(double) * (size_t)q->N;
+        if (src && mem == FH_MEM_HOST) {
+            for (int64_t j = 0; j < 2 * q->N; ++j)
+                FH_ARG(std::isfinite(src[j]), FH_ERR_NONFINITE, "source term %lld not finite", (long long)(j / 2));
+        }
+        // Every call that may read the old terms, on any stream, has finished
+        // before they are replaced or released; the copy below is synchronous.
+        FH_HIP(hipDeviceSynchronize());
+        if (q->src && (!src || q->N == 0)) {
+            FH_TRY(dev_free(q->ctx, q->src));
+            q->src = nullptr;
+        }
+        if (src && q->N > 0) {
+            if (!q->src) {
+                void* p = nullptr;
+                FH_TRY(dev_alloc(q->ctx, bytes, &p));
+                q->src = static_cast<double*>(p);
+            }
+            FH_HIP(hipMemcpy(q->src, src, bytes, mem == FH_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice));
+        }
+        q->D = D;
+        return FH_OK;
+    } catch (...) {
+        set_error("host allocation failed");
+        return FH_ERR_ALLOC;
+    }
+}
+
 fh_status fh_quad_destroy(fh_quad* q)
 {
     if (!q) return FH_OK;
+    if (q->src) {
+        // the source terms are released at once (not pooled): every call
+        // that may still read them finishes first
+        (void)hipSetDevice(q->ctx->device);
+        (void)hipDeviceSynchronize();
+        (void)dev_free(q->ctx, q->src);
+        q->src = nullptr;
+    }
     try {
         // keep the buffer for the next rule of the same size: work already
         // enqueued on the context stream that reads it stays ordered before

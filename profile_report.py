@@ -8,7 +8,9 @@
                                    --source-hash HASH --out FILE.json [--command "..."]
       HBM bytes per launch of one kernel from a FETCH_SIZE run and a WRITE_SIZE
       run (KiB per dispatch), each scaled by what the same counter reads for a
-      plain 256 MiB device copy in the same run (bench.py --pmc-calib).
+      plain device copy of known size in the same run: the 1 GiB copy of
+      fh_probe_ceilings (k_probe_copy), which bench.py runs first, or else the
+      256 MiB torch copy of bench.py --pmc-calib.
 """
 from __future__ import annotations
 
@@ -44,20 +46,27 @@ def counter_per_dispatch(db, counter, substr):
     return mine, rows
 
 
+PROBE_COPY_BYTES = 1024 * 1024 * 1024
+
+
 def copy_counter(rows):
-    # the largest-volume elementwise copy kernel in the run is the calibration copy
+    """(counter KiB, bytes) of the calibration copy: the probe's plain 1 GiB
+    copy when present, else the largest elementwise copy (256 MiB)."""
+    probe = [v for n, v in rows if "k_probe_copy(" in n]
+    if probe:
+        return min(probe), PROBE_COPY_BYTES
     cand = [v for n, v in rows if "copy" in n.lower() or "elementwise" in n.lower()]
-    return max(cand) if cand else None
+    return (max(cand), COPY_BYTES) if cand else (None, None)
 
 
 def cmd_traffic(a):
     f_mine, f_rows = counter_per_dispatch(a.fetch, "FETCH_SIZE", a.kernel)
     w_mine, w_rows = counter_per_dispatch(a.write, "WRITE_SIZE", a.kernel)
-    f_copy, w_copy = copy_counter(f_rows), copy_counter(w_rows)
+    (f_copy, f_bytes), (w_copy, w_bytes) = copy_counter(f_rows), copy_counter(w_rows)
     if not f_mine or not w_mine or not f_copy or not w_copy:
         raise SystemExit("kernel or calibration copy not found in the counter runs")
-    f_scale = COPY_BYTES / (f_copy * 1024.0)
-    w_scale = COPY_BYTES / (w_copy * 1024.0)
+    f_scale = f_bytes / (f_copy * 1024.0)
+    w_scale = w_bytes / (w_copy * 1024.0)
     fetch = statistics.mean(f_mine) * 1024.0 * f_scale
     write = statistics.mean(w_mine) * 1024.0 * w_scale
     out = {"kernel_substring": a.kernel, "kernel": a.kernel_label or a.kernel, "source_hash": a.source_hash,
