@@ -396,6 +396,25 @@ fh_status fh_field_nsli(fh_ctx* ctx, const double* X, const double* Y, const dou
                         int64_t n, double lambda, double z, int64_t M, const double* xi,
                         const double* eta, double far, int32_t occulter, void* u, fh_memspace mem);
 
+/* Allocation-free form of fh_field_nsli, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, hosts
+ * that forbid hipMalloc.  Same arguments and result as fh_field_nsli with
+ * every array in device memory (X, Y, W, V: n doubles each; xi, eta: M
+ * doubles; u: M complex in the context's precision), enqueued on the context
+ * stream without synchronising.  It calls no allocator: when the targets are
+ * few enough that the nodes are split into groups, the groups' partial sums
+ * (4 x groups x M doubles) go to a 32 MiB device array that the library holds
+ * on each device until the process ends, shared by every call on that
+ * device, so calls that overlap on one device (two streams, two threads)
+ * race and must be ordered by the caller.  With fh_field_nsli's choice of
+ * node groups the partial sums stay below 32 MiB on devices of up to 320 CUs
+ * (MI355X has 256); a call whose partial sums would exceed it returns
+ * FH_ERR_UNSUPPORTED without enqueuing anything. */
+fh_status fh_field_nsli_noalloc(fh_ctx* ctx, const double* X, const double* Y, const double* W,
+                                const double* V, int64_t n, double lambda, double z, int64_t M,
+                                const double* xi, const double* eta, double far, int32_t occulter,
+                                void* u);
+
 /* --------------------------------------------------------------- autotuner */
 
 /* Time fh_field_grid for this rule and grid over a set of tile sizes,

@@ -40,6 +40,7 @@ EXPORTED = [
     "fh_boundary_radial", "fh_boundary_polygon", "fh_boundary_starshade", "fh_field_nsli",
     "fh_quad_fourier", "fh_boundary_fourier", "fh_quad_koch", "fh_quad_starshade_rigid",
     "fh_quad_starshade_tab", "fh_targets_sort", "fh_probe_ceilings", "fh_quad_set_illumination",
+    "fh_field_nsli_noalloc",
 ]
 
 
@@ -111,6 +112,7 @@ def lib():
             "fh_boundary_fourier": [vp, i32, vp, vp, vp, vp, i32, i32, vp, vp, vp, vp, ctypes.c_int],
             "fh_probe_ceilings": [vp, ctypes.POINTER(d)],
             "fh_quad_set_illumination": [vp, vp, vp, d, ctypes.c_int],
+            "fh_field_nsli_noalloc": [vp, vp, vp, vp, vp, i64, d, d, i64, vp, vp, d, i32, vp],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -408,6 +410,18 @@ def fh_field_nsli(ctx, B, lam, z, xi, eta, far, occulter, u):
     _check(lib().fh_field_nsli(ctx, _ptr_mem(X)[0], _ptr_mem(Y)[0], _ptr_mem(W)[0], _ptr_mem(V)[0], X.shape[0],
                                lam, z, len(xi), _ptr_mem(xi)[0], _ptr_mem(eta)[0], float(far),
                                int(bool(occulter)), _ptr_mem(u)[0], mem))
+
+
+def fh_field_nsli_noalloc(ctx, B, lam, z, xi, eta, far, occulter, u):
+    """As fh_field_nsli, device arrays only; the library allocates nothing."""
+    X, Y, W, V = _rows4(B)
+    if len(xi) != len(eta):
+        raise ValueError("xi and eta must have the same length")
+    if _same_mem(X, Y, W, V, xi, eta, u) != FH_MEM_DEVICE:
+        raise ValueError("fh_field_nsli_noalloc takes device arrays only")
+    _check(lib().fh_field_nsli_noalloc(ctx, _ptr_mem(X)[0], _ptr_mem(Y)[0], _ptr_mem(W)[0], _ptr_mem(V)[0],
+                                       X.shape[0], lam, z, len(xi), _ptr_mem(xi)[0], _ptr_mem(eta)[0],
+                                       float(far), int(bool(occulter)), _ptr_mem(u)[0]))
 
 
 def fh_targets_create(ctx, xi, eta, box=None):

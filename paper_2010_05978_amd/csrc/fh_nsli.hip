@@ -24,6 +24,7 @@
 // targets alone give fewer than two workgroups per CU, the nodes are split
 // into groups whose partial sums a second kernel adds in a fixed order.
 #include <algorithm>
+#include <mutex>
 
 #include "fh_common.hpp"
 
@@ -31,6 +32,34 @@ namespace fh {
 namespace {
 
 constexpr int kNsliBlock = 256;
+
+// Device scratch of the allocation-free edge integral (fh_field_nsli_noalloc):
+// the node groups' partial sums, 4 groups M doubles, at most 32 MiB.  Each
+// device holds its own copy until the process ends; every call on a device
+// shares it.  Host code never uses the array's name as an address: the
+// device's copy is found with hipGetSymbolAddress on the first call there.
+constexpr size_t kNsliScratchDoubles = size_t(4) << 20;
+static __device__ __align__(256) double scratch[kNsliScratchDoubles];
+
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kScratchDevices] = {};
+
+// The address of this device's scratch (the device must be current).
+fh_status scratch_for(int device, double** out)
+{
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    FH_ARG(device >= 0 && device < kScratchDevices, FH_ERR_UNSUPPORTED, "device %d beyond the %d supported", device,
+           kScratchDevices);
+    if (!g_scratch_ptr[device]) {
+        void* p = nullptr;
+        FH_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        FH_ARG(p != nullptr, FH_ERR_HIP, "no device address for the scratch array");
+        g_scratch_ptr[device] = static_cast<double*>(p);
+    }
+    *out = g_scratch_ptr[device];
+    return FH_OK;
+}
 constexpr double kNsliTiny = 1e-280;  // floor of r^2 before its reciprocal
 
 struct NsliParams {
@@ -244,6 +273,58 @@ fh_status nsli_launch(fh_ctx* c, NsliParams p, OUT* u)
     return FH_OK;
 }
 
+// Node groups: split the nodes only when the targets alone give fewer than
+// two workgroups per CU (then aim at four), at least 64 nodes each;
+// otherwise the partial sums would cost a second pass for nothing.  Returns
+// the number of non-empty groups and the nodes per group (at least 1, also
+// for an empty rule).
+void nsli_groups(const fh_ctx* c, int64_t n, int64_t M, int* groups_out, int64_t* per_out)
+{
+    const int64_t bx = (M + kNsliBlock * kNsliTpt - 1) / (kNsliBlock * kNsliTpt);
+    int groups = 1;
+    if (bx < 2LL * c->cu_count && n > 128)
+        groups = (int)std::min<int64_t>({(4LL * c->cu_count + bx - 1) / bx, n / 64, 1024});
+    groups = std::max(groups, 1);
+    const int64_t per = std::max<int64_t>(1, (n + groups - 1) / groups);
+    *groups_out = (int)std::max<int64_t>(1, (n + per - 1) / per);
+    *per_out = per;
+}
+
+fh_status nsli_check(const fh_ctx* c, const double* X, const double* Y, const double* W, const double* V, int64_t n,
+                     double lambda, double z, int64_t M, const double* xi, const double* eta, double far,
+                     const void* u)
+{
+    FH_ARG(c, FH_ERR_INVALID_ARG, "NULL context");
+    FH_ARG(n >= 0 && M >= 0, FH_ERR_INVALID_ARG, "negative size");
+    FH_ARG(n < ((int64_t)1 << 40) && M < ((int64_t)1 << 40), FH_ERR_INVALID_ARG, "size too large");
+    FH_ARG(n == 0 || (X && Y && W && V), FH_ERR_INVALID_ARG, "NULL boundary array");
+    FH_ARG(M == 0 || (xi && eta && u), FH_ERR_INVALID_ARG, "NULL target or output array");
+    FH_ARG(std::isfinite(lambda) && std::isfinite(z) && std::isfinite(far), FH_ERR_NONFINITE,
+           "lambda, z or far not finite");
+    FH_ARG(lambda * z > 0, FH_ERR_NONPOSITIVE_LZ, "lambda * z must be positive");
+    FH_ARG(far >= 0, FH_ERR_INVALID_ARG, "far must be >= 0");
+    return FH_OK;
+}
+
+NsliParams nsli_params(const double* X, const double* Y, const double* W, const double* V, int64_t n, double lambda,
+                       double z, int64_t M, const double* xi, const double* eta, double far, int32_t occulter,
+                       int groups, int64_t per)
+{
+    NsliParams p{};
+    p.X = X; p.Y = Y; p.W = W; p.V = V;
+    p.n = n;
+    p.xi = xi; p.eta = eta;
+    p.M = M;
+    p.inv2lz = 1.0 / (2.0 * lambda * z);
+    p.far2 = far * far;
+    p.shadow = far > 0;
+    p.occulter = occulter != 0;
+    p.groups = groups;
+    p.per = per;
+    p.part = nullptr;
+    return p;
+}
+
 }  // namespace
 }  // namespace fh
 
@@ -256,33 +337,15 @@ fh_status fh_field_nsli(fh_ctx* c, const double* X, const double* Y, const doubl
                         int32_t occulter, void* u, fh_memspace mem)
 {
     try {
-        FH_ARG(c, FH_ERR_INVALID_ARG, "NULL context");
-        FH_ARG(n >= 0 && M >= 0, FH_ERR_INVALID_ARG, "negative size");
-        FH_ARG(n < ((int64_t)1 << 40) && M < ((int64_t)1 << 40), FH_ERR_INVALID_ARG, "size too large");
-        FH_ARG(n == 0 || (X && Y && W && V), FH_ERR_INVALID_ARG, "NULL boundary array");
-        FH_ARG(M == 0 || (xi && eta && u), FH_ERR_INVALID_ARG, "NULL target or output array");
+        FH_TRY(nsli_check(c, X, Y, W, V, n, lambda, z, M, xi, eta, far, u));
         FH_ARG(mem == FH_MEM_HOST || mem == FH_MEM_DEVICE, FH_ERR_INVALID_ARG, "bad memspace");
-        FH_ARG(std::isfinite(lambda) && std::isfinite(z) && std::isfinite(far), FH_ERR_NONFINITE,
-               "lambda, z or far not finite");
-        FH_ARG(lambda * z > 0, FH_ERR_NONPOSITIVE_LZ, "lambda * z must be positive");
-        FH_ARG(far >= 0, FH_ERR_INVALID_ARG, "far must be >= 0");
         if (M == 0) return FH_OK;
         FH_HIP(hipSetDevice(c->device));
         const bool mixed = c->prec == FH_MIXED;
         const size_t usz = (mixed ? sizeof(float) : sizeof(double)) * 2 * (size_t)M;
-
-        // node groups: split the nodes only when the targets alone give fewer
-        // than two workgroups per CU (then aim at four), at least 64 nodes each;
-        // otherwise the partial sums would cost a second pass for nothing
-        const int64_t bx = (M + kNsliBlock * kNsliTpt - 1) / (kNsliBlock * kNsliTpt);
-        int groups = 1;
-        if (bx < 2LL * c->cu_count && n > 128)
-            groups = (int)std::min<int64_t>({(4LL * c->cu_count + bx - 1) / bx, n / 64, 1024});
-        groups = std::max(groups, 1);
-        // nodes per group (at least 1, also for an empty rule), then the
-        // number of non-empty groups
-        const int64_t per = std::max<int64_t>(1, (n + groups - 1) / groups);
-        groups = (int)std::max<int64_t>(1, (n + per - 1) / per);
+        int groups;
+        int64_t per;
+        nsli_groups(c, n, M, &groups, &per);
 
         size_t need = 0;
         if (groups > 1) need += aligned_bytes(sizeof(double) * 4 * (size_t)groups * M);
@@ -290,17 +353,7 @@ fh_status fh_field_nsli(fh_ctx* c, const double* X, const double* Y, const doubl
             need += 4 * aligned_bytes(sizeof(double) * std::max<int64_t>(n, 1)) +
                     2 * aligned_bytes(sizeof(double) * M) + aligned_bytes(usz);
         FH_TRY(arena_reserve(c, need));
-        NsliParams p{};
-        p.X = X; p.Y = Y; p.W = W; p.V = V;
-        p.n = n;
-        p.xi = xi; p.eta = eta;
-        p.M = M;
-        p.inv2lz = 1.0 / (2.0 * lambda * z);
-        p.far2 = far * far;
-        p.shadow = far > 0;
-        p.occulter = occulter != 0;
-        p.groups = groups;
-        p.per = per;
+        NsliParams p = nsli_params(X, Y, W, V, n, lambda, z, M, xi, eta, far, occulter, groups, per);
         p.part = groups > 1 ? c->arena.take<double>(4 * (size_t)groups * M) : nullptr;
         void* dout = u;
         if (mem == FH_MEM_HOST) {
@@ -328,6 +381,37 @@ fh_status fh_field_nsli(fh_ctx* c, const double* X, const double* Y, const doubl
             FH_HIP(hipMemcpyAsync(u, dout, usz, hipMemcpyDeviceToHost, c->stream));
             FH_HIP(hipStreamSynchronize(c->stream));
         }
+        return FH_OK;
+    } catch (...) {
+        set_error("host allocation failed");
+        return FH_ERR_ALLOC;
+    }
+}
+
+fh_status fh_field_nsli_noalloc(fh_ctx* c, const double* X, const double* Y, const double* W, const double* V,
+                                int64_t n, double lambda, double z, int64_t M, const double* xi, const double* eta,
+                                double far, int32_t occulter, void* u)
+{
+    try {
+        FH_TRY(nsli_check(c, X, Y, W, V, n, lambda, z, M, xi, eta, far, u));
+        if (M == 0) return FH_OK;
+        FH_HIP(hipSetDevice(c->device));
+        int groups;
+        int64_t per;
+        nsli_groups(c, n, M, &groups, &per);
+        NsliParams p = nsli_params(X, Y, W, V, n, lambda, z, M, xi, eta, far, occulter, groups, per);
+        if (groups > 1) {
+            const size_t want = 4 * (size_t)groups * (size_t)M;
+            FH_ARG(want <= kNsliScratchDoubles, FH_ERR_UNSUPPORTED,
+                   "the edge integral's partial sums need %zu bytes (%d node groups x %lld targets), beyond the "
+                   "%zu-byte device scratch of the allocation-free call",
+                   want * sizeof(double), groups, (long long)M, kNsliScratchDoubles * sizeof(double));
+            FH_TRY(scratch_for(c->device, &p.part));
+        }
+        if (c->prec == FH_MIXED)
+            FH_TRY(nsli_launch(c, p, static_cast<float*>(u)));
+        else
+            FH_TRY(nsli_launch(c, p, static_cast<double*>(u)));
         return FH_OK;
     } catch (...) {
         set_error("host allocation failed");
