@@ -195,6 +195,25 @@ fh_status fh_quad_starshade(fh_ctx* ctx, int32_t Np, double a, double R, double 
                             const double* coef, int32_t K, fh_memspace coef_mem,
                             fh_quad** out);
 
+/* Ribbon form of the perturbed starshade (sec. 5, the third construction):
+ * the unperturbed rule of fh_quad_starshade (same parameters), followed by,
+ * for each petal k, the signed ribbon between its upper edge and that edge
+ * moved outward by the arc length d+(r) and then the ribbon of its lower
+ * edge for d-(r) (coef and K as for fh_quad_starshade, required here).  The
+ * ribbon of an edge with ideal angle phi_e(r) covers the angles between
+ * phi_e(r) and phi_e(r) +- d(r)/r (+ for the upper edge); it gets the
+ * petal's m Gauss-Legendre radii times mr Gauss-Legendre nodes tau in (0, 1)
+ * across, node r (cos phi, sin phi) with phi = phi_e +- tau d/r and weight
+ * w_r d(r) w_tau (negative where the edge moved inward), across index outer
+ * and radial index inner.  mr = 0 gives the paper's line integral on the
+ * ideal boundary: one node on the edge with weight w_r d(r), whose error is
+ * second order in the ribbon's width.  The ideal part does not depend on
+ * the perturbation, so perturbation studies change only the ribbon nodes.
+ * N = nd md + Np np m + 2 Np m max(mr, 1). */
+fh_status fh_quad_starshade_ribbon(fh_ctx* ctx, int32_t Np, double a, double R, double b, double p,
+                                   int32_t m, int32_t np, int32_t nd, int32_t md, const double* coef,
+                                   int32_t K, fh_memspace coef_mem, int32_t mr, fh_quad** out);
+
 /* As fh_quad_starshade with a tabulated apodisation instead of the HG family
  * (the paper's NI2 design is given as samples of A(r), interpolated to the
  * radial Gauss nodes, sec. 4.2): A holds m host doubles, A[l] = A(r_l) at

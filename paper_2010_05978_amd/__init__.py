@@ -121,6 +121,11 @@ class Context:
         """Starshade with a tabulated apodisation A[l] = A(r_l) at the m radial Gauss nodes."""
         return Quad(self, abi.fh_quad_starshade_tab(self.handle, Np, a, R, A, m, np_, nd, md, coef, K))
 
+    def quad_starshade_ribbon(self, Np, a, R, b, p, m, np_, nd, md, coef, K, mr=2) -> Quad:
+        """Ideal starshade plus signed ribbons along the displaced petal edges (sec. 5);
+        mr nodes across each ribbon, or mr = 0 for the line integral on the ideal edge."""
+        return Quad(self, abi.fh_quad_starshade_ribbon(self.handle, Np, a, R, b, p, m, np_, nd, md, coef, K, mr))
+
     def quad_starshade_rigid(self, Np, a, R, b, p, m, np_, nd, md, motion, nb=16, mb=4) -> Quad:
         """Starshade whose petals moved rigidly (motion: Np rows of angle, tx, ty)."""
         return Quad(self, abi.fh_quad_starshade_rigid(self.handle, Np, a, R, b, p, m, np_, nd, md, motion, nb, mb))

@@ -40,7 +40,7 @@ EXPORTED = [
     "fh_boundary_radial", "fh_boundary_polygon", "fh_boundary_starshade", "fh_field_nsli",
     "fh_quad_fourier", "fh_boundary_fourier", "fh_quad_koch", "fh_quad_starshade_rigid",
     "fh_quad_starshade_tab", "fh_targets_sort", "fh_probe_ceilings", "fh_quad_set_illumination",
-    "fh_field_nsli_noalloc",
+    "fh_field_nsli_noalloc", "fh_quad_starshade_ribbon",
 ]
 
 
@@ -109,6 +109,7 @@ def lib():
             "fh_quad_koch": [vp, i32, vp, pvp],
             "fh_quad_starshade_rigid": [vp, i32, d, d, d, d, i32, i32, i32, i32, vp, i32, i32, pvp],
             "fh_quad_starshade_tab": [vp, i32, d, d, vp, i32, i32, i32, i32, vp, i32, ctypes.c_int, pvp],
+            "fh_quad_starshade_ribbon": [vp, i32, d, d, d, d, i32, i32, i32, i32, vp, i32, ctypes.c_int, i32, pvp],
             "fh_boundary_fourier": [vp, i32, vp, vp, vp, vp, i32, i32, vp, vp, vp, vp, ctypes.c_int],
             "fh_probe_ceilings": [vp, ctypes.POINTER(d)],
             "fh_quad_set_illumination": [vp, vp, vp, d, ctypes.c_int],
@@ -341,6 +342,15 @@ def fh_quad_fourier(ctx, ax, bx, ay, by, panels, q, m):
     K, cs = _fourier_coefs(ax, bx, ay, by)
     h = _new_quad()
     _check(lib().fh_quad_fourier(ctx, K, *[_ptr_mem(a)[0] for a in cs], panels, q, m, ctypes.byref(h)))
+    return h
+
+
+def fh_quad_starshade_ribbon(ctx, Np, a, R, b, p, m, np_, nd, md, coef, K, mr):
+    if not _is_torch(coef):
+        coef = np.ascontiguousarray(coef, dtype=np.float64)  # kept alive through the call
+    ptr, mem = _ptr_mem(coef)
+    h = _new_quad()
+    _check(lib().fh_quad_starshade_ribbon(ctx, Np, a, R, b, p, m, np_, nd, md, ptr, K, mem, mr, ctypes.byref(h)))
     return h
 
 

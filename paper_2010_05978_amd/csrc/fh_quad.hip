@@ -369,6 +369,50 @@ __global__ void k_petals(PetalParams pp, const double* __restrict__ glm, const d
     w[j] = r * wr * half * wt;
 }
 
+// Ribbon quadrature (sec. 5): the signed strip between each petal edge of the
+// ideal starshade and the same edge displaced outward by the arc length
+// d(r) = sum_s coef[s - 1] sin(s pi (r - a)/(R - a)) (the upper edge's
+// coefficients, then the lower edge's, per petal).  Node t = ((2 k + e) nt +
+// i) m + l of the ribbon part: petal k, edge e (0 upper, 1 lower), across
+// index i, radial index l; phi = ideal edge angle +- tau_i d(r_l)/r_l (+ for
+// the upper edge, - for the lower: outward), weight wr_l d(r_l) v_i.  glt
+// holds the nt across nodes tau in (0, 1) and their weights v (or the single
+// node tau = 0 with v = 1: the line integral on the ideal edge).
+struct RibbonParams {
+    int Np, m, nt, K;
+    double a, R, b, p;
+    int64_t off;  // first ribbon node
+};
+
+__global__ void k_ribbons(RibbonParams rp, const double* __restrict__ glm, const double* __restrict__ glt,
+                          const double* __restrict__ coef, double* __restrict__ x, double* __restrict__ y,
+                          double* __restrict__ w)
+{
+    const int64_t per_edge = (int64_t)rp.nt * rp.m;
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= 2 * per_edge * rp.Np) return;
+    const int ke = (int)(t / per_edge);  // 2 k + e
+    const int k = ke >> 1, e = ke & 1;
+    const int64_t rem = t - (int64_t)ke * per_edge;
+    const int i = (int)(rem / rp.m);
+    const int l = (int)(rem - (int64_t)i * rp.m);
+    const double L = rp.R - rp.a;
+    const double r = rp.a + 0.5 * L * (1.0 + glm[l]);
+    const double wr = 0.5 * L * glm[rp.m + l];
+    const double* cp = coef + (2 * (int64_t)k + e) * rp.K;
+    double d = 0.0;
+    for (int s = 1; s <= rp.K; ++s) d += cp[s - 1] * sin(s * kPi * (r - rp.a) / L);
+    const double sg = e == 0 ? 1.0 : -1.0;
+    const double A = exp(-pow((r - rp.a) / rp.b, rp.p));
+    const double phi = 2.0 * kPi * k / rp.Np + sg * (kPi * A / rp.Np + glt[i] * d / r);
+    double sp, cph;
+    sincos(phi, &sp, &cph);
+    const int64_t j = rp.off + t;
+    x[j] = r * cph;
+    y[j] = r * sp;
+    w[j] = wr * d * glt[rp.nt + i];
+}
+
 // Boundary rule alone (for the edge integral): one thread per node.
 __global__ void k_bdry_radial(RadialParams rp, const double* __restrict__ glq, int64_t n, double* __restrict__ X,
                               double* __restrict__ Y, double* __restrict__ Wv, double* __restrict__ Vv)
@@ -697,9 +741,13 @@ namespace {
 
 // The disc + petal rule; Atab (m host values at the radial nodes) replaces
 // the HG family when not null.
+// The starshade rule: disc, then petals.  mr < 0: the coefficients (if any)
+// deform the petals.  mr >= 0: the petals stay ideal and the coefficients
+// give the signed ribbons of sec. 5 after them (mr nodes across each, or the
+// line integral on the ideal edge for mr = 0).
 fh_status starshade_build(fh_ctx* c, int32_t Np, double a, double R, double b, double p, const double* Atab,
                           int32_t m, int32_t np, int32_t nd, int32_t md, const double* coef, int32_t K,
-                          fh_memspace coef_mem, fh_quad** out)
+                          fh_memspace coef_mem, fh_quad** out, int32_t mr = -1)
 {
     FH_ARG(c && out, FH_ERR_INVALID_ARG, "NULL argument");
     *out = nullptr;
@@ -720,13 +768,35 @@ fh_status starshade_build(fh_ctx* c, int32_t Np, double a, double R, double b, d
     FH_TRY(gl_table(c, m, &glm));
     FH_TRY(gl_table(c, np, &gln));
     FH_TRY(gl_table(c, md, &glmd));
+    FH_ARG(mr < 0 || (coef && !Atab), FH_ERR_INVALID_ARG, "a ribbon rule needs coefficients and the HG profile");
+    FH_ARG(mr <= 1024, FH_ERR_INVALID_ARG, "at most 1024 nodes across a ribbon");
+    const int nt = mr > 0 ? mr : 1;  // nodes across each ribbon
     const int64_t Nd = (int64_t)nd * md;
-    const int64_t N = Nd + (int64_t)Np * np * m;
+    const int64_t Npet = Nd + (int64_t)Np * np * m;
+    const int64_t N = Npet + (mr >= 0 ? 2 * (int64_t)Np * nt * m : 0);
+    // the across rule on (0, 1): Gauss-Legendre mapped from [-1, 1], or the
+    // single node on the ideal edge
+    std::vector<double> tab;
+    if (mr >= 0) {
+        tab.assign(2 * (size_t)nt, 0.0);
+        if (mr > 0) {
+            std::vector<double> gx, gw;
+            gl_host(mr, gx, gw);
+            for (int i = 0; i < mr; ++i) {
+                tab[i] = 0.5 * (1.0 + gx[i]);
+                tab[nt + i] = 0.5 * gw[i];
+            }
+        } else {
+            tab[0] = 0.0;
+            tab[1] = 1.0;
+        }
+    }
     fh_quad* qd = nullptr;
     FH_TRY(quad_alloc(c, N, &qd));
     const size_t ncoef = coef ? (size_t)2 * Np * K : 0;
     fh_status s = arena_reserve(c, aligned_bytes(sizeof(double) * std::max<size_t>(ncoef, 1)) +
-                                       aligned_bytes(sizeof(double) * (Atab ? (size_t)m : 1)));
+                                       aligned_bytes(sizeof(double) * (Atab ? (size_t)m : 1)) +
+                                       aligned_bytes(sizeof(double) * std::max<size_t>(tab.size(), 1)));
     if (s != FH_OK) {
         fh_quad_destroy(qd);
         return s;
@@ -753,12 +823,21 @@ fh_status starshade_build(fh_ctx* c, int32_t Np, double a, double R, double b, d
         hipLaunchKernelGGL(k_radial_rule, dim3(nblocks(Nd, 256)), dim3(256), 0, c->stream, rp,
                            (const double*)nullptr, (int64_t)nd, md, glmd, qd->x, qd->y, qd->w);
     }
-    PetalParams pp{Np, m, np, coef ? K : 0, a, R, b, p, Nd};
+    const bool deform = coef && mr < 0;
+    PetalParams pp{Np, m, np, deform ? K : 0, a, R, b, p, Nd};
     hipLaunchKernelGGL(k_petals, dim3(nblocks((int64_t)Np * np * m, 256)), dim3(256), 0, c->stream, pp, glm, gln,
-                       dcoef, dA, qd->x, qd->y, qd->w);
+                       deform ? dcoef : nullptr, dA, qd->x, qd->y, qd->w);
     FH_HIP(hipGetLastError());
-    // host inputs may be released by the caller on return
-    if ((coef && coef_mem == FH_MEM_HOST) || Atab) FH_HIP(hipStreamSynchronize(c->stream));
+    if (mr >= 0) {
+        double* dt = c->arena.take<double>(tab.size());
+        FH_HIP(hipMemcpyAsync(dt, tab.data(), sizeof(double) * tab.size(), hipMemcpyHostToDevice, c->stream));
+        RibbonParams rp{Np, m, nt, K, a, R, b, p, Npet};
+        hipLaunchKernelGGL(k_ribbons, dim3(nblocks(2 * (int64_t)Np * nt * m, 256)), dim3(256), 0, c->stream, rp,
+                           glm, (const double*)dt, dcoef, qd->x, qd->y, qd->w);
+        FH_HIP(hipGetLastError());
+    }
+    // host inputs (and the across table) may be released on return
+    if ((coef && coef_mem == FH_MEM_HOST) || Atab || mr >= 0) FH_HIP(hipStreamSynchronize(c->stream));
     // every node radius is at most R (edge perturbations move angles only)
     set_bbox(qd, -R, R, -R, R);
     *out = qd;
@@ -964,6 +1043,20 @@ fh_status fh_quad_starshade(fh_ctx* c, int32_t Np, double a, double R, double b,
 {
     try {
         return starshade_build(c, Np, a, R, b, p, nullptr, m, np, nd, md, coef, K, coef_mem, out);
+    } catch (...) {
+        set_error("host allocation failed");
+        return FH_ERR_ALLOC;
+    }
+}
+
+fh_status fh_quad_starshade_ribbon(fh_ctx* c, int32_t Np, double a, double R, double b, double p, int32_t m,
+                                   int32_t np, int32_t nd, int32_t md, const double* coef, int32_t K,
+                                   fh_memspace coef_mem, int32_t mr, fh_quad** out)
+{
+    try {
+        FH_ARG(coef, FH_ERR_INVALID_ARG, "a ribbon rule needs its edge coefficients");
+        FH_ARG(mr >= 0, FH_ERR_INVALID_ARG, "mr must be >= 0");
+        return starshade_build(c, Np, a, R, b, p, nullptr, m, np, nd, md, coef, K, coef_mem, out, mr);
     } catch (...) {
         set_error("host allocation failed");
         return FH_ERR_ALLOC;
