@@ -123,16 +123,25 @@ class Batch:
         self.ctx.close()
 
 
-def spread_name(prec, W, T=16):
-    """Kernel name of the wavefront spread for width W at tile T: two
-    wavefronts per work item when their two tiles (one spare cell each), the
-    staging of 64 points and two wavefronts' kernel arguments fit 64 KiB."""
+# MI355X published dense peaks (matrix cores, vector FP64) and HBM bandwidth
+MFMA_PEAK_TFLOPS = {"fp64": 78.6, "mixed": 157.3}
+FP64_PEAK_TFLOPS = 78.6
+HBM_PEAK_GBS = 8000.0
+
+
+def spread_name(prec, W):
+    """Kernel name of the default spread for width W: the matrix-core spread
+    on 16-cell padded tiles (tile 17 - W, one 16 x 16 block, 16 points staged
+    at a time) up to W = 11, else the wavefront spread on 16-cell tiles."""
     rs = 8 if prec == "fp64" else 4
-    L = T + W - 1
+    real = "double" if rs == 8 else "float"
+    if W <= 11:
+        return f"k_spread_mfma<{real}, {W}, 1, 16>"
+    L = 16 + W - 1
     tile = 2 * rs * (L * L + 1)
     staging = rs * (64 * (2 * W + 2) + 128)
     nv = 2 if 2 * tile + staging <= 64 * 1024 else 1
-    return f"k_spread_wave<{'double' if rs == 8 else 'float'}, {W}, false, {nv}>"
+    return f"k_spread_wave<{real}, {W}, false, {nv}>"
 
 
 def batch_leg(fh, prec, steps, warmup, ceilings):
@@ -154,21 +163,25 @@ def batch_leg(fh, prec, steps, warmup, ceilings):
     rs = 8 if prec == "fp64" else 4
     W = p["width"]
     t_spread = stages[1] * 1e-3
-    # one complex add per stencil cell and node, as the read and the write of
-    # the cell in LDS (the operations a run flush issues)
-    lds_bytes = b.N * W * W * 4 * rs
+    # the method's spreading work: per node and stencil cell a complex
+    # strength times two real kernel values, added to the cell (w^2 * 8 flops);
+    # the matrix cores issue 16 * 16 * 4 * 2 * 2 / 4 = 1024 flops per node on
+    # one 16 x 16 block (real and imaginary parts, four nodes per product)
+    flops = b.N * W * W * 8
+    issued = b.N * 1024
     hbm_bytes = b.N * (4 + 4 * rs)             # packed cell, offsets and strength per node
-    lds_peak = ceilings["lds_rmw_c128_gbs" if prec == "fp64" else "lds_rmw_c64_gbs"]
+    peak = MFMA_PEAK_TFLOPS[prec]
     kern = spread_name(prec, W)
-    roof = {"bound": "lds", "achieved": lds_bytes / t_spread / 1e9, "peak": lds_peak, "unit": "GB/s",
-            "frac": lds_bytes / t_spread / 1e9 / lds_peak, "traffic": None, "kernel": kern,
-            "avg_launch_ms": stages[1], "algorithmic_bytes_per_launch": lds_bytes,
-            "peak_source": "fh_probe_ceilings: LDS read-modify-write of complex " +
-                           ("double" if rs == 8 else "float") + " cells",
-            "hbm": {"achieved": hbm_bytes / t_spread / 1e9, "peak": ceilings["hbm_copy_gbs"], "unit": "GB/s",
-                    "frac": hbm_bytes / t_spread / 1e9 / ceilings["hbm_copy_gbs"],
+    roof = {"bound": "mfma", "achieved": flops / t_spread / 1e12, "peak": peak, "unit": "TFLOP/s",
+            "frac": flops / t_spread / 1e12 / peak, "traffic": None, "kernel": kern,
+            "avg_launch_ms": stages[1], "algorithmic_flops_per_launch": flops,
+            "peak_source": "MI355X published dense " + ("FP64" if rs == 8 else "FP32") + " matrix-core peak",
+            "issued_mfma_tflops": issued / t_spread / 1e12,
+            "measured_mfma_peak_tflops": ceilings["mfma_f64_tflops" if rs == 8 else "mfma_f32_tflops"],
+            "hbm": {"achieved": hbm_bytes / t_spread / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": hbm_bytes / t_spread / 1e9 / HBM_PEAK_GBS,
                     "algorithmic_bytes_per_launch": hbm_bytes,
-                    "peak_source": "fh_probe_ceilings: device copy"}}
+                    "measured_copy_gbs": ceilings["hbm_copy_gbs"]}}
     for path in TRAFFIC_FILES:
         if os.path.exists(path):
             t = json.load(open(path))
@@ -448,7 +461,6 @@ def grad_ratio(fh, precision, steps, warmup):
 # the two Taylor series of sin/cos(pi f), the refined reciprocal of r^2 and
 # the three accumulations).
 NSLI_FLOPS_PER_PAIR = 71
-FP64_PEAK_TFLOPS = 78.6
 
 
 def nsli_throughput(fh, wl, steps, warmup, cpu_seconds):

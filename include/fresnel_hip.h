@@ -79,7 +79,11 @@ typedef struct fh_options {
                              * tolerances of 1e-4 and looser)                */
     int32_t kernel_width;   /* 2..20 cells                                   */
     double beta;            /* kernel shape parameter                        */
-    int32_t tile;           /* spread tile edge in cells: 8, 16 or 32        */
+    int32_t tile;           /* spread tile edge in cells, 4..32 (the tile    *
+                             * reduce needs T + W - 2 < 3 T: a padded tile   *
+                             * may reach two tiles on, else the call is      *
+                             * FH_ERR_UNSUPPORTED); 0: 16, or for method 5   *
+                             * 17 - W when W <= 11 (a 16-cell padded tile)   */
     int32_t max_subproblem; /* nonuniform points per spread work item (a     *
                              * tile with more than 2048 items' worth gets    *
                              * larger items); 0: about 96 items per CU,      *
@@ -94,9 +98,14 @@ typedef struct fh_options {
                              * 4: four wavefronts per work item, each with   *
                              * the padded tile in registers (lane per column *
                              * and row bank), tiles 8 or 16 only (else 2);   *
-                             * 2, 3 and 4 sum a work item's points in a      *
-                             * fixed order (the point order within a tile    *
-                             * comes from atomic counters in the binning)    */
+                             * 5: one wavefront per work item holding its    *
+                             * padded tile (at most 32 x 32 cells) in        *
+                             * matrix-core accumulators, four points per     *
+                             * 16 x 16 x 4 product (every point costs the    *
+                             * same; method 2 wins where points crowd);      *
+                             * 2 to 5 sum a work item's points in a fixed    *
+                             * order (the point order within a tile comes    *
+                             * from atomic counters in the binning)          */
 } fh_options;
 
 /* ---------------------------------------------------------------- context */
@@ -466,7 +475,7 @@ fh_status fh_timing_totals(fh_ctx* ctx, int32_t kind, double* ms5, int64_t* ncal
 /* ------------------------------------------------------------ diagnostics */
 
 /* Measured ceilings of the device the context runs on, for roofline
- * fractions (not part of any field computation).  out (host, 5 doubles):
+ * fractions (not part of any field computation).  out (host, 7 doubles):
  *   out[0] HBM bandwidth of a device-to-device copy of 1 GiB (the faster of
  *          a plain and a four-loads-in-flight copy), in GB/s of bytes read
  *          plus bytes written;
@@ -475,7 +484,10 @@ fh_status fh_timing_totals(fh_ctx* ctx, int32_t kind, double* ms5, int64_t* ncal
  *   out[2] the same for double;
  *   out[3] LDS read-modify-write of complex doubles (16-byte cells), in GB/s
  *          of bytes read plus written;
- *   out[4] the same for complex floats (8-byte cells).
+ *   out[4] the same for complex floats (8-byte cells);
+ *   out[5] matrix-core rate of 16 x 16 x 4 double products (TFLOP/s, eight
+ *          independent accumulators per wavefront);
+ *   out[6] the same for float products.
  * Each is the best of five timed launches.  Allocates 2 GiB of device memory
  * for the duration of the call (FH_ERR_ALLOC if that fails) and synchronises
  * the context stream. */

@@ -529,8 +529,9 @@ def fh_timing_totals(ctx, kind: int, reset: bool = False):
 
 def fh_probe_ceilings(ctx):
     """Measured ceilings: {'hbm_copy_gbs', 'lds_add_f32_gbs', 'lds_add_f64_gbs', 'lds_rmw_c128_gbs',
-    'lds_rmw_c64_gbs'}."""
-    arr = (ctypes.c_double * 5)()
+    'lds_rmw_c64_gbs', 'mfma_f64_tflops', 'mfma_f32_tflops'}."""
+    arr = (ctypes.c_double * 7)()
     _check(lib().fh_probe_ceilings(ctx, arr))
     return {"hbm_copy_gbs": arr[0], "lds_add_f32_gbs": arr[1], "lds_add_f64_gbs": arr[2],
-            "lds_rmw_c128_gbs": arr[3], "lds_rmw_c64_gbs": arr[4]}
+            "lds_rmw_c128_gbs": arr[3], "lds_rmw_c64_gbs": arr[4], "mfma_f64_tflops": arr[5],
+            "mfma_f32_tflops": arr[6]}

@@ -238,7 +238,8 @@ fh_status grid_vjp_impl(fh_ctx* c, const fh_quad* q, double lambda, double z, in
         gg.wrap_y = 1;
         ip.sh2 = 0;
     }
-    gg.nty = gg.rows / gg.T;
+    gg.nty = (gg.rows + gg.T - 1) / gg.T;
+    gg.pady = gg.nty * gg.T - gg.rows;
     const double* ip1 = nullptr;
     const double* ip2 = nullptr;
     FH_TRY(iphi_table(c, pl.k, n1, gg.nf1, &ip1));

@@ -102,10 +102,11 @@ fh_status fh_autotune_grid(fh_ctx* c, const fh_quad* q, double lambda, double z,
         // the tolerance is looser than 1e-4.
         const bool try_125 = c->prec == FH_FP64 || c->tol >= 1e-4;
         for (double sigma : {2.0, 1.25})
-            for (int method : {2, 4, 3, 1})
-                for (int tile : {16, 32})
+            for (int method : {2, 5, 4, 3, 1})
+                for (int tile : {0, 16, 32})  // 0: the method's own choice (16 but for method 5)
                     for (int P : {0, 64, 256, 1024, 4096}) {  // 0: sized from the node count
                         if (sigma == 1.25 && !try_125) continue;
+                        if (tile == 0 && method != 5) continue;
                         fh_options o = saved;
                         o.sigma = sigma;
                         o.kernel_width = 0;

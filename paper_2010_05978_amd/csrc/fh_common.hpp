@@ -107,16 +107,20 @@ struct InstParams {
     const double* src;
 };
 
+// Tiles need not divide the grid: the last tile of a row (of a column)
+// covers the cells left, ntx T - nf1 (nty T - rows) fewer than T, and a padded
+// tile that wraps around the period lands that many cells earlier.
 struct GridGeom {
     int nf1, nf2;  // fine grid period (x fastest)
     int T;         // tile edge
-    int ntx, nty;  // tiles per dimension (nty covers the held rows)
+    int ntx, nty;  // tiles per dimension (nty covers the held rows), rounded up
     int W;         // kernel width
     int L;         // padded tile edge T + W - 1
     int P;         // min points per spread work item
-    int method;    // 1: thread per point, 2: wavefront per point
+    int method;    // 1: thread per point, 2: wavefront per point, ...
     int rows;      // fine-grid rows held per instance (nf2 unless windowed)
     int wrap_y;    // 1 when the held rows are the whole period
+    int padx, pady;  // ntx T - nf1 and nty T - rows (0 when T divides them)
 };
 
 struct Sub {
@@ -252,6 +256,7 @@ void gl_host(int q, std::vector<double>& x, std::vector<double>& w);
 EsKernel choose_kernel(const fh_ctx* c, int n_hint);
 void es_poly_attach(fh_ctx* c, EsKernel& k);
 int pick_tile(const fh_ctx* c, int nf, int w);
+int t1_method(const fh_ctx* c, int w);
 int next_fft_size(int n, int multiple);
 double phi_hat(const EsKernel& k, double theta);
 fh_status iphi_table(fh_ctx* c, const EsKernel& k, int n, int nf, const double** dev);

@@ -271,16 +271,28 @@ int next_fft_size(int n, int multiple)
     return (int)m;
 }
 
-// Spread tile edge: the option when set, else 16 (the wavefront spread keeps
-// a private padded tile in LDS, so small tiles leave room for more
-// wavefronts per CU, and the halo the reduce reads stays modest at the
-// kernel widths of 1e-5 and 1e-9); halved while the fine grid is under four
-// tiles across.
-int pick_tile(const fh_ctx* c, int nf, int /*w*/)
+// Spread tile edge (type 1): the option when set.  Otherwise, for the
+// matrix-core spread, 17 - w where that keeps the padded tile at 16 cells
+// (one 16 x 16 block of products) and the tile reduce's reach at two tiles
+// (w <= 11), else 16; for the other spreads 16 (the wavefront spread keeps a private
+// padded tile in LDS, so small tiles leave room for more wavefronts per CU,
+// and the halo the reduce reads stays modest at the kernel widths of 1e-5 and
+// 1e-9).  Halved while the fine grid is under four tiles across.
+int pick_tile(const fh_ctx* c, int nf, int w)
 {
     int T = c->opt.tile > 0 ? c->opt.tile : 16;
+    if (c->opt.tile <= 0 && t1_method(c, w) == 5 && w <= 11) T = 17 - w;
     while (T > 8 && nf < 4 * T) T /= 2;
     return T;
+}
+
+// Spread method of a type-1 call: the option when set, else the matrix-core
+// spread when the kernel is narrow enough for a 16-cell padded tile (w <= 11:
+// tolerances down to 1e-9 in FP64) and the wavefront spread otherwise.
+int t1_method(const fh_ctx* c, int w)
+{
+    if (c->opt.spread_method > 0) return c->opt.spread_method;
+    return w <= 11 ? 5 : 2;
 }
 
 // Fourier transform of the kernel in fine-grid units:
@@ -568,11 +580,10 @@ static fh_status check_options(const fh_options* o)
     FH_ARG(o->kernel_width == 0 || (o->kernel_width >= 2 && o->kernel_width <= kMaxWidth),
            FH_ERR_INVALID_ARG, "kernel_width must be 0 or in [2, %d]", kMaxWidth);
     FH_ARG(o->beta >= 0 && std::isfinite(o->beta), FH_ERR_INVALID_ARG, "beta must be >= 0");
-    FH_ARG(o->tile == 0 || o->tile == 8 || o->tile == 16 || o->tile == 32, FH_ERR_INVALID_ARG,
-           "tile must be 0, 8, 16 or 32");
+    FH_ARG(o->tile == 0 || (o->tile >= 4 && o->tile <= 32), FH_ERR_INVALID_ARG, "tile must be 0 or in [4, 32]");
     FH_ARG(o->max_subproblem >= 0, FH_ERR_INVALID_ARG, "max_subproblem must be >= 0");
-    FH_ARG(o->spread_method >= 0 && o->spread_method <= 4, FH_ERR_INVALID_ARG,
-           "spread_method must be 0, 1, 2, 3 or 4");
+    FH_ARG(o->spread_method >= 0 && o->spread_method <= 5, FH_ERR_INVALID_ARG,
+           "spread_method must be 0, 1, 2, 3, 4 or 5");
     return FH_OK;
 }
 
@@ -703,9 +714,11 @@ fh_status fh_query_params(const fh_ctx* c, int32_t n, int32_t* width, double* be
     if (beta) *beta = k.beta;
     if (sigma) *sigma = k.sigma;
     if (nf) {
+        // as the type-1 plan: power-of-two tiles divide the grid, other tiles
+        // keep the lengths of 16-cell tiles
         int need = std::max((int)std::ceil(k.sigma * n), 2 * k.w);
         int T = pick_tile(c, need, k.w);
-        *nf = next_fft_size(need, T);
+        *nf = next_fft_size(std::max(need, T + k.w), (T & (T - 1)) == 0 ? T : 16);
     }
     return FH_OK;
 }

@@ -177,7 +177,8 @@ fh_status t1_pipeline(fh_ctx* c, int B, const fh_quad* const* qs, const double* 
         gg.wrap_y = 1;
         for (auto& ip : inst) ip.sh2 = 0;
     }
-    gg.nty = gg.rows / gg.T;
+    gg.nty = (gg.rows + gg.T - 1) / gg.T;
+    gg.pady = gg.nty * gg.T - gg.rows;
     const int tpi = gg.ntx * gg.nty;
     for (int b = 0; b < B; ++b) {
         inst[b].tile_off = b * tpi;
@@ -420,6 +421,7 @@ fh_status t3_core(fh_ctx* c, const fh_quad* q, double lambda, double z, int64_t 
     gg.nty = d2.nf / T0;
     gg.rows = d2.nf;
     gg.wrap_y = 1;
+    gg.padx = gg.pady = 0;  // the type-3 grids are multiples of the tile
     spread_defaults(c, gg);
     size_items(c, gg, N);
     const int ntiles = gg.ntx * gg.nty;

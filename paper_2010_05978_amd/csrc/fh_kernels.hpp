@@ -351,8 +351,10 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_sums(const int* __restric
 __global__ void __launch_bounds__(kScanThreads) k_scan_tiles(const int* __restrict__ cnt, int ntiles, int P,
                                                              const int* __restrict__ bsum,
                                                              int* __restrict__ off, int* __restrict__ tsub,
-                                                             int* __restrict__ nsub_out)
+                                                             int* __restrict__ nsub_out, int* __restrict__ zero_out)
 {
+    // the counter of the tile reduce's list starts at zero
+    if (zero_out && blockIdx.x == 0 && threadIdx.x == 0) *zero_out = 0;
     __shared__ int wa[16], wb[16];
     // totals of the blocks before this one
     int base_a = 0, base_b = 0;
@@ -901,6 +903,217 @@ __global__ void __launch_bounds__(256) k_spread_reg(const Sub* __restrict__ subs
     }
 }
 
+// Matrix-core spread (method 5).  A work item's padded tile is a sum of
+// rank-one terms, one per point p: (c_p ky_p)(kx_p)^T, with ky_p and kx_p the
+// kernel values placed at the point's first cell (zero elsewhere), i.e. the
+// matrix product G = A^T B over the item's points with A[p][y] = c_p
+// ky_p(y - cy_p) and B[p][x] = kx_p(x - cx_p).  Each wavefront takes one item
+// and holds its tile, zero-extended to (16 NB)^2 cells, in matrix-core
+// accumulators: NB x NB blocks of 16 x 16, a real and an imaginary one each,
+// updated four points at a time by v_mfma_{f64,f32}_16x16x4 (lane l supplies
+// A[row l % 16][point l / 16] and B[point l / 16][column l % 16]).
+//
+// The operands are read from zero-padded rows of kx and c ky (real and
+// imaginary) staged in LDS for MS points at a time, so that a lane reads its
+// value with no bounds test: each point's shifted row base is staged too.  The kernel values
+// are evaluated by lanes over the value index with the polynomial table (as
+// the wavefront spread does), the y values multiplied by the strength there.
+// A point costs the same whatever its neighbours; the wavefront spread
+// instead merges runs of points that share a first cell, which wins where
+// points crowd.  Points are summed in their staged order, four at a time (the
+// order of a tile's points comes from the binning's atomic counters).  The
+// slot receives the L x L corner of the accumulators.
+template <class R> struct MfmaAcc;
+template <> struct MfmaAcc<double> {
+    typedef double V __attribute__((ext_vector_type(4)));
+    __device__ static V mma(double a, double b, V c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+    // output v of lane l holds row (l / 16) + 4 v, column l % 16
+    __device__ static int row(int lane, int v) { return (lane >> 4) + 4 * v; }
+};
+template <> struct MfmaAcc<float> {
+    typedef float V __attribute__((ext_vector_type(4)));
+    __device__ static V mma(float a, float b, V c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+    // output v of lane l holds row 4 (l / 16) + v, column l % 16
+    __device__ static int row(int lane, int v) { return 4 * (lane >> 4) + v; }
+};
+
+constexpr int kMfmaWaves = 4;  // wavefronts (items) per block
+
+// Operand rows in LDS: the x values of the MS staged points lie in one array,
+// point q's W values at positions q P + T - 1 .. q P + T + W - 2 and zeros
+// elsewhere; the real and imaginary y rows (times the strength) follow in two
+// arrays of the same layout.  Lane i of the block b reads position
+// q P + T - 1 - cx + 16 b + i, which stays inside point q's window
+// [q P, q P + 16 NB + T - 2]: that window holds no other point's values when
+// the period P is at least 16 NB (and the tile side L <= 16 NB).  P is odd so
+// that consecutive points start in different LDS banks.
+__host__ __device__ inline int mfma_period(int NB) { return 16 * NB + 1; }
+__host__ __device__ inline int mfma_rows(int NB, int T, int MS) { return MS * mfma_period(NB) + T; }
+
+// LDS bytes of one wavefront's staging of MS points: three operand arrays,
+// the strengths and the polynomial arguments (2 reals each per point), and
+// two row offsets per point.
+__host__ __device__ inline size_t mfma_wave_lds(int NB, int T, int MS, size_t rsize)
+{
+    return (3 * (size_t)mfma_rows(NB, T, MS) + 4 * (size_t)MS) * rsize + 2 * (size_t)MS * sizeof(int);
+}
+
+template <class R, int W, int NB, int MS>
+__global__ void __launch_bounds__(64 * kMfmaWaves) k_spread_mfma(const Sub* __restrict__ subs,
+                                                                 const int* __restrict__ nsub_ptr,
+                                                                 const uint32_t* __restrict__ cell,
+                                                                 const typename V2<R>::T* __restrict__ dd,
+                                                                 const typename V2<R>::T* __restrict__ cc,
+                                                                 typename V2<R>::T* __restrict__ slots, GridGeom gg,
+                                                                 int tpi, R beta, const R* __restrict__ poly)
+{
+    using C = typename V2<R>::T;
+    using M = MfmaAcc<R>;
+    using V = typename M::V;
+    constexpr int NP = W + kPolyExtra;  // coefficients per kernel polynomial
+    constexpr int KG = 64 / W;          // lane groups evaluating kernel values
+    static_assert(W <= 16 * NB, "the padded tile must fit the blocks");
+    static_assert(MS % 16 == 0 && MS <= 64, "points are staged in sixteens, one per lane at most");
+    extern __shared__ unsigned char smem_raw[];
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int lane = threadIdx.x & 63;
+    const int T = gg.T, L = gg.L;
+    const int P = mfma_period(NB), AL = mfma_rows(NB, T, MS);
+    unsigned char* wbase = smem_raw + (size_t)wv * mfma_wave_lds(NB, T, MS, sizeof(R));
+    R* rows = reinterpret_cast<R*>(wbase);  // x values, y values (real), y values (imaginary)
+    R* ctab = rows + 3 * AL;                // strengths, 2 reals per point
+    R* ttab = ctab + 2 * MS;                // polynomial arguments: x of each point, then y
+    int* shx = reinterpret_cast<int*>(ttab + 2 * MS);  // byte offset of q P + T - 1 - cx
+    int* shy = shx + MS;                                // byte offset of q P + T - 1 - cy
+    const int nsub = *nsub_ptr;
+    const int k4 = lane >> 4, i16 = lane & 15;
+    // lane (kg, ka), ka = lane % W, holds the coefficients of cell ka's
+    // polynomial and evaluates it at arguments kg, kg + KG, ...
+    const bool has_poly = poly != nullptr;
+    const int ka = lane % W, kg = lane / W;
+    R coef[NP];
+#pragma unroll
+    for (int j = 0; j < NP; ++j) coef[j] = has_poly ? poly[j * W + ka] : R(0);
+    // rows start at zero; staging only ever writes their W middle positions
+    for (int e = lane; e < 3 * AL; e += 64) rows[e] = R(0);
+    const uint32_t lane_off = (uint32_t)(i16 * sizeof(R));
+    for (int s = blockIdx.x * kMfmaWaves + wv; s < nsub; s += gridDim.x * kMfmaWaves) {
+        const Sub sb = subs[s];
+        int ox, oy;
+        tile_origin<R>(sb, gg, tpi, ox, oy);
+        const uint32_t org = (uint32_t)ox | ((uint32_t)oy << 16);
+        V are[NB][NB], aim[NB][NB];
+#pragma unroll
+        for (int br = 0; br < NB; ++br)
+#pragma unroll
+            for (int bc = 0; bc < NB; ++bc) {
+                are[br][bc] = V{R(0), R(0), R(0), R(0)};
+                aim[br][bc] = V{R(0), R(0), R(0), R(0)};
+            }
+        for (int base = sb.start; base < sb.end; base += MS) {
+            // stage: lane q < MS loads point base + q (zero strength past the
+            // item's end: such points add nothing)
+            if (lane < MS) {
+                const int p = base + lane;
+                C dv{R(0), R(0)}, cv{R(0), R(0)};
+                int cx = 0, cy = 0;
+                if (p < sb.end) {
+                    const uint32_t rel = cell[p] - org;  // tile-relative first cell (x, y < T)
+                    cx = (int)(rel & 0xffffu);
+                    cy = (int)(rel >> 16);
+                    dv = dd[p];
+                    cv = cc[p];
+                }
+                ctab[2 * lane] = cv.x;
+                ctab[2 * lane + 1] = cv.y;
+                ttab[lane] = R(2) * dv.x + R(W - 1);
+                ttab[MS + lane] = R(2) * dv.y + R(W - 1);
+                shx[lane] = (int)(sizeof(R) * (lane * P + T - 1 - cx));
+                shy[lane] = (int)(sizeof(R) * (AL + lane * P + T - 1 - cy));
+            }
+            wave_lds_order();
+            // the kernel values: arguments 0..MS-1 are the points' x, the
+            // next MS their y (times the strength)
+#pragma unroll
+            for (int r = 0; r < (2 * MS + KG - 1) / KG; ++r) {
+                const int qq = r * KG + kg;
+                if (kg < KG && qq < 2 * MS) {
+                    const R t = ttab[qq];
+                    R k;
+                    if (has_poly) {
+                        k = coef[0];
+#pragma unroll
+                        for (int j = 1; j < NP; ++j) k = k * t + coef[j];
+                    } else {
+                        k = es_one<R, W>((t - R(W - 1)) * R(0.5), ka, beta, nullptr);
+                    }
+                    const int q = qq < MS ? qq : qq - MS;
+                    R* row = rows + q * P + T - 1 + ka;
+                    if (qq < MS) {
+                        row[0] = k;
+                    } else {
+                        row[AL] = ctab[2 * q] * k;
+                        row[2 * AL] = ctab[2 * q + 1] * k;
+                    }
+                }
+            }
+            wave_lds_order();
+            const int np = min(MS, sb.end - base);
+#pragma unroll
+            for (int h = 0; h < MS / 16; ++h) {
+                if (16 * h >= np) break;  // wavefront-uniform
+                // four points per product, the operands of all sixteen read
+                // first (points past np carry zero strength)
+                R bx[4][NB], ar[4][NB], ai[4][NB];
+#pragma unroll
+                for (int g = 0; g < 4; ++g) {
+                    const int q = 16 * h + 4 * g + k4;
+                    const unsigned char* px = reinterpret_cast<const unsigned char*>(rows) + shx[q] + lane_off;
+                    const unsigned char* py = reinterpret_cast<const unsigned char*>(rows) + shy[q] + lane_off;
+#pragma unroll
+                    for (int b = 0; b < NB; ++b) {
+                        bx[g][b] = reinterpret_cast<const R*>(px)[16 * b];
+                        ar[g][b] = reinterpret_cast<const R*>(py)[16 * b];
+                        ai[g][b] = reinterpret_cast<const R*>(py)[16 * b + AL];
+                    }
+                }
+#pragma unroll
+                for (int g = 0; g < 4; ++g) {
+                    if (16 * h + 4 * g >= np) break;  // wavefront-uniform
+#pragma unroll
+                    for (int br = 0; br < NB; ++br)
+#pragma unroll
+                        for (int bc = 0; bc < NB; ++bc) {
+                            are[br][bc] = M::mma(ar[g][br], bx[g][bc], are[br][bc]);
+                            aim[br][bc] = M::mma(ai[g][br], bx[g][bc], aim[br][bc]);
+                        }
+                }
+            }
+            // the next stage rewrites the staging
+            wave_lds_order();
+        }
+        C* slot = slots + (size_t)s * L * L;
+#pragma unroll
+        for (int br = 0; br < NB; ++br)
+#pragma unroll
+            for (int bc = 0; bc < NB; ++bc)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int y = 16 * br + M::row(lane, v), x = 16 * bc + i16;
+                    if (x < L && y < L) slot[y * L + x] = C{are[br][bc][v], aim[br][bc][v]};
+                }
+    }
+}
+
+// Points staged per wavefront at a time.
+template <class R> constexpr int mfma_stage() { return 16; }
+
+// LDS bytes of one matrix-core spread block: the staging of each wavefront.
+inline size_t mfma_spread_lds(int NB, int T, size_t rsize)
+{
+    return (size_t)kMfmaWaves * mfma_wave_lds(NB, T, rsize == 8 ? mfma_stage<double>() : mfma_stage<float>(), rsize);
+}
+
 // ----------------------------------------------------------------- reduce
 // A tile with cnt work items is merged in levels: level l sums, for every
 // item r (its index within the tile) divisible by G^l, the slots r + k G^(l-1)
@@ -951,7 +1164,8 @@ __global__ void __launch_bounds__(256) k_merge_slots(typename V2<R>::T* __restri
 // Fine-grid cell (gx, gy) of tile (tx, ty) is covered by the padded tiles of
 // (tx - dx, ty - dy) for every dx, dy >= 0 with i + dx T < L and j + dy T < L
 // (periodic in x, and in y when the window is the whole grid; a padded tile
-// reaches ceil((W-1)/T) tiles on).  Each thread sums, in item order, the
+// reaches ceil((W-1)/T) tiles on; one reached through the wrap of a period
+// whose last tile is partial sits padx (pady) cells closer).  Each thread sums, in item order, the
 // merged slots of those tiles at its cell and writes the cell: every cell of
 // the held rows is written, zeros included.
 // The (first, count) pairs of all covering tiles are loaded at once, then
@@ -986,16 +1200,22 @@ __global__ void __launch_bounds__(256) k_reduce_tiles(const typename V2<R>::T* _
         if (threadIdx.x == 0) cnt[tile] = 0;
         const int b = tile / tpi, tl = tile - b * tpi;
         const int ty = tl / gg.ntx, tx = tl - ty * gg.ntx;
+        // cells of this tile inside the grid (the last tile of a row or
+        // column may be partial)
+        const int wx = min(T, gg.nf1 - tx * T), wy = min(T, gg.rows - ty * T);
         // covering tile i = (dy, dx): its first merged slot, slot stride
-        // and number of merged slots (0 where no tile reaches)
-        int first[NC], stride[NC], heads[NC];
+        // and number of merged slots (0 where no tile reaches), and the
+        // shift of its padded cells when it wraps around the period
+        int first[NC], stride[NC], heads[NC], sx[NC], sy[NC];
         bool any = false;
 #pragma unroll
         for (int i = 0; i < NC; ++i) {
             const int dy = i / (REACH + 1), dx = i % (REACH + 1);
             int sty = ty - dy;
             const bool ok = sty >= 0 || gg.wrap_y;
+            sy[i] = sty < 0 ? gg.pady : 0;
             if (sty < 0) sty = ((sty % gg.nty) + gg.nty) % gg.nty;
+            sx[i] = tx - dx < 0 ? gg.padx : 0;
             const int stx = (((tx - dx) % gg.ntx) + gg.ntx) % gg.ntx;
             const int t = b * tpi + sty * gg.ntx + stx;
             const int n = ok ? tsub[2 * t + 1] : 0;
@@ -1008,7 +1228,8 @@ __global__ void __launch_bounds__(256) k_reduce_tiles(const typename V2<R>::T* _
         }
         C* out = Fv + ((size_t)b * gg.rows + (size_t)ty * T) * gg.nf1 + (size_t)tx * T;
         if (!any) {
-            for (int e = threadIdx.x; e < TT; e += blockDim.x) out[(size_t)(e / T) * gg.nf1 + e % T] = C{R(0), R(0)};
+            for (int e = threadIdx.x; e < TT; e += blockDim.x)
+                if (e % T < wx && e / T < wy) out[(size_t)(e / T) * gg.nf1 + e % T] = C{R(0), R(0)};
             continue;
         }
         // the first kRedU slots of every covering tile at each cell
@@ -1018,7 +1239,7 @@ __global__ void __launch_bounds__(256) k_reduce_tiles(const typename V2<R>::T* _
 #pragma unroll
             for (int i = 0; i < NC; ++i) {
                 const int dy = i / (REACH + 1), dx = i % (REACH + 1);
-                const int lx = ci[q] + dx * T, ly = cj[q] + dy * T;
+                const int lx = ci[q] + dx * T - sx[i], ly = cj[q] + dy * T - sy[i];
                 const bool in = cv[q] && lx < L && ly < L;
                 const C* sp = slots + (size_t)first[i] * LL + (in ? ly * L + lx : 0);
 #pragma unroll
@@ -1038,7 +1259,7 @@ __global__ void __launch_bounds__(256) k_reduce_tiles(const typename V2<R>::T* _
                 if (heads[i] > kRedU) {
                     // merged slots past the first kRedU (clustered tiles)
                     const int dy = i / (REACH + 1), dx = i % (REACH + 1);
-                    const int lx = ci[q] + dx * T, ly = cj[q] + dy * T;
+                    const int lx = ci[q] + dx * T - sx[i], ly = cj[q] + dy * T - sy[i];
                     const bool in = cv[q] && lx < L && ly < L;
                     const size_t st = (size_t)stride[i] * LL;
                     const C* sp = slots + (size_t)first[i] * LL + (in ? ly * L + lx : 0);
@@ -1054,8 +1275,129 @@ __global__ void __launch_bounds__(256) k_reduce_tiles(const typename V2<R>::T* _
                     }
                 }
             }
-            if (cv[q]) out[(size_t)cj[q] * gg.nf1 + ci[q]] = C{ar, ai};
+            if (cv[q] && ci[q] < wx && cj[q] < wy) out[(size_t)cj[q] * gg.nf1 + ci[q]] = C{ar, ai};
         }
+    }
+}
+
+// Cell-parallel form of the tile reduce, for small tiles (whose blocks of one
+// tile would leave most lanes idle): a thread per fine-grid cell, 64 x 4
+// cells per block (x fastest, so the stores of a row are contiguous), grid z
+// the instance.  A cell of a tile that no padded tile reaches is zero;
+// otherwise the thread finds the covering tiles and sums their merged slots
+// in the same order as k_reduce_tiles: covering tiles in (dy, dx) order,
+// slots in item order.
+// Tiles that some padded tile reaches (any of their covering tiles holds work
+// items), appended to a list: most of a batch's fine grids are empty, and the
+// list reduce visits only these.  One atomic per wavefront reserves its
+// entries (the list's order does not matter: every cell is summed by one
+// thread in a fixed order).  Also leaves the binning counters at zero for
+// the next call.
+template <int REACH>
+__global__ void __launch_bounds__(256) k_tile_active(const int* __restrict__ tsub, GridGeom gg, int tpi,
+                                                     int ntiles_total, int* __restrict__ list,
+                                                     int* __restrict__ nlist, int* __restrict__ cnt)
+{
+    const int tile = blockIdx.x * blockDim.x + threadIdx.x;
+    int any = 0;
+    if (tile < ntiles_total) {
+        cnt[tile] = 0;
+        const int b = tile / tpi, tl = tile - b * tpi;
+        const int ty = tl / gg.ntx, tx = tl - ty * gg.ntx;
+#pragma unroll
+        for (int i = 0; i < (REACH + 1) * (REACH + 1); ++i) {
+            const int dy = i / (REACH + 1), dx = i % (REACH + 1);
+            int sty = ty - dy;
+            if (sty < 0 && !gg.wrap_y) continue;
+            if (sty < 0) sty = ((sty % gg.nty) + gg.nty) % gg.nty;
+            const int stx = (((tx - dx) % gg.ntx) + gg.ntx) % gg.ntx;
+            any |= tsub[2 * (b * tpi + sty * gg.ntx + stx) + 1];
+        }
+    }
+    const uint64_t m = __ballot(any != 0);
+    if (!m) return;
+    const int lane = (int)__lane_id();
+    const int lead = __ffsll((unsigned long long)m) - 1;
+    int base = 0;
+    if (lane == lead) base = atomicAdd(nlist, __popcll(m));
+    base = __shfl(base, lead);
+    if (any) list[base + __popcll(m & ((1ull << lane) - 1ull))] = tile;
+}
+
+// Tile reduce over the listed tiles (the rest of the fine grid was filled
+// with zeros): persistent blocks walk the cells of the listed tiles, 256 at
+// a time, a thread per cell.  Each thread finds the covering tiles and sums
+// their merged slots in the same order as k_reduce_tiles: covering tiles in
+// (dy, dx) order, slots in item order; cells of a partial last tile outside
+// the grid are skipped.
+template <class R, int REACH>
+__global__ void __launch_bounds__(256) k_reduce_list(const typename V2<R>::T* __restrict__ slots,
+                                                     const int* __restrict__ tsub, const int* __restrict__ list,
+                                                     const int* __restrict__ nlist, GridGeom gg, int tpi,
+                                                     R* __restrict__ F)
+{
+    using C = typename V2<R>::T;
+    constexpr int NC = (REACH + 1) * (REACH + 1);
+    const int T = gg.T, TT = T * T, L = gg.L, LL = L * L;
+    const int64_t ncell = (int64_t)(*nlist) * TT;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < ncell;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int k = (int)(e / TT), c = (int)(e - (int64_t)k * TT);
+        const int tile = list[k];
+        const int b = tile / tpi, tl = tile - b * tpi;
+        const int ty = tl / gg.ntx, tx = tl - ty * gg.ntx;
+        const int cj = c / T, ci = c - cj * T;
+        if (tx * T + ci >= gg.nf1 || ty * T + cj >= gg.rows) continue;
+        int first[NC], stride[NC], heads[NC], off[NC];
+#pragma unroll
+        for (int i = 0; i < NC; ++i) {
+            const int dy = i / (REACH + 1), dx = i % (REACH + 1);
+            int sty = ty - dy, sy = 0;
+            const bool okr = sty >= 0 || gg.wrap_y;
+            if (sty < 0) {
+                sty += gg.nty;
+                sy = gg.pady;
+                if (sty < 0) sty = ((sty % gg.nty) + gg.nty) % gg.nty;
+            }
+            int stx = tx - dx, sx = 0;
+            if (stx < 0) {
+                stx += gg.ntx;
+                sx = gg.padx;
+                if (stx < 0) stx = ((stx % gg.ntx) + gg.ntx) % gg.ntx;
+            }
+            const int lx = ci + dx * T - sx, ly = cj + dy * T - sy;
+            const bool in = okr && lx < L && ly < L;
+            const int t = b * tpi + sty * gg.ntx + stx;
+            const int n = in ? tsub[2 * t + 1] : 0;
+            first[i] = in ? tsub[2 * t] : 0;
+            int st = 1;
+            for (int l = merge_levels(n); l > 0; --l) st *= kMergeG;
+            stride[i] = st;
+            heads[i] = (n + st - 1) / st;
+            off[i] = in ? ly * L + lx : 0;
+        }
+        C r[NC][kRedU];
+#pragma unroll
+        for (int i = 0; i < NC; ++i)
+#pragma unroll
+            for (int u = 0; u < kRedU; ++u)
+                r[i][u] =
+                    u < heads[i] ? slots[((size_t)first[i] + (size_t)u * stride[i]) * LL + off[i]] : C{R(0), R(0)};
+        R ar = R(0), ai = R(0);
+#pragma unroll
+        for (int i = 0; i < NC; ++i) {
+#pragma unroll
+            for (int u = 0; u < kRedU; ++u) {
+                ar += r[i][u].x;
+                ai += r[i][u].y;
+            }
+            for (int q = kRedU; q < heads[i]; ++q) {
+                const C v = slots[((size_t)first[i] + (size_t)q * stride[i]) * LL + off[i]];
+                ar += v.x;
+                ai += v.y;
+            }
+        }
+        reinterpret_cast<C*>(F)[((size_t)b * gg.rows + ty * T + cj) * gg.nf1 + tx * T + ci] = C{ar, ai};
     }
 }
 
@@ -1632,6 +1974,7 @@ inline int spread_waves(const GridGeom& gg, size_t rsize)
 // LDS bytes of one spread block.
 inline size_t spread_lds(const GridGeom& gg, size_t rsize)
 {
+    if (gg.method == 5) return mfma_spread_lds(gg.L <= 16 ? 1 : 2, gg.T, rsize);
     if (gg.method == 4) {
         // staging of 32 points (W + KYP + 2 reals and 2 ints each) and the 4
         // wavefront tiles (see RegTile and reg_spread_lds)
@@ -1654,6 +1997,21 @@ void launch_spread_w(fh_ctx* c, unsigned grid, const Sub* subs, const int* nsub,
     if (gg.method == 1) {
         hipLaunchKernelGGL((k_spread_thread<R, W>), dim3(grid), dim3(256), tile, c->stream, subs, nsub, cell,
                            (const C2*)dd, (const C2*)cc, slots, gg, tpi, (R)beta, (const R*)poly);
+        return;
+    }
+    if (gg.method == 5) {
+        // (T + W - 1) <= 32: two 16-cell blocks per dimension, else one
+        if constexpr (W <= 16) {
+            if (gg.L <= 16) {
+                hipLaunchKernelGGL((k_spread_mfma<R, W, 1, mfma_stage<R>()>), dim3(grid), dim3(64 * kMfmaWaves),
+                                   mfma_spread_lds(1, gg.T, sizeof(R)), c->stream, subs, nsub, cell, (const C2*)dd,
+                                   (const C2*)cc, slots, gg, tpi, (R)beta, (const R*)poly);
+                return;
+            }
+        }
+            hipLaunchKernelGGL((k_spread_mfma<R, W, 2, mfma_stage<R>()>), dim3(grid), dim3(64 * kMfmaWaves), mfma_spread_lds(2, gg.T, sizeof(R)),
+                               c->stream, subs, nsub, cell, (const C2*)dd, (const C2*)cc, slots, gg, tpi, (R)beta,
+                               (const R*)poly);
         return;
     }
     if (gg.method == 4) {
@@ -1752,6 +2110,8 @@ struct SpreadBufs {
     int* nsub;      // number of work items (device)
     int* bsum;      // per scan block: points and work items
     void* slots;    // one padded L x L complex tile per work item
+    int* list;      // tiles some padded tile reaches (list reduce), and their count
+    int* nlist;
     int64_t max_sub;
 };
 
@@ -1768,7 +2128,8 @@ size_t spread_bytes(int64_t Ntot, const GridGeom& gg, int ntiles_total, size_t r
            aligned_bytes(2 * sizeof(int) * (size_t)(ntiles_total / kScanChunk + 1)) +
            aligned_bytes(sizeof(int) * Ntot) + aligned_bytes(sizeof(uint32_t) * Ntot) +
            2 * aligned_bytes(2 * rsize * Ntot) + aligned_bytes(sizeof(Sub) * max_sub) + aligned_bytes(sizeof(int)) +
-           aligned_bytes(2 * rsize * (size_t)gg.L * gg.L * max_sub);
+           aligned_bytes(2 * rsize * (size_t)gg.L * gg.L * max_sub) + aligned_bytes(sizeof(int) * (size_t)ntiles_total) +
+           aligned_bytes(sizeof(int));
 }
 
 SpreadBufs spread_carve(fh_ctx* c, int64_t Ntot, const GridGeom& gg, int ntiles_total, size_t rsize)
@@ -1786,6 +2147,8 @@ SpreadBufs spread_carve(fh_ctx* c, int64_t Ntot, const GridGeom& gg, int ntiles_
     b.nsub = c->arena.take<int>(1);
     b.bsum = c->arena.take<int>(2 * (size_t)(ntiles_total / kScanChunk + 1));
     b.slots = c->arena.take<char>(2 * rsize * (size_t)gg.L * gg.L * b.max_sub);
+    b.list = c->arena.take<int>((size_t)ntiles_total);
+    b.nlist = c->arena.take<int>(1);
     return b;
 }
 
@@ -1809,7 +2172,7 @@ fh_status run_spread(fh_ctx* c, const InstParams& p0, const InstParams* table, i
         hipLaunchKernelGGL(k_scan_sums, dim3(nscan), dim3(kScanThreads), 0, c->stream, b.cnt, ntiles_total, gg.P,
                            b.bsum);
     hipLaunchKernelGGL(k_scan_tiles, dim3(nscan), dim3(kScanThreads), 0, c->stream, b.cnt, ntiles_total, gg.P,
-                       b.bsum, b.off, b.tsub, b.nsub);
+                       b.bsum, b.off, b.tsub, b.nsub, b.nlist);
     if (Ntot > 0) {
         hipLaunchKernelGGL((k_bin_place<R>), dim3(nblocks(Ntot, 256)), dim3(256), 0, c->stream, p0, table, ninst,
                            Ntot, gg, b.cnt, b.off, b.tsub, b.rank, b.cell, (typename V2<R>::T*)b.dd,
@@ -1821,8 +2184,11 @@ fh_status run_spread(fh_ctx* c, const InstParams& p0, const InstParams* table, i
         // one block per work item up to a few waves of the whole chip
         // (wavefront blocks: as many as fit in LDS, at most 32 per CU)
         const int64_t per_cu = gg.method == 1 ? 8 : std::min<int64_t>(32, kCuLds / spread_lds(gg, sizeof(R)));
+        // (the matrix-core spread takes kMfmaWaves items per block)
+        const int64_t items_per_block = gg.method == 5 ? kMfmaWaves : 1;
         const unsigned grid = (unsigned)std::max<int64_t>(
-            1, std::min<int64_t>(b.max_sub, (int64_t)c->cu_count * std::max<int64_t>(1, per_cu) * 4));
+            1, std::min<int64_t>((b.max_sub + items_per_block - 1) / items_per_block,
+                                 (int64_t)c->cu_count * std::max<int64_t>(1, per_cu) * 4));
         FH_TRY(launch_spread<R>(c, grid, b.subs, b.nsub, b.cell, b.dd, b.cc, (typename V2<R>::T*)b.slots, gg, tpi,
                                 beta, poly));
     }
@@ -1838,7 +2204,9 @@ fh_status run_spread(fh_ctx* c, const InstParams& p0, const InstParams* table, i
     }
     const unsigned rgrid = (unsigned)std::max<int64_t>(
         1, std::min<int64_t>(ntiles_total, (int64_t)c->cu_count * 16));
-    const int reach = (gg.L - 1) / gg.T;
+    // how many tiles on a padded tile reaches, also through the wrap of the
+    // period, where a partial last tile brings the next tiles closer
+    const int reach = (gg.L - 1 + std::max(gg.padx, gg.wrap_y ? gg.pady : 0)) / gg.T;
     const int TT = gg.T * gg.T;
     const unsigned rthreads = (unsigned)std::min(256, TT);
     FH_ARG(reach >= 1 && reach <= (TT > 256 ? 1 : 2) && TT <= 1024, FH_ERR_UNSUPPORTED,
@@ -1846,7 +2214,27 @@ fh_status run_spread(fh_ctx* c, const InstParams& p0, const InstParams* table, i
 #define FH_REDUCE(RE, K)                                                                                     \
     hipLaunchKernelGGL((k_reduce_tiles<R, RE, K>), dim3(rgrid), dim3(rthreads), 0, c->stream,                \
                        (const typename V2<R>::T*)b.slots, b.tsub, gg, tpi, ntiles_total, F, b.cnt)
-    if (TT > 256) {
+#define FH_REDUCE_CELLS(RE)                                                                                  \
+    do {                                                                                                     \
+        hipLaunchKernelGGL((k_tile_active<RE>), dim3(nblocks(ntiles_total, 256)), dim3(256), 0, c->stream,   \
+                           b.tsub, gg, tpi, ntiles_total, b.list, b.nlist, b.cnt);                           \
+        hipLaunchKernelGGL((k_reduce_list<R, RE>), dim3(lgrid), dim3(256), 0, c->stream,                      \
+                           (const typename V2<R>::T*)b.slots, b.tsub, (const int*)b.list, (const int*)b.nlist, \
+                           gg, tpi, F);                                                                      \
+    } while (0)
+    // Tiles under 128 cells (the matrix-core spread's), and grids of 4M
+    // cells or more (mostly empty in a batch), are reduced from the list of
+    // reached tiles after a zero fill: three launches, but every thread has
+    // a cell to sum.  Small grids of larger tiles take one launch, a tile per
+    // block.
+    const bool by_cell = TT < 128 || (int64_t)ntiles_total * TT >= ((int64_t)1 << 22);
+    const unsigned lgrid = (unsigned)std::max<int64_t>(
+        1, std::min<int64_t>((int64_t)c->cu_count * 8, ((int64_t)ntiles_total * TT + 255) / 256));
+    if (by_cell) FH_TRY(launch_zero(c, F, 2 * sizeof(R) * (size_t)ninst * gg.rows * gg.nf1));
+    if (by_cell) {
+        if (reach == 1) FH_REDUCE_CELLS(1);
+        else FH_REDUCE_CELLS(2);
+    } else if (TT > 256) {
         // T = 32: a padded tile reaches one tile on for every width
         FH_REDUCE(1, 4);
     } else {
@@ -1854,6 +2242,7 @@ fh_status run_spread(fh_ctx* c, const InstParams& p0, const InstParams* table, i
         else FH_REDUCE(2, 1);
     }
 #undef FH_REDUCE
+#undef FH_REDUCE_CELLS
     FH_HIP(hipGetLastError());
     c->tile_cnt_dirty = false;
     return FH_OK;
@@ -1877,15 +2266,20 @@ fh_status check_grid(int n1, int n2, double h1, double h2, double xc, double yc)
     return FH_OK;
 }
 
-// Spread method: the wavefront spread is the default (robust to the dense
-// clusters of dilation rules).  The work-item size is set per call.
-void spread_defaults(const fh_ctx* c, GridGeom& g)
+// Spread method: the option when set, else auto_method (the wavefront spread
+// for type 3, whose grids are small and points crowd; t1_method for type 1).
+// The work-item size is set per call.
+void spread_defaults(const fh_ctx* c, GridGeom& g, int auto_method = 2)
 {
-    g.method = c->opt.spread_method > 0 ? c->opt.spread_method : 2;
+    g.method = c->opt.spread_method > 0 ? c->opt.spread_method : auto_method;
     // the register tile needs T = 8 or 16, a padded tile row within one
     // wavefront and its four tiles within the LDS budget
     if (g.method == 4 && !((g.T == 8 || g.T == 16) && g.L <= 64 &&
                            spread_lds(g, c->prec == FH_FP64 ? 8 : 4) <= kLdsBudget))
+        g.method = 2;
+    // the matrix-core spread holds at most 32 x 32 cells, and its staging
+    // must fit the LDS budget
+    if (g.method == 5 && (g.L > 32 || mfma_spread_lds(g.L <= 16 ? 1 : 2, g.T, c->prec == FH_FP64 ? 8 : 4) > kLdsBudget))
         g.method = 2;
     g.P = c->opt.max_subproblem > 0 ? c->opt.max_subproblem : 0;
 }
@@ -1919,13 +2313,30 @@ T1Plan plan_t1(fh_ctx* c, int n1, int n2)
     g.T = T;
     g.W = W;
     g.L = T + W - 1;
-    g.nf1 = next_fft_size(std::max(need1, T + W), T);
-    g.nf2 = next_fft_size(std::max(need2, T + W), T);
-    g.ntx = g.nf1 / T;
-    g.nty = g.nf2 / T;
+    // power-of-two tiles divide the grid; other tiles (the matrix-core
+    // spread's 16-cell padded tiles) leave a partial last tile and keep the
+    // grid lengths of 16-cell tiles
+    const int step = (T & (T - 1)) == 0 ? T : 16;
+    g.nf1 = next_fft_size(std::max(need1, T + W), step);
+    g.nf2 = next_fft_size(std::max(need2, T + W), step);
+    g.ntx = (g.nf1 + T - 1) / T;
+    g.nty = (g.nf2 + T - 1) / T;
     g.rows = g.nf2;
     g.wrap_y = 1;
-    spread_defaults(c, g);
+    g.padx = g.ntx * T - g.nf1;
+    g.pady = g.nty * T - g.nf2;
+    // the tile reduce follows a padded tile at most two tiles on (one for
+    // tiles over 256 cells); a partial last tile brings the wrapped ones
+    // closer, so a tile that does not divide the grid falls back to 16
+    if ((T & (T - 1)) != 0 && (g.L - 1 + std::max(g.padx, g.pady)) / T > (T * T > 256 ? 1 : 2)) {
+        T = 16;
+        g.T = T;
+        g.L = T + W - 1;
+        g.ntx = g.nf1 / T;
+        g.nty = g.nf2 / T;
+        g.padx = g.pady = 0;
+    }
+    spread_defaults(c, g, t1_method(c, W));
     return p;
 }
 

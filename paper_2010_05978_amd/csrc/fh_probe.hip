@@ -1,8 +1,9 @@
 // fh_probe.hip -- measured ceilings for the rooflines that the benchmark
-// reports: HBM bandwidth from a device-to-device copy, and the LDS rates of
-// the operations the spread is built from (float and double atomic adds, and
-// the read-modify-write of complex double and complex float cells).  Each
-// figure is the best of several timed launches over the whole chip.
+// reports: HBM bandwidth from a device-to-device copy, the LDS rates of the
+// operations the spread is built from (float and double atomic adds, and the
+// read-modify-write of complex double and complex float cells), and the
+// matrix-core rate of the 16 x 16 x 4 products of the matrix-core spread.
+// Each figure is the best of several timed launches over the whole chip.
 #include "fh_common.hpp"
 
 namespace fh {
@@ -76,6 +77,38 @@ __global__ void __launch_bounds__(256) k_probe_lds_rmw(int iters, double* __rest
     }
     __syncthreads();
     if (threadIdx.x == 0) out[blockIdx.x] = (double)s[blockIdx.x & 2047].x;
+}
+
+// Matrix-core throughput of the 16 x 16 x 4 products the matrix-core spread
+// issues (v_mfma_f64_16x16x4f64, v_mfma_f32_16x16x4f32): every wavefront
+// keeps 8 independent accumulators and issues 8 products per iteration.
+template <class R> struct ProbeMma;
+template <> struct ProbeMma<double> {
+    typedef double V __attribute__((ext_vector_type(4)));
+    __device__ static V mma(double a, double b, V c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+};
+template <> struct ProbeMma<float> {
+    typedef float V __attribute__((ext_vector_type(4)));
+    __device__ static V mma(float a, float b, V c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+};
+
+template <class R>
+__global__ void __launch_bounds__(256) k_probe_mfma(int iters, double* __restrict__ out)
+{
+    using V = typename ProbeMma<R>::V;
+    V acc[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) acc[k] = V{R(0), R(0), R(0), R(0)};
+    R a = R(1) + R(threadIdx.x) * R(1e-3), b = R(2) - R(threadIdx.x) * R(1e-3);
+    for (int i = 0; i < iters; ++i) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) acc[k] = ProbeMma<R>::mma(a, b, acc[k]);
+        a += R(1e-7);
+    }
+    R t = R(0);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) t += acc[k][0] + acc[k][1] + acc[k][2] + acc[k][3];
+    if (t == R(-1)) out[blockIdx.x] = (double)t;  // never true; keeps the products live
 }
 
 // Best time in ms of `reps` launches of `launch` on the context stream.
@@ -175,6 +208,21 @@ extern "C" fh_status fh_probe_ceilings(fh_ctx* c, double* out)
             }, &ms);
         // 8 cells of 8 bytes read and written per lane and iteration
         if (s == FH_OK) out[4] = (double)lgrid * 256.0 * iters * 8 * 16.0 / (ms * 1e-3) / 1e9;
+        // matrix cores: 8 products of 16 x 16 x 4 (2 x 1024 flops) per
+        // wavefront and iteration, 4 wavefronts per block
+        const double mflop = (double)lgrid * 4.0 * iters * 8 * 2048.0;
+        if (s == FH_OK)
+            s = best_ms(c, 5, [&] {
+                hipLaunchKernelGGL((k_probe_mfma<double>), dim3(lgrid), dim3(256), 0, c->stream, iters,
+                                   static_cast<double*>(sink));
+            }, &ms);
+        if (s == FH_OK) out[5] = mflop / (ms * 1e-3) / 1e12;
+        if (s == FH_OK)
+            s = best_ms(c, 5, [&] {
+                hipLaunchKernelGGL((k_probe_mfma<float>), dim3(lgrid), dim3(256), 0, c->stream, iters,
+                                   static_cast<double*>(sink));
+            }, &ms);
+        if (s == FH_OK) out[6] = mflop / (ms * 1e-3) / 1e12;
         (void)hipStreamSynchronize(c->stream);
         (void)dev_free(c, sink);
         return s;

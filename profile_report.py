@@ -11,6 +11,10 @@
       plain device copy of known size in the same run: the 1 GiB copy of
       fh_probe_ceilings (k_probe_copy), which bench.py runs first, or else the
       256 MiB torch copy of bench.py --pmc-calib.
+
+  python profile_report.py table --fetch FETCH.db --write WRITE.db [--top N]
+      the same calibrated bytes per launch for every kernel of the two runs,
+      heaviest first.
 """
 from __future__ import annotations
 
@@ -78,6 +82,32 @@ def cmd_traffic(a):
     print(json.dumps(out))
 
 
+def cmd_table(a):
+    _, f_rows = counter_per_dispatch(a.fetch, "FETCH_SIZE", "")
+    _, w_rows = counter_per_dispatch(a.write, "WRITE_SIZE", "")
+    (f_copy, f_bytes), (w_copy, w_bytes) = copy_counter(f_rows), copy_counter(w_rows)
+    if not f_copy or not w_copy:
+        raise SystemExit("calibration copy not found in the counter runs")
+    f_scale = f_bytes / (f_copy * 1024.0)
+    w_scale = w_bytes / (w_copy * 1024.0)
+    per = {}
+    for rows, col, scale in ((f_rows, 0, f_scale), (w_rows, 1, w_scale)):
+        for n, v in rows:
+            per.setdefault(n, ([], []))[col].append(v * 1024.0 * scale)
+    tab = []
+    for n, (f, w) in per.items():
+        fm = statistics.mean(f) if f else float("nan")
+        wm = statistics.mean(w) if w else float("nan")
+        tab.append((fm + wm, fm, wm, len(f), len(w), n))
+    tab.sort(key=lambda r: -(r[0] if r[0] == r[0] else 0.0))
+    print(f"calibration: FETCH_SIZE x {f_scale:.4f}, WRITE_SIZE x {w_scale:.4f} "
+          "(bytes of the plain copy over the counter's reading)\n")
+    print("| dispatches (fetch, write) | fetch MB/launch | write MB/launch | kernel |")
+    print("|---:|---:|---:|---|")
+    for tot, fm, wm, nf, nw, n in tab[: a.top]:
+        print(f"| {nf}, {nw} | {fm / 1e6:.1f} | {wm / 1e6:.1f} | `{n[:110]}` |")
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -92,8 +122,12 @@ def main():
     t.add_argument("--source-hash", required=True)
     t.add_argument("--out", required=True)
     t.add_argument("--command", default="")
+    b = sub.add_parser("table")
+    b.add_argument("--fetch", required=True)
+    b.add_argument("--write", required=True)
+    b.add_argument("--top", type=int, default=30)
     a = ap.parse_args()
-    cmd_stats(a) if a.cmd == "stats" else cmd_traffic(a)
+    {"stats": cmd_stats, "traffic": cmd_traffic, "table": cmd_table}[a.cmd](a)
 
 
 if __name__ == "__main__":

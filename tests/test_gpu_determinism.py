@@ -37,7 +37,7 @@ def test_spread_repeatable_to_rounding(fh, prec):
     ctx = fh.Context(prec)
     q = ctx.quad_for(wl.shape)
     out = {}
-    for method in (2, 3, 4):
+    for method in (2, 3, 4, 5):
         ctx.set_options(fh.fh_options(sigma=0, kernel_width=0, beta=0.0, tile=16, max_subproblem=0,
                                       spread_method=method))
         a = ctx.field_grid(q, wl.lam, wl.z, g.n1, g.n2, g.h1, g.h2).clone()

@@ -158,7 +158,8 @@ def test_grid_shapes_and_translation(ctx, n1, n2, h1, h2, xc, yc):
     (1, 16, 64, 0.0), (2, 16, 64, 0.0), (1, 32, 1024, 0.0), (2, 32, 4096, 0.0), (2, 8, 256, 0.0),
     (2, 32, 256, 1.25), (1, 16, 512, 1.25), (3, 16, 64, 0.0), (3, 32, 16, 1.25), (0, 0, 0, 0.0),
     (4, 16, 64, 0.0), (4, 8, 256, 0.0), (4, 16, 32, 1.25), (4, 32, 64, 0.0), (4, 16, 4096, 0.0),
-    (4, 8, 16, 0.0),
+    (4, 8, 16, 0.0), (5, 16, 64, 0.0), (5, 8, 256, 0.0), (5, 16, 4096, 1.25), (5, 8, 16, 0.0),
+    (5, 32, 1024, 0.0),
 ])
 def test_spread_variants(fh, ctx, method, tile, P, sigma):
     # every spread method / tile / work-item size / upsampling the autotuner
@@ -403,9 +404,9 @@ def test_error_statuses(fh):
     with pytest.raises(fh.FresnelError) as e:
         abi.fh_quad_radial(c.handle, 1.0, np.zeros(65), None, 1, 4, 3)
     assert e.value.status == fh.FH_ERR_INVALID_ARG
-    # spread tiles of 8, 16 or 32 cells only (the tile reduce covers at most
+    # spread tiles of 4 to 32 cells only (the tile reduce covers at most
     # 1024 cells per tile)
-    for bad in (4, 64):
+    for bad in (3, 64):
         with pytest.raises(fh.FresnelError) as e:
             c.set_options(fh.fh_options(sigma=0, kernel_width=0, beta=0.0, tile=bad, max_subproblem=0,
                                         spread_method=0))
@@ -443,3 +444,33 @@ def test_many_transform_lengths(fh, ctx):
         up = cpu(ctx.field_points(q, lam, z, torch.tensor(xi, device="cuda"), torch.tensor(eta, device="cuda")))
         ref = oracle.fresnel_direct(x, y, w, lam, z, xi, eta)
         assert relL2(up, ref) <= TOL[ctx.precision], ext
+
+
+@pytest.mark.parametrize("method,tile", [(5, 0), (5, 6), (5, 10), (2, 6), (2, 10)])
+@pytest.mark.parametrize("h", [0.006, 0.05])
+def test_tiles_that_do_not_divide_the_grid(fh, ctx, method, tile, h):
+    # tiles of 6 or 10 cells on fine grids of 1024 x 768 cells: the last
+    # tile of each row (and, for 10, of each column) is partial and the
+    # padded tiles that wrap around the period land closer; h = 0.006 holds a
+    # window of rows, h = 0.05 the whole period (folded nodes, wrap in y)
+    wl = workloads.workload(2)
+    shape = workloads.RadialCurve(1.0, wl.shape.a, wl.shape.b, panels=12, q=16, m=60)
+    opt = fh.fh_options(sigma=2.0, kernel_width=0, beta=0.0, tile=tile, max_subproblem=0, spread_method=method)
+    ctx.set_options(opt)
+    n1, n2 = 512, 384
+    try:
+        q = ctx.quad_for(shape)
+        u = cpu(ctx.field_grid(q, wl.lam, wl.z, n1, n2, h, 0.9 * h, xc=0.02, yc=-0.03)).ravel()
+        assert ctx.query_params(n1)["nf"] == 1024
+    finally:
+        ctx.set_options(None)
+    x, y, w = oracle_quad(shape)
+    xi, eta = oracle.grid_targets(n1, n2, h, 0.9 * h, 0.02, -0.03)
+    idx = np.random.Generator(np.random.PCG64(41)).choice(n1 * n2, 4000, replace=False)
+    # every target of the first and last rows and columns as well
+    k = np.arange(n1 * n2).reshape(n2, n1)
+    idx = np.unique(np.concatenate([idx, k[0], k[-1], k[:, 0], k[:, -1]]))
+    ref = oracle.fresnel_direct(x, y, w, wl.lam, wl.z, xi[idx], eta[idx])
+    err = relL2(u[idx], ref)
+    print(f"  {ctx.precision} method {method} tile {tile} h {h}: rel L2 {err:.2e}", flush=True)
+    assert err <= TOL[ctx.precision]
