@@ -7,9 +7,11 @@ in [1e4, 4e5], 51.7 million nodes in all), one wavelength each from 64
 log-spaced in [0.5, 1.0] um, z = 1e5 m, every shape's field on a 512 x 512
 grid over [-1.5, 1.5)^2 (67.1 million targets), as one batched call: strengths
 and binning, the spread over every instance's work items, the row FFTs, the
-column FFTs with the deconvolving epilogue, replayed from a hipGraph.  As in
-the paper's timings, the rules are built before the timed region; a second
-figure builds all 256 rules on the device in every step.
+column FFTs with the deconvolving epilogue, replayed from a hipGraph, with the
+options the batch autotuner picks for this batch (tuned before the timed
+region).  As in the paper's timings, the rules are built before the timed
+region; a second figure (with_rules) regenerates all 256 rules on the device
+inside the same captured graph in every step.
 
 value = targets/s of the FP64 path (tolerance 1e-9, relative L2 against the
 exact quadrature sum); beside it the mixed-precision path (tolerance 1e-5) and
@@ -18,8 +20,10 @@ and rules are resident on the device before the timed region starts.
 
 The roofline entry is for the kernel with the most device time in the
 headline step (the spread), from its average launch time measured live with
-HIP events on the library's stream over a second pass of the same steps, with
-denominators measured on the device (fh_probe_ceilings).  Further legs: the
+HIP events on the library's stream over a second pass of the same steps,
+against MI355X's published peak for the unit that bounds it (the matrix
+cores for the matrix-core spread), with the measured ceilings beside it
+(fh_probe_ceilings).  Further legs: the
 starshade of workload 3 (2048^2 grid and 1e6 pupil points at 3 wavelengths),
 the starfish of workload 2, the shape gradient of workload 5, the edge
 integral and the paper's own tasks (kite, HG starshade, Koch snowflake).
@@ -105,13 +109,31 @@ class Batch:
         self.N = sum(q.N for q in self.quads)
         self.M = self.B * self.g.M
         self.out = torch.empty((self.B, self.g.n2, self.g.n1), dtype=self.ctx.cdtype, device="cuda")
+        self.tuned = None
+
+    def tune(self):
+        """Options of the batched call from the batch autotuner (graph replays
+        of this batch over methods, tiles, item sizes and sigma)."""
+        g = self.g
+        t0 = time.perf_counter()
+        o = self.ctx.autotune_batch(self.quads, self.lams, self.zs, g.n1, g.n2, g.h1, g.h2)
+        self.tuned = {"sigma": o.sigma, "tile": o.tile, "max_subproblem": o.max_subproblem,
+                      "spread_method": o.spread_method, "tuning_s": time.perf_counter() - t0}
+        return self.tuned
 
     def field(self, quads=None):
         g = self.g
         self.ctx.field_grid_batch(quads or self.quads, self.lams, self.zs, g.n1, g.n2, g.h1, g.h2, out=self.out)
 
-    def with_rules(self):
-        """Build all 256 rules on the device, then the batched field."""
+    def field_rebuild(self):
+        """The batched field with all 256 rules generated again on the device
+        inside the same captured graph."""
+        g = self.g
+        self.ctx.field_grid_batch_rebuild(self.quads, self.lams, self.zs, g.n1, g.n2, g.h1, g.h2, out=self.out)
+
+    def with_rules_api(self):
+        """Build all 256 rules through the API (one call each), then the
+        batched field."""
         quads = [self.ctx.quad_for(s) for s in self.shapes]
         self.field(quads)
         for q in quads:
@@ -129,19 +151,25 @@ FP64_PEAK_TFLOPS = 78.6
 HBM_PEAK_GBS = 8000.0
 
 
-def spread_name(prec, W):
-    """Kernel name of the default spread for width W: the matrix-core spread
-    on 16-cell padded tiles (tile 17 - W, one 16 x 16 block, 16 points staged
-    at a time) up to W = 11, else the wavefront spread on 16-cell tiles."""
+def spread_name(prec, W, method=5, tile=0):
+    """Kernel name of the spread for width W, method and tile option (0:
+    the method's own tile): the matrix-core spread holds a 16-cell padded
+    tile (tile 17 - W) in one 16 x 16 block, a larger one in 2 x 2 blocks, and
+    stages 16 points at a time; the wavefront spread takes two wavefronts per
+    work item when their two tiles and the staging fit 64 KiB."""
     rs = 8 if prec == "fp64" else 4
     real = "double" if rs == 8 else "float"
-    if W <= 11:
-        return f"k_spread_mfma<{real}, {W}, 1, 16>"
-    L = 16 + W - 1
-    tile = 2 * rs * (L * L + 1)
+    if method == 5 and W <= 11:
+        T = tile if tile else 17 - W
+        return f"k_spread_mfma<{real}, {W}, {1 if T + W - 1 <= 16 else 2}, 16>"
+    T = tile if tile else 16
+    L = T + W - 1
+    if method == 4:
+        return f"k_spread_reg<{real}, {W}, {T}>"
+    tile_b = 2 * rs * (L * L + 1)
     staging = rs * (64 * (2 * W + 2) + 128)
-    nv = 2 if 2 * tile + staging <= 64 * 1024 else 1
-    return f"k_spread_wave<{real}, {W}, false, {nv}>"
+    nv = 2 if 2 * tile_b + staging <= 64 * 1024 else 1
+    return f"k_spread_wave<{real}, {W}, {'true' if method == 3 else 'false'}, {nv}>"
 
 
 def batch_leg(fh, prec, steps, warmup, ceilings):
@@ -150,8 +178,10 @@ def batch_leg(fh, prec, steps, warmup, ceilings):
     library's stream (timing on: the batch then runs eagerly, stage [1]
     brackets the spread kernel alone)."""
     b = Batch(fh, prec)
+    tuned = b.tune()
     ms = cuda_ms(b.field, steps, warmup)
-    ms_rules = cuda_ms(b.with_rules, max(3, steps // 4), 1)
+    ms_rules = cuda_ms(b.field_rebuild, steps, warmup)
+    ms_api = cuda_ms(b.with_rules_api, max(3, steps // 4), 1)
     b.ctx.set_timing(True)
     b.ctx.timing_totals(3, reset=True)
     for _ in range(steps):
@@ -168,20 +198,31 @@ def batch_leg(fh, prec, steps, warmup, ceilings):
     # the matrix cores issue 16 * 16 * 4 * 2 * 2 / 4 = 1024 flops per node on
     # one 16 x 16 block (real and imaginary parts, four nodes per product)
     flops = b.N * W * W * 8
-    issued = b.N * 1024
     hbm_bytes = b.N * (4 + 4 * rs)             # packed cell, offsets and strength per node
-    peak = MFMA_PEAK_TFLOPS[prec]
-    kern = spread_name(prec, W)
-    roof = {"bound": "mfma", "achieved": flops / t_spread / 1e12, "peak": peak, "unit": "TFLOP/s",
-            "frac": flops / t_spread / 1e12 / peak, "traffic": None, "kernel": kern,
-            "avg_launch_ms": stages[1], "algorithmic_flops_per_launch": flops,
-            "peak_source": "MI355X published dense " + ("FP64" if rs == 8 else "FP32") + " matrix-core peak",
-            "issued_mfma_tflops": issued / t_spread / 1e12,
-            "measured_mfma_peak_tflops": ceilings["mfma_f64_tflops" if rs == 8 else "mfma_f32_tflops"],
-            "hbm": {"achieved": hbm_bytes / t_spread / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": hbm_bytes / t_spread / 1e9 / HBM_PEAK_GBS,
-                    "algorithmic_bytes_per_launch": hbm_bytes,
-                    "measured_copy_gbs": ceilings["hbm_copy_gbs"]}}
+    kern = spread_name(prec, W, tuned["spread_method"], tuned["tile"])
+    hbm = {"achieved": hbm_bytes / t_spread / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": hbm_bytes / t_spread / 1e9 / HBM_PEAK_GBS, "algorithmic_bytes_per_launch": hbm_bytes,
+           "measured_copy_gbs": ceilings["hbm_copy_gbs"]}
+    if kern.startswith("k_spread_mfma"):
+        # the matrix cores issue 16 * 16 * 4 * 2 * 2 / 4 flops per node and
+        # 16 x 16 block (real and imaginary parts, four nodes per product)
+        issued = b.N * 1024 * (1 if ", 1, 16>" in kern else 4)
+        peak = MFMA_PEAK_TFLOPS[prec]
+        roof = {"bound": "mfma", "achieved": flops / t_spread / 1e12, "peak": peak, "unit": "TFLOP/s",
+                "frac": flops / t_spread / 1e12 / peak, "traffic": None, "kernel": kern,
+                "avg_launch_ms": stages[1], "algorithmic_flops_per_launch": flops,
+                "peak_source": "MI355X published dense " + ("FP64" if rs == 8 else "FP32") + " matrix-core peak",
+                "issued_mfma_tflops": issued / t_spread / 1e12,
+                "measured_mfma_peak_tflops": ceilings["mfma_f64_tflops" if rs == 8 else "mfma_f32_tflops"],
+                "hbm": hbm}
+    else:
+        # one complex read-modify-write of an LDS cell per stencil cell and node
+        lds_bytes = b.N * W * W * 4 * rs
+        lds_peak = ceilings["lds_rmw_c128_gbs" if prec == "fp64" else "lds_rmw_c64_gbs"]
+        roof = {"bound": "lds", "achieved": lds_bytes / t_spread / 1e9, "peak": lds_peak, "unit": "GB/s",
+                "frac": lds_bytes / t_spread / 1e9 / lds_peak, "traffic": None, "kernel": kern,
+                "avg_launch_ms": stages[1], "algorithmic_bytes_per_launch": lds_bytes,
+                "peak_source": "fh_probe_ceilings: LDS read-modify-write of complex cells", "hbm": hbm}
     for path in TRAFFIC_FILES:
         if os.path.exists(path):
             t = json.load(open(path))
@@ -194,7 +235,12 @@ def batch_leg(fh, prec, steps, warmup, ceilings):
                          "slot_merge_reduce_row_fft": stages[2], "column_fft_epilogue": stages[3],
                          "whole_call_eager": stages[4]},
            "with_rules": {"ms_per_step": ms_rules, "value": b.M / (ms_rules * 1e-3),
-                          "note": "256 device rule builds (one launch each) plus the batched call per step"},
+                          "note": "the 256 rule kernels and the batched call in one captured graph per step "
+                                  "(fh_field_grid_batch_rebuild)"},
+           "rules_through_api": {"ms_per_step": ms_api,
+                                 "note": "256 fh_quad_* calls (allocation and one launch each), then the "
+                                         "batched call"},
+           "tuned_options": tuned,
            "roofline": roof}
     b.close()
     return out
@@ -732,7 +778,8 @@ def main():
             "config": {"workload": "256 random shapes (smooth radial Fourier curves and polygons, 8-32 modes), "
                                    "node counts uniform in [1e4, 4e5], one wavelength each from 64 log-spaced in "
                                    "[0.5, 1.0] um, z = 1e5 m; 512x512 grid on [-1.5, 1.5)^2 per shape; one "
-                                   "batched call replayed from a hipGraph; rules built before the timed region",
+                                   "batched call replayed from a hipGraph with autotuned options; rules built "
+                                   "before the timed region (with_rules: inside it)",
                        "instances": r["instances"], "nodes": r["nodes"], "targets_per_step": r["targets"],
                        "tolerance": r["tolerance"]},
             "roofline": r["roofline"],

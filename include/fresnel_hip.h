@@ -106,6 +106,14 @@ typedef struct fh_options {
                              * 2 to 5 sum a work item's points in a fixed    *
                              * order (the point order within a tile comes    *
                              * from atomic counters in the binning)          */
+    int32_t deterministic;  /* 1: stable binning -- the nodes of each tile   *
+                             * in node order (a stable radix sort of the     *
+                             * tile keys instead of atomic ranks), method 1  *
+                             * replaced by 2, and batched calls run eagerly  *
+                             * (no graph): a call repeated with the same     *
+                             * inputs and options on the same device gives   *
+                             * bitwise the same field.  0: atomic ranks,     *
+                             * equal to rounding only.                       */
 } fh_options;
 
 /* ---------------------------------------------------------------- context */
@@ -352,6 +360,21 @@ fh_status fh_field_grid_batch(fh_ctx* ctx, int32_t B, const fh_quad* const* q,
                               double h1, double h2, double xc, double yc,
                               const int32_t* occulter, void* u);
 
+/* As fh_field_grid_batch, with the quadrature generation (sec. 3) inside the
+ * call: every rule's nodes and weights are first computed again on the
+ * device, in place, from the boundary parameters it was made with, and for
+ * B > 1 those rule kernels are captured into the same hipGraph as the field
+ * (the paper's wavelength sweep counts quadrature generation, sec. 4.3).
+ * Only rules built by one launch from parameters held by value can be
+ * rebuilt: fh_quad_radial rules and fh_quad_polygon rules of up to 128
+ * vertices; any other rule gives FH_ERR_UNSUPPORTED before anything is
+ * enqueued.  The rules' contents afterwards are what their constructors
+ * wrote. */
+fh_status fh_field_grid_batch_rebuild(fh_ctx* ctx, int32_t B, fh_quad* const* q,
+                                      const double* lambda, const double* z, int32_t n1,
+                                      int32_t n2, double h1, double h2, double xc, double yc,
+                                      const int32_t* occulter, void* u);
+
 /* ----------------------------------------------------------------- adjoint */
 
 /* Vector-Jacobian product of fh_field_grid with respect to the rule's nodes
@@ -454,6 +477,21 @@ fh_status fh_field_nsli_noalloc(fh_ctx* ctx, const double* X, const double* Y, c
 fh_status fh_autotune_grid(fh_ctx* ctx, const fh_quad* q, double lambda, double z, int32_t n1,
                            int32_t n2, double h1, double h2, const char* cache_path,
                            fh_options* best);
+
+/* The same for a batch (sec. 4.3's many shapes and wavelengths): time
+ * fh_field_grid_batch with these B rules, wavelengths and distances as it
+ * runs (captured into a graph, then replayed) over spread methods 5, 2 and
+ * 4, tile edges, work-item sizes and upsampling factors that meet the
+ * context's tolerance, and keep the fastest in the context (the caller's
+ * kernel width, beta and deterministic flag are kept).  The cache key is the
+ * batch's signature: precision, tolerance, grid size, B, and the node-count
+ * classes (powers of two) of the whole batch and of its largest rule.
+ * Arguments as fh_field_grid_batch (plane grids centred on the axis, no
+ * occulter); q, lambda and z are host arrays of B entries.  Allocates a
+ * B x n2 x n1 output for the trials. */
+fh_status fh_autotune_batch(fh_ctx* ctx, int32_t B, const fh_quad* const* q, const double* lambda,
+                            const double* z, int32_t n1, int32_t n2, double h1, double h2,
+                            const char* cache_path, fh_options* best);
 
 /* Stage timing.  While enabled (fh_set_timing, or FH_TIMING=1 in the
  * environment at fh_create) every fh_field_grid / fh_field_points /

@@ -234,6 +234,16 @@ class Context:
                                 occulter, out)
         return out
 
+    def field_grid_batch_rebuild(self, quads, lams, zs, n1, n2, h1, h2, xc=0.0, yc=0.0, occulter=False, out=None):
+        """field_grid_batch with every rule rebuilt on the device first, inside
+        the same captured graph (radial and polygon rules only)."""
+        import torch
+        if out is None:
+            out = torch.empty((len(quads), n2, n1), dtype=self.cdtype, device=self.device)
+        abi.fh_field_grid_batch_rebuild(self.handle, [q.handle for q in quads], lams, zs, n1, n2, h1, h2, xc, yc,
+                                        occulter, out)
+        return out
+
     def field_grid_vjp(self, quad: Quad, lam, z, n1, n2, h1, h2, g_u, xc=0.0, yc=0.0, occulter=False):
         import torch
         n = quad.N
@@ -245,6 +255,11 @@ class Context:
     def autotune_grid(self, quad: Quad, lam, z, n1, n2, h1, h2, cache_path=None) -> fh_options:
         """Time the grid field over the tuning space and keep the fastest options."""
         return abi.fh_autotune_grid(self.handle, quad.handle, lam, z, n1, n2, h1, h2, cache_path)
+
+    def autotune_batch(self, quads, lams, zs, n1, n2, h1, h2, cache_path=None) -> fh_options:
+        """Time the batched call (graph capture and replay) over the tuning
+        space and keep the fastest options; keyed by the batch's signature."""
+        return abi.fh_autotune_batch(self.handle, [q.handle for q in quads], lams, zs, n1, n2, h1, h2, cache_path)
 
     def query_params(self, n):
         return abi.fh_query_params(self.handle, n)

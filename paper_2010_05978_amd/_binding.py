@@ -40,7 +40,7 @@ EXPORTED = [
     "fh_boundary_radial", "fh_boundary_polygon", "fh_boundary_starshade", "fh_field_nsli",
     "fh_quad_fourier", "fh_boundary_fourier", "fh_quad_koch", "fh_quad_starshade_rigid",
     "fh_quad_starshade_tab", "fh_targets_sort", "fh_probe_ceilings", "fh_quad_set_illumination",
-    "fh_field_nsli_noalloc", "fh_quad_starshade_ribbon",
+    "fh_field_nsli_noalloc", "fh_quad_starshade_ribbon", "fh_autotune_batch", "fh_field_grid_batch_rebuild",
 ]
 
 
@@ -52,7 +52,8 @@ class FresnelError(RuntimeError):
 
 class fh_options(ctypes.Structure):
     _fields_ = [("sigma", ctypes.c_double), ("kernel_width", ctypes.c_int32), ("beta", ctypes.c_double),
-                ("tile", ctypes.c_int32), ("max_subproblem", ctypes.c_int32), ("spread_method", ctypes.c_int32)]
+                ("tile", ctypes.c_int32), ("max_subproblem", ctypes.c_int32), ("spread_method", ctypes.c_int32),
+                ("deterministic", ctypes.c_int32)]
 
 
 _lib = None
@@ -98,6 +99,8 @@ def lib():
             "fh_field_grid_vjp": [vp, vp, d, d, i32, i32, d, d, d, d, i32, vp, vp, vp, vp],
             "fh_starshade_vjp": [vp, i32, d, d, d, d, i32, i32, i32, i32, vp, i32, vp, vp, vp, vp],
             "fh_autotune_grid": [vp, vp, d, d, i32, i32, d, d, ctypes.c_char_p, ctypes.POINTER(fh_options)],
+            "fh_autotune_batch": [vp, i32, vp, vp, vp, i32, i32, d, d, ctypes.c_char_p, ctypes.POINTER(fh_options)],
+            "fh_field_grid_batch_rebuild": [vp, i32, vp, vp, vp, i32, i32, d, d, d, d, vp, vp],
             "fh_set_timing": [vp, i32],
             "fh_last_timing": [vp, ctypes.POINTER(d)],
             "fh_timing_totals": [vp, i32, ctypes.POINTER(d), ctypes.POINTER(i64), i32],
@@ -503,6 +506,31 @@ def fh_autotune_grid(ctx, q, lam, z, n1, n2, h1, h2, cache_path=None):
     best = fh_options()
     cp = cache_path.encode() if cache_path else None
     _check(lib().fh_autotune_grid(ctx, q, lam, z, n1, n2, h1, h2, cp, ctypes.byref(best)))
+    return best
+
+
+def fh_field_grid_batch_rebuild(ctx, quads, lams, zs, n1, n2, h1, h2, xc, yc, occulter, u):
+    B = len(quads)
+    qarr = (ctypes.c_void_p * B)(*[q.value if isinstance(q, ctypes.c_void_p) else q for q in quads])
+    la = np.ascontiguousarray(lams, dtype=np.float64)
+    za = np.ascontiguousarray(zs, dtype=np.float64)
+    oc = np.ascontiguousarray(np.broadcast_to(np.asarray(occulter, dtype=np.int32), (B,)))
+    ptr, mem = _ptr_mem(u)
+    if mem != FH_MEM_DEVICE:
+        raise ValueError("fh_field_grid_batch_rebuild writes device memory only")
+    _check(lib().fh_field_grid_batch_rebuild(ctx, B, ctypes.cast(qarr, ctypes.c_void_p), _ptr_mem(la)[0],
+                                             _ptr_mem(za)[0], n1, n2, h1, h2, xc, yc, _ptr_mem(oc)[0], ptr))
+
+
+def fh_autotune_batch(ctx, quads, lams, zs, n1, n2, h1, h2, cache_path=None):
+    B = len(quads)
+    qarr = (ctypes.c_void_p * B)(*[q.value if isinstance(q, ctypes.c_void_p) else q for q in quads])
+    la = np.ascontiguousarray(lams, dtype=np.float64)
+    za = np.ascontiguousarray(zs, dtype=np.float64)
+    best = fh_options()
+    cp = cache_path.encode() if cache_path else None
+    _check(lib().fh_autotune_batch(ctx, B, ctypes.cast(qarr, ctypes.c_void_p), _ptr_mem(la)[0], _ptr_mem(za)[0],
+                                   n1, n2, h1, h2, cp, ctypes.byref(best)))
     return best
 
 

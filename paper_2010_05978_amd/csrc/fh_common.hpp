@@ -12,6 +12,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
+#include <functional>
 #include <map>
 #include <memory>
 #include <string>
@@ -216,6 +217,18 @@ struct fh_ctx {
     uint64_t order_seq = 0;          // last value enqueued for it
 };
 
+namespace fh {
+// Polygons of up to this many vertices pass them to the rule kernel by value.
+constexpr int kPolyByValue = 128;
+
+// The stable binning's sort of n (tile key, node index) pairs by the low
+// key_bits of the key, on the context stream, and its scratch bytes
+// (fh_field.hip).
+size_t tile_sort_bytes(int64_t n);
+fh_status tile_sort(fh_ctx* c, const uint32_t* key, uint32_t* key_sorted, const int* vals, int* vals_sorted,
+                    int64_t n, int key_bits, void* tmp, size_t tmp_bytes);
+}  // namespace fh
+
 struct fh_quad {
     fh_ctx* ctx = nullptr;
     int64_t N = 0;
@@ -231,6 +244,11 @@ struct fh_quad {
     double D = 0.0;
     bool bbox_valid = false;
     double bbox[4] = {0, 0, 0, 0};  // xmin, xmax, ymin, ymax
+    // Enqueues the rule kernels again, in place, from the boundary parameters
+    // the rule was made from (rules built by one launch with their
+    // parameters by value: radial curves and small polygons); empty for the
+    // others.
+    std::function<fh_status()> rebuild;
 };
 
 // A scattered-target set: the device coordinates (the caller's arrays, or a

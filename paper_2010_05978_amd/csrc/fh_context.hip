@@ -584,6 +584,7 @@ static fh_status check_options(const fh_options* o)
     FH_ARG(o->max_subproblem >= 0, FH_ERR_INVALID_ARG, "max_subproblem must be >= 0");
     FH_ARG(o->spread_method >= 0 && o->spread_method <= 5, FH_ERR_INVALID_ARG,
            "spread_method must be 0, 1, 2, 3, 4 or 5");
+    FH_ARG(o->deterministic == 0 || o->deterministic == 1, FH_ERR_INVALID_ARG, "deterministic must be 0 or 1");
     return FH_OK;
 }
 

@@ -11,10 +11,10 @@
 //        spread:  exponential-of-semicircle (ES) kernel into a (T+W-1)^2 LDS
 //                 tile per work item, written out as one slot per work item,
 //        reduce:  every fine-grid cell sums the slots that cover it (no
-//                 global atomics, no separate zero fill; a fixed order of
-//                 slots, though the binning's atomic counters may order a
-//                 tile's points differently from call to call),
-//        FFT:     rocFFT,
+//                 global atomics; a fixed order of slots, though the
+//                 binning's atomic counters may order a tile's points
+//                 differently from call to call),
+//        FFT:     in LDS where a row or column fits, else rocFFT,
 //        finish:  deconvolution by the kernel's Fourier transform (type 1), or
 //                 precorrection, a second FFT and kernel interpolation at the
 //                 targets (type 3);
@@ -22,14 +22,37 @@
 //      u_oc = 1 - u_ap for occulters (eq. bab).
 //
 // Type 1 holds only the fine-grid rows the nodes can reach (a window found
-// from the rule's bounding box): the first FFT pass runs over those rows, a
-// transpose pads the n1 needed columns back to full length, and the second
-// pass and the epilogue work on those columns only.
+// from the rule's bounding box): the first FFT pass runs over those rows, and
+// the second pass and the epilogue work on the n1 needed columns only.  When
+// a row and a column fit in LDS, the first pass is fused with the reduce (the
+// fine grid is never stored) and the second with the epilogue; otherwise
+// rocFFT transforms the stored rows, and a transpose pads the needed columns
+// back to full length for a second rocFFT pass.
 #include "fh_kernels.hpp"
 
 #include <hipcub/device/device_radix_sort.hpp>
 
 namespace fh {
+
+size_t tile_sort_bytes(int64_t n)
+{
+    size_t temp = 0;
+    if (hipcub::DeviceRadixSort::SortPairs(nullptr, temp, (const uint32_t*)nullptr, (uint32_t*)nullptr,
+                                           (const int*)nullptr, (int*)nullptr, (int)n, 0, 32) != hipSuccess)
+        temp = 0;
+    return std::max<size_t>(temp, 1);
+}
+
+// Stable sort of n (tile key, node index) pairs by the low key_bits of the
+// key: least-significant-digit radix passes keep equal keys in input order.
+fh_status tile_sort(fh_ctx* c, const uint32_t* key, uint32_t* key_sorted, const int* vals, int* vals_sorted,
+                    int64_t n, int key_bits, void* tmp, size_t tmp_bytes)
+{
+    size_t temp = tmp_bytes;
+    FH_HIP(hipcub::DeviceRadixSort::SortPairs(tmp, temp, key, key_sorted, vals, vals_sorted, (int)n, 0, key_bits,
+                                              c->stream));
+    return FH_OK;
+}
 
 // Sequences per workgroup for an LDS FFT of length n over `count`
 // sequences: as many as give 64 bytes of contiguous output per row segment
@@ -132,13 +155,50 @@ LdsCols lds_cols_plan(fh_ctx* c, int n, int64_t count, size_t rs, int min_c = 0)
             FH_LDS_LAUNCH_R7(KERNEL, R, false, lc, grid, stream, __VA_ARGS__);                                   \
     } while (0)
 
+// LDS bytes of a k_t1_rows block: the rows and twiddles of the FFT, then the
+// heads of the covering tile rows.
+inline size_t t1_rows_lds(const LdsCols& lr, const GridGeom& gg, int reach, size_t rs)
+{
+    return t1_rows_table_offset(lr.C, lr.plan.n, lr.plan.ntw, 2 * rs) +
+           sizeof(int4) * (size_t)t1_rows_table_rows(lr.C, gg.T, reach) * gg.ntx;
+}
+
+// The fused tile reduce and first FFT pass (k_t1_rows) in the block shape
+// that lr picked, for a padded tile reaching one tile on.
+template <class R>
+fh_status launch_t1_rows(fh_ctx* c, const LdsCols& lr, int reach, int B, int groups, const GridGeom& gg,
+                         const SpreadBufs& sb, int n1, R* G)
+{
+    using C2 = typename V2<R>::T;
+    const int tpi = gg.ntx * gg.nty;
+    const dim3 grid(xcd_blocks(groups), B);
+    const size_t lds = t1_rows_lds(lr, gg, reach, sizeof(R));
+#define FH_ROWS(RE, R7)                                                                                          \
+    do {                                                                                                         \
+        if (lr.small)                                                                                            \
+            hipLaunchKernelGGL((k_t1_rows<R, kLdsFftSmall, 256, R7, RE>), grid, dim3(256), lds, c->stream,       \
+                               (const C2*)sb.slots, sb.tsub, gg, tpi, lr.C, groups, lr.plan, n1, G, sb.cnt);     \
+        else                                                                                                     \
+            hipLaunchKernelGGL((k_t1_rows<R, (int)(kLdsFftBytes / (2 * sizeof(R))), 512, R7, RE>), grid,          \
+                               dim3(512), lds, c->stream, (const C2*)sb.slots, sb.tsub, gg, tpi, lr.C, groups,    \
+                               lr.plan, n1, G, sb.cnt);                                                          \
+    } while (0)
+    FH_ARG(reach == 1, FH_ERR_UNSUPPORTED, "the fused row pass needs a padded tile reaching one tile on");
+    if (lds_has7(lr.plan)) FH_ROWS(1, true);
+    else FH_ROWS(1, false);
+#undef FH_ROWS
+    FH_HIP(hipGetLastError());
+    return FH_OK;
+}
+
 // The type-1 pipeline for B instances sharing one grid geometry; u is device
 // memory (B x n2 x n1).  With `capture`, the launch sequence is recorded into
-// a hipGraph keyed by everything baked into it and replayed.
+// a hipGraph keyed by everything baked into it and replayed.  With
+// `rebuild`, every rule's kernels run again first (inside the graph).
 template <class R>
 fh_status t1_pipeline(fh_ctx* c, int B, const fh_quad* const* qs, const double* lambda, const double* z, int n1,
                       int n2, double h1, double h2, double xc, double yc, const int32_t* occ, R* u, bool capture,
-                      size_t extra_bytes, void** extra)
+                      size_t extra_bytes, void** extra, bool rebuild = false)
 {
     const size_t rs = sizeof(R);
     T1Plan pl = plan_t1(c, n1, n2);
@@ -191,17 +251,26 @@ fh_status t1_pipeline(fh_ctx* c, int B, const fh_quad* const* qs, const double* 
     FH_TRY(iphi_table(c, pl.k, n2, gg.nf2, &ip2));
     FftPlan* fa = nullptr;
     FftPlan* fb = nullptr;
-    FH_TRY(fft_plan(c, gg.nf1, 0, gg.rows * B, &fa));
     // second pass: in LDS, fused with the epilogue, when a column fits
     LdsCols lc = lds_cols_plan(c, gg.nf2, (int64_t)n1 * B, rs);
+    // first pass: in LDS as well, fused with the tile reduce, when a row fits
+    // too and a padded tile reaches one tile on (nine covering tiles per
+    // cell cost more than the stored grid's list reduce); the fine grid is
+    // then never stored, only the n1 needed columns of its transformed rows
+    // (F holds B x rows x n1 values)
+    const int reach = tile_reach(gg);
+    LdsCols lr;
+    if (lc.C > 0 && reach == 1) lr = lds_cols_plan(c, gg.nf1, (int64_t)gg.rows * B, rs, 1);
+    const bool fused = lr.C > 0 && t1_rows_lds(lr, gg, reach, rs) <= kLdsFftBytes;
+    if (!fused) FH_TRY(fft_plan(c, gg.nf1, 0, gg.rows * B, &fa));
     if (lc.C == 0) FH_TRY(fft_plan(c, gg.nf2, 0, n1 * B, &fb));
 
     FH_TRY(counters_ready(c, (int64_t)tpi * B));
-    const size_t F_count = 2 * (size_t)B * gg.rows * gg.nf1;
+    const size_t F_count = 2 * (size_t)B * gg.rows * (fused ? n1 : gg.nf1);
     const size_t Z_count = lc.C > 0 ? 0 : 2 * (size_t)B * n1 * gg.nf2;
     const size_t E2_bytes = lc.C > 0 ? aligned_bytes(sizeof(double2) * (size_t)B * n2) : 0;
     size_t need = aligned_bytes(rs * F_count) + aligned_bytes(rs * Z_count) + E2_bytes +
-                  spread_bytes(Ntot, gg, tpi * B, rs) + aligned_bytes(sizeof(InstParams) * B) +
+                  spread_bytes(c, Ntot, gg, tpi * B, rs) + aligned_bytes(sizeof(InstParams) * B) +
                   aligned_bytes(sizeof(EpiInst) * B) + aligned_bytes(extra_bytes);
     FH_TRY(arena_reserve(c, need));
     R* F = c->arena.take<R>(F_count);
@@ -220,15 +289,24 @@ fh_status t1_pipeline(fh_ctx* c, int B, const fh_quad* const* qs, const double* 
 
     auto run = [&]() -> fh_status {
         timing_mark(c, 0);
-        FH_TRY(run_spread<R>(c, inst[0], batched ? dinst : nullptr, B, Ntot, gg, sb, F, pl.k.beta, pl.k.poly));
-        FH_TRY(fft_exec(c, fa, F));
+        if (rebuild)
+            for (int b = 0; b < B; ++b) FH_TRY(qs[b]->rebuild());
+        if (fused) {
+            FH_TRY(spread_items<R>(c, inst[0], batched ? dinst : nullptr, B, Ntot, gg, sb, pl.k.beta, pl.k.poly));
+            FH_TRY(launch_t1_rows<R>(c, lr, reach, B, (gg.rows + lr.C - 1) / lr.C, gg, sb, n1, F));
+            c->tile_cnt_dirty = false;
+        } else {
+            FH_TRY(run_spread<R>(c, inst[0], batched ? dinst : nullptr, B, Ntot, gg, sb, F, pl.k.beta, pl.k.poly));
+            FH_TRY(fft_exec(c, fa, F));
+        }
         EpiParams ep{n1, n2, gg.nf1, gg.nf2, h1, h2, xc, yc, ip1, ip2};
         if (lc.C > 0) {
             hipLaunchKernelGGL(k_t1_rowfactors, dim3(nblocks(n2, 256), B), dim3(256), 0, c->stream, ep, epi[0],
                                batched ? (const EpiInst*)depi : nullptr, E2);
             timing_mark(c, 3);
             const int groups = (n1 + lc.C - 1) / lc.C;
-            FH_LDS_LAUNCH(k_t1_cols, R, lc, dim3(xcd_blocks(groups), B), c->stream, F, u, gg.rows, lc.C, groups,
+            FH_LDS_LAUNCH(k_t1_cols, R, lc, dim3(xcd_blocks(groups), B), c->stream, F, u, gg.rows,
+                          fused ? n1 : gg.nf1, fused ? 1 : 0, lc.C, groups,
                           lc.plan, ep, epi[0], batched ? (const EpiInst*)depi : nullptr, (const double2*)E2);
             FH_HIP(hipGetLastError());
             timing_mark(c, 4);
@@ -249,13 +327,15 @@ fh_status t1_pipeline(fh_ctx* c, int B, const fh_quad* const* qs, const double* 
     // A single instance passes its parameters to the kernels by value (no
     // device table), so a graph would bake in this call's quadrature and
     // wavelength: it runs eagerly, exactly as fh_field_grid does.
-    if (!capture || B == 1 || c->timing || std::getenv("FH_NO_GRAPH")) return run();
+    // The stable binning's radix sort is a library call that may record
+    // memory fills, which replay wrongly from a graph: it runs eagerly too.
+    if (!capture || B == 1 || c->timing || c->opt.deterministic || std::getenv("FH_NO_GRAPH")) return run();
 
     // graph key: every pointer and size baked into the launches
     char key[512];
-    snprintf(key, sizeof(key), "%p|%zu|%d|%lld|%d|%d|%d|%d|%d|%d|%a|%a|%a|%a|%d|%d|%d|%p|%p", (void*)c->arena.base,
-             c->arena.cap, B, (long long)Ntot, n1, n2, gg.nf1, gg.nf2, gg.W, gg.rows, h1, h2, xc, yc, gg.T, gg.P,
-             gg.method, (void*)u, (void*)c->tile_cnt);
+    snprintf(key, sizeof(key), "%p|%zu|%d|%lld|%d|%d|%d|%d|%d|%d|%a|%a|%a|%a|%d|%d|%d|%p|%p|%d",
+             (void*)c->arena.base, c->arena.cap, B, (long long)Ntot, n1, n2, gg.nf1, gg.nf2, gg.W, gg.rows, h1, h2,
+             xc, yc, gg.T, gg.P, gg.method, (void*)u, (void*)c->tile_cnt, rebuild ? 1 : 0);
     std::string k2(key);
     for (int b = 0; b < B; ++b) k2 += "|" + std::to_string(qs[b]->N);
     // Graphs are captured and replayed on a private stream (the caller's may
@@ -441,7 +521,7 @@ fh_status t3_core(fh_ctx* c, const fh_quad* q, double lambda, double z, int64_t 
     const size_t fine_count = 2 * (size_t)d1.nf * d2.nf;
     const size_t up_count = 2 * (size_t)d1.m * d2.m;
     const size_t need = aligned_bytes(rs * fine_count) + aligned_bytes(rs * up_count) +
-                        spread_bytes(N, gg, ntiles, rs) + (host ? 2 * cbytes : 0) +
+                        spread_bytes(c, N, gg, ntiles, rs) + (host ? 2 * cbytes : 0) +
                         (stage_out ? obytes : 0);
     FH_TRY(arena_reserve(c, need));
     R* fine = c->arena.take<R>(fine_count);
@@ -931,6 +1011,36 @@ fh_status fh_field_grid_batch(fh_ctx* c, int32_t B, const fh_quad* const* q, con
                                        true, 0, nullptr);
         return t1_pipeline<float>(c, B, q, lambda, z, n1, n2, h1, h2, xc, yc, occulter, static_cast<float*>(u), true,
                                   0, nullptr);
+    } catch (...) {
+        set_error("host allocation failed");
+        return FH_ERR_ALLOC;
+    }
+}
+
+fh_status fh_field_grid_batch_rebuild(fh_ctx* c, int32_t B, fh_quad* const* q, const double* lambda,
+                                      const double* z, int32_t n1, int32_t n2, double h1, double h2, double xc,
+                                      double yc, const int32_t* occulter, void* u)
+{
+    try {
+        FH_ARG(c && q && lambda && z && occulter && u, FH_ERR_INVALID_ARG, "NULL argument");
+        FH_ARG(B >= 1, FH_ERR_INVALID_ARG, "B must be >= 1");
+        FH_TRY(check_grid(n1, n2, h1, h2, xc, yc));
+        for (int b = 0; b < B; ++b) {
+            FH_ARG(q[b] && q[b]->ctx->device == c->device, FH_ERR_INVALID_ARG, "quadrature %d NULL or on another device", b);
+            FH_ARG(static_cast<bool>(q[b]->rebuild), FH_ERR_UNSUPPORTED,
+                   "quadrature %d cannot be rebuilt on the device (radial curves and polygons of up to %d vertices "
+                   "can)",
+                   b, kPolyByValue);
+            FH_TRY(check_lz(lambda[b], z[b]));
+        }
+        FH_HIP(hipSetDevice(c->device));
+        c->timing_kind = 3;
+        const fh_quad* const* cq = q;
+        if (c->prec == FH_FP64)
+            return t1_pipeline<double>(c, B, cq, lambda, z, n1, n2, h1, h2, xc, yc, occulter,
+                                       static_cast<double*>(u), true, 0, nullptr, true);
+        return t1_pipeline<float>(c, B, cq, lambda, z, n1, n2, h1, h2, xc, yc, occulter, static_cast<float*>(u),
+                                  true, 0, nullptr, true);
     } catch (...) {
         set_error("host allocation failed");
         return FH_ERR_ALLOC;

@@ -197,9 +197,12 @@ __global__ void k_fill_field(R* __restrict__ u, int64_t M, R re)
 constexpr int kBinBlock = 1024;
 constexpr int kBinKeys = 128;
 
+// With `key` (the stable binning), each node also writes its tile and its
+// index, the keys and values of the sort that then fixes the ranks.
 __global__ void __launch_bounds__(kBinBlock) k_bin_count(InstParams p0, const InstParams* __restrict__ table,
                                                          int ninst, int64_t Ntot, GridGeom gg,
-                                                         int* __restrict__ cnt, int* __restrict__ rank)
+                                                         int* __restrict__ cnt, int* __restrict__ rank,
+                                                         uint32_t* __restrict__ key, int* __restrict__ vals)
 {
     __shared__ int s_key[kBinKeys];
     __shared__ int s_cnt[kBinKeys];
@@ -221,6 +224,10 @@ __global__ void __launch_bounds__(kBinBlock) k_bin_count(InstParams p0, const In
         double d1, d2;
         node_cell(ip, gg, ip.x[jj], ip.y[jj], l1, l2, d1, d2);
         tile = ip.tile_off + (l2 / gg.T) * gg.ntx + (l1 / gg.T);
+        if (key) {
+            key[j] = (uint32_t)tile;
+            vals[j] = (int)j;
+        }
     }
     // groups of lanes with one tile; the lowest lane leads each group
     const int lane = (int)__lane_id();
@@ -390,6 +397,16 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_tiles(const int* __restri
         eb += ns;
     }
     if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) *nsub_out = base_b + tb;
+}
+
+// Stable binning: after the sort by tile (ties in node order), the node at
+// sorted position pos ranks pos - off[tile] within its tile.
+__global__ void k_rank_sorted(const uint32_t* __restrict__ key_sorted, const int* __restrict__ vals_sorted,
+                              int64_t Ntot, const int* __restrict__ off, int* __restrict__ rank)
+{
+    const int64_t pos = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (pos >= Ntot) return;
+    rank[vals_sorted[pos]] = (int)(pos - off[key_sorted[pos]]);
 }
 
 // Strength (FP64 phase in turns, reduced, times the node's source term when
@@ -1324,12 +1341,88 @@ __global__ void __launch_bounds__(256) k_tile_active(const int* __restrict__ tsu
     if (any) list[base + __popcll(m & ((1ull << lane) - 1ull))] = tile;
 }
 
+// Merged slots of a tile with n work items: (first item, number of merged
+// slots, item stride between them).
+__device__ __forceinline__ int4 tile_heads(int first, int n)
+{
+    int st = 1;
+    for (int l = merge_levels(n); l > 0; --l) st *= kMergeG;
+    return make_int4(first, (n + st - 1) / st, st, 0);
+}
+
+// Sum at cell (ci, cj) of tile (tx, ty) of one instance: the merged slots of
+// the tiles whose padded tiles cover it, covering tiles in (dy, dx) order,
+// slots in item order (the order of k_reduce_tiles).  head(ty', tx') gives
+// tile_heads of tile (tx', ty'), where tx' is already wrapped into [0, ntx)
+// and ty' may be negative (wrapped by head, when the grid wraps in y).
+template <class R, int REACH, int U = kRedU, class Head>
+__device__ __forceinline__ typename V2<R>::T reduce_cell(const typename V2<R>::T* __restrict__ slots,
+                                                         const GridGeom& gg, int tx, int ty, int ci, int cj,
+                                                         const Head& head)
+{
+    using C = typename V2<R>::T;
+    constexpr int NC = (REACH + 1) * (REACH + 1);
+    const int T = gg.T, L = gg.L, LL = L * L;
+    int first[NC], stride[NC], heads[NC], off[NC];
+#pragma unroll
+    for (int i = 0; i < NC; ++i) {
+        const int dy = i / (REACH + 1), dx = i % (REACH + 1);
+        const int sty = ty - dy;
+        const int sy = sty < 0 ? gg.pady : 0;
+        const bool okr = sty >= 0 || gg.wrap_y;
+        int stx = tx - dx, sx = 0;
+        if (stx < 0) {
+            stx += gg.ntx;
+            sx = gg.padx;
+            if (stx < 0) stx = ((stx % gg.ntx) + gg.ntx) % gg.ntx;
+        }
+        const int lx = ci + dx * T - sx, ly = cj + dy * T - sy;
+        const bool in = okr && lx < L && ly < L;
+        const int4 h = in ? head(sty, stx) : make_int4(0, 0, 1, 0);
+        first[i] = h.x;
+        heads[i] = h.y;
+        stride[i] = h.z;
+        off[i] = in ? ly * L + lx : 0;
+    }
+    C r[NC][U];
+#pragma unroll
+    for (int i = 0; i < NC; ++i)
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            r[i][u] = u < heads[i] ? slots[((size_t)first[i] + (size_t)u * stride[i]) * LL + off[i]] : C{R(0), R(0)};
+    R ar = R(0), ai = R(0);
+#pragma unroll
+    for (int i = 0; i < NC; ++i) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            ar += r[i][u].x;
+            ai += r[i][u].y;
+        }
+        for (int q = U; q < heads[i]; ++q) {
+            const C v = slots[((size_t)first[i] + (size_t)q * stride[i]) * LL + off[i]];
+            ar += v.x;
+            ai += v.y;
+        }
+    }
+    return C{ar, ai};
+}
+
+// Tile heads straight from the scan's table (tiles of instance b).
+struct TsubHead {
+    const int* tsub;
+    int base, ntx, nty;
+    __device__ int4 operator()(int sty, int stx) const
+    {
+        if (sty < 0) sty = ((sty % nty) + nty) % nty;
+        const int t = base + sty * ntx + stx;
+        return tile_heads(tsub[2 * t], tsub[2 * t + 1]);
+    }
+};
+
 // Tile reduce over the listed tiles (the rest of the fine grid was filled
 // with zeros): persistent blocks walk the cells of the listed tiles, 256 at
-// a time, a thread per cell.  Each thread finds the covering tiles and sums
-// their merged slots in the same order as k_reduce_tiles: covering tiles in
-// (dy, dx) order, slots in item order; cells of a partial last tile outside
-// the grid are skipped.
+// a time, a thread per cell (reduce_cell); cells of a partial last tile
+// outside the grid are skipped.
 template <class R, int REACH>
 __global__ void __launch_bounds__(256) k_reduce_list(const typename V2<R>::T* __restrict__ slots,
                                                      const int* __restrict__ tsub, const int* __restrict__ list,
@@ -1337,8 +1430,7 @@ __global__ void __launch_bounds__(256) k_reduce_list(const typename V2<R>::T* __
                                                      R* __restrict__ F)
 {
     using C = typename V2<R>::T;
-    constexpr int NC = (REACH + 1) * (REACH + 1);
-    const int T = gg.T, TT = T * T, L = gg.L, LL = L * L;
+    const int T = gg.T, TT = T * T;
     const int64_t ncell = (int64_t)(*nlist) * TT;
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < ncell;
          e += (int64_t)gridDim.x * blockDim.x) {
@@ -1348,56 +1440,93 @@ __global__ void __launch_bounds__(256) k_reduce_list(const typename V2<R>::T* __
         const int ty = tl / gg.ntx, tx = tl - ty * gg.ntx;
         const int cj = c / T, ci = c - cj * T;
         if (tx * T + ci >= gg.nf1 || ty * T + cj >= gg.rows) continue;
-        int first[NC], stride[NC], heads[NC], off[NC];
-#pragma unroll
-        for (int i = 0; i < NC; ++i) {
-            const int dy = i / (REACH + 1), dx = i % (REACH + 1);
-            int sty = ty - dy, sy = 0;
-            const bool okr = sty >= 0 || gg.wrap_y;
-            if (sty < 0) {
-                sty += gg.nty;
-                sy = gg.pady;
-                if (sty < 0) sty = ((sty % gg.nty) + gg.nty) % gg.nty;
-            }
-            int stx = tx - dx, sx = 0;
-            if (stx < 0) {
-                stx += gg.ntx;
-                sx = gg.padx;
-                if (stx < 0) stx = ((stx % gg.ntx) + gg.ntx) % gg.ntx;
-            }
-            const int lx = ci + dx * T - sx, ly = cj + dy * T - sy;
-            const bool in = okr && lx < L && ly < L;
-            const int t = b * tpi + sty * gg.ntx + stx;
-            const int n = in ? tsub[2 * t + 1] : 0;
-            first[i] = in ? tsub[2 * t] : 0;
-            int st = 1;
-            for (int l = merge_levels(n); l > 0; --l) st *= kMergeG;
-            stride[i] = st;
-            heads[i] = (n + st - 1) / st;
-            off[i] = in ? ly * L + lx : 0;
+        reinterpret_cast<C*>(F)[((size_t)b * gg.rows + ty * T + cj) * gg.nf1 + tx * T + ci] =
+            reduce_cell<R, REACH>(slots, gg, tx, ty, ci, cj, TsubHead{tsub, b * tpi, gg.ntx, gg.nty});
+    }
+}
+
+// Tile heads of the tile rows [ty_lo, ty_lo + nt) of one instance, copied
+// to LDS (rows before 0 wrap when the grid wraps in y, else are empty).
+struct LdsHead {
+    const int4* tab;
+    int ty_lo, ntx;
+    __device__ int4 operator()(int sty, int stx) const { return tab[(sty - ty_lo) * ntx + stx]; }
+};
+
+// Tile rows whose heads a group of C fine-grid rows starting at r0 needs,
+// and the table's byte offset in LDS (after the rows and the twiddles,
+// 16-byte aligned).
+__host__ __device__ inline int t1_rows_table_rows(int C, int T, int reach) { return (C - 1) / T + 2 + reach; }
+__host__ __device__ inline size_t t1_rows_table_offset(int C, int n, int ntw, size_t csize)
+{
+    return (csize * ((size_t)C * n + ntw) + 15) / 16 * 16;
+}
+
+// Tile reduce fused with the first FFT pass of type 1.  Workgroup (group g,
+// instance b) takes the C fine-grid rows [g C, g C + C) of the band: it
+// copies the heads of the tile rows covering them to LDS, each cell sums its
+// covering slots (reduce_cell) straight into LDS, the rows are transformed
+// there (length nf1), and only the n1 needed columns k1 mod nf1,
+// k1 in [-n1/2, n1/2), are written to G (B x rows x n1, row stride n1, in k1
+// order).  The fine grid itself is never stored.  The binning counters of
+// the tile rows that start in this group's rows are left at zero for the
+// next call.  Every cell looks up its covering tiles, so this pays where
+// the tiles are large (a padded tile reaching one tile on) or the grid is
+// densely covered; the list reduce into a stored grid visits only the
+// reached tiles.
+template <class R, int MAXE, int NT, bool R7, int REACH>
+__global__ void __launch_bounds__(NT) k_t1_rows(const typename V2<R>::T* __restrict__ slots,
+                                                const int* __restrict__ tsub, GridGeom gg, int tpi, int C,
+                                                int groups, LdsFftPlan plan, int n1, R* __restrict__ G,
+                                                int* __restrict__ cnt)
+{
+    using C2 = typename V2<R>::T;
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    C2* buf = reinterpret_cast<C2*>(lds_raw);
+    const int g = xcd_group(groups);
+    if (g >= groups) return;
+    const int b = blockIdx.y;
+    const int nf1 = plan.n, T = gg.T;
+    const int r0 = g * C;
+    const int nr = min(C, gg.rows - r0);
+    // heads of the covering tile rows, after the FFT's data and twiddles
+    const int ty_lo = r0 / T - REACH;
+    const int nt = t1_rows_table_rows(C, T, REACH);
+    int4* tab = reinterpret_cast<int4*>(lds_raw + t1_rows_table_offset(C, nf1, plan.ntw, sizeof(C2)));
+    for (int e = threadIdx.x; e < nt * gg.ntx; e += NT) {
+        const int k = e / gg.ntx, tx = e - k * gg.ntx;
+        int sty = ty_lo + k;
+        int4 h = make_int4(0, 0, 1, 0);
+        if (sty < gg.nty && (sty >= 0 || gg.wrap_y)) {
+            if (sty < 0) sty = ((sty % gg.nty) + gg.nty) % gg.nty;
+            const int t = b * tpi + sty * gg.ntx + tx;
+            h = tile_heads(tsub[2 * t], tsub[2 * t + 1]);
         }
-        C r[NC][kRedU];
-#pragma unroll
-        for (int i = 0; i < NC; ++i)
-#pragma unroll
-            for (int u = 0; u < kRedU; ++u)
-                r[i][u] =
-                    u < heads[i] ? slots[((size_t)first[i] + (size_t)u * stride[i]) * LL + off[i]] : C{R(0), R(0)};
-        R ar = R(0), ai = R(0);
-#pragma unroll
-        for (int i = 0; i < NC; ++i) {
-#pragma unroll
-            for (int u = 0; u < kRedU; ++u) {
-                ar += r[i][u].x;
-                ai += r[i][u].y;
-            }
-            for (int q = kRedU; q < heads[i]; ++q) {
-                const C v = slots[((size_t)first[i] + (size_t)q * stride[i]) * LL + off[i]];
-                ar += v.x;
-                ai += v.y;
-            }
+        tab[e] = h;
+    }
+    // tile rows ty with r0 <= ty T < r0 + nr
+    const int ty0 = (r0 + T - 1) / T, ty1 = (r0 + nr + T - 1) / T;
+    for (int e = threadIdx.x; e < (ty1 - ty0) * gg.ntx; e += NT) cnt[b * tpi + ty0 * gg.ntx + e] = 0;
+    __syncthreads();
+    const LdsHead head{tab, ty_lo, gg.ntx};
+    const FastDiv dT = fast_div((unsigned)T), dn = fast_div((unsigned)nf1);
+    for (int e = threadIdx.x; e < C * nf1; e += NT) {
+        const int rr = (int)fdiv((unsigned)e, dn), x = e - rr * nf1;
+        C2 v{R(0), R(0)};
+        if (rr < nr) {
+            const int y = r0 + rr;
+            const int tx = (int)fdiv((unsigned)x, dT), ty = (int)fdiv((unsigned)y, dT);
+            v = reduce_cell<R, REACH, 1>(slots, gg, tx, ty, x - tx * T, y - ty * T, head);
         }
-        reinterpret_cast<C*>(F)[((size_t)b * gg.rows + ty * T + cj) * gg.nf1 + tx * T + ci] = C{ar, ai};
+        buf[e] = v;
+    }
+    __syncthreads();
+    lds_fft<MAXE, NT, R7>(buf, plan, C, buf + (size_t)C * nf1);
+    C2* Gv = reinterpret_cast<C2*>(G) + ((size_t)b * gg.rows + r0) * n1;
+    for (int e = threadIdx.x; e < nr * n1; e += NT) {
+        const int rr = e / n1, k1i = e - rr * n1;
+        const int k1 = k1i - n1 / 2;
+        Gv[e] = buf[(size_t)rr * nf1 + (k1 < 0 ? k1 + nf1 : k1)];
     }
 }
 
@@ -1548,13 +1677,15 @@ __global__ void __launch_bounds__(256) k_t1_rowfactors(EpiParams ep, EpiInst e0,
 // Type-1 second pass and epilogue in one kernel.  Workgroup (group g,
 // instance b) takes the C output columns k1 + n1/2 in [g C, g C + C): it
 // loads their band of `rows` values from F (after the first pass over the
-// rows), zero-pads each to nf2 in LDS, transforms, and writes
+// rows; row stride ldf, and either the full nf1 columns, column k1 at
+// k1 mod nf1, or with `compact` only the n1 needed ones in k1 order),
+// zero-pads each to nf2 in LDS, transforms, and writes
 // u[b][k2][k1] = epilogue(column value at k2 mod nf2) for every k2, with the
 // factors of k_epilogue_t1: its column factors here, its row factors from
 // k_t1_rowfactors.
 template <class R, int MAXE, int NT, bool R7>
-__global__ void __launch_bounds__(NT) k_t1_cols(const R* __restrict__ F, R* __restrict__ u, int rows,
-                                                            int C, int groups, LdsFftPlan plan, EpiParams ep,
+__global__ void __launch_bounds__(NT) k_t1_cols(const R* __restrict__ F, R* __restrict__ u, int rows, int ldf,
+                                                            int compact, int C, int groups, LdsFftPlan plan, EpiParams ep,
                                                             EpiInst e0, const EpiInst* __restrict__ table,
                                                             const double2* __restrict__ E2all)
 {
@@ -1585,16 +1716,19 @@ __global__ void __launch_bounds__(NT) k_t1_cols(const R* __restrict__ F, R* __re
         E1[threadIdx.x] = f;
     }
     // band of the C columns (adjacent lanes read adjacent columns of a row)
-    const C2* Fv = reinterpret_cast<const C2*>(F) + (size_t)b * rows * ep.nf1;
+    const C2* Fv = reinterpret_cast<const C2*>(F) + (size_t)b * rows * ldf;
     for (int e = threadIdx.x; e < C * nf2; e += NT) {
         const int r = e / C, c = e - r * C;
         C2 v;
         v.x = R(0);
         v.y = R(0);
         if (r < rows && c < ncol) {
-            int col = col0 + c - ep.n1 / 2;
-            if (col < 0) col += ep.nf1;
-            v = Fv[(size_t)r * ep.nf1 + col];
+            int col = col0 + c;
+            if (!compact) {
+                col -= ep.n1 / 2;
+                if (col < 0) col += ep.nf1;
+            }
+            v = Fv[(size_t)r * ldf + col];
         }
         buf[c * nf2 + r] = v;
     }
@@ -2112,8 +2246,17 @@ struct SpreadBufs {
     void* slots;    // one padded L x L complex tile per work item
     int* list;      // tiles some padded tile reaches (list reduce), and their count
     int* nlist;
+    // stable binning only: tile keys and node indices, before and after the
+    // sort, and the sort's scratch
+    uint32_t* key;
+    uint32_t* key_sorted;
+    int* vals;
+    int* vals_sorted;
+    void* sort_tmp;
+    size_t sort_bytes;
     int64_t max_sub;
 };
+
 
 // Type-1 geometry: kernel, fine grid and tiling.
 struct T1Plan {
@@ -2121,10 +2264,13 @@ struct T1Plan {
     GridGeom gg;
 };
 
-size_t spread_bytes(int64_t Ntot, const GridGeom& gg, int ntiles_total, size_t rsize)
+size_t spread_bytes(const fh_ctx* c, int64_t Ntot, const GridGeom& gg, int ntiles_total, size_t rsize)
 {
     const int64_t max_sub = Ntot / gg.P + std::min<int64_t>(Ntot, ntiles_total) + 1;
-    return aligned_bytes(sizeof(int) * (size_t)ntiles_total) + aligned_bytes(2 * sizeof(int) * ntiles_total) +
+    const size_t sort = c->opt.deterministic
+                            ? 4 * aligned_bytes(sizeof(int) * (size_t)Ntot) + aligned_bytes(tile_sort_bytes(Ntot))
+                            : 0;
+    return sort + aligned_bytes(sizeof(int) * (size_t)ntiles_total) + aligned_bytes(2 * sizeof(int) * ntiles_total) +
            aligned_bytes(2 * sizeof(int) * (size_t)(ntiles_total / kScanChunk + 1)) +
            aligned_bytes(sizeof(int) * Ntot) + aligned_bytes(sizeof(uint32_t) * Ntot) +
            2 * aligned_bytes(2 * rsize * Ntot) + aligned_bytes(sizeof(Sub) * max_sub) + aligned_bytes(sizeof(int)) +
@@ -2149,13 +2295,33 @@ SpreadBufs spread_carve(fh_ctx* c, int64_t Ntot, const GridGeom& gg, int ntiles_
     b.slots = c->arena.take<char>(2 * rsize * (size_t)gg.L * gg.L * b.max_sub);
     b.list = c->arena.take<int>((size_t)ntiles_total);
     b.nlist = c->arena.take<int>(1);
+    b.key = b.key_sorted = nullptr;
+    b.vals = b.vals_sorted = nullptr;
+    b.sort_tmp = nullptr;
+    b.sort_bytes = 0;
+    if (c->opt.deterministic) {
+        b.key = c->arena.take<uint32_t>(Ntot);
+        b.key_sorted = c->arena.take<uint32_t>(Ntot);
+        b.vals = c->arena.take<int>(Ntot);
+        b.vals_sorted = c->arena.take<int>(Ntot);
+        b.sort_bytes = tile_sort_bytes(Ntot);
+        b.sort_tmp = c->arena.take<char>(b.sort_bytes);
+    }
     return b;
 }
 
-// Bin, spread into slots, and reduce into F (B instances x rows x nf1).
+// How many tiles on a padded tile reaches, also through the wrap of the
+// period, where a partial last tile brings the next tiles closer.
+inline int tile_reach(const GridGeom& gg)
+{
+    return (gg.L - 1 + std::max(gg.padx, gg.wrap_y ? gg.pady : 0)) / gg.T;
+}
+
+// Bin and spread into slots, then merge the slots of each tile's work items
+// (the reduce follows: reduce_grid, or the type-1 row pass that fuses it).
 template <class R>
-fh_status run_spread(fh_ctx* c, const InstParams& p0, const InstParams* table, int ninst, int64_t Ntot,
-                     const GridGeom& gg, const SpreadBufs& b, R* F, double beta, const void* poly)
+fh_status spread_items(fh_ctx* c, const InstParams& p0, const InstParams* table, int ninst, int64_t Ntot,
+                       const GridGeom& gg, const SpreadBufs& b, double beta, const void* poly)
 {
     const int tpi = gg.ntx * gg.nty;
     const int ntiles_total = tpi * ninst;
@@ -2164,8 +2330,12 @@ fh_status run_spread(fh_ctx* c, const InstParams& p0, const InstParams* table, i
     c->tile_cnt_dirty = true;
     if (Ntot > 0) {
         hipLaunchKernelGGL(k_bin_count, dim3(nblocks(Ntot, kBinBlock)), dim3(kBinBlock), 0, c->stream, p0, table,
-                           ninst, Ntot,
-                           gg, b.cnt, b.rank);
+                           ninst, Ntot, gg, b.cnt, b.rank, b.key, b.vals);
+        if (b.key) {
+            int bits = 1;
+            while (bits < 32 && ((int64_t)1 << bits) < ntiles_total) ++bits;
+            FH_TRY(tile_sort(c, b.key, b.key_sorted, b.vals, b.vals_sorted, Ntot, bits, b.sort_tmp, b.sort_bytes));
+        }
     }
     const int nscan = std::max(1, (ntiles_total + kScanChunk - 1) / kScanChunk);
     if (nscan > 1)
@@ -2173,6 +2343,9 @@ fh_status run_spread(fh_ctx* c, const InstParams& p0, const InstParams* table, i
                            b.bsum);
     hipLaunchKernelGGL(k_scan_tiles, dim3(nscan), dim3(kScanThreads), 0, c->stream, b.cnt, ntiles_total, gg.P,
                        b.bsum, b.off, b.tsub, b.nsub, b.nlist);
+    if (Ntot > 0 && b.key)
+        hipLaunchKernelGGL(k_rank_sorted, dim3(nblocks(Ntot, 256)), dim3(256), 0, c->stream, b.key_sorted,
+                           b.vals_sorted, Ntot, b.off, b.rank);
     if (Ntot > 0) {
         hipLaunchKernelGGL((k_bin_place<R>), dim3(nblocks(Ntot, 256)), dim3(256), 0, c->stream, p0, table, ninst,
                            Ntot, gg, b.cnt, b.off, b.tsub, b.rank, b.cell, (typename V2<R>::T*)b.dd,
@@ -2202,11 +2375,18 @@ fh_status run_spread(fh_ctx* c, const InstParams& p0, const InstParams* table, i
                                (typename V2<R>::T*)b.slots, b.subs, b.nsub, b.tsub, (int)LL, level);
         FH_HIP(hipGetLastError());
     }
+    return FH_OK;
+}
+
+// Reduce the merged slots into F (B instances x rows x nf1).
+template <class R>
+fh_status reduce_grid(fh_ctx* c, int ninst, const GridGeom& gg, const SpreadBufs& b, R* F)
+{
+    const int tpi = gg.ntx * gg.nty;
+    const int ntiles_total = tpi * ninst;
     const unsigned rgrid = (unsigned)std::max<int64_t>(
         1, std::min<int64_t>(ntiles_total, (int64_t)c->cu_count * 16));
-    // how many tiles on a padded tile reaches, also through the wrap of the
-    // period, where a partial last tile brings the next tiles closer
-    const int reach = (gg.L - 1 + std::max(gg.padx, gg.wrap_y ? gg.pady : 0)) / gg.T;
+    const int reach = tile_reach(gg);
     const int TT = gg.T * gg.T;
     const unsigned rthreads = (unsigned)std::min(256, TT);
     FH_ARG(reach >= 1 && reach <= (TT > 256 ? 1 : 2) && TT <= 1024, FH_ERR_UNSUPPORTED,
@@ -2248,6 +2428,15 @@ fh_status run_spread(fh_ctx* c, const InstParams& p0, const InstParams* table, i
     return FH_OK;
 }
 
+// Bin, spread into slots, and reduce into F (B instances x rows x nf1).
+template <class R>
+fh_status run_spread(fh_ctx* c, const InstParams& p0, const InstParams* table, int ninst, int64_t Ntot,
+                     const GridGeom& gg, const SpreadBufs& b, R* F, double beta, const void* poly)
+{
+    FH_TRY(spread_items<R>(c, p0, table, ninst, Ntot, gg, b, beta, poly));
+    return reduce_grid<R>(c, ninst, gg, b, F);
+}
+
 fh_status check_lz(double lambda, double z)
 {
     FH_ARG(std::isfinite(lambda) && std::isfinite(z), FH_ERR_NONFINITE, "lambda or z not finite");
@@ -2272,6 +2461,9 @@ fh_status check_grid(int n1, int n2, double h1, double h2, double xc, double yc)
 void spread_defaults(const fh_ctx* c, GridGeom& g, int auto_method = 2)
 {
     g.method = c->opt.spread_method > 0 ? c->opt.spread_method : auto_method;
+    // the thread-per-point spread adds to a shared tile with atomics in no
+    // fixed order
+    if (g.method == 1 && c->opt.deterministic) g.method = 2;
     // the register tile needs T = 8 or 16, a padded tile row within one
     // wavefront and its four tiles within the LDS budget
     if (g.method == 4 && !((g.T == 8 || g.T == 16) && g.L <= 64 &&

@@ -261,7 +261,6 @@ __global__ void k_bdry_polygon(const double* __restrict__ vx, const double* __re
 }
 
 // Polygons of up to this many vertices travel in the kernel arguments.
-constexpr int kPolyByValue = 128;
 struct PolyParams {
     int nv, q;
     double vx[kPolyByValue];
@@ -880,6 +879,7 @@ fh_status fh_quad_radial(fh_ctx* c, double r0, const double* a, const double* b,
             fh_quad_destroy(qd);
             return s;
         }
+        qd->rebuild = [c, rp, n, m, qd]() { return radial_into(c, rp, n, m, qd->x, qd->y, qd->w); };
         double box[4];
         radial_box(rp, n, box);
         set_bbox(qd, box[0], box[1], box[2], box[3]);
@@ -928,6 +928,12 @@ fh_status fh_quad_polygon(fh_ctx* c, const double* vx, const double* vy, int32_t
             hipLaunchKernelGGL(k_polygon_rule, dim3(nblocks(n * m, 256)), dim3(256), 0, c->stream, pp, glq, m, glm,
                                qd->x, qd->y, qd->w);
             FH_HIP(hipGetLastError());
+            qd->rebuild = [c, pp, glq, m, glm, n, qd]() -> fh_status {
+                hipLaunchKernelGGL(k_polygon_rule, dim3(nblocks(n * m, 256)), dim3(256), 0, c->stream, pp, glq, m,
+                                   glm, qd->x, qd->y, qd->w);
+                FH_HIP(hipGetLastError());
+                return FH_OK;
+            };
             set_bbox(qd, bb[0], bb[1], bb[2], bb[3]);
             *out = qd;
             return FH_OK;

@@ -1,5 +1,6 @@
 """Batched grid fields (one persistent spread over every instance's work
-items, one batched FFT, hipGraph capture and replay) and the autotuner."""
+items, one batched FFT, hipGraph capture and replay), the rule rebuild inside
+the graph, and the autotuner (single rule and batch)."""
 import os
 
 import numpy as np
@@ -115,7 +116,7 @@ def test_autotune_keeps_accuracy_and_caches(ctx, tmp_path):
     best = ctx.autotune_grid(q, wl.lam, wl.z, n, n, h, h, cache_path=path)
     print(f"  tuned {ctx.precision}: sigma {best.sigma} tile {best.tile} P {best.max_subproblem} "
           f"method {best.spread_method}", flush=True)
-    assert best.spread_method in (1, 2, 3, 4) and best.sigma in (1.25, 2.0)
+    assert best.spread_method in (1, 2, 3, 4, 5) and best.sigma in (1.25, 2.0)
     assert os.path.exists(path)
     again = ctx.autotune_grid(q, wl.lam, wl.z, n, n, h, h, cache_path=path)
     assert (again.sigma, again.tile, again.max_subproblem, again.spread_method) == \
@@ -152,3 +153,77 @@ def test_single_instance_batches_use_each_calls_parameters(fh, prec):
     qa.close()
     qb.close()
     ctx.close()
+
+
+class _DeviceArray:
+    """A raw device pointer seen by torch (no copy)."""
+
+    def __init__(self, ptr, n):
+        self.__cuda_array_interface__ = {"shape": (n,), "typestr": "<f8", "data": (ptr, False), "version": 3}
+
+
+def _wipe_weights(fh, q):
+    _, _, wp = fh._binding.fh_quad_device_ptrs(q.handle)
+    torch.as_tensor(_DeviceArray(wp, q.N), device="cuda").zero_()
+
+
+def test_rebuild_batch_recomputes_rules_in_the_graph(ctx, fh):
+    shapes, lams, zs, occ, g = _batch_inputs()
+    quads = [ctx.quad_for(s) for s in shapes]
+    ref = cpu(ctx.field_grid_batch(quads, lams, zs, g.n1, g.n2, g.h1, g.h2, occulter=occ))
+    out = torch.empty((len(quads), g.n2, g.n1), dtype=ctx.cdtype, device="cuda")
+    for rep in range(3):  # capture, then replays
+        # zero every rule's weights: only the rebuild inside the call brings
+        # them back
+        ctx.synchronize()
+        for q in quads:
+            _wipe_weights(fh, q)
+        torch.cuda.synchronize()
+        got = cpu(ctx.field_grid_batch_rebuild(quads, lams, zs, g.n1, g.n2, g.h1, g.h2, occulter=occ, out=out))
+        for b in range(len(quads)):
+            e = relL2(got[b] - occ[b], ref[b] - occ[b])
+            assert e <= TOL[ctx.precision], (rep, b, e)
+    print(f"  rebuild {ctx.precision}: three calls match the plain batch", flush=True)
+    # the rules hold their constructors' nodes and weights again
+    for q, s in zip(quads[:2], shapes[:2]):
+        x, y, w = (cpu(t) for t in q.export())
+        xo, yo, wo = oracle_quad(s)
+        assert np.abs(x - xo).max() <= 1e-14 and np.abs(w - wo).max() <= 1e-14 * np.abs(wo).max()
+    # a starshade rule cannot be rebuilt: refused before anything runs
+    st = ctx.quad_for(workloads.workload(5, reduced=True).shape)
+    with pytest.raises(fh.FresnelError, match="FH_ERR_UNSUPPORTED"):
+        ctx.field_grid_batch_rebuild(quads[:2] + [st], lams[:3], zs[:3], g.n1, g.n2, g.h1, g.h2)
+    st.close()
+    for q in quads:
+        q.close()
+
+
+def test_autotune_batch_keeps_accuracy_flags_and_caches(ctx, fh, tmp_path):
+    shapes, lams, zs, occ, g = _batch_inputs()
+    quads = [ctx.quad_for(s) for s in shapes]
+    path = str(tmp_path / "tune_batch.jsonl")
+    ctx.set_options(fh.fh_options(deterministic=1))
+    best = ctx.autotune_batch(quads, lams, zs, g.n1, g.n2, g.h1, g.h2, cache_path=path)
+    print(f"  batch tuned {ctx.precision}: sigma {best.sigma} tile {best.tile} P {best.max_subproblem} "
+          f"method {best.spread_method} deterministic {best.deterministic}", flush=True)
+    assert best.spread_method in (2, 4, 5) and best.sigma in (1.25, 2.0)
+    assert best.deterministic == 1
+    with open(path) as f:
+        assert '"key": "batch|' in f.read()
+    ctx.set_options(None)
+    again = ctx.autotune_batch(quads, lams, zs, g.n1, g.n2, g.h1, g.h2, cache_path=path)
+    assert (again.sigma, again.tile, again.max_subproblem, again.spread_method) == \
+        (best.sigma, best.tile, best.max_subproblem, best.spread_method)
+    assert again.deterministic == 0
+    u = cpu(ctx.field_grid_batch(quads, lams, zs, g.n1, g.n2, g.h1, g.h2, occulter=occ))
+    xi, eta = oracle.grid_targets(g.n1, g.n2, g.h1, g.h2)
+    for b, s in enumerate(shapes):
+        x, y, w = oracle_quad(s)
+        idx = np.random.Generator(np.random.PCG64(40 + b)).choice(g.M, 200, replace=False)
+        ref = oracle.fresnel_direct(x, y, w, lams[b], zs[b], xi[idx], eta[idx])
+        got = u[b].ravel()[idx]
+        got = 1 - got if occ[b] else got
+        assert relL2(got, ref) <= TOL[ctx.precision], b
+    ctx.set_options(None)
+    for q in quads:
+        q.close()

@@ -3,7 +3,8 @@
 Every work item's points are summed in a fixed order and the slots reduced in
 a fixed order, but the binning ranks the points of a tile with atomic
 counters, so their order within a tile -- and the last bits of the sums --
-can change between calls.  The starfish field of the benchmark step (40,000
+can change between calls.  The deterministic option replaces the atomic
+ranks by a stable sort, and then repeated calls must agree bit for bit.  The starfish field of the benchmark step (40,000
 nodes whose spokes crowd the tiles near the origin, so runs of points share a
 first cell) computed twice, with each spread method, must then agree to
 rounding: relative L2 difference below 1e-13 in FP64 and 2e-6 in mixed
@@ -52,4 +53,80 @@ def test_spread_repeatable_to_rounding(fh, prec):
         assert d < BOUND[prec], m
     ctx.set_options(None)
     q.close()
+    ctx.close()
+
+
+def det_options(fh, method=0, tile=0):
+    return fh.fh_options(sigma=0, kernel_width=0, beta=0.0, tile=tile, max_subproblem=0, spread_method=method,
+                         deterministic=1)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_deterministic_mode_is_bitwise_repeatable(fh, prec):
+    # the stable binning orders each tile's nodes by node index, so two calls
+    # (and two contexts) give the same bits, for every spread method
+    import numpy as np
+    import oracle
+    wl = workloads.workload(2)
+    g = wl.grid
+    ctxs = [fh.Context(prec), fh.Context(prec)]
+    quads = [c.quad_for(wl.shape) for c in ctxs]
+    ref = None
+    for method, tile in ((0, 0), (1, 16), (2, 16), (3, 16), (4, 16), (5, 0)):
+        outs = []
+        for c, q in zip(ctxs, quads):
+            c.set_options(det_options(fh, method, tile))
+            outs.append(c.field_grid(q, wl.lam, wl.z, g.n1, g.n2, g.h1, g.h2).clone())
+            outs.append(c.field_grid(q, wl.lam, wl.z, g.n1, g.n2, g.h1, g.h2).clone())
+        same = all(torch.equal(outs[0], o) for o in outs[1:])
+        print(f"{prec} method {method} tile {tile}: four calls on two contexts bitwise equal: {same}", flush=True)
+        assert same, (method, tile)
+        if method == 0:
+            ref = outs[0]
+            # and still the field: against the oracle's direct sum
+            s = wl.shape
+            x, y, w = oracle.quad_radial(s.r0, s.a, s.b, s.panels, s.q, s.m)
+            xi, eta = oracle.grid_targets(g.n1, g.n2, g.h1, g.h2)
+            idx = np.random.Generator(np.random.PCG64(11)).choice(g.M, 400, replace=False)
+            u = ref.cpu().numpy().ravel()[idx]
+            d = oracle.fresnel_direct(x, y, w, wl.lam, wl.z, xi[idx], eta[idx])
+            err = float(np.linalg.norm(u - d) / np.linalg.norm(d))
+            print(f"  vs oracle: rel L2 {err:.2e}", flush=True)
+            assert err <= ctxs[0].tol
+        else:
+            assert rel(outs[0], ref) < BOUND[prec], method
+    # type 3 at scattered points
+    rng = np.random.Generator(np.random.PCG64(12))
+    xs = torch.tensor(rng.uniform(-1.4, 1.4, 20000), device="cuda")
+    ys = torch.tensor(rng.uniform(-1.4, 1.4, 20000), device="cuda")
+    pts = []
+    for c, q in zip(ctxs, quads):
+        c.set_options(det_options(fh))
+        pts.append(c.field_points(q, wl.lam, wl.z, xs, ys).clone())
+        pts.append(c.field_points(q, wl.lam, wl.z, xs, ys).clone())
+    assert all(torch.equal(pts[0], p) for p in pts[1:])
+    for c, q in zip(ctxs, quads):
+        q.close()
+        c.close()
+
+
+def test_deterministic_batches_are_bitwise_repeatable(fh):
+    import numpy as np
+    shapes = workloads.batch_shapes(count=6, nmin=5000, nmax=40000)
+    lams = workloads.batch_lambdas(64)[:6] * 1.0
+    zs = np.full(6, workloads.BATCH_Z)
+    n = 128
+    h = 3.0 / n
+    ctx = fh.Context("mixed")
+    quads = [ctx.quad_for(s) for s in shapes]
+    ctx.set_options(det_options(fh))
+    a = ctx.field_grid_batch(quads, lams, zs, n, n, h, h).clone()
+    b = ctx.field_grid_batch(quads, lams, zs, n, n, h, h).clone()
+    print(f"batch of 6: bitwise equal {torch.equal(a, b)}", flush=True)
+    assert torch.equal(a, b)
+    ctx.set_options(None)
+    c = ctx.field_grid_batch(quads, lams, zs, n, n, h, h)
+    assert rel(c, a) < BOUND["mixed"]
+    for q in quads:
+        q.close()
     ctx.close()

@@ -55,17 +55,21 @@ def test_allocation_cap(fh, monkeypatch):
 
 
 def test_refused_fft_plan(fh, monkeypatch):
+    # a 2048^2 grid in FP64 needs rocFFT (a 4096-point row of complex doubles
+    # does not fit in LDS); smaller grids run both passes in LDS
     monkeypatch.setenv("FH_INJECT_FAULT", "fft_plan")
     ctx = fh.Context("fp64")
     monkeypatch.delenv("FH_INJECT_FAULT")
     wl, ref = disk()
     q = ctx.quad_for(wl.shape)
     g = wl.grid
+    n, h = 2048, 3.0 / 2048
     with pytest.raises(fh.FresnelError) as e:
-        ctx.field_grid(q, wl.lam, wl.z, g.n1, g.n2, g.h1, g.h2)
+        ctx.field_grid(q, wl.lam, wl.z, n, n, h, h)
     assert e.value.status == fh.FH_ERR_FFT
-    # type 3 on small grids runs its transforms in LDS (no rocFFT plan): the
-    # context still serves it
+    # the context still serves what needs no rocFFT plan: the small grid and
+    # type 3 on small grids
+    assert relL2(cpu(ctx.field_grid(q, wl.lam, wl.z, g.n1, g.n2, g.h1, g.h2)), ref) <= 1e-9
     rng = np.random.Generator(np.random.PCG64(5))
     xi, eta = rng.uniform(-1.2, 1.2, 500), rng.uniform(-1.2, 1.2, 500)
     v = cpu(ctx.field_points(q, wl.lam, wl.z, torch.tensor(xi, device="cuda"), torch.tensor(eta, device="cuda")))
@@ -76,7 +80,10 @@ def test_refused_fft_plan(fh, monkeypatch):
     # a context made without the fault plans normally
     ok = fh.Context("fp64")
     q = ok.quad_for(wl.shape)
-    assert relL2(cpu(ok.field_grid(q, wl.lam, wl.z, g.n1, g.n2, g.h1, g.h2)), ref) <= 1e-9
+    u = cpu(ok.field_grid(q, wl.lam, wl.z, n, n, h, h)).ravel()
+    gx, gy = oracle.grid_targets(n, n, h, h)
+    idx = np.random.Generator(np.random.PCG64(6)).choice(n * n, 300, replace=False)
+    assert relL2(u[idx], oracle.fresnel_direct(x, y, w, wl.lam, wl.z, gx[idx], gy[idx])) <= 1e-9
     q.close()
     ok.close()
 
