@@ -219,7 +219,7 @@ fh_status grid_vjp_impl(fh_ctx* c, const fh_quad* q, double lambda, double z, in
     const int64_t N = q->N;
     c->timing_kind = 2;
     if (N == 0) return FH_OK;
-    T1Plan pl = plan_t1(c, n1, n2);
+    T1Plan pl = plan_t1(c, n1, n2, N);
     FH_ARG(!pl.k.clamped, FH_ERR_UNSUPPORTED, "tolerance %g needs a kernel wider than %d at sigma %g", c->tol,
            kMaxWidth, pl.k.sigma);
     GridGeom gg = pl.gg;

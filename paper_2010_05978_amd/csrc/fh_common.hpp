@@ -249,6 +249,10 @@ struct fh_quad {
     // parameters by value: radial curves and small polygons); empty for the
     // others.
     std::function<fh_status()> rebuild;
+    // Computes the bounding box on the host when a call first needs it
+    // (generated rules whose box comes from their boundary parameters);
+    // empty: a device reduction over the nodes.
+    std::function<void(double*)> host_box;
 };
 
 // A scattered-target set: the device coordinates (the caller's arrays, or a
@@ -273,8 +277,9 @@ fh_status gl_table(fh_ctx* c, int q, const double** dev);  // x[q] then w[q]
 void gl_host(int q, std::vector<double>& x, std::vector<double>& w);
 EsKernel choose_kernel(const fh_ctx* c, int n_hint);
 void es_poly_attach(fh_ctx* c, EsKernel& k);
-int pick_tile(const fh_ctx* c, int nf, int w);
-int t1_method(const fh_ctx* c, int w);
+constexpr int64_t kMfmaMinNodes = (int64_t)1 << 18;  // nodes per call before the matrix-core spread pays
+int pick_tile(const fh_ctx* c, int nf, int w, int64_t N);
+int t1_method(const fh_ctx* c, int w, int64_t N);
 int next_fft_size(int n, int multiple);
 double phi_hat(const EsKernel& k, double theta);
 fh_status iphi_table(fh_ctx* c, const EsKernel& k, int n, int nf, const double** dev);

@@ -88,7 +88,7 @@ fh_status arena_reserve(fh_ctx* c, size_t bytes)
 // q-node rule on [-1,1], ascending: Newton's method on P_q, with P_q and
 // P_q' from the Bonnet recurrence, started from the asymptotic root
 // estimate cos(pi (k - 1/4)/(q + 1/2)).
-void gl_host(int q, std::vector<double>& x, std::vector<double>& w)
+static void gl_newton(int q, std::vector<double>& x, std::vector<double>& w)
 {
     x.assign(q, 0.0);
     w.assign(q, 0.0);
@@ -127,6 +127,21 @@ void gl_host(int q, std::vector<double>& x, std::vector<double>& w)
         w[k - 1] = wt;
     }
     if (q % 2 == 1) x[q / 2] = 0.0;
+}
+
+// The rules are kept per thread once computed: host code asks for the same
+// few orders on every rule it builds.
+void gl_host(int q, std::vector<double>& x, std::vector<double>& w)
+{
+    thread_local std::map<int, std::pair<std::vector<double>, std::vector<double>>> memo;
+    auto it = memo.find(q);
+    if (it == memo.end()) {
+        std::vector<double> nx, nw;
+        gl_newton(q, nx, nw);
+        it = memo.emplace(q, std::make_pair(std::move(nx), std::move(nw))).first;
+    }
+    x = it->second.first;
+    w = it->second.second;
 }
 
 fh_status gl_table(fh_ctx* c, int q, const double** dev)
@@ -278,21 +293,24 @@ int next_fft_size(int n, int multiple)
 // padded tile in LDS, so small tiles leave room for more wavefronts per CU,
 // and the halo the reduce reads stays modest at the kernel widths of 1e-5 and
 // 1e-9).  Halved while the fine grid is under four tiles across.
-int pick_tile(const fh_ctx* c, int nf, int w)
+int pick_tile(const fh_ctx* c, int nf, int w, int64_t N)
 {
     int T = c->opt.tile > 0 ? c->opt.tile : 16;
-    if (c->opt.tile <= 0 && t1_method(c, w) == 5 && w <= 11) T = 17 - w;
+    if (c->opt.tile <= 0 && t1_method(c, w, N) == 5 && w <= 11) T = 17 - w;
     while (T > 8 && nf < 4 * T) T /= 2;
     return T;
 }
 
-// Spread method of a type-1 call: the option when set, else the matrix-core
-// spread when the kernel is narrow enough for a 16-cell padded tile (w <= 11:
-// tolerances down to 1e-9 in FP64) and the wavefront spread otherwise.
-int t1_method(const fh_ctx* c, int w)
+// Spread method of a type-1 call over N nodes (N < 0: not known): the option
+// when set, else the matrix-core spread when the kernel is narrow enough for
+// a 16-cell padded tile (w <= 11: tolerances down to 1e-9 in FP64) and the
+// call has nodes enough to keep the chip busy with it (below that the call
+// is bound by latency, and the wavefront spread's run merging and larger
+// tiles do as well with fewer slots), the wavefront spread otherwise.
+int t1_method(const fh_ctx* c, int w, int64_t N)
 {
     if (c->opt.spread_method > 0) return c->opt.spread_method;
-    return w <= 11 ? 5 : 2;
+    return w <= 11 && (N < 0 || N >= kMfmaMinNodes) ? 5 : 2;
 }
 
 // Fourier transform of the kernel in fine-grid units:
@@ -540,7 +558,8 @@ fh_status quad_bbox(fh_ctx* c, const fh_quad* q, double* bb)
 {
     if (!q->bbox_valid) {
         fh_quad* mq = const_cast<fh_quad*>(q);
-        FH_TRY(device_bbox(c, q->x, q->y, q->N, mq->bbox));
+        if (q->host_box) q->host_box(mq->bbox);
+        else FH_TRY(device_bbox(c, q->x, q->y, q->N, mq->bbox));
         mq->bbox_valid = true;
     }
     std::memcpy(bb, q->bbox, sizeof(double) * 4);
@@ -718,7 +737,7 @@ fh_status fh_query_params(const fh_ctx* c, int32_t n, int32_t* width, double* be
         // as the type-1 plan: power-of-two tiles divide the grid, other tiles
         // keep the lengths of 16-cell tiles
         int need = std::max((int)std::ceil(k.sigma * n), 2 * k.w);
-        int T = pick_tile(c, need, k.w);
+        int T = pick_tile(c, need, k.w, -1);
         *nf = next_fft_size(std::max(need, T + k.w), (T & (T - 1)) == 0 ? T : 16);
     }
     return FH_OK;

@@ -201,7 +201,9 @@ fh_status t1_pipeline(fh_ctx* c, int B, const fh_quad* const* qs, const double* 
                       size_t extra_bytes, void** extra, bool rebuild = false)
 {
     const size_t rs = sizeof(R);
-    T1Plan pl = plan_t1(c, n1, n2);
+    int64_t Nall = 0;
+    for (int b = 0; b < B; ++b) Nall += qs[b]->N;
+    T1Plan pl = plan_t1(c, n1, n2, Nall);
     FH_ARG(!pl.k.clamped, FH_ERR_UNSUPPORTED, "tolerance %g needs a kernel wider than %d at sigma %g", c->tol,
            kMaxWidth, pl.k.sigma);
     GridGeom gg = pl.gg;
@@ -254,13 +256,16 @@ fh_status t1_pipeline(fh_ctx* c, int B, const fh_quad* const* qs, const double* 
     // second pass: in LDS, fused with the epilogue, when a column fits
     LdsCols lc = lds_cols_plan(c, gg.nf2, (int64_t)n1 * B, rs);
     // first pass: in LDS as well, fused with the tile reduce, when a row fits
-    // too and a padded tile reaches one tile on (nine covering tiles per
-    // cell cost more than the stored grid's list reduce); the fine grid is
-    // then never stored, only the n1 needed columns of its transformed rows
-    // (F holds B x rows x n1 values)
+    // too, a padded tile reaches one tile on (nine covering tiles per cell
+    // cost more than the stored grid's list reduce) and there are rows
+    // enough for 16 workgroups per CU (one row per workgroup: with fewer,
+    // rocFFT's row pass and the tile reduce fill the chip better); the fine
+    // grid is then never stored, only the n1 needed columns of its
+    // transformed rows (F holds B x rows x n1 values)
     const int reach = tile_reach(gg);
     LdsCols lr;
-    if (lc.C > 0 && reach == 1) lr = lds_cols_plan(c, gg.nf1, (int64_t)gg.rows * B, rs, 1);
+    if (lc.C > 0 && reach == 1 && (int64_t)gg.rows * B >= 16 * (int64_t)c->cu_count)
+        lr = lds_cols_plan(c, gg.nf1, (int64_t)gg.rows * B, rs, 1);
     const bool fused = lr.C > 0 && t1_rows_lds(lr, gg, reach, rs) <= kLdsFftBytes;
     if (!fused) FH_TRY(fft_plan(c, gg.nf1, 0, gg.rows * B, &fa));
     if (lc.C == 0) FH_TRY(fft_plan(c, gg.nf2, 0, n1 * B, &fb));

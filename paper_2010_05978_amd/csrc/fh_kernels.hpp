@@ -2490,8 +2490,9 @@ void size_items(const fh_ctx* c, GridGeom& g, int64_t Ntot)
     g.P = (int)std::min<int64_t>(1 << 24, std::max<int64_t>(64, (Ntot + target - 1) / target));
 }
 
-// Type-1 geometry for an n1 x n2 grid; the row window is set per call.
-T1Plan plan_t1(fh_ctx* c, int n1, int n2)
+// Type-1 geometry for an n1 x n2 grid and N nodes in all (N < 0: not
+// known); the row window is set per call.
+T1Plan plan_t1(fh_ctx* c, int n1, int n2, int64_t N)
 {
     T1Plan p;
     p.k = choose_kernel(c, std::max(n1, n2));
@@ -2499,7 +2500,8 @@ T1Plan plan_t1(fh_ctx* c, int n1, int n2)
     const int W = p.k.w;
     const int need1 = std::max((int)std::ceil(p.k.sigma * n1), 2 * W);
     const int need2 = std::max((int)std::ceil(p.k.sigma * n2), 2 * W);
-    int T = pick_tile(c, std::min(need1, need2), W);
+    int method = t1_method(c, W, N);
+    int T = pick_tile(c, std::min(need1, need2), W, N);
     if (c->prec == FH_FP64 && T > 32) T = 32;
     GridGeom& g = p.gg;
     g.T = T;
@@ -2527,8 +2529,12 @@ T1Plan plan_t1(fh_ctx* c, int n1, int n2)
         g.ntx = g.nf1 / T;
         g.nty = g.nf2 / T;
         g.padx = g.pady = 0;
+        // a 16-cell tile's padded tile takes 2 x 2 blocks of matrix-core
+        // products, four times the work: the chosen spread becomes the
+        // wavefront spread unless the caller asked for this one
+        if (c->opt.spread_method <= 0) method = 2;
     }
-    spread_defaults(c, g, t1_method(c, W));
+    spread_defaults(c, g, method);
     return p;
 }
 

@@ -580,30 +580,55 @@ void set_bbox(fh_quad* q, double x0, double x1, double y0, double y1)
 // with 0 < alpha < 1, so the box of the boundary nodes and the origin holds
 // them all.  The boundary nodes are evaluated on the host at the rule's own
 // parameters t_i (Gauss-Legendre panels, or the trapezoid rule when panels is
-// 0), curve(t, X, Y) giving the point; the box is widened by a relative 1e-9
-// for the rounding of either side.  A tight box keeps the type-1 row window
-// (and with it the FFT and the column pass) as small as the shape allows.
+// 0), curve(cos t, sin t, X, Y) giving the point; the box is widened by a
+// relative 1e-9 for the rounding of either side.  A tight box keeps the
+// type-1 row window (and with it the FFT and the column pass) as small as the
+// shape allows.  cos t and sin t come from angle-addition recurrences (one
+// sincos per panel and per Gauss node offset, or a rotation by 2 pi/n per
+// trapezoid node, re-anchored every 1024 nodes), whose rounding the widening
+// covers: a rule is
+// built per call, and a sincos per boundary node would cost tens of
+// microseconds of host time for a few hundred nodes.
 template <class Curve>
 void boundary_box(int64_t n, int panels, int q, Curve curve, double* box)
 {
-    std::vector<double> gx, gw;
-    if (panels > 0) gl_host(q, gx, gw);
     double b[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int64_t i = 0; i < n; ++i) {
-        double t;
-        if (panels > 0) {
-            const int64_t p = i / q;
-            const int k = (int)(i - p * q);
-            t = (2.0 * kPi / panels) * ((double)p + 0.5 * (1.0 + gx[k]));
-        } else {
-            t = 2.0 * kPi * (double)(i + 1) / (double)n;
-        }
+    auto take = [&](double ct, double st) {
         double X, Y;
-        curve(t, X, Y);
+        curve(ct, st, X, Y);
         b[0] = std::min(b[0], X);
         b[1] = std::max(b[1], X);
         b[2] = std::min(b[2], Y);
         b[3] = std::max(b[3], Y);
+    };
+    if (panels > 0) {
+        std::vector<double> gx, gw, cd(q), sd(q);
+        gl_host(q, gx, gw);
+        const double hp = 2.0 * kPi / panels;
+        for (int k = 0; k < q; ++k) {
+            cd[k] = std::cos(0.5 * hp * (1.0 + gx[k]));
+            sd[k] = std::sin(0.5 * hp * (1.0 + gx[k]));
+        }
+        for (int p = 0; p < panels; ++p) {
+            const double cp = std::cos(hp * p), sp = std::sin(hp * p);
+            for (int k = 0; k < q; ++k) take(cp * cd[k] - sp * sd[k], sp * cd[k] + cp * sd[k]);
+        }
+    } else {
+        const double cs = std::cos(2.0 * kPi / (double)n), sn = std::sin(2.0 * kPi / (double)n);
+        double ct = cs, st = sn;  // t_0 = 2 pi/n
+        for (int64_t i = 0; i < n; ++i) {
+            take(ct, st);
+            if ((i & 1023) == 1023) {
+                // re-anchored every 1024 nodes: the drift stays ~1e-13
+                const double t = 2.0 * kPi * (double)(i + 2) / (double)n;
+                ct = std::cos(t);
+                st = std::sin(t);
+                continue;
+            }
+            const double cn = ct * cs - st * sn;
+            st = st * cs + ct * sn;
+            ct = cn;
+        }
     }
     const double pad = 1e-9 * (std::max({-b[0], b[1], -b[2], b[3]}) + 1.0);
     box[0] = b[0] - pad;
@@ -612,10 +637,9 @@ void boundary_box(int64_t n, int panels, int q, Curve curve, double* box)
     box[3] = b[3] + pad;
 }
 
-// cos kt and sin kt for k = 1..K by the rotation recurrence, into c[], s[].
-inline void harmonics(double t, int K, double* c, double* s)
+// cos k t and sin k t for k = 1..K from c1 = cos t, s1 = sin t.
+inline void harmonics(double c1, double s1, int K, double* c, double* s)
 {
-    const double c1 = std::cos(t), s1 = std::sin(t);
     double ck = 1.0, sk = 0.0;
     for (int k = 1; k <= K; ++k) {
         const double cn = ck * c1 - sk * s1;
@@ -628,21 +652,21 @@ inline void harmonics(double t, int K, double* c, double* s)
 
 void radial_box(const RadialParams& rp, int64_t n, double* box)
 {
-    boundary_box(n, rp.panels, rp.q, [&](double t, double& X, double& Y) {
+    boundary_box(n, rp.panels, rp.q, [&](double ct, double st, double& X, double& Y) {
         double c[kMaxFourier + 1], s[kMaxFourier + 1];
-        harmonics(t, rp.K, c, s);
+        harmonics(ct, st, rp.K, c, s);
         double r = rp.r0;
         for (int k = 1; k <= rp.K; ++k) r += rp.a[k - 1] * c[k] + rp.b[k - 1] * s[k];
-        X = r * std::cos(t);
-        Y = r * std::sin(t);
+        X = r * ct;
+        Y = r * st;
     }, box);
 }
 
 void fourier_box(const FourierParams& fp, int64_t n, double* box)
 {
-    boundary_box(n, fp.panels, fp.q, [&](double t, double& X, double& Y) {
+    boundary_box(n, fp.panels, fp.q, [&](double ct, double st, double& X, double& Y) {
         double c[kMaxFourier + 1], s[kMaxFourier + 1];
-        harmonics(t, fp.K, c, s);
+        harmonics(ct, st, fp.K, c, s);
         X = fp.ax[0];
         Y = fp.ay[0];
         for (int k = 1; k <= fp.K; ++k) {
@@ -880,9 +904,8 @@ fh_status fh_quad_radial(fh_ctx* c, double r0, const double* a, const double* b,
             return s;
         }
         qd->rebuild = [c, rp, n, m, qd]() { return radial_into(c, rp, n, m, qd->x, qd->y, qd->w); };
-        double box[4];
-        radial_box(rp, n, box);
-        set_bbox(qd, box[0], box[1], box[2], box[3]);
+        // the box waits for a call that needs it (a type-1 row window)
+        qd->host_box = [rp, n](double* box) { radial_box(rp, n, box); };
         *out = qd;
         return FH_OK;
     } catch (...) {
