@@ -462,43 +462,58 @@ def starfish_leg(fh, prec, steps, warmup, cpu_seconds):
 def grad_ratio(fh, precision, steps, warmup):
     """Backward/forward device time of the starshade shape-gradient problem
     (workload 5: 998,400 nodes, 384 edge coefficients, 512^2 pupil grid with
-    the k1^2 + k2^2 < 256^2 mask, 3 wavelengths, loss = mean |u_oc|^2)."""
+    the k1^2 + k2^2 < 256^2 mask, 3 wavelengths, loss = mean |u_oc|^2): the
+    sweep form (the rule built once per forward, one batched call for the
+    three fields; the backward sums the node gradients over the wavelengths
+    in one call and chains them to the coefficients once), and beside it the
+    per-wavelength form (a rule, a field and a chain rule per wavelength)."""
     import torch
     import workloads
-    from paper_2010_05978_amd.autograd import starshade_field
+    from paper_2010_05978_amd.autograd import starshade_field, starshade_sweep
     wl = workloads.workload(5)
     ctx = fh.Context(precision)
     rdt = torch.float64 if precision == "fp64" else torch.float32
     mask = torch.tensor(workloads.pupil_mask(wl.grid.n1), dtype=rdt, device="cuda")
     Min = float(mask.sum())
+    nl = len(wl.lams)
     coef = torch.tensor(wl.shape.coef, dtype=torch.float64, device="cuda", requires_grad=True)
 
-    def forward():
+    def sweep():
+        u = starshade_sweep(coef, ctx, wl.shape, wl.lams, wl.z, wl.grid, occulter=True)
+        return ((u.abs() ** 2).reshape(nl, -1) * mask.reshape(1, -1)).sum() / (nl * Min)
+
+    def per_wavelength():
         L = 0.0
         for lam in wl.lams:
             u = starshade_field(coef, ctx, wl.shape, lam, wl.z, wl.grid, occulter=True)
-            L = L + ((u.abs() ** 2).reshape(-1) * mask).sum() / (len(wl.lams) * Min)
+            L = L + ((u.abs() ** 2).reshape(-1) * mask).sum() / (nl * Min)
         return L
 
-    for _ in range(warmup):
-        forward().backward()
-    fwd = bwd = 0.0
-    for _ in range(steps):
-        coef.grad = None
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        L = forward()
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        L.backward()
-        torch.cuda.synchronize()
-        t2 = time.perf_counter()
-        fwd += t1 - t0
-        bwd += t2 - t1
+    def timed(forward):
+        for _ in range(warmup):
+            forward().backward()
+        fwd = bwd = 0.0
+        for _ in range(steps):
+            coef.grad = None
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            L = forward()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            L.backward()
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            fwd += t1 - t0
+            bwd += t2 - t1
+        return 1e3 * fwd / steps, 1e3 * bwd / steps
+
+    f1, b1 = timed(sweep)
+    f0, b0 = timed(per_wavelength)
     ctx.close()
-    return {"fwd_ms": 1e3 * fwd / steps, "bwd_ms": 1e3 * bwd / steps, "ratio": bwd / fwd,
+    return {"fwd_ms": f1, "bwd_ms": b1, "ratio": b1 / f1,
+            "per_wavelength": {"fwd_ms": f0, "bwd_ms": b0, "ratio": b0 / f0},
             "workload": "24-petal starshade, 998400 nodes, 384 edge coefficients, 512^2 masked pupil, "
-                        "3 wavelengths; forward includes quadrature generation"}
+                        "3 wavelengths; forward includes quadrature generation (once per forward)"}
 
 
 # FP64 flops per node-target pair of the edge-integral kernel (an FMA counts

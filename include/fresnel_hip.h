@@ -389,6 +389,18 @@ fh_status fh_field_grid_vjp(fh_ctx* ctx, const fh_quad* q, double lambda, double
                             int32_t occulter, const void* g_u, double* g_x, double* g_y,
                             double* g_w);
 
+/* The node gradients of a loss summed over L wavelengths (the paper's
+ * sweep of one rule over wavelengths, sec. 4.3): as fh_field_grid_vjp for
+ * each (lambda[l], z[l]) with cotangent plane l of g_u (device, L x n2 x n1
+ * complex in the context's precision), the L results added in order into
+ * g_x, g_y, g_w (device, N doubles each, overwritten).  The chain rule
+ * through the rule's construction is linear, so it then runs once on the
+ * sums (fh_starshade_vjp).  lambda and z are host arrays of L entries. */
+fh_status fh_field_grid_vjp_sum(fh_ctx* ctx, const fh_quad* q, int32_t L, const double* lambda,
+                                const double* z, int32_t n1, int32_t n2, double h1, double h2,
+                                double xc, double yc, int32_t occulter, const void* g_u,
+                                double* g_x, double* g_y, double* g_w);
+
 /* Chain (dL/dx, dL/dy, dL/dw) of a perturbed starshade rule (same
  * parameters as fh_quad_starshade; all arrays on the device) to dL/dcoef
  * (2 Np K doubles). */

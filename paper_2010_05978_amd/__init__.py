@@ -252,6 +252,15 @@ class Context:
                               g_u.contiguous(), gx, gy, gw)
         return gx, gy, gw
 
+    def field_grid_vjp_sum(self, quad: Quad, lams, zs, n1, n2, h1, h2, g_u, xc=0.0, yc=0.0, occulter=False):
+        """Node gradients summed over wavelengths; g_u holds one cotangent plane per wavelength."""
+        import torch
+        n = quad.N
+        gx, gy, gw = (torch.empty(n, dtype=torch.float64, device=self.device) for _ in range(3))
+        abi.fh_field_grid_vjp_sum(self.handle, quad.handle, lams, zs, n1, n2, h1, h2, xc, yc, occulter,
+                                  g_u.contiguous(), gx, gy, gw)
+        return gx, gy, gw
+
     def autotune_grid(self, quad: Quad, lam, z, n1, n2, h1, h2, cache_path=None) -> fh_options:
         """Time the grid field over the tuning space and keep the fastest options."""
         return abi.fh_autotune_grid(self.handle, quad.handle, lam, z, n1, n2, h1, h2, cache_path)

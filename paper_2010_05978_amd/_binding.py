@@ -41,6 +41,7 @@ EXPORTED = [
     "fh_quad_fourier", "fh_boundary_fourier", "fh_quad_koch", "fh_quad_starshade_rigid",
     "fh_quad_starshade_tab", "fh_targets_sort", "fh_probe_ceilings", "fh_quad_set_illumination",
     "fh_field_nsli_noalloc", "fh_quad_starshade_ribbon", "fh_autotune_batch", "fh_field_grid_batch_rebuild",
+    "fh_field_grid_vjp_sum",
 ]
 
 
@@ -101,6 +102,7 @@ def lib():
             "fh_autotune_grid": [vp, vp, d, d, i32, i32, d, d, ctypes.c_char_p, ctypes.POINTER(fh_options)],
             "fh_autotune_batch": [vp, i32, vp, vp, vp, i32, i32, d, d, ctypes.c_char_p, ctypes.POINTER(fh_options)],
             "fh_field_grid_batch_rebuild": [vp, i32, vp, vp, vp, i32, i32, d, d, d, d, vp, vp],
+            "fh_field_grid_vjp_sum": [vp, vp, i32, vp, vp, i32, i32, d, d, d, d, i32, vp, vp, vp, vp],
             "fh_set_timing": [vp, i32],
             "fh_last_timing": [vp, ctypes.POINTER(d)],
             "fh_timing_totals": [vp, i32, ctypes.POINTER(d), ctypes.POINTER(i64), i32],
@@ -492,6 +494,19 @@ def fh_field_grid_vjp(ctx, q, lam, z, n1, n2, h1, h2, xc, yc, occulter, g_u, g_x
             raise ValueError("fh_field_grid_vjp takes device arrays")
     _check(lib().fh_field_grid_vjp(ctx, q, lam, z, n1, n2, h1, h2, xc, yc, int(bool(occulter)),
                                    _ptr_mem(g_u)[0], _ptr_mem(g_x)[0], _ptr_mem(g_y)[0], _ptr_mem(g_w)[0]))
+
+
+def fh_field_grid_vjp_sum(ctx, q, lams, zs, n1, n2, h1, h2, xc, yc, occulter, g_u, g_x, g_y, g_w):
+    for a in (g_u, g_x, g_y, g_w):
+        if _ptr_mem(a)[1] != FH_MEM_DEVICE:
+            raise ValueError("fh_field_grid_vjp_sum takes device arrays")
+    la = np.ascontiguousarray(lams, dtype=np.float64)
+    za = np.ascontiguousarray(zs, dtype=np.float64)
+    if la.shape != za.shape or la.ndim != 1:
+        raise ValueError("lams and zs must be 1-D arrays of one length")
+    _check(lib().fh_field_grid_vjp_sum(ctx, q, len(la), _ptr_mem(la)[0], _ptr_mem(za)[0], n1, n2, h1, h2, xc, yc,
+                                       int(bool(occulter)), _ptr_mem(g_u)[0], _ptr_mem(g_x)[0], _ptr_mem(g_y)[0],
+                                       _ptr_mem(g_w)[0]))
 
 
 def fh_starshade_vjp(ctx, Np, a, R, b, p, m, np_, nd, md, coef, K, g_x, g_y, g_w, g_coef):

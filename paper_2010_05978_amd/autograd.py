@@ -57,6 +57,45 @@ class StarshadeGridField(torch.autograd.Function):
         return gcoef, None, None, None, None, None, None
 
 
+class StarshadeGridSweep(torch.autograd.Function):
+    """u[l] = field_grid(perturbed starshade rule(coef), lams[l], zs[l]) for L
+    wavelengths (sec. 4.3's sweep of one rule): the rule is built once and
+    the L fields computed in one batched call; the backward pass sums the L
+    node gradients in one library call and chains them to the 2 Np K edge
+    coefficients once."""
+
+    @staticmethod
+    def forward(ctx, coef, fctx, shape, lams, zs, grid, occulter):
+        import numpy as np
+        c = coef.detach().contiguous()
+        q = fctx.quad_starshade(shape.Np, shape.a, shape.R, shape.b, shape.p, shape.m, shape.np_, shape.nd,
+                                shape.md, c, shape.K)
+        lams = np.asarray(lams, dtype=np.float64)
+        zs = np.broadcast_to(np.asarray(zs, dtype=np.float64), lams.shape).copy()
+        u = fctx.field_grid_batch([q] * len(lams), lams, zs, grid.n1, grid.n2, grid.h1, grid.h2, grid.xc, grid.yc,
+                                  occulter)
+        ctx.fctx, ctx.q, ctx.args = fctx, q, (shape, lams, zs, grid, occulter)
+        ctx.save_for_backward(c)
+        return u
+
+    @staticmethod
+    def backward(ctx, gu):
+        (c,) = ctx.saved_tensors
+        shape, lams, zs, grid, occulter = ctx.args
+        f = ctx.fctx
+        gx, gy, gw = f.field_grid_vjp_sum(ctx.q, lams, zs, grid.n1, grid.n2, grid.h1, grid.h2, gu.contiguous(),
+                                          grid.xc, grid.yc, occulter)
+        gcoef = torch.empty_like(c)
+        abi.fh_starshade_vjp(f.handle, shape.Np, shape.a, shape.R, shape.b, shape.p, shape.m, shape.np_, shape.nd,
+                             shape.md, c, shape.K, gx, gy, gw, gcoef)
+        return gcoef, None, None, None, None, None, None
+
+
+def starshade_sweep(coef, fctx, shape, lams, zs, grid, occulter=True):
+    """Fields of one perturbed starshade at several wavelengths (L x n2 x n1)."""
+    return StarshadeGridSweep.apply(coef, fctx, shape, lams, zs, grid, occulter)
+
+
 def starshade_field(coef, fctx, shape, lam, z, grid, occulter=True):
     return StarshadeGridField.apply(coef, fctx, shape, lam, z, grid, occulter)
 

@@ -119,79 +119,272 @@ __global__ void __launch_bounds__(256) k_adj_transpose(const R* __restrict__ Zt,
 }
 
 // Gather the three channels at each node with the ES kernel, then form the
-// node gradients.
-template <class R, int W>
-__global__ void __launch_bounds__(256) k_adj_gather(const R* __restrict__ F1, InstParams ip, GridGeom gg, R beta,
-                                                    const R* __restrict__ poly, double lz, double* __restrict__ gx,
-                                                    double* __restrict__ gy, double* __restrict__ gw)
+// node gradients (written, or with ACC added to what the outputs hold).  A
+// wavefront takes up to 64 nodes at a time: lane l first finds node l's
+// stencil cell and its 2W kernel values (staged in LDS); the wavefront then
+// gathers in trips of 64/GS nodes, GS lanes per node, lane r taking stencil
+// column r down all W rows of the three channels (3W loads in flight, and
+// each load instruction reads, per node, a contiguous run of a row rather
+// than one line per lane, as the type-3 interpolation does); the column is
+// weighted down its rows, then by its own kernel value, and summed over the
+// group by a fixed butterfly.  Lane l finally forms node l's gradients.
+template <class R, int W, bool ACC>
+__global__ void __launch_bounds__(64) k_adj_gather(const R* __restrict__ F1, InstParams ip, GridGeom gg, R beta,
+                                                   const R* __restrict__ poly, double lz, int tpw,
+                                                   double* __restrict__ gx, double* __restrict__ gy,
+                                                   double* __restrict__ gw)
 {
-    using C2 = typename V2<R>::T;
-    const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (j >= ip.N) return;
-    const double x = ip.x[j], y = ip.y[j], w = ip.w[j];
-    int l1, l2;
-    double d1, d2;
-    if (!node_cell(ip, gg, x, y, l1, l2, d1, d2)) {
-        gx[j] = 0.0;
-        gy[j] = 0.0;
-        gw[j] = 0.0;
-        return;
-    }
-    R k1[W];
-    es_weights<R, W>((R)d1, beta, poly, k1);
+    using C = typename V2<R>::T;
+    constexpr int GS = interp_group<W>();
+    constexpr int NT = 64 / GS;
+    constexpr int KS = 2 * W + 1;
+    __shared__ R ks[64 * KS];
+    __shared__ uint32_t cs[64];
+    __shared__ C res[3][64];
+    const int lane = threadIdx.x, g = lane / GS, r = lane % GS;
+    const C* F = reinterpret_cast<const C*>(F1);
     const size_t plane = (size_t)gg.rows * gg.nf1;
-    const C2* F = reinterpret_cast<const C2*>(F1);
-    R t0r = 0, t0i = 0, t1r = 0, t1i = 0, t2r = 0, t2i = 0;
-#pragma unroll 1
-    for (int b = 0; b < W; ++b) {
-        int row = l2 + b;
-        if (row >= gg.rows) row -= gg.rows;  // periodic only when the rows are the whole period
-        const C2* fr = F + (size_t)row * gg.nf1;
-        R a0r = 0, a0i = 0, a1r = 0, a1i = 0, a2r = 0, a2i = 0;
-#pragma unroll
-        for (int a = 0; a < W; ++a) {
-            int col = l1 + a;
-            if (col >= gg.nf1) col -= gg.nf1;
-            const C2 v0 = fr[col], v1 = fr[plane + col], v2 = fr[2 * plane + col];
-            a0r += v0.x * k1[a];
-            a0i += v0.y * k1[a];
-            a1r += v1.x * k1[a];
-            a1i += v1.y * k1[a];
-            a2r += v2.x * k1[a];
-            a2i += v2.y * k1[a];
+    for (int64_t base = blockIdx.x * (int64_t)tpw; base < ip.N; base += (int64_t)gridDim.x * tpw) {
+        const int64_t j = base + lane;
+        const bool live = lane < tpw && j < ip.N;
+        const int64_t k = live ? j : 0;
+        const double x = ip.x[k], y = ip.y[k];
+        int l1, l2;
+        double d1, d2;
+        const bool ok = node_cell(ip, gg, x, y, l1, l2, d1, d2);
+        if (!ok) {
+            // a node outside the window: gathered from cell 0 with any
+            // weights, its gradients are zero
+            l1 = l2 = 0;
+            d1 = d2 = 0.0;
         }
-        const R kb = es_one<R, W>((R)d2, b, beta, poly);
-        t0r += a0r * kb;
-        t0i += a0i * kb;
-        t1r += a1r * kb;
-        t1i += a1i * kb;
-        t2r += a2r * kb;
-        t2i += a2i * kb;
+        cs[lane] = (uint32_t)l1 | ((uint32_t)l2 << 16);
+        {
+            R kv[W];
+            es_weights<R, W>((R)d1, beta, poly, kv);
+#pragma unroll
+            for (int a = 0; a < W; ++a) ks[lane * KS + a] = kv[a];
+            es_weights<R, W>((R)d2, beta, poly, kv);
+#pragma unroll
+            for (int b = 0; b < W; ++b) ks[lane * KS + W + b] = kv[b];
+        }
+        wave_lds_order();
+        const int nq = (int)min<int64_t>(tpw, ip.N - base);
+        const int rr = min(r, W - 1);
+        for (int q0 = 0; q0 < nq; q0 += NT) {
+            const int q = q0 + g, qq = min(q, nq - 1);
+            const uint32_t cp = cs[qq];
+            int col = (int)(cp & 0xffffu) + rr;
+            col = col >= gg.nf1 ? col - gg.nf1 : col;
+            const int row0 = (int)(cp >> 16);
+            C v0[W], v1[W], v2[W];
+#pragma unroll
+            for (int b = 0; b < W; ++b) {
+                int row = row0 + b;
+                if (row >= gg.rows) row -= gg.rows;  // periodic only when the rows are the whole period
+                const size_t e = (size_t)row * gg.nf1 + col;
+                v0[b] = F[e];
+                v1[b] = F[plane + e];
+                v2[b] = F[2 * plane + e];
+            }
+            const R* kq = ks + qq * KS;
+            R s0r = 0, s0i = 0, s1r = 0, s1i = 0, s2r = 0, s2i = 0;
+#pragma unroll
+            for (int b = 0; b < W; ++b) {
+                const R kb = kq[W + b];
+                s0r += v0[b].x * kb;
+                s0i += v0[b].y * kb;
+                s1r += v1[b].x * kb;
+                s1i += v1[b].y * kb;
+                s2r += v2[b].x * kb;
+                s2i += v2[b].y * kb;
+            }
+            const R kx = (q < nq && r < W) ? kq[rr] : R(0);
+            s0r = group_sum<GS>(s0r * kx);
+            s0i = group_sum<GS>(s0i * kx);
+            s1r = group_sum<GS>(s1r * kx);
+            s1i = group_sum<GS>(s1i * kx);
+            s2r = group_sum<GS>(s2r * kx);
+            s2i = group_sum<GS>(s2i * kx);
+            if (r == 0 && q < nq) {
+                res[0][q] = C{s0r, s0i};
+                res[1][q] = C{s1r, s1i};
+                res[2][q] = C{s2r, s2i};
+            }
+        }
+        wave_lds_order();
+        if (live) {
+            double ox = 0.0, oy = 0.0, ow = 0.0;
+            if (ok) {
+                const C t0 = res[0][lane], t1 = res[1][lane], t2 = res[2][lane];
+                // P_j = exp(2 pi i t), t = the forward strength phase in turns
+                const double t = ((x * x + y * y) * ip.pa + (x * ip.px + y * ip.py)) + ip.pc;
+                const double f = t - rint(t);
+                double sn, c;
+                sincospi(2.0 * f, &sn, &c);
+                const double Gr = c * (double)t0.x - sn * (double)t0.y, Gi = sn * (double)t0.x + c * (double)t0.y;
+                const double Hxr = c * (double)t1.x - sn * (double)t1.y;
+                const double Hyr = c * (double)t2.x - sn * (double)t2.y;
+                const double fac = 2.0 * kPi * ip.w[k] / (lz * lz);
+                ow = Gi / lz;
+                ox = fac * (x * Gr - Hxr);
+                oy = fac * (y * Gr - Hyr);
+            }
+            if (ACC) {
+                gx[j] += ox;
+                gy[j] += oy;
+                gw[j] += ow;
+            } else {
+                gx[j] = ox;
+                gy[j] = oy;
+                gw[j] = ow;
+            }
+        }
+        wave_lds_order();
     }
-    // P_j = exp(2 pi i t), t = the forward strength phase in turns
-    const double t = ((x * x + y * y) * ip.pa + (x * ip.px + y * ip.py)) + ip.pc;
-    const double f = t - rint(t);
-    double s, c;
-    sincospi(2.0 * f, &s, &c);
-    const double Gr = c * t0r - s * t0i, Gi = s * t0r + c * t0i;
-    const double Hxr = c * t1r - s * t1i;
-    const double Hyr = c * t2r - s * t2i;
-    gw[j] = Gi / lz;
-    const double fac = 2.0 * kPi * w / (lz * lz);
-    gx[j] = fac * (x * Gr - Hxr);
-    gy[j] = fac * (y * Gr - Hyr);
 }
 
+// The same gradients when the three channels' cells that the nodes reach
+// fit in LDS (a rule whose nodes crowd a few cells, as a starshade does on a
+// pupil grid): each block first copies that window -- every held row, the
+// span1 columns from (col0 mod nf1) on -- into LDS, then a thread per node
+// gathers its W x W cells of each channel from there.  The window comes
+// from the rule's bounding box (with a cell of margin), so every node's
+// stencil lies inside it; reads are clamped to the window all the same.
+template <class R, int W, bool ACC>
+__global__ void __launch_bounds__(256) k_adj_gather_lds(const R* __restrict__ F1, InstParams ip, GridGeom gg, R beta,
+                                                        const R* __restrict__ poly, double lz, int col0, int span1,
+                                                        double* __restrict__ gx, double* __restrict__ gy,
+                                                        double* __restrict__ gw)
+{
+    using C = typename V2<R>::T;
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    C* win = reinterpret_cast<C*>(lds_raw);
+    const C* F = reinterpret_cast<const C*>(F1);
+    const size_t plane = (size_t)gg.rows * gg.nf1;
+    const int wplane = gg.rows * span1;
+    for (int e = threadIdx.x; e < 3 * wplane; e += blockDim.x) {
+        const int ch = e / wplane, rem = e - ch * wplane;
+        const int row = rem / span1, wc = rem - row * span1;
+        int col = (col0 + wc) % gg.nf1;
+        if (col < 0) col += gg.nf1;
+        win[e] = F[ch * plane + (size_t)row * gg.nf1 + col];
+    }
+    __syncthreads();
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < ip.N; j += (int64_t)gridDim.x * blockDim.x) {
+        const double x = ip.x[j], y = ip.y[j];
+        int l1, l2;
+        double d1, d2;
+        double ox = 0.0, oy = 0.0, ow = 0.0;
+        if (node_cell(ip, gg, x, y, l1, l2, d1, d2)) {
+            R k1[W];
+            es_weights<R, W>((R)d1, beta, poly, k1);
+            int wc0 = (l1 - col0) % gg.nf1;
+            if (wc0 < 0) wc0 += gg.nf1;
+            wc0 = min(wc0, span1 - W);
+            const int r0 = min(l2, gg.rows - W);
+            R t0r = 0, t0i = 0, t1r = 0, t1i = 0, t2r = 0, t2i = 0;
+#pragma unroll 1
+            for (int b = 0; b < W; ++b) {
+                const C* wr = win + (r0 + b) * span1 + wc0;
+                R a0r = 0, a0i = 0, a1r = 0, a1i = 0, a2r = 0, a2i = 0;
+#pragma unroll
+                for (int a = 0; a < W; ++a) {
+                    const C v0 = wr[a], v1 = wr[wplane + a], v2 = wr[2 * wplane + a];
+                    a0r += v0.x * k1[a];
+                    a0i += v0.y * k1[a];
+                    a1r += v1.x * k1[a];
+                    a1i += v1.y * k1[a];
+                    a2r += v2.x * k1[a];
+                    a2i += v2.y * k1[a];
+                }
+                const R kb = es_one<R, W>((R)d2, b, beta, poly);
+                t0r += a0r * kb;
+                t0i += a0i * kb;
+                t1r += a1r * kb;
+                t1i += a1i * kb;
+                t2r += a2r * kb;
+                t2i += a2i * kb;
+            }
+            // P_j = exp(2 pi i t), t = the forward strength phase in turns
+            const double t = ((x * x + y * y) * ip.pa + (x * ip.px + y * ip.py)) + ip.pc;
+            const double f = t - rint(t);
+            double sn, c;
+            sincospi(2.0 * f, &sn, &c);
+            const double Gr = c * t0r - sn * t0i, Gi = sn * t0r + c * t0i;
+            const double Hxr = c * t1r - sn * t1i;
+            const double Hyr = c * t2r - sn * t2i;
+            const double fac = 2.0 * kPi * ip.w[j] / (lz * lz);
+            ow = Gi / lz;
+            ox = fac * (x * Gr - Hxr);
+            oy = fac * (y * Gr - Hyr);
+        }
+        if (ACC) {
+            gx[j] += ox;
+            gy[j] += oy;
+            gw[j] += ow;
+        } else {
+            gx[j] = ox;
+            gy[j] = oy;
+            gw[j] = ow;
+        }
+    }
+}
+
+// LDS bytes of the gather's window, or 0 when it does not fit the budget.
+inline size_t adj_window_lds(int rows, int span1, size_t rs)
+{
+    const size_t b = 3 * 2 * rs * (size_t)rows * span1;
+    return b <= kLdsBudget ? b : 0;
+}
+
+// Nodes per wavefront: 64, halved (down to one gather trip's worth) while
+// that leaves fewer than about 4 wavefronts per CU.
 template <class R>
 fh_status launch_gather(fh_ctx* c, int W, const R* F1, const InstParams& ip, const GridGeom& gg, double beta,
-                        const void* poly, double lz, double* gx, double* gy, double* gw)
+                        const void* poly, double lz, bool acc, int col0, int span1, double* gx, double* gy,
+                        double* gw)
 {
-    const unsigned g = nblocks(ip.N, 256);
+    const size_t wl = span1 > 0 ? adj_window_lds(gg.rows, span1, sizeof(R)) : 0;
+    if (wl > 0) {
+        // a block per window copy: as many as keep every CU busy, each
+        // walking its share of the nodes
+        const unsigned g = (unsigned)std::max<int64_t>(
+            1, std::min<int64_t>((ip.N + 255) / 256, (int64_t)c->cu_count * (int64_t)(kCuLds / wl)));
+        switch (W) {
+#define FH_GATHER_LDS_CASE(w)                                                                                    \
+    case w:                                                                                                     \
+        if (acc)                                                                                                \
+            hipLaunchKernelGGL((k_adj_gather_lds<R, w, true>), dim3(g), dim3(256), wl, c->stream, F1, ip, gg,    \
+                               (R)beta, (const R*)poly, lz, col0, span1, gx, gy, gw);                           \
+        else                                                                                                    \
+            hipLaunchKernelGGL((k_adj_gather_lds<R, w, false>), dim3(g), dim3(256), wl, c->stream, F1, ip, gg,   \
+                               (R)beta, (const R*)poly, lz, col0, span1, gx, gy, gw);                           \
+        break;
+            FH_GATHER_LDS_CASE(2) FH_GATHER_LDS_CASE(3) FH_GATHER_LDS_CASE(4) FH_GATHER_LDS_CASE(5)
+            FH_GATHER_LDS_CASE(6) FH_GATHER_LDS_CASE(7) FH_GATHER_LDS_CASE(8) FH_GATHER_LDS_CASE(9)
+            FH_GATHER_LDS_CASE(10) FH_GATHER_LDS_CASE(11) FH_GATHER_LDS_CASE(12) FH_GATHER_LDS_CASE(13)
+            FH_GATHER_LDS_CASE(14) FH_GATHER_LDS_CASE(15) FH_GATHER_LDS_CASE(16) FH_GATHER_LDS_CASE(17)
+            FH_GATHER_LDS_CASE(18) FH_GATHER_LDS_CASE(19) FH_GATHER_LDS_CASE(20)
+#undef FH_GATHER_LDS_CASE
+        default: set_error("kernel width %d unsupported", W); return FH_ERR_UNSUPPORTED;
+        }
+        FH_HIP(hipGetLastError());
+        return FH_OK;
+    }
+    const int per_trip = W <= 8 ? 8 : (W <= 16 ? 4 : 2);
+    int tpw = 64;
+    while (tpw > per_trip && ip.N / tpw < (int64_t)c->cu_count * 4) tpw /= 2;
+    const unsigned g = (unsigned)std::min<int64_t>((ip.N + tpw - 1) / tpw, 1 << 20);
     switch (W) {
 #define FH_GATHER_CASE(w)                                                                                        \
     case w:                                                                                                     \
-        hipLaunchKernelGGL((k_adj_gather<R, w>), dim3(g), dim3(256), 0, c->stream, F1, ip, gg, (R)beta,         \
-                           (const R*)poly, lz, gx, gy, gw);                                                     \
+        if (acc)                                                                                                \
+            hipLaunchKernelGGL((k_adj_gather<R, w, true>), dim3(g), dim3(64), 0, c->stream, F1, ip, gg, (R)beta, \
+                               (const R*)poly, lz, tpw, gx, gy, gw);                                            \
+        else                                                                                                    \
+            hipLaunchKernelGGL((k_adj_gather<R, w, false>), dim3(g), dim3(64), 0, c->stream, F1, ip, gg,         \
+                               (R)beta, (const R*)poly, lz, tpw, gx, gy, gw);                                   \
         break;
         FH_GATHER_CASE(2) FH_GATHER_CASE(3) FH_GATHER_CASE(4) FH_GATHER_CASE(5) FH_GATHER_CASE(6)
         FH_GATHER_CASE(7) FH_GATHER_CASE(8) FH_GATHER_CASE(9) FH_GATHER_CASE(10) FH_GATHER_CASE(11)
@@ -210,9 +403,12 @@ __global__ void k_zero_doubles(double* __restrict__ p, int64_t n)
     if (i < n) p[i] = 0.0;
 }
 
+// Node gradients of one grid field's cotangent g_u, written to (acc: added
+// to) g_x, g_y, g_w.
 template <class R>
 fh_status grid_vjp_impl(fh_ctx* c, const fh_quad* q, double lambda, double z, int n1, int n2, double h1, double h2,
-                        double xc, double yc, int occ, const void* g_u, double* g_x, double* g_y, double* g_w)
+                        double xc, double yc, int occ, const void* g_u, double* g_x, double* g_y, double* g_w,
+                        bool acc = false)
 {
     const size_t rs = sizeof(R);
     const double lz = lambda * z;
@@ -267,7 +463,18 @@ fh_status grid_vjp_impl(fh_ctx* c, const fh_quad* q, double lambda, double z, in
     FH_HIP(hipGetLastError());
     FH_TRY(fft_exec(c, fb, F1));
     timing_mark(c, 3);
-    FH_TRY(launch_gather<R>(c, gg.W, F1, ip, gg, pl.k.beta, pl.k.poly, lz, g_x, g_y, g_w));
+    // the columns the nodes reach: their box's cells with a cell of margin
+    // (as the row window), when the rows are windowed too
+    int col0 = 0, span1 = 0;
+    if (!gg.wrap_y) {
+        const double a0 = std::ceil(bb[0] * ip.s1 - 0.5 * gg.W) - 1.0;
+        const double a1 = std::ceil(bb[1] * ip.s1 - 0.5 * gg.W) + gg.W + 1.0;
+        if (a1 - a0 < gg.nf1 && std::fabs(a0) < 1e9) {
+            col0 = (int)a0;
+            span1 = (int)(a1 - a0);
+        }
+    }
+    FH_TRY(launch_gather<R>(c, gg.W, F1, ip, gg, pl.k.beta, pl.k.poly, lz, acc, col0, span1, g_x, g_y, g_w));
     timing_mark(c, 4);
     timing_mark(c, 5);
     return FH_OK;
@@ -309,11 +516,37 @@ __global__ void __launch_bounds__(128) k_ss_vjp_partial(SsParams sp, int s0, con
         const double wr = 0.5 * L * glm[sp.m + l];
         const double tau = gln[i], wt = gln[sp.np + i];
         const double A = exp(-pow((r - sp.a) / sp.b, sp.p));
+        // sin(s theta), s = 1..K, by the three-term recurrence
+        // sin((s+1) theta) = 2 cos(theta) sin(s theta) - sin((s-1) theta), as
+        // the rule kernel evaluates them
+        const double u = (r - sp.a) / L;
+        double s1, c1;
+        sincospi(u, &s1, &c1);
         double dp = 0.0, dm = 0.0;
-        for (int s = 1; s <= sp.K; ++s) {
-            const double sk = sin(s * kPi * (r - sp.a) / L);
-            dp += cp[s - 1] * sk;
-            dm += cp[sp.K + s - 1] * sk;
+        {
+            double sm = 0.0, sk = s1;
+            for (int s = 1; s <= sp.K; ++s) {
+                dp += cp[s - 1] * sk;
+                dm += cp[sp.K + s - 1] * sk;
+                const double sn = 2.0 * c1 * sk - sm;
+                sm = sk;
+                sk = sn;
+            }
+        }
+        // the group's sin((s0 + q + 1) theta), q < kCoefGroup, by the same
+        // recurrence from sin(s0 theta)
+        double sg[kCoefGroup];
+        {
+            double sa, ca;
+            sincospi(s0 * u, &sa, &ca);
+            double prev = sa, cur = sa * c1 + ca * s1;
+#pragma unroll
+            for (int q = 0; q < kCoefGroup; ++q) {
+                sg[q] = cur;
+                const double nx = 2.0 * c1 * cur - prev;
+                prev = cur;
+                cur = nx;
+            }
         }
         const double mid = (dp - dm) / (2.0 * r);
         const double half = kPi * A / sp.Np + (dp + dm) / (2.0 * r);
@@ -328,9 +561,8 @@ __global__ void __launch_bounds__(128) k_ss_vjp_partial(SsParams sp, int s0, con
 #pragma unroll
         for (int s = 0; s < kCoefGroup; ++s) {
             if (s < ns) {
-                const double sk = sin((s0 + s + 1) * kPi * (r - sp.a) / L);
-                accp[s] += up * sk + dwc * sk;
-                accm[s] += um * sk + dwc * sk;
+                accp[s] += up * sg[s] + dwc * sg[s];
+                accm[s] += um * sg[s] + dwc * sg[s];
             }
         }
     }
@@ -391,6 +623,38 @@ fh_status fh_field_grid_vjp(fh_ctx* c, const fh_quad* q, double lambda, double z
         if (c->prec == FH_FP64)
             return grid_vjp_impl<double>(c, q, lambda, z, n1, n2, h1, h2, xc, yc, occulter, g_u, g_x, g_y, g_w);
         return grid_vjp_impl<float>(c, q, lambda, z, n1, n2, h1, h2, xc, yc, occulter, g_u, g_x, g_y, g_w);
+    } catch (...) {
+        set_error("host allocation failed");
+        return FH_ERR_ALLOC;
+    }
+}
+
+fh_status fh_field_grid_vjp_sum(fh_ctx* c, const fh_quad* q, int32_t L, const double* lambda, const double* z,
+                                int32_t n1, int32_t n2, double h1, double h2, double xc, double yc, int32_t occulter,
+                                const void* g_u, double* g_x, double* g_y, double* g_w)
+{
+    try {
+        FH_ARG(c && q && lambda && z, FH_ERR_INVALID_ARG, "NULL argument");
+        FH_ARG(L >= 1, FH_ERR_INVALID_ARG, "L must be >= 1");
+        FH_ARG(q->ctx->device == c->device, FH_ERR_INVALID_ARG, "quadrature lives on another device");
+        FH_ARG(q->N == 0 || (g_u && g_x && g_y && g_w), FH_ERR_INVALID_ARG, "NULL array");
+        for (int l = 0; l < L; ++l) FH_TRY(check_lz(lambda[l], z[l]));
+        FH_TRY(check_grid(n1, n2, h1, h2, xc, yc));
+        FH_ARG(q->N < ((int64_t)1 << 31), FH_ERR_UNSUPPORTED, "at most 2^31 - 1 nodes per call");
+        FH_ARG(!q->src && !(q->D > 0.0), FH_ERR_UNSUPPORTED,
+               "the adjoint covers plane-wave illumination without source terms");
+        FH_HIP(hipSetDevice(c->device));
+        const size_t plane = (c->prec == FH_FP64 ? 16 : 8) * (size_t)n1 * n2;
+        for (int l = 0; l < L; ++l) {
+            const void* gl = static_cast<const char*>(g_u) + plane * l;
+            if (c->prec == FH_FP64)
+                FH_TRY(grid_vjp_impl<double>(c, q, lambda[l], z[l], n1, n2, h1, h2, xc, yc, occulter, gl, g_x, g_y,
+                                             g_w, l > 0));
+            else
+                FH_TRY(grid_vjp_impl<float>(c, q, lambda[l], z[l], n1, n2, h1, h2, xc, yc, occulter, gl, g_x, g_y,
+                                            g_w, l > 0));
+        }
+        return FH_OK;
     } catch (...) {
         set_error("host allocation failed");
         return FH_ERR_ALLOC;

@@ -188,14 +188,15 @@ __global__ void k_fill_field(R* __restrict__ u, int64_t M, R re)
 
 // ------------------------------------------------------------------- bin
 // Block-aggregated counting: the wavefronts of a block first combine their
-// per-tile counts in a small LDS table (tiles of one block are few, since
-// nodes arrive in spoke order), then one global atomic per distinct tile of
-// the block reserves the block's positions.  A table overflow falls back to
-// one global atomic per wavefront group.  When every node of a rule falls in
-// a couple of tiles (a starshade seen on a coarse pupil grid), this turns
-// one same-address atomic chain per wavefront into one per block.
+// per-tile counts in an LDS hash table (open addressing, twice as many
+// entries as the block has nodes, so it never fills), then one global atomic
+// per distinct tile of the block reserves the block's positions.  When
+// every node of a rule falls in a couple of tiles (a starshade seen on a
+// coarse pupil grid), this turns one same-address atomic chain per wavefront
+// into one per block; with small tiles, a block's nodes touch hundreds.
 constexpr int kBinBlock = 1024;
-constexpr int kBinKeys = 128;
+constexpr int kBinKeyBits = 11;  // twice the block's nodes: the table never overflows
+constexpr int kBinKeys = 1 << kBinKeyBits;
 
 // With `key` (the stable binning), each node also writes its tile and its
 // index, the keys and values of the sort that then fixes the ranks.
@@ -208,9 +209,9 @@ __global__ void __launch_bounds__(kBinBlock) k_bin_count(InstParams p0, const In
     __shared__ int s_cnt[kBinKeys];
     __shared__ int s_base[kBinKeys];
     __shared__ int s_inst[2];
-    if (threadIdx.x < kBinKeys) {
-        s_key[threadIdx.x] = -1;
-        s_cnt[threadIdx.x] = 0;
+    for (int e = threadIdx.x; e < kBinKeys; e += kBinBlock) {
+        s_key[e] = -1;
+        s_cnt[e] = 0;
     }
     if (table) block_inst_bounds(table, ninst, Ntot, s_inst);
     __syncthreads();
@@ -247,7 +248,7 @@ __global__ void __launch_bounds__(kBinBlock) k_bin_count(InstParams p0, const In
     const bool lead = valid && leader == lane;
     int slot = -1, off = 0, gbase = 0;
     if (lead) {
-        int h = (int)(((unsigned)tile * 2654435761u) >> 25) & (kBinKeys - 1);
+        int h = (int)(((unsigned)tile * 2654435761u) >> (32 - kBinKeyBits));
         for (int probe = 0; probe < kBinKeys; ++probe) {
             const int prev = atomicCAS(&s_key[h], -1, tile);
             if (prev == -1 || prev == tile) {
@@ -262,8 +263,8 @@ __global__ void __launch_bounds__(kBinBlock) k_bin_count(InstParams p0, const In
             gbase = atomicAdd(&cnt[tile], __popcll(mine));
     }
     __syncthreads();
-    if (threadIdx.x < kBinKeys && s_key[threadIdx.x] >= 0)
-        s_base[threadIdx.x] = atomicAdd(&cnt[s_key[threadIdx.x]], s_cnt[threadIdx.x]);
+    for (int e = threadIdx.x; e < kBinKeys; e += kBinBlock)
+        if (s_key[e] >= 0) s_base[e] = atomicAdd(&cnt[s_key[e]], s_cnt[e]);
     __syncthreads();
     int base = 0;
     if (lead) base = slot >= 0 ? s_base[slot] + off : gbase;

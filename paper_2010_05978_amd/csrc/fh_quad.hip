@@ -350,11 +350,18 @@ __global__ void k_petals(PetalParams pp, const double* __restrict__ glm, const d
     const double A = Atab ? Atab[l] : exp(-pow((r - pp.a) / pp.b, pp.p));
     double dp = 0.0, dm = 0.0;
     if (coef) {
+        // sin(s theta), s = 1..K, by the three-term recurrence
+        // sin((s+1) theta) = 2 cos(theta) sin(s theta) - sin((s-1) theta)
         const double* cp = coef + 2 * (int64_t)k * pp.K;
+        double s1, c1;
+        sincospi((r - pp.a) / L, &s1, &c1);
+        double sm = 0.0, sk = s1;
         for (int s = 1; s <= pp.K; ++s) {
-            const double sk = sin(s * kPi * (r - pp.a) / L);
             dp += cp[s - 1] * sk;
             dm += cp[pp.K + s - 1] * sk;
+            const double sn = 2.0 * c1 * sk - sm;
+            sm = sk;
+            sk = sn;
         }
     }
     const double mid = (dp - dm) / (2.0 * r);
@@ -400,7 +407,18 @@ __global__ void k_ribbons(RibbonParams rp, const double* __restrict__ glm, const
     const double wr = 0.5 * L * glm[rp.m + l];
     const double* cp = coef + (2 * (int64_t)k + e) * rp.K;
     double d = 0.0;
-    for (int s = 1; s <= rp.K; ++s) d += cp[s - 1] * sin(s * kPi * (r - rp.a) / L);
+    {
+        // sin(s theta) by the three-term recurrence, as in k_petals
+        double s1, c1;
+        sincospi((r - rp.a) / L, &s1, &c1);
+        double sm = 0.0, sk = s1;
+        for (int s = 1; s <= rp.K; ++s) {
+            d += cp[s - 1] * sk;
+            const double sn = 2.0 * c1 * sk - sm;
+            sm = sk;
+            sk = sn;
+        }
+    }
     const double sg = e == 0 ? 1.0 : -1.0;
     const double A = exp(-pow((r - rp.a) / rp.b, rp.p));
     const double phi = 2.0 * kPi * k / rp.Np + sg * (kPi * A / rp.Np + glt[i] * d / r);

@@ -133,6 +133,61 @@ def test_autograd_starshade_gradient_vs_direct_sum(ctx):
     assert errg <= TOL[ctx.precision]
 
 
+def test_wavelength_sweep_gradient(ctx):
+    """The sweep form (rule built once, one batched forward over the three
+    wavelengths, node gradients summed over them in one call and chained
+    once) against the oracle's direct-sum gradient and against the
+    per-wavelength form."""
+    from paper_2010_05978_amd.autograd import starshade_sweep
+    wl = workloads.workload(5, reduced=True)
+    mask = workloads.pupil_mask(wl.grid.n1)
+    rdt = torch.float64 if ctx.precision == "fp64" else torch.float32
+    mask_t = torch.tensor(mask, dtype=rdt, device="cuda")
+    Min = int(mask_t.sum())
+    nl = len(wl.lams)
+    coef = torch.tensor(wl.shape.coef, dtype=torch.float64, device="cuda", requires_grad=True)
+    u = starshade_sweep(coef, ctx, wl.shape, wl.lams, wl.z, wl.grid, occulter=True)
+    assert u.shape == (nl, wl.grid.n2, wl.grid.n1)
+    L = ((u.abs() ** 2).reshape(nl, -1) * mask_t.reshape(1, -1)).sum() / (nl * Min)
+    L.backward()
+    g_sweep = cpu(coef.grad)
+    Lref, gref, kappa = _oracle_loss_and_grad(wl, mask)
+    errL = abs(float(L) - Lref) / Lref
+    errg = relL2(g_sweep, gref)
+    print(f"sweep {ctx.precision}: loss rel {errL:.2e}, grad rel L2 {errg:.2e} (kappa {kappa:.1f})", flush=True)
+    assert errL <= TOL[ctx.precision]
+    assert errg <= TOL[ctx.precision]
+    coef2 = torch.tensor(wl.shape.coef, dtype=torch.float64, device="cuda", requires_grad=True)
+    _gpu_loss(ctx, wl, coef2, mask_t).backward()
+    d = relL2(g_sweep, cpu(coef2.grad))
+    print(f"  sweep vs per-wavelength form: {d:.2e}", flush=True)
+    assert d <= (1e-12 if ctx.precision == "fp64" else 1e-6)
+
+
+def test_vjp_sum_is_the_sum_of_vjps(ctx):
+    wl = workloads.workload(5, reduced=True)
+    s = wl.shape
+    q = ctx.quad_starshade(s.Np, s.a, s.R, s.b, s.p, s.m, s.np_, s.nd, s.md, s.coef, s.K)
+    g = wl.grid
+    rng = np.random.Generator(np.random.PCG64(23))
+    nl = len(wl.lams)
+    gu_np = rng.standard_normal((nl, g.n2, g.n1)) + 1j * rng.standard_normal((nl, g.n2, g.n1))
+    gu = torch.tensor(gu_np, dtype=ctx.cdtype, device="cuda")
+    zs = np.full(nl, wl.z)
+    sx, sy, sw = ctx.field_grid_vjp_sum(q, wl.lams, zs, g.n1, g.n2, g.h1, g.h2, gu, occulter=True)
+    acc = [np.zeros(q.N) for _ in range(3)]
+    for l in range(nl):
+        parts = ctx.field_grid_vjp(q, wl.lams[l], wl.z, g.n1, g.n2, g.h1, g.h2, gu[l].contiguous(), occulter=True)
+        for a, p in zip(acc, parts):
+            a += cpu(p)
+    for got, ref in zip((sx, sy, sw), acc):
+        e = relL2(cpu(got), ref)
+        assert e <= 1e-14 if ctx.precision == "fp64" else e <= 1e-6, e
+    with pytest.raises(Exception):
+        ctx.field_grid_vjp_sum(q, wl.lams, zs[:1], g.n1, g.n2, g.h1, g.h2, gu)
+    q.close()
+
+
 def test_finite_differences(fh):
     """Central differences of the FP64 GPU loss against the adjoint, on 32
     seeded coefficients and one seeded random direction of all 384.  The bar
