@@ -65,6 +65,24 @@ def build_native(directory: str) -> str:
     return path
 
 
+def build_sanitized(directory: str) -> str:
+    """Compile an AddressSanitizer + UndefinedBehaviorSanitizer copy of the
+    oracle (gcc -O1 -g, no OpenMP, any report aborts) into `directory` and
+    use it for every later call of this module.  A process that loads it
+    needs the ASan runtime preloaded (its path: gcc -print-file-name=libasan.so)."""
+    global _lib, _LIB
+    os.makedirs(directory, exist_ok=True)
+    path = os.path.join(directory, "libfresnel_oracle_san.so")
+    tmp = path + ".tmp"
+    cmd = ["gcc", "-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+           "-fno-sanitize-recover=all", "-fPIC", "-shared", "-std=c99", "-D_GNU_SOURCE", _SRC, "-o", tmp, "-lm"]
+    subprocess.check_call(cmd, stderr=subprocess.DEVNULL)
+    os.replace(tmp, path)
+    _LIB = path
+    _lib = None
+    return path
+
+
 _lib = None
 
 
