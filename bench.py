@@ -60,6 +60,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the headline oracle sample")
     ap.add_argument("--only", choices=["fp64", "mixed"], default=None, help="time one precision only")
+    ap.add_argument("--tune-cache", default=None,
+                    help="JSON-lines cache of the batch autotuner (a later run with the same file skips the tuning)")
     ap.add_argument("--pmc-calib", action="store_true",
                     help="also run a plain 256 MiB device copy (counter calibration for rocprofv3 --pmc)")
     ap.add_argument("--parts", default=ALL_PARTS,
@@ -111,12 +113,13 @@ class Batch:
         self.out = torch.empty((self.B, self.g.n2, self.g.n1), dtype=self.ctx.cdtype, device="cuda")
         self.tuned = None
 
-    def tune(self):
+    def tune(self, cache=None):
         """Options of the batched call from the batch autotuner (graph replays
-        of this batch over methods, tiles, item sizes and sigma)."""
+        of this batch over methods, tiles, item sizes and sigma), or from its
+        cache file when that holds this batch's signature."""
         g = self.g
         t0 = time.perf_counter()
-        o = self.ctx.autotune_batch(self.quads, self.lams, self.zs, g.n1, g.n2, g.h1, g.h2)
+        o = self.ctx.autotune_batch(self.quads, self.lams, self.zs, g.n1, g.n2, g.h1, g.h2, cache_path=cache)
         self.tuned = {"sigma": o.sigma, "tile": o.tile, "max_subproblem": o.max_subproblem,
                       "spread_method": o.spread_method, "tuning_s": time.perf_counter() - t0}
         return self.tuned
@@ -172,13 +175,13 @@ def spread_name(prec, W, method=5, tile=0):
     return f"k_spread_wave<{real}, {W}, {'true' if method == 3 else 'false'}, {nv}>"
 
 
-def batch_leg(fh, prec, steps, warmup, ceilings):
+def batch_leg(fh, prec, steps, warmup, ceilings, tune_cache=None):
     """Throughput of the batched call, the same steps with the rules built in
     each, and the spread's average launch time from HIP events on the
     library's stream (timing on: the batch then runs eagerly, stage [1]
     brackets the spread kernel alone)."""
     b = Batch(fh, prec)
-    tuned = b.tune()
+    tuned = b.tune(tune_cache)
     ms = cuda_ms(b.field, steps, warmup)
     ms_rules = cuda_ms(b.field_rebuild, steps, warmup)
     ms_api = cuda_ms(b.with_rules_api, max(3, steps // 4), 1)
@@ -786,7 +789,7 @@ def main():
            "warmup": args.warmup, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f64" if precs[0] == "fp64" else "c64-f64phase", "data": "synthetic"}
     if "batch" in parts:
-        res = {p: batch_leg(fh, p, args.steps, args.warmup, ceilings) for p in precs}
+        res = {p: batch_leg(fh, p, args.steps, args.warmup, ceilings, args.tune_cache) for p in precs}
         r = res[precs[0]]
         out.update({
             "value": r["value"], "ms_per_step": r["ms_per_call"],
