@@ -227,3 +227,35 @@ def test_autotune_batch_keeps_accuracy_flags_and_caches(ctx, fh, tmp_path):
     ctx.set_options(None)
     for q in quads:
         q.close()
+
+
+def test_batch_with_empty_and_single_node_instances(ctx):
+    """Ragged batches: an instance with no nodes (u_ap = 0, u_oc = 1) and one
+    with a single node (a closed form) between ordinary ones, captured and
+    replayed."""
+    shapes, lams, zs, occ, g = _batch_inputs(count=2)
+    quads = [ctx.quad_for(s) for s in shapes]
+    empty = ctx.quad_from_nodes(np.zeros(0), np.zeros(0), np.zeros(0))
+    x0, y0, w0 = 0.013, -0.021, 0.7
+    one = ctx.quad_from_nodes(np.array([x0]), np.array([y0]), np.array([w0]))
+    qs = [quads[0], empty, one, quads[1], empty]
+    la = np.array([lams[0], lams[1], 0.9e-6, lams[1], 0.7e-6])
+    za = np.full(5, workloads.BATCH_Z)
+    oc = np.array([0, 1, 0, 1, 0], dtype=np.int32)
+    xi, eta = oracle.grid_targets(g.n1, g.n2, g.h1, g.h2)
+    out = torch.empty((5, g.n2, g.n1), dtype=ctx.cdtype, device="cuda")
+    for rep in range(3):
+        u = cpu(ctx.field_grid_batch(qs, la, za, g.n1, g.n2, g.h1, g.h2, occulter=oc, out=out))
+        assert np.all(u[1] == 1) and np.all(u[4] == 0), rep
+        lz = la[2] * za[2]
+        ref1 = np.exp(1j * np.pi * ((xi - x0) ** 2 + (eta - y0) ** 2) / lz) * w0 / (1j * lz)
+        assert relL2(u[2].ravel(), ref1) <= TOL[ctx.precision], rep
+        for b, s in ((0, shapes[0]), (3, shapes[1])):
+            x, y, w = oracle_quad(s)
+            idx = np.random.Generator(np.random.PCG64(70 + b)).choice(g.M, 200, replace=False)
+            ref = oracle.fresnel_direct(x, y, w, la[b], za[b], xi[idx], eta[idx])
+            got = u[b].ravel()[idx]
+            got = 1 - got if oc[b] else got
+            assert relL2(got, ref) <= TOL[ctx.precision], (rep, b)
+    for q in quads + [empty, one]:
+        q.close()
