@@ -211,18 +211,20 @@ fh_status t1_pipeline(fh_ctx* c, int B, const fh_quad* const* qs, const double* 
     std::vector<EpiInst> epi(B);
     int64_t Ntot = 0;
     int max_span = 0;
+    std::vector<int> spans(B, 0);
     for (int b = 0; b < B; ++b) {
         inst[b] = inst_t1(qs[b], lambda[b], z[b], h1, h2, xc, yc, gg);
         inst[b].node_off = Ntot;
         Ntot += qs[b]->N;
         const double lz = lambda[b] * z[b];
-        epi[b] = EpiInst{0.5 / lz, 1.0 / lz, occ[b] ? 1 : 0, 0};
+        epi[b] = EpiInst{0.5 / lz, 1.0 / lz, occ[b] ? 1 : 0, 0, 0, 0};
         if (qs[b]->N > 0) {
             double bb[4];
             FH_TRY(quad_bbox(c, qs[b], bb));
             int lo, span;
             window_rows(bb, inst[b].s2, gg.W, lo, span);
             inst[b].sh2 = lo;
+            spans[b] = span;
             max_span = std::max(max_span, span);
         }
     }
@@ -245,6 +247,8 @@ fh_status t1_pipeline(fh_ctx* c, int B, const fh_quad* const* qs, const double* 
     for (int b = 0; b < B; ++b) {
         inst[b].tile_off = b * tpi;
         epi[b].sh2 = inst[b].sh2;
+        epi[b].rows = gg.rows;
+        epi[b].roff = b * gg.rows;
     }
     FH_ARG((int64_t)tpi * B < ((int64_t)1 << 31), FH_ERR_UNSUPPORTED, "too many tiles");
     const double* ip1 = nullptr;
@@ -267,16 +271,36 @@ fh_status t1_pipeline(fh_ctx* c, int B, const fh_quad* const* qs, const double* 
     if (lc.C > 0 && reach == 1 && (int64_t)gg.rows * B >= 16 * (int64_t)c->cu_count)
         lr = lds_cols_plan(c, gg.nf1, (int64_t)gg.rows * B, rs, 1);
     const bool fused = lr.C > 0 && t1_rows_lds(lr, gg, reach, rs) <= kLdsFftBytes;
-    if (!fused) FH_TRY(fft_plan(c, gg.nf1, 0, gg.rows * B, &fa));
+    // A batch of windowed instances on the stored grid holds each instance's
+    // own rows (its span rounded up to whole tiles), one after another: the
+    // zero fill, the row transforms and the column pass's loads then cover
+    // only those; the tiles stay those of the tallest window.
+    const bool ragged = B > 1 && !gg.wrap_y && !fused && lc.C > 0;
+    std::vector<int2> rwin;
+    int64_t total_rows = (int64_t)B * gg.rows;
+    if (ragged) {
+        rwin.resize(B);
+        total_rows = 0;
+        for (int b = 0; b < B; ++b) {
+            const int rb = std::min(gg.rows, (spans[b] + gg.T - 1) / gg.T * gg.T);
+            rwin[b] = make_int2(rb, (int)total_rows);
+            epi[b].rows = rb;
+            epi[b].roff = (int)total_rows;
+            total_rows += rb;
+        }
+        FH_ARG(total_rows * gg.nf1 < ((int64_t)1 << 40), FH_ERR_UNSUPPORTED, "fine grid too large");
+    }
+    if (!fused) FH_TRY(fft_plan(c, gg.nf1, 0, (int)std::max<int64_t>(total_rows, 1), &fa));
     if (lc.C == 0) FH_TRY(fft_plan(c, gg.nf2, 0, n1 * B, &fb));
 
     FH_TRY(counters_ready(c, (int64_t)tpi * B));
-    const size_t F_count = 2 * (size_t)B * gg.rows * (fused ? n1 : gg.nf1);
+    const size_t F_count = 2 * (size_t)std::max<int64_t>(total_rows, 1) * (fused ? n1 : gg.nf1);
     const size_t Z_count = lc.C > 0 ? 0 : 2 * (size_t)B * n1 * gg.nf2;
     const size_t E2_bytes = lc.C > 0 ? aligned_bytes(sizeof(double2) * (size_t)B * n2) : 0;
     size_t need = aligned_bytes(rs * F_count) + aligned_bytes(rs * Z_count) + E2_bytes +
                   spread_bytes(c, Ntot, gg, tpi * B, rs) + aligned_bytes(sizeof(InstParams) * B) +
-                  aligned_bytes(sizeof(EpiInst) * B) + aligned_bytes(extra_bytes);
+                  aligned_bytes(sizeof(EpiInst) * B) + aligned_bytes(sizeof(int2) * B) +
+                  aligned_bytes(extra_bytes);
     FH_TRY(arena_reserve(c, need));
     R* F = c->arena.take<R>(F_count);
     R* Z = c->arena.take<R>(Z_count);
@@ -284,12 +308,15 @@ fh_status t1_pipeline(fh_ctx* c, int B, const fh_quad* const* qs, const double* 
     SpreadBufs sb = spread_carve(c, Ntot, gg, tpi * B, rs);
     InstParams* dinst = c->arena.take<InstParams>(B);
     EpiInst* depi = c->arena.take<EpiInst>(B);
+    int2* drwin = c->arena.take<int2>(B);
     if (extra) *extra = c->arena.take<char>(extra_bytes);
     if (!u) u = static_cast<R*>(*extra);
     const bool batched = B > 1;
     if (batched) {
         FH_HIP(hipMemcpyAsync(dinst, inst.data(), sizeof(InstParams) * B, hipMemcpyHostToDevice, c->stream));
         FH_HIP(hipMemcpyAsync(depi, epi.data(), sizeof(EpiInst) * B, hipMemcpyHostToDevice, c->stream));
+        if (ragged)
+            FH_HIP(hipMemcpyAsync(drwin, rwin.data(), sizeof(int2) * B, hipMemcpyHostToDevice, c->stream));
     }
 
     auto run = [&]() -> fh_status {
@@ -301,8 +328,9 @@ fh_status t1_pipeline(fh_ctx* c, int B, const fh_quad* const* qs, const double* 
             FH_TRY(launch_t1_rows<R>(c, lr, reach, B, (gg.rows + lr.C - 1) / lr.C, gg, sb, n1, F));
             c->tile_cnt_dirty = false;
         } else {
-            FH_TRY(run_spread<R>(c, inst[0], batched ? dinst : nullptr, B, Ntot, gg, sb, F, pl.k.beta, pl.k.poly));
-            FH_TRY(fft_exec(c, fa, F));
+            FH_TRY(run_spread<R>(c, inst[0], batched ? dinst : nullptr, B, Ntot, gg, sb, F, pl.k.beta, pl.k.poly,
+                                 ragged ? (const int2*)drwin : nullptr, total_rows));
+            if (total_rows > 0) FH_TRY(fft_exec(c, fa, F));
         }
         EpiParams ep{n1, n2, gg.nf1, gg.nf2, h1, h2, xc, yc, ip1, ip2};
         if (lc.C > 0) {
@@ -338,9 +366,9 @@ fh_status t1_pipeline(fh_ctx* c, int B, const fh_quad* const* qs, const double* 
 
     // graph key: every pointer and size baked into the launches
     char key[512];
-    snprintf(key, sizeof(key), "%p|%zu|%d|%lld|%d|%d|%d|%d|%d|%d|%a|%a|%a|%a|%d|%d|%d|%p|%p|%d",
+    snprintf(key, sizeof(key), "%p|%zu|%d|%lld|%d|%d|%d|%d|%d|%d|%a|%a|%a|%a|%d|%d|%d|%p|%p|%d|%lld",
              (void*)c->arena.base, c->arena.cap, B, (long long)Ntot, n1, n2, gg.nf1, gg.nf2, gg.W, gg.rows, h1, h2,
-             xc, yc, gg.T, gg.P, gg.method, (void*)u, (void*)c->tile_cnt, rebuild ? 1 : 0);
+             xc, yc, gg.T, gg.P, gg.method, (void*)u, (void*)c->tile_cnt, rebuild ? 1 : 0, (long long)total_rows);
     std::string k2(key);
     for (int b = 0; b < B; ++b) k2 += "|" + std::to_string(qs[b]->N);
     // Graphs are captured and replayed on a private stream (the caller's may

@@ -1195,10 +1195,18 @@ __global__ void __launch_bounds__(256) k_merge_slots(typename V2<R>::T* __restri
 // rather than two per covering tile.  REACH = (L - 1)/T; KC cells per thread.
 constexpr int kRedU = 2;
 
+// Rows held for instance b and its first row in F: its own window when the
+// batch holds ragged windows (rwin), else gg.rows each, one after another.
+__device__ __forceinline__ int2 inst_rows(const int2* __restrict__ rwin, const GridGeom& gg, int b)
+{
+    return rwin ? rwin[b] : make_int2(gg.rows, b * gg.rows);
+}
+
 template <class R, int REACH, int KC>
 __global__ void __launch_bounds__(256) k_reduce_tiles(const typename V2<R>::T* __restrict__ slots,
                                                       const int* __restrict__ tsub, GridGeom gg, int tpi,
-                                                      int ntiles_total, R* __restrict__ F, int* __restrict__ cnt)
+                                                      int ntiles_total, R* __restrict__ F, int* __restrict__ cnt,
+                                                      const int2* __restrict__ rwin)
 {
     using C = typename V2<R>::T;
     constexpr int NC = (REACH + 1) * (REACH + 1);  // covering tiles
@@ -1221,8 +1229,10 @@ __global__ void __launch_bounds__(256) k_reduce_tiles(const typename V2<R>::T* _
         const int b = tile / tpi, tl = tile - b * tpi;
         const int ty = tl / gg.ntx, tx = tl - ty * gg.ntx;
         // cells of this tile inside the grid (the last tile of a row or
-        // column may be partial)
-        const int wx = min(T, gg.nf1 - tx * T), wy = min(T, gg.rows - ty * T);
+        // column may be partial; an instance may hold fewer rows)
+        const int2 rw = inst_rows(rwin, gg, b);
+        const int wx = min(T, gg.nf1 - tx * T), wy = min(T, rw.x - ty * T);
+        if (wy <= 0) continue;
         // covering tile i = (dy, dx): its first merged slot, slot stride
         // and number of merged slots (0 where no tile reaches), and the
         // shift of its padded cells when it wraps around the period
@@ -1246,7 +1256,7 @@ __global__ void __launch_bounds__(256) k_reduce_tiles(const typename V2<R>::T* _
             heads[i] = (n + st - 1) / st;
             any = any || n > 0;
         }
-        C* out = Fv + ((size_t)b * gg.rows + (size_t)ty * T) * gg.nf1 + (size_t)tx * T;
+        C* out = Fv + ((size_t)rw.y + (size_t)ty * T) * gg.nf1 + (size_t)tx * T;
         if (!any) {
             for (int e = threadIdx.x; e < TT; e += blockDim.x)
                 if (e % T < wx && e / T < wy) out[(size_t)(e / T) * gg.nf1 + e % T] = C{R(0), R(0)};
@@ -1430,7 +1440,7 @@ template <class R, int REACH>
 __global__ void __launch_bounds__(256) k_reduce_list(const typename V2<R>::T* __restrict__ slots,
                                                      const int* __restrict__ tsub, const int* __restrict__ list,
                                                      const int* __restrict__ nlist, GridGeom gg, int tpi,
-                                                     R* __restrict__ F)
+                                                     R* __restrict__ F, const int2* __restrict__ rwin)
 {
     using C = typename V2<R>::T;
     const int T = gg.T, TT = T * T;
@@ -1442,8 +1452,9 @@ __global__ void __launch_bounds__(256) k_reduce_list(const typename V2<R>::T* __
         const int b = tile / tpi, tl = tile - b * tpi;
         const int ty = tl / gg.ntx, tx = tl - ty * gg.ntx;
         const int cj = c / T, ci = c - cj * T;
-        if (tx * T + ci >= gg.nf1 || ty * T + cj >= gg.rows) continue;
-        reinterpret_cast<C*>(F)[((size_t)b * gg.rows + ty * T + cj) * gg.nf1 + tx * T + ci] =
+        const int2 rw = inst_rows(rwin, gg, b);
+        if (tx * T + ci >= gg.nf1 || ty * T + cj >= rw.x) continue;
+        reinterpret_cast<C*>(F)[((size_t)rw.y + ty * T + cj) * gg.nf1 + tx * T + ci] =
             reduce_cell<R, REACH>(slots, gg, tx, ty, ci, cj, TsubHead{tsub, b * tpi, gg.ntx, gg.nty});
     }
 }
@@ -1539,6 +1550,8 @@ struct EpiInst {
     double invlz;   // 1/(lambda z)
     int occ;
     int sh2;        // row shift of the instance's window
+    int rows;       // rows held for the instance (its window)
+    int roff;       // its first row in the band array
 };
 
 struct EpiParams {
@@ -1719,13 +1732,14 @@ __global__ void __launch_bounds__(NT) k_t1_cols(const R* __restrict__ F, R* __re
         E1[threadIdx.x] = f;
     }
     // band of the C columns (adjacent lanes read adjacent columns of a row)
-    const C2* Fv = reinterpret_cast<const C2*>(F) + (size_t)b * rows * ldf;
+    const C2* Fv = reinterpret_cast<const C2*>(F) + (size_t)ei.roff * ldf;
+    const int rb = min(ei.rows, rows);
     for (int e = threadIdx.x; e < C * nf2; e += NT) {
         const int r = e / C, c = e - r * C;
         C2 v;
         v.x = R(0);
         v.y = R(0);
-        if (r < rows && c < ncol) {
+        if (r < rb && c < ncol) {
             int col = col0 + c;
             if (!compact) {
                 col -= ep.n1 / 2;
@@ -2381,10 +2395,14 @@ fh_status spread_items(fh_ctx* c, const InstParams& p0, const InstParams* table,
     return FH_OK;
 }
 
-// Reduce the merged slots into F (B instances x rows x nf1).
+// Reduce the merged slots into F: B instances x rows x nf1, or with rwin
+// (device, one (rows, first row) per instance) each instance's own rows one
+// after another, total_rows in all.
 template <class R>
-fh_status reduce_grid(fh_ctx* c, int ninst, const GridGeom& gg, const SpreadBufs& b, R* F)
+fh_status reduce_grid(fh_ctx* c, int ninst, const GridGeom& gg, const SpreadBufs& b, R* F,
+                      const int2* rwin = nullptr, int64_t total_rows = -1)
 {
+    if (total_rows < 0) total_rows = (int64_t)ninst * gg.rows;
     const int tpi = gg.ntx * gg.nty;
     const int ntiles_total = tpi * ninst;
     const unsigned rgrid = (unsigned)std::max<int64_t>(
@@ -2396,14 +2414,14 @@ fh_status reduce_grid(fh_ctx* c, int ninst, const GridGeom& gg, const SpreadBufs
            "tile %d with width %d", gg.T, gg.W);
 #define FH_REDUCE(RE, K)                                                                                     \
     hipLaunchKernelGGL((k_reduce_tiles<R, RE, K>), dim3(rgrid), dim3(rthreads), 0, c->stream,                \
-                       (const typename V2<R>::T*)b.slots, b.tsub, gg, tpi, ntiles_total, F, b.cnt)
+                       (const typename V2<R>::T*)b.slots, b.tsub, gg, tpi, ntiles_total, F, b.cnt, rwin)
 #define FH_REDUCE_CELLS(RE)                                                                                  \
     do {                                                                                                     \
         hipLaunchKernelGGL((k_tile_active<RE>), dim3(nblocks(ntiles_total, 256)), dim3(256), 0, c->stream,   \
                            b.tsub, gg, tpi, ntiles_total, b.list, b.nlist, b.cnt);                           \
         hipLaunchKernelGGL((k_reduce_list<R, RE>), dim3(lgrid), dim3(256), 0, c->stream,                      \
                            (const typename V2<R>::T*)b.slots, b.tsub, (const int*)b.list, (const int*)b.nlist, \
-                           gg, tpi, F);                                                                      \
+                           gg, tpi, F, rwin);                                                                \
     } while (0)
     // Tiles under 128 cells (the matrix-core spread's), and grids of 4M
     // cells or more (mostly empty in a batch), are reduced from the list of
@@ -2413,7 +2431,7 @@ fh_status reduce_grid(fh_ctx* c, int ninst, const GridGeom& gg, const SpreadBufs
     const bool by_cell = TT < 128 || (int64_t)ntiles_total * TT >= ((int64_t)1 << 22);
     const unsigned lgrid = (unsigned)std::max<int64_t>(
         1, std::min<int64_t>((int64_t)c->cu_count * 8, ((int64_t)ntiles_total * TT + 255) / 256));
-    if (by_cell) FH_TRY(launch_zero(c, F, 2 * sizeof(R) * (size_t)ninst * gg.rows * gg.nf1));
+    if (by_cell) FH_TRY(launch_zero(c, F, 2 * sizeof(R) * (size_t)total_rows * gg.nf1));
     if (by_cell) {
         if (reach == 1) FH_REDUCE_CELLS(1);
         else FH_REDUCE_CELLS(2);
@@ -2431,13 +2449,14 @@ fh_status reduce_grid(fh_ctx* c, int ninst, const GridGeom& gg, const SpreadBufs
     return FH_OK;
 }
 
-// Bin, spread into slots, and reduce into F (B instances x rows x nf1).
+// Bin, spread into slots, and reduce into F (as reduce_grid).
 template <class R>
 fh_status run_spread(fh_ctx* c, const InstParams& p0, const InstParams* table, int ninst, int64_t Ntot,
-                     const GridGeom& gg, const SpreadBufs& b, R* F, double beta, const void* poly)
+                     const GridGeom& gg, const SpreadBufs& b, R* F, double beta, const void* poly,
+                     const int2* rwin = nullptr, int64_t total_rows = -1)
 {
     FH_TRY(spread_items<R>(c, p0, table, ninst, Ntot, gg, b, beta, poly));
-    return reduce_grid<R>(c, ninst, gg, b, F);
+    return reduce_grid<R>(c, ninst, gg, b, F, rwin, total_rows);
 }
 
 fh_status check_lz(double lambda, double z)
