@@ -1734,12 +1734,13 @@ __global__ void __launch_bounds__(NT) k_t1_cols(const R* __restrict__ F, R* __re
     // band of the C columns (adjacent lanes read adjacent columns of a row)
     const C2* Fv = reinterpret_cast<const C2*>(F) + (size_t)ei.roff * ldf;
     const int rb = min(ei.rows, rows);
-    for (int e = threadIdx.x; e < C * nf2; e += NT) {
-        const int r = e / C, c = e - r * C;
+    const FastDiv dC = fast_div((unsigned)C);
+    for (int e = threadIdx.x; e < C * rb; e += NT) {
+        const int r = (int)fdiv((unsigned)e, dC), c = e - r * C;
         C2 v;
         v.x = R(0);
         v.y = R(0);
-        if (r < rb && c < ncol) {
+        if (c < ncol) {
             int col = col0 + c;
             if (!compact) {
                 col -= ep.n1 / 2;
@@ -1749,6 +1750,18 @@ __global__ void __launch_bounds__(NT) k_t1_cols(const R* __restrict__ F, R* __re
         }
         buf[c * nf2 + r] = v;
     }
+    // the zero padding below the band, column by column
+    const int nz = nf2 - rb;
+    if (nz > 0) {
+        const FastDiv dz = fast_div((unsigned)nz);
+        for (int e = threadIdx.x; e < C * nz; e += NT) {
+            const int c = (int)fdiv((unsigned)e, dz);
+            C2 v;
+            v.x = R(0);
+            v.y = R(0);
+            buf[c * nf2 + rb + (e - c * nz)] = v;
+        }
+    }
     __syncthreads();
     lds_fft<MAXE, NT, R7>(buf, plan, C, buf + (size_t)C * plan.n);
     // epilogue: C lanes write C consecutive outputs of a row, with the row
@@ -1756,7 +1769,7 @@ __global__ void __launch_bounds__(NT) k_t1_cols(const R* __restrict__ F, R* __re
     const double2* E2 = E2all + (size_t)b * ep.n2;
     C2* uv = reinterpret_cast<C2*>(u) + (size_t)b * ep.n2 * ep.n1;
     for (int e = threadIdx.x; e < ep.n2 * C; e += NT) {
-        const int k2i = e / C, c = e - k2i * C;
+        const int k2i = (int)fdiv((unsigned)e, dC), c = e - k2i * C;
         if (c >= ncol) continue;
         const int k2 = k2i - ep.n2 / 2;
         const int r = k2 < 0 ? k2 + nf2 : k2;
