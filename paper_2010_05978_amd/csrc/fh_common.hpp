@@ -67,10 +67,17 @@ struct EsKernel {
 };
 
 // The kernel on one stencil is evaluated as w polynomials of degree
-// w + kPolyExtra - 1 in t = 2 d + w - 1, d in [-w/2, -w/2 + 1) the offset of
+// poly_np(w) - 1 in t = 2 d + w - 1, d in [-w/2, -w/2 + 1) the offset of
 // the first stencil cell: poly[j * w + a] is the coefficient of t^(deg - j)
 // for stencil index a, in the working precision.
-constexpr int kPolyExtra = 4;
+// poly_np(w) is the fewest coefficients whose Chebyshev interpolants come
+// within a quarter of the error floor that the square-root branch point of
+// phi at the stencil edges puts under every degree (near e^-beta / 2): more
+// only cost arithmetic.  From width 14 on the floor is rounding.
+__host__ __device__ constexpr int poly_np(int w)
+{
+    return w <= 3 ? 6 : w <= 5 ? 7 : w <= 8 ? w + 2 : w <= 11 ? 11 : w == 12 ? 13 : w + 2;
+}
 
 // Wavefront spread staging: per point its 2w kernel values and its strength
 // (2 reals), for 64 points, and the kernel arguments of 64 points for each of

@@ -213,7 +213,7 @@ void es_poly_attach(fh_ctx* c, EsKernel& k)
         k.poly = it->second;
         return;
     }
-    const int W = k.w, np = W + kPolyExtra, deg = np - 1;
+    const int W = k.w, np = poly_np(W), deg = np - 1;
     double eps = c->tol * 0.1;
     if (c->prec == FH_MIXED) eps = std::max(eps, 2e-8);
     const double tol_abs = std::max(eps / W, 1e-14);

@@ -99,7 +99,7 @@ template <class R, int W>
 __device__ __forceinline__ void es_weights(R d, R beta, const R* __restrict__ poly, R* k)
 {
     if (poly) {
-        constexpr int NP = W + kPolyExtra;
+        constexpr int NP = poly_np(W);
         const R t = R(2) * d + R(W - 1);
 #pragma unroll
         for (int a = 0; a < W; ++a) k[a] = poly[a];
@@ -127,7 +127,7 @@ template <class R, int W>
 __device__ __forceinline__ R es_one(R d, int a, R beta, const R* __restrict__ poly)
 {
     if (poly) {
-        constexpr int NP = W + kPolyExtra;
+        constexpr int NP = poly_np(W);
         const R t = R(2) * d + R(W - 1);
         R v = poly[a];
 #pragma unroll
@@ -590,7 +590,7 @@ __global__ void __launch_bounds__(64 * NV) k_spread_wave(const Sub* __restrict__
     constexpr int NPASS = (W * W + 63) / 64;  // stencil passes per point
     constexpr int U = sizeof(R) == 8 ? 4 : 8; // points per trip
     constexpr int QW = 64 / NV;               // points of a batch per wavefront
-    constexpr int NP = W + kPolyExtra;        // coefficients per kernel polynomial
+    constexpr int NP = poly_np(W);        // coefficients per kernel polynomial
     constexpr int KG = 64 / W;                // lane groups evaluating the kernel
     extern __shared__ unsigned char smem_raw[];
     const int L = gg.L, LL = L * L;
@@ -990,7 +990,7 @@ __global__ void __launch_bounds__(64 * kMfmaWaves) k_spread_mfma(const Sub* __re
     using C = typename V2<R>::T;
     using M = MfmaAcc<R>;
     using V = typename M::V;
-    constexpr int NP = W + kPolyExtra;  // coefficients per kernel polynomial
+    constexpr int NP = poly_np(W);  // coefficients per kernel polynomial
     constexpr int KG = 64 / W;          // lane groups evaluating kernel values
     static_assert(W <= 16 * NB, "the padded tile must fit the blocks");
     static_assert(MS % 16 == 0 && MS <= 64, "points are staged in sixteens, one per lane at most");
