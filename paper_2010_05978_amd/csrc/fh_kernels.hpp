@@ -40,23 +40,37 @@ __device__ __forceinline__ int find_inst(const InstParams* t, int n, int64_t j)
     return lo;
 }
 
-// Instance of node j for a block of consecutive nodes: one search for the
-// block's first and last node (thread 0, through LDS; the caller
-// synchronises), and a per-node search only when the block straddles
-// instances.
-__device__ __forceinline__ void block_inst_bounds(const InstParams* t, int n, int64_t Ntot, int* s_inst)
+// Instance of every kChunk-th node: chunk[c] = instance of node
+// min(c kChunk, Ntot - 1), for c = 0 .. ceil(Ntot / kChunk), written once per
+// call by k_chunk_inst.  A block of consecutive nodes [j0, j1] with j0 a
+// multiple of kChunk reads the instance of j0 and an upper bound, the
+// instance of node j1 + 1 (or of the last node): when the two agree every
+// node of the block lies in that instance, else a node searches between them.
+constexpr int kChunk = 256;
+
+__global__ void k_chunk_inst(const InstParams* __restrict__ t, int n, int64_t Ntot, int* __restrict__ chunk)
 {
-    if (threadIdx.x == 0) {
-        const int64_t j0 = blockIdx.x * (int64_t)blockDim.x;
-        const int64_t j1 = min(j0 + (int64_t)blockDim.x, Ntot) - 1;
-        s_inst[0] = find_inst(t, n, j0);
-        s_inst[1] = find_inst(t, n, max(j0, j1));
-    }
+    const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t nc = (Ntot + kChunk - 1) / kChunk;
+    if (c > nc) return;
+    chunk[c] = find_inst(t, n, min(c * kChunk, Ntot - 1));
 }
-__device__ __forceinline__ int node_inst(const InstParams* t, int n, int64_t j, const int* s_inst)
+
+__device__ __forceinline__ int2 block_inst_bounds(const int* __restrict__ chunk, int64_t Ntot)
 {
-    const int a = s_inst[0], b = s_inst[1];
-    return a == b ? __builtin_amdgcn_readfirstlane(a) : find_inst(t, n, j);
+    const int64_t j0 = blockIdx.x * (int64_t)blockDim.x;
+    const int64_t j1 = min(j0 + (int64_t)blockDim.x, Ntot) - 1;
+    return make_int2(chunk[j0 / kChunk], chunk[(j1 + kChunk) / kChunk]);
+}
+__device__ __forceinline__ int node_inst(const InstParams* t, int64_t j, int2 ab)
+{
+    if (ab.x == ab.y) return __builtin_amdgcn_readfirstlane(ab.x);
+    int lo = ab.x, hi = ab.y;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (t[mid].node_off <= j) lo = mid; else hi = mid - 1;
+    }
+    return lo;
 }
 
 // Fine-grid coordinate g -> first stencil cell (wrapped to [0, nf)) and the
@@ -203,25 +217,24 @@ constexpr int kBinKeys = 1 << kBinKeyBits;
 // With `key` (the stable binning), each node also writes its tile and its
 // index, the keys and values of the sort that then fixes the ranks.
 __global__ void __launch_bounds__(kBinBlock) k_bin_count(InstParams p0, const InstParams* __restrict__ table,
-                                                         int ninst, int64_t Ntot, GridGeom gg,
+                                                         const int* __restrict__ chunk, int64_t Ntot, GridGeom gg,
                                                          int* __restrict__ cnt, int* __restrict__ rank,
                                                          uint32_t* __restrict__ key, int* __restrict__ vals)
 {
     __shared__ int s_key[kBinKeys];
     __shared__ int s_cnt[kBinKeys];
     __shared__ int s_base[kBinKeys];
-    __shared__ int s_inst[2];
     for (int e = threadIdx.x; e < kBinKeys; e += kBinBlock) {
         s_key[e] = -1;
         s_cnt[e] = 0;
     }
-    if (table) block_inst_bounds(table, ninst, Ntot, s_inst);
+    const int2 ib = table ? block_inst_bounds(chunk, Ntot) : make_int2(0, 0);
     __syncthreads();
     const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     const bool valid = j < Ntot;
     int tile = 0;
     if (valid) {
-        const InstParams ip = table ? table[node_inst(table, ninst, j, s_inst)] : p0;
+        const InstParams ip = table ? table[node_inst(table, j, ib)] : p0;
         const int64_t jj = j - ip.node_off;
         int l1, l2;
         double d1, d2;
@@ -415,21 +428,16 @@ __global__ void k_rank_sorted(const uint32_t* __restrict__ key_sorted, const int
 // Strength (FP64 phase in turns, reduced, times the node's source term when
 // the rule has one), stencil offsets, and the sorted position of each node.
 template <class R>
-__global__ void __launch_bounds__(256) k_bin_place(InstParams p0, const InstParams* __restrict__ table, int ninst,
-                                                   int64_t Ntot, GridGeom gg, const int* __restrict__ cnt,
+__global__ void __launch_bounds__(256) k_bin_place(InstParams p0, const InstParams* __restrict__ table,
+                                                   const int* __restrict__ chunk, int64_t Ntot, GridGeom gg, const int* __restrict__ cnt,
                                                    const int* __restrict__ off, const int* __restrict__ tsub,
                                                    const int* __restrict__ rank, uint32_t* __restrict__ cell,
                                                    typename V2<R>::T* __restrict__ dd,
                                                    typename V2<R>::T* __restrict__ cc, Sub* __restrict__ subs)
 {
-    __shared__ int s_inst[2];
-    if (table) {
-        block_inst_bounds(table, ninst, Ntot, s_inst);
-        __syncthreads();
-    }
     const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (j >= Ntot) return;
-    const InstParams ip = table ? table[node_inst(table, ninst, j, s_inst)] : p0;
+    const InstParams ip = table ? table[node_inst(table, j, block_inst_bounds(chunk, Ntot))] : p0;
     const int64_t jj = j - ip.node_off;
     const double x = ip.x[jj], y = ip.y[jj];
     double w = ip.w[jj];
@@ -2276,6 +2284,7 @@ struct SpreadBufs {
     void* slots;    // one padded L x L complex tile per work item
     int* list;      // tiles some padded tile reaches (list reduce), and their count
     int* nlist;
+    int* chunk;     // instance of every kChunk-th node (batches)
     // stable binning only: tile keys and node indices, before and after the
     // sort, and the sort's scratch
     uint32_t* key;
@@ -2305,7 +2314,7 @@ size_t spread_bytes(const fh_ctx* c, int64_t Ntot, const GridGeom& gg, int ntile
            aligned_bytes(sizeof(int) * Ntot) + aligned_bytes(sizeof(uint32_t) * Ntot) +
            2 * aligned_bytes(2 * rsize * Ntot) + aligned_bytes(sizeof(Sub) * max_sub) + aligned_bytes(sizeof(int)) +
            aligned_bytes(2 * rsize * (size_t)gg.L * gg.L * max_sub) + aligned_bytes(sizeof(int) * (size_t)ntiles_total) +
-           aligned_bytes(sizeof(int));
+           aligned_bytes(sizeof(int)) + aligned_bytes(sizeof(int) * (size_t)(Ntot / kChunk + 2));
 }
 
 SpreadBufs spread_carve(fh_ctx* c, int64_t Ntot, const GridGeom& gg, int ntiles_total, size_t rsize)
@@ -2325,6 +2334,7 @@ SpreadBufs spread_carve(fh_ctx* c, int64_t Ntot, const GridGeom& gg, int ntiles_
     b.slots = c->arena.take<char>(2 * rsize * (size_t)gg.L * gg.L * b.max_sub);
     b.list = c->arena.take<int>((size_t)ntiles_total);
     b.nlist = c->arena.take<int>(1);
+    b.chunk = c->arena.take<int>((size_t)(Ntot / kChunk + 2));
     b.key = b.key_sorted = nullptr;
     b.vals = b.vals_sorted = nullptr;
     b.sort_tmp = nullptr;
@@ -2359,8 +2369,11 @@ fh_status spread_items(fh_ctx* c, const InstParams& p0, const InstParams* table,
     // zeroes them again; until it is enqueued they count as dirty
     c->tile_cnt_dirty = true;
     if (Ntot > 0) {
+        if (table)
+            hipLaunchKernelGGL(k_chunk_inst, dim3(nblocks(Ntot / kChunk + 2, 256)), dim3(256), 0, c->stream, table,
+                               ninst, Ntot, b.chunk);
         hipLaunchKernelGGL(k_bin_count, dim3(nblocks(Ntot, kBinBlock)), dim3(kBinBlock), 0, c->stream, p0, table,
-                           ninst, Ntot, gg, b.cnt, b.rank, b.key, b.vals);
+                           (const int*)b.chunk, Ntot, gg, b.cnt, b.rank, b.key, b.vals);
         if (b.key) {
             int bits = 1;
             while (bits < 32 && ((int64_t)1 << bits) < ntiles_total) ++bits;
@@ -2377,8 +2390,8 @@ fh_status spread_items(fh_ctx* c, const InstParams& p0, const InstParams* table,
         hipLaunchKernelGGL(k_rank_sorted, dim3(nblocks(Ntot, 256)), dim3(256), 0, c->stream, b.key_sorted,
                            b.vals_sorted, Ntot, b.off, b.rank);
     if (Ntot > 0) {
-        hipLaunchKernelGGL((k_bin_place<R>), dim3(nblocks(Ntot, 256)), dim3(256), 0, c->stream, p0, table, ninst,
-                           Ntot, gg, b.cnt, b.off, b.tsub, b.rank, b.cell, (typename V2<R>::T*)b.dd,
+        hipLaunchKernelGGL((k_bin_place<R>), dim3(nblocks(Ntot, 256)), dim3(256), 0, c->stream, p0, table,
+                           (const int*)b.chunk, Ntot, gg, b.cnt, b.off, b.tsub, b.rank, b.cell, (typename V2<R>::T*)b.dd,
                            (typename V2<R>::T*)b.cc, b.subs);
     }
     FH_HIP(hipGetLastError());
