@@ -128,8 +128,9 @@ LdsCols lds_cols_plan(fh_ctx* c, int n, int64_t count, size_t rs, int min_c = 0)
     C = std::min({C, cap, 16});
     // but keep at least two workgroups per CU where the count allows
     while (C > 1 && count / C < 2 * (int64_t)c->cu_count) C /= 2;
-    // rather fewer sequences per block than the 512-thread shape
-    while (C > 1 && n * C > kLdsFftSmall && n * (C / 2) >= 1 && n <= kLdsFftSmall) C /= 2;
+    // rather fewer sequences per block than the 512-thread shape: as many as
+    // the 256-thread shape holds
+    if (n <= kLdsFftSmall && n * C > kLdsFftSmall) C = kLdsFftSmall / n;
     r.C = C;
     r.plan.tw = lds_twiddles(c, r.plan, rs);
     r.lds = cb * ((size_t)n * C + r.plan.ntw);
