@@ -274,8 +274,21 @@ __device__ __forceinline__ float2 unit_root(float2*, int k, int L)
     return make_float2(c, s);
 }
 
-// One radix-R pass over nseq sequences of length n at buf[s n], Ns = product
-// of the radices already applied.  The twiddles exp(-2 pi i k r/(Ns R)) of a
+// LDS layout of a block's transforms: element i = s n + j (sequence s, index
+// j) sits at lds_pad(i), one spare slot after every 16 elements.  Without it
+// the first pass of a power-of-two length writes each thread's R outputs side
+// by side, R elements apart across the lanes, and every lane of the write
+// lands in the same banks; padded, 16 complex elements span 17 and the lanes
+// spread over all banks.  lds_span: elements that nseq sequences occupy.
+__host__ __device__ __forceinline__ int lds_pad(int i) { return i + (i >> 4); }
+__host__ __device__ inline size_t lds_span(int n, int nseq)
+{
+    const size_t e = (size_t)n * nseq;
+    return e + (e >> 4);
+}
+
+// One radix-R pass over nseq sequences of length n at lds_pad(s n), Ns =
+// product of the radices already applied.  The twiddles exp(-2 pi i k r/(Ns R)) of a
 // butterfly are the powers of its root tw[k] = exp(-2 pi i k/(Ns R)).
 template <int R, int MAXE, int NT, class C2>
 __device__ __forceinline__ void lds_fft_pass(C2* buf, int n, int nseq, int Ns, const C2* tw)
@@ -284,17 +297,29 @@ __device__ __forceinline__ void lds_fft_pass(C2* buf, int n, int nseq, int Ns, c
     const int nb = n / R;
     const int total = nb * nseq;
     const FastDiv dnb = fast_div((unsigned)nb), dns = fast_div((unsigned)Ns);
+    // A butterfly reads R elements nb apart and writes R elements Ns apart.
+    // Padded, such a run stays evenly spaced when its stride is a multiple
+    // of 16 (stride s becomes s + s/16) or when the R writes fill part of
+    // one aligned run of 16 (Ns R divides 16); else each address is padded.
+    const int rstr = (nb & 15) == 0 ? nb + (nb >> 4) : 0;
+    const int wstr = (Ns & 15) == 0 ? Ns + (Ns >> 4) : (16 % (Ns * R) == 0 ? Ns : 0);
     C2 v[KB][R];
 #pragma unroll
     for (int i = 0; i < KB; ++i) {
         const int g = threadIdx.x + i * NT;
         if (g < total) {
             const int s = (int)fdiv((unsigned)g, dnb), j = g - s * nb;
-            const C2* src = buf + s * n + j;
+            const int base = s * n + j;
             const int k = j - (int)fdiv((unsigned)j, dns) * Ns;
             C2 t[R];
+            if (rstr) {
+                const C2* src = buf + lds_pad(base);
 #pragma unroll
-            for (int r = 0; r < R; ++r) t[r] = src[r * nb];
+                for (int r = 0; r < R; ++r) t[r] = src[r * rstr];
+            } else {
+#pragma unroll
+                for (int r = 0; r < R; ++r) t[r] = buf[lds_pad(base + r * nb)];
+            }
             if (k != 0) {
                 const C2 w1 = tw[k];
                 C2 w = w1;
@@ -314,16 +339,23 @@ __device__ __forceinline__ void lds_fft_pass(C2* buf, int n, int nseq, int Ns, c
         if (g < total) {
             const int s = (int)fdiv((unsigned)g, dnb), j = g - s * nb;
             const int q = (int)fdiv((unsigned)j, dns), k = j - q * Ns;
-            C2* dst = buf + s * n + q * Ns * R + k;
+            const int base = s * n + q * Ns * R + k;
+            if (wstr) {
+                C2* dst = buf + lds_pad(base);
 #pragma unroll
-            for (int r = 0; r < R; ++r) dst[r * Ns] = v[i][r];
+                for (int r = 0; r < R; ++r) dst[r * wstr] = v[i][r];
+            } else {
+#pragma unroll
+                for (int r = 0; r < R; ++r) buf[lds_pad(base + r * Ns)] = v[i][r];
+            }
         }
     }
     __syncthreads();
 }
 
-// Whole-block forward FFT of nseq sequences (n nseq <= MAXE) in LDS; the
-// caller synchronises before (data written) and may read right after.
+// Whole-block forward FFT of nseq sequences (n nseq <= MAXE) in LDS, laid
+// out by lds_pad; the caller synchronises before (data written) and may read
+// right after.
 // twl: LDS room for p.ntw entries, filled here with every pass's roots
 // (copied from p.tw when the plan has a precomputed table).
 // R7: the radix-7 pass is compiled in.  Its pass holds two 7-point

@@ -120,7 +120,8 @@ LdsCols lds_cols_plan(fh_ctx* c, int n, int64_t count, size_t rs, int min_c = 0)
     const size_t cb = 2 * rs;
     if (!lds_fft_plan(n, r.plan)) return r;
     // data of C sequences and the twiddle table in one block's LDS
-    const int cap = (int)((kLdsFftBytes - 512 - cb * (size_t)r.plan.ntw) / (cb * (size_t)n));
+    int cap = 0;
+    while (cap < 16 && cb * (lds_span(n, cap + 1) + (size_t)r.plan.ntw) + 512 <= kLdsFftBytes) ++cap;
     if (cap < 1) return r;
     int C = min_c > 0 ? min_c : std::max(1, (int)(64 / cb));
     const int64_t want = std::max<int64_t>(1, count / (2 * (int64_t)c->cu_count));
@@ -133,7 +134,7 @@ LdsCols lds_cols_plan(fh_ctx* c, int n, int64_t count, size_t rs, int min_c = 0)
     if (n <= kLdsFftSmall && n * C > kLdsFftSmall) C = kLdsFftSmall / n;
     r.C = C;
     r.plan.tw = lds_twiddles(c, r.plan, rs);
-    r.lds = cb * ((size_t)n * C + r.plan.ntw);
+    r.lds = cb * (lds_span(n, C) + r.plan.ntw);
     r.small = n * C <= kLdsFftSmall;
     return r;
 }

@@ -1481,7 +1481,7 @@ struct LdsHead {
 __host__ __device__ inline int t1_rows_table_rows(int C, int T, int reach) { return (C - 1) / T + 2 + reach; }
 __host__ __device__ inline size_t t1_rows_table_offset(int C, int n, int ntw, size_t csize)
 {
-    return (csize * ((size_t)C * n + ntw) + 15) / 16 * 16;
+    return (csize * (lds_span(n, C) + ntw) + 15) / 16 * 16;
 }
 
 // Tile reduce fused with the first FFT pass of type 1.  Workgroup (group g,
@@ -1540,15 +1540,15 @@ __global__ void __launch_bounds__(NT) k_t1_rows(const typename V2<R>::T* __restr
             const int tx = (int)fdiv((unsigned)x, dT), ty = (int)fdiv((unsigned)y, dT);
             v = reduce_cell<R, REACH, 1>(slots, gg, tx, ty, x - tx * T, y - ty * T, head);
         }
-        buf[e] = v;
+        buf[lds_pad(e)] = v;
     }
     __syncthreads();
-    lds_fft<MAXE, NT, R7>(buf, plan, C, buf + (size_t)C * nf1);
+    lds_fft<MAXE, NT, R7>(buf, plan, C, buf + lds_span(nf1, C));
     C2* Gv = reinterpret_cast<C2*>(G) + ((size_t)b * gg.rows + r0) * n1;
     for (int e = threadIdx.x; e < nr * n1; e += NT) {
         const int rr = e / n1, k1i = e - rr * n1;
         const int k1 = k1i - n1 / 2;
-        Gv[e] = buf[(size_t)rr * nf1 + (k1 < 0 ? k1 + nf1 : k1)];
+        Gv[e] = buf[lds_pad(rr * nf1 + (k1 < 0 ? k1 + nf1 : k1))];
     }
 }
 
@@ -1756,7 +1756,7 @@ __global__ void __launch_bounds__(NT) k_t1_cols(const R* __restrict__ F, R* __re
             }
             v = Fv[(size_t)r * ldf + col];
         }
-        buf[c * nf2 + r] = v;
+        buf[lds_pad(c * nf2 + r)] = v;
     }
     // the zero padding below the band, column by column
     const int nz = nf2 - rb;
@@ -1767,11 +1767,11 @@ __global__ void __launch_bounds__(NT) k_t1_cols(const R* __restrict__ F, R* __re
             C2 v;
             v.x = R(0);
             v.y = R(0);
-            buf[c * nf2 + rb + (e - c * nz)] = v;
+            buf[lds_pad(c * nf2 + rb + (e - c * nz))] = v;
         }
     }
     __syncthreads();
-    lds_fft<MAXE, NT, R7>(buf, plan, C, buf + (size_t)C * plan.n);
+    lds_fft<MAXE, NT, R7>(buf, plan, C, buf + lds_span(plan.n, C));
     // epilogue: C lanes write C consecutive outputs of a row, with the row
     // factors of k_t1_rowfactors and the column factors above
     const double2* E2 = E2all + (size_t)b * ep.n2;
@@ -1781,7 +1781,7 @@ __global__ void __launch_bounds__(NT) k_t1_cols(const R* __restrict__ F, R* __re
         if (c >= ncol) continue;
         const int k2 = k2i - ep.n2 / 2;
         const int r = k2 < 0 ? k2 + nf2 : k2;
-        const C2 fv = buf[(size_t)c * nf2 + r];
+        const C2 fv = buf[lds_pad(c * nf2 + r)];
         const double2 er = E2[k2i];
         const double2 a = E1[c];
         const double ar = a.x * er.x - a.y * er.y, ai = a.x * er.y + a.y * er.x;
@@ -1838,12 +1838,12 @@ __global__ void __launch_bounds__(NT) k_t3_rows(const R* __restrict__ bgrid, int
                 v.y = (R)(x.y * sc);
             }
         }
-        buf[e] = v;
+        buf[lds_pad(e)] = v;
     }
     __syncthreads();
-    lds_fft<MAXE, NT, R7>(buf, plan, C, buf + (size_t)C * plan.n);
+    lds_fft<MAXE, NT, R7>(buf, plan, C, buf + lds_span(plan.n, C));
     C2* Gv = reinterpret_cast<C2*>(G);
-    for (int e = threadIdx.x; e < nrow * m1; e += NT) Gv[(size_t)row0 * m1 + e] = buf[e];
+    for (int e = threadIdx.x; e < nrow * m1; e += NT) Gv[(size_t)row0 * m1 + e] = buf[lds_pad(e)];
 }
 
 // Type-3 column pass, in place: workgroup g transforms the C columns
@@ -1866,13 +1866,13 @@ __global__ void __launch_bounds__(NT) k_t3_cols(R* __restrict__ G, int m1, int m
         v.x = R(0);
         v.y = R(0);
         if (c < ncol) v = Gv[(size_t)i2 * m1 + col0 + c];
-        buf[c * m2 + i2] = v;
+        buf[lds_pad(c * m2 + i2)] = v;
     }
     __syncthreads();
-    lds_fft<MAXE, NT, R7>(buf, plan, C, buf + (size_t)C * plan.n);
+    lds_fft<MAXE, NT, R7>(buf, plan, C, buf + lds_span(plan.n, C));
     for (int e = threadIdx.x; e < C * m2; e += NT) {
         const int i2 = e / C, c = e - i2 * C;
-        if (c < ncol) Gv[(size_t)i2 * m1 + col0 + c] = buf[c * m2 + i2];
+        if (c < ncol) Gv[(size_t)i2 * m1 + col0 + c] = buf[lds_pad(c * m2 + i2)];
     }
 }
 
