@@ -1155,37 +1155,59 @@ __host__ __device__ __forceinline__ int merge_levels(int cnt)
     return l;
 }
 
+// A block takes 256 consecutive work items at a time: a thread per item
+// checks whether the item heads a group at this level (most items do not:
+// only crowded tiles merge), the block lists those in LDS and then sums each
+// listed group, a thread per slot element.
 template <class R>
 __global__ void __launch_bounds__(256) k_merge_slots(typename V2<R>::T* __restrict__ slots,
                                                      const Sub* __restrict__ subs, const int* __restrict__ nsub_ptr,
                                                      const int* __restrict__ tsub, int LL, int level)
 {
     using C = typename V2<R>::T;
+    __shared__ int s_item[256];
+    __shared__ int s_nk[256];
+    __shared__ int s_n;
     const int nsub = *nsub_ptr;
     int stride = 1;
     for (int l = 1; l < level; ++l) stride *= kMergeG;
     const int span = stride * kMergeG;
-    for (int i = blockIdx.x; i < nsub; i += gridDim.x) {
-        const int t = subs[i].tile;
-        const int first = tsub[2 * t], cnt = tsub[2 * t + 1];
-        const int r = i - first;
-        if (merge_levels(cnt) < level || r % span != 0) continue;
-        const int nk = min(kMergeG, (cnt - r + stride - 1) / stride);
-        const size_t st = (size_t)stride * LL;
-        for (int e = threadIdx.x; e < LL; e += blockDim.x) {
-            C* sp = slots + (size_t)i * LL + e;
-            // all loads of the group in flight at once, then summed in order
-            C v[kMergeG];
-#pragma unroll
-            for (int k = 0; k < kMergeG; ++k) v[k] = k < nk ? sp[k * st] : C{R(0), R(0)};
-            C acc = v[0];
-#pragma unroll
-            for (int k = 1; k < kMergeG; ++k) {
-                acc.x += v[k].x;
-                acc.y += v[k].y;
+    const size_t st = (size_t)stride * LL;
+    for (int i0 = blockIdx.x * 256; i0 < nsub; i0 += gridDim.x * 256) {
+        if (threadIdx.x == 0) s_n = 0;
+        __syncthreads();
+        const int i = i0 + (int)threadIdx.x;
+        if (i < nsub) {
+            const int t = subs[i].tile;
+            const int first = tsub[2 * t], cnt = tsub[2 * t + 1];
+            const int r = i - first;
+            if (merge_levels(cnt) >= level && r % span == 0) {
+                const int m = atomicAdd(&s_n, 1);
+                s_item[m] = i;
+                s_nk[m] = min(kMergeG, (cnt - r + stride - 1) / stride);
             }
-            sp[0] = acc;
         }
+        __syncthreads();
+        const int n = s_n;
+        for (int m = 0; m < n; ++m) {
+            const int nk = s_nk[m];
+            C* sp0 = slots + (size_t)s_item[m] * LL;
+            for (int e = threadIdx.x; e < LL; e += blockDim.x) {
+                C* sp = sp0 + e;
+                // all loads of the group in flight at once, then summed in order
+                C v[kMergeG];
+#pragma unroll
+                for (int k = 0; k < kMergeG; ++k) v[k] = k < nk ? sp[k * st] : C{R(0), R(0)};
+                C acc = v[0];
+#pragma unroll
+                for (int k = 1; k < kMergeG; ++k) {
+                    acc.x += v[k].x;
+                    acc.y += v[k].y;
+                }
+                sp[0] = acc;
+            }
+        }
+        __syncthreads();
     }
 }
 
@@ -2412,7 +2434,7 @@ fh_status spread_items(fh_ctx* c, const InstParams& p0, const InstParams* table,
     if (Ntot > 0) {
         const int64_t LL = (int64_t)gg.L * gg.L;
         const unsigned mgrid =
-            (unsigned)std::max<int64_t>(1, std::min<int64_t>(b.max_sub, (int64_t)c->cu_count * 16));
+            (unsigned)std::max<int64_t>(1, std::min<int64_t>((b.max_sub + 255) / 256, (int64_t)c->cu_count * 16));
         for (int level = 1; level <= kMergeLevels; ++level)
             hipLaunchKernelGGL((k_merge_slots<R>), dim3(mgrid), dim3(256), 0, c->stream,
                                (typename V2<R>::T*)b.slots, b.subs, b.nsub, b.tsub, (int)LL, level);
