@@ -1465,7 +1465,26 @@ struct TsubHead {
 // Tile reduce over the listed tiles (the rest of the fine grid was filled
 // with zeros): persistent blocks walk the cells of the listed tiles, 256 at
 // a time, a thread per cell (reduce_cell); cells of a partial last tile
-// outside the grid are skipped.
+// outside the grid are skipped.  The 256 cells of a step touch at most
+// kRedTiles listed tiles: the heads of their covering tiles are looked up
+// once, into LDS, and the cells read them there, so a cell waits on one
+// round of global loads (its slots) rather than two.  (Tiles are at least
+// 4 x 4 cells; a step that still spanned more than kRedTiles tiles would look
+// the heads up from the scan's table, cell by cell.)
+constexpr int kRedTiles = 256 / 16 + 2;
+
+template <int REACH>
+struct ListHead {
+    const int4* tab;  // (REACH + 1)^2 heads per listed tile of the step, (dy, dx) order
+    int tx, ty, ntx;
+    __device__ int4 operator()(int sty, int stx) const
+    {
+        int dx = tx - stx;
+        if (dx < 0) dx += ntx;
+        return tab[(ty - sty) * (REACH + 1) + dx];
+    }
+};
+
 template <class R, int REACH>
 __global__ void __launch_bounds__(256) k_reduce_list(const typename V2<R>::T* __restrict__ slots,
                                                      const int* __restrict__ tsub, const int* __restrict__ list,
@@ -1473,19 +1492,48 @@ __global__ void __launch_bounds__(256) k_reduce_list(const typename V2<R>::T* __
                                                      R* __restrict__ F, const int2* __restrict__ rwin)
 {
     using C = typename V2<R>::T;
+    constexpr int NC = (REACH + 1) * (REACH + 1);
+    __shared__ int4 s_head[kRedTiles * NC];
     const int T = gg.T, TT = T * T;
-    const int64_t ncell = (int64_t)(*nlist) * TT;
-    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < ncell;
-         e += (int64_t)gridDim.x * blockDim.x) {
-        const int k = (int)(e / TT), c = (int)(e - (int64_t)k * TT);
-        const int tile = list[k];
-        const int b = tile / tpi, tl = tile - b * tpi;
-        const int ty = tl / gg.ntx, tx = tl - ty * gg.ntx;
-        const int cj = c / T, ci = c - cj * T;
-        const int2 rw = inst_rows(rwin, gg, b);
-        if (tx * T + ci >= gg.nf1 || ty * T + cj >= rw.x) continue;
-        reinterpret_cast<C*>(F)[((size_t)rw.y + ty * T + cj) * gg.nf1 + tx * T + ci] =
-            reduce_cell<R, REACH>(slots, gg, tx, ty, ci, cj, TsubHead{tsub, b * tpi, gg.ntx, gg.nty});
+    const int nl = *nlist;
+    const int64_t ncell = (int64_t)nl * TT;
+    for (int64_t e0 = blockIdx.x * (int64_t)blockDim.x; e0 < ncell; e0 += (int64_t)gridDim.x * blockDim.x) {
+        const int k0 = (int)(e0 / TT);
+        const int nt = min((int)((e0 + blockDim.x - 1) / TT), nl - 1) - k0 + 1;
+        const bool staged = nt <= kRedTiles;
+        for (int h = threadIdx.x; staged && h < nt * NC; h += blockDim.x) {
+            const int kk = h / NC, i = h - kk * NC;
+            const int dy = i / (REACH + 1), dx = i - dy * (REACH + 1);
+            const int tile = list[k0 + kk];
+            const int b = tile / tpi, tl = tile - b * tpi;
+            const int ty = tl / gg.ntx, tx = tl - ty * gg.ntx;
+            int sty = ty - dy;
+            int4 hv = make_int4(0, 0, 1, 0);
+            if (sty >= 0 || gg.wrap_y) {
+                if (sty < 0) sty = ((sty % gg.nty) + gg.nty) % gg.nty;
+                const int stx = (((tx - dx) % gg.ntx) + gg.ntx) % gg.ntx;
+                const int t = b * tpi + sty * gg.ntx + stx;
+                hv = tile_heads(tsub[2 * t], tsub[2 * t + 1]);
+            }
+            s_head[h] = hv;
+        }
+        __syncthreads();
+        const int64_t e = e0 + threadIdx.x;
+        if (e < ncell) {
+            const int k = (int)(e / TT), c = (int)(e - (int64_t)k * TT);
+            const int tile = list[k];
+            const int b = tile / tpi, tl = tile - b * tpi;
+            const int ty = tl / gg.ntx, tx = tl - ty * gg.ntx;
+            const int cj = c / T, ci = c - cj * T;
+            const int2 rw = inst_rows(rwin, gg, b);
+            if (tx * T + ci < gg.nf1 && ty * T + cj < rw.x)
+                reinterpret_cast<C*>(F)[((size_t)rw.y + ty * T + cj) * gg.nf1 + tx * T + ci] =
+                    staged ? reduce_cell<R, REACH>(slots, gg, tx, ty, ci, cj,
+                                                   ListHead<REACH>{s_head + (k - k0) * NC, tx, ty, gg.ntx})
+                           : reduce_cell<R, REACH>(slots, gg, tx, ty, ci, cj,
+                                                   TsubHead{tsub, b * tpi, gg.ntx, gg.nty});
+        }
+        __syncthreads();
     }
 }
 

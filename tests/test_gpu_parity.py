@@ -185,6 +185,30 @@ def test_spread_variants(fh, ctx, method, tile, P, sigma):
     assert relL2(up, refp) <= TOL[ctx.precision]
 
 
+@pytest.mark.parametrize("tile", [4, 5])
+def test_small_tiles(fh, ctx, tile):
+    # the smallest tiles the options allow (16 and 25 cells) with a width-5
+    # kernel: 256 consecutive cells of the list reduce then span the most
+    # listed tiles a step stages in LDS (17 of 18 for 16-cell tiles)
+    wl = workloads.workload(2)
+    shape = workloads.RadialCurve(1.0, wl.shape.a, wl.shape.b, panels=12, q=16, m=60)
+    opt = fh.fh_options(sigma=2.0, kernel_width=5, beta=0.0, tile=tile, max_subproblem=0, spread_method=2)
+    ctx.set_options(opt)
+    n = 160
+    try:
+        q = ctx.quad_for(shape)
+        u = cpu(ctx.field_grid(q, wl.lam, wl.z, n, n, 0.02, 0.02))
+    finally:
+        ctx.set_options(None)
+    x, y, w = oracle_quad(shape)
+    xi, eta = oracle.grid_targets(n, n, 0.02, 0.02)
+    ref = oracle.fresnel_direct(x, y, w, wl.lam, wl.z, xi, eta)
+    err = relL2(u, ref)
+    print(f"  {ctx.precision} tile {tile} width 5: rel L2 {err:.2e}", flush=True)
+    # a width-5 kernel resolves about 1e-5 (the ES rule for sigma = 2)
+    assert err <= 1e-4
+
+
 def test_grid_folding_undersampled(ctx):
     # target grid coarser than the field: rescaled nodes leave [-pi, pi) and
     # must be folded (sec. 2.2)
