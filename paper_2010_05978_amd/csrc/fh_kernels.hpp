@@ -1545,6 +1545,73 @@ struct LdsHead {
     __device__ int4 operator()(int sty, int stx) const { return tab[(sty - ty_lo) * ntx + stx]; }
 };
 
+// Tile reduce by strips: workgroup (ty, b) writes every cell of tile row ty
+// of instance b (rows ty T .. min(ty T + T, its rows) - 1, all nf1 columns,
+// row-major, so a step's 256 writes are contiguous), zeros included: no zero
+// fill and no list of reached tiles.  It first copies to LDS the heads of
+// the REACH + 1 tile rows that cover the strip, then a flag per tile column:
+// whether any covering tile holds points; cells under none are written as
+// zeros without a load.  The sums are those of reduce_cell, in its order.
+// The block also clears the binning counters of its tile row for the next
+// call; a tile row past the instance's window has no cells.
+__host__ __device__ inline size_t reduce_strips_lds(int reach, int ntx)
+{
+    return (size_t)(reach + 1) * ntx * sizeof(int4) + (size_t)ntx * sizeof(int);
+}
+
+template <class R, int REACH>
+__global__ void __launch_bounds__(256) k_reduce_strips(const typename V2<R>::T* __restrict__ slots,
+                                                       const int* __restrict__ tsub, GridGeom gg, int tpi,
+                                                       R* __restrict__ F, int* __restrict__ cnt,
+                                                       const int2* __restrict__ rwin)
+{
+    using C = typename V2<R>::T;
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    const int ty = blockIdx.x, b = blockIdx.y;
+    const int T = gg.T, ntx = gg.ntx;
+    int4* tab = reinterpret_cast<int4*>(lds_raw);                    // (REACH + 1) x ntx heads
+    int* act = reinterpret_cast<int*>(lds_raw + (size_t)(REACH + 1) * ntx * sizeof(int4));
+    for (int tx = threadIdx.x; tx < ntx; tx += blockDim.x) cnt[b * tpi + ty * ntx + tx] = 0;
+    const int2 rw = inst_rows(rwin, gg, b);
+    const int y0 = ty * T;
+    if (y0 >= rw.x) return;
+    const int ty_lo = ty - REACH;
+    for (int e = threadIdx.x; e < (REACH + 1) * ntx; e += blockDim.x) {
+        const int k = e / ntx, tx = e - k * ntx;
+        int sty = ty_lo + k;
+        int4 h = make_int4(0, 0, 1, 0);
+        if (sty >= 0 || gg.wrap_y) {
+            if (sty < 0) sty = ((sty % gg.nty) + gg.nty) % gg.nty;
+            const int t = b * tpi + sty * ntx + tx;
+            h = tile_heads(tsub[2 * t], tsub[2 * t + 1]);
+        }
+        tab[e] = h;
+    }
+    __syncthreads();
+    for (int tx = threadIdx.x; tx < ntx; tx += blockDim.x) {
+        int any = 0;
+#pragma unroll
+        for (int dx = 0; dx <= REACH; ++dx) {
+            const int stx = (((tx - dx) % ntx) + ntx) % ntx;
+#pragma unroll
+            for (int k = 0; k <= REACH; ++k) any |= tab[k * ntx + stx].y;
+        }
+        act[tx] = any;
+    }
+    __syncthreads();
+    const int nrow = min(T, rw.x - y0), nf1 = gg.nf1;
+    const LdsHead head{tab, ty_lo, ntx};
+    const FastDiv dn = fast_div((unsigned)nf1), dT = fast_div((unsigned)T);
+    C* Fr = reinterpret_cast<C*>(F) + ((size_t)rw.y + y0) * nf1;
+    for (int e = threadIdx.x; e < nrow * nf1; e += blockDim.x) {
+        const int cj = (int)fdiv((unsigned)e, dn), x = e - cj * nf1;
+        const int tx = (int)fdiv((unsigned)x, dT);
+        C v{R(0), R(0)};
+        if (act[tx]) v = reduce_cell<R, REACH>(slots, gg, tx, ty, x - tx * T, cj, head);
+        Fr[e] = v;
+    }
+}
+
 // Tile rows whose heads a group of C fine-grid rows starting at r0 needs,
 // and the table's byte offset in LDS (after the rows and the twiddles,
 // 16-byte aligned).
@@ -2520,15 +2587,26 @@ fh_status reduce_grid(fh_ctx* c, int ninst, const GridGeom& gg, const SpreadBufs
                            gg, tpi, F, rwin);                                                                \
     } while (0)
     // Tiles under 128 cells (the matrix-core spread's), and grids of 4M
-    // cells or more (mostly empty in a batch), are reduced from the list of
-    // reached tiles after a zero fill: three launches, but every thread has
-    // a cell to sum.  Small grids of larger tiles take one launch, a tile per
-    // block.
+    // cells or more (mostly empty in a batch), are reduced a thread per cell:
+    // by strips of one tile row (one launch, every cell written once) when
+    // the strip's heads fit in LDS, else from the list of reached tiles after
+    // a zero fill (three launches).  Small grids of larger tiles take one
+    // launch, a tile per block.
     const bool by_cell = TT < 128 || (int64_t)ntiles_total * TT >= ((int64_t)1 << 22);
+    const size_t slds = reduce_strips_lds(reach, gg.ntx);
+    const bool strips = by_cell && slds <= kLdsBudget && ninst <= 65535;
     const unsigned lgrid = (unsigned)std::max<int64_t>(
         1, std::min<int64_t>((int64_t)c->cu_count * 8, ((int64_t)ntiles_total * TT + 255) / 256));
-    if (by_cell) FH_TRY(launch_zero(c, F, 2 * sizeof(R) * (size_t)total_rows * gg.nf1));
-    if (by_cell) {
+    if (strips) {
+        const dim3 sgrid((unsigned)gg.nty, (unsigned)ninst);
+        if (reach == 1)
+            hipLaunchKernelGGL((k_reduce_strips<R, 1>), sgrid, dim3(256), slds, c->stream,
+                               (const typename V2<R>::T*)b.slots, b.tsub, gg, tpi, F, b.cnt, rwin);
+        else
+            hipLaunchKernelGGL((k_reduce_strips<R, 2>), sgrid, dim3(256), slds, c->stream,
+                               (const typename V2<R>::T*)b.slots, b.tsub, gg, tpi, F, b.cnt, rwin);
+    } else if (by_cell) {
+        FH_TRY(launch_zero(c, F, 2 * sizeof(R) * (size_t)total_rows * gg.nf1));
         if (reach == 1) FH_REDUCE_CELLS(1);
         else FH_REDUCE_CELLS(2);
     } else if (TT > 256) {
