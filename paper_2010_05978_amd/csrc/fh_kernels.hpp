@@ -209,14 +209,19 @@ __global__ void k_fill_field(R* __restrict__ u, int64_t M, R re)
 // starshade seen on a coarse pupil grid), this turns one same-address atomic
 // chain per wavefront into one per block.  (A table of twice the block's
 // nodes, which never fills, measured no faster on the batch's 6-cell tiles:
-// 0.68 against 0.63 ms.)
-constexpr int kBinBlock = 1024;
+// 0.68 against 0.63 ms.)  A batch's nodes spread over many tiles and the
+// kernel waits on memory: 256-thread blocks, four times as many per CU,
+// hide more of it (whole binning 1.50 against 1.57 ms on the 256-shape
+// batch).
+constexpr int kBinBlock = 1024;      // one rule: its nodes may crowd a few tiles
+constexpr int kBinBlockBatch = 256;  // a batch: spread over many tiles, latency bound
 constexpr int kBinKeyBits = 7;
 constexpr int kBinKeys = 1 << kBinKeyBits;
 
 // With `key` (the stable binning), each node also writes its tile and its
 // index, the keys and values of the sort that then fixes the ranks.
-__global__ void __launch_bounds__(kBinBlock) k_bin_count(InstParams p0, const InstParams* __restrict__ table,
+template <int BS>
+__global__ void __launch_bounds__(BS) k_bin_count(InstParams p0, const InstParams* __restrict__ table,
                                                          const int* __restrict__ chunk, int64_t Ntot, GridGeom gg,
                                                          int* __restrict__ cnt, int* __restrict__ rank,
                                                          uint32_t* __restrict__ key, int* __restrict__ vals)
@@ -224,7 +229,7 @@ __global__ void __launch_bounds__(kBinBlock) k_bin_count(InstParams p0, const In
     __shared__ int s_key[kBinKeys];
     __shared__ int s_cnt[kBinKeys];
     __shared__ int s_base[kBinKeys];
-    for (int e = threadIdx.x; e < kBinKeys; e += kBinBlock) {
+    for (int e = threadIdx.x; e < kBinKeys; e += BS) {
         s_key[e] = -1;
         s_cnt[e] = 0;
     }
@@ -278,7 +283,7 @@ __global__ void __launch_bounds__(kBinBlock) k_bin_count(InstParams p0, const In
             gbase = atomicAdd(&cnt[tile], __popcll(mine));
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < kBinKeys; e += kBinBlock)
+    for (int e = threadIdx.x; e < kBinKeys; e += BS)
         if (s_key[e] >= 0) s_base[e] = atomicAdd(&cnt[s_key[e]], s_cnt[e]);
     __syncthreads();
     int base = 0;
@@ -2509,8 +2514,13 @@ fh_status spread_items(fh_ctx* c, const InstParams& p0, const InstParams* table,
         if (table)
             hipLaunchKernelGGL(k_chunk_inst, dim3(nblocks(Ntot / kChunk + 2, 256)), dim3(256), 0, c->stream, table,
                                ninst, Ntot, b.chunk);
-        hipLaunchKernelGGL(k_bin_count, dim3(nblocks(Ntot, kBinBlock)), dim3(kBinBlock), 0, c->stream, p0, table,
-                           (const int*)b.chunk, Ntot, gg, b.cnt, b.rank, b.key, b.vals);
+        if (table)
+            hipLaunchKernelGGL(k_bin_count<kBinBlockBatch>, dim3(nblocks(Ntot, kBinBlockBatch)),
+                               dim3(kBinBlockBatch), 0, c->stream, p0, table, (const int*)b.chunk, Ntot, gg, b.cnt,
+                               b.rank, b.key, b.vals);
+        else
+            hipLaunchKernelGGL(k_bin_count<kBinBlock>, dim3(nblocks(Ntot, kBinBlock)), dim3(kBinBlock), 0,
+                               c->stream, p0, table, (const int*)b.chunk, Ntot, gg, b.cnt, b.rank, b.key, b.vals);
         if (b.key) {
             int bits = 1;
             while (bits < 32 && ((int64_t)1 << bits) < ntiles_total) ++bits;
