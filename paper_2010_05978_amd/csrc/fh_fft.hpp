@@ -40,8 +40,8 @@ struct LdsFftPlan {
                                // null: each workgroup computes it
 };
 
-// Radix passes for n (7s, 5s and 3s first, then 16, 8, 4, 2); false if n has
-// another prime factor.  A pass with Ns = 1 writes each thread's R outputs
+// Radix passes for n (7s, 5s and 3s first, then the power of two in passes
+// of at most 16, as even as they go); false if n has another prime factor.  A pass with Ns = 1 writes each thread's R outputs
 // side by side, so neighbouring lanes write R elements apart: with R a power
 // of two every lane of a write instruction lands in the same LDS banks,
 // with R odd they spread over all of them; the later passes (Ns > 1) write
@@ -62,6 +62,19 @@ inline bool lds_fft_plan(int n, LdsFftPlan& p)
     take(7);
     take(5);
     take(3);
+    // the power of two 2^k left: ceil(k / 4) passes of radix 16 at most,
+    // the k bits spread as evenly as they go (1024 = 8 8 16, not 16 16 4),
+    // so that every pass gives each thread about the same work
+    int k = 0;
+    while ((1 << (k + 1)) <= m && m % (1 << (k + 1)) == 0) ++k;
+    if (k > 0 && (1 << k) == m) {
+        const int np = (k + 3) / 4;
+        for (int i = 0; i < np && p.nst < kLdsFftMaxStages; ++i) {
+            const int bits = k / np + (i >= np - k % np ? 1 : 0);
+            p.radix[p.nst++] = 1 << bits;
+            m >>= bits;
+        }
+    }
     take(16);
     take(8);
     take(4);
