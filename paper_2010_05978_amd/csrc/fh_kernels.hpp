@@ -1550,14 +1550,16 @@ struct LdsHead {
     __device__ int4 operator()(int sty, int stx) const { return tab[(sty - ty_lo) * ntx + stx]; }
 };
 
-// Tile reduce by strips: workgroup (ty, b) writes every cell of tile row ty
-// of instance b (rows ty T .. min(ty T + T, its rows) - 1, all nf1 columns,
+// Tile reduce by strips: workgroup (ty S + sl, b) writes every cell of slice
+// sl (of S) of tile row ty of instance b (rows ty T + sl RB .. of the rows
+// ty T .. min(ty T + T, its rows) - 1, RB = ceil(T / S); all nf1 columns,
 // row-major, so a step's 256 writes are contiguous), zeros included: no zero
-// fill and no list of reached tiles.  It first copies to LDS the heads of
+// fill and no list of reached tiles.  Slices (S > 1) give a single large
+// grid workgroups enough to fill the chip.  It first copies to LDS the heads of
 // the REACH + 1 tile rows that cover the strip, then a flag per tile column:
 // whether any covering tile holds points; cells under none are written as
 // zeros without a load.  The sums are those of reduce_cell, in its order.
-// The block also clears the binning counters of its tile row for the next
+// Slice 0 also clears the binning counters of its tile row for the next
 // call; a tile row past the instance's window has no cells.
 __host__ __device__ inline size_t reduce_strips_lds(int reach, int ntx)
 {
@@ -1568,18 +1570,20 @@ template <class R, int REACH>
 __global__ void __launch_bounds__(256) k_reduce_strips(const typename V2<R>::T* __restrict__ slots,
                                                        const int* __restrict__ tsub, GridGeom gg, int tpi,
                                                        R* __restrict__ F, int* __restrict__ cnt,
-                                                       const int2* __restrict__ rwin)
+                                                       const int2* __restrict__ rwin, int S)
 {
     using C = typename V2<R>::T;
     extern __shared__ __align__(16) unsigned char lds_raw[];
-    const int ty = blockIdx.x, b = blockIdx.y;
+    const int ty = blockIdx.x / S, sl = blockIdx.x - ty * S, b = blockIdx.y;
     const int T = gg.T, ntx = gg.ntx;
     int4* tab = reinterpret_cast<int4*>(lds_raw);                    // (REACH + 1) x ntx heads
     int* act = reinterpret_cast<int*>(lds_raw + (size_t)(REACH + 1) * ntx * sizeof(int4));
-    for (int tx = threadIdx.x; tx < ntx; tx += blockDim.x) cnt[b * tpi + ty * ntx + tx] = 0;
+    if (sl == 0)
+        for (int tx = threadIdx.x; tx < ntx; tx += blockDim.x) cnt[b * tpi + ty * ntx + tx] = 0;
     const int2 rw = inst_rows(rwin, gg, b);
-    const int y0 = ty * T;
-    if (y0 >= rw.x) return;
+    const int RB = (T + S - 1) / S;
+    const int y0 = ty * T, ys = y0 + sl * RB;
+    if (ys >= min(y0 + T, rw.x)) return;
     const int ty_lo = ty - REACH;
     for (int e = threadIdx.x; e < (REACH + 1) * ntx; e += blockDim.x) {
         const int k = e / ntx, tx = e - k * ntx;
@@ -1604,15 +1608,15 @@ __global__ void __launch_bounds__(256) k_reduce_strips(const typename V2<R>::T* 
         act[tx] = any;
     }
     __syncthreads();
-    const int nrow = min(T, rw.x - y0), nf1 = gg.nf1;
+    const int nrow = min(min(RB, y0 + T - ys), rw.x - ys), nf1 = gg.nf1;
     const LdsHead head{tab, ty_lo, ntx};
     const FastDiv dn = fast_div((unsigned)nf1), dT = fast_div((unsigned)T);
-    C* Fr = reinterpret_cast<C*>(F) + ((size_t)rw.y + y0) * nf1;
+    C* Fr = reinterpret_cast<C*>(F) + ((size_t)rw.y + ys) * nf1;
     for (int e = threadIdx.x; e < nrow * nf1; e += blockDim.x) {
-        const int cj = (int)fdiv((unsigned)e, dn), x = e - cj * nf1;
+        const int r = (int)fdiv((unsigned)e, dn), x = e - r * nf1;
         const int tx = (int)fdiv((unsigned)x, dT);
         C v{R(0), R(0)};
-        if (act[tx]) v = reduce_cell<R, REACH>(slots, gg, tx, ty, x - tx * T, cj, head);
+        if (act[tx]) v = reduce_cell<R, REACH>(slots, gg, tx, ty, x - tx * T, ys - y0 + r, head);
         Fr[e] = v;
     }
 }
@@ -2608,13 +2612,16 @@ fh_status reduce_grid(fh_ctx* c, int ninst, const GridGeom& gg, const SpreadBufs
     const unsigned lgrid = (unsigned)std::max<int64_t>(
         1, std::min<int64_t>((int64_t)c->cu_count * 8, ((int64_t)ntiles_total * TT + 255) / 256));
     if (strips) {
-        const dim3 sgrid((unsigned)gg.nty, (unsigned)ninst);
+        // slices per tile row: enough workgroups for 8 per CU, at most a row each
+        const int64_t nstrip = (int64_t)gg.nty * ninst;
+        const int S = (int)std::min<int64_t>(gg.T, std::max<int64_t>(1, (8 * (int64_t)c->cu_count + nstrip - 1) / nstrip));
+        const dim3 sgrid((unsigned)(gg.nty * S), (unsigned)ninst);
         if (reach == 1)
             hipLaunchKernelGGL((k_reduce_strips<R, 1>), sgrid, dim3(256), slds, c->stream,
-                               (const typename V2<R>::T*)b.slots, b.tsub, gg, tpi, F, b.cnt, rwin);
+                               (const typename V2<R>::T*)b.slots, b.tsub, gg, tpi, F, b.cnt, rwin, S);
         else
             hipLaunchKernelGGL((k_reduce_strips<R, 2>), sgrid, dim3(256), slds, c->stream,
-                               (const typename V2<R>::T*)b.slots, b.tsub, gg, tpi, F, b.cnt, rwin);
+                               (const typename V2<R>::T*)b.slots, b.tsub, gg, tpi, F, b.cnt, rwin, S);
     } else if (by_cell) {
         FH_TRY(launch_zero(c, F, 2 * sizeof(R) * (size_t)total_rows * gg.nf1));
         if (reach == 1) FH_REDUCE_CELLS(1);
