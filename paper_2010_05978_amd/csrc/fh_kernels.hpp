@@ -1160,29 +1160,34 @@ __host__ __device__ __forceinline__ int merge_levels(int cnt)
     return l;
 }
 
-// A block takes 256 consecutive work items at a time: a thread per item
-// checks whether the item heads a group at this level (most items do not:
-// only crowded tiles merge), the block lists those in LDS and then sums each
-// listed group, a thread per slot element.
+// A block takes kMergeChunk consecutive work items at a time: a thread per
+// item checks whether the item heads a group at this level (most items do
+// not: only crowded tiles merge) and the block lists those in LDS; then its
+// threads sum the listed groups, a thread per (group, slot element).  The
+// chunk is small so that the consecutive heads of one crowded tile spread
+// over many blocks.
+constexpr int kMergeChunk = 32;
+
 template <class R>
 __global__ void __launch_bounds__(256) k_merge_slots(typename V2<R>::T* __restrict__ slots,
                                                      const Sub* __restrict__ subs, const int* __restrict__ nsub_ptr,
                                                      const int* __restrict__ tsub, int LL, int level)
 {
     using C = typename V2<R>::T;
-    __shared__ int s_item[256];
-    __shared__ int s_nk[256];
+    __shared__ int s_item[kMergeChunk];
+    __shared__ int s_nk[kMergeChunk];
     __shared__ int s_n;
     const int nsub = *nsub_ptr;
     int stride = 1;
     for (int l = 1; l < level; ++l) stride *= kMergeG;
     const int span = stride * kMergeG;
     const size_t st = (size_t)stride * LL;
-    for (int i0 = blockIdx.x * 256; i0 < nsub; i0 += gridDim.x * 256) {
+    const FastDiv dLL = fast_div((unsigned)LL);
+    for (int i0 = blockIdx.x * kMergeChunk; i0 < nsub; i0 += gridDim.x * kMergeChunk) {
         if (threadIdx.x == 0) s_n = 0;
         __syncthreads();
         const int i = i0 + (int)threadIdx.x;
-        if (i < nsub) {
+        if (threadIdx.x < kMergeChunk && i < nsub) {
             const int t = subs[i].tile;
             const int first = tsub[2 * t], cnt = tsub[2 * t + 1];
             const int r = i - first;
@@ -1194,23 +1199,21 @@ __global__ void __launch_bounds__(256) k_merge_slots(typename V2<R>::T* __restri
         }
         __syncthreads();
         const int n = s_n;
-        for (int m = 0; m < n; ++m) {
+        for (int w = threadIdx.x; w < n * LL; w += blockDim.x) {
+            const int m = (int)fdiv((unsigned)w, dLL), e = w - m * LL;
             const int nk = s_nk[m];
-            C* sp0 = slots + (size_t)s_item[m] * LL;
-            for (int e = threadIdx.x; e < LL; e += blockDim.x) {
-                C* sp = sp0 + e;
-                // all loads of the group in flight at once, then summed in order
-                C v[kMergeG];
+            C* sp = slots + (size_t)s_item[m] * LL + e;
+            // all loads of the group in flight at once, then summed in order
+            C v[kMergeG];
 #pragma unroll
-                for (int k = 0; k < kMergeG; ++k) v[k] = k < nk ? sp[k * st] : C{R(0), R(0)};
-                C acc = v[0];
+            for (int k = 0; k < kMergeG; ++k) v[k] = k < nk ? sp[k * st] : C{R(0), R(0)};
+            C acc = v[0];
 #pragma unroll
-                for (int k = 1; k < kMergeG; ++k) {
-                    acc.x += v[k].x;
-                    acc.y += v[k].y;
-                }
-                sp[0] = acc;
+            for (int k = 1; k < kMergeG; ++k) {
+                acc.x += v[k].x;
+                acc.y += v[k].y;
             }
+            sp[0] = acc;
         }
         __syncthreads();
     }
@@ -1610,14 +1613,15 @@ __global__ void __launch_bounds__(256) k_reduce_strips(const typename V2<R>::T* 
     __syncthreads();
     const int nrow = min(min(RB, y0 + T - ys), rw.x - ys), nf1 = gg.nf1;
     const LdsHead head{tab, ty_lo, ntx};
-    const FastDiv dn = fast_div((unsigned)nf1), dT = fast_div((unsigned)T);
-    C* Fr = reinterpret_cast<C*>(F) + ((size_t)rw.y + ys) * nf1;
-    for (int e = threadIdx.x; e < nrow * nf1; e += blockDim.x) {
-        const int r = (int)fdiv((unsigned)e, dn), x = e - r * nf1;
-        const int tx = (int)fdiv((unsigned)x, dT);
-        C v{R(0), R(0)};
-        if (act[tx]) v = reduce_cell<R, REACH>(slots, gg, tx, ty, x - tx * T, ys - y0 + r, head);
-        Fr[e] = v;
+    const FastDiv dT = fast_div((unsigned)T);
+    for (int r = 0; r < nrow; ++r) {
+        C* Fr = reinterpret_cast<C*>(F) + ((size_t)rw.y + ys + r) * nf1;
+        for (int x = threadIdx.x; x < nf1; x += blockDim.x) {
+            const int tx = (int)fdiv((unsigned)x, dT);
+            C v{R(0), R(0)};
+            if (act[tx]) v = reduce_cell<R, REACH>(slots, gg, tx, ty, x - tx * T, ys - y0 + r, head);
+            Fr[x] = v;
+        }
     }
 }
 
@@ -2563,7 +2567,8 @@ fh_status spread_items(fh_ctx* c, const InstParams& p0, const InstParams* table,
     if (Ntot > 0) {
         const int64_t LL = (int64_t)gg.L * gg.L;
         const unsigned mgrid =
-            (unsigned)std::max<int64_t>(1, std::min<int64_t>((b.max_sub + 255) / 256, (int64_t)c->cu_count * 16));
+            (unsigned)std::max<int64_t>(1, std::min<int64_t>((b.max_sub + kMergeChunk - 1) / kMergeChunk,
+                                                            (int64_t)c->cu_count * 16));
         for (int level = 1; level <= kMergeLevels; ++level)
             hipLaunchKernelGGL((k_merge_slots<R>), dim3(mgrid), dim3(256), 0, c->stream,
                                (typename V2<R>::T*)b.slots, b.subs, b.nsub, b.tsub, (int)LL, level);
