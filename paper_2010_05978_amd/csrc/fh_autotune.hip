@@ -232,7 +232,7 @@ fh_status fh_autotune_batch(fh_ctx* c, int32_t B, const fh_quad* const* q, const
         const std::vector<int32_t> occ(B, 0);
         // the batched call as it runs: captured into a graph, then replayed
         const fh_status st =
-            tune(c, std::max(n1, n2), {5, 2, 4}, {0, 16, 32}, {0, 256, 1024}, 3, batch_key(c, B, n1, n2, Ntot, Nmax),
+            tune(c, std::max(n1, n2), {5, 2, 4}, {0, 16, 32}, {0, 256, 512, 1024, 2048}, 3, batch_key(c, B, n1, n2, Ntot, Nmax),
                  cache_path, best, [&]() {
                      return fh_field_grid_batch(c, B, q, lambda, z, n1, n2, h1, h2, 0.0, 0.0, occ.data(), u);
                  });
