@@ -212,84 +212,110 @@ __global__ void k_fill_field(R* __restrict__ u, int64_t M, R re)
 // 0.68 against 0.63 ms.)  A batch's nodes spread over many tiles and the
 // kernel waits on memory: 256-thread blocks, four times as many per CU,
 // hide more of it (whole binning 1.50 against 1.57 ms on the 256-shape
-// batch).
+// batch), and four nodes per thread more still (1.44 ms; mixed 1.23 ->
+// 1.11 ms).
 constexpr int kBinBlock = 1024;      // one rule: its nodes may crowd a few tiles
 constexpr int kBinBlockBatch = 256;  // a batch: spread over many tiles, latency bound
-constexpr int kBinKeyBits = 7;
-constexpr int kBinKeys = 1 << kBinKeyBits;
+constexpr int kBinNodesBatch = 4;    // nodes per thread in a batch
+constexpr int kBinKeyBits = 7;       // hash table of one rule's 1024-node block
+constexpr int kBinKeyBitsBatch = 9;  // and of a batch's 1024-node block
+constexpr int kBinProbes = 16;       // slots a lookup tries before its global atomic
 
-// With `key` (the stable binning), each node also writes its tile and its
-// index, the keys and values of the sort that then fixes the ranks.
-template <int BS>
+// A thread takes NPT nodes, BS apart (each load coalesced): the block's chain
+// of latencies (instance lookup, node loads, the table, the global atomics)
+// is paid once for BS NPT nodes.  A lookup tries at most kBinProbes slots; a
+// group whose tile finds none takes a global atomic of its own.
+template <int BS, int NPT, int KB>
 __global__ void __launch_bounds__(BS) k_bin_count(InstParams p0, const InstParams* __restrict__ table,
-                                                         const int* __restrict__ chunk, int64_t Ntot, GridGeom gg,
-                                                         int* __restrict__ cnt, int* __restrict__ rank,
-                                                         uint32_t* __restrict__ key, int* __restrict__ vals)
+                                                  const int* __restrict__ chunk, int64_t Ntot, GridGeom gg,
+                                                  int* __restrict__ cnt, int* __restrict__ rank,
+                                                  uint32_t* __restrict__ key, int* __restrict__ vals)
 {
-    __shared__ int s_key[kBinKeys];
-    __shared__ int s_cnt[kBinKeys];
-    __shared__ int s_base[kBinKeys];
-    for (int e = threadIdx.x; e < kBinKeys; e += BS) {
+    constexpr int NK = 1 << KB;
+    static_assert((BS * NPT) % kChunk == 0, "a block starts at a chunk");
+    __shared__ int s_key[NK];
+    __shared__ int s_cnt[NK];
+    __shared__ int s_base[NK];
+    for (int e = threadIdx.x; e < NK; e += BS) {
         s_key[e] = -1;
         s_cnt[e] = 0;
     }
-    const int2 ib = table ? block_inst_bounds(chunk, Ntot) : make_int2(0, 0);
-    __syncthreads();
-    const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    const bool valid = j < Ntot;
-    int tile = 0;
-    if (valid) {
-        const InstParams ip = table ? table[node_inst(table, j, ib)] : p0;
-        const int64_t jj = j - ip.node_off;
-        int l1, l2;
-        double d1, d2;
-        node_cell(ip, gg, ip.x[jj], ip.y[jj], l1, l2, d1, d2);
-        tile = ip.tile_off + (l2 / gg.T) * gg.ntx + (l1 / gg.T);
-        if (key) {
-            key[j] = (uint32_t)tile;
-            vals[j] = (int)j;
-        }
+    const int64_t j0 = blockIdx.x * (int64_t)(BS * NPT);
+    int2 ib = make_int2(0, 0);
+    if (table) {
+        const int64_t j1 = min(j0 + (int64_t)(BS * NPT), Ntot) - 1;
+        ib = make_int2(chunk[j0 / kChunk], chunk[(j1 + kChunk) / kChunk]);
     }
-    // groups of lanes with one tile; the lowest lane leads each group
+    __syncthreads();
     const int lane = (int)__lane_id();
-    uint64_t remaining = __ballot(valid);
-    uint64_t mine = 0;
-    int leader = lane;
-    while (remaining) {
-        const int l = __ffsll((unsigned long long)remaining) - 1;
-        const int lkey = __shfl(tile, l);
-        const uint64_t same = __ballot(valid && tile == lkey) & remaining;
-        if ((same >> lane) & 1ull) {
-            mine = same;
-            leader = l;
-        }
-        remaining &= ~same;
-    }
-    const bool lead = valid && leader == lane;
-    int slot = -1, off = 0, gbase = 0;
-    if (lead) {
-        int h = (int)(((unsigned)tile * 2654435761u) >> (32 - kBinKeyBits));
-        for (int probe = 0; probe < kBinKeys; ++probe) {
-            const int prev = atomicCAS(&s_key[h], -1, tile);
-            if (prev == -1 || prev == tile) {
-                slot = h;
-                break;
+    int tile[NPT];
+    bool valid[NPT];
+#pragma unroll
+    for (int k = 0; k < NPT; ++k) {
+        const int64_t j = j0 + (int64_t)k * BS + threadIdx.x;
+        valid[k] = j < Ntot;
+        tile[k] = 0;
+        if (valid[k]) {
+            const InstParams ip = table ? table[node_inst(table, j, ib)] : p0;
+            const int64_t jj = j - ip.node_off;
+            int l1, l2;
+            double d1, d2;
+            node_cell(ip, gg, ip.x[jj], ip.y[jj], l1, l2, d1, d2);
+            tile[k] = ip.tile_off + (l2 / gg.T) * gg.ntx + (l1 / gg.T);
+            if (key) {
+                key[j] = (uint32_t)tile[k];
+                vals[j] = (int)j;
             }
-            h = (h + 1) & (kBinKeys - 1);
         }
-        if (slot >= 0)
-            off = atomicAdd(&s_cnt[slot], __popcll(mine));
-        else
-            gbase = atomicAdd(&cnt[tile], __popcll(mine));
+    }
+    uint64_t mine[NPT];
+    int leader[NPT], slot[NPT], off[NPT], gbase[NPT];
+#pragma unroll
+    for (int k = 0; k < NPT; ++k) {
+        // groups of lanes with one tile; the lowest lane leads each group
+        uint64_t remaining = __ballot(valid[k]);
+        mine[k] = 0;
+        leader[k] = lane;
+        while (remaining) {
+            const int l = __ffsll((unsigned long long)remaining) - 1;
+            const int lkey = __shfl(tile[k], l);
+            const uint64_t same = __ballot(valid[k] && tile[k] == lkey) & remaining;
+            if ((same >> lane) & 1ull) {
+                mine[k] = same;
+                leader[k] = l;
+            }
+            remaining &= ~same;
+        }
+        slot[k] = -1;
+        off[k] = 0;
+        gbase[k] = 0;
+        if (valid[k] && leader[k] == lane) {
+            int h = (int)(((unsigned)tile[k] * 2654435761u) >> (32 - KB));
+            for (int probe = 0; probe < kBinProbes; ++probe) {
+                const int prev = atomicCAS(&s_key[h], -1, tile[k]);
+                if (prev == -1 || prev == tile[k]) {
+                    slot[k] = h;
+                    break;
+                }
+                h = (h + 1) & (NK - 1);
+            }
+            if (slot[k] >= 0)
+                off[k] = atomicAdd(&s_cnt[slot[k]], __popcll(mine[k]));
+            else
+                gbase[k] = atomicAdd(&cnt[tile[k]], __popcll(mine[k]));
+        }
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < kBinKeys; e += BS)
+    for (int e = threadIdx.x; e < NK; e += BS)
         if (s_key[e] >= 0) s_base[e] = atomicAdd(&cnt[s_key[e]], s_cnt[e]);
     __syncthreads();
-    int base = 0;
-    if (lead) base = slot >= 0 ? s_base[slot] + off : gbase;
-    base = __shfl(base, leader);
-    if (valid) rank[j] = base + __popcll(mine & ((1ull << lane) - 1ull));
+#pragma unroll
+    for (int k = 0; k < NPT; ++k) {
+        int base = 0;
+        if (valid[k] && leader[k] == lane) base = slot[k] >= 0 ? s_base[slot[k]] + off[k] : gbase[k];
+        base = __shfl(base, leader[k]);
+        if (valid[k]) rank[j0 + (int64_t)k * BS + threadIdx.x] = base + __popcll(mine[k] & ((1ull << lane) - 1ull));
+    }
 }
 
 // Points per work item of a tile holding c points: at least P, and large
@@ -2523,12 +2549,13 @@ fh_status spread_items(fh_ctx* c, const InstParams& p0, const InstParams* table,
             hipLaunchKernelGGL(k_chunk_inst, dim3(nblocks(Ntot / kChunk + 2, 256)), dim3(256), 0, c->stream, table,
                                ninst, Ntot, b.chunk);
         if (table)
-            hipLaunchKernelGGL(k_bin_count<kBinBlockBatch>, dim3(nblocks(Ntot, kBinBlockBatch)),
-                               dim3(kBinBlockBatch), 0, c->stream, p0, table, (const int*)b.chunk, Ntot, gg, b.cnt,
-                               b.rank, b.key, b.vals);
-        else
-            hipLaunchKernelGGL(k_bin_count<kBinBlock>, dim3(nblocks(Ntot, kBinBlock)), dim3(kBinBlock), 0,
+            hipLaunchKernelGGL((k_bin_count<kBinBlockBatch, kBinNodesBatch, kBinKeyBitsBatch>),
+                               dim3(nblocks(Ntot, kBinBlockBatch * kBinNodesBatch)), dim3(kBinBlockBatch), 0,
                                c->stream, p0, table, (const int*)b.chunk, Ntot, gg, b.cnt, b.rank, b.key, b.vals);
+        else
+            hipLaunchKernelGGL((k_bin_count<kBinBlock, 1, kBinKeyBits>), dim3(nblocks(Ntot, kBinBlock)),
+                               dim3(kBinBlock), 0, c->stream, p0, table, (const int*)b.chunk, Ntot, gg, b.cnt,
+                               b.rank, b.key, b.vals);
         if (b.key) {
             int bits = 1;
             while (bits < 32 && ((int64_t)1 << bits) < ntiles_total) ++bits;
