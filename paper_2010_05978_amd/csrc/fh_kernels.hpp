@@ -56,12 +56,6 @@ __global__ void k_chunk_inst(const InstParams* __restrict__ t, int n, int64_t Nt
     chunk[c] = find_inst(t, n, min(c * kChunk, Ntot - 1));
 }
 
-__device__ __forceinline__ int2 block_inst_bounds(const int* __restrict__ chunk, int64_t Ntot)
-{
-    const int64_t j0 = blockIdx.x * (int64_t)blockDim.x;
-    const int64_t j1 = min(j0 + (int64_t)blockDim.x, Ntot) - 1;
-    return make_int2(chunk[j0 / kChunk], chunk[(j1 + kChunk) / kChunk]);
-}
 __device__ __forceinline__ int node_inst(const InstParams* t, int64_t j, int2 ab)
 {
     if (ab.x == ab.y) return __builtin_amdgcn_readfirstlane(ab.x);
@@ -458,56 +452,91 @@ __global__ void k_rank_sorted(const uint32_t* __restrict__ key_sorted, const int
 
 // Strength (FP64 phase in turns, reduced, times the node's source term when
 // the rule has one), stencil offsets, and the sorted position of each node.
+// A thread takes kPlaceNodes nodes, 256 apart: first every node's loads and
+// strength, then its tile's offset and count, then the stores, so that each
+// round of memory latency covers all of them.
+constexpr int kPlaceNodes = 2;
+
 template <class R>
 __global__ void __launch_bounds__(256) k_bin_place(InstParams p0, const InstParams* __restrict__ table,
-                                                   const int* __restrict__ chunk, int64_t Ntot, GridGeom gg, const int* __restrict__ cnt,
-                                                   const int* __restrict__ off, const int* __restrict__ tsub,
-                                                   const int* __restrict__ rank, uint32_t* __restrict__ cell,
-                                                   typename V2<R>::T* __restrict__ dd,
+                                                   const int* __restrict__ chunk, int64_t Ntot, GridGeom gg,
+                                                   const int* __restrict__ cnt, const int* __restrict__ off,
+                                                   const int* __restrict__ tsub, const int* __restrict__ rank,
+                                                   uint32_t* __restrict__ cell, typename V2<R>::T* __restrict__ dd,
                                                    typename V2<R>::T* __restrict__ cc, Sub* __restrict__ subs)
 {
-    const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (j >= Ntot) return;
-    const InstParams ip = table ? table[node_inst(table, j, block_inst_bounds(chunk, Ntot))] : p0;
-    const int64_t jj = j - ip.node_off;
-    const double x = ip.x[jj], y = ip.y[jj];
-    double w = ip.w[jj];
-    int l1, l2;
-    double d1, d2;
-    if (!node_cell(ip, gg, x, y, l1, l2, d1, d2)) w = 0.0;
-    const int tile = ip.tile_off + (l2 / gg.T) * gg.ntx + (l1 / gg.T);
-    const double t = ((x * x + y * y) * ip.pa + (x * ip.px + y * ip.py)) + ip.pc;
-    const double f = t - rint(t);
-    double s, c;
-    sincospi(2.0 * f, &s, &c);
-    double cr = w * c, ci = w * s;
-    if (ip.src && jj < ip.N) {
-        // the node's source term multiplies its strength (jj < N always
-        // holds: j lies in this instance's node range)
-        const double sr = ip.src[2 * jj], si = ip.src[2 * jj + 1];
-        const double tr = cr * sr - ci * si;
-        ci = cr * si + ci * sr;
-        cr = tr;
+    constexpr int NPT = kPlaceNodes;
+    static_assert((256 * NPT) % kChunk == 0, "a block starts at a chunk");
+    const int64_t j0 = blockIdx.x * (int64_t)(256 * NPT);
+    int2 ib = make_int2(0, 0);
+    if (table) {
+        const int64_t j1 = min(j0 + (int64_t)(256 * NPT), Ntot) - 1;
+        ib = make_int2(chunk[j0 / kChunk], chunk[(j1 + kChunk) / kChunk]);
     }
-    const int rk = rank[j];
-    const int pos = off[tile] + rk;
-    cell[pos] = (uint32_t)l1 | ((uint32_t)l2 << 16);
-    typename V2<R>::T dv, cv;
-    dv.x = (R)d1;
-    dv.y = (R)d2;
-    cv.x = (R)cr;
-    cv.y = (R)ci;
-    dd[pos] = dv;
-    cc[pos] = cv;
-    // the point that opens a work item of its tile writes the item
-    const int ct = cnt[tile];
-    const int Pt = tile_item_points(ct, gg.P);
-    if (rk % Pt == 0) {
-        Sub it;
-        it.tile = tile;
-        it.start = pos;
-        it.end = min(pos + Pt, off[tile] + ct);
-        subs[tsub[2 * tile] + rk / Pt] = it;
+    bool ok[NPT];
+    int tile[NPT], rk[NPT];
+    uint32_t cl[NPT];
+    typename V2<R>::T dv[NPT], cv[NPT];
+#pragma unroll
+    for (int k = 0; k < NPT; ++k) {
+        const int64_t j = j0 + (int64_t)k * 256 + threadIdx.x;
+        ok[k] = j < Ntot;
+        tile[k] = 0;
+        rk[k] = 0;
+        cl[k] = 0;
+        dv[k] = typename V2<R>::T{R(0), R(0)};
+        cv[k] = typename V2<R>::T{R(0), R(0)};
+        if (!ok[k]) continue;
+        const InstParams ip = table ? table[node_inst(table, j, ib)] : p0;
+        const int64_t jj = j - ip.node_off;
+        const double x = ip.x[jj], y = ip.y[jj];
+        double w = ip.w[jj];
+        int l1, l2;
+        double d1, d2;
+        if (!node_cell(ip, gg, x, y, l1, l2, d1, d2)) w = 0.0;
+        tile[k] = ip.tile_off + (l2 / gg.T) * gg.ntx + (l1 / gg.T);
+        const double t = ((x * x + y * y) * ip.pa + (x * ip.px + y * ip.py)) + ip.pc;
+        const double f = t - rint(t);
+        double sn, cs;
+        sincospi(2.0 * f, &sn, &cs);
+        double cr = w * cs, ci = w * sn;
+        if (ip.src && jj < ip.N) {
+            // the node's source term multiplies its strength (jj < N always
+            // holds: j lies in this instance's node range)
+            const double sr = ip.src[2 * jj], si = ip.src[2 * jj + 1];
+            const double tr = cr * sr - ci * si;
+            ci = cr * si + ci * sr;
+            cr = tr;
+        }
+        rk[k] = rank[j];
+        cl[k] = (uint32_t)l1 | ((uint32_t)l2 << 16);
+        dv[k].x = (R)d1;
+        dv[k].y = (R)d2;
+        cv[k].x = (R)cr;
+        cv[k].y = (R)ci;
+    }
+    int o[NPT], ct[NPT];
+#pragma unroll
+    for (int k = 0; k < NPT; ++k) {
+        o[k] = ok[k] ? off[tile[k]] : 0;
+        ct[k] = ok[k] ? cnt[tile[k]] : 0;
+    }
+#pragma unroll
+    for (int k = 0; k < NPT; ++k) {
+        if (!ok[k]) continue;
+        const int pos = o[k] + rk[k];
+        cell[pos] = cl[k];
+        dd[pos] = dv[k];
+        cc[pos] = cv[k];
+        // the point that opens a work item of its tile writes the item
+        const int Pt = tile_item_points(ct[k], gg.P);
+        if (rk[k] % Pt == 0) {
+            Sub it;
+            it.tile = tile[k];
+            it.start = pos;
+            it.end = min(pos + Pt, o[k] + ct[k]);
+            subs[tsub[2 * tile[k]] + rk[k] / Pt] = it;
+        }
     }
 }
 
@@ -2572,7 +2601,7 @@ fh_status spread_items(fh_ctx* c, const InstParams& p0, const InstParams* table,
         hipLaunchKernelGGL(k_rank_sorted, dim3(nblocks(Ntot, 256)), dim3(256), 0, c->stream, b.key_sorted,
                            b.vals_sorted, Ntot, b.off, b.rank);
     if (Ntot > 0) {
-        hipLaunchKernelGGL((k_bin_place<R>), dim3(nblocks(Ntot, 256)), dim3(256), 0, c->stream, p0, table,
+        hipLaunchKernelGGL((k_bin_place<R>), dim3(nblocks(Ntot, 256 * kPlaceNodes)), dim3(256), 0, c->stream, p0, table,
                            (const int*)b.chunk, Ntot, gg, b.cnt, b.off, b.tsub, b.rank, b.cell, (typename V2<R>::T*)b.dd,
                            (typename V2<R>::T*)b.cc, b.subs);
     }
