@@ -79,6 +79,17 @@ __host__ __device__ constexpr int poly_np(int w)
     return w <= 3 ? 6 : w <= 5 ? 7 : w <= 8 ? w + 2 : w <= 11 ? 11 : w == 12 ? 13 : w + 2;
 }
 
+// The pieces mirror each other: the piece of stencil cell w - 1 - a at t is
+// that of cell a at -t (phi is even).  The matrix-core spread evaluates each
+// such pair from one piece split into even and odd parts in s = t^2,
+// P_a(t) = E(s) + t O(s) and P_{w-1-a}(t) = E(s) - t O(s), for half the
+// multiply-adds.  Its table follows the plain one in the same allocation:
+// for pair p < poly_npair(w), E's poly_ne(w) coefficients (highest power
+// first), then O's poly_no(w), at eo[j * npair + p].
+__host__ __device__ constexpr int poly_npair(int w) { return (w + 1) / 2; }
+__host__ __device__ constexpr int poly_ne(int w) { return (poly_np(w) - 1) / 2 + 1; }
+__host__ __device__ constexpr int poly_no(int w) { return poly_np(w) / 2; }
+
 // Wavefront spread staging: per point its 2w kernel values and its strength
 // (2 reals), for 64 points, and the kernel arguments of 64 points for each of
 // up to two wavefronts.

@@ -225,6 +225,7 @@ void es_poly_attach(fh_ctx* c, EsKernel& k)
     for (int q = 2; q < np; ++q)
         for (int i = 0; i < np; ++i) T[q][i] = (i > 0 ? 2.0 * T[q - 1][i - 1] : 0.0) - T[q - 2][i];
     std::vector<double> table((size_t)np * W);
+    std::vector<std::vector<double>> monos(W);
     bool ok = true;
     for (int a = 0; a < W && ok; ++a) {
         auto f = [&](double t) { return phi(((t + 1.0) / 2.0 + a - 0.5 * W) * 2.0 / W); };
@@ -244,6 +245,31 @@ void es_poly_attach(fh_ctx* c, EsKernel& k)
             ok = std::fabs(v - f(t)) <= tol_abs;
         }
         for (int j = 0; j < np; ++j) table[(size_t)j * W + a] = mono[deg - j];
+        monos[a] = mono;
+    }
+    // the even/odd pair table of the matrix-core spread, checked against phi
+    // for both pieces of every pair
+    const int npair = poly_npair(W), ne = poly_ne(W), no = poly_no(W);
+    for (int p = 0; p < npair && ok; ++p) {
+        std::vector<double> ce(ne), co(no);
+        for (int j = 0; j < ne; ++j) ce[j] = monos[p][2 * (ne - 1 - j)];
+        for (int j = 0; j < no; ++j) co[j] = monos[p][2 * (no - 1 - j) + 1];
+        auto fa = [&](double t, int a) { return phi(((t + 1.0) / 2.0 + a - 0.5 * W) * 2.0 / W); };
+        for (int s = 0; s <= 512 && ok; ++s) {
+            const double t = -1.0 + 2.0 * s / 512, s2 = t * t;
+            double e = ce[0], o = co[0];
+            for (int j = 1; j < ne; ++j) e = e * s2 + ce[j];
+            for (int j = 1; j < no; ++j) o = o * s2 + co[j];
+            ok = std::fabs(e + t * o - fa(t, p)) <= tol_abs && std::fabs(e - t * o - fa(t, W - 1 - p)) <= tol_abs;
+        }
+    }
+    if (ok) {
+        std::vector<double> eo((size_t)(ne + no) * npair);
+        for (int p = 0; p < npair; ++p) {
+            for (int j = 0; j < ne; ++j) eo[(size_t)j * npair + p] = monos[p][2 * (ne - 1 - j)];
+            for (int j = 0; j < no; ++j) eo[(size_t)(ne + j) * npair + p] = monos[p][2 * (no - 1 - j) + 1];
+        }
+        table.insert(table.end(), eo.begin(), eo.end());
     }
     void* dev = nullptr;
     if (ok) {

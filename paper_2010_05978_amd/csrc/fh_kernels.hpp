@@ -1059,7 +1059,12 @@ __global__ void __launch_bounds__(64 * kMfmaWaves) k_spread_mfma(const Sub* __re
     using M = MfmaAcc<R>;
     using V = typename M::V;
     constexpr int NP = poly_np(W);  // coefficients per kernel polynomial
-    constexpr int KG = 64 / W;          // lane groups evaluating kernel values
+    constexpr int KG = 64 / W;          // lane groups evaluating kernel values (no table)
+    constexpr int NPAIR = poly_npair(W), NE = poly_ne(W), NO = poly_no(W);
+    constexpr int KGP = 64 / NPAIR;     // lane groups evaluating mirrored pairs (table)
+    // Mirrored pairs measured faster in FP32 (batch spread 1.045 -> 0.934 ms)
+    // and slower in FP64 (2.40 -> 2.50 ms), so FP64 keeps a cell per lane.
+    constexpr bool PAIRS = sizeof(R) == 4;
     static_assert(W <= 16 * NB, "the padded tile must fit the blocks");
     static_assert(MS % 16 == 0 && MS <= 64, "points are staged in sixteens, one per lane at most");
     extern __shared__ unsigned char smem_raw[];
@@ -1075,13 +1080,26 @@ __global__ void __launch_bounds__(64 * kMfmaWaves) k_spread_mfma(const Sub* __re
     int* shy = shx + MS;                                // byte offset of q P + T - 1 - cy
     const int nsub = *nsub_ptr;
     const int k4 = lane >> 4, i16 = lane & 15;
-    // lane (kg, ka), ka = lane % W, holds the coefficients of cell ka's
-    // polynomial and evaluates it at arguments kg, kg + KG, ...
+    // FP32 with the table: lane (pg, pp), pp = lane % NPAIR, holds the even
+    // and odd parts of cell pp's polynomial and evaluates cells pp and
+    // W - 1 - pp at arguments pg, pg + KGP, ...  Otherwise lane (kg, ka)
+    // holds cell ka's coefficients (ka = lane % W; phi itself without the
+    // table) and evaluates it at arguments kg, kg + KG, ...
     const bool has_poly = poly != nullptr;
     const int ka = lane % W, kg = lane / W;
-    R coef[NP];
+    const int pp = lane % NPAIR, pg = lane / NPAIR;
+    constexpr int NC1 = PAIRS ? NE : NP, NC2 = PAIRS ? NO : 1;
+    R ce[NC1], co[NC2];
+    if constexpr (PAIRS) {
 #pragma unroll
-    for (int j = 0; j < NP; ++j) coef[j] = has_poly ? poly[j * W + ka] : R(0);
+        for (int j = 0; j < NE; ++j) ce[j] = has_poly ? poly[NP * W + j * NPAIR + pp] : R(0);
+#pragma unroll
+        for (int j = 0; j < NO; ++j) co[j] = has_poly ? poly[NP * W + (NE + j) * NPAIR + pp] : R(0);
+    } else {
+#pragma unroll
+        for (int j = 0; j < NP; ++j) ce[j] = has_poly ? poly[j * W + ka] : R(0);
+        co[0] = R(0);
+    }
     // rows start at zero; staging only ever writes their W middle positions
     for (int e = lane; e < 3 * AL; e += 64) rows[e] = R(0);
     const uint32_t lane_off = (uint32_t)(i16 * sizeof(R));
@@ -1122,26 +1140,57 @@ __global__ void __launch_bounds__(64 * kMfmaWaves) k_spread_mfma(const Sub* __re
             wave_lds_order();
             // the kernel values: arguments 0..MS-1 are the points' x, the
             // next MS their y (times the strength)
+            if (PAIRS && has_poly) {
 #pragma unroll
-            for (int r = 0; r < (2 * MS + KG - 1) / KG; ++r) {
-                const int qq = r * KG + kg;
-                if (kg < KG && qq < 2 * MS) {
-                    const R t = ttab[qq];
-                    R k;
-                    if (has_poly) {
-                        k = coef[0];
+                for (int r = 0; r < (2 * MS + KGP - 1) / KGP; ++r) {
+                    const int qq = r * KGP + pg;
+                    if (pg < KGP && qq < 2 * MS) {
+                        const R t = ttab[qq], s2 = t * t;
+                        R e = ce[0], o = co[0];
 #pragma unroll
-                        for (int j = 1; j < NP; ++j) k = k * t + coef[j];
-                    } else {
-                        k = es_one<R, W>((t - R(W - 1)) * R(0.5), ka, beta, nullptr);
+                        for (int j = 1; j < NC1; ++j) e = e * s2 + ce[j];
+#pragma unroll
+                        for (int j = 1; j < NC2; ++j) o = o * s2 + co[j];
+                        const R lo = e + t * o, hi = e - t * o;  // cells pp and W - 1 - pp
+                        const bool two = 2 * pp != W - 1;
+                        const int q = qq < MS ? qq : qq - MS;
+                        R* row = rows + q * P + T - 1;
+                        if (qq < MS) {
+                            row[pp] = lo;
+                            if (two) row[W - 1 - pp] = hi;
+                        } else {
+                            const R cr = ctab[2 * q], ci = ctab[2 * q + 1];
+                            row[AL + pp] = cr * lo;
+                            row[2 * AL + pp] = ci * lo;
+                            if (two) {
+                                row[AL + W - 1 - pp] = cr * hi;
+                                row[2 * AL + W - 1 - pp] = ci * hi;
+                            }
+                        }
                     }
-                    const int q = qq < MS ? qq : qq - MS;
-                    R* row = rows + q * P + T - 1 + ka;
-                    if (qq < MS) {
-                        row[0] = k;
-                    } else {
-                        row[AL] = ctab[2 * q] * k;
-                        row[2 * AL] = ctab[2 * q + 1] * k;
+                }
+            } else {
+#pragma unroll
+                for (int r = 0; r < (2 * MS + KG - 1) / KG; ++r) {
+                    const int qq = r * KG + kg;
+                    if (kg < KG && qq < 2 * MS) {
+                        const R t = ttab[qq];
+                        R k;
+                        if (has_poly) {
+                            k = ce[0];
+#pragma unroll
+                            for (int j = 1; j < NC1; ++j) k = k * t + ce[j];
+                        } else {
+                            k = es_one<R, W>((t - R(W - 1)) * R(0.5), ka, beta, nullptr);
+                        }
+                        const int q = qq < MS ? qq : qq - MS;
+                        R* row = rows + q * P + T - 1 + ka;
+                        if (qq < MS) {
+                            row[0] = k;
+                        } else {
+                            row[AL] = ctab[2 * q] * k;
+                            row[2 * AL] = ctab[2 * q + 1] * k;
+                        }
                     }
                 }
             }
