@@ -770,8 +770,9 @@ def hg_starshade(fh, steps, warmup):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported by this build "
-              "(the path shards by instance or by node; see DESIGN.md)", file=sys.stderr)
+        print(f"bench.py runs on one GPU; --gpus {args.gpus} is not supported "
+              "(batches would shard by whole instances and a single large rule by its nodes, "
+              "with one reduction of the partial fields; only one GPU is driven here)", file=sys.stderr)
         sys.exit(2)
     import torch
     import paper_2010_05978_amd as fh

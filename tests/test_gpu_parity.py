@@ -1,6 +1,6 @@
 """GPU path vs the CPU FP64 oracle, through the C ABI.
 
-Bars (relative L2 over the compared targets, on u_ap):
+Bars (relative L2 over the compared targets, on u_ap: the context's tolerance):
   FP64 context, tol 1e-9   ->  <= 1e-9
   mixed context, tol 1e-5  ->  <= 1e-5
 Full-size workloads compare a seeded sample of targets that the oracle sums
