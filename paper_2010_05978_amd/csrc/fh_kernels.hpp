@@ -455,7 +455,7 @@ __global__ void k_rank_sorted(const uint32_t* __restrict__ key_sorted, const int
 // A thread takes kPlaceNodes nodes, 256 apart: first every node's loads and
 // strength, then its tile's offset and count, then the stores, so that each
 // round of memory latency covers all of them.
-constexpr int kPlaceNodes = 2;
+constexpr int kPlaceNodes = 4;
 
 template <class R>
 __global__ void __launch_bounds__(256) k_bin_place(InstParams p0, const InstParams* __restrict__ table,
