@@ -1046,11 +1046,12 @@ __host__ __device__ inline size_t mfma_wave_lds(int NB, int T, int MS, size_t rs
     return (3 * (size_t)mfma_rows(NB, T, MS) + 4 * (size_t)MS) * rsize + 2 * (size_t)MS * sizeof(int);
 }
 
-// FP32 asks the register allocator for eight waves per SIMD (61 registers;
-// seven by default: batch spread 0.93 -> 0.88 ms); FP64 keeps its default
-// allocation (four waves: asking for five spills, 2.43 -> 2.47 ms).
+// The register allocator is asked for eight waves per SIMD in FP32 (61
+// registers; seven by default: batch spread 0.93 -> 0.88 ms) and four in
+// FP64, where the mirrored-pair evaluation would otherwise take 130
+// registers and three waves (2.40 -> 2.22 ms with four; five spill).
 template <class R, int W, int NB, int MS>
-__global__ void __launch_bounds__(64 * kMfmaWaves) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 8 : 1))) k_spread_mfma(const Sub* __restrict__ subs,
+__global__ void __launch_bounds__(64 * kMfmaWaves) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 8 : 4))) k_spread_mfma(const Sub* __restrict__ subs,
                                                                  const int* __restrict__ nsub_ptr,
                                                                  const uint32_t* __restrict__ cell,
                                                                  const typename V2<R>::T* __restrict__ dd,
@@ -1065,9 +1066,6 @@ __global__ void __launch_bounds__(64 * kMfmaWaves) __attribute__((amdgpu_waves_p
     constexpr int KG = 64 / W;          // lane groups evaluating kernel values (no table)
     constexpr int NPAIR = poly_npair(W), NE = poly_ne(W), NO = poly_no(W);
     constexpr int KGP = 64 / NPAIR;     // lane groups evaluating mirrored pairs (table)
-    // Mirrored pairs measured faster in FP32 (batch spread 1.045 -> 0.934 ms)
-    // and slower in FP64 (2.40 -> 2.50 ms), so FP64 keeps a cell per lane.
-    constexpr bool PAIRS = sizeof(R) == 4;
     static_assert(W <= 16 * NB, "the padded tile must fit the blocks");
     static_assert(MS % 16 == 0 && MS <= 64, "points are staged in sixteens, one per lane at most");
     extern __shared__ unsigned char smem_raw[];
@@ -1083,26 +1081,20 @@ __global__ void __launch_bounds__(64 * kMfmaWaves) __attribute__((amdgpu_waves_p
     int* shy = shx + MS;                                // byte offset of q P + T - 1 - cy
     const int nsub = *nsub_ptr;
     const int k4 = lane >> 4, i16 = lane & 15;
-    // FP32 with the table: lane (pg, pp), pp = lane % NPAIR, holds the even
-    // and odd parts of cell pp's polynomial and evaluates cells pp and
-    // W - 1 - pp at arguments pg, pg + KGP, ...  Otherwise lane (kg, ka)
-    // holds cell ka's coefficients (ka = lane % W; phi itself without the
-    // table) and evaluates it at arguments kg, kg + KG, ...
+    // With the table, lane (pg, pp), pp = lane % NPAIR, holds the even and
+    // odd parts of cell pp's polynomial and evaluates cells pp and W - 1 - pp
+    // at arguments pg, pg + KGP, ... (measured against a cell per lane, which
+    // needs fewer registers: FP32 1.045 -> 0.93 ms, FP64 2.40 -> 2.22 ms once
+    // held to four waves).  Without it, lane (kg, ka), ka = lane % W,
+    // evaluates phi itself for cell ka at arguments kg, kg + KG, ...
     const bool has_poly = poly != nullptr;
     const int ka = lane % W, kg = lane / W;
     const int pp = lane % NPAIR, pg = lane / NPAIR;
-    constexpr int NC1 = PAIRS ? NE : NP, NC2 = PAIRS ? NO : 1;
-    R ce[NC1], co[NC2];
-    if constexpr (PAIRS) {
+    R ce[NE], co[NO];
 #pragma unroll
-        for (int j = 0; j < NE; ++j) ce[j] = has_poly ? poly[NP * W + j * NPAIR + pp] : R(0);
+    for (int j = 0; j < NE; ++j) ce[j] = has_poly ? poly[NP * W + j * NPAIR + pp] : R(0);
 #pragma unroll
-        for (int j = 0; j < NO; ++j) co[j] = has_poly ? poly[NP * W + (NE + j) * NPAIR + pp] : R(0);
-    } else {
-#pragma unroll
-        for (int j = 0; j < NP; ++j) ce[j] = has_poly ? poly[j * W + ka] : R(0);
-        co[0] = R(0);
-    }
+    for (int j = 0; j < NO; ++j) co[j] = has_poly ? poly[NP * W + (NE + j) * NPAIR + pp] : R(0);
     // rows start at zero; staging only ever writes their W middle positions
     for (int e = lane; e < 3 * AL; e += 64) rows[e] = R(0);
     const uint32_t lane_off = (uint32_t)(i16 * sizeof(R));
@@ -1143,7 +1135,7 @@ __global__ void __launch_bounds__(64 * kMfmaWaves) __attribute__((amdgpu_waves_p
             wave_lds_order();
             // the kernel values: arguments 0..MS-1 are the points' x, the
             // next MS their y (times the strength)
-            if (PAIRS && has_poly) {
+            if (has_poly) {
 #pragma unroll
                 for (int r = 0; r < (2 * MS + KGP - 1) / KGP; ++r) {
                     const int qq = r * KGP + pg;
@@ -1151,9 +1143,9 @@ __global__ void __launch_bounds__(64 * kMfmaWaves) __attribute__((amdgpu_waves_p
                         const R t = ttab[qq], s2 = t * t;
                         R e = ce[0], o = co[0];
 #pragma unroll
-                        for (int j = 1; j < NC1; ++j) e = e * s2 + ce[j];
+                        for (int j = 1; j < NE; ++j) e = e * s2 + ce[j];
 #pragma unroll
-                        for (int j = 1; j < NC2; ++j) o = o * s2 + co[j];
+                        for (int j = 1; j < NO; ++j) o = o * s2 + co[j];
                         const R lo = e + t * o, hi = e - t * o;  // cells pp and W - 1 - pp
                         const bool two = 2 * pp != W - 1;
                         const int q = qq < MS ? qq : qq - MS;
@@ -1178,14 +1170,7 @@ __global__ void __launch_bounds__(64 * kMfmaWaves) __attribute__((amdgpu_waves_p
                     const int qq = r * KG + kg;
                     if (kg < KG && qq < 2 * MS) {
                         const R t = ttab[qq];
-                        R k;
-                        if (has_poly) {
-                            k = ce[0];
-#pragma unroll
-                            for (int j = 1; j < NC1; ++j) k = k * t + ce[j];
-                        } else {
-                            k = es_one<R, W>((t - R(W - 1)) * R(0.5), ka, beta, nullptr);
-                        }
+                        const R k = es_one<R, W>((t - R(W - 1)) * R(0.5), ka, beta, nullptr);
                         const int q = qq < MS ? qq : qq - MS;
                         R* row = rows + q * P + T - 1 + ka;
                         if (qq < MS) {
