@@ -283,8 +283,14 @@ __global__ void __launch_bounds__(256) k_adj_gather_lds(const R* __restrict__ F1
             if (wc0 < 0) wc0 += gg.nf1;
             wc0 = min(wc0, span1 - W);
             const int r0 = min(l2, gg.rows - W);
+            // the row kernel values too, once per node (a row index into the
+            // table inside the loop made the compiler keep the whole table in
+            // registers); the rows are unrolled, each row's loads issued
+            // after the previous row's sums
+            R k2[W];
+            es_weights<R, W>((R)d2, beta, poly, k2);
             R t0r = 0, t0i = 0, t1r = 0, t1i = 0, t2r = 0, t2i = 0;
-#pragma unroll 1
+#pragma unroll
             for (int b = 0; b < W; ++b) {
                 const C* wr = win + (r0 + b) * span1 + wc0;
                 R a0r = 0, a0i = 0, a1r = 0, a1i = 0, a2r = 0, a2i = 0;
@@ -298,7 +304,8 @@ __global__ void __launch_bounds__(256) k_adj_gather_lds(const R* __restrict__ F1
                     a2r += v2.x * k1[a];
                     a2i += v2.y * k1[a];
                 }
-                const R kb = es_one<R, W>((R)d2, b, beta, poly);
+                const R kb = k2[b];
+                __builtin_amdgcn_sched_barrier(0);
                 t0r += a0r * kb;
                 t0i += a0i * kb;
                 t1r += a1r * kb;
